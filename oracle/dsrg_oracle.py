@@ -1,0 +1,432 @@
+"""CPU FP64 oracle for the DF-DSRG-MRPT2 terms F1 (CCVV), F2 (CAVV), F3 (CCAV).
+
+TEST INFRASTRUCTURE ONLY. This file is the slow, plain reference that the
+HIP path is checked against. Only the test-suite, the package smoke check and
+the benchmark's CPU-baseline leg may import or run it; the product path never
+does, and the two share no code (inputs come from the seeded generator
+module, which holds no arithmetic of the method).
+
+Notation (paper section II): core m,n (also i,j), active u,v,w, virtual
+e,f (also a,b). Chemists' integrals come from the factorisation of Eq.
+int_fact, (pq|rs) = sum_Q B^Q_pq B^Q_rs, with the three blocks that F1-F3
+touch: B_cv[Q][m][e], B_ca[Q][m][u], B_av[Q][u][e]. Denominators are
+Delta^{ab}_{ij} = e_i + e_j - e_a - e_b (section II.B, after Eq. T2amp).
+
+Spin adaptation (a reading of the spin-orbital Table II; see the pinned
+brute-force in ``brute_force_spinorbital``): restricted core and virtual
+orbitals, spin-summed active density Gamma (spin-orbital gamma = Gamma/2 in
+each spin block, eta = 1 - gamma), which gives
+
+  E_CCVV = sum_{ij} sum_{ab} (ia|jb) [2 (ia|jb) - (ib|ja)] R(D^{ab}_{ij})
+  E_CAVV = sum_{uv} Gamma_uv sum_m sum_{ef} (me|uf) S(D^{ef}_{mu})
+                                       [2 (me|vf) - (mf|ve)] R1(D^{ef}_{mv})
+  E_CCAV = sum_{uv} (2 delta_uv - Gamma_uv) sum_{mn} sum_e (me|nv) S(D^{ev}_{mn})
+                                       [2 (me|nu) - (mu|ne)] R1(D^{eu}_{mn})
+
+with R(D) = (1 - exp(-2 s D^2)) / D (Eq. expensive),
+R1(D) = (1 - exp(-s D^2)) / D (Eq. T2amp), S(D) = 1 + exp(-s D^2)
+(Eq. v_tilde). At D == 0 the regularisers take their limits R = R1 = 0.
+
+Regularisers use libm ``expm1``; every sum over many elements is a
+``math.fsum``. Gradients are written out from the same formulas by the chain
+rule, term by term, in separate plain code.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, Tuple
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# regularisers (Eq. T2amp, Eq. v_tilde, Eq. expensive)
+# ---------------------------------------------------------------------------
+def _safe_div(num: np.ndarray, den: np.ndarray) -> np.ndarray:
+    out = np.zeros(np.broadcast(num, den).shape)
+    nz = den != 0.0
+    np.divide(num, den, out=out, where=nz)
+    return out
+
+
+def reg_R(D: np.ndarray, s: float) -> np.ndarray:
+    """(1 - exp(-2 s D^2)) / D, with value 0 at D = 0."""
+    D = np.asarray(D, dtype=np.float64)
+    return _safe_div(-np.expm1(-2.0 * s * D * D), D)
+
+
+def reg_R1(D: np.ndarray, s: float) -> np.ndarray:
+    """(1 - exp(-s D^2)) / D, the T2 renormalised denominator; 0 at D = 0."""
+    D = np.asarray(D, dtype=np.float64)
+    return _safe_div(-np.expm1(-s * D * D), D)
+
+
+def reg_S(D: np.ndarray, s: float) -> np.ndarray:
+    """1 + exp(-s D^2), the factor that turns v into v-tilde."""
+    D = np.asarray(D, dtype=np.float64)
+    return 1.0 + np.exp(-s * D * D)
+
+
+def dreg_R(D, s):
+    """dR/dD = 4 s exp(-2 s D^2) - R/D, with the limit 2 s at D = 0."""
+    D = np.asarray(D, dtype=np.float64)
+    e = np.exp(-2.0 * s * D * D)
+    return np.where(D == 0.0, 2.0 * s, 4.0 * s * e - _safe_div(reg_R(D, s), D))
+
+
+def dreg_R1(D, s):
+    """dR1/dD = 2 s exp(-s D^2) - R1/D, with the limit s at D = 0."""
+    D = np.asarray(D, dtype=np.float64)
+    e = np.exp(-s * D * D)
+    return np.where(D == 0.0, s, 2.0 * s * e - _safe_div(reg_R1(D, s), D))
+
+
+def dreg_S(D, s):
+    """dS/dD = -2 s D exp(-s D^2)."""
+    D = np.asarray(D, dtype=np.float64)
+    return -2.0 * s * D * np.exp(-s * D * D)
+
+
+def sreg_R(D, s):
+    """dR/ds = 2 D exp(-2 s D^2)."""
+    D = np.asarray(D, dtype=np.float64)
+    return 2.0 * D * np.exp(-2.0 * s * D * D)
+
+
+def sreg_R1(D, s):
+    """dR1/ds = D exp(-s D^2)."""
+    D = np.asarray(D, dtype=np.float64)
+    return D * np.exp(-s * D * D)
+
+
+def sreg_S(D, s):
+    """dS/ds = -D^2 exp(-s D^2)."""
+    D = np.asarray(D, dtype=np.float64)
+    return -D * D * np.exp(-s * D * D)
+
+
+def _fsum(a: np.ndarray) -> float:
+    return math.fsum(np.asarray(a, dtype=np.float64).ravel().tolist())
+
+
+# ---------------------------------------------------------------------------
+# energies
+# ---------------------------------------------------------------------------
+def ccvv_pair_energies(B_cv, eps_c, eps_v, s) -> np.ndarray:
+    """Pair energies e_ij of F1 (Eq. expensive; the pair loop of section III).
+
+    Returns the full nc x nc matrix e[i, j] = sum_ab (ia|jb)[2(ia|jb)-(ib|ja)]
+    R(D^{ab}_{ij}) over ordered pairs, so that E_CCVV = sum_ij e[i, j].
+    """
+    naux, nc, nv = B_cv.shape
+    e = np.zeros((nc, nc))
+    for i in range(nc):
+        Bi = np.ascontiguousarray(B_cv[:, i, :])
+        for j in range(i, nc):
+            Bj = np.ascontiguousarray(B_cv[:, j, :])
+            K = Bi.T @ Bj                      # K[a, b] = (ia|jb)
+            D = eps_c[i] + eps_c[j] - eps_v[:, None] - eps_v[None, :]
+            val = _fsum(K * (2.0 * K - K.T) * reg_R(D, s))
+            e[i, j] = val
+            e[j, i] = val                      # (ji) term equals (ij) term
+    return e
+
+
+def energy_ccvv(B_cv, eps_c, eps_v, s) -> float:
+    """F1 of Table II after spin summation."""
+    if s == 0.0:
+        return 0.0
+    return math.fsum(ccvv_pair_energies(B_cv, eps_c, eps_v, s).ravel().tolist())
+
+
+def energy_cavv(B_cv, B_av, eps_c, eps_a, eps_v, gamma1, s) -> float:
+    """F2 of Table II after spin summation (spin-summed Gamma)."""
+    naux, nc, nv = B_cv.shape
+    na = B_av.shape[1]
+    if na == 0 or s == 0.0:
+        return 0.0
+    parts = []
+    for m in range(nc):
+        Bm = np.ascontiguousarray(B_cv[:, m, :])
+        X = [Bm.T @ np.ascontiguousarray(B_av[:, u, :]) for u in range(na)]  # X[u][e,f] = (me|uf)
+        D = [eps_c[m] + eps_a[u] - eps_v[:, None] - eps_v[None, :] for u in range(na)]
+        Y = [(2.0 * X[v] - X[v].T) * reg_R1(D[v], s) for v in range(na)]
+        for u in range(na):
+            Z = X[u] * reg_S(D[u], s)
+            T = sum(gamma1[u, v] * Y[v] for v in range(na))
+            parts.append(_fsum(Z * T))
+    return math.fsum(parts)
+
+
+def energy_ccav(B_cv, B_ca, eps_c, eps_a, eps_v, gamma1, s) -> float:
+    """F3 of Table II after spin summation (eta-bar = 2 I - Gamma)."""
+    naux, nc, nv = B_cv.shape
+    na = B_ca.shape[2]
+    if na == 0 or s == 0.0:
+        return 0.0
+    etab = 2.0 * np.eye(na) - gamma1
+    # J[m][n][e, u] = (me|nu)
+    J = np.empty((nc, nc, nv, na))
+    for m in range(nc):
+        Bm = np.ascontiguousarray(B_cv[:, m, :])
+        for n in range(nc):
+            J[m, n] = Bm.T @ np.ascontiguousarray(B_ca[:, n, :])
+    parts = []
+    for m in range(nc):
+        for n in range(nc):
+            D = eps_c[m] + eps_c[n] - eps_v[:, None] - eps_a[None, :]   # D[e, u]
+            Z = J[m, n] * reg_S(D, s)                                  # (me|nv) S, column v
+            W = (2.0 * J[m, n] - J[n, m]) * reg_R1(D, s)               # [2(me|nu)-(mu|ne)] R1, column u
+            parts.append(_fsum(Z * (W @ etab)))                        # sum_uv etab_uv Z[:,v] W[:,u]
+    return math.fsum(parts)
+
+
+def energy_terms(p, terms=("ccvv", "cavv", "ccav")) -> Tuple[float, float, float]:
+    """(E_CCVV, E_CAVV, E_CCAV) for a workloads.Problem-like object."""
+    e1 = energy_ccvv(p.B_cv, p.eps_c, p.eps_v, p.s) if "ccvv" in terms else 0.0
+    e2 = (energy_cavv(p.B_cv, p.B_av, p.eps_c, p.eps_a, p.eps_v, p.gamma1, p.s)
+          if "cavv" in terms else 0.0)
+    e3 = (energy_ccav(p.B_cv, p.B_ca, p.eps_c, p.eps_a, p.eps_v, p.gamma1, p.s)
+          if "ccav" in terms else 0.0)
+    return e1, e2, e3
+
+
+def closed_shell_df_mp2(B_cv, eps_c, eps_v) -> float:
+    """Textbook closed-shell DF-MP2 correlation energy
+    sum_ijab (ia|jb)[2(ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b),
+    written with one four-index tensor (the s -> infinity limit of F1)."""
+    K = np.einsum("Qia,Qjb->iajb", B_cv, B_cv, optimize=True)
+    D = (eps_c[:, None, None, None] - eps_v[None, :, None, None]
+         + eps_c[None, None, :, None] - eps_v[None, None, None, :])
+    return _fsum(K * (2.0 * K - K.transpose(0, 3, 2, 1)) / D)
+
+
+# ---------------------------------------------------------------------------
+# gradients: dE/dB, dE/deps, dE/ds of sum_t gE[t] * E_t
+# ---------------------------------------------------------------------------
+def gradients(p, gE=(1.0, 1.0, 1.0)) -> Dict[str, np.ndarray]:
+    """Analytic gradient of gE[0] E_CCVV + gE[1] E_CAVV + gE[2] E_CCAV."""
+    B_cv, B_ca, B_av = p.B_cv, p.B_ca, p.B_av
+    eps_c, eps_a, eps_v, gam, s = p.eps_c, p.eps_a, p.eps_v, p.gamma1, p.s
+    naux, nc, nv = B_cv.shape
+    na = B_ca.shape[2]
+    g = dict(B_cv=np.zeros_like(B_cv), B_ca=np.zeros_like(B_ca),
+             B_av=np.zeros_like(B_av), eps_c=np.zeros(nc), eps_a=np.zeros(na),
+             eps_v=np.zeros(nv), s=np.zeros(1))
+    ds_parts = []
+    # ---- F1 (CCVV): E = sum_ij sum_ab P R,  P = K (2K - K^T) ----
+    if gE[0] != 0.0:
+        w = gE[0]
+        for i in range(nc):
+            Bi = np.ascontiguousarray(B_cv[:, i, :])
+            for j in range(nc):
+                Bj = np.ascontiguousarray(B_cv[:, j, :])
+                K = Bi.T @ Bj
+                D = eps_c[i] + eps_c[j] - eps_v[:, None] - eps_v[None, :]
+                R = reg_R(D, s)
+                G = 2.0 * R * (2.0 * K - K.T)          # dE/dK^{ij}_{ab}
+                # dE/dB_{Q,ia} = 2 sum_jb G^{ij}_{ab} B_{Q,jb}  (sum over ordered j)
+                g["B_cv"][:, i, :] += w * 2.0 * (Bj @ G.T)
+                P = K * (2.0 * K - K.T)
+                dD = P * dreg_R(D, s)
+                # D contains +e_i +e_j -e_a -e_b
+                g["eps_c"][i] += w * _fsum(dD)
+                g["eps_c"][j] += w * _fsum(dD)
+                g["eps_v"] -= w * (dD.sum(axis=1) + dD.sum(axis=0))
+                ds_parts.append(w * _fsum(P * sreg_R(D, s)))
+    # ---- F2 (CAVV) ----
+    if gE[1] != 0.0 and na > 0:
+        w = gE[1]
+        for m in range(nc):
+            Bm = np.ascontiguousarray(B_cv[:, m, :])
+            X = [Bm.T @ np.ascontiguousarray(B_av[:, u, :]) for u in range(na)]
+            D = [eps_c[m] + eps_a[u] - eps_v[:, None] - eps_v[None, :] for u in range(na)]
+            S = [reg_S(D[u], s) for u in range(na)]
+            R1 = [reg_R1(D[u], s) for u in range(na)]
+            Wt = [2.0 * X[u] - X[u].T for u in range(na)]
+            Y = [Wt[u] * R1[u] for u in range(na)]
+            Z = [X[u] * S[u] for u in range(na)]
+            A = [sum(gam[u, v] * Y[v] for v in range(na)) for u in range(na)]   # dE/dS^{mu} = X A
+            C = [sum(gam[u, v] * Z[u] for u in range(na)) for v in range(na)]   # dE/dR1^{mv} = W C
+            for x in range(na):
+                # dE/dX^{mx}_{ef}
+                Gx = S[x] * A[x] + R1[x] * (2.0 * C[x] - C[x].T)
+                g["B_cv"][:, m, :] += w * (np.ascontiguousarray(B_av[:, x, :]) @ Gx.T)
+                g["B_av"][:, x, :] += w * (Bm @ Gx)
+                dD = X[x] * A[x] * dreg_S(D[x], s) + Wt[x] * C[x] * dreg_R1(D[x], s)
+                g["eps_c"][m] += w * _fsum(dD)
+                g["eps_a"][x] += w * _fsum(dD)
+                g["eps_v"] -= w * (dD.sum(axis=1) + dD.sum(axis=0))
+                ds_parts.append(w * _fsum(X[x] * A[x] * sreg_S(D[x], s)
+                                          + Wt[x] * C[x] * sreg_R1(D[x], s)))
+    # ---- F3 (CCAV) ----
+    if gE[2] != 0.0 and na > 0:
+        w = gE[2]
+        etab = 2.0 * np.eye(na) - gam
+        J = np.empty((nc, nc, nv, na))
+        for m in range(nc):
+            Bm = np.ascontiguousarray(B_cv[:, m, :])
+            for n in range(nc):
+                J[m, n] = Bm.T @ np.ascontiguousarray(B_ca[:, n, :])
+        Dmn = {}
+        for m in range(nc):
+            for n in range(nc):
+                Dmn[m, n] = eps_c[m] + eps_c[n] - eps_v[:, None] - eps_a[None, :]
+        C3 = {}
+        for m in range(nc):
+            for n in range(nc):
+                Z3 = J[m, n] * reg_S(Dmn[m, n], s)
+                C3[m, n] = Z3 @ etab                    # C3[e,u] = sum_v etab_uv Z3[e,v]
+        for m in range(nc):
+            for n in range(nc):
+                D = Dmn[m, n]
+                Sx, R1x = reg_S(D, s), reg_R1(D, s)
+                Wt = 2.0 * J[m, n] - J[n, m]
+                A3 = (Wt * R1x) @ etab                  # A3[e,v] = sum_u etab_uv W3[e,u]
+                G3 = Sx * A3 + R1x * (2.0 * C3[m, n] - C3[n, m])   # dE/dJ^{mn}_{ew}
+                g["B_cv"][:, m, :] += w * (np.ascontiguousarray(B_ca[:, n, :]) @ G3.T)
+                g["B_ca"][:, n, :] += w * (np.ascontiguousarray(B_cv[:, m, :]) @ G3)
+                dD = J[m, n] * A3 * dreg_S(D, s) + Wt * C3[m, n] * dreg_R1(D, s)
+                g["eps_c"][m] += w * _fsum(dD)
+                g["eps_c"][n] += w * _fsum(dD)
+                g["eps_v"] -= w * dD.sum(axis=1)
+                g["eps_a"] -= w * dD.sum(axis=0)
+                ds_parts.append(w * _fsum(J[m, n] * A3 * sreg_S(D, s)
+                                          + Wt * C3[m, n] * sreg_R1(D, s)))
+    g["s"][0] = math.fsum(ds_parts)
+    return g
+
+
+# ---------------------------------------------------------------------------
+# spin-orbital brute force (Eq. expensive_term and Table II, tiny inputs)
+# ---------------------------------------------------------------------------
+def full_symmetric_B(B_cv, B_ca, B_av, rng=None, B_cc=None, B_aa=None, B_vv=None):
+    """Assemble a full B[Q][p][q] over spatial orbitals ordered C|A|V that is
+    symmetric in p<->q and whose cv, ca, av blocks are the given ones. The
+    remaining diagonal blocks (cc, aa, vv) are symmetric random unless given.
+    """
+    naux, nc, nv = B_cv.shape
+    na = B_ca.shape[2]
+    n = nc + na + nv
+    C, A, V = slice(0, nc), slice(nc, nc + na), slice(nc + na, n)
+    rng = np.random.default_rng(99) if rng is None else rng
+
+    def sym(k):
+        x = rng.standard_normal((naux, k, k)) * 0.05
+        return 0.5 * (x + x.transpose(0, 2, 1))
+
+    B = np.zeros((naux, n, n))
+    B[:, C, C] = sym(nc) if B_cc is None else B_cc
+    B[:, A, A] = sym(na) if B_aa is None else B_aa
+    B[:, V, V] = sym(nv) if B_vv is None else B_vv
+    B[:, C, V] = B_cv
+    B[:, V, C] = B_cv.transpose(0, 2, 1)
+    B[:, C, A] = B_ca
+    B[:, A, C] = B_ca.transpose(0, 2, 1)
+    B[:, A, V] = B_av
+    B[:, V, A] = B_av.transpose(0, 2, 1)
+    return B
+
+
+def brute_force_spinorbital(eri, nc, na, nv, eps, gamma1, s):
+    """Spin-orbital evaluation of term F (Eq. expensive_term) and of its
+    eight pieces F1..F8 (Table II), from the full chemists' tensor
+    eri[p,q,r,s] = (pq|rs) over spatial orbitals ordered C|A|V.
+
+    Spin orbitals are (spatial, spin); <pq||rs> = <pq|rs> - <pq|sr> with
+    <pq|rs> = (pr|qs) delta_spin. One-particle density: core 1, virtual 0,
+    active Gamma/2 in each spin block; eta = 1 - gamma. First-order T2
+    amplitudes t^{ij}_{ab} = v (1 - exp(-s D^2))/D for i,j in H = C+A and
+    a,b in P = A+V with the all-active block removed (section II.A); the
+    modified integrals carry 1 + exp(-s D^2) (Eq. v_tilde).
+
+    Returns dict(F=..., F1..F8=...).
+    """
+    n = nc + na + nv
+    ns = 2 * n
+    sp = np.arange(ns) // 2           # spatial index
+    sg = np.arange(ns) % 2            # spin
+    same = (sg[:, None] == sg[None, :]).astype(float)
+    # <pq|rs> = (pr|qs) d(sp,sr) d(sq,ss)
+    phys = eri[np.ix_(sp, sp, sp, sp)].transpose(0, 2, 1, 3)     # [p,q,r,s] = (pr|qs)
+    phys = phys * same[:, None, :, None] * same[None, :, None, :]
+    v = phys - phys.transpose(0, 1, 3, 2)
+    e = eps[sp]
+    # spin-orbital index sets
+    core = [p for p in range(ns) if sp[p] < nc]
+    act = [p for p in range(ns) if nc <= sp[p] < nc + na]
+    vir = [p for p in range(ns) if sp[p] >= nc + na]
+    H = core + act
+    P = act + vir
+    # densities on the full spin-orbital space
+    gam = np.zeros((ns, ns))
+    for p in core:
+        gam[p, p] = 1.0
+    for p in act:
+        for q in act:
+            if sg[p] == sg[q]:
+                gam[p, q] = 0.5 * gamma1[sp[p] - nc, sp[q] - nc]
+    eta = np.eye(ns) - gam
+    for p in core:
+        eta[p, p] = 0.0
+    # amplitudes t[i,j,a,b] (i,j in H; a,b in P) and modified integrals vt
+    iH, iP = np.array(H), np.array(P)
+    vHP = v[np.ix_(iH, iH, iP, iP)]
+    Dl = (e[iH][:, None, None, None] + e[iH][None, :, None, None]
+          - e[iP][None, None, :, None] - e[iP][None, None, None, :])
+    t = vHP * reg_R1(Dl, s)
+    vt = vHP * reg_S(Dl, s)
+    isA_H = np.array([p in act for p in H])
+    isA_P = np.array([p in act for p in P])
+    allact = (isA_H[:, None, None, None] & isA_H[None, :, None, None]
+              & isA_P[None, None, :, None] & isA_P[None, None, None, :])
+    t[allact] = 0.0
+    vt[allact] = 0.0
+    gH = gam[np.ix_(iH, iH)]
+    eP = eta[np.ix_(iP, iP)]
+    # Eq. expensive_term: F = 1/4 vt[k,l,c,d] t[i,j,a,b] g[k,i] g[l,j] eta[a,c] eta[b,d]
+    F = 0.25 * np.einsum("klcd,ijab,ki,lj,ac,bd->", vt, t, gH, gH, eP, eP, optimize=True)
+    # Table II pieces, each with its own index ranges
+    pos_H = {p: k for k, p in enumerate(H)}
+    pos_P = {p: k for k, p in enumerate(P)}
+    hc = [pos_H[p] for p in core]
+    ha = [pos_H[p] for p in act]
+    pa = [pos_P[p] for p in act]
+    pv = [pos_P[p] for p in vir]
+    gA = gam[np.ix_(act, act)]
+    eA = eta[np.ix_(act, act)]
+
+    def blk(x, i1, i2, i3, i4):
+        return x[np.ix_(i1, i2, i3, i4)]
+
+    F1 = 0.25 * np.einsum("mnef,mnef->", blk(vt, hc, hc, pv, pv), blk(t, hc, hc, pv, pv))
+    F2 = 0.5 * np.einsum("muef,mvef,uv->", blk(vt, hc, ha, pv, pv), blk(t, hc, ha, pv, pv), gA)
+    F3 = 0.5 * np.einsum("mnev,mneu,uv->", blk(vt, hc, hc, pv, pa), blk(t, hc, hc, pv, pa), eA)
+    F4 = 0.25 * np.einsum("xuef,yvef,xy,uv->", blk(vt, ha, ha, pv, pv), blk(t, ha, ha, pv, pv), gA, gA)
+    F5 = 0.25 * np.einsum("mnvy,mnux,uv,xy->", blk(vt, hc, hc, pa, pa), blk(t, hc, hc, pa, pa), eA, eA)
+    F6 = np.einsum("mxve,myue,xy,uv->", blk(vt, hc, ha, pa, pv), blk(t, hc, ha, pa, pv), gA, eA)
+    F7 = 0.5 * np.einsum("yzve,wxue,yw,zx,uv->", blk(vt, ha, ha, pa, pv), blk(t, ha, ha, pa, pv), gA, gA, eA)
+    F8 = 0.5 * np.einsum("mwvy,mzux,wz,uv,xy->", blk(vt, hc, ha, pa, pa), blk(t, hc, ha, pa, pa), gA, eA, eA)
+    return dict(F=F, F1=F1, F2=F2, F3=F3, F4=F4, F5=F5, F6=F6, F7=F7, F8=F8)
+
+
+def pivoted_cholesky(M: np.ndarray, tol: float = 0.0) -> np.ndarray:
+    """Pivoted Cholesky of a symmetric PSD matrix M ~= L L^T (the numerical
+    decomposition that generates CD factors, section II.C). Stops when the
+    largest remaining diagonal is <= tol. Returns L with shape (n, rank)."""
+    M = np.array(M, dtype=np.float64)
+    n = M.shape[0]
+    d = np.diag(M).copy()
+    cols = []
+    for _ in range(n):
+        p = int(np.argmax(d))
+        if d[p] <= tol:
+            break
+        col = M[:, p].copy()
+        for c in cols:
+            col -= c * c[p]
+        col /= math.sqrt(d[p])
+        cols.append(col)
+        d -= col * col
+        d[p] = 0.0
+    return np.array(cols).T if cols else np.zeros((n, 0))

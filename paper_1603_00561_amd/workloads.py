@@ -1,0 +1,144 @@
+"""Seeded synthetic DF-DSRG-MRPT2 problems.
+
+This module only draws random numbers; it holds none of the method's
+arithmetic, so both the HIP path and the CPU oracle can take their inputs
+from it.
+
+The paper's timing study (section V.B, Table VIII) runs singlet
+(2,3)-naphthyne with cc-pVXZ / cc-pVXZ-RI bases; neither the geometries nor
+the bases are available here, so seeded synthetic tensors of the same block
+shapes stand in for them:
+
+* B^Q_pq blocks (the density-fitting / Cholesky factors of Eq. int_fact):
+  N(0,1) * 0.05 * exp(-3 Q / naux), Q counted from 0, in the order
+  B_cv [naux][nc][nv], B_ca [naux][nc][na], B_av [naux][na][nv].
+* semicanonical orbital energies (diagonal generalized Fock, section II.B):
+  core U[-2.0, -0.3], active U[-0.3, 0.1], virtual U[0.1, 5.0] Eh.
+* spin-summed active 1-RDM Gamma = O diag(lam) O^T, O from the QR of a
+  standard-normal matrix with diag(R) > 0, lam_k = 1 + (v_k - mean v) /
+  max(1, max_k |v_k - mean v|), v ~ U[-1, 1]: eigenvalues in [0, 2], trace na.
+
+One ``numpy.random.default_rng(seed)`` per problem, drawn in exactly the
+order listed above.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+DEFAULT_SEED = 1603
+
+
+@dataclass
+class Problem:
+    """One DF-DSRG-MRPT2 F1-F3 problem (host arrays, float64, C order)."""
+
+    nc: int
+    na: int
+    nv: int
+    naux: int
+    B_cv: np.ndarray          # [naux][nc][nv]
+    B_ca: np.ndarray          # [naux][nc][na]
+    B_av: np.ndarray          # [naux][na][nv]
+    eps_c: np.ndarray         # [nc]
+    eps_a: np.ndarray         # [na]
+    eps_v: np.ndarray         # [nv]
+    gamma1: np.ndarray        # [na][na] spin-summed, symmetric
+    s: float                  # flow parameter, Eh^-2
+    name: str = "custom"
+    seed: Optional[int] = None
+    meta: dict = field(default_factory=dict)
+
+    def arrays(self):
+        return (self.B_cv, self.B_ca, self.B_av, self.eps_c, self.eps_a,
+                self.eps_v, self.gamma1)
+
+    def with_s(self, s: float) -> "Problem":
+        return Problem(self.nc, self.na, self.nv, self.naux, self.B_cv,
+                       self.B_ca, self.B_av, self.eps_c, self.eps_a,
+                       self.eps_v, self.gamma1, float(s), self.name,
+                       self.seed, dict(self.meta))
+
+
+# The five workload shapes: (nc, na, nv, naux, s, terms, gradient wanted).
+# cfg1: small case the oracle finishes in seconds (CCVV only).
+# cfg2: triple-zeta-shaped naphthyne, all three terms, FP64.
+# cfg3: larger triple-zeta-like case, s in {0.1, 0.5, 1.0}, split precision.
+# cfg4: energy + gradient case.
+# cfg5: quintuple-zeta-shaped case, energy + gradient.
+CONFIGS = {
+    "cfg1": dict(nc=8, na=4, nv=40, naux=160, s=0.5, terms=("ccvv",), grad=False),
+    "cfg2": dict(nc=23, na=2, nv=380, naux=1100, s=0.5,
+                 terms=("ccvv", "cavv", "ccav"), grad=False),
+    "cfg3": dict(nc=23, na=2, nv=700, naux=2000, s=0.5,
+                 terms=("ccvv", "cavv", "ccav"), grad=False, s_list=(0.1, 0.5, 1.0)),
+    "cfg4": dict(nc=16, na=4, nv=300, naux=900, s=0.5,
+                 terms=("ccvv", "cavv", "ccav"), grad=True),
+    "cfg5": dict(nc=23, na=6, nv=1100, naux=3000, s=0.5,
+                 terms=("ccvv", "cavv", "ccav"), grad=True),
+}
+
+
+def _gamma(rng: np.random.Generator, na: int) -> np.ndarray:
+    if na == 0:
+        return np.zeros((0, 0))
+    g = rng.standard_normal((na, na))
+    q, r = np.linalg.qr(g)
+    q = q * np.sign(np.diag(r))[None, :]
+    v = rng.uniform(-1.0, 1.0, size=na)
+    dv = v - v.mean()
+    lam = 1.0 + dv / max(1.0, float(np.max(np.abs(dv))))
+    gam = (q * lam[None, :]) @ q.T
+    return 0.5 * (gam + gam.T)
+
+
+def make_problem(nc: int, na: int, nv: int, naux: int, s: float = 0.5,
+                 seed: int = DEFAULT_SEED, name: str = "custom",
+                 b_scale: float = 0.05, b_decay: float = 3.0) -> Problem:
+    """Draw one seeded problem with the recipe in the module docstring."""
+    rng = np.random.default_rng(seed)
+    q = np.arange(naux, dtype=np.float64)
+    scale = (b_scale * np.exp(-b_decay * q / max(naux, 1)))[:, None, None]
+    B_cv = rng.standard_normal((naux, nc, nv)) * scale
+    B_ca = rng.standard_normal((naux, nc, na)) * scale
+    B_av = rng.standard_normal((naux, na, nv)) * scale
+    eps_c = rng.uniform(-2.0, -0.3, size=nc)
+    eps_a = rng.uniform(-0.3, 0.1, size=na)
+    eps_v = rng.uniform(0.1, 5.0, size=nv)
+    gamma1 = _gamma(rng, na)
+    return Problem(nc, na, nv, naux, B_cv, B_ca, B_av, eps_c, eps_a, eps_v,
+                   gamma1, float(s), name, seed)
+
+
+def make_config(name: str, seed: int = DEFAULT_SEED, s: Optional[float] = None) -> Problem:
+    c = CONFIGS[name]
+    p = make_problem(c["nc"], c["na"], c["nv"], c["naux"],
+                     c["s"] if s is None else s, seed=seed, name=name)
+    p.meta = {k: v for k, v in c.items()}
+    return p
+
+
+def make_near_degenerate(nc: int = 3, na: int = 2, nv: int = 20, naux: int = 48,
+                         seed: int = 7, s: float = 0.5) -> Problem:
+    """A problem whose orbital energies put many denominators near zero
+    (|Delta| down to ~1e-3 Eh), so that s*Delta^2 spans the small-argument
+    regime of the regulariser. Core energies are drawn first, then every
+    virtual and active energy is set to a random core-pair mean plus a small
+    random offset."""
+    rng = np.random.default_rng(seed)
+    q = np.arange(naux, dtype=np.float64)
+    scale = (0.05 * np.exp(-3.0 * q / naux))[:, None, None]
+    B_cv = rng.standard_normal((naux, nc, nv)) * scale
+    B_ca = rng.standard_normal((naux, nc, na)) * scale
+    B_av = rng.standard_normal((naux, na, nv)) * scale
+    eps_c = rng.uniform(-0.6, -0.3, size=nc)
+    pick_v = rng.integers(0, nc, size=(nv, 2))
+    off_v = rng.uniform(-2e-3, 2e-3, size=nv) * rng.choice([1e-3, 1e-1, 1.0], size=nv)
+    eps_v = eps_c[pick_v].sum(axis=1) / 2.0 + off_v
+    pick_a = rng.integers(0, nc, size=na)
+    eps_a = eps_c[pick_a] + rng.uniform(-2e-3, 2e-3, size=na)
+    gamma1 = _gamma(rng, na)
+    return Problem(nc, na, nv, naux, B_cv, B_ca, B_av, eps_c, eps_a, eps_v,
+                   gamma1, float(s), "near_degenerate", seed)
