@@ -1,0 +1,157 @@
+/*
+ * dsrg_df.h - C ABI of libdsrgdf, the MI355X (gfx950) library for the
+ * density-fitted DSRG-MRPT2 energy terms F1 (CCVV), F2 (CAVV) and F3 (CCAV).
+ *
+ * What is computed (Hannon, Li, Evangelista, "An integral-factorized
+ * implementation of the driven similarity renormalization group second-order
+ * multireference perturbation theory"):
+ *
+ *   The three pieces of term F (Eq. expensive_term) that Table II names F1,
+ *   F2 and F3, after spin summation over restricted core / virtual orbitals
+ *   with a spin-summed active density Gamma:
+ *
+ *   E_CCVV = sum_{ij in C} sum_{ab in V} (ia|jb) [2(ia|jb) - (ib|ja)] R(D^{ab}_{ij})
+ *   E_CAVV = sum_{uv} Gamma_uv sum_m sum_{ef} (me|uf) S(D^{ef}_{mu})
+ *                                   [2(me|vf) - (mf|ve)] R1(D^{ef}_{mv})
+ *   E_CCAV = sum_{uv} (2 delta_uv - Gamma_uv) sum_{mn} sum_e (me|nv) S(D^{ev}_{mn})
+ *                                   [2(me|nu) - (mu|ne)] R1(D^{eu}_{mn})
+ *
+ *   with (pq|rs) = sum_Q B^Q_pq B^Q_rs (Eq. int_fact), the Moller-Plesset
+ *   denominator D^{ab}_{ij} = e_i + e_j - e_a - e_b (section II.B), and the
+ *   regularisers R(D) = (1 - exp(-2 s D^2))/D (Eq. expensive),
+ *   R1(D) = (1 - exp(-s D^2))/D (Eq. T2amp), S(D) = 1 + exp(-s D^2)
+ *   (Eq. v_tilde). No four-index tensor is ever stored (section III).
+ *
+ * Conventions shared by every entry point:
+ *   - Every array pointer is HIP device memory owned by the caller, FP64,
+ *     C (row-major) order, 8-byte aligned. Nothing is retained after return.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls only enqueue work on it: they never synchronise and never
+ *     allocate device memory. The caller keeps inputs, outputs and the
+ *     workspace alive until that work completes.
+ *   - Outputs are overwritten, never accumulated into.
+ *   - Every argument is validated on the host before anything is enqueued.
+ *     On any error the call returns a non-zero status, enqueues nothing and
+ *     leaves every output untouched; dsrg_df_last_error() then describes it.
+ *     NaN or Inf inside B or the orbital energies is not checked; it
+ *     propagates into the results.
+ *   - Not re-entrant on one workspace: two calls that overlap in time must
+ *     use different workspaces.
+ */
+#ifndef DSRG_DF_H
+#define DSRG_DF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSRG_OK = 0,
+  DSRG_ERR_ARG = 1,          /* invalid argument (null, bad size, bad value)   */
+  DSRG_ERR_UNSUPPORTED = 2,  /* valid but not supported (e.g. na too large)    */
+  DSRG_ERR_WORKSPACE = 3,    /* workspace missing or smaller than required     */
+  DSRG_ERR_HIP = 4           /* the HIP runtime refused a launch               */
+} dsrg_status;
+
+/* Arithmetic of the (pq|rs) contractions. Denominators, regularisers and
+ * every energy accumulation are FP64 in all modes. */
+typedef enum {
+  DSRG_FP64 = 0,        /* FP64 matrix-core contractions                         */
+  DSRG_SPLIT_BF16 = 1,  /* B = hi + lo in BF16, three products, FP32 accumulate  */
+  DSRG_SPLIT_OZAKI = 2  /* error-free int8 slices of B, exact int32 accumulate   */
+} dsrg_precision;
+
+/* Term mask bits (argument `terms`). */
+enum {
+  DSRG_TERM_CCVV = 1,   /* F1 */
+  DSRG_TERM_CAVV = 2,   /* F2 */
+  DSRG_TERM_CCAV = 4,   /* F3 */
+  DSRG_TERM_ALL = 7,
+  /* Option bit: reduce tile partial energies with FP64 atomics into one slot
+   * per term instead of one slot per workgroup. Results then depend on the
+   * order in which workgroups finish (last-bit differences run to run). */
+  DSRG_OPT_ATOMIC_REDUCE = 0x100,
+  /* Option bit: record a HIP event pair around every kernel the call
+   * enqueues, so dsrg_df_kernel_times() can report per-kernel durations. */
+  DSRG_OPT_KERNEL_TIMING = 0x200
+};
+
+/* One problem. Orbitals are ordered core | active | virtual; only the three
+ * off-diagonal blocks of B that F1-F3 touch are read, and B is taken to be
+ * symmetric in its two orbital indices (real orbitals), so the transposed
+ * blocks are never needed. */
+typedef struct {
+  int64_t nc;            /* correlated core orbitals, >= 1 (frozen core excluded)  */
+  int64_t na;            /* active orbitals, >= 0                                  */
+  int64_t nv;            /* virtual orbitals, >= 1                                 */
+  int64_t naux;          /* auxiliary (DF) or Cholesky vectors M, >= 1             */
+  const double *B_cv;    /* [naux][nc][nv]  B^Q_{me}                               */
+  const double *B_ca;    /* [naux][nc][na]  B^Q_{mu}  (may be NULL when na == 0)   */
+  const double *B_av;    /* [naux][na][nv]  B^Q_{ue}  (may be NULL when na == 0)   */
+  const double *eps_c;   /* [nc] semicanonical core orbital energies, Eh           */
+  const double *eps_a;   /* [na] semicanonical active orbital energies (NULL if 0) */
+  const double *eps_v;   /* [nv] semicanonical virtual orbital energies            */
+  const double *gamma1;  /* [na][na] spin-summed active 1-RDM, symmetric (NULL if 0)*/
+  double s;              /* flow parameter, Eh^-2, finite and >= 0                 */
+} dsrg_df_problem;
+
+/* Largest na the CAVV and CCAV kernels are compiled for. */
+#define DSRG_DF_MAX_ACTIVE 8
+
+/* Bytes of device workspace that dsrg_df_energy (with_grad == 0) or
+ * dsrg_df_energy_backward (with_grad != 0) needs for this problem,
+ * precision and term mask. Reads only the sizes in *p (no pointer is
+ * dereferenced). Returns DSRG_OK and stores the size in *bytes. */
+dsrg_status dsrg_df_workspace_size(const dsrg_df_problem *p, int precision,
+                                   int terms, int with_grad, size_t *bytes);
+
+/* Energies of the selected terms (Table II F1, F2, F3).
+ *   E_terms   device [3]: E_CCVV, E_CAVV, E_CCAV in Eh; unselected terms are 0.
+ *   workspace device buffer of at least dsrg_df_workspace_size(...) bytes,
+ *             256-byte aligned; its contents on entry do not matter.
+ * The energies are exactly 0 for s == 0 and tend to the closed-shell DF-MP2
+ * form of Eq. expensive as s grows. */
+dsrg_status dsrg_df_energy(const dsrg_df_problem *p, int precision, int terms,
+                           double *E_terms, void *workspace, size_t ws_bytes,
+                           void *stream);
+
+/* Gradient of L = sum_t gE[t] * E_t with respect to every input that the
+ * energy depends on (the adjoint of dsrg_df_energy; amplitudes are
+ * recomputed, never stored).
+ *   gE                   device [3]: dL/dE_CCVV, dL/dE_CAVV, dL/dE_CCAV
+ *   dB_cv, dB_ca, dB_av  device, shapes as B_cv, B_ca, B_av (dB_ca, dB_av may be
+ *                        NULL when na == 0)
+ *   deps_c, deps_a, deps_v  device [nc], [na], [nv]
+ *   ds                   device [1]
+ *   E_terms              optional device [3] (NULL = not wanted): the energies
+ * Terms outside `terms` contribute nothing. */
+dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int terms,
+                                    const double *gE,
+                                    double *dB_cv, double *dB_ca, double *dB_av,
+                                    double *deps_c, double *deps_a, double *deps_v,
+                                    double *ds, double *E_terms,
+                                    void *workspace, size_t ws_bytes, void *stream);
+
+/* Text of the last error raised on the calling thread ("" if none). Valid
+ * until the next dsrg_df_* call on that thread. */
+const char *dsrg_df_last_error(void);
+
+/* Per-kernel device durations (milliseconds) recorded on this thread by the
+ * calls that set DSRG_OPT_KERNEL_TIMING since the previous read (at most 512
+ * kernels; later ones are not recorded). Waits for those kernels to finish,
+ * writes at most `cap` entries to ms[] and, if names != NULL, a static name
+ * per entry, clears the record and returns the number of kernels recorded
+ * (-1 if an event could not be read). Entries are in launch order. */
+int dsrg_df_kernel_times(double *ms, const char **names, int cap);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int dsrg_df_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSRG_DF_H */

@@ -1,0 +1,191 @@
+"""Thin Python binding of libdsrgdf (ctypes).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library. PyTorch supplies device memory and the current stream. There is no
+CPU fallback; if the library is missing this module raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Union
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsrgdf.so")
+
+DSRG_OK, DSRG_ERR_ARG, DSRG_ERR_UNSUPPORTED, DSRG_ERR_WORKSPACE, DSRG_ERR_HIP = range(5)
+PRECISIONS = {"fp64": 0, "split_bf16": 1, "ozaki": 2}
+TERM_BITS = {"ccvv": 1, "cavv": 2, "ccav": 4}
+TERM_ALL = 7
+OPT_ATOMIC_REDUCE = 0x100
+OPT_KERNEL_TIMING = 0x200
+MAX_ACTIVE = 8
+
+EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward",
+            "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_version")
+
+
+class DsrgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libdsrgdf status {status}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("nc", ctypes.c_int64), ("na", ctypes.c_int64), ("nv", ctypes.c_int64),
+        ("naux", ctypes.c_int64),
+        ("B_cv", ctypes.c_void_p), ("B_ca", ctypes.c_void_p), ("B_av", ctypes.c_void_p),
+        ("eps_c", ctypes.c_void_p), ("eps_a", ctypes.c_void_p), ("eps_v", ctypes.c_void_p),
+        ("gamma1", ctypes.c_void_p),
+        ("s", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libdsrgdf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libdsrgdf.so not found at {path}; build it first "
+            "(python -m paper_1603_00561_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    lib.dsrg_df_workspace_size.argtypes = [ctypes.POINTER(Problem), i32, i32, i32,
+                                           ctypes.POINTER(sz)]
+    lib.dsrg_df_workspace_size.restype = i32
+    lib.dsrg_df_energy.argtypes = [ctypes.POINTER(Problem), i32, i32, vp, vp, sz, vp]
+    lib.dsrg_df_energy.restype = i32
+    lib.dsrg_df_energy_backward.argtypes = [ctypes.POINTER(Problem), i32, i32, vp,
+                                            vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.dsrg_df_energy_backward.restype = i32
+    lib.dsrg_df_last_error.argtypes = []
+    lib.dsrg_df_last_error.restype = ctypes.c_char_p
+    lib.dsrg_df_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_char_p), i32]
+    lib.dsrg_df_kernel_times.restype = i32
+    lib.dsrg_df_version.argtypes = []
+    lib.dsrg_df_version.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != DSRG_OK:
+        msg = load_library().dsrg_df_last_error().decode(errors="replace")
+        raise DsrgError(status, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def kernel_times(cap: int = 32):
+    """[(kernel name, ms)] of the last call made with timing=True on this
+    thread (waits for that work to finish)."""
+    lib = load_library()
+    ms = (ctypes.c_double * cap)()
+    names = (ctypes.c_char_p * cap)()
+    n = lib.dsrg_df_kernel_times(ms, names, cap)
+    if n < 0:
+        raise DsrgError(DSRG_ERR_HIP, "could not read kernel timing events")
+    return [(names[k].decode(), ms[k]) for k in range(min(n, cap))]
+
+
+def _terms_mask(terms: Union[str, int, Sequence[str]], atomic: bool, timing: bool = False) -> int:
+    if isinstance(terms, int):
+        m = terms
+    elif terms == "all":
+        m = TERM_ALL
+    elif isinstance(terms, str):
+        m = TERM_BITS[terms]
+    else:
+        m = 0
+        for t in terms:
+            m |= TERM_BITS[t]
+    return m | (OPT_ATOMIC_REDUCE if atomic else 0) | (OPT_KERNEL_TIMING if timing else 0)
+
+
+def _as_dev(t: Optional[torch.Tensor], name: str, shape, device) -> Optional[torch.Tensor]:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU (got {t.device}); there is no CPU path")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64 (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t.contiguous()
+
+
+def make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s):
+    """Validate tensors and fill the C problem struct. Returns (struct, kept
+    tensors) so the caller keeps the contiguous copies alive."""
+    naux, nc, nv = B_cv.shape
+    na = 0 if B_ca is None else B_ca.shape[2]
+    dev = B_cv.device
+    keep = [
+        _as_dev(B_cv, "B_cv", (naux, nc, nv), dev),
+        _as_dev(B_ca, "B_ca", (naux, nc, na), dev) if na else None,
+        _as_dev(B_av, "B_av", (naux, na, nv), dev) if na else None,
+        _as_dev(eps_c, "eps_c", (nc,), dev),
+        _as_dev(eps_a, "eps_a", (na,), dev) if na else None,
+        _as_dev(eps_v, "eps_v", (nv,), dev),
+        _as_dev(gamma1, "gamma1", (na, na), dev) if na else None,
+    ]
+    p = Problem(nc, na, nv, naux, *[_ptr(t) for t in keep], float(s))
+    return p, keep
+
+
+def workspace_size(nc, na, nv, naux, precision="fp64", terms="all", with_grad=False,
+                   atomic=False) -> int:
+    lib = load_library()
+    p = Problem(nc, na, nv, naux, None, None, None, None, None, None, None, 0.5)
+    out = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_workspace_size(ctypes.byref(p), PRECISIONS[precision],
+                                      _terms_mask(terms, atomic), int(bool(with_grad)),
+                                      ctypes.byref(out)))
+    return out.value
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.Tensor:
+    if workspace is not None:
+        if workspace.device != device or workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError("workspace is too small or on the wrong device")
+        return workspace
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def energy(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
+           terms="all", atomic=False, workspace: Optional[torch.Tensor] = None,
+           timing: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """E_CCVV, E_CAVV, E_CCAV (device tensor [3], float64) via dsrg_df_energy."""
+    lib = load_library()
+    p, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s)
+    dev = B_cv.device
+    mask = _terms_mask(terms, atomic, timing)
+    prec = PRECISIONS[precision]
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_workspace_size(ctypes.byref(p), prec, mask, 0, ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    E = torch.empty(3, dtype=torch.float64, device=dev) if out is None else out
+    _check(lib.dsrg_df_energy(ctypes.byref(p), prec, mask, E.data_ptr(), ws.data_ptr(),
+                              nbytes.value, _stream_handle(dev)))
+    del keep
+    return E

@@ -1,0 +1,243 @@
+// Host side of the libdsrgdf C ABI: argument validation, workspace planning
+// and kernel launches. Nothing here allocates device memory or waits on the
+// device; every error is found before the first launch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "../../include/dsrg_df.h"
+#include "internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+dsrg_status fail(dsrg_status code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+// ---- per-kernel timing: one table per host thread ----
+// Calls that set DSRG_OPT_KERNEL_TIMING append an event pair per kernel;
+// dsrg_df_kernel_times() reads and clears the table.
+struct TimerTable {
+  static constexpr int kMax = 512;
+  hipEvent_t ev[2 * kMax] = {};
+  const char *name[kMax] = {};
+  int n = 0;          // kernels recorded since the last read
+  int created = 0;    // events created so far
+  int device = -1;
+  bool active = false;
+};
+thread_local TimerTable g_timer;
+
+void timer_reset(bool on) {
+  g_timer.active = false;
+  if (!on) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (g_timer.device != dev) {
+    for (int k = 0; k < g_timer.created; ++k) (void)hipEventDestroy(g_timer.ev[k]);
+    g_timer.created = 0;
+    g_timer.n = 0;
+    g_timer.device = dev;
+  }
+  g_timer.active = true;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// Validate sizes, scalar arguments and the option bits; fill the plan.
+dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int with_grad,
+                      dsrg::Plan &pl) {
+  using namespace dsrg;
+  if (!p) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  if (p->nc < 1) return fail(DSRG_ERR_ARG, "nc must be >= 1 (got %lld)", (long long)p->nc);
+  if (p->nv < 1) return fail(DSRG_ERR_ARG, "nv must be >= 1 (got %lld)", (long long)p->nv);
+  if (p->naux < 1) return fail(DSRG_ERR_ARG, "naux must be >= 1 (got %lld)", (long long)p->naux);
+  if (p->na < 0) return fail(DSRG_ERR_ARG, "na must be >= 0 (got %lld)", (long long)p->na);
+  if (!(p->s >= 0.0) || !isfinite(p->s))
+    return fail(DSRG_ERR_ARG, "s must be finite and >= 0 (got %g)", p->s);
+  if (precision != DSRG_FP64 && precision != DSRG_SPLIT_BF16 && precision != DSRG_SPLIT_OZAKI)
+    return fail(DSRG_ERR_ARG, "unknown precision %d", precision);
+  const int term_bits = terms & DSRG_TERM_ALL;
+  if (term_bits == 0) return fail(DSRG_ERR_ARG, "term mask selects no term (0x%x)", terms);
+  if (terms & ~(DSRG_TERM_ALL | DSRG_OPT_ATOMIC_REDUCE | DSRG_OPT_KERNEL_TIMING))
+    return fail(DSRG_ERR_ARG, "unknown bits in term mask 0x%x", terms);
+  const bool need_act = p->na > 0 && (term_bits & (DSRG_TERM_CAVV | DSRG_TERM_CCAV));
+  if (need_act && p->na > DSRG_DF_MAX_ACTIVE)
+    return fail(DSRG_ERR_UNSUPPORTED, "na = %lld exceeds the compiled maximum %d",
+                (long long)p->na, DSRG_DF_MAX_ACTIVE);
+  // index ranges used by the kernels (int for orbital indices, int64 offsets)
+  if (p->nc > (1 << 20) || p->nv > (1 << 24) || p->naux > (1 << 24))
+    return fail(DSRG_ERR_UNSUPPORTED, "dimensions too large (nc %lld, nv %lld, naux %lld)",
+                (long long)p->nc, (long long)p->nv, (long long)p->naux);
+  if (precision != DSRG_FP64)
+    return fail(DSRG_ERR_UNSUPPORTED, "precision %d is not available in this build", precision);
+  if (with_grad) return fail(DSRG_ERR_UNSUPPORTED, "gradients are not available in this build");
+
+  pl.nc = p->nc;
+  pl.na = p->na;
+  pl.nv = p->nv;
+  pl.naux = p->naux;
+  pl.s = p->s;
+  pl.precision = precision;
+  pl.terms = term_bits;
+  pl.atomic_reduce = (terms & DSRG_OPT_ATOMIC_REDUCE) != 0;
+  pl.with_grad = with_grad != 0;
+  pl.naux_p = round_up(pl.naux, kChunk);
+  pl.ntv = ceil_div(pl.nv, kPanel);
+  pl.cavv_tile = (pl.na <= 2) ? 64 : 32;
+
+  const int64_t npo = tri_off(pl.nc), ntpo = tri_off(pl.ntv);
+  pl.n_ccvv = (term_bits & DSRG_TERM_CCVV)
+                  ? (npo * ntpo + npo * pl.ntv + pl.nc * ntpo + pl.nc * pl.ntv)
+                  : 0;
+  const int64_t ntw = ceil_div(pl.nv, pl.cavv_tile);
+  pl.n_cavv = ((term_bits & DSRG_TERM_CAVV) && pl.na > 0) ? pl.nc * (tri_off(ntw) + ntw) : 0;
+  pl.n_ccav =
+      ((term_bits & DSRG_TERM_CCAV) && pl.na > 0) ? (pl.nc * (pl.nc + 1) / 2) * pl.ntv : 0;
+  const int64_t maxgrid = ((int64_t)1 << 31) - 1;
+  if (pl.n_ccvv > maxgrid || pl.n_cavv > maxgrid || pl.n_ccav > maxgrid)
+    return fail(DSRG_ERR_UNSUPPORTED, "work list exceeds one launch grid");
+
+  size_t off = 0;
+  pl.off_pcv = off;
+  off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.ntv * pl.naux_p * kPanel));
+  pl.off_pav = off;
+  if (pl.na > 0 && (term_bits & DSRG_TERM_CAVV))
+    off = align256(off + sizeof(double) * (size_t)(pl.na * pl.ntv * pl.naux_p * kPanel));
+  pl.off_pca = off;
+  if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV))
+    off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.naux_p * kActPanel));
+  pl.off_slots = off;
+  pl.slot_base[0] = 0;
+  pl.slot_base[1] = pl.n_ccvv;
+  pl.slot_base[2] = pl.n_ccvv + pl.n_cavv;
+  off = align256(off + sizeof(double) * (size_t)(pl.n_ccvv + pl.n_cavv + pl.n_ccav + 1));
+  pl.off_acc = off;
+  off = align256(off + sizeof(double) * 4);
+  pl.total = off;
+  return DSRG_OK;
+}
+
+dsrg_status check_inputs(const dsrg_df_problem *p, const dsrg::Plan &pl) {
+  if (!p->B_cv || !aligned8(p->B_cv)) return fail(DSRG_ERR_ARG, "B_cv is NULL or misaligned");
+  if (!p->eps_c || !aligned8(p->eps_c)) return fail(DSRG_ERR_ARG, "eps_c is NULL or misaligned");
+  if (!p->eps_v || !aligned8(p->eps_v)) return fail(DSRG_ERR_ARG, "eps_v is NULL or misaligned");
+  const bool cavv = pl.na > 0 && (pl.terms & DSRG_TERM_CAVV);
+  const bool ccav = pl.na > 0 && (pl.terms & DSRG_TERM_CCAV);
+  if (cavv && (!p->B_av || !aligned8(p->B_av)))
+    return fail(DSRG_ERR_ARG, "B_av is NULL or misaligned");
+  if (ccav && (!p->B_ca || !aligned8(p->B_ca)))
+    return fail(DSRG_ERR_ARG, "B_ca is NULL or misaligned");
+  if ((cavv || ccav) && (!p->eps_a || !aligned8(p->eps_a)))
+    return fail(DSRG_ERR_ARG, "eps_a is NULL or misaligned");
+  if ((cavv || ccav) && (!p->gamma1 || !aligned8(p->gamma1)))
+    return fail(DSRG_ERR_ARG, "gamma1 is NULL or misaligned");
+  return DSRG_OK;
+}
+
+dsrg_status check_workspace(const dsrg::Plan &pl, void *ws, size_t ws_bytes) {
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!ws) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  return DSRG_OK;
+}
+
+}  // namespace
+
+namespace dsrg {
+void timer_begin(const char *name, hipStream_t st) {
+  TimerTable &t = g_timer;
+  if (!t.active || t.n >= TimerTable::kMax) return;
+  while (t.created < 2 * (t.n + 1)) {
+    if (hipEventCreate(&t.ev[t.created]) != hipSuccess) {
+      t.active = false;
+      return;
+    }
+    ++t.created;
+  }
+  t.name[t.n] = name;
+  (void)hipEventRecord(t.ev[2 * t.n], st);
+}
+void timer_end(hipStream_t st) {
+  TimerTable &t = g_timer;
+  if (!t.active || t.n >= TimerTable::kMax) return;
+  (void)hipEventRecord(t.ev[2 * t.n + 1], st);
+  ++t.n;
+}
+}  // namespace dsrg
+
+extern "C" {
+
+dsrg_status dsrg_df_workspace_size(const dsrg_df_problem *p, int precision, int terms,
+                                   int with_grad, size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::Plan pl;
+  dsrg_status st = make_plan(p, precision, terms, with_grad, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_energy(const dsrg_df_problem *p, int precision, int terms, double *E_terms,
+                           void *workspace, size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  dsrg::Plan pl;
+  dsrg_status st = make_plan(p, precision, terms, 0, pl);
+  if (st != DSRG_OK) return st;
+  if ((st = check_inputs(p, pl)) != DSRG_OK) return st;
+  if (!E_terms || !aligned8(E_terms)) return fail(DSRG_ERR_ARG, "E_terms is NULL or misaligned");
+  if ((st = check_workspace(pl, workspace, ws_bytes)) != DSRG_OK) return st;
+
+  dsrg::Inputs in{p->B_cv, p->B_ca, p->B_av, p->eps_c, p->eps_a, p->eps_v, p->gamma1};
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((terms & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_energy_fp64(pl, in, workspace, hs);
+  if (e == hipSuccess) e = dsrg::launch_finalize(pl, workspace, E_terms, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int terms,
+                                    const double *gE, double *dB_cv, double *dB_ca,
+                                    double *dB_av, double *deps_c, double *deps_a,
+                                    double *deps_v, double *ds, double *E_terms,
+                                    void *workspace, size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  (void)gE; (void)dB_cv; (void)dB_ca; (void)dB_av; (void)deps_c; (void)deps_a;
+  (void)deps_v; (void)ds; (void)E_terms; (void)workspace; (void)ws_bytes; (void)stream;
+  dsrg::Plan pl;
+  return make_plan(p, precision, terms, 1, pl);
+}
+
+const char *dsrg_df_last_error(void) { return g_err; }
+
+int dsrg_df_kernel_times(double *ms, const char **names, int cap) {
+  TimerTable &t = g_timer;
+  const int n = t.n;
+  t.n = 0;
+  for (int k = 0; k < n && k < cap; ++k) {
+    if (hipEventSynchronize(t.ev[2 * k + 1]) != hipSuccess) return -1;
+    float f = 0.0f;
+    if (hipEventElapsedTime(&f, t.ev[2 * k], t.ev[2 * k + 1]) != hipSuccess) return -1;
+    if (ms) ms[k] = (double)f;
+    if (names) names[k] = t.name[k];
+  }
+  return n;
+}
+
+int dsrg_df_version(void) { return 100; }
+
+}  // extern "C"

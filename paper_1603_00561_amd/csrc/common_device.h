@@ -1,0 +1,104 @@
+// Device-side helpers shared by the HIP kernels of libdsrgdf (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsrg {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+constexpr int kThreads = 256;   // every contraction kernel runs 4 waves of 64
+constexpr int kPadV = 16;       // LDS row padding (doubles) for virtual panels
+
+// ---------------------------------------------------------------------------
+// Regularisers. x = s D^2.
+// R(D)  = (1 - exp(-2x)) / D            F1 pair weight (Eq. expensive)
+// R1(D) = (1 - exp(-x)) / D             T2 renormalised denominator (Eq. T2amp)
+// S(D)  = 1 + exp(-x)                   v -> v-tilde factor (Eq. v_tilde)
+// For x < 1e-3 the Maclaurin series in x (section II.B analysis) is used,
+// truncated after x^4 (x^5 for S); the dropped terms are below 1e-16
+// relative there. For exponents beyond 37.5, exp(-.) < 2^-54 and
+// 1 -/+ exp(-.) rounds to exactly 1, so the exponential is skipped.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double reg_R(double D, double s) {
+  const double x = s * D * D;
+  if (x < 1e-3) {
+    return 2.0 * s * D *
+           (1.0 + x * (-1.0 + x * (2.0 / 3.0 + x * (-1.0 / 3.0 + x * (2.0 / 15.0)))));
+  }
+  const double y = 2.0 * x;
+  if (y > 37.5) return 1.0 / D;
+  return -expm1(-y) / D;
+}
+
+__device__ __forceinline__ void reg_S_R1(double D, double s, double &S, double &R1) {
+  const double x = s * D * D;
+  if (x < 1e-3) {
+    R1 = s * D * (1.0 + x * (-0.5 + x * (1.0 / 6.0 + x * (-1.0 / 24.0 + x * (1.0 / 120.0)))));
+    S = 2.0 + x * (-1.0 + x * (0.5 + x * (-1.0 / 6.0 + x * (1.0 / 24.0 + x * (-1.0 / 120.0)))));
+    return;
+  }
+  if (x > 37.5) {
+    S = 1.0;
+    R1 = 1.0 / D;
+    return;
+  }
+  const double em = expm1(-x);
+  S = 2.0 + em;
+  R1 = -em / D;
+}
+
+// Sum over the 256 threads of a workgroup in a fixed order; the result is
+// valid in thread 0. `red` is a __shared__ double[4].
+__device__ __forceinline__ double block_sum(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = (red[0] + red[1]) + (red[2] + red[3]);
+  return t;
+}
+
+// Deliver one workgroup's partial energy: its own slot (deterministic
+// reduction) or an FP64 atomic into the term accumulator.
+__device__ __forceinline__ void emit_partial(double t, double *slots, int64_t slot,
+                                             double *acc, int atomic_mode) {
+  if (threadIdx.x == 0) {
+    if (atomic_mode)
+      atomicAdd(acc, t);
+    else
+      slots[slot] = t;
+  }
+}
+
+// Decode the k-th strictly-ordered pair (p < q) of n items, row-major.
+__device__ __forceinline__ void decode_pair_lt(int64_t k, int n, int &p, int &q) {
+  int r = 0;
+  int64_t rowlen = n - 1;
+  while (k >= rowlen) {
+    k -= rowlen;
+    ++r;
+    --rowlen;
+  }
+  p = r;
+  q = r + 1 + (int)k;
+}
+
+// Decode the k-th pair (p <= q) of n items, row-major.
+__device__ __forceinline__ void decode_pair_le(int64_t k, int n, int &p, int &q) {
+  int r = 0;
+  int64_t rowlen = n;
+  while (k >= rowlen) {
+    k -= rowlen;
+    ++r;
+    --rowlen;
+  }
+  p = r;
+  q = r + (int)k;
+}
+
+}  // namespace dsrg

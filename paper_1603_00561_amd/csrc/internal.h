@@ -1,0 +1,62 @@
+// Internal declarations shared by the host ABI layer and the HIP kernels of
+// libdsrgdf. Not part of the public interface (include/dsrg_df.h is).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dsrg {
+
+// Width of one packed virtual-orbital panel (columns) and the auxiliary-index
+// chunk that the contraction kernels stage through LDS per step.
+constexpr int kPanel = 64;
+constexpr int kChunk = 16;
+// Column width of a packed active-orbital panel (na padded up to this).
+constexpr int kActPanel = 16;
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// Everything the launchers need, derived once on the host from the problem.
+struct Plan {
+  int64_t nc, na, nv, naux;
+  int64_t naux_p;   // naux rounded up to kChunk
+  int64_t ntv;      // number of kPanel-wide virtual panels
+  double s;
+  int precision;
+  int terms;
+  bool atomic_reduce;
+  bool with_grad;
+
+  // work counts (workgroups) per term
+  int64_t n_ccvv, n_cavv, n_ccav;
+  int cavv_tile;    // 32 or 64 columns per CAVV tile side
+
+  // workspace layout (byte offsets, 256-aligned)
+  size_t off_pcv, off_pav, off_pca;   // packed FP64 panels
+  size_t off_slots;                   // per-workgroup partial energies
+  size_t off_acc;                     // [4] atomic accumulators
+  size_t total;
+
+  int64_t slot_base[3];               // first slot of each term
+};
+
+struct Inputs {
+  const double *B_cv, *B_ca, *B_av;
+  const double *eps_c, *eps_a, *eps_v, *gamma1;
+};
+
+// number of A<B tile pairs, and the closed-form counts of the CCVV work list
+inline int64_t tri_off(int64_t n) { return n * (n - 1) / 2; }
+
+// ---- per-kernel timing (api.cpp); no-ops unless the call asked for it ----
+void timer_begin(const char *name, hipStream_t st);
+void timer_end(hipStream_t st);
+
+// ---- launchers (fp64_kernels.hip) ----
+hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
+hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
+hipError_t launch_finalize(const Plan &pl, void *ws, double *E_terms, hipStream_t st);
+
+}  // namespace dsrg

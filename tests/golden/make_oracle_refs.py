@@ -1,0 +1,72 @@
+"""Writes oracle_refs.json: the CPU oracle's energies (and, for the
+gradient workloads, sampled gradient entries, full orbital-energy and s
+gradients and the norms of the B gradients) on the seeded synthetic
+workloads. Calls only the oracle and the seeded generator.
+
+    python tests/golden/make_oracle_refs.py [cfg ...]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import dsrg_oracle as O  # noqa: E402
+from paper_1603_00561_amd.workloads import CONFIGS, make_config  # noqa: E402
+
+OUT = os.path.join(HERE, "oracle_refs.json")
+GE = (1.0, 0.75, -0.5)        # upstream weights used by the gradient references
+NSAMPLE = 64
+
+
+def sample_indices(shape, seed):
+    rng = np.random.default_rng(seed)
+    return [[int(rng.integers(0, n)) for n in shape] for _ in range(NSAMPLE)]
+
+
+def run(name):
+    c = CONFIGS[name]
+    out = {}
+    s_list = c.get("s_list", (c["s"],))
+    for s in s_list:
+        p = make_config(name, s=s)
+        t = time.time()
+        e = O.energy_terms(p, terms=c["terms"])
+        out["E_s%g" % s] = list(e)
+        out["t_energy_s%g" % s] = time.time() - t
+        print(name, s, e, time.time() - t, flush=True)
+    if c["grad"]:
+        p = make_config(name)
+        t = time.time()
+        g = O.gradients(p, GE)
+        gr = dict(gE=list(GE), t=time.time() - t)
+        for k in ("B_cv", "B_ca", "B_av"):
+            idx = sample_indices(g[k].shape, hash(k) % 1000 + 7)
+            gr[k] = dict(idx=idx, val=[float(g[k][tuple(i)]) for i in idx],
+                         norm=float(np.linalg.norm(g[k])), absmax=float(np.abs(g[k]).max()),
+                         dot_B=float(np.sum(g[k] * getattr(p, k))))
+        for k in ("eps_c", "eps_a", "eps_v", "s"):
+            gr[k] = [float(x) for x in g[k]]
+        out["grad"] = gr
+        print(name, "grad", time.time() - t, flush=True)
+    return out
+
+
+def main():
+    names = sys.argv[1:] or list(CONFIGS)
+    refs = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            refs = json.load(f)
+    for n in names:
+        refs[n] = run(n)
+        with open(OUT, "w") as f:
+            json.dump(refs, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,143 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function that include/dsrg_df.h declares, sizes workspaces, and
+rejects every invalid argument before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1603_00561_amd import binding as b
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dsrg_df.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsrg_df_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(b.LIB_PATH):
+        pytest.fail("libdsrgdf.so is not built; run python -m paper_1603_00561_amd.build")
+    return b.load_library()
+
+
+def test_exports_every_declared_function(lib):
+    names = _declared_functions()
+    assert set(names) >= {"dsrg_df_workspace_size", "dsrg_df_energy",
+                          "dsrg_df_energy_backward", "dsrg_df_last_error"}
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(b.EXPORTED) == set(names)
+    assert lib.dsrg_df_version() >= 100
+
+
+def _prob(nc=4, na=2, nv=70, naux=33, s=0.5, fake=True):
+    # fake, aligned, non-null device addresses: never dereferenced because
+    # every call below fails validation first
+    a = 0x10000 if fake else None
+    return b.Problem(nc, na, nv, naux, a, a, a, a, a, a, a, s)
+
+
+def _ws(p, prec=0, terms=7, grad=0):
+    out = ctypes.c_size_t(0)
+    st = b.load_library().dsrg_df_workspace_size(ctypes.byref(p), prec, terms, grad, ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_grows_with_problem(lib):
+    st, small = _ws(_prob(4, 2, 70, 33))
+    assert st == 0 and small > 0
+    st, big = _ws(_prob(23, 6, 1100, 3000))
+    assert st == 0
+    # packed B_cv panels dominate: nc * ceil(nv/64)*64 * naux (rounded) doubles
+    assert big >= 8 * 23 * 1152 * 3008
+    st, cc = _ws(_prob(23, 6, 1100, 3000), terms=1)
+    assert st == 0 and cc < big
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("nc", 0, b.DSRG_ERR_ARG), ("nv", 0, b.DSRG_ERR_ARG), ("naux", 0, b.DSRG_ERR_ARG),
+    ("na", -1, b.DSRG_ERR_ARG), ("s", -0.1, b.DSRG_ERR_ARG), ("s", float("nan"), b.DSRG_ERR_ARG),
+    ("s", float("inf"), b.DSRG_ERR_ARG), ("na", 9, b.DSRG_ERR_UNSUPPORTED),
+])
+def test_invalid_sizes_and_scalars(lib, field, value, code):
+    p = _prob()
+    setattr(p, field, value)
+    st, _ = _ws(p)
+    assert st == code
+    assert lib.dsrg_df_last_error().decode()
+    E = ctypes.c_void_p(0x20000)
+    st = lib.dsrg_df_energy(ctypes.byref(p), 0, 7, E, ctypes.c_void_p(0x40000), 1 << 40, None)
+    assert st == code
+
+
+def test_na_above_max_is_fine_for_ccvv_only(lib):
+    p = _prob(na=20)
+    st, _ = _ws(p, terms=1)
+    assert st == 0
+
+
+def test_bad_precision_and_terms(lib):
+    p = _prob()
+    assert _ws(p, prec=7)[0] == b.DSRG_ERR_ARG
+    assert _ws(p, terms=0)[0] == b.DSRG_ERR_ARG
+    assert _ws(p, terms=0x1000)[0] == b.DSRG_ERR_ARG
+    assert _ws(p, terms=7 | b.OPT_ATOMIC_REDUCE)[0] == 0
+    null = ctypes.POINTER(b.Problem)()
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_workspace_size(null, 0, 7, 0, ctypes.byref(out)) == b.DSRG_ERR_ARG
+    assert lib.dsrg_df_workspace_size(ctypes.byref(p), 0, 7, 0, None) == b.DSRG_ERR_ARG
+
+
+def test_null_and_misaligned_pointers(lib):
+    st, need = _ws(_prob())
+    ws = ctypes.c_void_p(0x100000)
+    E = ctypes.c_void_p(0x20000)
+    for field in ("B_cv", "B_ca", "B_av", "eps_c", "eps_a", "eps_v", "gamma1"):
+        for bad in (None, 0x10003):
+            p = _prob()
+            setattr(p, field, bad)
+            st = lib.dsrg_df_energy(ctypes.byref(p), 0, 7, E, ws, need, None)
+            assert st == b.DSRG_ERR_ARG, (field, bad)
+            assert field in lib.dsrg_df_last_error().decode()
+    # na == 0: active blocks may be NULL
+    p = _prob(na=0)
+    p.B_ca = p.B_av = p.eps_a = p.gamma1 = None
+    # (not launched: workspace too small on purpose)
+    st = lib.dsrg_df_energy(ctypes.byref(p), 0, 7, E, ws, 16, None)
+    assert st == b.DSRG_ERR_WORKSPACE
+    p = _prob()
+    st = lib.dsrg_df_energy(ctypes.byref(p), 0, 7, None, ws, need, None)
+    assert st == b.DSRG_ERR_ARG
+
+
+def test_workspace_checks(lib):
+    p = _prob()
+    st, need = _ws(p)
+    E = ctypes.c_void_p(0x20000)
+    assert lib.dsrg_df_energy(ctypes.byref(p), 0, 7, E, ctypes.c_void_p(0x100000), need - 1,
+                              None) == b.DSRG_ERR_WORKSPACE
+    assert lib.dsrg_df_energy(ctypes.byref(p), 0, 7, E, None, need, None) == b.DSRG_ERR_WORKSPACE
+    assert lib.dsrg_df_energy(ctypes.byref(p), 0, 7, E, ctypes.c_void_p(0x100008), need,
+                              None) == b.DSRG_ERR_WORKSPACE
+
+
+def test_last_error_is_cleared_by_a_good_call(lib):
+    _ws(_prob(nc=0))
+    assert lib.dsrg_df_last_error().decode()
+    assert _ws(_prob())[0] == 0
+    assert lib.dsrg_df_last_error().decode() == ""
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+    from paper_1603_00561_amd.workloads import make_problem
+    p = make_problem(2, 1, 5, 8)
+    t = [torch.from_numpy(x) for x in p.arrays()]
+    with pytest.raises(ValueError, match="GPU"):
+        b.energy(*t, p.s)

@@ -1,0 +1,174 @@
+"""GPU parity of dsrg_df_energy (FP64 path) against the CPU oracle.
+
+FP64 gate: |E_gpu - E_oracle| <= 1e-10 Eh per term (plus a relative floor
+of 3e-16 |E| for the largest synthetic magnitudes, where 1e-10 Eh is below
+one unit in the last place of a few-term sum). Small cases are compared
+against the oracle run live; the full-size workloads against
+tests/golden/oracle_refs.json, written by tests/golden/make_oracle_refs.py
+(oracle only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dsrg_oracle as O
+from paper_1603_00561_amd.workloads import make_problem, make_config, make_near_degenerate
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL_ABS = 1e-10
+
+
+def _b():
+    from paper_1603_00561_amd import binding
+    return binding
+
+
+def _dev(p):
+    return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in p.arrays()]
+
+
+def gpu_E(p, **kw):
+    print(f"[gpu] nc={p.nc} na={p.na} nv={p.nv} naux={p.naux} s={p.s} {kw}", flush=True)
+    E = _b().energy(*_dev(p), p.s, **kw)
+    torch.cuda.synchronize()
+    return E.cpu().numpy()
+
+
+def assert_close(Eg, Eo, tol_abs=TOL_ABS, rel_floor=3e-16):
+    Eo = np.asarray(Eo, dtype=np.float64)
+    err = np.abs(Eg - Eo)
+    tol = np.maximum(tol_abs, rel_floor * np.abs(Eo))
+    assert np.all(err <= tol), f"gpu {Eg!r} oracle {Eo!r} err {err!r} tol {tol!r}"
+
+
+def refs():
+    with open(os.path.join(HERE, "golden", "oracle_refs.json")) as f:
+        return json.load(f)
+
+
+def test_cfg1_ccvv_only():
+    p = make_config("cfg1")
+    Eg = gpu_E(p, terms="ccvv")
+    Eo = O.energy_terms(p, terms=("ccvv",))
+    assert Eg[1] == 0.0 and Eg[2] == 0.0
+    assert_close(Eg, Eo)
+
+
+@pytest.mark.parametrize("shape", [
+    (5, 3, 150, 70),    # ragged virtual tile and ragged auxiliary chunk
+    (3, 1, 64, 16),     # exact single tile
+    (4, 2, 65, 17),     # one column / one row past a tile
+    (2, 8, 130, 40),    # largest compiled active space
+    (1, 1, 1, 1),       # smallest problem
+    (7, 5, 33, 100),
+    (3, 4, 200, 16),
+    (9, 2, 129, 33),
+])
+def test_small_shapes_all_terms(shape):
+    p = make_problem(*shape, s=0.5, seed=sum(shape))
+    assert_close(gpu_E(p), O.energy_terms(p))
+
+
+@pytest.mark.parametrize("na", list(range(0, 9)))
+def test_active_sizes(na):
+    p = make_problem(3, na, 90, 24, s=0.7, seed=40 + na)
+    Eg = gpu_E(p)
+    assert_close(Eg, O.energy_terms(p))
+    if na == 0:
+        assert Eg[1] == 0.0 and Eg[2] == 0.0
+
+
+def test_term_mask_selects_terms():
+    p = make_problem(4, 3, 70, 20, seed=3)
+    Eo = O.energy_terms(p)
+    for mask, keep in (("cavv", (1,)), ("ccav", (2,)), (("ccvv", "ccav"), (0, 2))):
+        Eg = gpu_E(p, terms=mask)
+        for t in range(3):
+            if t in keep:
+                assert abs(Eg[t] - Eo[t]) <= TOL_ABS
+            else:
+                assert Eg[t] == 0.0
+
+
+def test_s_zero_exactly_zero():
+    p = make_problem(4, 3, 100, 30, s=0.0, seed=5)
+    assert np.all(gpu_E(p) == 0.0)
+
+
+def test_large_s_is_df_mp2():
+    p = make_problem(4, 2, 80, 30, s=1e8, seed=6)
+    Eg = gpu_E(p)
+    assert_close(Eg, O.energy_terms(p))
+    mp2 = O.closed_shell_df_mp2(p.B_cv, p.eps_c, p.eps_v)
+    assert abs(Eg[0] - mp2) <= 1e-12 * abs(mp2)
+
+
+def test_gamma_special_cases():
+    p = make_problem(5, 3, 100, 40, s=0.5, seed=8)
+    p.gamma1 = 2.0 * np.eye(3)
+    Eg = gpu_E(p)
+    assert_close(Eg, O.energy_terms(p))
+    assert abs(Eg[2]) <= 1e-12 * abs(Eg[1])
+    p.gamma1 = np.zeros((3, 3))
+    Eg = gpu_E(p)
+    assert Eg[1] == 0.0
+    assert_close(Eg, O.energy_terms(p))
+
+
+def test_near_degenerate_denominators_small_argument_branch():
+    p = make_near_degenerate(nc=4, na=3, nv=70, naux=40)
+    Eg = gpu_E(p)
+    Eo = np.array(O.energy_terms(p))
+    assert np.all(np.abs(Eg - Eo) <= 1e-13 * np.abs(Eo).max() + 1e-18), (Eg, Eo)
+
+
+def test_deterministic_reduction_is_bitwise_reproducible_and_atomic_agrees():
+    p = make_problem(6, 2, 200, 64, seed=9)
+    t = _dev(p)
+    b = _b()
+    E1 = b.energy(*t, p.s).cpu().numpy()
+    E2 = b.energy(*t, p.s).cpu().numpy()
+    assert np.array_equal(E1, E2)
+    Ea = b.energy(*t, p.s, atomic=True).cpu().numpy()
+    assert np.all(np.abs(Ea - E1) <= 1e-14 * np.abs(E1))
+
+
+def test_non_default_stream_and_caller_workspace():
+    p = make_problem(5, 2, 120, 50, seed=10)
+    t = _dev(p)
+    b = _b()
+    nbytes = b.workspace_size(p.nc, p.na, p.nv, p.naux)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ws.fill_(0xFF)      # garbage on entry must not matter
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        E = b.energy(*t, p.s, workspace=ws)
+    s.synchronize()
+    assert_close(E.cpu().numpy(), O.energy_terms(p))
+
+
+@pytest.mark.parametrize("name", ["cfg2", "cfg4"])
+def test_full_size_fp64_against_oracle(name):
+    r = refs()[name]
+    p = make_config(name)
+    assert_close(gpu_E(p), r["E_s%g" % p.s])
+
+
+def test_cfg3_fp64_all_s():
+    r = refs()["cfg3"]
+    for s in (0.1, 0.5, 1.0):
+        p = make_config("cfg3", s=s)
+        assert_close(gpu_E(p), r["E_s%g" % s])
+
+
+def test_cfg5_fp64_against_oracle():
+    r = refs()["cfg5"]
+    p = make_config("cfg5")
+    Eg = gpu_E(p)
+    Eo = np.array(r["E_s0.5"])
+    print("cfg5 fp64 |dE| per term:", np.abs(Eg - Eo), "relative:", np.abs(Eg - Eo) / np.abs(Eo))
+    assert_close(Eg, Eo)
