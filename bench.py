@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
+                         "hardware byte counters can be scaled")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -113,6 +116,13 @@ def main():
     import torch
     from paper_1603_00561_amd import binding
     from paper_1603_00561_amd.workloads import make_config, CONFIGS
+
+    if args.calibrate_copy:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
 
     p = make_config(args.config)
     c = CONFIGS[args.config]
