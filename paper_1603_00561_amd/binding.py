@@ -189,3 +189,40 @@ def energy(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
                               nbytes.value, _stream_handle(dev)))
     del keep
     return E
+
+
+def energy_backward(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, gE, precision="fp64",
+                    terms="all", want_energy=True, workspace: Optional[torch.Tensor] = None,
+                    timing: bool = False):
+    """Gradient of sum_t gE[t] E_t via dsrg_df_energy_backward.
+
+    Returns a dict with device tensors dB_cv, dB_ca, dB_av, deps_c, deps_a,
+    deps_v, ds (shape [1]) and, if want_energy, E (shape [3])."""
+    lib = load_library()
+    p, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s)
+    dev = B_cv.device
+    gE = _as_dev(gE, "gE", (3,), dev)
+    mask = _terms_mask(terms, False, timing)
+    prec = PRECISIONS[precision]
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_workspace_size(ctypes.byref(p), prec, mask, 1, ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    naux, nc, nv = B_cv.shape
+    na = p.na
+    f64 = dict(dtype=torch.float64, device=dev)
+    out = dict(dB_cv=torch.empty(naux, nc, nv, **f64),
+               dB_ca=torch.empty(naux, nc, na, **f64),
+               dB_av=torch.empty(naux, na, nv, **f64),
+               deps_c=torch.empty(nc, **f64), deps_a=torch.empty(na, **f64),
+               deps_v=torch.empty(nv, **f64), ds=torch.empty(1, **f64))
+    E = torch.empty(3, **f64) if want_energy else None
+    nz = lambda t: t.data_ptr() if t.numel() else None  # noqa: E731
+    _check(lib.dsrg_df_energy_backward(
+        ctypes.byref(p), prec, mask, gE.data_ptr(), out["dB_cv"].data_ptr(), nz(out["dB_ca"]),
+        nz(out["dB_av"]), out["deps_c"].data_ptr(), nz(out["deps_a"]), out["deps_v"].data_ptr(),
+        out["ds"].data_ptr(), None if E is None else E.data_ptr(), ws.data_ptr(), nbytes.value,
+        _stream_handle(dev)))
+    del keep
+    if want_energy:
+        out["E"] = E
+    return out

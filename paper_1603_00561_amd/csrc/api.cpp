@@ -80,7 +80,6 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
                 (long long)p->nc, (long long)p->nv, (long long)p->naux);
   if (precision != DSRG_FP64)
     return fail(DSRG_ERR_UNSUPPORTED, "precision %d is not available in this build", precision);
-  if (with_grad) return fail(DSRG_ERR_UNSUPPORTED, "gradients are not available in this build");
 
   pl.nc = p->nc;
   pl.na = p->na;
@@ -116,6 +115,22 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   pl.off_pca = off;
   if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV))
     off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.naux_p * kActPanel));
+  pl.off_gs = pl.off_g2 = pl.off_g3 = off;
+  if (pl.with_grad) {
+    const size_t Np = (size_t)(pl.nc * pl.ntv * kPanel);
+    if (term_bits & DSRG_TERM_CCVV) {
+      pl.off_gs = off;
+      off = align256(off + sizeof(double) * Np * Np);
+    }
+    if (pl.na > 0 && (term_bits & DSRG_TERM_CAVV)) {
+      pl.off_g2 = off;
+      off = align256(off + sizeof(double) * Np * (size_t)(pl.na * pl.ntv * kPanel));
+    }
+    if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV)) {
+      pl.off_g3 = off;
+      off = align256(off + sizeof(double) * Np * (size_t)(pl.nc * kActPanel));
+    }
+  }
   pl.off_slots = off;
   pl.slot_base[0] = 0;
   pl.slot_base[1] = pl.n_ccvv;
@@ -216,10 +231,33 @@ dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int
                                     double *deps_v, double *ds, double *E_terms,
                                     void *workspace, size_t ws_bytes, void *stream) {
   g_err[0] = 0;
-  (void)gE; (void)dB_cv; (void)dB_ca; (void)dB_av; (void)deps_c; (void)deps_a;
-  (void)deps_v; (void)ds; (void)E_terms; (void)workspace; (void)ws_bytes; (void)stream;
   dsrg::Plan pl;
-  return make_plan(p, precision, terms, 1, pl);
+  dsrg_status st = make_plan(p, precision, terms, 1, pl);
+  if (st != DSRG_OK) return st;
+  if ((st = check_inputs(p, pl)) != DSRG_OK) return st;
+  if (!gE || !aligned8(gE)) return fail(DSRG_ERR_ARG, "gE is NULL or misaligned");
+  if (!dB_cv || !aligned8(dB_cv)) return fail(DSRG_ERR_ARG, "dB_cv is NULL or misaligned");
+  if (!deps_c || !aligned8(deps_c)) return fail(DSRG_ERR_ARG, "deps_c is NULL or misaligned");
+  if (!deps_v || !aligned8(deps_v)) return fail(DSRG_ERR_ARG, "deps_v is NULL or misaligned");
+  if (!ds || !aligned8(ds)) return fail(DSRG_ERR_ARG, "ds is NULL or misaligned");
+  if (pl.na > 0) {
+    if (!dB_ca || !aligned8(dB_ca)) return fail(DSRG_ERR_ARG, "dB_ca is NULL or misaligned");
+    if (!dB_av || !aligned8(dB_av)) return fail(DSRG_ERR_ARG, "dB_av is NULL or misaligned");
+    if (!deps_a || !aligned8(deps_a)) return fail(DSRG_ERR_ARG, "deps_a is NULL or misaligned");
+  }
+  if (E_terms && !aligned8(E_terms)) return fail(DSRG_ERR_ARG, "E_terms is misaligned");
+  if ((st = check_workspace(pl, workspace, ws_bytes)) != DSRG_OK) return st;
+
+  pl.atomic_reduce = false;   // the adjoint kernels always fill per-workgroup slots
+  dsrg::Inputs in{p->B_cv, p->B_ca, p->B_av, p->eps_c, p->eps_a, p->eps_v, p->gamma1};
+  dsrg::BwdOut o{dB_cv, pl.na > 0 ? dB_ca : nullptr, pl.na > 0 ? dB_av : nullptr,
+                 deps_c, pl.na > 0 ? deps_a : nullptr, deps_v, ds, gE};
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((terms & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_backward_fp64(pl, in, o, workspace, hs);
+  if (e == hipSuccess && E_terms) e = dsrg::launch_finalize(pl, workspace, E_terms, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
 }
 
 const char *dsrg_df_last_error(void) { return g_err; }

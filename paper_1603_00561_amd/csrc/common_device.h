@@ -50,6 +50,47 @@ __device__ __forceinline__ void reg_S_R1(double D, double s, double &S, double &
   R1 = -em / D;
 }
 
+// Regularisers with their derivatives for the adjoint kernels.
+// dR/dD = 4 s e^{-2x} - R/D, dR/ds = 2 D e^{-2x}; series for x < 1e-3:
+// dR/dD = 2s[1 - 3x + 10/3 x^2 - 7/3 x^3 + 6/5 x^4].
+__device__ __forceinline__ void reg_R_grad(double D, double s, double &R, double &dD,
+                                           double &ds) {
+  const double x = s * D * D;
+  const double e2 = exp(-2.0 * x);
+  ds = 2.0 * D * e2;
+  if (x < 1e-3) {
+    R = 2.0 * s * D *
+        (1.0 + x * (-1.0 + x * (2.0 / 3.0 + x * (-1.0 / 3.0 + x * (2.0 / 15.0)))));
+    dD = 2.0 * s * (1.0 + x * (-3.0 + x * (10.0 / 3.0 + x * (-7.0 / 3.0 + x * (6.0 / 5.0)))));
+    return;
+  }
+  R = -expm1(-2.0 * x) / D;
+  dD = 4.0 * s * e2 - R / D;
+}
+
+// S, R1 with dS/dD = -2 s D e^{-x}, dR1/dD = 2 s e^{-x} - R1/D,
+// dS/ds = -D^2 e^{-x}, dR1/ds = D e^{-x}; series for x < 1e-3:
+// dR1/dD = s[1 - 3/2 x + 5/6 x^2 - 7/24 x^3 + 3/40 x^4].
+__device__ __forceinline__ void reg_S_R1_grad(double D, double s, double &S, double &R1,
+                                              double &dS, double &dR1, double &sS,
+                                              double &sR1) {
+  const double x = s * D * D;
+  const double e1 = exp(-x);
+  dS = -2.0 * s * D * e1;
+  sS = -D * D * e1;
+  sR1 = D * e1;
+  if (x < 1e-3) {
+    R1 = s * D * (1.0 + x * (-0.5 + x * (1.0 / 6.0 + x * (-1.0 / 24.0 + x * (1.0 / 120.0)))));
+    S = 2.0 + x * (-1.0 + x * (0.5 + x * (-1.0 / 6.0 + x * (1.0 / 24.0 + x * (-1.0 / 120.0)))));
+    dR1 = s * (1.0 + x * (-1.5 + x * (5.0 / 6.0 + x * (-7.0 / 24.0 + x * (3.0 / 40.0)))));
+    return;
+  }
+  const double em = expm1(-x);
+  S = 2.0 + em;
+  R1 = -em / D;
+  dR1 = 2.0 * s * e1 - R1 / D;
+}
+
 // Sum over the 256 threads of a workgroup in a fixed order; the result is
 // valid in thread 0. `red` is a __shared__ double[4].
 __device__ __forceinline__ double block_sum(double v, double *red) {

@@ -1,0 +1,769 @@
+// FP64 adjoint path of libdsrgdf: gradients of L = sum_t gE[t] E_t with
+// respect to B, the orbital energies and s.
+//
+// Step 1 (adjoint tiles): the (pq|rs) tiles are recomputed exactly as in the
+// forward kernels (never stored from the forward) and the epilogue writes
+// the adjoint tiles dL/d(pq|rs) to the workspace, accumulating dL/deps and
+// dL/ds on the way:
+//   Gs[(j,b)][(i,a)] = 2 dL/d(ia|jb)          (CCVV, symmetric N x N)
+//   G2[(m,e)][(w,f)] = dL/d(me|wf)            (CAVV)
+//   G3[(m,e)][(n,w)] = dL/d(me|nw)            (CCAV)
+// with N = nc * ntv * 64 padded core-virtual rows. Step 2 (adjoint GEMMs):
+// dB^Q_{pq} = sum over the contracted index pair of B^Q times the adjoint
+// tile (the chain rule through Eq. int_fact):
+//   dB_cv = Pcv . Gs + Pav . G2^T + Pca . G3^T,  dB_av = Pcv . G2,  dB_ca = Pcv . G3.
+#include "fp64_tiles.h"
+
+namespace dsrg {
+
+static inline double *ws_d(void *ws, size_t off) {
+  return reinterpret_cast<double *>(static_cast<char *>(ws) + off);
+}
+
+__global__ void zero_fill_kernel(double *p, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
+    p[k] = 0.0;
+}
+
+static hipError_t zero_fill(double *p, int64_t n, hipStream_t st) {
+  if (!p || n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(zero_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+// Write a 64 x 64 tile held in LDS (T[r][c], row stride 65) transposed into a
+// row-major global matrix: dst[c * ld + r] = T[r][c], coalesced along r.
+__device__ __forceinline__ void store_transposed64(const double (*T)[kPanel + 1], double *dst,
+                                                   int64_t ld) {
+  for (int k = threadIdx.x; k < kPanel * kPanel; k += kThreads) {
+    const int c = k / kPanel, r = k % kPanel;
+    dst[(int64_t)c * ld + r] = T[r][c];
+  }
+}
+
+struct GradOut {
+  double *deps_c, *deps_a, *deps_v, *ds;
+  const double *gE;
+};
+
+// ---------------------------------------------------------------------------
+// CCVV adjoint tiles. For element (a,b) of work item (i,j,A,B):
+// x = (ia|jb), y = (ib|ja), P = w (x^2 - x y + y^2) (all ordered terms the
+// item covers), and dL/dD = gE0 P R'(D) feeds eps_i, eps_j (+) and eps_a,
+// eps_b (-); dL/ds += gE0 P dR/ds. Adjoint values
+//   g1 = 2 dL/d(ia|jb) = 4 gE0 R (2x - y),  g2 = 2 dL/d(ib|ja) = 4 gE0 R (2y - x)
+// go to Gs[(i,a)][(j,b)] = Gs[(j,b)][(i,a)] = g1 and
+// Gs[(j,a)][(i,b)] = Gs[(i,b)][(j,a)] = g2 (the blocks each class owns).
+// ---------------------------------------------------------------------------
+struct CcvvAdjArgs {
+  int nc, nv, ntv;
+  int64_t naux_p;
+  double s;
+  int64_t n0, n1, n2;
+  int64_t slot_base;
+  int64_t Np;   // row length of Gs
+};
+
+__global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
+    const double *__restrict__ Pcv, const double *__restrict__ eps_c,
+    const double *__restrict__ eps_v, CcvvAdjArgs a, GradOut g, double *__restrict__ Gs,
+    double *slots) {
+  constexpr int W = kPanel;
+  __shared__ double lds[kCcvvLds];
+  __shared__ double rsum[W], csum[W];
+  const CcvvWork c = decode_ccvv(blockIdx.x, a.nc, a.ntv, a.n0, a.n1, a.n2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int cl = lane & 15, kl = lane >> 4;
+  d4 ax[2][2], ay[2][2];
+  ccvv_compute(Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
+  if (threadIdx.x < W) {
+    rsum[threadIdx.x] = 0.0;
+    csum[threadIdx.x] = 0.0;
+  }
+  __syncthreads();
+
+  const double gE0 = g.gE[0];
+  const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
+  const double eij = eps_c[c.i] + eps_c[c.j];
+  double eb[2];
+  int bcol[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    bcol[q] = c.B * W + 32 * wc + 16 * q + cl;
+    eb[q] = bcol[q] < a.nv ? eps_v[bcol[q]] : 0.0;
+  }
+  double e_part = 0.0, d_part = 0.0, s_part = 0.0, csl[2] = {0.0, 0.0};
+  double g1[2][2][4], g2[2][2][4];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ar = 32 * wr + 16 * p + 4 * r + kl;
+      const int arow = c.A * W + ar;
+      const double ea = arow < a.nv ? eps_v[arow] : 0.0;
+      double rs = 0.0;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        g1[p][q][r] = 0.0;
+        g2[p][q][r] = 0.0;
+        if (arow >= a.nv || bcol[q] >= a.nv) continue;
+        double R, dRD, dRs;
+        reg_R_grad(eij - (ea + eb[q]), a.s, R, dRD, dRs);
+        const double x = ax[p][q][r], y = ay[p][q][r];
+        const double P = w * (x * x - x * y + y * y);
+        e_part += R * P;
+        const double dd = P * dRD;
+        d_part += dd;
+        rs += dd;
+        csl[q] += dd;
+        s_part += P * dRs;
+        g1[p][q][r] = 4.0 * gE0 * R * (2.0 * x - y);
+        g2[p][q][r] = 4.0 * gE0 * R * (2.0 * y - x);
+      }
+      if (rs != 0.0) atomicAdd(&rsum[ar], rs);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (csl[q] != 0.0) atomicAdd(&csum[32 * wc + 16 * q + cl], csl[q]);
+
+  // natural-orientation blocks: Gs[(i,A)][(j,B)] = g1 and Gs[(j,A)][(i,B)] = g2
+  const int64_t rowI = (int64_t)c.i * a.ntv * W, rowJ = (int64_t)c.j * a.ntv * W;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t ra = c.A * W + 32 * wr + 16 * p + 4 * r + kl;
+        const int64_t cb = c.B * W + 32 * wc + 16 * q + cl;
+        Gs[(rowI + ra) * a.Np + rowJ + cb] = g1[p][q][r];
+        if (c.cls == 0 || c.cls == 1) Gs[(rowJ + ra) * a.Np + rowI + cb] = g2[p][q][r];
+      }
+  // transposed blocks (classes 0 and 2): Gs[(j,B)][(i,A)] = g1^T, Gs[(i,B)][(j,A)] = g2^T
+  if (c.cls == 0 || c.cls == 2) {
+    double (*T)[W + 1] = reinterpret_cast<double (*)[W + 1]>(lds);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          T[32 * wr + 16 * p + 4 * r + kl][32 * wc + 16 * q + cl] = g1[p][q][r];
+    __syncthreads();
+    store_transposed64(T, Gs + (rowJ + c.B * W) * a.Np + rowI + c.A * W, a.Np);
+    if (c.cls == 0) {
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            T[32 * wr + 16 * p + 4 * r + kl][32 * wc + 16 * q + cl] = g2[p][q][r];
+      __syncthreads();
+      store_transposed64(T, Gs + (rowI + c.B * W) * a.Np + rowJ + c.A * W, a.Np);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < W) {
+    const int t = threadIdx.x;
+    if (c.A * W + t < a.nv) atomicAdd(&g.deps_v[c.A * W + t], -gE0 * rsum[t]);
+    if (c.B * W + t < a.nv) atomicAdd(&g.deps_v[c.B * W + t], -gE0 * csum[t]);
+  }
+  const double tE = block_sum(e_part, lds);
+  __syncthreads();
+  const double tD = block_sum(d_part, lds);
+  __syncthreads();
+  const double tS = block_sum(s_part, lds);
+  if (threadIdx.x == 0) {
+    slots[a.slot_base + blockIdx.x] = tE;
+    atomicAdd(&g.deps_c[c.i], gE0 * tD);
+    atomicAdd(&g.deps_c[c.j], gE0 * tD);
+    atomicAdd(g.ds, gE0 * tS);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CAVV adjoint tiles for (m, A <= B). Per (e,f) and active w (X_u = (me|uf),
+// Y_u = (mf|ue) = (me|uf) with e<->f):
+//   A_w  = sum_v Gamma_wv R1_v (2X_v - Y_v),  A'_w = sum_v Gamma_wv R1_v (2Y_v - X_v)
+//   C_w  = sum_u Gamma_uw S_u X_u,            C'_w = sum_u Gamma_uw S_u Y_u
+//   dL/d(me|wf) = gE1 [S_w A_w  + R1_w (2C_w  - C'_w)]   -> G2[(m,e)][(w,f)]
+//   dL/d(mf|we) = gE1 [S_w A'_w + R1_w (2C'_w - C_w )]   -> G2[(m,f)][(w,e)]
+//   dE/dD^{mw}_{ef} = X_w A_w S'_w + (2X_w - Y_w) C_w R1'_w  (+ the (f,e) mirror)
+// Diagonal tiles (A = B) cover both orientations through their own
+// elements, carry weight 1/2 in the sums and write only the first block.
+// ---------------------------------------------------------------------------
+struct CavvAdjArgs {
+  int nc, na, nv, ntv, ntw;
+  int64_t naux_p;
+  double s;
+  int64_t n0;
+  int64_t slot_base;
+  int64_t N2;   // row length of G2 = na * ntv * 64
+};
+
+template <int NA, int TW>
+__global__ __launch_bounds__(256) void cavv_adj_fp64_kernel(
+    const double *__restrict__ Pcv, const double *__restrict__ Pav,
+    const double *__restrict__ eps_c, const double *__restrict__ eps_a,
+    const double *__restrict__ eps_v, const double *__restrict__ gamma1, CavvAdjArgs a,
+    GradOut g, double *__restrict__ G2, double *slots) {
+  using Cfg = CavvCfg<NA, TW>;
+  constexpr int HB = Cfg::HB, HW = Cfg::HW;
+  constexpr int LDSN = (Cfg::LDS > NA * TW * (TW + 1)) ? Cfg::LDS : NA * TW * (TW + 1);
+  __shared__ double lds[LDSN];
+  __shared__ double rsum[TW], csum[TW], asum[NA];
+  const CavvWork c = decode_cavv(blockIdx.x, a.ntw, a.n0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int cl = lane & 15, kl = lane >> 4;
+  d4 X[NA][HB][HB], Y[NA][HB][HB];
+  cavv_compute<NA, TW>(Pcv, Pav, a.naux_p, a.ntv, c, lds, X, Y, wr, wc, cl, kl);
+  if (threadIdx.x < TW) {
+    rsum[threadIdx.x] = 0.0;
+    csum[threadIdx.x] = 0.0;
+  }
+  if (threadIdx.x < NA) asum[threadIdx.x] = 0.0;
+  __syncthreads();
+
+  const double gE1 = g.gE[1];
+  const double wgt = c.diag ? 0.5 : 1.0;
+  double Gm[NA][NA], ea[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    ea[u] = eps_a[u];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) Gm[u][v] = gamma1[u * NA + v];
+  }
+  const double em = eps_c[c.m];
+  double e_part = 0.0, d_part = 0.0, s_part = 0.0, dw[NA], csl[HB];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) dw[u] = 0.0;
+#pragma unroll
+  for (int q = 0; q < HB; ++q) csl[q] = 0.0;
+  // transposed-orientation values, staged through LDS per w afterwards
+  double gT[NA][HB][HB][4];
+  const int64_t rowM = (int64_t)c.m * a.ntv * kPanel;
+#pragma unroll
+  for (int p = 0; p < HB; ++p) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int el = HW * wr + 16 * p + 4 * r + kl;
+      const int e = c.A * TW + el;
+      double rs = 0.0;
+#pragma unroll
+      for (int q = 0; q < HB; ++q) {
+        const int fl = HW * wc + 16 * q + cl;
+        const int f = c.B * TW + fl;
+        const bool ok = (e < a.nv) && (f < a.nv);
+        double S[NA], R1[NA], dS[NA], dR1[NA], sS[NA], sR1[NA];
+        const double base = em - ((ok ? eps_v[e] : 0.0) + (ok ? eps_v[f] : 0.0));
+#pragma unroll
+        for (int u = 0; u < NA; ++u)
+          reg_S_R1_grad(base + ea[u], a.s, S[u], R1[u], dS[u], dR1[u], sS[u], sR1[u]);
+        double Wv[NA], Wp[NA], Av[NA], Ap[NA], Cv[NA], Cp[NA];
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+          const double xv = X[v][p][q][r], yv = Y[v][p][q][r];
+          Wv[v] = 2.0 * xv - yv;
+          Wp[v] = 2.0 * yv - xv;
+        }
+#pragma unroll
+        for (int w = 0; w < NA; ++w) {
+          double sa = 0.0, sp = 0.0, ca = 0.0, cp = 0.0;
+#pragma unroll
+          for (int v = 0; v < NA; ++v) {
+            sa += Gm[w][v] * R1[v] * Wv[v];
+            sp += Gm[w][v] * R1[v] * Wp[v];
+            ca += Gm[v][w] * S[v] * X[v][p][q][r];
+            cp += Gm[v][w] * S[v] * Y[v][p][q][r];
+          }
+          Av[w] = sa;
+          Ap[w] = sp;
+          Cv[w] = ca;
+          Cp[w] = cp;
+        }
+        double dsum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NA; ++w) {
+          const double xw = X[w][p][q][r], yw = Y[w][p][q][r];
+          const double gn = ok ? gE1 * (S[w] * Av[w] + R1[w] * (2.0 * Cv[w] - Cp[w])) : 0.0;
+          const double gt = ok ? gE1 * (S[w] * Ap[w] + R1[w] * (2.0 * Cp[w] - Cv[w])) : 0.0;
+          G2[(rowM + c.A * TW + el) * a.N2 + (int64_t)w * a.ntv * kPanel + c.B * TW + fl] = gn;
+          gT[w][p][q][r] = gt;
+          if (ok) {
+            e_part += wgt * S[w] * (xw * Av[w] + yw * Ap[w]);
+            const double dd = wgt * (xw * Av[w] * dS[w] + Wv[w] * Cv[w] * dR1[w] +
+                                     yw * Ap[w] * dS[w] + Wp[w] * Cp[w] * dR1[w]);
+            s_part += wgt * (xw * Av[w] * sS[w] + Wv[w] * Cv[w] * sR1[w] +
+                             yw * Ap[w] * sS[w] + Wp[w] * Cp[w] * sR1[w]);
+            dw[w] += dd;
+            dsum += dd;
+          }
+        }
+        d_part += dsum;
+        rs += dsum;
+        csl[q] += dsum;
+      }
+      if (rs != 0.0) atomicAdd(&rsum[HW * wr + 16 * p + 4 * r + kl], rs);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < HB; ++q)
+    if (csl[q] != 0.0) atomicAdd(&csum[HW * wc + 16 * q + cl], csl[q]);
+#pragma unroll
+  for (int w = 0; w < NA; ++w)
+    if (dw[w] != 0.0) atomicAdd(&asum[w], dw[w]);
+  if (!c.diag) {
+    // G2[(m,f)][(w,e)] = gt: stage each w's tile as T_w[e][f] and write transposed
+    double *T = lds;
+#pragma unroll
+    for (int w = 0; w < NA; ++w)
+#pragma unroll
+      for (int p = 0; p < HB; ++p)
+#pragma unroll
+        for (int q = 0; q < HB; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            T[(w * TW + HW * wr + 16 * p + 4 * r + kl) * (TW + 1) + HW * wc + 16 * q + cl] =
+                gT[w][p][q][r];
+    __syncthreads();
+    for (int k = threadIdx.x; k < NA * TW * TW; k += kThreads) {
+      const int w = k / (TW * TW), rem = k % (TW * TW);
+      const int fl = rem / TW, el = rem % TW;
+      G2[(rowM + c.B * TW + fl) * a.N2 + (int64_t)w * a.ntv * kPanel + c.A * TW + el] =
+          T[(w * TW + el) * (TW + 1) + fl];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < TW) {
+    const int t = threadIdx.x;
+    if (c.A * TW + t < a.nv) atomicAdd(&g.deps_v[c.A * TW + t], -gE1 * rsum[t]);
+    if (c.B * TW + t < a.nv) atomicAdd(&g.deps_v[c.B * TW + t], -gE1 * csum[t]);
+  }
+  if (threadIdx.x < NA) atomicAdd(&g.deps_a[threadIdx.x], gE1 * asum[threadIdx.x]);
+  const double tE = block_sum(e_part, lds);
+  __syncthreads();
+  const double tD = block_sum(d_part, lds);
+  __syncthreads();
+  const double tS = block_sum(s_part, lds);
+  if (threadIdx.x == 0) {
+    slots[a.slot_base + blockIdx.x] = tE;
+    atomicAdd(&g.deps_c[c.m], gE1 * tD);
+    atomicAdd(g.ds, gE1 * tS);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CCAV adjoint tiles for (m <= n, 64-row tile T). Per e and active w, with
+// x_u = (me|nu), y_u = (ne|mu), etab = 2I - Gamma:
+//   A_w = sum_u etab_uw R1_u (2x_u - y_u),  A'_w = sum_u etab_uw R1_u (2y_u - x_u)
+//   C_w = sum_v etab_wv S_v x_v,            C'_w = sum_v etab_wv S_v y_v
+//   dL/d(me|nw) = gE2 [S_w A_w  + R1_w (2C_w  - C'_w)]  -> G3[(m,e)][(n,w)]
+//   dL/d(ne|mw) = gE2 [S_w A'_w + R1_w (2C'_w - C_w )]  -> G3[(n,e)][(m,w)]
+//   dE/dD^{ew}_{mn} = x_w A_w S'_w + (2x_w - y_w) C_w R1'_w (+ the (n,m) mirror)
+// weight 1/2 for m = n. Columns w >= na and padded rows are written as 0.
+// ---------------------------------------------------------------------------
+struct CcavAdjArgs {
+  int nc, na, nv, ntv;
+  int64_t naux_p;
+  double s;
+  int64_t slot_base;
+  int64_t N3;   // row length of G3 = nc * 16
+};
+
+template <int NA>
+__global__ __launch_bounds__(256) void ccav_adj_fp64_kernel(
+    const double *__restrict__ Pcv, const double *__restrict__ Pca,
+    const double *__restrict__ eps_c, const double *__restrict__ eps_a,
+    const double *__restrict__ eps_v, const double *__restrict__ gamma1, CcavAdjArgs a,
+    GradOut g, double *__restrict__ G3, double *slots) {
+  constexpr int W = kPanel, WA = kActPanel;
+  __shared__ double lds[kCcavLds];
+  __shared__ double xs[2][kPanel][kActPanel + 1];
+  __shared__ double asum[NA];
+  int m, n;
+  decode_pair_le(blockIdx.x / a.ntv, a.nc, m, n);
+  const int T = (int)(blockIdx.x % a.ntv);
+  if (threadIdx.x < NA) asum[threadIdx.x] = 0.0;
+  ccav_compute(Pcv, Pca, a.naux_p, a.ntv, m, n, T, lds, xs);
+  const double gE2 = g.gE[2];
+  const double wgt = (m == n) ? 0.5 : 1.0;
+  double e_part = 0.0, d_part = 0.0, s_part = 0.0;
+  if (threadIdx.x < W) {
+    const int el = threadIdx.x;
+    const int e = T * W + el;
+    const bool ok = e < a.nv;
+    double gmn[WA], gnm[WA];
+#pragma unroll
+    for (int w = 0; w < WA; ++w) gmn[w] = gnm[w] = 0.0;
+    if (ok) {
+      const double base = eps_c[m] + eps_c[n] - eps_v[e];
+      double S[NA], R1[NA], dS[NA], dR1[NA], sS[NA], sR1[NA], xv[NA], yv[NA], eb[NA][NA];
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        reg_S_R1_grad(base - eps_a[u], a.s, S[u], R1[u], dS[u], dR1[u], sS[u], sR1[u]);
+        xv[u] = xs[0][el][u];
+        yv[u] = xs[1][el][u];
+#pragma unroll
+        for (int v = 0; v < NA; ++v) eb[u][v] = (u == v ? 2.0 : 0.0) - gamma1[u * NA + v];
+      }
+#pragma unroll
+      for (int w = 0; w < NA; ++w) {
+        double Aw = 0.0, Ap = 0.0, Cw = 0.0, Cp = 0.0;
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+          Aw += eb[u][w] * R1[u] * (2.0 * xv[u] - yv[u]);
+          Ap += eb[u][w] * R1[u] * (2.0 * yv[u] - xv[u]);
+          Cw += eb[w][u] * S[u] * xv[u];
+          Cp += eb[w][u] * S[u] * yv[u];
+        }
+        gmn[w] = gE2 * (S[w] * Aw + R1[w] * (2.0 * Cw - Cp));
+        gnm[w] = gE2 * (S[w] * Ap + R1[w] * (2.0 * Cp - Cw));
+        e_part += wgt * S[w] * (xv[w] * Aw + yv[w] * Ap);
+        const double dd = wgt * (xv[w] * Aw * dS[w] + (2.0 * xv[w] - yv[w]) * Cw * dR1[w] +
+                                 yv[w] * Ap * dS[w] + (2.0 * yv[w] - xv[w]) * Cp * dR1[w]);
+        s_part += wgt * (xv[w] * Aw * sS[w] + (2.0 * xv[w] - yv[w]) * Cw * sR1[w] +
+                         yv[w] * Ap * sS[w] + (2.0 * yv[w] - xv[w]) * Cp * sR1[w]);
+        d_part += dd;
+        atomicAdd(&asum[w], dd);
+      }
+    }
+    double *rm = G3 + ((int64_t)m * a.ntv * W + e) * a.N3 + (int64_t)n * WA;
+    double *rn = G3 + ((int64_t)n * a.ntv * W + e) * a.N3 + (int64_t)m * WA;
+#pragma unroll
+    for (int w = 0; w < WA; w += 2) *reinterpret_cast<d2v *>(rm + w) = d2v{gmn[w], gmn[w + 1]};
+    if (m != n) {
+#pragma unroll
+      for (int w = 0; w < WA; w += 2) *reinterpret_cast<d2v *>(rn + w) = d2v{gnm[w], gnm[w + 1]};
+    }
+    if (ok) {
+      double dsum = 0.0;
+      // d_part accumulated above equals this thread's sum over w
+      dsum = d_part;
+      atomicAdd(&g.deps_v[e], -gE2 * dsum);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < NA) atomicAdd(&g.deps_a[threadIdx.x], -gE2 * asum[threadIdx.x]);
+  const double tE = block_sum(e_part, lds);
+  __syncthreads();
+  const double tD = block_sum(d_part, lds);
+  __syncthreads();
+  const double tS = block_sum(s_part, lds);
+  if (threadIdx.x == 0) {
+    slots[a.slot_base + blockIdx.x] = tE;
+    atomicAdd(&g.deps_c[m], gE2 * tD);
+    atomicAdd(&g.deps_c[n], gE2 * tD);
+    atomicAdd(g.ds, gE2 * tS);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint GEMM: C[Q][col(n)] (+)= sum_k A[Q][k] Bm[k][n], with
+//   A[Q][k]  = Apan[k / PW][Q][k % PW]   (packed panels, Q rows < naux_p)
+//   Bm[k][n] = TB ? G[n * ldg + k] : G[k * ldg + n]
+//   col(n)   = (n / GP) * nvalid + n % GP for n % GP < nvalid (else skipped)
+// 128 x 128 output tile per workgroup, 4 waves of 64 x 64, K chunks of 8
+// double-buffered in LDS.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  int64_t naux, naux_p;   // rows of C / rows stored per panel
+  int64_t K;              // contraction length (multiple of 8)
+  int PW;                 // panel width of A (16 or 64)
+  int64_t Ncols;          // columns of Bm (padded index space)
+  int64_t ldg;
+  int64_t GP, nvalid, ldc;
+  int accumulate;
+};
+
+constexpr int kGT = 128, kGK = 8, kGA = kGK + 1;
+
+template <bool TB>
+__global__ __launch_bounds__(256) void gemm_adj_fp64_kernel(const double *__restrict__ Apan,
+                                                            const double *__restrict__ G,
+                                                            GemmArgs a, double *__restrict__ C) {
+  __shared__ double sA[2][kGT * kGA];
+  __shared__ double sB[2][kGK * kGT];
+  const int64_t Q0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int cl = lane & 15, kl = lane >> 4;
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = zero4();
+
+  d2v ra[2], rb[2];
+  auto gload = [&](int64_t k0) {
+    const int64_t pan = k0 / a.PW, c0 = k0 % a.PW;
+    const double *Ab = Apan + pan * a.naux_p * a.PW + c0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = t + h * kThreads;       // 512 double2 = 128 rows x 4
+      const int row = idx >> 2, c2 = idx & 3;
+      const int64_t Q = Q0 + row;
+      ra[h] = (Q < a.naux_p) ? *reinterpret_cast<const d2v *>(Ab + Q * a.PW + 2 * c2)
+                             : d2v{0.0, 0.0};
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = t + h * kThreads;
+      if constexpr (!TB) {
+        const int row = idx >> 6, c2 = idx & 63;   // 8 rows x 64 double2
+        const int64_t n = n0 + 2 * c2;
+        rb[h] = (n < a.Ncols) ? *reinterpret_cast<const d2v *>(G + (k0 + row) * a.ldg + n)
+                              : d2v{0.0, 0.0};
+      } else {
+        const int nr = idx >> 2, c2 = idx & 3;     // 128 n-rows x 4 double2
+        const int64_t n = n0 + nr;
+        rb[h] = (n < a.Ncols) ? *reinterpret_cast<const d2v *>(G + n * a.ldg + k0 + 2 * c2)
+                              : d2v{0.0, 0.0};
+      }
+    }
+  };
+  auto sstore = [&](int b) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = t + h * kThreads;
+      const int row = idx >> 2, c2 = idx & 3;
+      sA[b][row * kGA + 2 * c2] = ra[h][0];
+      sA[b][row * kGA + 2 * c2 + 1] = ra[h][1];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = t + h * kThreads;
+      if constexpr (!TB) {
+        const int row = idx >> 6, c2 = idx & 63;
+        *reinterpret_cast<d2v *>(&sB[b][row * kGT + ((2 * c2) ^ swz(row))]) = rb[h];
+      } else {
+        const int nr = idx >> 2, c2 = idx & 3;
+        const int k0 = 2 * c2, k1 = 2 * c2 + 1;
+        sB[b][k0 * kGT + (nr ^ swz(k0))] = rb[h][0];
+        sB[b][k1 * kGT + (nr ^ swz(k1))] = rb[h][1];
+      }
+    }
+  };
+
+  gload(0);
+  sstore(0);
+  if (a.K > kGK) gload(kGK);
+  __syncthreads();
+  int b = 0;
+  for (int64_t k0 = 0; k0 < a.K; k0 += kGK) {
+    const double *LA = sA[b], *LB = sB[b];
+#pragma unroll
+    for (int kk = 0; kk < kGK / 4; ++kk) {
+      const int k = kk * 4 + kl;
+      double fa[4], fb[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) fa[p] = LA[(64 * wr + 16 * p + cl) * kGA + k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fb[q] = LB[k * kGT + ((64 * wc + 16 * q + cl) ^ swz(k))];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[p][q] = mfma64(fa[p], fb[q], acc[p][q]);
+    }
+    if (k0 + kGK < a.K) {
+      sstore(b ^ 1);
+      if (k0 + 2 * kGK < a.K) gload(k0 + 2 * kGK);
+    }
+    __syncthreads();
+    b ^= 1;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t n = n0 + 64 * wc + 16 * q + cl;
+    if (n >= a.Ncols) continue;
+    const int64_t grp = n / a.GP, cc = n % a.GP;
+    if (cc >= a.nvalid) continue;
+    const int64_t col = grp * a.nvalid + cc;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t Q = Q0 + 64 * wr + 16 * p + 4 * r + kl;
+        if (Q >= a.naux) continue;
+        double *dst = C + Q * a.ldc + col;
+        *dst = a.accumulate ? (*dst + acc[p][q][r]) : acc[p][q][r];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <bool TB>
+static hipError_t gemm(const Plan &pl, const double *Apan, int PW, int64_t npan,
+                       const double *G, int64_t Ncols, int64_t ldg, int64_t GP, int64_t nvalid,
+                       double *C, int64_t ldc, bool accumulate, hipStream_t st) {
+  GemmArgs a;
+  a.naux = pl.naux;
+  a.naux_p = pl.naux_p;
+  a.K = npan * PW;
+  a.PW = PW;
+  a.Ncols = Ncols;
+  a.ldg = ldg;
+  a.GP = GP;
+  a.nvalid = nvalid;
+  a.ldc = ldc;
+  a.accumulate = accumulate ? 1 : 0;
+  const dim3 grid((unsigned)ceil_div(pl.naux, kGT), (unsigned)ceil_div(Ncols, kGT));
+  timer_begin(TB ? "gemm_adj_tb_fp64" : "gemm_adj_fp64", st);
+  hipLaunchKernelGGL(gemm_adj_fp64_kernel<TB>, grid, dim3(256), 0, st, Apan, G, a, C);
+  timer_end(st);
+  return hipGetLastError();
+}
+
+template <int NA>
+static hipError_t launch_adj_act(const Plan &pl, const Inputs &in, const GradOut &g, void *ws,
+                                 hipStream_t st) {
+  double *slots = ws_d(ws, pl.off_slots);
+  const int64_t N2 = pl.na * pl.ntv * kPanel;
+  if ((pl.terms & 2)) {
+    CavvAdjArgs a;
+    a.nc = (int)pl.nc;
+    a.na = (int)pl.na;
+    a.nv = (int)pl.nv;
+    a.ntv = (int)pl.ntv;
+    a.ntw = (int)ceil_div(pl.nv, pl.cavv_tile);
+    a.naux_p = pl.naux_p;
+    a.s = pl.s;
+    a.n0 = pl.nc * tri_off(a.ntw);
+    a.slot_base = pl.slot_base[1];
+    a.N2 = N2;
+    timer_begin("cavv_adj_fp64", st);
+    if (pl.cavv_tile == 64) {
+      if constexpr (NA <= 2)
+        hipLaunchKernelGGL((cavv_adj_fp64_kernel<NA, 64>), dim3((unsigned)pl.n_cavv), dim3(256),
+                           0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), in.eps_c,
+                           in.eps_a, in.eps_v, in.gamma1, a, g, ws_d(ws, pl.off_g2), slots);
+    } else {
+      hipLaunchKernelGGL((cavv_adj_fp64_kernel<NA, 32>), dim3((unsigned)pl.n_cavv), dim3(256), 0,
+                         st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), in.eps_c, in.eps_a,
+                         in.eps_v, in.gamma1, a, g, ws_d(ws, pl.off_g2), slots);
+    }
+    timer_end(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if ((pl.terms & 4)) {
+    CcavAdjArgs a;
+    a.nc = (int)pl.nc;
+    a.na = (int)pl.na;
+    a.nv = (int)pl.nv;
+    a.ntv = (int)pl.ntv;
+    a.naux_p = pl.naux_p;
+    a.s = pl.s;
+    a.slot_base = pl.slot_base[2];
+    a.N3 = pl.nc * kActPanel;
+    timer_begin("ccav_adj_fp64", st);
+    hipLaunchKernelGGL((ccav_adj_fp64_kernel<NA>), dim3((unsigned)pl.n_ccav), dim3(256), 0, st,
+                       ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), in.eps_c, in.eps_a, in.eps_v,
+                       in.gamma1, a, g, ws_d(ws, pl.off_g3), slots);
+    timer_end(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                hipStream_t st) {
+  hipError_t e;
+  GradOut g{o.deps_c, o.deps_a, o.deps_v, o.ds, o.gE};
+  if ((e = zero_fill(o.deps_c, pl.nc, st)) != hipSuccess) return e;
+  if ((e = zero_fill(o.deps_a, pl.na, st)) != hipSuccess) return e;
+  if ((e = zero_fill(o.deps_v, pl.nv, st)) != hipSuccess) return e;
+  if ((e = zero_fill(o.ds, 1, st)) != hipSuccess) return e;
+  if ((e = launch_pack_fp64(pl, in, ws, st)) != hipSuccess) return e;
+  const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
+  const int64_t Np = pl.nc * pl.ntv * kPanel;
+  if (pl.terms & 1) {
+    CcvvAdjArgs a;
+    a.nc = (int)pl.nc;
+    a.nv = (int)pl.nv;
+    a.ntv = (int)pl.ntv;
+    a.naux_p = pl.naux_p;
+    a.s = pl.s;
+    const int64_t npo = tri_off(pl.nc), ntpo = tri_off(pl.ntv);
+    a.n0 = npo * ntpo;
+    a.n1 = npo * pl.ntv;
+    a.n2 = pl.nc * ntpo;
+    a.slot_base = pl.slot_base[0];
+    a.Np = Np;
+    timer_begin("ccvv_adj_fp64", st);
+    hipLaunchKernelGGL(ccvv_adj_fp64_kernel, dim3((unsigned)pl.n_ccvv), dim3(256), 0, st,
+                       ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, g, ws_d(ws, pl.off_gs),
+                       ws_d(ws, pl.off_slots));
+    timer_end(st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (cavv && pl.ntv * kPanel != ceil_div(pl.nv, pl.cavv_tile) * pl.cavv_tile) {
+    // CAVV tiles do not reach the end of the padded panels: clear G2 first
+    if ((e = zero_fill(ws_d(ws, pl.off_g2), Np * pl.na * pl.ntv * kPanel, st)) != hipSuccess)
+      return e;
+  }
+  if (cavv || ccav) {
+    switch (pl.na) {
+      case 1: e = launch_adj_act<1>(pl, in, g, ws, st); break;
+      case 2: e = launch_adj_act<2>(pl, in, g, ws, st); break;
+      case 3: e = launch_adj_act<3>(pl, in, g, ws, st); break;
+      case 4: e = launch_adj_act<4>(pl, in, g, ws, st); break;
+      case 5: e = launch_adj_act<5>(pl, in, g, ws, st); break;
+      case 6: e = launch_adj_act<6>(pl, in, g, ws, st); break;
+      case 7: e = launch_adj_act<7>(pl, in, g, ws, st); break;
+      case 8: e = launch_adj_act<8>(pl, in, g, ws, st); break;
+      default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  // ---- adjoint GEMMs ----
+  const int64_t ldcv = pl.nc * pl.nv;
+  bool first = true;
+  if (pl.terms & 1) {
+    e = gemm<false>(pl, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_gs), Np,
+                    Np, pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, false, st);
+    if (e != hipSuccess) return e;
+    first = false;
+  }
+  if (cavv) {
+    const int64_t N2 = pl.na * pl.ntv * kPanel;
+    e = gemm<true>(pl, ws_d(ws, pl.off_pav), kPanel, pl.na * pl.ntv, ws_d(ws, pl.off_g2), Np,
+                   N2, pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, !first, st);
+    if (e != hipSuccess) return e;
+    first = false;
+    e = gemm<false>(pl, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g2), N2,
+                    N2, pl.ntv * kPanel, pl.nv, o.dB_av, pl.na * pl.nv, false, st);
+    if (e != hipSuccess) return e;
+  } else if (o.dB_av) {
+    if ((e = zero_fill(o.dB_av, pl.naux * pl.na * pl.nv, st)) != hipSuccess) return e;
+  }
+  if (ccav) {
+    const int64_t N3 = pl.nc * kActPanel;
+    e = gemm<true>(pl, ws_d(ws, pl.off_pca), kActPanel, pl.nc, ws_d(ws, pl.off_g3), Np, N3,
+                   pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, !first, st);
+    if (e != hipSuccess) return e;
+    first = false;
+    e = gemm<false>(pl, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g3), N3,
+                    N3, kActPanel, pl.na, o.dB_ca, pl.nc * pl.na, false, st);
+    if (e != hipSuccess) return e;
+  } else if (o.dB_ca) {
+    if ((e = zero_fill(o.dB_ca, pl.naux * pl.nc * pl.na, st)) != hipSuccess) return e;
+  }
+  if (first) {
+    if ((e = zero_fill(o.dB_cv, pl.naux * ldcv, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace dsrg

@@ -6,8 +6,7 @@
 // with L and R packed panels [Q][64 columns]; the (pq|rs) tiles live only in
 // registers and are reduced into energies in the same kernel (section III:
 // no four-index storage).
-#include "common_device.h"
-#include "internal.h"
+#include "fp64_tiles.h"
 
 namespace dsrg {
 
@@ -35,59 +34,10 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Staging of NP panel chunks (KC rows of W doubles each, row stride ld in
-// global memory) through registers into LDS rows of length LDW.
-// ---------------------------------------------------------------------------
-template <int NP, int W, int KC>
-struct Stage {
-  static constexpr int N2 = KC * W / 2;                         // double2 per chunk
-  static constexpr int PER = (N2 + kThreads - 1) / kThreads;    // per thread
-  d2v r[NP][PER];
-
-  __device__ __forceinline__ void load(const double *const *src, int64_t ld, int64_t q0) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-#pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int idx = threadIdx.x + k * kThreads;
-        if (N2 % kThreads == 0 || idx < N2) {
-          const int row = idx / (W / 2);
-          const int c2 = idx % (W / 2);
-          r[p][k] = *reinterpret_cast<const d2v *>(src[p] + (q0 + row) * ld + 2 * c2);
-        }
-      }
-    }
-  }
-  template <int LDW>
-  __device__ __forceinline__ void store(double (*lds)[KC][LDW]) const {
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-#pragma unroll
-      for (int k = 0; k < PER; ++k) {
-        const int idx = threadIdx.x + k * kThreads;
-        if (N2 % kThreads == 0 || idx < N2) {
-          const int row = idx / (W / 2);
-          const int c2 = idx % (W / 2);
-          *reinterpret_cast<d2v *>(&lds[p][row][2 * c2]) = r[p][k];
-        }
-      }
-    }
-  }
-};
-
-// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
-// result register r of lane l holds D[4 r + l / 16][l % 16] (rows interleaved
-// by four, unlike the FP32-output shapes).
-__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// ---------------------------------------------------------------------------
-// CCVV (F1). One workgroup per (core pair i <= j, virtual tile pair A <= B).
-// x = K^{ij}[A,B] = B_iA^T B_jB and y = K^{ji}[A,B] = B_jA^T B_iB, so that
-// y[a][b] = (ib|ja) sits in the same registers as x[a][b] = (ia|jb).
-// Work order: (i<j, A<B), (i<j, A=B), (i=j, A<B), (i=j, A=B); the energy
-// weight c of c R (x^2 - x y + y^2) is 4, 2, 2, 1 respectively.
+// CCVV (F1). One workgroup per (core pair i <= j, virtual tile pair A <= B),
+// classes in decreasing cost (see decode_ccvv): the tile contributes
+// weight * R(D) (x^2 - x y + y^2) with x = (ia|jb), y = (ib|ja) and weight
+// 4, 2, 2, 1 for (i<j, A<B), (i<j, A=B), (i=j, A<B), (i=j, A=B).
 // ---------------------------------------------------------------------------
 struct CcvvArgs {
   int nc, nv, ntv;
@@ -98,98 +48,30 @@ struct CcvvArgs {
   int atomic_mode;
 };
 
-template <int KC>
+__device__ __forceinline__ double ccvv_weight(int cls) {
+  return (cls == 0) ? 4.0 : (cls == 3 ? 1.0 : 2.0);
+}
+
 __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict__ Pcv,
                                                         const double *__restrict__ eps_c,
                                                         const double *__restrict__ eps_v,
                                                         CcvvArgs a, double *slots,
                                                         double *acc) {
-  constexpr int W = kPanel, LDW = W + kPadV;
-  __shared__ double lds[4][KC][LDW];
-  __shared__ double red[4];
-
-  // ---- decode the work item ----
-  int64_t w = blockIdx.x;
-  int i, j, A, B;
-  double weight;
-  const int64_t ntp_lt = (int64_t)a.ntv * (a.ntv - 1) / 2;
-  if (w < a.n0) {
-    decode_pair_lt(w / ntp_lt, a.nc, i, j);
-    decode_pair_lt(w % ntp_lt, a.ntv, A, B);
-    weight = 4.0;
-  } else if ((w -= a.n0) < a.n1) {
-    decode_pair_lt(w / a.ntv, a.nc, i, j);
-    A = B = (int)(w % a.ntv);
-    weight = 2.0;
-  } else if ((w -= a.n1) < a.n2) {
-    i = j = (int)(w / ntp_lt);
-    decode_pair_lt(w % ntp_lt, a.ntv, A, B);
-    weight = 2.0;
-  } else {
-    w -= a.n2;
-    i = j = (int)(w / a.ntv);
-    A = B = (int)(w % a.ntv);
-    weight = 1.0;
-  }
-  const bool need_y = (i != j);
-  const int64_t pstride = a.naux_p * W;
-  const double *src[4] = {Pcv + (int64_t)(i * a.ntv + A) * pstride,
-                          Pcv + (int64_t)(j * a.ntv + B) * pstride,
-                          Pcv + (int64_t)(j * a.ntv + A) * pstride,
-                          Pcv + (int64_t)(i * a.ntv + B) * pstride};
-
+  constexpr int W = kPanel;
+  __shared__ double lds[kCcvvLds];
+  const CcvvWork c = decode_ccvv(blockIdx.x, a.nc, a.ntv, a.n0, a.n1, a.n2);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
-
   d4 ax[2][2], ay[2][2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      ax[p][q] = d4{0.0, 0.0, 0.0, 0.0};
-      ay[p][q] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+  ccvv_compute(Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
 
-  Stage<4, W, KC> st;
-  st.load(src, W, 0);
-  for (int64_t q0 = 0; q0 < a.naux_p; q0 += KC) {
-    __syncthreads();
-    st.template store<LDW>(lds);
-    __syncthreads();
-    if (q0 + KC < a.naux_p) st.load(src, W, q0 + KC);
-#pragma unroll
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      const int k = kk * 4 + kl;
-      double fa[2], fb[2];
-#pragma unroll
-      for (int p = 0; p < 2; ++p) fa[p] = lds[0][k][32 * wr + 16 * p + cl];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) fb[q] = lds[1][k][32 * wc + 16 * q + cl];
-#pragma unroll
-      for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) ax[p][q] = mfma64(fa[p], fb[q], ax[p][q]);
-      if (need_y) {
-#pragma unroll
-        for (int p = 0; p < 2; ++p) fa[p] = lds[2][k][32 * wr + 16 * p + cl];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) fb[q] = lds[3][k][32 * wc + 16 * q + cl];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-          for (int q = 0; q < 2; ++q) ay[p][q] = mfma64(fa[p], fb[q], ay[p][q]);
-      }
-    }
-  }
-
-  // ---- epilogue: c R(D) (x^2 - x y + y^2) ----
-  const double eij = eps_c[i] + eps_c[j];
+  const double eij = eps_c[c.i] + eps_c[c.j];
   double eb[2];
   int bcol[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    bcol[q] = B * W + 32 * wc + 16 * q + cl;
+    bcol[q] = c.B * W + 32 * wc + 16 * q + cl;
     eb[q] = bcol[q] < a.nv ? eps_v[bcol[q]] : 0.0;
   }
   double part = 0.0;
@@ -197,30 +79,28 @@ __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict
   for (int p = 0; p < 2; ++p) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int arow = A * W + 32 * wr + 16 * p + 4 * r + kl;
+      const int arow = c.A * W + 32 * wr + 16 * p + 4 * r + kl;
       if (arow >= a.nv) continue;
       const double ea = eps_v[arow];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         if (bcol[q] >= a.nv) continue;
-        const double D = eij - ea - eb[q];
-        const double R = reg_R(D, a.s);
-        const double x = ax[p][q][r];
-        const double y = need_y ? ay[p][q][r] : x;
+        const double R = reg_R(eij - ea - eb[q], a.s);
+        const double x = ax[p][q][r], y = ay[p][q][r];
         part += R * (x * x - x * y + y * y);
       }
     }
   }
-  const double t = block_sum(part, red) * weight;
+  const double t = block_sum(part, lds) * ccvv_weight(c.cls);
   emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
 }
 
 // ---------------------------------------------------------------------------
 // CAVV (F2). One workgroup per (core m, virtual tile pair A <= B) with tiles
-// of TW columns. For every active u: X_u[e][f] = (me|uf) = B_mA^T B_uB and
-// Y_u[e][f] = (mf|ue) = B_uA^T B_mB. The epilogue forms, per (e,f),
+// of TW columns; per (e,f) the epilogue forms
 //   sum_uv Gamma_uv S(D_mu) R1(D_mv) [X_u (2X_v - Y_v) + Y_u (2Y_v - X_v)]
-// which covers (e,f) and (f,e); weight 1 for A<B and 1/2 for A=B.
+// with X_u = (me|uf), Y_u = (mf|ue): both (e,f) and (f,e). Weight 1 for
+// A<B and 1/2 for A=B.
 // ---------------------------------------------------------------------------
 struct CavvArgs {
   int nc, na, nv, ntv, ntw;
@@ -231,94 +111,22 @@ struct CavvArgs {
   int atomic_mode;
 };
 
-template <int NA, int TW, int KC>
+template <int NA, int TW>
 __global__ __launch_bounds__(256) void cavv_fp64_kernel(
     const double *__restrict__ Pcv, const double *__restrict__ Pav,
     const double *__restrict__ eps_c, const double *__restrict__ eps_a,
     const double *__restrict__ eps_v, const double *__restrict__ gamma1, CavvArgs a,
     double *slots, double *acc) {
-  constexpr int NP = 2 + 2 * NA;
-  constexpr int LDW = TW + kPadV;
-  constexpr int HB = TW / 32;   // 16-row blocks per wave side
-  __shared__ double lds[NP][KC][LDW];
-  __shared__ double red[4];
-
-  int64_t w = blockIdx.x;
-  int m, A, B;
-  double weight;
-  const int64_t ntp_lt = (int64_t)a.ntw * (a.ntw - 1) / 2;
-  if (w < a.n0) {
-    m = (int)(w / ntp_lt);
-    decode_pair_lt(w % ntp_lt, a.ntw, A, B);
-    weight = 1.0;
-  } else {
-    w -= a.n0;
-    m = (int)(w / a.ntw);
-    A = B = (int)(w % a.ntw);
-    weight = 0.5;
-  }
-  const int64_t pstride = a.naux_p * kPanel;
-  const int pA = (A * TW) / kPanel, oA = (A * TW) % kPanel;
-  const int pB = (B * TW) / kPanel, oB = (B * TW) % kPanel;
-  const double *src[NP];
-  src[0] = Pcv + (int64_t)(m * a.ntv + pA) * pstride + oA;
-  src[1] = Pcv + (int64_t)(m * a.ntv + pB) * pstride + oB;
-#pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    src[2 + u] = Pav + (int64_t)(u * a.ntv + pA) * pstride + oA;
-    src[2 + NA + u] = Pav + (int64_t)(u * a.ntv + pB) * pstride + oB;
-  }
-
+  using Cfg = CavvCfg<NA, TW>;
+  constexpr int HB = Cfg::HB, HW = Cfg::HW;
+  __shared__ double lds[Cfg::LDS];
+  const CavvWork c = decode_cavv(blockIdx.x, a.ntw, a.n0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
-  constexpr int HW = TW / 2;
-
   d4 X[NA][HB][HB], Y[NA][HB][HB];
-#pragma unroll
-  for (int u = 0; u < NA; ++u)
-#pragma unroll
-    for (int p = 0; p < HB; ++p)
-#pragma unroll
-      for (int q = 0; q < HB; ++q) {
-        X[u][p][q] = d4{0.0, 0.0, 0.0, 0.0};
-        Y[u][p][q] = d4{0.0, 0.0, 0.0, 0.0};
-      }
+  cavv_compute<NA, TW>(Pcv, Pav, a.naux_p, a.ntv, c, lds, X, Y, wr, wc, cl, kl);
 
-  Stage<NP, TW, KC> st;
-  st.load(src, kPanel, 0);
-  for (int64_t q0 = 0; q0 < a.naux_p; q0 += KC) {
-    __syncthreads();
-    st.template store<LDW>(lds);
-    __syncthreads();
-    if (q0 + KC < a.naux_p) st.load(src, kPanel, q0 + KC);
-#pragma unroll
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      const int k = kk * 4 + kl;
-      double am[HB], bm[HB];
-#pragma unroll
-      for (int p = 0; p < HB; ++p) am[p] = lds[0][k][HW * wr + 16 * p + cl];
-#pragma unroll
-      for (int q = 0; q < HB; ++q) bm[q] = lds[1][k][HW * wc + 16 * q + cl];
-#pragma unroll
-      for (int u = 0; u < NA; ++u) {
-        double au[HB], bu[HB];
-#pragma unroll
-        for (int p = 0; p < HB; ++p) au[p] = lds[2 + u][k][HW * wr + 16 * p + cl];
-#pragma unroll
-        for (int q = 0; q < HB; ++q) bu[q] = lds[2 + NA + u][k][HW * wc + 16 * q + cl];
-#pragma unroll
-        for (int p = 0; p < HB; ++p)
-#pragma unroll
-          for (int q = 0; q < HB; ++q) {
-            X[u][p][q] = mfma64(am[p], bu[q], X[u][p][q]);
-            Y[u][p][q] = mfma64(au[p], bm[q], Y[u][p][q]);
-          }
-      }
-    }
-  }
-
-  // ---- epilogue ----
   double G[NA][NA], ea[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
@@ -326,18 +134,18 @@ __global__ __launch_bounds__(256) void cavv_fp64_kernel(
 #pragma unroll
     for (int v = 0; v < NA; ++v) G[u][v] = gamma1[u * NA + v];
   }
-  const double em = eps_c[m];
+  const double em = eps_c[c.m];
   double part = 0.0;
 #pragma unroll
   for (int q = 0; q < HB; ++q) {
-    const int f = B * TW + HW * wc + 16 * q + cl;
+    const int f = c.B * TW + HW * wc + 16 * q + cl;
     if (f >= a.nv) continue;
     const double ef = eps_v[f];
 #pragma unroll
     for (int p = 0; p < HB; ++p) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int e = A * TW + HW * wr + 16 * p + 4 * r + kl;
+        const int e = c.A * TW + HW * wr + 16 * p + 4 * r + kl;
         if (e >= a.nv) continue;
         const double base = em - eps_v[e] - ef;
         double S[NA], R1[NA];
@@ -365,16 +173,15 @@ __global__ __launch_bounds__(256) void cavv_fp64_kernel(
       }
     }
   }
-  const double t = block_sum(part, red) * weight;
+  const double t = block_sum(part, lds) * (c.diag ? 0.5 : 1.0);
   emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
 }
 
 // ---------------------------------------------------------------------------
-// CCAV (F3). One workgroup per (core pair m <= n, 64-wide virtual tile T).
-// x[e][u] = (me|nu) = B_mT^T B_n(act), y[e][u] = (ne|mu) = B_nT^T B_m(act).
-// Per e: sum_uv etab_uv S(D^{ev}_{mn}) R1(D^{eu}_{mn})
-//        [x_v (2 x_u - y_u) + y_v (2 y_u - x_u)],  etab = 2I - Gamma,
-// which covers (m,n) and (n,m); weight 1 for m<n and 1/2 for m=n.
+// CCAV (F3). One workgroup per (core pair m <= n, 64-row virtual tile T),
+// x[e][u] = (me|nu), y[e][u] = (ne|mu). Per e:
+//   sum_uv etab_uv S(D^{ev}_{mn}) R1(D^{eu}_{mn}) [x_v (2x_u - y_u) + y_v (2y_u - x_u)]
+// with etab = 2I - Gamma: covers (m,n) and (n,m); weight 1 (m<n), 1/2 (m=n).
 // ---------------------------------------------------------------------------
 struct CcavArgs {
   int nc, na, nv, ntv;
@@ -384,59 +191,19 @@ struct CcavArgs {
   int atomic_mode;
 };
 
-template <int NA, int KC>
+template <int NA>
 __global__ __launch_bounds__(256) void ccav_fp64_kernel(
     const double *__restrict__ Pcv, const double *__restrict__ Pca,
     const double *__restrict__ eps_c, const double *__restrict__ eps_a,
     const double *__restrict__ eps_v, const double *__restrict__ gamma1, CcavArgs a,
     double *slots, double *acc) {
-  constexpr int W = kPanel, LDW = W + kPadV, WA = kActPanel;
-  __shared__ double lv[2][KC][LDW];
-  __shared__ double la[2][KC][WA];
-  __shared__ double xs[2][W][WA + 1];
-  __shared__ double red[4];
-
-  const int64_t w = blockIdx.x;
+  constexpr int W = kPanel;
+  __shared__ double lds[kCcavLds];
+  __shared__ double xs[2][kPanel][kActPanel + 1];
   int m, n;
-  decode_pair_le(w / a.ntv, a.nc, m, n);
-  const int T = (int)(w % a.ntv);
-  const double weight = (m == n) ? 0.5 : 1.0;
-  const int64_t pstride = a.naux_p * W;
-  const double *srcv[2] = {Pcv + (int64_t)(m * a.ntv + T) * pstride,
-                           Pcv + (int64_t)(n * a.ntv + T) * pstride};
-  const double *srca[2] = {Pca + (int64_t)n * a.naux_p * WA, Pca + (int64_t)m * a.naux_p * WA};
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int cl = lane & 15, kl = lane >> 4;
-  d4 x = {0.0, 0.0, 0.0, 0.0}, y = {0.0, 0.0, 0.0, 0.0};
-
-  Stage<2, W, KC> sv;
-  Stage<2, WA, KC> sa;
-  sv.load(srcv, W, 0);
-  sa.load(srca, WA, 0);
-  for (int64_t q0 = 0; q0 < a.naux_p; q0 += KC) {
-    __syncthreads();
-    sv.template store<LDW>(lv);
-    sa.template store<WA>(la);
-    __syncthreads();
-    if (q0 + KC < a.naux_p) {
-      sv.load(srcv, W, q0 + KC);
-      sa.load(srca, WA, q0 + KC);
-    }
-#pragma unroll
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      const int k = kk * 4 + kl;
-      x = mfma64(lv[0][k][16 * wave + cl], la[0][k][cl], x);
-      y = mfma64(lv[1][k][16 * wave + cl], la[1][k][cl], y);
-    }
-  }
-  // stage the two 64 x 16 tiles through LDS so one thread sees a whole row
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    xs[0][16 * wave + 4 * r + kl][cl] = x[r];
-    xs[1][16 * wave + 4 * r + kl][cl] = y[r];
-  }
-  __syncthreads();
+  decode_pair_le(blockIdx.x / a.ntv, a.nc, m, n);
+  const int T = (int)(blockIdx.x % a.ntv);
+  ccav_compute(Pcv, Pca, a.naux_p, a.ntv, m, n, T, lds, xs);
   double part = 0.0;
   if (threadIdx.x < W) {
     const int e = T * W + threadIdx.x;
@@ -462,7 +229,7 @@ __global__ __launch_bounds__(256) void ccav_fp64_kernel(
       }
     }
   }
-  const double t = block_sum(part, red) * weight;
+  const double t = block_sum(part, lds) * ((m == n) ? 0.5 : 1.0);
   emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
 }
 
@@ -572,24 +339,18 @@ static hipError_t launch_cavv_na(const Plan &pl, const Inputs &in, void *ws, hip
   a.slot_base = pl.slot_base[1];
   a.atomic_mode = pl.atomic_reduce ? 1 : 0;
   const dim3 grid((unsigned)pl.n_cavv), block(256);
-  if constexpr (NA <= 2) {
-    if (pl.cavv_tile == 64) {
-      timer_begin("cavv_fp64", st);
-      hipLaunchKernelGGL((cavv_fp64_kernel<NA, 64, 16>), grid, block, 0, st,
-                         ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), in.eps_c, in.eps_a,
-                         in.eps_v, in.gamma1, a, slots, acc + 1);
-      timer_end(st);
-      return hipGetLastError();
-    }
+  timer_begin("cavv_fp64", st);
+  if (pl.cavv_tile == 64) {
+    if constexpr (NA <= 2)
+      hipLaunchKernelGGL((cavv_fp64_kernel<NA, 64>), grid, block, 0, st, ws_d(ws, pl.off_pcv),
+                         ws_d(ws, pl.off_pav), in.eps_c, in.eps_a, in.eps_v, in.gamma1, a, slots,
+                         acc + 1);
+  } else {
+    hipLaunchKernelGGL((cavv_fp64_kernel<NA, 32>), grid, block, 0, st, ws_d(ws, pl.off_pcv),
+                       ws_d(ws, pl.off_pav), in.eps_c, in.eps_a, in.eps_v, in.gamma1, a, slots,
+                       acc + 1);
   }
-  {
-    constexpr int KC = (NA <= 4) ? 16 : 8;
-    timer_begin("cavv_fp64", st);
-    hipLaunchKernelGGL((cavv_fp64_kernel<NA, 32, KC>), grid, block, 0, st,
-                       ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), in.eps_c, in.eps_a, in.eps_v,
-                       in.gamma1, a, slots, acc + 1);
-    timer_end(st);
-  }
+  timer_end(st);
   return hipGetLastError();
 }
 
@@ -606,7 +367,7 @@ static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hip
   a.slot_base = pl.slot_base[2];
   a.atomic_mode = pl.atomic_reduce ? 1 : 0;
   timer_begin("ccav_fp64", st);
-  hipLaunchKernelGGL((ccav_fp64_kernel<NA, kChunk>), dim3((unsigned)pl.n_ccav), dim3(256), 0,
+  hipLaunchKernelGGL((ccav_fp64_kernel<NA>), dim3((unsigned)pl.n_ccav), dim3(256), 0,
                      st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), in.eps_c, in.eps_a,
                      in.eps_v, in.gamma1, a, slots, acc + 2);
   timer_end(st);
@@ -658,7 +419,7 @@ hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStr
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
     timer_begin("ccvv_fp64", st);
-    hipLaunchKernelGGL(ccvv_fp64_kernel<kChunk>, dim3((unsigned)pl.n_ccvv), dim3(256), 0, st,
+    hipLaunchKernelGGL(ccvv_fp64_kernel, dim3((unsigned)pl.n_ccvv), dim3(256), 0, st,
                        ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, slots, acc + 0);
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;

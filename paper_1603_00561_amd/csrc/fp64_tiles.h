@@ -1,0 +1,371 @@
+// FP64 tile machinery shared by the forward and adjoint kernels: staging of
+// packed panel chunks through LDS, the double-buffered K loop over the
+// auxiliary index, and the FP64 matrix-core fragment helpers (gfx950).
+#pragma once
+
+#include "common_device.h"
+#include "internal.h"
+
+namespace dsrg {
+
+// v_mfma_f64_16x16x4f64: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// result register r of lane l holds D[4 r + l / 16][l % 16] (rows interleaved
+// by four, unlike the FP32-output shapes).
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
+
+// LDS rows of W doubles hold one auxiliary index each. The 16-column halves
+// of odd rows are swapped (column c of row k lives at c ^ swz(k)), so the two
+// rows that one 32-lane half of a fragment read touches land in different
+// bank halves without padding.
+__device__ __forceinline__ int swz(int k) { return (k & 1) << 4; }
+
+// NP panel chunks of KC rows x W doubles, global row stride ld, copied
+// global -> registers -> LDS by all 256 threads with 16-byte accesses.
+template <int NP, int W, int KC>
+struct Stage {
+  static constexpr int N2 = KC * W / 2;                         // double2 per chunk
+  static constexpr int PER = (N2 + kThreads - 1) / kThreads;    // per thread
+  d2v r[NP][PER];
+
+  __device__ __forceinline__ void load(const double *const *src, int64_t ld, int64_t q0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = threadIdx.x + k * kThreads;
+        if (N2 % kThreads == 0 || idx < N2) {
+          const int row = idx / (W / 2);
+          const int c2 = idx % (W / 2);
+          r[p][k] = *reinterpret_cast<const d2v *>(src[p] + (q0 + row) * ld + 2 * c2);
+        }
+      }
+    }
+  }
+  // buf: NP consecutive [KC][W] blocks
+  __device__ __forceinline__ void store(double *buf) const {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int idx = threadIdx.x + k * kThreads;
+        if (N2 % kThreads == 0 || idx < N2) {
+          const int row = idx / (W / 2);
+          const int c2 = idx % (W / 2);
+          const int col = (W >= 32) ? ((2 * c2) ^ swz(row)) : 2 * c2;
+          *reinterpret_cast<d2v *>(&buf[(p * KC + row) * W + col]) = r[p][k];
+        }
+      }
+    }
+  }
+};
+
+// Column of row k in an LDS panel of width W (matches Stage::store).
+template <int W>
+__device__ __forceinline__ int lcol(int c, int k) {
+  return (W >= 32) ? (c ^ swz(k)) : c;
+}
+
+// Double-buffered K loop: lds holds 2 * NP * KC * W doubles. compute(L) is
+// called once per chunk with L = the NP staged [KC][W] panels. While it
+// runs, chunk c+1 waits in registers and is then written to the other
+// buffer, and chunk c+2 is fetched; one barrier per chunk. Ends on a barrier.
+template <int NP, int W, int KC, typename F>
+__device__ __forceinline__ void kloop(const double *const *src, int64_t ld, int64_t naux_p,
+                                      double *lds, F &&compute) {
+  constexpr int BUF = NP * KC * W;
+  Stage<NP, W, KC> st;
+  st.load(src, ld, 0);
+  st.store(lds);
+  if (naux_p > KC) st.load(src, ld, KC);
+  __syncthreads();
+  int b = 0;
+  for (int64_t q0 = 0; q0 < naux_p; q0 += KC) {
+    compute(static_cast<const double *>(lds + b * BUF));
+    if (q0 + KC < naux_p) {
+      st.store(lds + (b ^ 1) * BUF);
+      if (q0 + 2 * KC < naux_p) st.load(src, ld, q0 + 2 * KC);
+    }
+    __syncthreads();
+    b ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CCVV tile pair: x = K^{ij}[A,B] = B_iA^T B_jB, y = K^{ji}[A,B] = B_jA^T B_iB
+// on a 64 x 64 tile, each wave owning a 32 x 32 quadrant (wr, wc).
+// src = {B_iA, B_jB, B_jA, B_iB} packed panels.
+// ---------------------------------------------------------------------------
+struct CcvvWork {
+  int i, j, A, B, cls;   // cls 0: i<j,A<B  1: i<j,A=B  2: i=j,A<B  3: i=j,A=B
+};
+
+__device__ __forceinline__ CcvvWork decode_ccvv(int64_t w, int nc, int ntv, int64_t n0,
+                                                int64_t n1, int64_t n2) {
+  CcvvWork c;
+  const int64_t ntp_lt = (int64_t)ntv * (ntv - 1) / 2;
+  if (w < n0) {
+    decode_pair_lt(w / ntp_lt, nc, c.i, c.j);
+    decode_pair_lt(w % ntp_lt, ntv, c.A, c.B);
+    c.cls = 0;
+  } else if ((w -= n0) < n1) {
+    decode_pair_lt(w / ntv, nc, c.i, c.j);
+    c.A = c.B = (int)(w % ntv);
+    c.cls = 1;
+  } else if ((w -= n1) < n2) {
+    c.i = c.j = (int)(w / ntp_lt);
+    decode_pair_lt(w % ntp_lt, ntv, c.A, c.B);
+    c.cls = 2;
+  } else {
+    w -= n2;
+    c.i = c.j = (int)(w / ntv);
+    c.A = c.B = (int)(w % ntv);
+    c.cls = 3;
+  }
+  return c;
+}
+
+constexpr int kCcvvKC = 16;
+constexpr int kCcvvLds = 2 * 4 * kCcvvKC * kPanel;   // doubles
+
+// Computes ax (and ay for class 0); classes 1-3 derive ay afterwards.
+template <bool NEED_Y>
+__device__ __forceinline__ void ccvv_tiles(const double *const *src, int64_t naux_p,
+                                           double *lds, d4 (&ax)[2][2], d4 (&ay)[2][2],
+                                           int wr, int wc, int cl, int kl) {
+  constexpr int W = kPanel, KC = kCcvvKC;
+  constexpr int NP = NEED_Y ? 4 : 2;
+  kloop<NP, W, KC>(src, W, naux_p, lds, [&](const double *L) {
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int k = kk * 4 + kl;
+      double fa[2], fb[2], ga[2], gb[2];
+#pragma unroll
+      for (int p = 0; p < 2; ++p) fa[p] = L[(0 * KC + k) * W + lcol<W>(32 * wr + 16 * p + cl, k)];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) fb[q] = L[(1 * KC + k) * W + lcol<W>(32 * wc + 16 * q + cl, k)];
+      if constexpr (NEED_Y) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          ga[p] = L[(2 * KC + k) * W + lcol<W>(32 * wr + 16 * p + cl, k)];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          gb[q] = L[(3 * KC + k) * W + lcol<W>(32 * wc + 16 * q + cl, k)];
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          ax[p][q] = mfma64(fa[p], fb[q], ax[p][q]);
+          if constexpr (NEED_Y) ay[p][q] = mfma64(ga[p], gb[q], ay[p][q]);
+        }
+    }
+  });
+}
+
+// Full x, y for one CCVV work item (x^T through LDS for class 1, y = x for
+// classes 2 and 3). Leaves LDS free (ends on a barrier).
+__device__ __forceinline__ void ccvv_compute(const double *Pcv, int64_t naux_p, int ntv,
+                                             const CcvvWork &c, double *lds, d4 (&ax)[2][2],
+                                             d4 (&ay)[2][2], int wr, int wc, int cl, int kl) {
+  constexpr int W = kPanel;
+  const int64_t pstride = naux_p * W;
+  const double *src[4] = {Pcv + (int64_t)(c.i * ntv + c.A) * pstride,
+                          Pcv + (int64_t)(c.j * ntv + c.B) * pstride,
+                          Pcv + (int64_t)(c.j * ntv + c.A) * pstride,
+                          Pcv + (int64_t)(c.i * ntv + c.B) * pstride};
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      ax[p][q] = zero4();
+      ay[p][q] = zero4();
+    }
+  if (c.cls == 0)
+    ccvv_tiles<true>(src, naux_p, lds, ax, ay, wr, wc, cl, kl);
+  else
+    ccvv_tiles<false>(src, naux_p, lds, ax, ay, wr, wc, cl, kl);
+  if (c.cls == 1) {
+    double (*T)[W + 1] = reinterpret_cast<double (*)[W + 1]>(lds);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          T[32 * wr + 16 * p + 4 * r + kl][32 * wc + 16 * q + cl] = ax[p][q][r];
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          ay[p][q][r] = T[32 * wc + 16 * q + cl][32 * wr + 16 * p + 4 * r + kl];
+    __syncthreads();
+  } else if (c.cls != 0) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) ay[p][q] = ax[p][q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CAVV tiles for one (m, A <= B): X_u = B_mA^T B_uB, Y_u = B_uA^T B_mB for all
+// u < NA on TW x TW tiles (TW = 32 or 64), each wave owning a quadrant.
+// ---------------------------------------------------------------------------
+template <int NA, int TW>
+struct CavvCfg {
+  static constexpr int NP = 2 + 2 * NA;
+  static constexpr int HB = TW / 32;
+  static constexpr int HW = TW / 2;
+  // chunk length keeps both LDS buffers within 96 KB
+  static constexpr int KC = (2 * NP * 16 * TW * 8 <= 98304) ? 16 : ((2 * NP * 8 * TW * 8 <= 98304) ? 8 : 4);
+  static constexpr int LDS = 2 * NP * KC * TW;   // doubles
+};
+
+struct CavvWork {
+  int m, A, B;
+  bool diag;
+};
+
+__device__ __forceinline__ CavvWork decode_cavv(int64_t w, int ntw, int64_t n0) {
+  CavvWork c;
+  const int64_t ntp_lt = (int64_t)ntw * (ntw - 1) / 2;
+  if (w < n0) {
+    c.m = (int)(w / ntp_lt);
+    decode_pair_lt(w % ntp_lt, ntw, c.A, c.B);
+    c.diag = false;
+  } else {
+    w -= n0;
+    c.m = (int)(w / ntw);
+    c.A = c.B = (int)(w % ntw);
+    c.diag = true;
+  }
+  return c;
+}
+
+template <int NA, int TW>
+__device__ __forceinline__ void cavv_compute(const double *Pcv, const double *Pav,
+                                             int64_t naux_p, int ntv, const CavvWork &c,
+                                             double *lds, d4 (&X)[NA][TW / 32][TW / 32],
+                                             d4 (&Y)[NA][TW / 32][TW / 32], int wr, int wc,
+                                             int cl, int kl) {
+  using C = CavvCfg<NA, TW>;
+  constexpr int KC = C::KC, HB = C::HB, HW = C::HW, NP = C::NP;
+  const int64_t pstride = naux_p * kPanel;
+  const int pA = (c.A * TW) / kPanel, oA = (c.A * TW) % kPanel;
+  const int pB = (c.B * TW) / kPanel, oB = (c.B * TW) % kPanel;
+  const double *src[NP];
+  src[0] = Pcv + (int64_t)(c.m * ntv + pA) * pstride + oA;
+  src[1] = Pcv + (int64_t)(c.m * ntv + pB) * pstride + oB;
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    src[2 + u] = Pav + (int64_t)(u * ntv + pA) * pstride + oA;
+    src[2 + NA + u] = Pav + (int64_t)(u * ntv + pB) * pstride + oB;
+  }
+#pragma unroll
+  for (int u = 0; u < NA; ++u)
+#pragma unroll
+    for (int p = 0; p < HB; ++p)
+#pragma unroll
+      for (int q = 0; q < HB; ++q) {
+        X[u][p][q] = zero4();
+        Y[u][p][q] = zero4();
+      }
+  kloop<NP, TW, KC>(src, kPanel, naux_p, lds, [&](const double *L) {
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int k = kk * 4 + kl;
+      double am[HB], bm[HB];
+#pragma unroll
+      for (int p = 0; p < HB; ++p) am[p] = L[(0 * KC + k) * TW + lcol<TW>(HW * wr + 16 * p + cl, k)];
+#pragma unroll
+      for (int q = 0; q < HB; ++q) bm[q] = L[(1 * KC + k) * TW + lcol<TW>(HW * wc + 16 * q + cl, k)];
+#pragma unroll
+      for (int u = 0; u < NA; ++u) {
+        double au[HB], bu[HB];
+#pragma unroll
+        for (int p = 0; p < HB; ++p)
+          au[p] = L[((2 + u) * KC + k) * TW + lcol<TW>(HW * wr + 16 * p + cl, k)];
+#pragma unroll
+        for (int q = 0; q < HB; ++q)
+          bu[q] = L[((2 + NA + u) * KC + k) * TW + lcol<TW>(HW * wc + 16 * q + cl, k)];
+#pragma unroll
+        for (int p = 0; p < HB; ++p)
+#pragma unroll
+          for (int q = 0; q < HB; ++q) {
+            X[u][p][q] = mfma64(am[p], bu[q], X[u][p][q]);
+            Y[u][p][q] = mfma64(au[p], bm[q], Y[u][p][q]);
+          }
+      }
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// CCAV tiles for one (m <= n, 64-row virtual tile T): x[e][u] = (me|nu),
+// y[e][u] = (ne|mu), na padded to 16 columns; each wave owns 16 rows. The two
+// 64 x 16 tiles are left in LDS as xs[2][64][17] for row-wise epilogues.
+// ---------------------------------------------------------------------------
+constexpr int kCcavKC = 16;
+constexpr int kCcavLdsV = 2 * 2 * kCcavKC * kPanel;       // doubles
+constexpr int kCcavLdsA = 2 * 2 * kCcavKC * kActPanel;    // doubles
+constexpr int kCcavLds = kCcavLdsV + kCcavLdsA;
+
+__device__ __forceinline__ void ccav_compute(const double *Pcv, const double *Pca,
+                                             int64_t naux_p, int ntv, int m, int n, int T,
+                                             double *lds, double (*xs)[kPanel][kActPanel + 1]) {
+  constexpr int W = kPanel, WA = kActPanel, KC = kCcavKC;
+  const int64_t pstride = naux_p * W;
+  const double *srcv[2] = {Pcv + (int64_t)(m * ntv + T) * pstride,
+                           Pcv + (int64_t)(n * ntv + T) * pstride};
+  const double *srca[2] = {Pca + (int64_t)n * naux_p * WA, Pca + (int64_t)m * naux_p * WA};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, kl = lane >> 4;
+  d4 x = zero4(), y = zero4();
+  double *lv = lds, *la = lds + kCcavLdsV;
+  Stage<2, W, KC> sv;
+  Stage<2, WA, KC> sa;
+  sv.load(srcv, W, 0);
+  sa.load(srca, WA, 0);
+  sv.store(lv);
+  sa.store(la);
+  if (naux_p > KC) {
+    sv.load(srcv, W, KC);
+    sa.load(srca, WA, KC);
+  }
+  __syncthreads();
+  int b = 0;
+  for (int64_t q0 = 0; q0 < naux_p; q0 += KC) {
+    const double *LV = lv + b * (2 * KC * W), *LA = la + b * (2 * KC * WA);
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int k = kk * 4 + kl;
+      x = mfma64(LV[(0 * KC + k) * W + lcol<W>(16 * wave + cl, k)], LA[(0 * KC + k) * WA + cl], x);
+      y = mfma64(LV[(1 * KC + k) * W + lcol<W>(16 * wave + cl, k)], LA[(1 * KC + k) * WA + cl], y);
+    }
+    if (q0 + KC < naux_p) {
+      sv.store(lv + (b ^ 1) * (2 * KC * W));
+      sa.store(la + (b ^ 1) * (2 * KC * WA));
+      if (q0 + 2 * KC < naux_p) {
+        sv.load(srcv, W, q0 + 2 * KC);
+        sa.load(srca, WA, q0 + 2 * KC);
+      }
+    }
+    __syncthreads();
+    b ^= 1;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    xs[0][16 * wave + 4 * r + kl][cl] = x[r];
+    xs[1][16 * wave + 4 * r + kl][cl] = y[r];
+  }
+  __syncthreads();
+}
+
+}  // namespace dsrg

@@ -35,6 +35,7 @@ struct Plan {
 
   // workspace layout (byte offsets, 256-aligned)
   size_t off_pcv, off_pav, off_pca;   // packed FP64 panels
+  size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
   size_t off_slots;                   // per-workgroup partial energies
   size_t off_acc;                     // [4] atomic accumulators
   size_t total;
@@ -45,6 +46,12 @@ struct Plan {
 struct Inputs {
   const double *B_cv, *B_ca, *B_av;
   const double *eps_c, *eps_a, *eps_v, *gamma1;
+};
+
+struct BwdOut {
+  double *dB_cv, *dB_ca, *dB_av;
+  double *deps_c, *deps_a, *deps_v, *ds;
+  const double *gE;
 };
 
 // number of A<B tile pairs, and the closed-form counts of the CCVV work list
@@ -58,5 +65,8 @@ void timer_end(hipStream_t st);
 hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_finalize(const Plan &pl, void *ws, double *E_terms, hipStream_t st);
+// ---- adjoint (fp64_bwd.hip) ----
+hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                hipStream_t st);
 
 }  // namespace dsrg
