@@ -78,8 +78,14 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   if (p->nc > (1 << 20) || p->nv > (1 << 24) || p->naux > (1 << 24))
     return fail(DSRG_ERR_UNSUPPORTED, "dimensions too large (nc %lld, nv %lld, naux %lld)",
                 (long long)p->nc, (long long)p->nv, (long long)p->naux);
-  if (precision != DSRG_FP64)
+  if (precision == DSRG_SPLIT_BF16)
     return fail(DSRG_ERR_UNSUPPORTED, "precision %d is not available in this build", precision);
+  if (precision == DSRG_SPLIT_OZAKI && with_grad)
+    return fail(DSRG_ERR_UNSUPPORTED, "gradients are available in FP64 only");
+  if (precision == DSRG_SPLIT_OZAKI && p->naux > 100000)
+    return fail(DSRG_ERR_UNSUPPORTED,
+                "naux = %lld exceeds 100000, beyond which int32 slice sums could overflow",
+                (long long)p->naux);
 
   pl.nc = p->nc;
   pl.na = p->na;
@@ -99,22 +105,74 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
                   ? (npo * ntpo + npo * pl.ntv + pl.nc * ntpo + pl.nc * pl.ntv)
                   : 0;
   const int64_t ntw = ceil_div(pl.nv, pl.cavv_tile);
-  pl.n_cavv = ((term_bits & DSRG_TERM_CAVV) && pl.na > 0) ? pl.nc * (tri_off(ntw) + ntw) : 0;
-  pl.n_ccav =
-      ((term_bits & DSRG_TERM_CCAV) && pl.na > 0) ? (pl.nc * (pl.nc + 1) / 2) * pl.ntv : 0;
+  const bool split = precision == DSRG_SPLIT_OZAKI;
+  const bool has_cavv = (term_bits & DSRG_TERM_CAVV) && pl.na > 0;
+  const bool has_ccav = (term_bits & DSRG_TERM_CCAV) && pl.na > 0;
+  pl.nqc = ceil_div(pl.naux, 32);
+  if (split) {
+    // CAVV integral batches of at most 512 MB
+    const int64_t per_m = pl.na * (pl.ntv * kPanel) * (pl.ntv * kPanel) * 8;
+    pl.cavv_mb = per_m > 0 ? (((int64_t)512 << 20) / per_m) : pl.nc;
+    if (pl.cavv_mb < 1) pl.cavv_mb = 1;
+    if (pl.cavv_mb > pl.nc) pl.cavv_mb = pl.nc;
+  } else {
+    pl.cavv_mb = 0;
+  }
+  pl.n_cavv = !has_cavv ? 0
+              : split   ? pl.nc * pl.ntv * ceil_div(pl.nv, 256)
+                        : pl.nc * (tri_off(ntw) + ntw);
+  pl.ccav_cols = round_up(pl.nc * pl.na, 16);
+  // forward: one slot per (m <= n, 256 virtual orbitals); adjoint: per (m <= n, 64-tile)
+  pl.n_ccav = has_ccav
+                  ? (pl.nc * (pl.nc + 1) / 2) * (pl.with_grad ? pl.ntv : ceil_div(pl.nv, 256))
+                  : 0;
   const int64_t maxgrid = ((int64_t)1 << 31) - 1;
   if (pl.n_ccvv > maxgrid || pl.n_cavv > maxgrid || pl.n_ccav > maxgrid)
     return fail(DSRG_ERR_UNSUPPORTED, "work list exceeds one launch grid");
 
   size_t off = 0;
+  // FP64 panels: every FP64 kernel; in the slice path only the CCAV GEMM
   pl.off_pcv = off;
-  off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.ntv * pl.naux_p * kPanel));
+  if (!split || has_ccav)
+    off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.ntv * pl.naux_p * kPanel));
   pl.off_pav = off;
-  if (pl.na > 0 && (term_bits & DSRG_TERM_CAVV))
+  if (!split && has_cavv)
     off = align256(off + sizeof(double) * (size_t)(pl.na * pl.ntv * pl.naux_p * kPanel));
   pl.off_pca = off;
-  if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV))
-    off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.naux_p * kActPanel));
+  pl.off_j = off;
+  if (has_ccav) {
+    if (pl.with_grad) {
+      off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.naux_p * kActPanel));
+    } else {
+      off = align256(off + sizeof(double) * (size_t)(pl.naux_p * pl.ccav_cols));
+      pl.off_j = off;
+      off = align256(off + sizeof(double) *
+                               (size_t)(pl.nc * pl.ntv * kPanel) * (size_t)pl.ccav_cols);
+    }
+  }
+  pl.off_s8c = pl.off_s8a = pl.off_sigc = pl.off_siga = pl.off_diag = pl.off_xb = pl.off_scr =
+      off;
+  if (split) {
+    const size_t chunk = 5 * kPanel * 32;   // bytes per (panel, 32 auxiliary indices)
+    const size_t colc = (size_t)(pl.nc * pl.ntv * kPanel), cola = (size_t)(pl.na * pl.ntv * kPanel);
+    pl.off_s8c = off;
+    off = align256(off + chunk * (size_t)(pl.nc * pl.ntv * pl.nqc));
+    pl.off_sigc = off;
+    off = align256(off + sizeof(double) * colc);
+    pl.off_diag = off;
+    off = align256(off + sizeof(double) * colc);
+    pl.off_scr = off;
+    off = align256(off + sizeof(double) * 2 * 32 * (colc > cola ? colc : cola));
+    if (has_cavv) {
+      pl.off_s8a = off;
+      off = align256(off + chunk * (size_t)(pl.na * pl.ntv * pl.nqc));
+      pl.off_siga = off;
+      off = align256(off + sizeof(double) * cola);
+      pl.off_xb = off;
+      off = align256(off + sizeof(double) * (size_t)(pl.cavv_mb * pl.na) *
+                               (size_t)(pl.ntv * kPanel) * (size_t)(pl.ntv * kPanel));
+    }
+  }
   pl.off_gs = pl.off_g2 = pl.off_g3 = off;
   if (pl.with_grad) {
     const size_t Np = (size_t)(pl.nc * pl.ntv * kPanel);
@@ -219,7 +277,8 @@ dsrg_status dsrg_df_energy(const dsrg_df_problem *p, int precision, int terms, d
   dsrg::Inputs in{p->B_cv, p->B_ca, p->B_av, p->eps_c, p->eps_a, p->eps_v, p->gamma1};
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   timer_reset((terms & DSRG_OPT_KERNEL_TIMING) != 0);
-  hipError_t e = dsrg::launch_energy_fp64(pl, in, workspace, hs);
+  hipError_t e = (precision == DSRG_SPLIT_OZAKI) ? dsrg::launch_energy_split(pl, in, workspace, hs)
+                                                 : dsrg::launch_energy_fp64(pl, in, workspace, hs);
   if (e == hipSuccess) e = dsrg::launch_finalize(pl, workspace, E_terms, hs);
   if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return DSRG_OK;

@@ -178,58 +178,124 @@ __global__ __launch_bounds__(256) void cavv_fp64_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// CCAV (F3). One workgroup per (core pair m <= n, 64-row virtual tile T),
-// x[e][u] = (me|nu), y[e][u] = (ne|mu). Per e:
+// CCAV (F3), two steps. (1) J[(m,e)][(n,u)] = (me|nu) = sum_Q B^Q_me B^Q_nu as
+// one FP64 matrix-core GEMM over all core-virtual rows (m, e) and all
+// core-active columns (n, u) (the B_ca block flattened, padded to a multiple
+// of 16 columns); J holds nc^2 nv na values, the size of the integrals with
+// one active index. (2) per (m <= n, e):
 //   sum_uv etab_uv S(D^{ev}_{mn}) R1(D^{eu}_{mn}) [x_v (2x_u - y_u) + y_v (2y_u - x_u)]
-// with etab = 2I - Gamma: covers (m,n) and (n,m); weight 1 (m<n), 1/2 (m=n).
+// with x_u = (me|nu), y_u = (ne|mu), etab = 2I - Gamma: covers (m,n) and
+// (n,m); weight 1 for m < n and 1/2 for m = n.
 // ---------------------------------------------------------------------------
-struct CcavArgs {
-  int nc, na, nv, ntv;
+struct CcavJArgs {
+  int ntv;
   int64_t naux_p;
+  int64_t ncols;     // padded column count of J (multiple of 16)
+};
+
+template <int NB>   // column blocks of 16 per workgroup
+__global__ __launch_bounds__(256) void ccav_j_fp64_kernel(const double *__restrict__ Pcv,
+                                                          const double *__restrict__ Pca2,
+                                                          CcavJArgs a, double *__restrict__ J) {
+  constexpr int W = kPanel, WB = 16 * NB, KC = 16;
+  __shared__ double lv[2 * KC * W];
+  __shared__ double lb[2 * KC * WB];
+  const int64_t panel = blockIdx.x;                 // (m, T) panel index
+  const int64_t c0 = (int64_t)blockIdx.y * WB;      // first column of this workgroup
+  const double *srcv[1] = {Pcv + panel * a.naux_p * W};
+  const double *srcb[1] = {Pca2 + c0};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane & 15, kl = lane >> 4;
+  d4 acc[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) acc[q] = zero4();
+  Stage<1, W, KC> sv;
+  Stage<1, WB, KC> sb;
+  sv.load(srcv, W, 0);
+  sb.load(srcb, a.ncols, 0);
+  sv.store(lv);
+  sb.store(lb);
+  if (a.naux_p > KC) {
+    sv.load(srcv, W, KC);
+    sb.load(srcb, a.ncols, KC);
+  }
+  __syncthreads();
+  int b = 0;
+  for (int64_t q0 = 0; q0 < a.naux_p; q0 += KC) {
+    const double *LV = lv + b * (KC * W), *LB = lb + b * (KC * WB);
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int k = kk * 4 + kl;
+      const double fa = LV[k * W + lcol<W>(16 * wave + cl, k)];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) acc[q] = mfma64(fa, LB[k * WB + lcol<WB>(16 * q + cl, k)], acc[q]);
+    }
+    if (q0 + KC < a.naux_p) {
+      sv.store(lv + (b ^ 1) * (KC * W));
+      sb.store(lb + (b ^ 1) * (KC * WB));
+      if (q0 + 2 * KC < a.naux_p) {
+        sv.load(srcv, W, q0 + 2 * KC);
+        sb.load(srcb, a.ncols, q0 + 2 * KC);
+      }
+    }
+    __syncthreads();
+    b ^= 1;
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int64_t col = c0 + 16 * q + cl;
+    if (col >= a.ncols) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = panel * W + 16 * wave + 4 * r + kl;
+      J[row * a.ncols + col] = acc[q][r];
+    }
+  }
+}
+
+struct CcavEpiArgs {
+  int nc, na, nv, ntv;
+  int64_t ncols;
   double s;
+  int echunks;       // blocks of 256 virtual orbitals per core pair
   int64_t slot_base;
   int atomic_mode;
 };
 
 template <int NA>
-__global__ __launch_bounds__(256) void ccav_fp64_kernel(
-    const double *__restrict__ Pcv, const double *__restrict__ Pca,
-    const double *__restrict__ eps_c, const double *__restrict__ eps_a,
-    const double *__restrict__ eps_v, const double *__restrict__ gamma1, CcavArgs a,
-    double *slots, double *acc) {
-  constexpr int W = kPanel;
-  __shared__ double lds[kCcavLds];
-  __shared__ double xs[2][kPanel][kActPanel + 1];
+__global__ __launch_bounds__(256) void ccav_epi_fp64_kernel(
+    const double *__restrict__ J, const double *__restrict__ eps_c,
+    const double *__restrict__ eps_a, const double *__restrict__ eps_v,
+    const double *__restrict__ gamma1, CcavEpiArgs a, double *slots, double *acc) {
+  __shared__ double red[4];
   int m, n;
-  decode_pair_le(blockIdx.x / a.ntv, a.nc, m, n);
-  const int T = (int)(blockIdx.x % a.ntv);
-  ccav_compute(Pcv, Pca, a.naux_p, a.ntv, m, n, T, lds, xs);
+  decode_pair_le(blockIdx.x / a.echunks, a.nc, m, n);
+  const int e = (int)(blockIdx.x % a.echunks) * 256 + threadIdx.x;
   double part = 0.0;
-  if (threadIdx.x < W) {
-    const int e = T * W + threadIdx.x;
-    if (e < a.nv) {
-      const double base = eps_c[m] + eps_c[n] - eps_v[e];
-      double S[NA], R1[NA], xv[NA], yv[NA];
+  if (e < a.nv) {
+    const double *xr = J + ((int64_t)m * a.ntv * kPanel + e) * a.ncols + (int64_t)n * NA;
+    const double *yr = J + ((int64_t)n * a.ntv * kPanel + e) * a.ncols + (int64_t)m * NA;
+    const double base = eps_c[m] + eps_c[n] - eps_v[e];
+    double S[NA], R1[NA], xv[NA], yv[NA];
 #pragma unroll
-      for (int u = 0; u < NA; ++u) {
-        reg_S_R1(base - eps_a[u], a.s, S[u], R1[u]);
-        xv[u] = xs[0][threadIdx.x][u];
-        yv[u] = xs[1][threadIdx.x][u];
+    for (int u = 0; u < NA; ++u) {
+      reg_S_R1(base - eps_a[u], a.s, S[u], R1[u]);
+      xv[u] = xr[u];
+      yv[u] = yr[u];
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int v = 0; v < NA; ++v) {
+        const double eb = (u == v ? 2.0 : 0.0) - gamma1[u * NA + v];
+        sx += eb * S[v] * xv[v];
+        sy += eb * S[v] * yv[v];
       }
-#pragma unroll
-      for (int u = 0; u < NA; ++u) {
-        double sx = 0.0, sy = 0.0;
-#pragma unroll
-        for (int v = 0; v < NA; ++v) {
-          const double eb = (u == v ? 2.0 : 0.0) - gamma1[u * NA + v];
-          sx += eb * S[v] * xv[v];
-          sy += eb * S[v] * yv[v];
-        }
-        part += R1[u] * ((2.0 * xv[u] - yv[u]) * sx + (2.0 * yv[u] - xv[u]) * sy);
-      }
+      part += R1[u] * ((2.0 * xv[u] - yv[u]) * sx + (2.0 * yv[u] - xv[u]) * sy);
     }
   }
-  const double t = block_sum(part, lds) * ((m == n) ? 0.5 : 1.0);
+  const double t = block_sum(part, red) * ((m == n) ? 0.5 : 1.0);
   emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
 }
 
@@ -311,14 +377,18 @@ hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStrea
   hipError_t e = pack_one(in.B_cv, ws_d(ws, pl.off_pcv), pl.nc, pl.nv, pl.naux, pl.naux_p,
                           pl.ntv, kPanel, st);
   if (e != hipSuccess) return e;
-  if (pl.na > 0 && (pl.terms & 2)) {
+  if (pl.na > 0 && (pl.terms & 2) && pl.precision == 0) {
     e = pack_one(in.B_av, ws_d(ws, pl.off_pav), pl.na, pl.nv, pl.naux, pl.naux_p, pl.ntv,
                  kPanel, st);
     if (e != hipSuccess) return e;
   }
   if (pl.na > 0 && (pl.terms & 4)) {
-    e = pack_one(in.B_ca, ws_d(ws, pl.off_pca), pl.nc, pl.na, pl.naux, pl.naux_p, 1,
-                 kActPanel, st);
+    if (pl.with_grad)
+      e = pack_one(in.B_ca, ws_d(ws, pl.off_pca), pl.nc, pl.na, pl.naux, pl.naux_p, 1,
+                   kActPanel, st);
+    else   // flattened (n,u) columns, padded to ccav_cols
+      e = pack_one(in.B_ca, ws_d(ws, pl.off_pca), 1, pl.nc * pl.na, pl.naux, pl.naux_p, 1,
+                   (int)pl.ccav_cols, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -357,19 +427,39 @@ static hipError_t launch_cavv_na(const Plan &pl, const Inputs &in, void *ws, hip
 template <int NA>
 static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                                  double *slots, double *acc) {
-  CcavArgs a;
+  CcavJArgs ja;
+  ja.ntv = (int)pl.ntv;
+  ja.naux_p = pl.naux_p;
+  ja.ncols = pl.ccav_cols;
+  // column blocks of 16 per workgroup: the largest of 4, 3, 2, 1 that divides
+  // the block count, so no workgroup reads past the last column
+  const int nblk = (int)(pl.ccav_cols / 16);
+  const int NBsel = (nblk % 4 == 0) ? 4 : (nblk % 3 == 0) ? 3 : (nblk % 2 == 0) ? 2 : 1;
+  const dim3 gj((unsigned)(pl.nc * pl.ntv), (unsigned)ceil_div(nblk, NBsel));
+  timer_begin("ccav_j_fp64", st);
+  switch (NBsel) {
+    case 1: hipLaunchKernelGGL(ccav_j_fp64_kernel<1>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
+    case 2: hipLaunchKernelGGL(ccav_j_fp64_kernel<2>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
+    case 3: hipLaunchKernelGGL(ccav_j_fp64_kernel<3>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
+    default: hipLaunchKernelGGL(ccav_j_fp64_kernel<4>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
+  }
+  timer_end(st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  CcavEpiArgs a;
   a.nc = (int)pl.nc;
   a.na = (int)pl.na;
   a.nv = (int)pl.nv;
   a.ntv = (int)pl.ntv;
-  a.naux_p = pl.naux_p;
+  a.ncols = pl.ccav_cols;
   a.s = pl.s;
+  a.echunks = (int)ceil_div(pl.nv, 256);
   a.slot_base = pl.slot_base[2];
   a.atomic_mode = pl.atomic_reduce ? 1 : 0;
-  timer_begin("ccav_fp64", st);
-  hipLaunchKernelGGL((ccav_fp64_kernel<NA>), dim3((unsigned)pl.n_ccav), dim3(256), 0,
-                     st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), in.eps_c, in.eps_a,
-                     in.eps_v, in.gamma1, a, slots, acc + 2);
+  timer_begin("ccav_epi_fp64", st);
+  hipLaunchKernelGGL((ccav_epi_fp64_kernel<NA>), dim3((unsigned)pl.n_ccav), dim3(256), 0, st,
+                     ws_d(ws, pl.off_j), in.eps_c, in.eps_a, in.eps_v, in.gamma1, a, slots,
+                     acc + 2);
   timer_end(st);
   return hipGetLastError();
 }
@@ -394,6 +484,15 @@ static hipError_t launch_cavv(const Plan &pl, const Inputs &in, void *ws, hipStr
 static hipError_t launch_ccav(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                               double *slots, double *acc) {
   DSRG_NA_SWITCH(launch_ccav_na, pl, in, ws, st, slots, acc)
+}
+
+hipError_t launch_ccav_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st) {
+  return launch_ccav(pl, in, ws, st, ws_d(ws, pl.off_slots), ws_d(ws, pl.off_acc));
+}
+
+hipError_t launch_zero(double *p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st) {

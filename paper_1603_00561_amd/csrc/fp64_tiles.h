@@ -17,8 +17,8 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 
 __device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
 
-// LDS rows of W doubles hold one auxiliary index each. The 16-column halves
-// of odd rows are swapped (column c of row k lives at c ^ swz(k)), so the two
+// LDS rows of W doubles hold one auxiliary index each. For W a multiple of
+// 32, the 16-column halves of odd rows are swapped (column c of row k lives at c ^ swz(k)), so the two
 // rows that one 32-lane half of a fragment read touches land in different
 // bank halves without padding.
 __device__ __forceinline__ int swz(int k) { return (k & 1) << 4; }
@@ -55,7 +55,7 @@ struct Stage {
         if (N2 % kThreads == 0 || idx < N2) {
           const int row = idx / (W / 2);
           const int c2 = idx % (W / 2);
-          const int col = (W >= 32) ? ((2 * c2) ^ swz(row)) : 2 * c2;
+          const int col = (W % 32 == 0) ? ((2 * c2) ^ swz(row)) : 2 * c2;
           *reinterpret_cast<d2v *>(&buf[(p * KC + row) * W + col]) = r[p][k];
         }
       }
@@ -66,7 +66,7 @@ struct Stage {
 // Column of row k in an LDS panel of width W (matches Stage::store).
 template <int W>
 __device__ __forceinline__ int lcol(int c, int k) {
-  return (W >= 32) ? (c ^ swz(k)) : c;
+  return (W % 32 == 0) ? (c ^ swz(k)) : c;
 }
 
 // Double-buffered K loop: lds holds 2 * NP * KC * W doubles. compute(L) is

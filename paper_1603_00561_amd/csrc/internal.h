@@ -32,9 +32,15 @@ struct Plan {
   // work counts (workgroups) per term
   int64_t n_ccvv, n_cavv, n_ccav;
   int cavv_tile;    // 32 or 64 columns per CAVV tile side
+  int64_t ccav_cols; // padded (n, u) column count of the CCAV integral block
 
   // workspace layout (byte offsets, 256-aligned)
   size_t off_pcv, off_pav, off_pca;   // packed FP64 panels
+  size_t off_j;                       // CCAV integrals (me|nu)
+  // int8 slice path
+  int64_t nqc;                        // chunks of 32 auxiliary indices
+  int64_t cavv_mb;                    // core orbitals per CAVV integral batch
+  size_t off_s8c, off_s8a, off_sigc, off_siga, off_diag, off_xb, off_scr;
   size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
   size_t off_slots;                   // per-workgroup partial energies
   size_t off_acc;                     // [4] atomic accumulators
@@ -65,6 +71,10 @@ void timer_end(hipStream_t st);
 hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_finalize(const Plan &pl, void *ws, double *E_terms, hipStream_t st);
+hipError_t launch_ccav_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
+hipError_t launch_zero(double *p, int n, hipStream_t st);
+// ---- int8 slice path (split_kernels.hip) ----
+hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 // ---- adjoint (fp64_bwd.hip) ----
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st);
