@@ -109,18 +109,20 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   const bool has_cavv = (term_bits & DSRG_TERM_CAVV) && pl.na > 0;
   const bool has_ccav = (term_bits & DSRG_TERM_CCAV) && pl.na > 0;
   pl.nqc = ceil_div(pl.naux, 32);
-  if (split) {
-    // CAVV integral batches of at most 512 MB
+  // forward CAVV (both precisions) goes through batches of (me|uf) integrals
+  // of at most 512 MB
+  const bool xbatch = has_cavv && !pl.with_grad;
+  if (xbatch) {
     const int64_t per_m = pl.na * (pl.ntv * kPanel) * (pl.ntv * kPanel) * 8;
-    pl.cavv_mb = per_m > 0 ? (((int64_t)512 << 20) / per_m) : pl.nc;
+    pl.cavv_mb = ((int64_t)512 << 20) / per_m;
     if (pl.cavv_mb < 1) pl.cavv_mb = 1;
     if (pl.cavv_mb > pl.nc) pl.cavv_mb = pl.nc;
   } else {
     pl.cavv_mb = 0;
   }
-  pl.n_cavv = !has_cavv ? 0
-              : split   ? pl.nc * pl.ntv * ceil_div(pl.nv, 256)
-                        : pl.nc * (tri_off(ntw) + ntw);
+  pl.n_cavv = !has_cavv      ? 0
+              : pl.with_grad ? pl.nc * (tri_off(ntw) + ntw)
+                             : pl.nc * pl.ntv * ceil_div(pl.nv, 256);
   pl.ccav_cols = round_up(pl.nc * pl.na, 16);
   // forward: one slot per (m <= n, 256 virtual orbitals); adjoint: per (m <= n, 64-tile)
   pl.n_ccav = has_ccav
@@ -168,10 +170,12 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       off = align256(off + chunk * (size_t)(pl.na * pl.ntv * pl.nqc));
       pl.off_siga = off;
       off = align256(off + sizeof(double) * cola);
-      pl.off_xb = off;
-      off = align256(off + sizeof(double) * (size_t)(pl.cavv_mb * pl.na) *
-                               (size_t)(pl.ntv * kPanel) * (size_t)(pl.ntv * kPanel));
     }
+  }
+  if (xbatch) {
+    pl.off_xb = off;
+    off = align256(off + sizeof(double) * (size_t)(pl.cavv_mb * pl.na) *
+                             (size_t)(pl.ntv * kPanel) * (size_t)(pl.ntv * kPanel));
   }
   pl.off_gs = pl.off_g2 = pl.off_g3 = off;
   if (pl.with_grad) {

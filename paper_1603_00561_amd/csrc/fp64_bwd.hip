@@ -73,12 +73,14 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
   constexpr int W = kPanel;
   __shared__ double lds[kCcvvLds];
   __shared__ double rsum[W], csum[W];
-  const CcvvWork c = decode_ccvv(blockIdx.x, a.nc, a.ntv, a.n0, a.n1, a.n2);
+  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.nc * (a.nc + 1) / 2, a.ntv);
+  if (pt.item < 0) return;
+  const CcvvWork c = ccvv_work_from(pt, a.nc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
   d4 ax[2][2], ay[2][2];
-  ccvv_compute(Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
+  ccvv_compute(Pcv, Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
   if (threadIdx.x < W) {
     rsum[threadIdx.x] = 0.0;
     csum[threadIdx.x] = 0.0;
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
   __syncthreads();
   const double tS = block_sum(s_part, lds);
   if (threadIdx.x == 0) {
-    slots[a.slot_base + blockIdx.x] = tE;
+    slots[a.slot_base + pt.item] = tE;
     atomicAdd(&g.deps_c[c.i], gE0 * tD);
     atomicAdd(&g.deps_c[c.j], gE0 * tD);
     atomicAdd(g.ds, gE0 * tS);
@@ -702,7 +704,7 @@ hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &
     a.slot_base = pl.slot_base[0];
     a.Np = Np;
     timer_begin("ccvv_adj_fp64", st);
-    hipLaunchKernelGGL(ccvv_adj_fp64_kernel, dim3((unsigned)pl.n_ccvv), dim3(256), 0, st,
+    hipLaunchKernelGGL(ccvv_adj_fp64_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(256), 0, st,
                        ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, g, ws_d(ws, pl.off_gs),
                        ws_d(ws, pl.off_slots));
     timer_end(st);

@@ -59,12 +59,14 @@ __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict
                                                         double *acc) {
   constexpr int W = kPanel;
   __shared__ double lds[kCcvvLds];
-  const CcvvWork c = decode_ccvv(blockIdx.x, a.nc, a.ntv, a.n0, a.n1, a.n2);
+  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.nc * (a.nc + 1) / 2, a.ntv);
+  if (pt.item < 0) return;
+  const CcvvWork c = ccvv_work_from(pt, a.nc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
   d4 ax[2][2], ay[2][2];
-  ccvv_compute(Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
+  ccvv_compute(Pcv, Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
 
   const double eij = eps_c[c.i] + eps_c[c.j];
   double eb[2];
@@ -85,96 +87,73 @@ __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         if (bcol[q] >= a.nv) continue;
-        const double R = reg_R(eij - ea - eb[q], a.s);
+        const double R = reg_R(eij - (ea + eb[q]), a.s);
         const double x = ax[p][q][r], y = ay[p][q][r];
         part += R * (x * x - x * y + y * y);
       }
     }
   }
   const double t = block_sum(part, lds) * ccvv_weight(c.cls);
-  emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
+  emit_partial(t, slots, a.slot_base + pt.item, acc, a.atomic_mode);
 }
 
 // ---------------------------------------------------------------------------
-// CAVV (F2). One workgroup per (core m, virtual tile pair A <= B) with tiles
-// of TW columns; per (e,f) the epilogue forms
-//   sum_uv Gamma_uv S(D_mu) R1(D_mv) [X_u (2X_v - Y_v) + Y_u (2Y_v - X_v)]
-// with X_u = (me|uf), Y_u = (mf|ue): both (e,f) and (f,e). Weight 1 for
-// A<B and 1/2 for A=B.
+// CAVV (F2), step 1 in FP64: for core orbitals m0 .. m0+mb-1 and active u, the
+// integrals X^{mu}[e][f] = (me|uf) of every virtual tile pair A <= B (the CCVV
+// tile machinery with pair (m, u), left panels B_cv, right panels B_av) are
+// written to Xb[(m - m0)][u][e][f]: block [A,B] from x and block [B,A] from
+// y = X^{mu}[B,A]^T. Step 2 (cavv_epi_kernel) forms the energy.
 // ---------------------------------------------------------------------------
-struct CavvArgs {
-  int nc, na, nv, ntv, ntw;
+struct CavvXArgs64 {
+  int na, ntv;
   int64_t naux_p;
-  double s;
-  int64_t n0;              // number of A<B work items
-  int64_t slot_base;
-  int atomic_mode;
+  int m0, mb;
 };
 
-template <int NA, int TW>
-__global__ __launch_bounds__(256) void cavv_fp64_kernel(
-    const double *__restrict__ Pcv, const double *__restrict__ Pav,
-    const double *__restrict__ eps_c, const double *__restrict__ eps_a,
-    const double *__restrict__ eps_v, const double *__restrict__ gamma1, CavvArgs a,
-    double *slots, double *acc) {
-  using Cfg = CavvCfg<NA, TW>;
-  constexpr int HB = Cfg::HB, HW = Cfg::HW;
-  __shared__ double lds[Cfg::LDS];
-  const CavvWork c = decode_cavv(blockIdx.x, a.ntw, a.n0);
+__global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restrict__ Pcv,
+                                                          const double *__restrict__ Pav,
+                                                          CavvXArgs64 a, double *__restrict__ Xb) {
+  constexpr int W = kPanel;
+  __shared__ double lds[kCcvvLds];
+  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.mb * a.na, a.ntv);
+  if (pt.item < 0) return;
+  const int ml = (int)(pt.p / a.na), u = (int)(pt.p % a.na);
+  CcvvWork c;
+  c.i = a.m0 + ml;
+  c.j = u;
+  c.A = pt.A;
+  c.B = pt.B;
+  c.cls = (c.A == c.B) ? 2 : 0;   // y is needed only off the diagonal
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
-  d4 X[NA][HB][HB], Y[NA][HB][HB];
-  cavv_compute<NA, TW>(Pcv, Pav, a.naux_p, a.ntv, c, lds, X, Y, wr, wc, cl, kl);
-
-  double G[NA][NA], ea[NA];
+  d4 ax[2][2], ay[2][2];
+  ccvv_compute(Pcv, Pav, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
+  const int64_t ld = (int64_t)a.ntv * W;
+  double *X = Xb + ((int64_t)ml * a.na + u) * ld * ld;
 #pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    ea[u] = eps_a[u];
+  for (int p = 0; p < 2; ++p)
 #pragma unroll
-    for (int v = 0; v < NA; ++v) G[u][v] = gamma1[u * NA + v];
-  }
-  const double em = eps_c[c.m];
-  double part = 0.0;
+    for (int q = 0; q < 2; ++q)
 #pragma unroll
-  for (int q = 0; q < HB; ++q) {
-    const int f = c.B * TW + HW * wc + 16 * q + cl;
-    if (f >= a.nv) continue;
-    const double ef = eps_v[f];
+      for (int r = 0; r < 4; ++r)
+        X[(int64_t)(c.A * W + 32 * wr + 16 * p + 4 * r + kl) * ld + c.B * W + 32 * wc + 16 * q +
+          cl] = ax[p][q][r];
+  if (c.A != c.B) {
+    double (*T)[W + 1] = reinterpret_cast<double (*)[W + 1]>(lds);
 #pragma unroll
-    for (int p = 0; p < HB; ++p) {
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = c.A * TW + HW * wr + 16 * p + 4 * r + kl;
-        if (e >= a.nv) continue;
-        const double base = em - eps_v[e] - ef;
-        double S[NA], R1[NA];
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int u = 0; u < NA; ++u) reg_S_R1(base + ea[u], a.s, S[u], R1[u]);
-        double Wv[NA], Wp[NA];
-#pragma unroll
-        for (int v = 0; v < NA; ++v) {
-          const double xv = X[v][p][q][r], yv = Y[v][p][q][r];
-          Wv[v] = R1[v] * (2.0 * xv - yv);
-          Wp[v] = R1[v] * (2.0 * yv - xv);
-        }
-        double val = 0.0;
-#pragma unroll
-        for (int u = 0; u < NA; ++u) {
-          double tw = 0.0, tp = 0.0;
-#pragma unroll
-          for (int v = 0; v < NA; ++v) {
-            tw += G[u][v] * Wv[v];
-            tp += G[u][v] * Wp[v];
-          }
-          val += S[u] * (X[u][p][q][r] * tw + Y[u][p][q][r] * tp);
-        }
-        part += val;
-      }
+        for (int r = 0; r < 4; ++r)
+          T[32 * wr + 16 * p + 4 * r + kl][32 * wc + 16 * q + cl] = ay[p][q][r];
+    __syncthreads();
+    for (int k = threadIdx.x; k < W * W; k += kThreads) {
+      const int fr = k / W, ec = k % W;
+      X[(int64_t)(c.B * W + fr) * ld + c.A * W + ec] = T[ec][fr];
     }
   }
-  const double t = block_sum(part, lds) * (c.diag ? 0.5 : 1.0);
-  emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,36 +374,6 @@ hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStrea
 }
 
 template <int NA>
-static hipError_t launch_cavv_na(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
-                                 double *slots, double *acc) {
-  CavvArgs a;
-  a.nc = (int)pl.nc;
-  a.na = (int)pl.na;
-  a.nv = (int)pl.nv;
-  a.ntv = (int)pl.ntv;
-  a.ntw = (int)ceil_div(pl.nv, pl.cavv_tile);
-  a.naux_p = pl.naux_p;
-  a.s = pl.s;
-  a.n0 = pl.nc * tri_off(a.ntw);
-  a.slot_base = pl.slot_base[1];
-  a.atomic_mode = pl.atomic_reduce ? 1 : 0;
-  const dim3 grid((unsigned)pl.n_cavv), block(256);
-  timer_begin("cavv_fp64", st);
-  if (pl.cavv_tile == 64) {
-    if constexpr (NA <= 2)
-      hipLaunchKernelGGL((cavv_fp64_kernel<NA, 64>), grid, block, 0, st, ws_d(ws, pl.off_pcv),
-                         ws_d(ws, pl.off_pav), in.eps_c, in.eps_a, in.eps_v, in.gamma1, a, slots,
-                         acc + 1);
-  } else {
-    hipLaunchKernelGGL((cavv_fp64_kernel<NA, 32>), grid, block, 0, st, ws_d(ws, pl.off_pcv),
-                       ws_d(ws, pl.off_pav), in.eps_c, in.eps_a, in.eps_v, in.gamma1, a, slots,
-                       acc + 1);
-  }
-  timer_end(st);
-  return hipGetLastError();
-}
-
-template <int NA>
 static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                                  double *slots, double *acc) {
   CcavJArgs ja;
@@ -478,8 +427,25 @@ static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hip
   }
 
 static hipError_t launch_cavv(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
-                              double *slots, double *acc) {
-  DSRG_NA_SWITCH(launch_cavv_na, pl, in, ws, st, slots, acc)
+                              double *, double *) {
+  for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
+    const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
+    CavvXArgs64 xa;
+    xa.na = (int)pl.na;
+    xa.ntv = (int)pl.ntv;
+    xa.naux_p = pl.naux_p;
+    xa.m0 = (int)m0;
+    xa.mb = mb;
+    timer_begin("cavv_fp64_x", st);
+    hipLaunchKernelGGL(cavv_fp64_x_kernel, dim3((unsigned)pairtile_grid((int64_t)mb * pl.na, pl.ntv)),
+                       dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), xa,
+                       ws_d(ws, pl.off_xb));
+    timer_end(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_cavv_epi(pl, in, ws, (int)m0, mb, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 static hipError_t launch_ccav(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                               double *slots, double *acc) {
@@ -518,7 +484,7 @@ hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStr
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
     timer_begin("ccvv_fp64", st);
-    hipLaunchKernelGGL(ccvv_fp64_kernel, dim3((unsigned)pl.n_ccvv), dim3(256), 0, st,
+    hipLaunchKernelGGL(ccvv_fp64_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(256), 0, st,
                        ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, slots, acc + 0);
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -128,6 +128,75 @@ __device__ __forceinline__ CcvvWork decode_ccvv(int64_t w, int nc, int ntv, int6
   return c;
 }
 
+// Pair-tile schedule. Items are (pair p, virtual tile pair A <= B) for P pairs
+// and T = ntv (ntv + 1) / 2 tile pairs. Workgroup b runs on XCD b % 8 (the
+// hardware deals workgroups round-robin over the eight XCDs); pairs are
+// dealt to XCDs round-robin too, so the eight XCDs work on eight consecutive
+// pairs at a time (sharing one core orbital), and each XCD walks the tile
+// pairs of its pair in 4 x 4 blocks so that concurrent workgroups share
+// panels in its L2. Item id = p * T + t (its slot); grid = 8 ceil(P/8) T.
+constexpr int kTileBlock = 4;
+
+__device__ __forceinline__ void decode_tile_blocked(int64_t t, int ntv, int &A, int &B) {
+  const int nb = (ntv + kTileBlock - 1) / kTileBlock;
+  for (int ba = 0; ba < nb; ++ba) {
+    const int na_ = (ba == nb - 1) ? ntv - ba * kTileBlock : kTileBlock;
+    for (int bb = ba; bb < nb; ++bb) {
+      const int nb_ = (bb == nb - 1) ? ntv - bb * kTileBlock : kTileBlock;
+      const int64_t size = (ba == bb) ? (int64_t)na_ * (na_ + 1) / 2 : (int64_t)na_ * nb_;
+      if (t < size) {
+        int a0, b0;
+        if (ba == bb) {
+          decode_pair_le(t, na_, a0, b0);
+        } else {
+          a0 = (int)(t / nb_);
+          b0 = (int)(t % nb_);
+        }
+        A = ba * kTileBlock + a0;
+        B = bb * kTileBlock + b0;
+        return;
+      }
+      t -= size;
+    }
+  }
+  A = B = 0;   // not reached for t < T
+}
+
+struct PairTile {
+  int64_t item;   // p * T + t, or -1 when this workgroup has no item
+  int64_t p;
+  int A, B;
+};
+
+__device__ __forceinline__ PairTile decode_pairtile(int64_t bid, int64_t P, int ntv) {
+  const int64_t T = (int64_t)ntv * (ntv + 1) / 2;
+  const int64_t x = bid % 8, k = bid / 8;
+  const int64_t lp = k / T, t = k % T;
+  PairTile r;
+  r.p = lp * 8 + x;
+  if (r.p >= P) {
+    r.item = -1;
+    r.A = r.B = 0;
+    return r;
+  }
+  r.item = r.p * T + t;
+  decode_tile_blocked(t, ntv, r.A, r.B);
+  return r;
+}
+
+inline int64_t pairtile_grid(int64_t P, int64_t ntv) {
+  return 8 * ((P + 7) / 8) * (ntv * (ntv + 1) / 2);
+}
+
+__device__ __forceinline__ CcvvWork ccvv_work_from(const PairTile &pt, int nc) {
+  CcvvWork c;
+  decode_pair_le(pt.p, nc, c.i, c.j);
+  c.A = pt.A;
+  c.B = pt.B;
+  c.cls = (c.i == c.j) ? (c.A == c.B ? 3 : 2) : (c.A == c.B ? 1 : 0);
+  return c;
+}
+
 constexpr int kCcvvKC = 16;
 constexpr int kCcvvLds = 2 * 4 * kCcvvKC * kPanel;   // doubles
 
@@ -168,15 +237,18 @@ __device__ __forceinline__ void ccvv_tiles(const double *const *src, int64_t nau
 
 // Full x, y for one CCVV work item (x^T through LDS for class 1, y = x for
 // classes 2 and 3). Leaves LDS free (ends on a barrier).
-__device__ __forceinline__ void ccvv_compute(const double *Pcv, int64_t naux_p, int ntv,
-                                             const CcvvWork &c, double *lds, d4 (&ax)[2][2],
-                                             d4 (&ay)[2][2], int wr, int wc, int cl, int kl) {
+// PL holds the panels of orbital c.i, PR those of orbital c.j (both Pcv for
+// CCVV; Pcv and Pav for the CAVV integrals (me|uf)).
+__device__ __forceinline__ void ccvv_compute(const double *PL, const double *PR, int64_t naux_p,
+                                             int ntv, const CcvvWork &c, double *lds,
+                                             d4 (&ax)[2][2], d4 (&ay)[2][2], int wr, int wc,
+                                             int cl, int kl) {
   constexpr int W = kPanel;
   const int64_t pstride = naux_p * W;
-  const double *src[4] = {Pcv + (int64_t)(c.i * ntv + c.A) * pstride,
-                          Pcv + (int64_t)(c.j * ntv + c.B) * pstride,
-                          Pcv + (int64_t)(c.j * ntv + c.A) * pstride,
-                          Pcv + (int64_t)(c.i * ntv + c.B) * pstride};
+  const double *src[4] = {PL + (int64_t)(c.i * ntv + c.A) * pstride,
+                          PR + (int64_t)(c.j * ntv + c.B) * pstride,
+                          PR + (int64_t)(c.j * ntv + c.A) * pstride,
+                          PL + (int64_t)(c.i * ntv + c.B) * pstride};
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll

@@ -75,6 +75,8 @@ hipError_t launch_ccav_fp64(const Plan &pl, const Inputs &in, void *ws, hipStrea
 hipError_t launch_zero(double *p, int n, hipStream_t st);
 // ---- int8 slice path (split_kernels.hip) ----
 hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
+hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
+                           hipStream_t st);
 // ---- adjoint (fp64_bwd.hip) ----
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st);

@@ -285,7 +285,9 @@ __global__ __launch_bounds__(256) void ccvv_i8_kernel(const int8_t *__restrict__
                                                       const double *__restrict__ eps_v,
                                                       CcvvI8Args a, double *slots, double *acc) {
   __shared__ __attribute__((aligned(16))) int8_t lds[kI8Lds];
-  const CcvvWork c = decode_ccvv(blockIdx.x, a.nc, a.ntv, a.n0, a.n1, a.n2);
+  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.nc * (a.nc + 1) / 2, a.ntv);
+  if (pt.item < 0) return;
+  const CcvvWork c = ccvv_work_from(pt, a.nc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   double x[16], y[16];
@@ -309,7 +311,7 @@ __global__ __launch_bounds__(256) void ccvv_i8_kernel(const int8_t *__restrict__
   }
   const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
   const double t = block_sum(part, reinterpret_cast<double *>(lds)) * w;
-  emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
+  emit_partial(t, slots, a.slot_base + pt.item, acc, a.atomic_mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,8 +323,7 @@ __global__ __launch_bounds__(256) void ccvv_i8_kernel(const int8_t *__restrict__
 struct CavvXArgs {
   int na, nv, ntv;
   int64_t nqc;
-  int m0;
-  int64_t ntp;   // tile pairs A <= B per (m, u)
+  int m0, mb;
 };
 
 __global__ __launch_bounds__(256) void cavv_i8_x_kernel(const int8_t *__restrict__ S8c,
@@ -331,11 +332,10 @@ __global__ __launch_bounds__(256) void cavv_i8_x_kernel(const int8_t *__restrict
                                                         const double *__restrict__ siga,
                                                         CavvXArgs a, double *__restrict__ Xb) {
   __shared__ __attribute__((aligned(16))) int8_t lds[kI8Lds];
-  const int64_t w = blockIdx.x;
-  const int64_t tp = w % a.ntp, mu = w / a.ntp;
-  const int u = (int)(mu % a.na), ml = (int)(mu / a.na);
-  int A, B;
-  decode_pair_le(tp, a.ntv, A, B);
+  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.mb * a.na, a.ntv);
+  if (pt.item < 0) return;
+  const int u = (int)(pt.p % a.na), ml = (int)(pt.p / a.na);
+  const int A = pt.A, B = pt.B;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   double x[16], y[16];
@@ -450,8 +450,8 @@ static hipError_t slice_one(const double *B, int64_t nrow, const Plan &pl, doubl
 }
 
 template <int NA>
-static hipError_t cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
-                           hipStream_t st) {
+static hipError_t cavv_epi_na(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
+                              hipStream_t st) {
   CavvEpiArgs a;
   a.na = (int)pl.na;
   a.nv = (int)pl.nv;
@@ -468,6 +468,21 @@ static hipError_t cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, i
                      ws_d(ws, pl.off_slots), ws_d(ws, pl.off_acc) + 1);
   timer_end(st);
   return hipGetLastError();
+}
+
+hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
+                           hipStream_t st) {
+  switch (pl.na) {
+    case 1: return cavv_epi_na<1>(pl, in, ws, m0, mb, st);
+    case 2: return cavv_epi_na<2>(pl, in, ws, m0, mb, st);
+    case 3: return cavv_epi_na<3>(pl, in, ws, m0, mb, st);
+    case 4: return cavv_epi_na<4>(pl, in, ws, m0, mb, st);
+    case 5: return cavv_epi_na<5>(pl, in, ws, m0, mb, st);
+    case 6: return cavv_epi_na<6>(pl, in, ws, m0, mb, st);
+    case 7: return cavv_epi_na<7>(pl, in, ws, m0, mb, st);
+    case 8: return cavv_epi_na<8>(pl, in, ws, m0, mb, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st) {
@@ -500,14 +515,13 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
     timer_begin("ccvv_i8", st);
-    hipLaunchKernelGGL(ccvv_i8_kernel, dim3((unsigned)pl.n_ccvv), dim3(256), 0, st,
+    hipLaunchKernelGGL(ccvv_i8_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(256), 0, st,
                        ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
                        in.eps_c, in.eps_v, a, slots, acc + 0);
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (cavv) {
-    const int64_t ntp = pl.ntv * (pl.ntv + 1) / 2;
     for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
       const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
       CavvXArgs xa;
@@ -516,24 +530,14 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
       xa.ntv = (int)pl.ntv;
       xa.nqc = pl.nqc;
       xa.m0 = (int)m0;
-      xa.ntp = ntp;
+      xa.mb = mb;
       timer_begin("cavv_i8_x", st);
-      hipLaunchKernelGGL(cavv_i8_x_kernel, dim3((unsigned)(mb * pl.na * ntp)), dim3(256), 0, st,
+      hipLaunchKernelGGL(cavv_i8_x_kernel, dim3((unsigned)pairtile_grid((int64_t)mb * pl.na, pl.ntv)), dim3(256), 0, st,
                          ws_b(ws, pl.off_s8c), ws_b(ws, pl.off_s8a), ws_d(ws, pl.off_sigc),
                          ws_d(ws, pl.off_siga), xa, ws_d(ws, pl.off_xb));
       timer_end(st);
       if ((e = hipGetLastError()) != hipSuccess) return e;
-      switch (pl.na) {
-        case 1: e = cavv_epi<1>(pl, in, ws, (int)m0, mb, st); break;
-        case 2: e = cavv_epi<2>(pl, in, ws, (int)m0, mb, st); break;
-        case 3: e = cavv_epi<3>(pl, in, ws, (int)m0, mb, st); break;
-        case 4: e = cavv_epi<4>(pl, in, ws, (int)m0, mb, st); break;
-        case 5: e = cavv_epi<5>(pl, in, ws, (int)m0, mb, st); break;
-        case 6: e = cavv_epi<6>(pl, in, ws, (int)m0, mb, st); break;
-        case 7: e = cavv_epi<7>(pl, in, ws, (int)m0, mb, st); break;
-        case 8: e = cavv_epi<8>(pl, in, ws, (int)m0, mb, st); break;
-        default: e = hipErrorInvalidValue;
-      }
+      e = launch_cavv_epi(pl, in, ws, (int)m0, mb, st);
       if (e != hipSuccess) return e;
     }
   }
