@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--grad", action="store_true",
+                    help="time energy + gradient (dsrg_df_energy_backward) instead of energy")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
                          "hardware byte counters can be scaled")
@@ -134,9 +136,22 @@ def main():
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     E = torch.empty(3, dtype=torch.float64, device=dev)
 
+    gE = torch.tensor([1.0, 1.0, 1.0], dtype=torch.float64, device=dev)
+    if args.grad:
+        nbytes = binding.workspace_size(p.nc, p.na, p.nv, p.naux, precision=args.precision,
+                                        terms=list(terms), with_grad=True)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        gout = {}
+
     def step(timing):
-        binding.energy(*t_in, p.s, precision=args.precision, terms=list(terms), workspace=ws,
-                       out=E, timing=timing)
+        if args.grad:
+            g = binding.energy_backward(*t_in, p.s, gE, precision=args.precision,
+                                        terms=list(terms), workspace=ws, timing=timing)
+            E.copy_(g["E"])
+            gout["g"] = g
+        else:
+            binding.energy(*t_in, p.s, precision=args.precision, terms=list(terms),
+                           workspace=ws, out=E, timing=timing)
 
     for _ in range(args.warmup):
         step(False)
@@ -158,8 +173,18 @@ def main():
     avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
 
     F, Fparts = alg_flops(p.nc, p.na, p.nv, p.naux, terms)
+    if args.grad:
+        # recompute (1x) plus the two adjoint contractions (2x) of every term
+        F, Fparts = 3.0 * F, {k: 3.0 * v for k, v in Fparts.items()}
     value = F / (ms_per_step * 1e-3) / 1e12
-    if args.precision == "fp64":
+    if args.grad:
+        # dominant kernel: the adjoint GEMM (2/3 of the work); report all its launches
+        gm = per_kernel.get("gemm_adj_fp64", []) + per_kernel.get("gemm_adj_tb_fp64", [])
+        dom, unit, mult = "gemm_adj_fp64", "TFLOP/s", 1.0
+        avg[dom] = float(np.sum(gm)) / args.steps if gm else None
+        Fparts = dict(Fparts)
+        Fparts["ccvv"] = 2.0 / 3.0 * F
+    elif args.precision == "fp64":
         dom, unit, mult = "ccvv_fp64", "TFLOP/s", 1.0
     else:
         # int8 slices: 15 exact int8 products per algorithmic multiply-add
@@ -188,7 +213,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "i8 slices (int32 exact) + f64", "data": "synthetic",
         "config": {"workload": f"{args.config}: nc={p.nc} na={p.na} nv={p.nv} naux={p.naux} "
-                               f"s={p.s}, energy of " + "+".join(t.upper() for t in terms),
+                               f"s={p.s}, " + ("energy+gradient" if args.grad else "energy")
+                               + " of " + "+".join(t.upper() for t in terms),
                    "precision": args.precision, "parallelism": "single-gpu"},
         "kernel_ms": avg,
         "E_terms": [float(x) for x in Eg],

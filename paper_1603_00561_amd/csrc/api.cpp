@@ -108,7 +108,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   const bool split = precision == DSRG_SPLIT_OZAKI;
   const bool has_cavv = (term_bits & DSRG_TERM_CAVV) && pl.na > 0;
   const bool has_ccav = (term_bits & DSRG_TERM_CCAV) && pl.na > 0;
-  pl.nqc = ceil_div(pl.naux, 32);
+  pl.nqc = round_up(ceil_div(pl.naux, 32), 2);   // even: chunks are taken in pairs
   // forward CAVV (both precisions) goes through batches of (me|uf) integrals
   // of at most 512 MB
   const bool xbatch = has_cavv && !pl.with_grad;

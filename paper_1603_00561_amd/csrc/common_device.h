@@ -104,6 +104,22 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return t;
 }
 
+// Same for NW waves (blockDim = 64 NW); `red` is a __shared__ double[NW].
+template <int NW>
+__device__ __forceinline__ double block_sum_n(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += red[k];
+  }
+  return t;
+}
+
 // Deliver one workgroup's partial energy: its own slot (deterministic
 // reduction) or an FP64 atomic into the term accumulator.
 __device__ __forceinline__ void emit_partial(double t, double *slots, int64_t slot,

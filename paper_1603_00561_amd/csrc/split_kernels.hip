@@ -128,30 +128,37 @@ __global__ __launch_bounds__(256) void slice_pack_kernel(const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Pair tile on int8 slices: x = L0^T R0 and (optionally) y = L1^T R1 over
-// all auxiliary chunks, for 64 x 64 tiles; wave (wr, wc) owns the 32 x 32
-// quadrant. src[0..3] = slice panels L0, R0, L1, R1. Level accumulators
-// I_L (L = 0..4) per 32 x 32 block; one barrier per chunk, chunks
-// double-buffered in LDS.
+// Pair tile on int8 slices, eight waves (two per SIMD) per workgroup.
+// x = L0^T R0 and y = L1^T R1 over all auxiliary chunks for 64 x 64 tiles.
+// Waves 0-3 (group 0) own the four 32 x 32 quadrants of x, waves 4-7 (group
+// 1) those of y; each wave keeps its own five level accumulators. When only
+// x is needed, group 1 takes every second auxiliary chunk of x instead and
+// its exact int32 partial sums are added to group 0's at the end. A stage is
+// four 10 KB panel-chunks (L0, R0, L1, R1 of one chunk, or L0, R0 of two
+// chunks), double-buffered in LDS with one barrier per stage.
 // ---------------------------------------------------------------------------
-template <int NP>
+constexpr int kI8Threads = 512;
+constexpr int kI8Lds = 2 * 4 * kSlicePanelChunk;   // bytes: two stages of four panel-chunks
+
 struct I8Stage {
-  static constexpr int N16 = NP * kSlicePanelChunk / 16;            // 16-byte pieces
-  static constexpr int PER = N16 / kThreads;
-  static_assert(N16 % kThreads == 0, "stage must split evenly");
+  static constexpr int PER = 4 * (kSlicePanelChunk / 16) / kI8Threads;   // 16-byte pieces
+  static_assert(4 * (kSlicePanelChunk / 16) % kI8Threads == 0, "stage must split evenly");
   i4v r[PER];
-  __device__ __forceinline__ void load(const int8_t *const *src, int64_t qc) {
+  __device__ __forceinline__ void load(const int8_t *s0, const int8_t *s1, const int8_t *s2,
+                                       const int8_t *s3) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = threadIdx.x + k * kThreads;
+      const int idx = threadIdx.x + k * kI8Threads;
       const int p = idx / (kSlicePanelChunk / 16), off = idx % (kSlicePanelChunk / 16);
-      r[k] = reinterpret_cast<const i4v *>(src[p] + qc * (int64_t)kSlicePanelChunk)[off];
+      // select, not index: keeps the panel pointers in registers
+      const int8_t *base = (p == 0) ? s0 : (p == 1) ? s1 : (p == 2) ? s2 : s3;
+      r[k] = reinterpret_cast<const i4v *>(base)[off];
     }
   }
   __device__ __forceinline__ void store(int8_t *lds) const {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = threadIdx.x + k * kThreads;
+      const int idx = threadIdx.x + k * kI8Threads;
       reinterpret_cast<i4v *>(lds)[idx] = r[k];
     }
   }
@@ -162,45 +169,49 @@ __device__ __forceinline__ i4v frag_i8(const int8_t *panel, int s, int row, int 
   return *reinterpret_cast<const i4v *>(panel + off);
 }
 
-// 15 products of one 32 x 32 block into 5 level accumulators.
-__device__ __forceinline__ void level_products(const int8_t *Lp, const int8_t *Rp, int rowA,
-                                               int rowB, int h, i16v (&acc)[kSlices]) {
-  i4v a[kSlices], b[kSlices];
+// 15 products of one 32 x 32 block into 5 level accumulators, ordered so that
+// consecutive products go to different accumulators.
+__device__ __forceinline__ void level_products(const i4v (&a)[kSlices], const i4v (&b)[kSlices],
+                                               i16v (&acc)[kSlices]) {
 #pragma unroll
-  for (int s = 0; s < kSlices; ++s) {
-    a[s] = frag_i8(Lp, s, rowA, h);
-    b[s] = frag_i8(Rp, s, rowB, h);
-  }
+  for (int k = 0; k < kSlices; ++k)
 #pragma unroll
-  for (int L = 0; L < kSlices; ++L)
-#pragma unroll
-    for (int k = 0; k <= L; ++k) acc[L] = mfma_i8(a[k], b[L - k], acc[L]);
+    for (int L = k; L < kSlices; ++L) acc[L] = mfma_i8(a[k], b[L - k], acc[L]);
 }
 
-constexpr int kI8Lds = 2 * 4 * kSlicePanelChunk;   // bytes: two stages of four panels
-
 template <bool NEED_Y>
-__device__ __forceinline__ void i8_pair_tiles(const int8_t *const *src, int64_t nqc, int8_t *lds,
-                                              i16v (&ix)[kSlices], i16v (&iy)[kSlices],
-                                              int wr, int wc, int lane) {
-  constexpr int NP = NEED_Y ? 4 : 2;
-  constexpr int BUF = NP * kSlicePanelChunk;
+__device__ __forceinline__ void i8_tiles(const int8_t *const *P, int64_t nqc, int8_t *lds,
+                                         i16v (&acc)[kSlices], int g, int wr, int wc, int lane) {
+  constexpr int64_t CH = kSlicePanelChunk;
+  constexpr int BUF = 4 * kSlicePanelChunk;
+  constexpr int STEP = NEED_Y ? 1 : 2;
+  const int64_t nst = nqc / STEP;   // nqc is even
   const int row = lane & 31, h = lane >> 5;
-  I8Stage<NP> st;
-  st.load(src, 0);
+  I8Stage st;
+  auto fetch = [&](int64_t s) {
+    const int64_t c0 = s * STEP;
+    if constexpr (NEED_Y)
+      st.load(P[0] + c0 * CH, P[1] + c0 * CH, P[2] + c0 * CH, P[3] + c0 * CH);
+    else
+      st.load(P[0] + c0 * CH, P[1] + c0 * CH, P[0] + (c0 + 1) * CH, P[1] + (c0 + 1) * CH);
+  };
+  fetch(0);
   st.store(lds);
-  if (nqc > 1) st.load(src, 1);
+  if (nst > 1) fetch(1);
   __syncthreads();
   int b = 0;
-  for (int64_t qc = 0; qc < nqc; ++qc) {
-    const int8_t *L = lds + b * BUF;
-    level_products(L, L + kSlicePanelChunk, 32 * wr + row, 32 * wc + row, h, ix);
-    if constexpr (NEED_Y)
-      level_products(L + 2 * kSlicePanelChunk, L + 3 * kSlicePanelChunk, 32 * wr + row,
-                     32 * wc + row, h, iy);
-    if (qc + 1 < nqc) {
+  for (int64_t s = 0; s < nst; ++s) {
+    const int8_t *L = lds + b * BUF + 2 * g * CH;
+    i4v fa[kSlices], fb[kSlices];
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) {
+      fa[k] = frag_i8(L, k, 32 * wr + row, h);
+      fb[k] = frag_i8(L + CH, k, 32 * wc + row, h);
+    }
+    level_products(fa, fb, acc);
+    if (s + 1 < nst) {
       st.store(lds + (b ^ 1) * BUF);
-      if (qc + 2 < nqc) st.load(src, qc + 2);
+      if (s + 2 < nst) fetch(s + 2);
     }
     __syncthreads();
     b ^= 1;
@@ -221,48 +232,72 @@ __device__ __forceinline__ int i8_row(int wr, int lane, int r) {
 }
 __device__ __forceinline__ int i8_col(int wc, int lane) { return 32 * wc + (lane & 31); }
 
-// x, y (FP64) of one CCVV-type work item: classes as decode_ccvv. For class 1
-// y = x^T through LDS; for classes 2, 3 y = x. Ends on a barrier.
+// One pair-tile work item (classes as decode_ccvv) on slices. On return the
+// group-0 waves hold x and y (FP64) of their quadrant (class 1: y = x^T,
+// classes 2, 3: y = x); for class 0, T = lds viewed as double[64][65] still
+// holds y[row][col] (it is not written after the last barrier).
 __device__ __forceinline__ void i8_pair_compute(const int8_t *S8L, const int8_t *S8R,
                                                 const double *sigL, const double *sigR,
                                                 int64_t nqc, int ntv, int pi, int pj, int A,
                                                 int B, int cls, int8_t *lds, double (&x)[16],
-                                                double (&y)[16], int wr, int wc, int lane) {
+                                                double (&y)[16], int g, int wr, int wc,
+                                                int lane) {
   const int64_t ps = nqc * (int64_t)kSlicePanelChunk;
-  const int8_t *src[4] = {S8L + (int64_t)(pi * ntv + A) * ps, S8R + (int64_t)(pj * ntv + B) * ps,
-                          S8R + (int64_t)(pj * ntv + A) * ps, S8L + (int64_t)(pi * ntv + B) * ps};
-  i16v ix[kSlices], iy[kSlices];
+  const int8_t *P[4] = {S8L + (int64_t)(pi * ntv + A) * ps, S8R + (int64_t)(pj * ntv + B) * ps,
+                        S8R + (int64_t)(pj * ntv + A) * ps, S8L + (int64_t)(pi * ntv + B) * ps};
+  i16v acc[kSlices];
 #pragma unroll
-  for (int L = 0; L < kSlices; ++L) {
-    ix[L] = i16v{};
-    iy[L] = i16v{};
-  }
+  for (int L = 0; L < kSlices; ++L) acc[L] = i16v{};
   if (cls == 0)
-    i8_pair_tiles<true>(src, nqc, lds, ix, iy, wr, wc, lane);
+    i8_tiles<true>(P, nqc, lds, acc, g, wr, wc, lane);
   else
-    i8_pair_tiles<false>(src, nqc, lds, ix, iy, wr, wc, lane);
+    i8_tiles<false>(P, nqc, lds, acc, g, wr, wc, lane);
+  const int wq = 2 * wr + wc;
+  // group 1 holds the odd-chunk half of x when only x is needed: add it in
+  int *Ti = reinterpret_cast<int *>(lds);   // [4][5][16][64] ints = 80 KB
+  if (cls != 0 && g == 1) {
+#pragma unroll
+    for (int L = 0; L < kSlices; ++L)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Ti[((wq * kSlices + L) * 16 + r) * 64 + lane] = acc[L][r];
+  }
+  __syncthreads();
+  if (cls != 0 && g == 0) {
+#pragma unroll
+    for (int L = 0; L < kSlices; ++L)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[L][r] += Ti[((wq * kSlices + L) * 16 + r) * 64 + lane];
+  }
+  __syncthreads();
   const int cb = i8_col(wc, lane);
-  const double sB0 = sigR[(int64_t)pj * ntv * kPanel + B * kPanel + cb];
-  const double sB1 = sigL[(int64_t)pi * ntv * kPanel + B * kPanel + cb];
+  double (*T)[kPanel + 1] = reinterpret_cast<double (*)[kPanel + 1]>(lds);
+  if (g == 0) {
+    const double sB = sigR[(int64_t)pj * ntv * kPanel + B * kPanel + cb];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int ra = i8_row(wr, lane, r);
-    x[r] = sigL[(int64_t)pi * ntv * kPanel + A * kPanel + ra] * sB0 * level_value(ix, r);
-    if (cls == 0)
-      y[r] = sigR[(int64_t)pj * ntv * kPanel + A * kPanel + ra] * sB1 * level_value(iy, r);
+    for (int r = 0; r < 16; ++r)
+      x[r] = sigL[(int64_t)pi * ntv * kPanel + A * kPanel + i8_row(wr, lane, r)] * sB *
+             level_value(acc, r);
+    if (cls == 1) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) T[i8_row(wr, lane, r)][cb] = x[r];
+    }
+  } else if (cls == 0) {
+    const double sB = sigL[(int64_t)pi * ntv * kPanel + B * kPanel + cb];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int ra = i8_row(wr, lane, r);
+      T[ra][cb] = sigR[(int64_t)pj * ntv * kPanel + A * kPanel + ra] * sB * level_value(acc, r);
+    }
   }
-  if (cls == 1) {
-    double (*T)[kPanel + 1] = reinterpret_cast<double (*)[kPanel + 1]>(lds);
+  __syncthreads();
+  if (g == 0) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) T[i8_row(wr, lane, r)][cb] = x[r];
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 16; ++r) y[r] = T[cb][i8_row(wr, lane, r)];
-    __syncthreads();
-  } else if (cls != 0) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) y[r] = x[r];
+    for (int r = 0; r < 16; ++r) {
+      const int ra = i8_row(wr, lane, r);
+      y[r] = (cls == 0) ? T[ra][cb] : (cls == 1) ? T[cb][ra] : x[r];
+    }
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -273,12 +308,11 @@ struct CcvvI8Args {
   int nc, nv, ntv;
   int64_t nqc;
   double s;
-  int64_t n0, n1, n2;
   int64_t slot_base;
   int atomic_mode;
 };
 
-__global__ __launch_bounds__(256) void ccvv_i8_kernel(const int8_t *__restrict__ S8,
+__global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__ S8,
                                                       const double *__restrict__ sig,
                                                       const double *__restrict__ diag,
                                                       const double *__restrict__ eps_c,
@@ -289,28 +323,29 @@ __global__ __launch_bounds__(256) void ccvv_i8_kernel(const int8_t *__restrict__
   if (pt.item < 0) return;
   const CcvvWork c = ccvv_work_from(pt, a.nc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int g = wave >> 2, wr = (wave >> 1) & 1, wc = wave & 1;
   double x[16], y[16];
-  i8_pair_compute(S8, S8, sig, sig, a.nqc, a.ntv, c.i, c.j, c.A, c.B, c.cls, lds, x, y, wr, wc,
-                  lane);
-  const int cb = i8_col(wc, lane);
-  const int bcol = c.B * kPanel + cb;
-  const double eb = bcol < a.nv ? eps_v[bcol] : 0.0;
-  const double eij = eps_c[c.i] + eps_c[c.j];
+  i8_pair_compute(S8, S8, sig, sig, a.nqc, a.ntv, c.i, c.j, c.A, c.B, c.cls, lds, x, y, g, wr,
+                  wc, lane);
   double part = 0.0;
-  if (bcol < a.nv) {
+  if (g == 0) {
+    const int bcol = c.B * kPanel + i8_col(wc, lane);
+    const double eb = bcol < a.nv ? eps_v[bcol] : 0.0;
+    const double eij = eps_c[c.i] + eps_c[c.j];
+    if (bcol < a.nv) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int arow = c.A * kPanel + i8_row(wr, lane, r);
-      if (arow >= a.nv) continue;
-      double xv = x[r], yv = y[r];
-      if (c.cls == 3 && arow == bcol) xv = yv = diag[(int64_t)c.i * a.ntv * kPanel + arow];
-      const double R = reg_R(eij - (eps_v[arow] + eb), a.s);
-      part += R * (xv * xv - xv * yv + yv * yv);
+      for (int r = 0; r < 16; ++r) {
+        const int arow = c.A * kPanel + i8_row(wr, lane, r);
+        if (arow >= a.nv) continue;
+        double xv = x[r], yv = y[r];
+        if (c.cls == 3 && arow == bcol) xv = yv = diag[(int64_t)c.i * a.ntv * kPanel + arow];
+        const double R = reg_R(eij - (eps_v[arow] + eb), a.s);
+        part += R * (xv * xv - xv * yv + yv * yv);
+      }
     }
   }
   const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
-  const double t = block_sum(part, reinterpret_cast<double *>(lds)) * w;
+  const double t = block_sum_n<8>(part, reinterpret_cast<double *>(lds)) * w;
   emit_partial(t, slots, a.slot_base + pt.item, acc, a.atomic_mode);
 }
 
@@ -326,7 +361,7 @@ struct CavvXArgs {
   int m0, mb;
 };
 
-__global__ __launch_bounds__(256) void cavv_i8_x_kernel(const int8_t *__restrict__ S8c,
+__global__ __launch_bounds__(512) void cavv_i8_x_kernel(const int8_t *__restrict__ S8c,
                                                         const int8_t *__restrict__ S8a,
                                                         const double *__restrict__ sigc,
                                                         const double *__restrict__ siga,
@@ -337,26 +372,23 @@ __global__ __launch_bounds__(256) void cavv_i8_x_kernel(const int8_t *__restrict
   const int u = (int)(pt.p % a.na), ml = (int)(pt.p / a.na);
   const int A = pt.A, B = pt.B;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int g = wave >> 2, wr = (wave >> 1) & 1, wc = wave & 1;
   double x[16], y[16];
   // pair (m, u): left panels from B_cv (m), right panels from B_av (u)
   i8_pair_compute(S8c, S8a, sigc, siga, a.nqc, a.ntv, a.m0 + ml, u, A, B, (A == B) ? 2 : 0,
-                  lds, x, y, wr, wc, lane);
+                  lds, x, y, g, wr, wc, lane);
   const int64_t ld = (int64_t)a.ntv * kPanel;
   double *X = Xb + ((int64_t)ml * a.na + u) * ld * ld;
-  const int cb = i8_col(wc, lane);
+  if (g == 0) {
+    const int cb = i8_col(wc, lane);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int ra = i8_row(wr, lane, r);
-    X[(int64_t)(A * kPanel + ra) * ld + B * kPanel + cb] = x[r];
+    for (int r = 0; r < 16; ++r)
+      X[(int64_t)(A * kPanel + i8_row(wr, lane, r)) * ld + B * kPanel + cb] = x[r];
   }
   if (A != B) {
-    // X^{mu}[f][e] for f in B, e in A equals y[e][f]: write y^T through LDS
-    double (*T)[kPanel + 1] = reinterpret_cast<double (*)[kPanel + 1]>(lds);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) T[i8_row(wr, lane, r)][cb] = y[r];
-    __syncthreads();
-    for (int k = threadIdx.x; k < kPanel * kPanel; k += kThreads) {
+    // X^{mu}[f][e] for f in B, e in A equals y[e][f], still in LDS as T[e][f]
+    const double (*T)[kPanel + 1] = reinterpret_cast<const double (*)[kPanel + 1]>(lds);
+    for (int k = threadIdx.x; k < kPanel * kPanel; k += kI8Threads) {
       const int fr = k / kPanel, ec = k % kPanel;
       X[(int64_t)(B * kPanel + fr) * ld + A * kPanel + ec] = T[ec][fr];
     }
@@ -508,14 +540,10 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
     a.ntv = (int)pl.ntv;
     a.nqc = pl.nqc;
     a.s = pl.s;
-    const int64_t npo = tri_off(pl.nc), ntpo = tri_off(pl.ntv);
-    a.n0 = npo * ntpo;
-    a.n1 = npo * pl.ntv;
-    a.n2 = pl.nc * ntpo;
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
     timer_begin("ccvv_i8", st);
-    hipLaunchKernelGGL(ccvv_i8_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(256), 0, st,
+    hipLaunchKernelGGL(ccvv_i8_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(kI8Threads), 0, st,
                        ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
                        in.eps_c, in.eps_v, a, slots, acc + 0);
     timer_end(st);
@@ -532,7 +560,7 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
       xa.m0 = (int)m0;
       xa.mb = mb;
       timer_begin("cavv_i8_x", st);
-      hipLaunchKernelGGL(cavv_i8_x_kernel, dim3((unsigned)pairtile_grid((int64_t)mb * pl.na, pl.ntv)), dim3(256), 0, st,
+      hipLaunchKernelGGL(cavv_i8_x_kernel, dim3((unsigned)pairtile_grid((int64_t)mb * pl.na, pl.ntv)), dim3(kI8Threads), 0, st,
                          ws_b(ws, pl.off_s8c), ws_b(ws, pl.off_s8a), ws_d(ws, pl.off_sigc),
                          ws_d(ws, pl.off_siga), xa, ws_d(ws, pl.off_xb));
       timer_end(st);
