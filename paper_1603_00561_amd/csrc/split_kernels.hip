@@ -179,6 +179,71 @@ __device__ __forceinline__ void level_products(const i4v (&a)[kSlices], const i4
     for (int L = k; L < kSlices; ++L) acc[L] = mfma_i8(a[k], b[L - k], acc[L]);
 }
 
+// Asynchronous variant: chunks are copied global -> LDS directly
+// (global_load_lds, 16 bytes per lane, no register staging) into a ring of
+// kI8Ring stage buffers, kI8Ring - 1 stages ahead of the compute.
+constexpr int kI8Ring = 4;
+constexpr int kI8LdsRing = kI8Ring * 4 * kSlicePanelChunk;   // 160 KB
+
+__device__ __forceinline__ void i8_issue_stage(const int8_t *s0, const int8_t *s1,
+                                               const int8_t *s2, const int8_t *s3,
+                                               int8_t *dst) {
+  constexpr int PIECES = kSlicePanelChunk / 16;   // per panel-chunk
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 4 * PIECES / kI8Threads; ++k) {
+    const int base = wave * 64 + k * kI8Threads;   // first piece of this wave (multiple of 64)
+    const int p = base / PIECES, off = base % PIECES + lane;
+    const int8_t *src = (p == 0) ? s0 : (p == 1) ? s1 : (p == 2) ? s2 : s3;
+    __builtin_amdgcn_global_load_lds(
+        reinterpret_cast<const void *>(src + off * 16),
+        (__attribute__((address_space(3))) void *)(dst + base * 16), 16, 0, 0);
+  }
+}
+
+template <bool NEED_Y>
+__device__ __forceinline__ void i8_tiles_async(const int8_t *const *P, int64_t nqc, int8_t *lds,
+                                               i16v (&acc)[kSlices], int g, int wr, int wc,
+                                               int lane) {
+  constexpr int64_t CH = kSlicePanelChunk;
+  constexpr int BUF = 4 * kSlicePanelChunk;
+  constexpr int STEP = NEED_Y ? 1 : 2;
+  const int64_t nst = nqc / STEP;   // nqc is even
+  const int row = lane & 31, h = lane >> 5;
+  auto issue = [&](int64_t s) {
+    const int64_t c0 = s * STEP;
+    int8_t *dst = lds + (int)(s % kI8Ring) * BUF;
+    if constexpr (NEED_Y)
+      i8_issue_stage(P[0] + c0 * CH, P[1] + c0 * CH, P[2] + c0 * CH, P[3] + c0 * CH, dst);
+    else
+      i8_issue_stage(P[0] + c0 * CH, P[1] + c0 * CH, P[0] + (c0 + 1) * CH, P[1] + (c0 + 1) * CH,
+                     dst);
+  };
+  for (int64_t s = 0; s < kI8Ring - 1 && s < nst; ++s) issue(s);
+  __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0): stage 0 (and the others issued) landed
+  __builtin_amdgcn_s_barrier();
+  for (int64_t s = 0; s < nst; ++s) {
+    const int8_t *L = lds + (int)(s % kI8Ring) * BUF + 2 * g * CH;
+    i4v fa[kSlices], fb[kSlices];
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) {
+      fa[k] = frag_i8(L, k, 32 * wr + row, h);
+      fb[k] = frag_i8(L + CH, k, 32 * wc + row, h);
+    }
+    level_products(fa, fb, acc);
+    // the ring slot of stage s + kI8Ring - 1 was last read in stage s - 1,
+    // which every wave finished before the barrier that ended it
+    if (s + kI8Ring - 1 < nst) {
+      issue(s + kI8Ring - 1);
+      // at most two later stages (10 copies per thread) may still be in flight
+      __builtin_amdgcn_s_waitcnt(0xF7A);   // vmcnt(10)
+    } else {
+      __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0)
+    }
+    __builtin_amdgcn_s_barrier();
+  }
+}
+
 template <bool NEED_Y>
 __device__ __forceinline__ void i8_tiles(const int8_t *const *P, int64_t nqc, int8_t *lds,
                                          i16v (&acc)[kSlices], int g, int wr, int wc, int lane) {
@@ -249,9 +314,9 @@ __device__ __forceinline__ void i8_pair_compute(const int8_t *S8L, const int8_t 
 #pragma unroll
   for (int L = 0; L < kSlices; ++L) acc[L] = i16v{};
   if (cls == 0)
-    i8_tiles<true>(P, nqc, lds, acc, g, wr, wc, lane);
+    i8_tiles_async<true>(P, nqc, lds, acc, g, wr, wc, lane);
   else
-    i8_tiles<false>(P, nqc, lds, acc, g, wr, wc, lane);
+    i8_tiles_async<false>(P, nqc, lds, acc, g, wr, wc, lane);
   const int wq = 2 * wr + wc;
   // group 1 holds the odd-chunk half of x when only x is needed: add it in
   int *Ti = reinterpret_cast<int *>(lds);   // [4][5][16][64] ints = 80 KB
@@ -318,7 +383,7 @@ __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__
                                                       const double *__restrict__ eps_c,
                                                       const double *__restrict__ eps_v,
                                                       CcvvI8Args a, double *slots, double *acc) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[kI8Lds];
+  __shared__ __attribute__((aligned(16))) int8_t lds[kI8LdsRing];
   const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.nc * (a.nc + 1) / 2, a.ntv);
   if (pt.item < 0) return;
   const CcvvWork c = ccvv_work_from(pt, a.nc);
@@ -366,7 +431,7 @@ __global__ __launch_bounds__(512) void cavv_i8_x_kernel(const int8_t *__restrict
                                                         const double *__restrict__ sigc,
                                                         const double *__restrict__ siga,
                                                         CavvXArgs a, double *__restrict__ Xb) {
-  __shared__ __attribute__((aligned(16))) int8_t lds[kI8Lds];
+  __shared__ __attribute__((aligned(16))) int8_t lds[kI8LdsRing];
   const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.mb * a.na, a.ntv);
   if (pt.item < 0) return;
   const int u = (int)(pt.p % a.na), ml = (int)(pt.p / a.na);
