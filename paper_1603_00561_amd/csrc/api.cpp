@@ -98,22 +98,27 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   pl.with_grad = with_grad != 0;
   pl.naux_p = round_up(pl.naux, kChunk);
   pl.ntv = ceil_div(pl.nv, kPanel);
+  pl.ntv_s = (precision == DSRG_SPLIT_OZAKI) ? round_up(pl.ntv, 2) : pl.ntv;
+  pl.xld = pl.ntv_s * kPanel;
   pl.cavv_tile = (pl.na <= 2) ? 64 : 32;
 
   const int64_t npo = tri_off(pl.nc), ntpo = tri_off(pl.ntv);
-  pl.n_ccvv = (term_bits & DSRG_TERM_CCVV)
-                  ? (npo * ntpo + npo * pl.ntv + pl.nc * ntpo + pl.nc * pl.ntv)
-                  : 0;
+  // one slot per (core pair, tile pair): 64-wide tiles in FP64, 128-wide on slices
+  const int64_t nt2 = pl.ntv_s / 2;
+  pl.n_ccvv = !(term_bits & DSRG_TERM_CCVV) ? 0
+              : (precision == DSRG_SPLIT_OZAKI)
+                  ? (pl.nc * (pl.nc + 1) / 2) * (nt2 * (nt2 + 1) / 2)
+                  : (npo * ntpo + npo * pl.ntv + pl.nc * ntpo + pl.nc * pl.ntv);
   const int64_t ntw = ceil_div(pl.nv, pl.cavv_tile);
   const bool split = precision == DSRG_SPLIT_OZAKI;
   const bool has_cavv = (term_bits & DSRG_TERM_CAVV) && pl.na > 0;
   const bool has_ccav = (term_bits & DSRG_TERM_CCAV) && pl.na > 0;
-  pl.nqc = round_up(ceil_div(pl.naux, 32), 2);   // even: chunks are taken in pairs
+  pl.nqc = ceil_div(pl.naux, 32);
   // forward CAVV (both precisions) goes through batches of (me|uf) integrals
   // of at most 512 MB
   const bool xbatch = has_cavv && !pl.with_grad;
   if (xbatch) {
-    const int64_t per_m = pl.na * (pl.ntv * kPanel) * (pl.ntv * kPanel) * 8;
+    const int64_t per_m = pl.na * pl.xld * pl.xld * 8;
     pl.cavv_mb = ((int64_t)512 << 20) / per_m;
     if (pl.cavv_mb < 1) pl.cavv_mb = 1;
     if (pl.cavv_mb > pl.nc) pl.cavv_mb = pl.nc;
@@ -122,7 +127,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   }
   pl.n_cavv = !has_cavv      ? 0
               : pl.with_grad ? pl.nc * (tri_off(ntw) + ntw)
-                             : pl.nc * pl.ntv * ceil_div(pl.nv, 256);
+                             : pl.nc * (ceil_div(pl.nv, 16) * (ceil_div(pl.nv, 16) + 1) / 2);
   pl.ccav_cols = round_up(pl.nc * pl.na, 16);
   // forward: one slot per (m <= n, 256 virtual orbitals); adjoint: per (m <= n, 64-tile)
   pl.n_ccav = has_ccav
@@ -156,9 +161,9 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       off;
   if (split) {
     const size_t chunk = 5 * kPanel * 32;   // bytes per (panel, 32 auxiliary indices)
-    const size_t colc = (size_t)(pl.nc * pl.ntv * kPanel), cola = (size_t)(pl.na * pl.ntv * kPanel);
+    const size_t colc = (size_t)(pl.nc * pl.ntv_s * kPanel), cola = (size_t)(pl.na * pl.ntv_s * kPanel);
     pl.off_s8c = off;
-    off = align256(off + chunk * (size_t)(pl.nc * pl.ntv * pl.nqc));
+    off = align256(off + chunk * (size_t)(pl.nc * pl.ntv_s * pl.nqc));
     pl.off_sigc = off;
     off = align256(off + sizeof(double) * colc);
     pl.off_diag = off;
@@ -167,16 +172,19 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
     off = align256(off + sizeof(double) * 2 * 32 * (colc > cola ? colc : cola));
     if (has_cavv) {
       pl.off_s8a = off;
-      off = align256(off + chunk * (size_t)(pl.na * pl.ntv * pl.nqc));
+      off = align256(off + chunk * (size_t)(pl.na * pl.ntv_s * pl.nqc));
       pl.off_siga = off;
       off = align256(off + sizeof(double) * cola);
     }
   }
   if (xbatch) {
     pl.off_xb = off;
-    off = align256(off + sizeof(double) * (size_t)(pl.cavv_mb * pl.na) *
-                             (size_t)(pl.ntv * kPanel) * (size_t)(pl.ntv * kPanel));
+    off = align256(off + sizeof(double) * (size_t)(pl.cavv_mb * pl.na) * (size_t)pl.xld *
+                             (size_t)pl.xld);
   }
+  pl.off_xs = off;
+  if (split && (term_bits & DSRG_TERM_CCVV))
+    off = align256(off + sizeof(double) * (size_t)(kSlicePersistWG * kSliceXsDoubles));
   pl.off_gs = pl.off_g2 = pl.off_g3 = off;
   if (pl.with_grad) {
     const size_t Np = (size_t)(pl.nc * pl.ntv * kPanel);

@@ -184,7 +184,7 @@ __device__ __forceinline__ PairTile decode_pairtile(int64_t bid, int64_t P, int 
   return r;
 }
 
-inline int64_t pairtile_grid(int64_t P, int64_t ntv) {
+__host__ __device__ inline int64_t pairtile_grid(int64_t P, int64_t ntv) {
   return 8 * ((P + 7) / 8) * (ntv * (ntv + 1) / 2);
 }
 

@@ -14,6 +14,10 @@ constexpr int kPanel = 64;
 constexpr int kChunk = 16;
 // Column width of a packed active-orbital panel (na padded up to this).
 constexpr int kActPanel = 16;
+// Persistent workgroups of the int8 CCVV kernel, each with an FP64 slot of
+// 512 lanes x 32 values for the first product of a two-product tile.
+constexpr int kSlicePersistWG = 256;
+constexpr int64_t kSliceXsDoubles = 512 * 32;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
@@ -23,6 +27,8 @@ struct Plan {
   int64_t nc, na, nv, naux;
   int64_t naux_p;   // naux rounded up to kChunk
   int64_t ntv;      // number of kPanel-wide virtual panels
+  int64_t ntv_s;    // panels of the int8 slices (ntv rounded up to even: 128-wide tiles)
+  int64_t xld;      // row length (doubles) of the CAVV integral batch
   double s;
   int precision;
   int terms;
@@ -41,6 +47,7 @@ struct Plan {
   int64_t nqc;                        // chunks of 32 auxiliary indices
   int64_t cavv_mb;                    // core orbitals per CAVV integral batch
   size_t off_s8c, off_s8a, off_sigc, off_siga, off_diag, off_xb, off_scr;
+  size_t off_xs;                      // per-workgroup x slots of the int8 CCVV kernel
   size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
   size_t off_slots;                   // per-workgroup partial energies
   size_t off_acc;                     // [4] atomic accumulators

@@ -128,158 +128,140 @@ __global__ __launch_bounds__(256) void slice_pack_kernel(const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Pair tile on int8 slices, eight waves (two per SIMD) per workgroup.
-// x = L0^T R0 and y = L1^T R1 over all auxiliary chunks for 64 x 64 tiles.
-// Waves 0-3 (group 0) own the four 32 x 32 quadrants of x, waves 4-7 (group
-// 1) those of y; each wave keeps its own five level accumulators. When only
-// x is needed, group 1 takes every second auxiliary chunk of x instead and
-// its exact int32 partial sums are added to group 0's at the end. A stage is
-// four 10 KB panel-chunks (L0, R0, L1, R1 of one chunk, or L0, R0 of two
-// chunks), double-buffered in LDS with one barrier per stage.
+// Int8 tile product, eight waves (two per SIMD) per workgroup.
+// K[a][b] = sum_Q L^Q_a R^Q_b for a 128 x 128 output tile: rows from two
+// 64-column slice panels (r0, r1), columns from two more (c0, c1). Wave w
+// owns rows 64 (w >> 2) .. +63 (two 32-row blocks q = 0, 1) and columns
+// 32 (w & 3) .. +31, with five int32 level accumulators per block (160
+// registers). A stage is one 32-index auxiliary chunk of the four panels
+// (4 x 10 KB); stages are copied global -> LDS directly (global_load_lds,
+// 16 bytes per lane) into a ring of four, three stages ahead of the matrix
+// cores.
 // ---------------------------------------------------------------------------
 constexpr int kI8Threads = 512;
-constexpr int kI8Lds = 2 * 4 * kSlicePanelChunk;   // bytes: two stages of four panel-chunks
-
-struct I8Stage {
-  static constexpr int PER = 4 * (kSlicePanelChunk / 16) / kI8Threads;   // 16-byte pieces
-  static_assert(4 * (kSlicePanelChunk / 16) % kI8Threads == 0, "stage must split evenly");
-  i4v r[PER];
-  __device__ __forceinline__ void load(const int8_t *s0, const int8_t *s1, const int8_t *s2,
-                                       const int8_t *s3) {
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int idx = threadIdx.x + k * kI8Threads;
-      const int p = idx / (kSlicePanelChunk / 16), off = idx % (kSlicePanelChunk / 16);
-      // select, not index: keeps the panel pointers in registers
-      const int8_t *base = (p == 0) ? s0 : (p == 1) ? s1 : (p == 2) ? s2 : s3;
-      r[k] = reinterpret_cast<const i4v *>(base)[off];
-    }
-  }
-  __device__ __forceinline__ void store(int8_t *lds) const {
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int idx = threadIdx.x + k * kI8Threads;
-      reinterpret_cast<i4v *>(lds)[idx] = r[k];
-    }
-  }
-};
+constexpr int kI8Tile = 128;
+constexpr int kI8Ring = 4;
+constexpr int kI8Stage = 4 * kSlicePanelChunk;       // 40 KB
+constexpr int kI8LdsRing = kI8Ring * kI8Stage;       // 160 KB
+constexpr int kI8Blocks = 2;                         // 32 x 32 blocks per wave
+constexpr int kI8Out = kI8Blocks * 16;               // outputs per lane
+static_assert(kI8Threads * kI8Out == kSliceXsDoubles, "x slot size");
+constexpr int kI8CopiesPerStage = 4 * (kSlicePanelChunk / 16) / kI8Threads;   // 5
 
 __device__ __forceinline__ i4v frag_i8(const int8_t *panel, int s, int row, int h) {
   const int off = (s * kPanel + row) * kQC + (((h ^ (row >> 3)) & 1) << 4);
   return *reinterpret_cast<const i4v *>(panel + off);
 }
 
-// 15 products of one 32 x 32 block into 5 level accumulators, ordered so that
-// consecutive products go to different accumulators.
-__device__ __forceinline__ void level_products(const i4v (&a)[kSlices], const i4v (&b)[kSlices],
-                                               i16v (&acc)[kSlices]) {
-#pragma unroll
-  for (int k = 0; k < kSlices; ++k)
-#pragma unroll
-    for (int L = k; L < kSlices; ++L) acc[L] = mfma_i8(a[k], b[L - k], acc[L]);
-}
-
-// Asynchronous variant: chunks are copied global -> LDS directly
-// (global_load_lds, 16 bytes per lane, no register staging) into a ring of
-// kI8Ring stage buffers, kI8Ring - 1 stages ahead of the compute.
-constexpr int kI8Ring = 4;
-constexpr int kI8LdsRing = kI8Ring * 4 * kSlicePanelChunk;   // 160 KB
-
+// Copy one stage (four panel-chunks, in order s0..s3) into the LDS ring slot
+// dst. Each wave moves 64 consecutive 16-byte pieces per instruction; a
+// panel-chunk is 640 pieces, so no wave's pieces straddle two panels, and
+// source base and LDS address are wave-uniform (scalar registers).
 __device__ __forceinline__ void i8_issue_stage(const int8_t *s0, const int8_t *s1,
                                                const int8_t *s2, const int8_t *s3,
                                                int8_t *dst) {
-  constexpr int PIECES = kSlicePanelChunk / 16;   // per panel-chunk
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int PIECES = kSlicePanelChunk / 16;
+  static_assert(PIECES % 64 == 0 && (4 * PIECES) % kI8Threads == 0, "stage split");
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int voff = (threadIdx.x & 63) * 16;
 #pragma unroll
-  for (int k = 0; k < 4 * PIECES / kI8Threads; ++k) {
-    const int base = wave * 64 + k * kI8Threads;   // first piece of this wave (multiple of 64)
-    const int p = base / PIECES, off = base % PIECES + lane;
-    const int8_t *src = (p == 0) ? s0 : (p == 1) ? s1 : (p == 2) ? s2 : s3;
+  for (int k = 0; k < kI8CopiesPerStage; ++k) {
+    const int base = wave * 64 + k * kI8Threads;
+    const int p = base / PIECES;
+    const int8_t *src = ((p == 0) ? s0 : (p == 1) ? s1 : (p == 2) ? s2 : s3) +
+                        (base % PIECES) * 16;
     __builtin_amdgcn_global_load_lds(
-        reinterpret_cast<const void *>(src + off * 16),
+        reinterpret_cast<const void *>(src + (uint32_t)voff),
         (__attribute__((address_space(3))) void *)(dst + base * 16), 16, 0, 0);
   }
 }
 
-template <bool NEED_Y>
-__device__ __forceinline__ void i8_tiles_async(const int8_t *const *P, int64_t nqc, int8_t *lds,
-                                               i16v (&acc)[kSlices], int g, int wr, int wc,
-                                               int lane) {
-  constexpr int64_t CH = kSlicePanelChunk;
-  constexpr int BUF = 4 * kSlicePanelChunk;
-  constexpr int STEP = NEED_Y ? 1 : 2;
-  const int64_t nst = nqc / STEP;   // nqc is even
-  const int row = lane & 31, h = lane >> 5;
-  auto issue = [&](int64_t s) {
-    const int64_t c0 = s * STEP;
-    int8_t *dst = lds + (int)(s % kI8Ring) * BUF;
-    if constexpr (NEED_Y)
-      i8_issue_stage(P[0] + c0 * CH, P[1] + c0 * CH, P[2] + c0 * CH, P[3] + c0 * CH, dst);
-    else
-      i8_issue_stage(P[0] + c0 * CH, P[1] + c0 * CH, P[0] + (c0 + 1) * CH, P[1] + (c0 + 1) * CH,
-                     dst);
-  };
-  for (int64_t s = 0; s < kI8Ring - 1 && s < nst; ++s) issue(s);
-  __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0): stage 0 (and the others issued) landed
+// Workgroup barrier that does not drain the vector-memory counter (the ring
+// waits for its copies explicitly); the empty asm keeps the compiler from
+// moving memory accesses across it.
+__device__ __forceinline__ void ring_barrier() {
+  asm volatile("" ::: "memory");
   __builtin_amdgcn_s_barrier();
-  for (int64_t s = 0; s < nst; ++s) {
-    const int8_t *L = lds + (int)(s % kI8Ring) * BUF + 2 * g * CH;
-    i4v fa[kSlices], fb[kSlices];
-#pragma unroll
-    for (int k = 0; k < kSlices; ++k) {
-      fa[k] = frag_i8(L, k, 32 * wr + row, h);
-      fb[k] = frag_i8(L + CH, k, 32 * wc + row, h);
-    }
-    level_products(fa, fb, acc);
-    // the ring slot of stage s + kI8Ring - 1 was last read in stage s - 1,
-    // which every wave finished before the barrier that ended it
-    if (s + kI8Ring - 1 < nst) {
-      issue(s + kI8Ring - 1);
-      // at most two later stages (10 copies per thread) may still be in flight
-      __builtin_amdgcn_s_waitcnt(0xF7A);   // vmcnt(10)
-    } else {
-      __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0)
-    }
-    __builtin_amdgcn_s_barrier();
-  }
+  asm volatile("" ::: "memory");
 }
 
-template <bool NEED_Y>
-__device__ __forceinline__ void i8_tiles(const int8_t *const *P, int64_t nqc, int8_t *lds,
-                                         i16v (&acc)[kSlices], int g, int wr, int wc, int lane) {
+// Ties a scalar value (a kernel argument) to this point: its scalar load
+// completes before the K-loop, so no scalar load is in flight there and the
+// loop's LDS waits can count outstanding reads instead of draining them.
+template <class T>
+__device__ __forceinline__ void scalar_here(const T &v) {
+  asm volatile("" ::"s"(v));
+}
+
+// s_waitcnt with only the vector-memory count (expcnt, lgkmcnt not waited)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Products of one stage are taken in five rounds: round r multiplies row
+// slice r with column slices 0 .. 4-r into the levels r .. 4, so two products
+// into one accumulator are at least four instructions apart, and after round
+// r the fragments of row slice r and column slice 4-r are dead: the next
+// stage's copies of exactly those are read into them at once. The LDS reads
+// of a stage thus overlap the matrix products of the previous one, which
+// needs the next stage in LDS one stage earlier than the products do.
+__device__ __forceinline__ void i8_tile_product(const int8_t *r0, const int8_t *r1,
+                                                const int8_t *c0, const int8_t *c1, int64_t nqc,
+                                                int8_t *lds, i16v (&acc)[kI8Blocks][kSlices],
+                                                int wr, int wc, int lane) {
   constexpr int64_t CH = kSlicePanelChunk;
-  constexpr int BUF = 4 * kSlicePanelChunk;
-  constexpr int STEP = NEED_Y ? 1 : 2;
-  const int64_t nst = nqc / STEP;   // nqc is even
   const int row = lane & 31, h = lane >> 5;
-  I8Stage st;
-  auto fetch = [&](int64_t s) {
-    const int64_t c0 = s * STEP;
-    if constexpr (NEED_Y)
-      st.load(P[0] + c0 * CH, P[1] + c0 * CH, P[2] + c0 * CH, P[3] + c0 * CH);
-    else
-      st.load(P[0] + c0 * CH, P[1] + c0 * CH, P[0] + (c0 + 1) * CH, P[1] + (c0 + 1) * CH);
-  };
-  fetch(0);
-  st.store(lds);
-  if (nst > 1) fetch(1);
-  __syncthreads();
-  int b = 0;
-  for (int64_t s = 0; s < nst; ++s) {
-    const int8_t *L = lds + b * BUF + 2 * g * CH;
-    i4v fa[kSlices], fb[kSlices];
+  const int cr = 32 * (wc & 1) + row;
 #pragma unroll
-    for (int k = 0; k < kSlices; ++k) {
-      fa[k] = frag_i8(L, k, 32 * wr + row, h);
-      fb[k] = frag_i8(L + CH, k, 32 * wc + row, h);
+  for (int q = 0; q < kI8Blocks; ++q)
+#pragma unroll
+    for (int L = 0; L < kSlices; ++L) acc[q][L] = i16v{};
+  auto issue = [&](int64_t s) {
+    i8_issue_stage(r0 + s * CH, r1 + s * CH, c0 + s * CH, c1 + s * CH,
+                   lds + (int)(s % kI8Ring) * kI8Stage);
+  };
+  // row panel of this wave, column panel, in ring slot b
+  auto lrow = [&](int64_t s) { return lds + (int)(s % kI8Ring) * kI8Stage + wr * CH; };
+  auto lcol = [&](int64_t s) { return lds + (int)(s % kI8Ring) * kI8Stage + (2 + (wc >> 1)) * CH; };
+  for (int64_t s = 0; s < kI8Ring - 1 && s < nqc; ++s) issue(s);
+  wait_vm<0>();
+  ring_barrier();
+  i4v fa[kI8Blocks][kSlices], fb[kSlices];
+#pragma unroll
+  for (int k = 0; k < kSlices; ++k) {
+    fb[k] = frag_i8(lcol(0), k, cr, h);
+#pragma unroll
+    for (int q = 0; q < kI8Blocks; ++q) fa[q][k] = frag_i8(lrow(0), k, 32 * q + row, h);
+  }
+  for (int64_t s = 0; s < nqc; ++s) {
+    // the slot of stage s + 3 held stage s - 1, whose fragments were read
+    // during stage s - 2 and consumed before the barrier that ended stage s - 1
+    const bool more = s + kI8Ring - 1 < nqc;
+    if (more) issue(s + kI8Ring - 1);
+    // fragments of stage s + 1 (a stale slot on the last stage: never used)
+    const int8_t *Lr = lrow(s + 1), *Lc = lcol(s + 1);
+#pragma unroll
+    for (int r = 0; r < kSlices; ++r) {
+#pragma unroll
+      for (int Lv = kSlices - 1; Lv >= r; --Lv)
+#pragma unroll
+        for (int q = 0; q < kI8Blocks; ++q)
+          acc[q][Lv] = mfma_i8(fa[q][r], fb[Lv - r], acc[q][Lv]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < kI8Blocks; ++q) fa[q][r] = frag_i8(Lr, r, 32 * q + row, h);
+      fb[kSlices - 1 - r] = frag_i8(Lc, kSlices - 1 - r, cr, h);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    level_products(fa, fb, acc);
-    if (s + 1 < nst) {
-      st.store(lds + (b ^ 1) * BUF);
-      if (s + 2 < nst) fetch(s + 2);
-    }
-    __syncthreads();
-    b ^= 1;
+    // stage s + 2 must have landed (its fragments are read during stage s + 1);
+    // stage s + 3 may still be in flight
+    if (more)
+      wait_vm<kI8CopiesPerStage>();
+    else
+      wait_vm<0>();
+    ring_barrier();
   }
 }
 
@@ -291,86 +273,109 @@ __device__ __forceinline__ double level_value(const i16v (&acc)[kSlices], int r)
   return v;
 }
 
-// Row / column of result register r of this lane inside the 64 x 64 tile.
-__device__ __forceinline__ int i8_row(int wr, int lane, int r) {
-  return 32 * wr + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+// Row / column inside the 128 x 128 tile of output r of block q of this lane.
+__device__ __forceinline__ int i8_row(int wr, int q, int lane, int r) {
+  return 64 * wr + 32 * q + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
-__device__ __forceinline__ int i8_col(int wc, int lane) { return 32 * wc + (lane & 31); }
+__device__ __forceinline__ int i8_col(int wc, int q, int lane) {
+  (void)q;
+  return 32 * wc + (lane & 31);
+}
 
-// One pair-tile work item (classes as decode_ccvv) on slices. On return the
-// group-0 waves hold x and y (FP64) of their quadrant (class 1: y = x^T,
-// classes 2, 3: y = x); for class 0, T = lds viewed as double[64][65] still
-// holds y[row][col] (it is not written after the last barrier).
-__device__ __forceinline__ void i8_pair_compute(const int8_t *S8L, const int8_t *S8R,
-                                                const double *sigL, const double *sigR,
-                                                int64_t nqc, int ntv, int pi, int pj, int A,
-                                                int B, int cls, int8_t *lds, double (&x)[16],
-                                                double (&y)[16], int g, int wr, int wc,
-                                                int lane) {
-  const int64_t ps = nqc * (int64_t)kSlicePanelChunk;
-  const int8_t *P[4] = {S8L + (int64_t)(pi * ntv + A) * ps, S8R + (int64_t)(pj * ntv + B) * ps,
-                        S8R + (int64_t)(pj * ntv + A) * ps, S8L + (int64_t)(pi * ntv + B) * ps};
-  i16v acc[kSlices];
+// FP64 values of block q: v[r] = sig_row[row] sig_col[col] K[row][col].
+__device__ __forceinline__ void i8_block_values(const i16v (&acc)[kSlices], const double *sig_row,
+                                                const double *sig_col, int wr, int wc, int q,
+                                                int lane, double (&v)[16]) {
+  const double sc = sig_col[i8_col(wc, q, lane)];
 #pragma unroll
-  for (int L = 0; L < kSlices; ++L) acc[L] = i16v{};
-  if (cls == 0)
-    i8_tiles_async<true>(P, nqc, lds, acc, g, wr, wc, lane);
-  else
-    i8_tiles_async<false>(P, nqc, lds, acc, g, wr, wc, lane);
-  const int wq = 2 * wr + wc;
-  // group 1 holds the odd-chunk half of x when only x is needed: add it in
-  int *Ti = reinterpret_cast<int *>(lds);   // [4][5][16][64] ints = 80 KB
-  if (cls != 0 && g == 1) {
-#pragma unroll
-    for (int L = 0; L < kSlices; ++L)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) Ti[((wq * kSlices + L) * 16 + r) * 64 + lane] = acc[L][r];
-  }
-  __syncthreads();
-  if (cls != 0 && g == 0) {
-#pragma unroll
-    for (int L = 0; L < kSlices; ++L)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[L][r] += Ti[((wq * kSlices + L) * 16 + r) * 64 + lane];
-  }
-  __syncthreads();
-  const int cb = i8_col(wc, lane);
-  double (*T)[kPanel + 1] = reinterpret_cast<double (*)[kPanel + 1]>(lds);
-  if (g == 0) {
-    const double sB = sigR[(int64_t)pj * ntv * kPanel + B * kPanel + cb];
-#pragma unroll
-    for (int r = 0; r < 16; ++r)
-      x[r] = sigL[(int64_t)pi * ntv * kPanel + A * kPanel + i8_row(wr, lane, r)] * sB *
-             level_value(acc, r);
-    if (cls == 1) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) T[i8_row(wr, lane, r)][cb] = x[r];
-    }
-  } else if (cls == 0) {
-    const double sB = sigL[(int64_t)pi * ntv * kPanel + B * kPanel + cb];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int ra = i8_row(wr, lane, r);
-      T[ra][cb] = sigR[(int64_t)pj * ntv * kPanel + A * kPanel + ra] * sB * level_value(acc, r);
+  for (int r = 0; r < 16; ++r)
+    v[r] = sig_row[i8_row(wr, q, lane, r)] * sc * level_value(acc, r);
+}
+
+// Slice panel t (64 columns) of orbital p; sigma of its first column.
+__device__ __forceinline__ const int8_t *slice_panel(const int8_t *S8, int64_t p, int64_t t,
+                                                     int64_t ntv_s, int64_t nqc) {
+  return S8 + (p * ntv_s + t) * nqc * (int64_t)kSlicePanelChunk;
+}
+
+// Blocked walk (kTileBlock x kTileBlock blocks) over the strictly ordered
+// tile pairs A < B of nt tiles.
+__device__ __forceinline__ void decode_tile_blocked_lt(int64_t t, int nt, int &A, int &B) {
+  const int nb = (nt + kTileBlock - 1) / kTileBlock;
+  for (int ba = 0; ba < nb; ++ba) {
+    const int na_ = (ba == nb - 1) ? nt - ba * kTileBlock : kTileBlock;
+    for (int bb = ba; bb < nb; ++bb) {
+      const int nb_ = (bb == nb - 1) ? nt - bb * kTileBlock : kTileBlock;
+      const int64_t size = (ba == bb) ? (int64_t)na_ * (na_ - 1) / 2 : (int64_t)na_ * nb_;
+      if (t < size) {
+        int a0, b0;
+        if (ba == bb) {
+          decode_pair_lt(t, na_, a0, b0);
+        } else {
+          a0 = (int)(t / nb_);
+          b0 = (int)(t % nb_);
+        }
+        A = ba * kTileBlock + a0;
+        B = bb * kTileBlock + b0;
+        return;
+      }
+      t -= size;
     }
   }
-  __syncthreads();
-  if (g == 0) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int ra = i8_row(wr, lane, r);
-      y[r] = (cls == 0) ? T[ra][cb] : (cls == 1) ? T[cb][ra] : x[r];
-    }
+  A = B = 0;   // not reached for t < nt (nt - 1) / 2
+}
+
+// Work list of the int8 CCVV kernel on XCD x (pairs p = x mod 8; pairs
+// 0 .. P0-1 are the i < j pairs in order, P0 + i the self pairs), item kk:
+// first every class-0 item (two products each) of its i < j pairs, then the
+// single-product items (class 1 of its i < j pairs, classes 2 and 3 of its
+// self pairs). The workgroups of one XCD take consecutive items, so each
+// round holds items of equal cost that share panels and stay in step along
+// the auxiliary index. slot = p T + (index of A <= B). Returns false past
+// the end of the list.
+__device__ __forceinline__ bool decode_ccvv_i8(int64_t kk, int x, int nc, int nt, CcvvWork &c,
+                                               int64_t &slot) {
+  const int64_t P0 = (int64_t)nc * (nc - 1) / 2;
+  const int64_t T0 = (int64_t)nt * (nt - 1) / 2, T = (int64_t)nt * (nt + 1) / 2;
+  const int64_t nlt = (P0 > x) ? (P0 - x + 7) / 8 : 0;
+  const int64_t first_eq = P0 + ((x - P0 % 8) + 8) % 8;   // first self pair on this XCD
+  const int64_t neq = (first_eq < P0 + nc) ? (P0 + nc - first_eq + 7) / 8 : 0;
+  int64_t p;
+  if (kk < nlt * T0) {
+    p = 8 * (kk / T0) + x;
+    decode_tile_blocked_lt(kk % T0, nt, c.A, c.B);
+    c.cls = 0;
+  } else if ((kk -= nlt * T0) < nlt * nt) {
+    p = 8 * (kk / nt) + x;
+    c.A = c.B = (int)(kk % nt);
+    c.cls = 1;
+  } else if ((kk -= nlt * nt) < neq * T) {
+    p = first_eq + 8 * (kk / T);
+    decode_tile_blocked(kk % T, nt, c.A, c.B);
+    c.cls = (c.A == c.B) ? 3 : 2;
+  } else {
+    return false;
   }
-  __syncthreads();
+  if (p < P0) {
+    decode_pair_lt(p, nc, c.i, c.j);
+  } else {
+    c.i = c.j = (int)(p - P0);
+  }
+  slot = p * T + (int64_t)c.A * nt - (int64_t)c.A * (c.A - 1) / 2 + (c.B - c.A);
+  return true;
 }
 
 // ---------------------------------------------------------------------------
-// CCVV on slices: same work list and epilogue as the FP64 kernel; the
-// self-pair diagonal (i = j, a = b) uses the FP64 sum of squares.
+// CCVV on slices. Work items are (core pair i <= j, 128-tile pair A <= B)
+// in the order of decode_ccvv_i8; classes 0: i<j, A<B (x and y = K^{ji}[A,B]),
+// 1: i<j, A=B (y = x^T), 2: i=j, A<B and 3: i=j, A=B (y = x). The grid is
+// persistent (kSlicePersistWG workgroups, a multiple of 8, each walking the
+// list of its XCD); a class-0 item parks x in its workgroup's FP64 slot xs
+// while y is formed. The self-pair diagonal (i = j, a = b) uses the FP64 sum
+// of squares.
 // ---------------------------------------------------------------------------
 struct CcvvI8Args {
-  int nc, nv, ntv;
+  int nc, nv, ntv_s;
   int64_t nqc;
   double s;
   int64_t slot_base;
@@ -382,49 +387,131 @@ __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__
                                                       const double *__restrict__ diag,
                                                       const double *__restrict__ eps_c,
                                                       const double *__restrict__ eps_v,
-                                                      CcvvI8Args a, double *slots, double *acc) {
+                                                      CcvvI8Args a, double *__restrict__ xs,
+                                                      double *slots, double *acc) {
   __shared__ __attribute__((aligned(16))) int8_t lds[kI8LdsRing];
-  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.nc * (a.nc + 1) / 2, a.ntv);
-  if (pt.item < 0) return;
-  const CcvvWork c = ccvv_work_from(pt, a.nc);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = wave >> 2, wr = (wave >> 1) & 1, wc = wave & 1;
-  double x[16], y[16];
-  i8_pair_compute(S8, S8, sig, sig, a.nqc, a.ntv, c.i, c.j, c.A, c.B, c.cls, lds, x, y, g, wr,
-                  wc, lane);
-  double part = 0.0;
-  if (g == 0) {
-    const int bcol = c.B * kPanel + i8_col(wc, lane);
-    const double eb = bcol < a.nv ? eps_v[bcol] : 0.0;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int nt = a.ntv_s / 2;   // 128-wide tiles
+  const int64_t ldv = (int64_t)a.ntv_s * kPanel;   // sigma / diagonal row length
+  double *xw = xs + (int64_t)blockIdx.x * kSliceXsDoubles + threadIdx.x;
+  const int x = blockIdx.x % 8;   // the XCD this workgroup runs on
+  scalar_here(sig);
+  scalar_here(diag);
+  scalar_here(eps_c);
+  scalar_here(eps_v);
+  scalar_here(slots);
+  scalar_here(acc);
+  scalar_here(a.s);
+  scalar_here(a.slot_base);
+  CcvvWork c;
+  int64_t slot;
+  for (int64_t kk = blockIdx.x / 8; decode_ccvv_i8(kk, x, a.nc, nt, c, slot);
+       kk += gridDim.x / 8) {
+    __syncthreads();   // the previous item's reduction is done with the LDS
+    const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
+    const double *sri = sig + c.i * ldv + c.A * kI8Tile, *scj = sig + c.j * ldv + c.B * kI8Tile;
+    const double *srj = sig + c.j * ldv + c.A * kI8Tile, *sci = sig + c.i * ldv + c.B * kI8Tile;
+    i16v ac[kI8Blocks][kSlices];
+    // pass 0: x = K^{ij}[A,B] (rows from i's A panels, columns from j's B
+    // panels); class 0 parks x and takes pass 1: y[a][b] = (ja|ib)
+    const int npass = (c.cls == 0) ? 2 : 1;
+    for (int pass = 0; pass < npass; ++pass) {
+      const int8_t *r0 = slice_panel(S8, pass ? c.j : c.i, 2 * c.A, a.ntv_s, a.nqc);
+      const int8_t *c0 = slice_panel(S8, pass ? c.i : c.j, 2 * c.B, a.ntv_s, a.nqc);
+      i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nqc, lds, ac, wr, wc, lane);
+      if (pass + 1 < npass) {
+#pragma unroll
+        for (int q = 0; q < kI8Blocks; ++q) {
+          double v[16];
+          i8_block_values(ac[q], sri, scj, wr, wc, q, lane, v);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) xw[(q * 16 + r) * kI8Threads] = v[r];
+        }
+      }
+    }
+    // FP64 values of the last product (class 0: y, else x); the level
+    // accumulators die here, before the exponentials of the epilogue
+    double v[kI8Out];
+#pragma unroll
+    for (int q = 0; q < kI8Blocks; ++q) {
+      double t[16];
+      if (c.cls == 0)
+        i8_block_values(ac[q], srj, sci, wr, wc, q, lane, t);
+      else
+        i8_block_values(ac[q], sri, scj, wr, wc, q, lane, t);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[q * 16 + r] = t[r];
+    }
+    double (*T)[kI8Tile + 1] = reinterpret_cast<double (*)[kI8Tile + 1]>(lds);
+    if (c.cls == 1) {
+      // y = x^T through LDS (the ring is free after the last barrier)
+#pragma unroll
+      for (int q = 0; q < kI8Blocks; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) T[i8_row(wr, q, lane, r)][i8_col(wc, q, lane)] = v[q * 16 + r];
+      __syncthreads();
+    }
+    double part = 0.0;
     const double eij = eps_c[c.i] + eps_c[c.j];
-    if (bcol < a.nv) {
+#pragma unroll
+    for (int q = 0; q < kI8Blocks; ++q) {
+      const int bcol = c.B * kI8Tile + i8_col(wc, q, lane);
+      if (bcol >= a.nv) continue;
+      const double eb = eps_v[bcol];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int arow = c.A * kPanel + i8_row(wr, lane, r);
+        const int arow = c.A * kI8Tile + i8_row(wr, q, lane, r);
         if (arow >= a.nv) continue;
-        double xv = x[r], yv = y[r];
-        if (c.cls == 3 && arow == bcol) xv = yv = diag[(int64_t)c.i * a.ntv * kPanel + arow];
+        double xv, yv;
+        if (c.cls == 0) {
+          xv = xw[(q * 16 + r) * kI8Threads];
+          yv = v[q * 16 + r];
+        } else if (c.cls == 1) {
+          xv = v[q * 16 + r];
+          yv = T[i8_col(wc, q, lane)][i8_row(wr, q, lane, r)];
+        } else {
+          xv = yv = v[q * 16 + r];
+          if (c.cls == 3 && arow == bcol) xv = yv = diag[c.i * ldv + arow];
+        }
         const double R = reg_R(eij - (eps_v[arow] + eb), a.s);
         part += R * (xv * xv - xv * yv + yv * yv);
       }
     }
+    if (c.cls == 1) __syncthreads();   // T is read before the reduction reuses the LDS
+    const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
+    const double t = block_sum_n<8>(part, reinterpret_cast<double *>(lds)) * w;
+    emit_partial(t, slots, a.slot_base + slot, acc, a.atomic_mode);
   }
-  const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
-  const double t = block_sum_n<8>(part, reinterpret_cast<double *>(lds)) * w;
-  emit_partial(t, slots, a.slot_base + pt.item, acc, a.atomic_mode);
 }
 
 // ---------------------------------------------------------------------------
-// CAVV on slices, step 1: for core orbitals m0 .. m0+mb-1, all active u and
-// virtual tile pairs A <= B, the FP64 integrals X^{mu}[e][f] = (me|uf) are
-// written to Xb[(m - m0)][u][e][f] (row length ntv*64): block [A,B] from x and
-// block [B,A] from y = X^{mu}[B,A]^T.
+// CAVV on slices, step 1: for core orbitals m0 .. m0+mb-1 and all active u,
+// the FP64 integrals X^{mu}[e][f] = (me|uf) = sum_Q B^Q_me B^Q_uf are written
+// to Xb[(m - m0)][u][e][f] (row length xld = 128 ntv_s / 2). One workgroup per
+// (pair (m, u), 128-tile pair (A, B)) over the full tile grid; pairs are dealt
+// round-robin over the XCDs and tiles walked in 4 x 4 blocks.
 // ---------------------------------------------------------------------------
 struct CavvXArgs {
-  int na, nv, ntv;
+  int na, ntv_s;
   int64_t nqc;
   int m0, mb;
 };
+
+__device__ __forceinline__ void decode_tile_full_blocked(int64_t t, int nt, int &A, int &B) {
+  const int nb = (nt + kTileBlock - 1) / kTileBlock;
+  const int64_t row = (int64_t)kTileBlock * nt;   // tiles in one band of kTileBlock rows
+  const int ba = (int)(t / row);
+  int64_t rest = t % row;
+  const int ha = (ba == nb - 1) ? nt - ba * kTileBlock : kTileBlock;   // band height
+  const int bb = (int)(rest / ((int64_t)ha * kTileBlock));
+  const int64_t in = rest % ((int64_t)ha * kTileBlock);
+  const int wb = (bb == nb - 1) ? nt - bb * kTileBlock : kTileBlock;  // block width
+  A = ba * kTileBlock + (int)(in / wb);
+  B = bb * kTileBlock + (int)(in % wb);
+}
+
+inline int64_t fulltile_grid(int64_t P, int64_t nt) { return 8 * ((P + 7) / 8) * nt * nt; }
 
 __global__ __launch_bounds__(512) void cavv_i8_x_kernel(const int8_t *__restrict__ S8c,
                                                         const int8_t *__restrict__ S8a,
@@ -432,46 +519,78 @@ __global__ __launch_bounds__(512) void cavv_i8_x_kernel(const int8_t *__restrict
                                                         const double *__restrict__ siga,
                                                         CavvXArgs a, double *__restrict__ Xb) {
   __shared__ __attribute__((aligned(16))) int8_t lds[kI8LdsRing];
-  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.mb * a.na, a.ntv);
-  if (pt.item < 0) return;
-  const int u = (int)(pt.p % a.na), ml = (int)(pt.p / a.na);
-  const int A = pt.A, B = pt.B;
+  const int nt = a.ntv_s / 2;
+  const int64_t T = (int64_t)nt * nt;
+  const int64_t xcd = blockIdx.x % 8, kk = blockIdx.x / 8;
+  const int64_t p = (kk / T) * 8 + xcd;
+  if (p >= (int64_t)a.mb * a.na) return;
+  int A, B;
+  decode_tile_full_blocked(kk % T, nt, A, B);
+  const int u = (int)(p % a.na), ml = (int)(p / a.na), m = a.m0 + ml;
+  scalar_here(sigc);
+  scalar_here(siga);
+  scalar_here(Xb);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = wave >> 2, wr = (wave >> 1) & 1, wc = wave & 1;
-  double x[16], y[16];
-  // pair (m, u): left panels from B_cv (m), right panels from B_av (u)
-  i8_pair_compute(S8c, S8a, sigc, siga, a.nqc, a.ntv, a.m0 + ml, u, A, B, (A == B) ? 2 : 0,
-                  lds, x, y, g, wr, wc, lane);
-  const int64_t ld = (int64_t)a.ntv * kPanel;
-  double *X = Xb + ((int64_t)ml * a.na + u) * ld * ld;
-  if (g == 0) {
-    const int cb = i8_col(wc, lane);
+  const int wr = wave >> 2, wc = wave & 3;
+  const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
+  const int8_t *r0 = slice_panel(S8c, m, 2 * A, a.ntv_s, a.nqc);
+  const int8_t *c0 = slice_panel(S8a, u, 2 * B, a.ntv_s, a.nqc);
+  i16v ac[kI8Blocks][kSlices];
+  i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nqc, lds, ac, wr, wc, lane);
+  const int64_t ld = (int64_t)a.ntv_s * kPanel;
+  double *X = Xb + ((int64_t)ml * a.na + u) * ld * ld + (int64_t)A * kI8Tile * ld + B * kI8Tile;
+#pragma unroll
+  for (int q = 0; q < kI8Blocks; ++q) {
+    double x[16];
+    i8_block_values(ac[q], sigc + m * ld + A * kI8Tile, siga + u * ld + B * kI8Tile, wr, wc, q,
+                    lane, x);
 #pragma unroll
     for (int r = 0; r < 16; ++r)
-      X[(int64_t)(A * kPanel + i8_row(wr, lane, r)) * ld + B * kPanel + cb] = x[r];
-  }
-  if (A != B) {
-    // X^{mu}[f][e] for f in B, e in A equals y[e][f], still in LDS as T[e][f]
-    const double (*T)[kPanel + 1] = reinterpret_cast<const double (*)[kPanel + 1]>(lds);
-    for (int k = threadIdx.x; k < kPanel * kPanel; k += kI8Threads) {
-      const int fr = k / kPanel, ec = k % kPanel;
-      X[(int64_t)(B * kPanel + fr) * ld + A * kPanel + ec] = T[ec][fr];
-    }
+      X[(int64_t)i8_row(wr, q, lane, r) * ld + i8_col(wc, q, lane)] = x[r];
   }
 }
 
-// CAVV step 2: per (m, e, f), with X_u = (me|uf), X'_u = (mf|ue):
-//   sum_uv Gamma_uv S(D_mu) R1(D_mv) X_u (2 X_v - X'_v), summed over all (e, f).
-// One workgroup per (m, 64-row block of e, 256 columns f); X'_u is read from
-// the mirrored rows through L2.
+// CAVV step 2 (both precisions). With X_u = (me|uf) = X^{mu}[e][f] and
+// X'_u = (mf|ue) = X^{mu}[f][e], the energy is the sum over (m, e, f) of
+//   sum_uv Gamma_uv [S(D_mu) X_u] [R1(D_mv) (2 X_v - X'_v)],
+// D_mu = eps_m + eps_u - eps_e - eps_f. One workgroup per (m, 16-block pair
+// E <= F): blocks X^{mu}[E][F] and X^{mu}[F][E] of every u are staged in LDS;
+// thread (e, f) takes element (e, f) of E x F and, when E < F, element (f, e)
+// of F x E, so every integral is read from memory once.
+constexpr int kEpiT = 16;
+
 struct CavvEpiArgs {
-  int na, nv, ntv;
+  int nv, nt16;
+  int64_t ld;
   double s;
   int m0;
-  int fchunks;
   int64_t slot_base;
   int atomic_mode;
 };
+
+template <int NA>
+__device__ __forceinline__ double cavv_epi_element(const double (&Xu)[NA], const double (&Xp)[NA],
+                                                   const double (&G)[NA][NA],
+                                                   const double (&ea)[NA], double base,
+                                                   double s) {
+  double Sx[NA], W[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    double S, R1;
+    reg_S_R1(base + ea[u], s, S, R1);
+    Sx[u] = S * Xu[u];
+    W[u] = R1 * (2.0 * Xu[u] - Xp[u]);
+  }
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    double t = 0.0;
+#pragma unroll
+    for (int v = 0; v < NA; ++v) t += G[u][v] * W[v];
+    part += Sx[u] * t;
+  }
+  return part;
+}
 
 template <int NA>
 __global__ __launch_bounds__(256) void cavv_epi_kernel(const double *__restrict__ Xb,
@@ -481,14 +600,22 @@ __global__ __launch_bounds__(256) void cavv_epi_kernel(const double *__restrict_
                                                        const double *__restrict__ gamma1,
                                                        CavvEpiArgs a, double *slots,
                                                        double *acc) {
+  __shared__ double Xs[NA][2][kEpiT][kEpiT + 1];
   __shared__ double red[4];
-  const int64_t ld = (int64_t)a.ntv * kPanel;
-  const int64_t w = blockIdx.x;
-  const int fch = (int)(w % a.fchunks);
-  const int64_t rest = w / a.fchunks;
-  const int eb = (int)(rest % a.ntv), ml = (int)(rest / a.ntv);
-  const int f = fch * 256 + threadIdx.x;
+  const int64_t T = (int64_t)a.nt16 * (a.nt16 + 1) / 2;
+  const int ml = (int)(blockIdx.x / T);
+  int E, F;
+  decode_pair_le(blockIdx.x % T, a.nt16, E, F);
+  const int e = threadIdx.x >> 4, f = threadIdx.x & 15;
+  const int64_t ld = a.ld;
   const double *X = Xb + (int64_t)ml * NA * ld * ld;
+  const int e0 = E * kEpiT, f0 = F * kEpiT;
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const double *Xu = X + (int64_t)u * ld * ld;
+    Xs[u][0][e][f] = Xu[(int64_t)(e0 + e) * ld + f0 + f];
+    Xs[u][1][e][f] = Xu[(int64_t)(f0 + e) * ld + e0 + f];
+  }
   double G[NA][NA], ea[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
@@ -497,28 +624,26 @@ __global__ __launch_bounds__(256) void cavv_epi_kernel(const double *__restrict_
     for (int v = 0; v < NA; ++v) G[u][v] = gamma1[u * NA + v];
   }
   const double em = eps_c[a.m0 + ml];
+  __syncthreads();
   double part = 0.0;
-  if (f < a.nv) {
-    const double ef = eps_v[f];
-    for (int el = 0; el < kPanel; ++el) {
-      const int e = eb * kPanel + el;
-      if (e >= a.nv) break;
-      const double base = em - (eps_v[e] + ef);
-      double S[NA], R1[NA], Xv[NA], W[NA];
+  double Xu[NA], Xp[NA];
+  if (e0 + e < a.nv && f0 + f < a.nv) {
+    // element (e0 + e, f0 + f)
 #pragma unroll
-      for (int u = 0; u < NA; ++u) {
-        reg_S_R1(base + ea[u], a.s, S[u], R1[u]);
-        Xv[u] = X[((int64_t)u * ld + e) * ld + f];
-        W[u] = R1[u] * (2.0 * Xv[u] - X[((int64_t)u * ld + f) * ld + e]);
-      }
-#pragma unroll
-      for (int u = 0; u < NA; ++u) {
-        double t = 0.0;
-#pragma unroll
-        for (int v = 0; v < NA; ++v) t += G[u][v] * W[v];
-        part += S[u] * Xv[u] * t;
-      }
+    for (int u = 0; u < NA; ++u) {
+      Xu[u] = Xs[u][0][e][f];
+      Xp[u] = Xs[u][1][f][e];
     }
+    part += cavv_epi_element<NA>(Xu, Xp, G, ea, em - (eps_v[e0 + e] + eps_v[f0 + f]), a.s);
+  }
+  if (E != F && f0 + e < a.nv && e0 + f < a.nv) {
+    // element (f0 + e, e0 + f)
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      Xu[u] = Xs[u][1][e][f];
+      Xp[u] = Xs[u][0][f][e];
+    }
+    part += cavv_epi_element<NA>(Xu, Xp, G, ea, em - (eps_v[f0 + e] + eps_v[e0 + f]), a.s);
   }
   const double t = block_sum(part, red);
   emit_partial(t, slots, a.slot_base + blockIdx.x, acc, a.atomic_mode);
@@ -529,11 +654,11 @@ __global__ __launch_bounds__(256) void cavv_epi_kernel(const double *__restrict_
 // ---------------------------------------------------------------------------
 static hipError_t slice_one(const double *B, int64_t nrow, const Plan &pl, double *sig,
                             double *diag, int8_t *S8, double *scratch, hipStream_t st) {
-  const int64_t ncol = nrow * pl.ntv * kPanel;
+  const int64_t ncol = nrow * pl.ntv_s * kPanel;
   double *pmax = scratch, *psum = scratch + kScaleGroups * ncol;
   timer_begin("slice_scale", st);
   hipLaunchKernelGGL(slice_scale_partial_kernel, dim3((unsigned)ceil_div(ncol, 256), kScaleGroups),
-                     dim3(256), 0, st, B, nrow, pl.nv, pl.naux, pl.ntv, pmax, psum);
+                     dim3(256), 0, st, B, nrow, pl.nv, pl.naux, pl.ntv_s, pmax, psum);
   hipLaunchKernelGGL(slice_scale_final_kernel, dim3((unsigned)ceil_div(ncol, 256)), dim3(256), 0,
                      st, pmax, psum, ncol, sig, diag);
   timer_end(st);
@@ -541,7 +666,7 @@ static hipError_t slice_one(const double *B, int64_t nrow, const Plan &pl, doubl
   if (e != hipSuccess) return e;
   timer_begin("slice_pack", st);
   hipLaunchKernelGGL(slice_pack_kernel, dim3((unsigned)ceil_div(ncol * pl.nqc, 256)), dim3(256),
-                     0, st, B, nrow, pl.nv, pl.naux, pl.ntv, pl.nqc, sig, S8);
+                     0, st, B, nrow, pl.nv, pl.naux, pl.ntv_s, pl.nqc, sig, S8);
   timer_end(st);
   return hipGetLastError();
 }
@@ -550,17 +675,16 @@ template <int NA>
 static hipError_t cavv_epi_na(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
                               hipStream_t st) {
   CavvEpiArgs a;
-  a.na = (int)pl.na;
   a.nv = (int)pl.nv;
-  a.ntv = (int)pl.ntv;
+  a.nt16 = (int)ceil_div(pl.nv, kEpiT);
+  a.ld = pl.xld;
   a.s = pl.s;
   a.m0 = m0;
-  a.fchunks = (int)ceil_div(pl.nv, 256);
-  a.slot_base = pl.slot_base[1] + (int64_t)m0 * pl.ntv * a.fchunks;
+  const int64_t T = (int64_t)a.nt16 * (a.nt16 + 1) / 2;
+  a.slot_base = pl.slot_base[1] + (int64_t)m0 * T;
   a.atomic_mode = pl.atomic_reduce ? 1 : 0;
-  const int64_t nblk = (int64_t)mb * pl.ntv * a.fchunks;
   timer_begin("cavv_epi", st);
-  hipLaunchKernelGGL((cavv_epi_kernel<NA>), dim3((unsigned)nblk), dim3(256), 0, st,
+  hipLaunchKernelGGL((cavv_epi_kernel<NA>), dim3((unsigned)(mb * T)), dim3(256), 0, st,
                      ws_d(ws, pl.off_xb), in.eps_c, in.eps_a, in.eps_v, in.gamma1, a,
                      ws_d(ws, pl.off_slots), ws_d(ws, pl.off_acc) + 1);
   timer_end(st);
@@ -602,15 +726,17 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
     CcvvI8Args a;
     a.nc = (int)pl.nc;
     a.nv = (int)pl.nv;
-    a.ntv = (int)pl.ntv;
+    a.ntv_s = (int)pl.ntv_s;
     a.nqc = pl.nqc;
     a.s = pl.s;
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
+    const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv_s / 2);
+    const int64_t grid = items < kSlicePersistWG ? items : kSlicePersistWG;   // multiples of 8
     timer_begin("ccvv_i8", st);
-    hipLaunchKernelGGL(ccvv_i8_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(kI8Threads), 0, st,
+    hipLaunchKernelGGL(ccvv_i8_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st,
                        ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
-                       in.eps_c, in.eps_v, a, slots, acc + 0);
+                       in.eps_c, in.eps_v, a, ws_d(ws, pl.off_xs), slots, acc + 0);
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -619,13 +745,12 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
       const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
       CavvXArgs xa;
       xa.na = (int)pl.na;
-      xa.nv = (int)pl.nv;
-      xa.ntv = (int)pl.ntv;
+      xa.ntv_s = (int)pl.ntv_s;
       xa.nqc = pl.nqc;
       xa.m0 = (int)m0;
       xa.mb = mb;
       timer_begin("cavv_i8_x", st);
-      hipLaunchKernelGGL(cavv_i8_x_kernel, dim3((unsigned)pairtile_grid((int64_t)mb * pl.na, pl.ntv)), dim3(kI8Threads), 0, st,
+      hipLaunchKernelGGL(cavv_i8_x_kernel, dim3((unsigned)fulltile_grid((int64_t)mb * pl.na, pl.ntv_s / 2)), dim3(kI8Threads), 0, st,
                          ws_b(ws, pl.off_s8c), ws_b(ws, pl.off_s8a), ws_d(ws, pl.off_sigc),
                          ws_d(ws, pl.off_siga), xa, ws_d(ws, pl.off_xb));
       timer_end(st);
