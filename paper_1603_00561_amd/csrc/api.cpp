@@ -184,7 +184,8 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   }
   pl.off_xs = off;
   if (split && (term_bits & DSRG_TERM_CCVV))
-    off = align256(off + sizeof(double) * (size_t)(kSlicePersistWG * kSliceXsDoubles));
+    off = align256(off + sizeof(double) * (size_t)(kSlicePersistWG * kSliceXsDoubles) +
+                   kSliceCounterBytes);
   pl.off_gs = pl.off_g2 = pl.off_g3 = off;
   if (pl.with_grad) {
     const size_t Np = (size_t)(pl.nc * pl.ntv * kPanel);

@@ -18,6 +18,8 @@ constexpr int kActPanel = 16;
 // 512 lanes x 32 values for the first product of a two-product tile.
 constexpr int kSlicePersistWG = 256;
 constexpr int64_t kSliceXsDoubles = 512 * 32;
+// followed by eight per-XCD work counters (ints; cleared before each launch)
+constexpr size_t kSliceCounterBytes = 64;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
@@ -47,7 +49,7 @@ struct Plan {
   int64_t nqc;                        // chunks of 32 auxiliary indices
   int64_t cavv_mb;                    // core orbitals per CAVV integral batch
   size_t off_s8c, off_s8a, off_sigc, off_siga, off_diag, off_xb, off_scr;
-  size_t off_xs;                      // per-workgroup x slots of the int8 CCVV kernel
+  size_t off_xs;                      // per-workgroup x slots of the int8 CCVV kernel, then its work counters
   size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
   size_t off_slots;                   // per-workgroup partial energies
   size_t off_acc;                     // [4] atomic accumulators

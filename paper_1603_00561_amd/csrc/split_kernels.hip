@@ -369,8 +369,9 @@ __device__ __forceinline__ bool decode_ccvv_i8(int64_t kk, int x, int nc, int nt
 // CCVV on slices. Work items are (core pair i <= j, 128-tile pair A <= B)
 // in the order of decode_ccvv_i8; classes 0: i<j, A<B (x and y = K^{ji}[A,B]),
 // 1: i<j, A=B (y = x^T), 2: i=j, A<B and 3: i=j, A=B (y = x). The grid is
-// persistent (kSlicePersistWG workgroups, a multiple of 8, each walking the
-// list of its XCD); a class-0 item parks x in its workgroup's FP64 slot xs
+// persistent (kSlicePersistWG workgroups, a multiple of 8, each taking the
+// next item of its XCD's list from that XCD's counter in ctr, which must be
+// zero at launch); a class-0 item parks x in its workgroup's FP64 slot xs
 // while y is formed. The self-pair diagonal (i = j, a = b) uses the FP64 sum
 // of squares.
 // ---------------------------------------------------------------------------
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__
                                                       const double *__restrict__ eps_c,
                                                       const double *__restrict__ eps_v,
                                                       CcvvI8Args a, double *__restrict__ xs,
-                                                      double *slots, double *acc) {
+                                                      int *ctr, double *slots, double *acc) {
   __shared__ __attribute__((aligned(16))) int8_t lds[kI8LdsRing];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 2, wc = wave & 3;
@@ -396,19 +397,33 @@ __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__
   const int64_t ldv = (int64_t)a.ntv_s * kPanel;   // sigma / diagonal row length
   double *xw = xs + (int64_t)blockIdx.x * kSliceXsDoubles + threadIdx.x;
   const int x = blockIdx.x % 8;   // the XCD this workgroup runs on
+  scalar_here(S8);
   scalar_here(sig);
   scalar_here(diag);
   scalar_here(eps_c);
   scalar_here(eps_v);
+  scalar_here(xs);
+  scalar_here(ctr);
   scalar_here(slots);
   scalar_here(acc);
+  scalar_here(a.nc);
+  scalar_here(a.nv);
+  scalar_here(a.ntv_s);
+  scalar_here(a.nqc);
   scalar_here(a.s);
   scalar_here(a.slot_base);
+  scalar_here(a.atomic_mode);
   CcvvWork c;
   int64_t slot;
-  for (int64_t kk = blockIdx.x / 8; decode_ccvv_i8(kk, x, a.nc, nt, c, slot);
-       kk += gridDim.x / 8) {
-    __syncthreads();   // the previous item's reduction is done with the LDS
+  // the next item of this XCD's list comes from its work counter, so the
+  // items in flight on an XCD are always consecutive ones (shared panels)
+  int *next = reinterpret_cast<int *>(lds + kI8LdsRing - sizeof(int));
+  for (;;) {
+    __syncthreads();   // the previous item is done with the LDS
+    if (threadIdx.x == 0) *next = atomicAdd(ctr + x, 1);
+    __syncthreads();
+    const int64_t kk = *next;
+    if (!decode_ccvv_i8(kk, x, a.nc, nt, c, slot)) break;
     const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
     const double *sri = sig + c.i * ldv + c.A * kI8Tile, *scj = sig + c.j * ldv + c.B * kI8Tile;
     const double *srj = sig + c.j * ldv + c.A * kI8Tile, *sci = sig + c.i * ldv + c.B * kI8Tile;
@@ -527,9 +542,13 @@ __global__ __launch_bounds__(512) void cavv_i8_x_kernel(const int8_t *__restrict
   int A, B;
   decode_tile_full_blocked(kk % T, nt, A, B);
   const int u = (int)(p % a.na), ml = (int)(p / a.na), m = a.m0 + ml;
+  scalar_here(S8c);
+  scalar_here(S8a);
   scalar_here(sigc);
   scalar_here(siga);
   scalar_here(Xb);
+  scalar_here(a.nqc);
+  scalar_here(a.ntv_s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 2, wc = wave & 3;
   const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
@@ -733,10 +752,13 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
     const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv_s / 2);
     const int64_t grid = items < kSlicePersistWG ? items : kSlicePersistWG;   // multiples of 8
+    double *xs = ws_d(ws, pl.off_xs);
+    int *ctr = reinterpret_cast<int *>(xs + (size_t)kSlicePersistWG * kSliceXsDoubles);
+    if ((e = launch_zero(reinterpret_cast<double *>(ctr), 4, st)) != hipSuccess) return e;
     timer_begin("ccvv_i8", st);
     hipLaunchKernelGGL(ccvv_i8_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st,
                        ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
-                       in.eps_c, in.eps_v, a, ws_d(ws, pl.off_xs), slots, acc + 0);
+                       in.eps_c, in.eps_v, a, xs, ctr, slots, acc + 0);
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
