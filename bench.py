@@ -179,8 +179,12 @@ def main():
     value = F / (ms_per_step * 1e-3) / 1e12
     if args.grad:
         # dominant kernel: the adjoint GEMM (2/3 of the work); report all its launches
-        gm = per_kernel.get("gemm_adj_fp64", []) + per_kernel.get("gemm_adj_tb_fp64", [])
-        dom, unit, mult = "gemm_adj_fp64", "TFLOP/s", 1.0
+        if args.precision == "fp64":
+            gm = per_kernel.get("gemm_adj_fp64", []) + per_kernel.get("gemm_adj_tb_fp64", [])
+            dom, unit, mult = "gemm_adj_fp64", "TFLOP/s", 1.0
+        else:
+            gm = per_kernel.get("gemm_adj_i8", [])
+            dom, unit, mult = "gemm_adj_i8", "TOP/s", 15.0
         avg[dom] = float(np.sum(gm)) / args.steps if gm else None
         Fparts = dict(Fparts)
         Fparts["ccvv"] = 2.0 / 3.0 * F

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <algorithm>
 #include <string.h>
 
 #include "../../include/dsrg_df.h"
@@ -80,8 +81,11 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
                 (long long)p->nc, (long long)p->nv, (long long)p->naux);
   if (precision == DSRG_SPLIT_BF16)
     return fail(DSRG_ERR_UNSUPPORTED, "precision %d is not available in this build", precision);
-  if (precision == DSRG_SPLIT_OZAKI && with_grad)
-    return fail(DSRG_ERR_UNSUPPORTED, "gradients are available in FP64 only");
+  if (precision == DSRG_SPLIT_OZAKI && with_grad &&
+      p->nc * ceil_div(p->nv, kPanel) * kPanel > 100000)
+    return fail(DSRG_ERR_UNSUPPORTED,
+                "nc * padded nv = %lld exceeds 100000, the longest int8 adjoint contraction",
+                (long long)(p->nc * ceil_div(p->nv, kPanel) * kPanel));
   if (precision == DSRG_SPLIT_OZAKI && p->naux > 100000)
     return fail(DSRG_ERR_UNSUPPORTED,
                 "naux = %lld exceeds 100000, beyond which int32 slice sums could overflow",
@@ -106,7 +110,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   // one slot per (core pair, tile pair): 64-wide tiles in FP64, 128-wide on slices
   const int64_t nt2 = pl.ntv_s / 2;
   pl.n_ccvv = !(term_bits & DSRG_TERM_CCVV) ? 0
-              : (precision == DSRG_SPLIT_OZAKI)
+              : (precision == DSRG_SPLIT_OZAKI && !with_grad)
                   ? (pl.nc * (pl.nc + 1) / 2) * (nt2 * (nt2 + 1) / 2)
                   : (npo * ntpo + npo * pl.ntv + pl.nc * ntpo + pl.nc * pl.ntv);
   const int64_t ntw = ceil_div(pl.nv, pl.cavv_tile);
@@ -139,11 +143,13 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
 
   size_t off = 0;
   // FP64 panels: every FP64 kernel; in the slice path only the CCAV GEMM
+  // (the slice-path gradient forms its adjoint tiles with the FP64 kernels)
+  const bool fp64_tiles = !split || pl.with_grad;
   pl.off_pcv = off;
-  if (!split || has_ccav)
+  if (fp64_tiles || has_ccav)
     off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.ntv * pl.naux_p * kPanel));
   pl.off_pav = off;
-  if (!split && has_cavv)
+  if (fp64_tiles && has_cavv)
     off = align256(off + sizeof(double) * (size_t)(pl.na * pl.ntv * pl.naux_p * kPanel));
   pl.off_pca = off;
   pl.off_j = off;
@@ -159,7 +165,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   }
   pl.off_s8c = pl.off_s8a = pl.off_sigc = pl.off_siga = pl.off_diag = pl.off_xb = pl.off_scr =
       off;
-  if (split) {
+  if (split && !pl.with_grad) {
     const size_t chunk = 5 * kPanel * 32;   // bytes per (panel, 32 auxiliary indices)
     const size_t colc = (size_t)(pl.nc * pl.ntv_s * kPanel), cola = (size_t)(pl.na * pl.ntv_s * kPanel);
     pl.off_s8c = off;
@@ -201,6 +207,39 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       pl.off_g3 = off;
       off = align256(off + sizeof(double) * Np * (size_t)(pl.nc * kActPanel));
     }
+  }
+  pl.off_SA1 = pl.off_SA2 = pl.off_SB = pl.off_sigA1 = pl.off_sigA2 = pl.off_sigB =
+      pl.off_opmax = off;
+  if (split && pl.with_grad) {
+    // operand slices of the int8 adjoint products (5 bytes per element) and
+    // their row scales; the G operands share one buffer, used in turn
+    const size_t W = (size_t)(pl.ntv * kPanel), Np = (size_t)pl.nc * W,
+                 N2 = (size_t)pl.na * W, N3 = (size_t)(pl.nc * kActPanel);
+    const size_t N3p = (size_t)round_up((int64_t)N3, 32);
+    const size_t RA = (size_t)round_up(pl.naux, 128);
+    auto r128 = [](size_t n) { return (size_t)round_up((int64_t)n, 128); };
+    const bool act = pl.na > 0 && (term_bits & (DSRG_TERM_CAVV | DSRG_TERM_CCAV));
+    size_t sb = 0, rbmax = 0;
+    if (term_bits & DSRG_TERM_CCVV) sb = std::max(sb, r128(Np) * Np);
+    if (pl.na > 0 && (term_bits & DSRG_TERM_CAVV))
+      sb = std::max(sb, std::max(r128(Np) * N2, r128(N2) * Np));
+    if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV))
+      sb = std::max(sb, std::max(r128(Np) * N3p, r128(N3) * Np));
+    rbmax = std::max(r128(Np), std::max(r128(N2), r128(N3)));
+    pl.off_SA1 = off;
+    off = align256(off + 5 * RA * Np);
+    pl.off_SA2 = off;
+    if (act) off = align256(off + 5 * RA * std::max(N2, N3p));
+    pl.off_SB = off;
+    off = align256(off + 5 * sb);
+    pl.off_sigA1 = off;
+    off = align256(off + sizeof(double) * RA);
+    pl.off_sigA2 = off;
+    off = align256(off + sizeof(double) * RA);
+    pl.off_sigB = off;
+    off = align256(off + sizeof(double) * rbmax);
+    pl.off_opmax = off;
+    off = align256(off + sizeof(double) * 32 * std::max(RA, rbmax));
   }
   pl.off_slots = off;
   pl.slot_base[0] = 0;
@@ -326,7 +365,9 @@ dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int
                  deps_c, pl.na > 0 ? deps_a : nullptr, deps_v, ds, gE};
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   timer_reset((terms & DSRG_OPT_KERNEL_TIMING) != 0);
-  hipError_t e = dsrg::launch_backward_fp64(pl, in, o, workspace, hs);
+  hipError_t e = (precision == DSRG_SPLIT_OZAKI)
+                     ? dsrg::launch_backward_split(pl, in, o, workspace, hs)
+                     : dsrg::launch_backward_fp64(pl, in, o, workspace, hs);
   if (e == hipSuccess && E_terms) e = dsrg::launch_finalize(pl, workspace, E_terms, hs);
   if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return DSRG_OK;

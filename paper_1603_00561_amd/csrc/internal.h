@@ -51,6 +51,8 @@ struct Plan {
   size_t off_s8c, off_s8a, off_sigc, off_siga, off_diag, off_xb, off_scr;
   size_t off_xs;                      // per-workgroup x slots of the int8 CCVV kernel, then its work counters
   size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
+  // int8 adjoint products (slice-path gradient): operand slices and scales
+  size_t off_SA1, off_SA2, off_SB, off_sigA1, off_sigA2, off_sigB, off_opmax;
   size_t off_slots;                   // per-workgroup partial energies
   size_t off_acc;                     // [4] atomic accumulators
   size_t total;
@@ -86,8 +88,13 @@ hipError_t launch_zero(double *p, int n, hipStream_t st);
 hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
                            hipStream_t st);
-// ---- adjoint (fp64_bwd.hip) ----
+// ---- adjoint (fp64_bwd.hip, split_bwd.hip) ----
+hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st);
+hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const BwdOut &o,
+                                     void *ws, hipStream_t st);
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st);
+hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                 hipStream_t st);
 
 }  // namespace dsrg

@@ -1,0 +1,312 @@
+// Backward pass of the int8 slice path (DSRG_SPLIT_OZAKI) of libdsrgdf
+// (gfx950): the adjoint contractions dE/dB = B G on the int8 matrix cores.
+//
+// The adjoint tiles G (Gs for CCVV, G2 for CAVV, G3 for CCAV) are formed in
+// FP64 exactly as in the FP64 backward; each product C[Q][n] = sum_k
+// B^Q_k G[k][n] is then taken on error-free int8 slices: both operands are
+// split per row (Q for B, the output index n for G) into five power-of-two
+// scaled slices, the 15 slice products of levels L <= 4 are exact int32
+// sums over k (|I_L| <= 5 * 4096 * K < 2^31 for K <= 100000), and the
+// levels are recombined in FP64 (the scheme of the forward slice path).
+#include "int8_tiles.h"
+
+namespace dsrg {
+
+// An FP64 operand seen as rows r (the index kept by the product) and a
+// contraction index k, both in padded index spaces made of blocks: element
+// (r, k) is base[(r / rblk) ldrb + (r % rblk) ldr + (k / kblk) ldkb +
+// (k % kblk) ldk], and zero when r >= rlim, k >= klim, r % rblk >= rval or
+// k % kblk >= kval.
+struct OpMap {
+  const double *base;
+  int64_t rblk, rval, ldrb, ldr, rlim;
+  int64_t kblk, kval, ldkb, ldk, klim;
+};
+
+// Row r of the map: returns its base pointer (or nullptr when the row is
+// padding); k is walked by op_next with a running (block, offset) pair.
+__device__ __forceinline__ const double *op_row(const OpMap &m, int64_t r) {
+  if (r >= m.rlim) return nullptr;
+  const int64_t rb = r / m.rblk, re = r % m.rblk;
+  if (re >= m.rval) return nullptr;
+  return m.base + rb * m.ldrb + re * m.ldr;
+}
+
+struct KWalk {
+  int64_t k, kb, ke;
+};
+
+__device__ __forceinline__ KWalk kwalk_start(const OpMap &m, int64_t k) {
+  return KWalk{k, k / m.kblk, k % m.kblk};
+}
+
+__device__ __forceinline__ double op_next(const OpMap &m, const double *row, KWalk &w) {
+  double v = 0.0;
+  if (row && w.k < m.klim && w.ke < m.kval) v = row[w.kb * m.ldkb + w.ke * m.ldk];
+  ++w.k;
+  if (++w.ke == m.kblk) {
+    w.ke = 0;
+    ++w.kb;
+  }
+  return v;
+}
+
+constexpr int kOpScaleGroups = 32;
+
+// max_k |op(r, k)| over kOpScaleGroups ranges of k, one thread per row.
+__global__ __launch_bounds__(256) void op_scale_partial_kernel(OpMap m, int64_t R, int64_t K,
+                                                               double *__restrict__ pmax) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int g = blockIdx.y;
+  if (r >= R) return;
+  const int64_t k0 = K * g / kOpScaleGroups, k1 = K * (g + 1) / kOpScaleGroups;
+  const double *row = op_row(m, r);
+  double mx = 0.0;
+  if (row) {
+    KWalk w = kwalk_start(m, k0);
+    for (int64_t k = k0; k < k1; ++k) mx = fmax(mx, fabs(op_next(m, row, w)));
+  }
+  pmax[g * R + r] = mx;
+}
+
+// sigma[r] = the smallest power of two above the row maximum (1 for zero rows)
+__global__ __launch_bounds__(256) void op_scale_final_kernel(const double *__restrict__ pmax,
+                                                             int64_t R,
+                                                             double *__restrict__ sig) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  double mx = 0.0;
+  for (int g = 0; g < kOpScaleGroups; ++g) mx = fmax(mx, pmax[g * R + r]);
+  int ex = 0;
+  if (mx > 0.0) (void)frexp(mx, &ex);   // mx < 2^ex
+  sig[r] = (mx > 0.0) ? ldexp(1.0, ex) : 1.0;
+}
+
+// Slices of rows r in the panel layout of the forward path: panel r / 64,
+// chunk qc of 32 contraction indices, slice s, column r % 64 (halves swapped
+// when (r >> 3) & 1). One thread per (row, chunk); consecutive threads take
+// consecutive rows.
+__global__ __launch_bounds__(256) void op_pack_kernel(OpMap m, int64_t R, int64_t nqc,
+                                                      const double *__restrict__ sig,
+                                                      int8_t *__restrict__ S8) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (id >= R * nqc) return;
+  const int64_t r = id % R, qc = id / R;
+  const double inv = 1.0 / sig[r];   // exact: a power of two
+  const double *row = op_row(m, r);
+  KWalk w = kwalk_start(m, qc * kQC);
+  int8_t buf[kSlices][kQC];
+#pragma unroll
+  for (int j = 0; j < kQC; ++j) {
+    double x = op_next(m, row, w) * inv * 64.0;
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      const double t = rint(x);
+      buf[s][j] = (int8_t)(int)t;
+      x = (x - t) * 128.0;
+    }
+  }
+  const int c = (int)(r % kPanel);
+  int8_t *dst = S8 + ((r / kPanel) * nqc + qc) * (int64_t)kSlicePanelChunk;
+  const int sw = (c >> 3) & 1;
+#pragma unroll
+  for (int s = 0; s < kSlices; ++s) {
+    i4v *o = reinterpret_cast<i4v *>(dst + (s * kPanel + c) * kQC);
+    const i4v *hh = reinterpret_cast<const i4v *>(buf[s]);
+    o[sw] = hh[0];
+    o[sw ^ 1] = hh[1];
+  }
+}
+
+// C[Q][n] (=|+=) sum_k A[Q][k] B[n][k] on slices, one 128 x 128 tile per
+// workgroup (A tiles fastest, so the workgroups of one XCD share A panels).
+// Output column n is written at (n / GP) nvalid + n % GP and skipped when
+// n % GP >= nvalid (padding of the column blocks).
+struct I8GemmArgs {
+  int64_t tA;                 // 128-row tiles of A
+  int64_t nqc;                // 32-wide contraction chunks
+  int64_t M;                  // valid rows of A
+  int64_t Ncols, GP, nvalid;  // padded output columns, their block width, valid per block
+  int64_t ldc;
+  int accumulate;
+};
+
+__global__ __launch_bounds__(512) void i8_gemm_kernel(const int8_t *__restrict__ SA,
+                                                      const double *__restrict__ sigA,
+                                                      const int8_t *__restrict__ SB,
+                                                      const double *__restrict__ sigB,
+                                                      I8GemmArgs a, double *__restrict__ C) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[kI8LdsRing];
+  scalar_here(SA);
+  scalar_here(sigA);
+  scalar_here(SB);
+  scalar_here(sigB);
+  scalar_here(C);
+  scalar_here(a.nqc);
+  const int64_t ta = blockIdx.x % a.tA, tb = blockIdx.x / a.tA;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
+  const int8_t *r0 = SA + 2 * ta * ps, *c0 = SB + 2 * tb * ps;
+  i16v ac[kI8Blocks][kSlices];
+  i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nqc, lds, ac, wr, wc, lane);
+#pragma unroll
+  for (int q = 0; q < kI8Blocks; ++q) {
+    double v[16];
+    i8_block_values(ac[q], sigA + ta * kI8Tile, sigB + tb * kI8Tile, wr, wc, q, lane, v);
+    const int64_t n = tb * kI8Tile + i8_col(wc, q, lane);
+    const int64_t nb = n / a.GP, ne = n % a.GP;
+    if (n >= a.Ncols || ne >= a.nvalid) continue;
+    double *Cn = C + nb * a.nvalid + ne;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t Q = ta * kI8Tile + i8_row(wr, q, lane, r);
+      if (Q >= a.M) continue;
+      double *d = Cn + Q * a.ldc;
+      *d = a.accumulate ? *d + v[r] : v[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static OpMap op_map(const double *base, int64_t rblk, int64_t rval, int64_t ldrb, int64_t ldr,
+                    int64_t rlim, int64_t kblk, int64_t kval, int64_t ldkb, int64_t ldk,
+                    int64_t klim) {
+  OpMap m;
+  m.base = base;
+  m.rblk = rblk;
+  m.rval = rval;
+  m.ldrb = ldrb;
+  m.ldr = ldr;
+  m.rlim = rlim;
+  m.kblk = kblk;
+  m.kval = kval;
+  m.ldkb = ldkb;
+  m.ldk = ldk;
+  m.klim = klim;
+  return m;
+}
+
+// Scales and slices of an operand with R rows (a multiple of 128) and K
+// contraction indices (a multiple of 32).
+static hipError_t pack_operand(const OpMap &m, int64_t R, int64_t K, double *sig,
+                               double *pmax, int8_t *S8, hipStream_t st) {
+  timer_begin("op_pack", st);
+  hipLaunchKernelGGL(op_scale_partial_kernel, dim3((unsigned)ceil_div(R, 256), kOpScaleGroups),
+                     dim3(256), 0, st, m, R, K, pmax);
+  hipLaunchKernelGGL(op_scale_final_kernel, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, st,
+                     pmax, R, sig);
+  const int64_t nqc = K / kQC;
+  hipLaunchKernelGGL(op_pack_kernel, dim3((unsigned)ceil_div(R * nqc, 256)), dim3(256), 0, st, m,
+                     R, nqc, sig, S8);
+  timer_end(st);
+  return hipGetLastError();
+}
+
+static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, const int8_t *SB,
+                          const double *sigB, int64_t RB, int64_t K, int64_t M, int64_t Ncols,
+                          int64_t GP, int64_t nvalid, double *C, int64_t ldc, bool accumulate,
+                          hipStream_t st) {
+  I8GemmArgs a;
+  a.tA = RA / kI8Tile;
+  a.nqc = K / kQC;
+  a.M = M;
+  a.Ncols = Ncols;
+  a.GP = GP;
+  a.nvalid = nvalid;
+  a.ldc = ldc;
+  a.accumulate = accumulate ? 1 : 0;
+  const int64_t grid = a.tA * (RB / kI8Tile);
+  timer_begin("gemm_adj_i8", st);
+  hipLaunchKernelGGL(i8_gemm_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st, SA, sigA, SB,
+                     sigB, a, C);
+  timer_end(st);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                 hipStream_t st) {
+  hipError_t e;
+  // adjoint tiles Gs, G2, G3 and the eps / s gradients, as in the FP64 backward
+  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, st)) != hipSuccess) return e;
+  const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
+  const int64_t W = pl.ntv * kPanel;             // padded virtual orbitals per orbital
+  const int64_t Np = pl.nc * W, N2 = pl.na * W, N3 = pl.nc * kActPanel;
+  const int64_t N3p = round_up(N3, kQC);
+  const int64_t RA = round_up(pl.naux, kI8Tile);
+  const int64_t big = (int64_t)1 << 40;
+  double *pmax = ws_d(ws, pl.off_opmax);
+  double *sigA1 = ws_d(ws, pl.off_sigA1), *sigA2 = ws_d(ws, pl.off_sigA2);
+  double *sigB = ws_d(ws, pl.off_sigB);
+  int8_t *SA1 = ws_b(ws, pl.off_SA1), *SA2 = ws_b(ws, pl.off_SA2), *SB = ws_b(ws, pl.off_SB);
+  const double *Gs = ws_d(ws, pl.off_gs), *G2 = ws_d(ws, pl.off_g2), *G3 = ws_d(ws, pl.off_g3);
+  const int64_t ldcv = pl.nc * pl.nv;
+
+  // A1 = B_cv with rows Q and contraction index (m, e) over the padded range Np
+  const OpMap Acv = op_map(in.B_cv, big, pl.naux, 0, ldcv, pl.naux, W, pl.nv, pl.nv, 1, Np);
+  if ((e = pack_operand(Acv, RA, Np, sigA1, pmax, SA1, st)) != hipSuccess) return e;
+
+  bool first = true;
+  if (pl.terms & 1) {
+    // dB_cv[Q][(m,e)] = sum_(j,b) B_cv[Q][(j,b)] Gs[(j,b)][(m,e)]   (Gs symmetric)
+    const int64_t RB = round_up(Np, kI8Tile);
+    const OpMap Bs = op_map(Gs, W, pl.nv, W, 1, Np, W, pl.nv, W * Np, Np, Np);
+    if ((e = pack_operand(Bs, RB, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB, Np, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
+                     false, st)) != hipSuccess)
+      return e;
+    first = false;
+  }
+  if (cavv) {
+    // dB_cv[Q][(m,e)] += sum_(w,f) B_av[Q][(w,f)] G2[(m,e)][(w,f)]
+    const OpMap Aav = op_map(in.B_av, big, pl.naux, 0, pl.na * pl.nv, pl.naux, W, pl.nv, pl.nv,
+                             1, N2);
+    if ((e = pack_operand(Aav, RA, N2, sigA2, pmax, SA2, st)) != hipSuccess) return e;
+    const int64_t RB = round_up(Np, kI8Tile);
+    const OpMap B2t = op_map(G2, W, pl.nv, W * N2, N2, Np, W, pl.nv, W, 1, N2);
+    if ((e = pack_operand(B2t, RB, N2, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = i8_gemm(SA2, sigA2, RA, SB, sigB, RB, N2, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
+                     !first, st)) != hipSuccess)
+      return e;
+    first = false;
+    // dB_av[Q][(w,f)] = sum_(m,e) B_cv[Q][(m,e)] G2[(m,e)][(w,f)]
+    const int64_t RB2 = round_up(N2, kI8Tile);
+    const OpMap B2 = op_map(G2, W, pl.nv, W, 1, N2, W, pl.nv, W * N2, N2, Np);
+    if ((e = pack_operand(B2, RB2, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB2, Np, pl.naux, N2, W, pl.nv, o.dB_av,
+                     pl.na * pl.nv, false, st)) != hipSuccess)
+      return e;
+  } else if (o.dB_av) {
+    if ((e = launch_zero_fill(o.dB_av, pl.naux * pl.na * pl.nv, st)) != hipSuccess) return e;
+  }
+  if (ccav) {
+    // dB_cv[Q][(m,e)] += sum_(n,u) B_ca[Q][(n,u)] G3[(m,e)][(n,u)]
+    const OpMap Aca = op_map(in.B_ca, big, pl.naux, 0, pl.nc * pl.na, pl.naux, kActPanel, pl.na,
+                             pl.na, 1, N3);
+    if ((e = pack_operand(Aca, RA, N3p, sigA2, pmax, SA2, st)) != hipSuccess) return e;
+    const int64_t RB = round_up(Np, kI8Tile);
+    const OpMap B3t = op_map(G3, W, pl.nv, W * N3, N3, Np, kActPanel, pl.na, kActPanel, 1, N3);
+    if ((e = pack_operand(B3t, RB, N3p, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = i8_gemm(SA2, sigA2, RA, SB, sigB, RB, N3p, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
+                     !first, st)) != hipSuccess)
+      return e;
+    first = false;
+    // dB_ca[Q][(n,u)] = sum_(m,e) B_cv[Q][(m,e)] G3[(m,e)][(n,u)]
+    const int64_t RB3 = round_up(N3, kI8Tile);
+    const OpMap B3 = op_map(G3, kActPanel, pl.na, kActPanel, 1, N3, W, pl.nv, W * N3, N3, Np);
+    if ((e = pack_operand(B3, RB3, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB3, Np, pl.naux, N3, kActPanel, pl.na, o.dB_ca,
+                     pl.nc * pl.na, false, st)) != hipSuccess)
+      return e;
+  } else if (o.dB_ca) {
+    if ((e = launch_zero_fill(o.dB_ca, pl.naux * pl.nc * pl.na, st)) != hipSuccess) return e;
+  }
+  if (first) {
+    if ((e = launch_zero_fill(o.dB_cv, pl.naux * ldcv, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace dsrg

@@ -13,36 +13,9 @@
 // naux <= 100000), so the only error left is the dropped levels and the
 // residual r. The self-pair diagonal (ia|ia) = sum_Q (B^Q_ia)^2, whose
 // dropped terms all have one sign, is taken in FP64 instead.
-#include "fp64_tiles.h"
+#include "int8_tiles.h"
 
 namespace dsrg {
-
-typedef int i4v __attribute__((ext_vector_type(4)));
-typedef int i16v __attribute__((ext_vector_type(16)));
-
-static inline double *ws_d(void *ws, size_t off) {
-  return reinterpret_cast<double *>(static_cast<char *>(ws) + off);
-}
-static inline int8_t *ws_b(void *ws, size_t off) {
-  return reinterpret_cast<int8_t *>(static_cast<char *>(ws) + off);
-}
-
-// v_mfma_i32_32x32x32_i8: lane l supplies 16 bytes of row l % 32 of A (and of
-// column l % 32 of B) for the k-range 16 (l / 32) .. +15; result register r
-// of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-__device__ __forceinline__ i16v mfma_i8(i4v a, i4v b, i16v c) {
-  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
-}
-
-// ---------------------------------------------------------------------------
-// Slicing. Slice panels: S8[(p * ntv + t)][qc][s][c][32 bytes] for a 64-column
-// virtual panel t of orbital p, chunk qc of 32 auxiliary indices, slice s,
-// column c; the two 16-byte halves of column c are swapped when (c >> 3) & 1
-// (bank-conflict-free fragment reads). sig[(p * ntv * 64) + e] = sigma.
-// ---------------------------------------------------------------------------
-constexpr int kSlices = 5;
-constexpr int kQC = 32;                                  // auxiliary indices per chunk
-constexpr int kSlicePanelChunk = kSlices * kPanel * kQC; // bytes per (panel, chunk)
 
 // Column maxima and sums of squares in kScaleGroups slices of the auxiliary
 // range (partials), then an in-order combine per column (deterministic).
@@ -125,177 +98,6 @@ __global__ __launch_bounds__(256) void slice_pack_kernel(const double *__restric
     o[sw] = h[0];
     o[sw ^ 1] = h[1];
   }
-}
-
-// ---------------------------------------------------------------------------
-// Int8 tile product, eight waves (two per SIMD) per workgroup.
-// K[a][b] = sum_Q L^Q_a R^Q_b for a 128 x 128 output tile: rows from two
-// 64-column slice panels (r0, r1), columns from two more (c0, c1). Wave w
-// owns rows 64 (w >> 2) .. +63 (two 32-row blocks q = 0, 1) and columns
-// 32 (w & 3) .. +31, with five int32 level accumulators per block (160
-// registers). A stage is one 32-index auxiliary chunk of the four panels
-// (4 x 10 KB); stages are copied global -> LDS directly (global_load_lds,
-// 16 bytes per lane) into a ring of four, three stages ahead of the matrix
-// cores.
-// ---------------------------------------------------------------------------
-constexpr int kI8Threads = 512;
-constexpr int kI8Tile = 128;
-constexpr int kI8Ring = 4;
-constexpr int kI8Stage = 4 * kSlicePanelChunk;       // 40 KB
-constexpr int kI8LdsRing = kI8Ring * kI8Stage;       // 160 KB
-constexpr int kI8Blocks = 2;                         // 32 x 32 blocks per wave
-constexpr int kI8Out = kI8Blocks * 16;               // outputs per lane
-static_assert(kI8Threads * kI8Out == kSliceXsDoubles, "x slot size");
-constexpr int kI8CopiesPerStage = 4 * (kSlicePanelChunk / 16) / kI8Threads;   // 5
-
-__device__ __forceinline__ i4v frag_i8(const int8_t *panel, int s, int row, int h) {
-  const int off = (s * kPanel + row) * kQC + (((h ^ (row >> 3)) & 1) << 4);
-  return *reinterpret_cast<const i4v *>(panel + off);
-}
-
-// Copy one stage (four panel-chunks, in order s0..s3) into the LDS ring slot
-// dst. Each wave moves 64 consecutive 16-byte pieces per instruction; a
-// panel-chunk is 640 pieces, so no wave's pieces straddle two panels, and
-// source base and LDS address are wave-uniform (scalar registers).
-__device__ __forceinline__ void i8_issue_stage(const int8_t *s0, const int8_t *s1,
-                                               const int8_t *s2, const int8_t *s3,
-                                               int8_t *dst) {
-  constexpr int PIECES = kSlicePanelChunk / 16;
-  static_assert(PIECES % 64 == 0 && (4 * PIECES) % kI8Threads == 0, "stage split");
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int voff = (threadIdx.x & 63) * 16;
-#pragma unroll
-  for (int k = 0; k < kI8CopiesPerStage; ++k) {
-    const int base = wave * 64 + k * kI8Threads;
-    const int p = base / PIECES;
-    const int8_t *src = ((p == 0) ? s0 : (p == 1) ? s1 : (p == 2) ? s2 : s3) +
-                        (base % PIECES) * 16;
-    __builtin_amdgcn_global_load_lds(
-        reinterpret_cast<const void *>(src + (uint32_t)voff),
-        (__attribute__((address_space(3))) void *)(dst + base * 16), 16, 0, 0);
-  }
-}
-
-// Workgroup barrier that does not drain the vector-memory counter (the ring
-// waits for its copies explicitly); the empty asm keeps the compiler from
-// moving memory accesses across it.
-__device__ __forceinline__ void ring_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
-// Ties a scalar value (a kernel argument) to this point: its scalar load
-// completes before the K-loop, so no scalar load is in flight there and the
-// loop's LDS waits can count outstanding reads instead of draining them.
-template <class T>
-__device__ __forceinline__ void scalar_here(const T &v) {
-  asm volatile("" ::"s"(v));
-}
-
-// s_waitcnt with only the vector-memory count (expcnt, lgkmcnt not waited)
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
-// Products of one stage are taken in five rounds: round r multiplies row
-// slice r with column slices 0 .. 4-r into the levels r .. 4, so two products
-// into one accumulator are at least four instructions apart, and after round
-// r the fragments of row slice r and column slice 4-r are dead: the next
-// stage's copies of exactly those are read into them at once. The LDS reads
-// of a stage thus overlap the matrix products of the previous one, which
-// needs the next stage in LDS one stage earlier than the products do.
-__device__ __forceinline__ void i8_tile_product(const int8_t *r0, const int8_t *r1,
-                                                const int8_t *c0, const int8_t *c1, int64_t nqc,
-                                                int8_t *lds, i16v (&acc)[kI8Blocks][kSlices],
-                                                int wr, int wc, int lane) {
-  constexpr int64_t CH = kSlicePanelChunk;
-  const int row = lane & 31, h = lane >> 5;
-  const int cr = 32 * (wc & 1) + row;
-#pragma unroll
-  for (int q = 0; q < kI8Blocks; ++q)
-#pragma unroll
-    for (int L = 0; L < kSlices; ++L) acc[q][L] = i16v{};
-  auto issue = [&](int64_t s) {
-    i8_issue_stage(r0 + s * CH, r1 + s * CH, c0 + s * CH, c1 + s * CH,
-                   lds + (int)(s % kI8Ring) * kI8Stage);
-  };
-  // row panel of this wave, column panel, in ring slot b
-  auto lrow = [&](int64_t s) { return lds + (int)(s % kI8Ring) * kI8Stage + wr * CH; };
-  auto lcol = [&](int64_t s) { return lds + (int)(s % kI8Ring) * kI8Stage + (2 + (wc >> 1)) * CH; };
-  for (int64_t s = 0; s < kI8Ring - 1 && s < nqc; ++s) issue(s);
-  wait_vm<0>();
-  ring_barrier();
-  i4v fa[kI8Blocks][kSlices], fb[kSlices];
-#pragma unroll
-  for (int k = 0; k < kSlices; ++k) {
-    fb[k] = frag_i8(lcol(0), k, cr, h);
-#pragma unroll
-    for (int q = 0; q < kI8Blocks; ++q) fa[q][k] = frag_i8(lrow(0), k, 32 * q + row, h);
-  }
-  for (int64_t s = 0; s < nqc; ++s) {
-    // the slot of stage s + 3 held stage s - 1, whose fragments were read
-    // during stage s - 2 and consumed before the barrier that ended stage s - 1
-    const bool more = s + kI8Ring - 1 < nqc;
-    if (more) issue(s + kI8Ring - 1);
-    // fragments of stage s + 1 (a stale slot on the last stage: never used)
-    const int8_t *Lr = lrow(s + 1), *Lc = lcol(s + 1);
-#pragma unroll
-    for (int r = 0; r < kSlices; ++r) {
-#pragma unroll
-      for (int Lv = kSlices - 1; Lv >= r; --Lv)
-#pragma unroll
-        for (int q = 0; q < kI8Blocks; ++q)
-          acc[q][Lv] = mfma_i8(fa[q][r], fb[Lv - r], acc[q][Lv]);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int q = 0; q < kI8Blocks; ++q) fa[q][r] = frag_i8(Lr, r, 32 * q + row, h);
-      fb[kSlices - 1 - r] = frag_i8(Lc, kSlices - 1 - r, cr, h);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    // stage s + 2 must have landed (its fragments are read during stage s + 1);
-    // stage s + 3 may still be in flight
-    if (more)
-      wait_vm<kI8CopiesPerStage>();
-    else
-      wait_vm<0>();
-    ring_barrier();
-  }
-}
-
-// sum_L 2^(-12-7L) I_L, smallest level first
-__device__ __forceinline__ double level_value(const i16v (&acc)[kSlices], int r) {
-  double v = 0.0;
-#pragma unroll
-  for (int L = kSlices - 1; L >= 0; --L) v += ldexp((double)acc[L][r], -12 - 7 * L);
-  return v;
-}
-
-// Row / column inside the 128 x 128 tile of output r of block q of this lane.
-__device__ __forceinline__ int i8_row(int wr, int q, int lane, int r) {
-  return 64 * wr + 32 * q + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-}
-__device__ __forceinline__ int i8_col(int wc, int q, int lane) {
-  (void)q;
-  return 32 * wc + (lane & 31);
-}
-
-// FP64 values of block q: v[r] = sig_row[row] sig_col[col] K[row][col].
-__device__ __forceinline__ void i8_block_values(const i16v (&acc)[kSlices], const double *sig_row,
-                                                const double *sig_col, int wr, int wc, int q,
-                                                int lane, double (&v)[16]) {
-  const double sc = sig_col[i8_col(wc, q, lane)];
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    v[r] = sig_row[i8_row(wr, q, lane, r)] * sc * level_value(acc, r);
-}
-
-// Slice panel t (64 columns) of orbital p; sigma of its first column.
-__device__ __forceinline__ const int8_t *slice_panel(const int8_t *S8, int64_t p, int64_t t,
-                                                     int64_t ntv_s, int64_t nqc) {
-  return S8 + (p * ntv_s + t) * nqc * (int64_t)kSlicePanelChunk;
 }
 
 // Blocked walk (kTileBlock x kTileBlock blocks) over the strictly ordered
