@@ -110,7 +110,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   // one slot per (core pair, tile pair): 64-wide tiles in FP64, 128-wide on slices
   const int64_t nt2 = pl.ntv_s / 2;
   pl.n_ccvv = !(term_bits & DSRG_TERM_CCVV) ? 0
-              : (precision == DSRG_SPLIT_OZAKI && !with_grad)
+              : (precision == DSRG_SPLIT_OZAKI)
                   ? (pl.nc * (pl.nc + 1) / 2) * (nt2 * (nt2 + 1) / 2)
                   : (npo * ntpo + npo * pl.ntv + pl.nc * ntpo + pl.nc * pl.ntv);
   const int64_t ntw = ceil_div(pl.nv, pl.cavv_tile);
@@ -165,7 +165,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   }
   pl.off_s8c = pl.off_s8a = pl.off_sigc = pl.off_siga = pl.off_diag = pl.off_xb = pl.off_scr =
       off;
-  if (split && !pl.with_grad) {
+  if (split) {
     const size_t chunk = 5 * kPanel * 32;   // bytes per (panel, 32 auxiliary indices)
     const size_t colc = (size_t)(pl.nc * pl.ntv_s * kPanel), cola = (size_t)(pl.na * pl.ntv_s * kPanel);
     pl.off_s8c = off;

@@ -684,7 +684,7 @@ hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st) { return zero_
 // Adjoint tiles Gs, G2, G3 (recomputed integrals, FP64) with the energies
 // and the orbital-energy and flow-parameter gradients.
 hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const BwdOut &o,
-                                     void *ws, hipStream_t st) {
+                                     void *ws, bool with_ccvv, hipStream_t st) {
   hipError_t e;
   GradOut g{o.deps_c, o.deps_a, o.deps_v, o.ds, o.gE};
   if ((e = zero_fill(o.deps_c, pl.nc, st)) != hipSuccess) return e;
@@ -694,7 +694,7 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
   if ((e = launch_pack_fp64(pl, in, ws, st)) != hipSuccess) return e;
   const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
   const int64_t Np = pl.nc * pl.ntv * kPanel;
-  if (pl.terms & 1) {
+  if ((pl.terms & 1) && with_ccvv) {
     CcvvAdjArgs a;
     a.nc = (int)pl.nc;
     a.nv = (int)pl.nv;
@@ -739,7 +739,7 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st) {
   hipError_t e;
-  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, st)) != hipSuccess) return e;
+  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, true, st)) != hipSuccess) return e;
   const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
   const int64_t Np = pl.nc * pl.ntv * kPanel;
   // ---- adjoint GEMMs ----

@@ -88,10 +88,13 @@ hipError_t launch_zero(double *p, int n, hipStream_t st);
 hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
                            hipStream_t st);
+// int8 slices of B_cv (with the FP64 diagonal) and, if with_av, of B_av
+hipError_t launch_slices(const Plan &pl, const Inputs &in, void *ws, bool with_av,
+                         hipStream_t st);
 // ---- adjoint (fp64_bwd.hip, split_bwd.hip) ----
 hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st);
 hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const BwdOut &o,
-                                     void *ws, hipStream_t st);
+                                     void *ws, bool with_ccvv, hipStream_t st);
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st);
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,

@@ -168,6 +168,180 @@ __global__ __launch_bounds__(512) void i8_gemm_kernel(const int8_t *__restrict__
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// CCVV adjoint tiles on slices. Same work list, integrals and persistent grid
+// as the forward slice kernel; per element (a, b) of item (i, j, A, B), with
+// x = (ia|jb), y = (ib|ja), class weight w and P = w (x^2 - x y + y^2):
+//   E += R P,  dL/dD = gE0 P R'(D) -> eps_i, eps_j (+), eps_a, eps_b (-),
+//   dL/ds += gE0 P dR/ds,
+//   g1 = 4 gE0 R (2x - y) -> Gs[(i,a)][(j,b)] and (classes 0, 2) Gs[(j,b)][(i,a)],
+//   g2 = 4 gE0 R (2y - x) -> Gs[(j,a)][(i,b)] (classes 0, 1) and (class 0)
+//   Gs[(i,b)][(j,a)],
+// so every element of the symmetric Gs (row (p, e) = p W + e, W = 64 ntv) with
+// e < nv is written once; the transposed blocks go through LDS. Padding
+// columns of Gs are never written (the operand packer masks them).
+// ---------------------------------------------------------------------------
+struct CcvvAdjI8Args {
+  int nc, nv, ntv_s;
+  int64_t nqc;
+  double s;
+  int64_t slot_base;
+  int64_t W, Np;   // Gs: padded virtual orbitals per core orbital, row length
+};
+
+__device__ __forceinline__ void store_transposed128(const double (*T)[kI8Tile + 1], double *dst,
+                                                    int64_t ld, int rvalid, int cvalid) {
+  for (int k = threadIdx.x; k < kI8Tile * kI8Tile; k += kI8Threads) {
+    const int c = k / kI8Tile, r = k % kI8Tile;
+    if (r < rvalid && c < cvalid) dst[(int64_t)c * ld + r] = T[r][c];
+  }
+}
+
+__global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
+    const int8_t *__restrict__ S8, const double *__restrict__ sig,
+    const double *__restrict__ diag, const double *__restrict__ eps_c,
+    const double *__restrict__ eps_v, CcvvAdjI8Args a, double *__restrict__ xs, int *ctr,
+    double *deps_c, double *deps_v, double *ds, const double *__restrict__ gE,
+    double *__restrict__ Gs, double *slots) {
+  __shared__ __attribute__((aligned(16))) int8_t lds[kI8LdsRing];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int nt = a.ntv_s / 2;
+  const int64_t ldv = (int64_t)a.ntv_s * kPanel;
+  double *xw = xs + (int64_t)blockIdx.x * kSliceXsDoubles + threadIdx.x;
+  const int x = blockIdx.x % 8;
+  scalar_here(S8);
+  scalar_here(sig);
+  scalar_here(diag);
+  scalar_here(eps_c);
+  scalar_here(eps_v);
+  scalar_here(xs);
+  scalar_here(ctr);
+  scalar_here(Gs);
+  scalar_here(slots);
+  scalar_here(a.nqc);
+  scalar_here(a.ntv_s);
+  scalar_here(a.s);
+  scalar_here(a.W);
+  scalar_here(a.Np);
+  double (*T)[kI8Tile + 1] = reinterpret_cast<double (*)[kI8Tile + 1]>(lds);
+  double *rsum = reinterpret_cast<double *>(lds) + kI8Tile * (kI8Tile + 1);
+  double *csum = rsum + kI8Tile;
+  double *red = reinterpret_cast<double *>(lds);
+  int *next = reinterpret_cast<int *>(lds + kI8LdsRing - sizeof(int));
+  static_assert((kI8Tile * (kI8Tile + 3)) * sizeof(double) + sizeof(int) <= kI8LdsRing, "LDS");
+  CcvvWork c;
+  int64_t slot;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) *next = atomicAdd(ctr + x, 1);
+    __syncthreads();
+    const int64_t kk = *next;
+    if (!decode_ccvv_i8(kk, x, a.nc, nt, c, slot)) break;
+    double v[kI8Out];
+    ccvv_i8_item(S8, sig, c, a.nqc, a.ntv_s, lds, xw, wr, wc, lane, v);
+    if (c.cls == 1) {
+#pragma unroll
+      for (int q = 0; q < kI8Blocks; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) T[i8_row(wr, q, lane, r)][i8_col(wc, q, lane)] = v[q * 16 + r];
+    }
+    if (threadIdx.x < 2 * kI8Tile) rsum[threadIdx.x] = 0.0;   // rsum and csum
+    __syncthreads();
+    const double gE0 = gE[0];
+    const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
+    const double eij = eps_c[c.i] + eps_c[c.j];
+    const int64_t rowI = (int64_t)c.i * a.W, rowJ = (int64_t)c.j * a.W;
+    double e_part = 0.0, d_part = 0.0, s_part = 0.0;
+    double g1v[kI8Out], g2v[kI8Out];
+#pragma unroll
+    for (int q = 0; q < kI8Blocks; ++q) {
+      const int cl = i8_col(wc, q, lane);
+      const int bcol = c.B * kI8Tile + cl;
+      const bool bok = bcol < a.nv;
+      const double eb = bok ? eps_v[bcol] : 0.0;
+      double cs = 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int rl = i8_row(wr, q, lane, r);
+        const int arow = c.A * kI8Tile + rl;
+        g1v[q * 16 + r] = 0.0;
+        g2v[q * 16 + r] = 0.0;
+        if (!bok || arow >= a.nv) continue;
+        double xv, yv;
+        if (c.cls == 0) {
+          xv = xw[(q * 16 + r) * kI8Threads];
+          yv = v[q * 16 + r];
+        } else if (c.cls == 1) {
+          xv = v[q * 16 + r];
+          yv = T[cl][rl];
+        } else {
+          xv = yv = v[q * 16 + r];
+          if (c.cls == 3 && arow == bcol) xv = yv = diag[c.i * ldv + arow];
+        }
+        double R, dRD, dRs;
+        reg_R_grad(eij - (eps_v[arow] + eb), a.s, R, dRD, dRs);
+        const double P = w * (xv * xv - xv * yv + yv * yv);
+        e_part += R * P;
+        const double dd = P * dRD;
+        d_part += dd;
+        cs += dd;
+        atomicAdd(&rsum[rl], dd);
+        s_part += P * dRs;
+        const double g1 = 4.0 * gE0 * R * (2.0 * xv - yv);
+        const double g2 = 4.0 * gE0 * R * (2.0 * yv - xv);
+        g1v[q * 16 + r] = g1;
+        g2v[q * 16 + r] = g2;
+        Gs[(rowI + arow) * a.Np + rowJ + bcol] = g1;
+        if (c.cls <= 1) Gs[(rowJ + arow) * a.Np + rowI + bcol] = g2;
+      }
+      if (cs != 0.0) atomicAdd(&csum[cl], cs);
+    }
+    const int rvalid = min(kI8Tile, a.nv - c.A * kI8Tile);
+    const int cvalid = min(kI8Tile, a.nv - c.B * kI8Tile);
+    if (c.cls == 0 || c.cls == 2) {
+      // transposed blocks: Gs[(j,B)][(i,A)] = g1^T, then (class 0) Gs[(i,B)][(j,A)] = g2^T
+      __syncthreads();   // class 1 has read T
+#pragma unroll
+      for (int q = 0; q < kI8Blocks; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) T[i8_row(wr, q, lane, r)][i8_col(wc, q, lane)] = g1v[q * 16 + r];
+      __syncthreads();
+      store_transposed128(T, Gs + (rowJ + c.B * kI8Tile) * a.Np + rowI + c.A * kI8Tile, a.Np,
+                          rvalid, cvalid);
+      if (c.cls == 0) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kI8Blocks; ++q)
+#pragma unroll
+          for (int r = 0; r < 16; ++r)
+            T[i8_row(wr, q, lane, r)][i8_col(wc, q, lane)] = g2v[q * 16 + r];
+        __syncthreads();
+        store_transposed128(T, Gs + (rowI + c.B * kI8Tile) * a.Np + rowJ + c.A * kI8Tile, a.Np,
+                            rvalid, cvalid);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < kI8Tile) {
+      const int t = threadIdx.x;
+      if (t < rvalid) atomicAdd(&deps_v[c.A * kI8Tile + t], -gE0 * rsum[t]);
+      if (t < cvalid) atomicAdd(&deps_v[c.B * kI8Tile + t], -gE0 * csum[t]);
+    }
+    const double tE = block_sum_n<8>(e_part, red);
+    __syncthreads();
+    const double tD = block_sum_n<8>(d_part, red);
+    __syncthreads();
+    const double tS = block_sum_n<8>(s_part, red);
+    if (threadIdx.x == 0) {
+      slots[a.slot_base + slot] = tE;
+      atomicAdd(&deps_c[c.i], gE0 * tD);
+      atomicAdd(&deps_c[c.j], gE0 * tD);
+      atomicAdd(ds, gE0 * tS);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -229,8 +403,34 @@ static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, cons
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                  hipStream_t st) {
   hipError_t e;
-  // adjoint tiles Gs, G2, G3 and the eps / s gradients, as in the FP64 backward
-  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, st)) != hipSuccess) return e;
+  // gradients of eps and s cleared, G2 and G3 (with their eps / s parts) from
+  // the FP64 adjoint tiles
+  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, false, st)) != hipSuccess) return e;
+  if (pl.terms & 1) {
+    // Gs and the CCVV eps / s parts from the slice-path adjoint tiles
+    if ((e = launch_slices(pl, in, ws, false, st)) != hipSuccess) return e;
+    CcvvAdjI8Args a;
+    a.nc = (int)pl.nc;
+    a.nv = (int)pl.nv;
+    a.ntv_s = (int)pl.ntv_s;
+    a.nqc = pl.nqc;
+    a.s = pl.s;
+    a.slot_base = pl.slot_base[0];
+    a.W = pl.ntv * kPanel;
+    a.Np = pl.nc * a.W;
+    const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv_s / 2);
+    const int64_t grid = items < kSlicePersistWG ? items : kSlicePersistWG;
+    double *xs = ws_d(ws, pl.off_xs);
+    int *ctr = reinterpret_cast<int *>(xs + (size_t)kSlicePersistWG * kSliceXsDoubles);
+    if ((e = launch_zero(reinterpret_cast<double *>(ctr), 4, st)) != hipSuccess) return e;
+    timer_begin("ccvv_adj_i8", st);
+    hipLaunchKernelGGL(ccvv_adj_i8_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st,
+                       ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
+                       in.eps_c, in.eps_v, a, xs, ctr, o.deps_c, o.deps_v, o.ds, o.gE,
+                       ws_d(ws, pl.off_gs), ws_d(ws, pl.off_slots));
+    timer_end(st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
   const int64_t W = pl.ntv * kPanel;             // padded virtual orbitals per orbital
   const int64_t Np = pl.nc * W, N2 = pl.na * W, N3 = pl.nc * kActPanel;

@@ -100,73 +100,6 @@ __global__ __launch_bounds__(256) void slice_pack_kernel(const double *__restric
   }
 }
 
-// Blocked walk (kTileBlock x kTileBlock blocks) over the strictly ordered
-// tile pairs A < B of nt tiles.
-__device__ __forceinline__ void decode_tile_blocked_lt(int64_t t, int nt, int &A, int &B) {
-  const int nb = (nt + kTileBlock - 1) / kTileBlock;
-  for (int ba = 0; ba < nb; ++ba) {
-    const int na_ = (ba == nb - 1) ? nt - ba * kTileBlock : kTileBlock;
-    for (int bb = ba; bb < nb; ++bb) {
-      const int nb_ = (bb == nb - 1) ? nt - bb * kTileBlock : kTileBlock;
-      const int64_t size = (ba == bb) ? (int64_t)na_ * (na_ - 1) / 2 : (int64_t)na_ * nb_;
-      if (t < size) {
-        int a0, b0;
-        if (ba == bb) {
-          decode_pair_lt(t, na_, a0, b0);
-        } else {
-          a0 = (int)(t / nb_);
-          b0 = (int)(t % nb_);
-        }
-        A = ba * kTileBlock + a0;
-        B = bb * kTileBlock + b0;
-        return;
-      }
-      t -= size;
-    }
-  }
-  A = B = 0;   // not reached for t < nt (nt - 1) / 2
-}
-
-// Work list of the int8 CCVV kernel on XCD x (pairs p = x mod 8; pairs
-// 0 .. P0-1 are the i < j pairs in order, P0 + i the self pairs), item kk:
-// first every class-0 item (two products each) of its i < j pairs, then the
-// single-product items (class 1 of its i < j pairs, classes 2 and 3 of its
-// self pairs). The workgroups of one XCD take consecutive items, so each
-// round holds items of equal cost that share panels and stay in step along
-// the auxiliary index. slot = p T + (index of A <= B). Returns false past
-// the end of the list.
-__device__ __forceinline__ bool decode_ccvv_i8(int64_t kk, int x, int nc, int nt, CcvvWork &c,
-                                               int64_t &slot) {
-  const int64_t P0 = (int64_t)nc * (nc - 1) / 2;
-  const int64_t T0 = (int64_t)nt * (nt - 1) / 2, T = (int64_t)nt * (nt + 1) / 2;
-  const int64_t nlt = (P0 > x) ? (P0 - x + 7) / 8 : 0;
-  const int64_t first_eq = P0 + ((x - P0 % 8) + 8) % 8;   // first self pair on this XCD
-  const int64_t neq = (first_eq < P0 + nc) ? (P0 + nc - first_eq + 7) / 8 : 0;
-  int64_t p;
-  if (kk < nlt * T0) {
-    p = 8 * (kk / T0) + x;
-    decode_tile_blocked_lt(kk % T0, nt, c.A, c.B);
-    c.cls = 0;
-  } else if ((kk -= nlt * T0) < nlt * nt) {
-    p = 8 * (kk / nt) + x;
-    c.A = c.B = (int)(kk % nt);
-    c.cls = 1;
-  } else if ((kk -= nlt * nt) < neq * T) {
-    p = first_eq + 8 * (kk / T);
-    decode_tile_blocked(kk % T, nt, c.A, c.B);
-    c.cls = (c.A == c.B) ? 3 : 2;
-  } else {
-    return false;
-  }
-  if (p < P0) {
-    decode_pair_lt(p, nc, c.i, c.j);
-  } else {
-    c.i = c.j = (int)(p - P0);
-  }
-  slot = p * T + (int64_t)c.A * nt - (int64_t)c.A * (c.A - 1) / 2 + (c.B - c.A);
-  return true;
-}
-
 // ---------------------------------------------------------------------------
 // CCVV on slices. Work items are (core pair i <= j, 128-tile pair A <= B)
 // in the order of decode_ccvv_i8; classes 0: i<j, A<B (x and y = K^{ji}[A,B]),
@@ -226,40 +159,8 @@ __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__
     __syncthreads();
     const int64_t kk = *next;
     if (!decode_ccvv_i8(kk, x, a.nc, nt, c, slot)) break;
-    const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
-    const double *sri = sig + c.i * ldv + c.A * kI8Tile, *scj = sig + c.j * ldv + c.B * kI8Tile;
-    const double *srj = sig + c.j * ldv + c.A * kI8Tile, *sci = sig + c.i * ldv + c.B * kI8Tile;
-    i16v ac[kI8Blocks][kSlices];
-    // pass 0: x = K^{ij}[A,B] (rows from i's A panels, columns from j's B
-    // panels); class 0 parks x and takes pass 1: y[a][b] = (ja|ib)
-    const int npass = (c.cls == 0) ? 2 : 1;
-    for (int pass = 0; pass < npass; ++pass) {
-      const int8_t *r0 = slice_panel(S8, pass ? c.j : c.i, 2 * c.A, a.ntv_s, a.nqc);
-      const int8_t *c0 = slice_panel(S8, pass ? c.i : c.j, 2 * c.B, a.ntv_s, a.nqc);
-      i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nqc, lds, ac, wr, wc, lane);
-      if (pass + 1 < npass) {
-#pragma unroll
-        for (int q = 0; q < kI8Blocks; ++q) {
-          double v[16];
-          i8_block_values(ac[q], sri, scj, wr, wc, q, lane, v);
-#pragma unroll
-          for (int r = 0; r < 16; ++r) xw[(q * 16 + r) * kI8Threads] = v[r];
-        }
-      }
-    }
-    // FP64 values of the last product (class 0: y, else x); the level
-    // accumulators die here, before the exponentials of the epilogue
     double v[kI8Out];
-#pragma unroll
-    for (int q = 0; q < kI8Blocks; ++q) {
-      double t[16];
-      if (c.cls == 0)
-        i8_block_values(ac[q], srj, sci, wr, wc, q, lane, t);
-      else
-        i8_block_values(ac[q], sri, scj, wr, wc, q, lane, t);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[q * 16 + r] = t[r];
-    }
+    ccvv_i8_item(S8, sig, c, a.nqc, a.ntv_s, lds, xw, wr, wc, lane, v);
     double (*T)[kI8Tile + 1] = reinterpret_cast<double (*)[kI8Tile + 1]>(lds);
     if (c.cls == 1) {
       // y = x^T through LDS (the ring is free after the last barrier)
@@ -490,6 +391,15 @@ static hipError_t slice_one(const double *B, int64_t nrow, const Plan &pl, doubl
                      0, st, B, nrow, pl.nv, pl.naux, pl.ntv_s, pl.nqc, sig, S8);
   timer_end(st);
   return hipGetLastError();
+}
+
+hipError_t launch_slices(const Plan &pl, const Inputs &in, void *ws, bool with_av,
+                         hipStream_t st) {
+  hipError_t e = slice_one(in.B_cv, pl.nc, pl, ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
+                           ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_scr), st);
+  if (e != hipSuccess || !with_av) return e;
+  return slice_one(in.B_av, pl.na, pl, ws_d(ws, pl.off_siga), nullptr, ws_b(ws, pl.off_s8a),
+                   ws_d(ws, pl.off_scr), st);
 }
 
 template <int NA>
