@@ -120,7 +120,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   pl.nqc = ceil_div(pl.naux, 32);
   // forward CAVV (both precisions) goes through batches of (me|uf) integrals
   // of at most 512 MB
-  const bool xbatch = has_cavv && !pl.with_grad;
+  const bool xbatch = has_cavv && (!pl.with_grad || split);
   if (xbatch) {
     const int64_t per_m = pl.na * pl.xld * pl.xld * 8;
     pl.cavv_mb = ((int64_t)512 << 20) / per_m;
@@ -129,8 +129,8 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   } else {
     pl.cavv_mb = 0;
   }
-  pl.n_cavv = !has_cavv      ? 0
-              : pl.with_grad ? pl.nc * (tri_off(ntw) + ntw)
+  pl.n_cavv = !has_cavv                ? 0
+              : pl.with_grad && !split ? pl.nc * (tri_off(ntw) + ntw)
                              : pl.nc * (ceil_div(pl.nv, 16) * (ceil_div(pl.nv, 16) + 1) / 2);
   pl.ccav_cols = round_up(pl.nc * pl.na, 16);
   // forward: one slot per (m <= n, 256 virtual orbitals); adjoint: per (m <= n, 64-tile)
@@ -149,7 +149,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   if (fp64_tiles || has_ccav)
     off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.ntv * pl.naux_p * kPanel));
   pl.off_pav = off;
-  if (fp64_tiles && has_cavv)
+  if (!split && has_cavv)
     off = align256(off + sizeof(double) * (size_t)(pl.na * pl.ntv * pl.naux_p * kPanel));
   pl.off_pca = off;
   pl.off_j = off;

@@ -628,10 +628,10 @@ static hipError_t gemm(const Plan &pl, const double *Apan, int PW, int64_t npan,
 
 template <int NA>
 static hipError_t launch_adj_act(const Plan &pl, const Inputs &in, const GradOut &g, void *ws,
-                                 hipStream_t st) {
+                                 int mask, hipStream_t st) {
   double *slots = ws_d(ws, pl.off_slots);
   const int64_t N2 = pl.na * pl.ntv * kPanel;
-  if ((pl.terms & 2)) {
+  if ((pl.terms & mask & 2)) {
     CavvAdjArgs a;
     a.nc = (int)pl.nc;
     a.na = (int)pl.na;
@@ -658,7 +658,7 @@ static hipError_t launch_adj_act(const Plan &pl, const Inputs &in, const GradOut
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if ((pl.terms & 4)) {
+  if ((pl.terms & mask & 4)) {
     CcavAdjArgs a;
     a.nc = (int)pl.nc;
     a.na = (int)pl.na;
@@ -684,7 +684,7 @@ hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st) { return zero_
 // Adjoint tiles Gs, G2, G3 (recomputed integrals, FP64) with the energies
 // and the orbital-energy and flow-parameter gradients.
 hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const BwdOut &o,
-                                     void *ws, bool with_ccvv, hipStream_t st) {
+                                     void *ws, int mask, hipStream_t st) {
   hipError_t e;
   GradOut g{o.deps_c, o.deps_a, o.deps_v, o.ds, o.gE};
   if ((e = zero_fill(o.deps_c, pl.nc, st)) != hipSuccess) return e;
@@ -692,9 +692,9 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
   if ((e = zero_fill(o.deps_v, pl.nv, st)) != hipSuccess) return e;
   if ((e = zero_fill(o.ds, 1, st)) != hipSuccess) return e;
   if ((e = launch_pack_fp64(pl, in, ws, st)) != hipSuccess) return e;
-  const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
+  const bool cavv = (pl.terms & mask & 2) && pl.na > 0, ccav = (pl.terms & mask & 4) && pl.na > 0;
   const int64_t Np = pl.nc * pl.ntv * kPanel;
-  if ((pl.terms & 1) && with_ccvv) {
+  if (pl.terms & mask & 1) {
     CcvvAdjArgs a;
     a.nc = (int)pl.nc;
     a.nv = (int)pl.nv;
@@ -721,14 +721,14 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
   }
   if (cavv || ccav) {
     switch (pl.na) {
-      case 1: e = launch_adj_act<1>(pl, in, g, ws, st); break;
-      case 2: e = launch_adj_act<2>(pl, in, g, ws, st); break;
-      case 3: e = launch_adj_act<3>(pl, in, g, ws, st); break;
-      case 4: e = launch_adj_act<4>(pl, in, g, ws, st); break;
-      case 5: e = launch_adj_act<5>(pl, in, g, ws, st); break;
-      case 6: e = launch_adj_act<6>(pl, in, g, ws, st); break;
-      case 7: e = launch_adj_act<7>(pl, in, g, ws, st); break;
-      case 8: e = launch_adj_act<8>(pl, in, g, ws, st); break;
+      case 1: e = launch_adj_act<1>(pl, in, g, ws, mask, st); break;
+      case 2: e = launch_adj_act<2>(pl, in, g, ws, mask, st); break;
+      case 3: e = launch_adj_act<3>(pl, in, g, ws, mask, st); break;
+      case 4: e = launch_adj_act<4>(pl, in, g, ws, mask, st); break;
+      case 5: e = launch_adj_act<5>(pl, in, g, ws, mask, st); break;
+      case 6: e = launch_adj_act<6>(pl, in, g, ws, mask, st); break;
+      case 7: e = launch_adj_act<7>(pl, in, g, ws, mask, st); break;
+      case 8: e = launch_adj_act<8>(pl, in, g, ws, mask, st); break;
       default: e = hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -739,7 +739,7 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st) {
   hipError_t e;
-  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, true, st)) != hipSuccess) return e;
+  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, kAllTerms, st)) != hipSuccess) return e;
   const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
   const int64_t Np = pl.nc * pl.ntv * kPanel;
   // ---- adjoint GEMMs ----

@@ -356,7 +356,7 @@ hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStrea
   hipError_t e = pack_one(in.B_cv, ws_d(ws, pl.off_pcv), pl.nc, pl.nv, pl.naux, pl.naux_p,
                           pl.ntv, kPanel, st);
   if (e != hipSuccess) return e;
-  if (pl.na > 0 && (pl.terms & 2) && (pl.precision == 0 || pl.with_grad)) {
+  if (pl.na > 0 && (pl.terms & 2) && pl.precision == 0) {
     e = pack_one(in.B_av, ws_d(ws, pl.off_pav), pl.na, pl.nv, pl.naux, pl.naux_p, pl.ntv,
                  kPanel, st);
     if (e != hipSuccess) return e;

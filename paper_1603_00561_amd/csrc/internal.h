@@ -12,6 +12,8 @@ namespace dsrg {
 // chunk that the contraction kernels stage through LDS per step.
 constexpr int kPanel = 64;
 constexpr int kChunk = 16;
+// Term mask selecting all three terms.
+constexpr int kAllTerms = 7;
 // Column width of a packed active-orbital panel (na padded up to this).
 constexpr int kActPanel = 16;
 // Persistent workgroups of the int8 CCVV kernel, each with an FP64 slot of
@@ -88,13 +90,15 @@ hipError_t launch_zero(double *p, int n, hipStream_t st);
 hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,
                            hipStream_t st);
+// (me|uf) integral batch Xb for core orbitals m0 .. m0+mb-1 from the slices
+hipError_t launch_cavv_x_split(const Plan &pl, void *ws, int m0, int mb, hipStream_t st);
 // int8 slices of B_cv (with the FP64 diagonal) and, if with_av, of B_av
 hipError_t launch_slices(const Plan &pl, const Inputs &in, void *ws, bool with_av,
                          hipStream_t st);
 // ---- adjoint (fp64_bwd.hip, split_bwd.hip) ----
 hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st);
 hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const BwdOut &o,
-                                     void *ws, bool with_ccvv, hipStream_t st);
+                                     void *ws, int mask, hipStream_t st);
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st);
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,

@@ -343,6 +343,173 @@ __global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
 }
 
 // ---------------------------------------------------------------------------
+// CAVV adjoint tiles from a batch of integrals X^{mu}[e][f] = (me|uf) (the
+// slice-path producer). One workgroup per (m, 16-block pair E <= F); thread
+// (e, f) of E x F takes the element pair (e, f), (f, e). With X_u = (me|uf),
+// Y_u = (mf|ue), S_u, R1_u at D^{mu}_{ef} (symmetric in e, f):
+//   A_w  = sum_v Gamma_wv R1_v (2X_v - Y_v),  A'_w = sum_v Gamma_wv R1_v (2Y_v - X_v)
+//   C_w  = sum_u Gamma_uw S_u X_u,            C'_w = sum_u Gamma_uw S_u Y_u
+//   E   += S_w (X_w A_w + Y_w A'_w)
+//   dL/d(me|wf) = gE1 [S_w A_w  + R1_w (2C_w  - C'_w)]   -> G2[(m,e)][(w,f)]
+//   dL/d(mf|we) = gE1 [S_w A'_w + R1_w (2C'_w - C_w )]   -> G2[(m,f)][(w,e)]
+//   dE/dD^{mw}_{ef} = X_w A_w S'_w + (2X_w - Y_w) C_w R1'_w + (the same with
+//   X <-> Y, A <-> A', C <-> C')
+// Diagonal block pairs (E = F) visit each pair twice: weight 1/2 in the sums,
+// and only the first G2 entry is written (the mirrored thread writes the other).
+// ---------------------------------------------------------------------------
+constexpr int kAdjT = 16;
+
+struct CavvAdjEpiArgs {
+  int nv, nt16;
+  int64_t ld;      // row length of the integral batch
+  double s;
+  int m0;
+  int64_t W, N2;   // G2: padded virtual orbitals per orbital, row length
+  int64_t slot_base;
+};
+
+template <int NA>
+__global__ __launch_bounds__(256) void cavv_adj_epi_kernel(
+    const double *__restrict__ Xb, const double *__restrict__ eps_c,
+    const double *__restrict__ eps_a, const double *__restrict__ eps_v,
+    const double *__restrict__ gamma1, CavvAdjEpiArgs a, double *deps_c, double *deps_a,
+    double *deps_v, double *ds, const double *__restrict__ gE, double *__restrict__ G2,
+    double *slots) {
+  __shared__ double Xs[NA][2][kAdjT][kAdjT + 1];
+  __shared__ double rs[kAdjT], cs[kAdjT], as_[NA], red[4];
+  const int64_t T = (int64_t)a.nt16 * (a.nt16 + 1) / 2;
+  const int ml = (int)(blockIdx.x / T);
+  int E, F;
+  decode_pair_le(blockIdx.x % T, a.nt16, E, F);
+  const int el = threadIdx.x >> 4, fl = threadIdx.x & 15;
+  const int64_t ld = a.ld;
+  const double *X = Xb + (int64_t)ml * NA * ld * ld;
+  const int e0 = E * kAdjT, f0 = F * kAdjT;
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const double *Xu = X + (int64_t)u * ld * ld;
+    Xs[u][0][el][fl] = Xu[(int64_t)(e0 + el) * ld + f0 + fl];
+    Xs[u][1][el][fl] = Xu[(int64_t)(f0 + el) * ld + e0 + fl];
+  }
+  if (threadIdx.x < kAdjT) {
+    rs[threadIdx.x] = 0.0;
+    cs[threadIdx.x] = 0.0;
+  }
+  if (threadIdx.x < NA) as_[threadIdx.x] = 0.0;
+  double Gm[NA][NA], ea[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    ea[u] = eps_a[u];
+#pragma unroll
+    for (int v = 0; v < NA; ++v) Gm[u][v] = gamma1[u * NA + v];
+  }
+  const int m = a.m0 + ml;
+  const double em = eps_c[m];
+  const double gE1 = gE[1];
+  const double wgt = (E == F) ? 0.5 : 1.0;
+  __syncthreads();
+  const int e = e0 + el, f = f0 + fl;
+  double e_part = 0.0, d_part = 0.0, s_part = 0.0;
+  if (e < a.nv && f < a.nv) {
+    double Xv[NA], Yv[NA], S[NA], R1[NA], dS[NA], dR1[NA], sS[NA], sR1[NA];
+    const double base = em - (eps_v[e] + eps_v[f]);
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      Xv[u] = Xs[u][0][el][fl];
+      Yv[u] = Xs[u][1][fl][el];
+      reg_S_R1_grad(base + ea[u], a.s, S[u], R1[u], dS[u], dR1[u], sS[u], sR1[u]);
+    }
+    double Av[NA], Ap[NA], Cv[NA], Cp[NA];
+#pragma unroll
+    for (int w = 0; w < NA; ++w) {
+      double sa = 0.0, sp = 0.0, ca = 0.0, cp = 0.0;
+#pragma unroll
+      for (int v = 0; v < NA; ++v) {
+        sa += Gm[w][v] * R1[v] * (2.0 * Xv[v] - Yv[v]);
+        sp += Gm[w][v] * R1[v] * (2.0 * Yv[v] - Xv[v]);
+        ca += Gm[v][w] * S[v] * Xv[v];
+        cp += Gm[v][w] * S[v] * Yv[v];
+      }
+      Av[w] = sa;
+      Ap[w] = sp;
+      Cv[w] = ca;
+      Cp[w] = cp;
+    }
+    double *Gn = G2 + ((int64_t)m * a.W + e) * a.N2 + f;   // + w W
+    double *Gt = G2 + ((int64_t)m * a.W + f) * a.N2 + e;
+#pragma unroll
+    for (int w = 0; w < NA; ++w) {
+      const double Wv = 2.0 * Xv[w] - Yv[w], Wp = 2.0 * Yv[w] - Xv[w];
+      Gn[(int64_t)w * a.W] = gE1 * (S[w] * Av[w] + R1[w] * (2.0 * Cv[w] - Cp[w]));
+      if (E != F) Gt[(int64_t)w * a.W] = gE1 * (S[w] * Ap[w] + R1[w] * (2.0 * Cp[w] - Cv[w]));
+      e_part += wgt * S[w] * (Xv[w] * Av[w] + Yv[w] * Ap[w]);
+      const double dd = wgt * (Xv[w] * Av[w] * dS[w] + Wv * Cv[w] * dR1[w] +
+                               Yv[w] * Ap[w] * dS[w] + Wp * Cp[w] * dR1[w]);
+      s_part += wgt * (Xv[w] * Av[w] * sS[w] + Wv * Cv[w] * sR1[w] + Yv[w] * Ap[w] * sS[w] +
+                       Wp * Cp[w] * sR1[w]);
+      d_part += dd;
+      atomicAdd(&as_[w], dd);
+    }
+    atomicAdd(&rs[el], d_part);
+    atomicAdd(&cs[fl], d_part);
+  }
+  __syncthreads();
+  if (threadIdx.x < kAdjT) {
+    const int t = threadIdx.x;
+    if (e0 + t < a.nv) atomicAdd(&deps_v[e0 + t], -gE1 * rs[t]);
+    if (f0 + t < a.nv) atomicAdd(&deps_v[f0 + t], -gE1 * cs[t]);
+  }
+  if (threadIdx.x < NA) atomicAdd(&deps_a[threadIdx.x], gE1 * as_[threadIdx.x]);
+  const double tE = block_sum(e_part, red);
+  __syncthreads();
+  const double tD = block_sum(d_part, red);
+  __syncthreads();
+  const double tS = block_sum(s_part, red);
+  if (threadIdx.x == 0) {
+    slots[a.slot_base + blockIdx.x] = tE;
+    atomicAdd(&deps_c[m], gE1 * tD);
+    atomicAdd(ds, gE1 * tS);
+  }
+}
+
+template <int NA>
+static hipError_t cavv_adj_epi_na(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                  int m0, int mb, hipStream_t st) {
+  CavvAdjEpiArgs a;
+  a.nv = (int)pl.nv;
+  a.nt16 = (int)ceil_div(pl.nv, kAdjT);
+  a.ld = pl.xld;
+  a.s = pl.s;
+  a.m0 = m0;
+  a.W = pl.ntv * kPanel;
+  a.N2 = pl.na * a.W;
+  const int64_t T = (int64_t)a.nt16 * (a.nt16 + 1) / 2;
+  a.slot_base = pl.slot_base[1] + (int64_t)m0 * T;
+  timer_begin("cavv_adj_epi", st);
+  hipLaunchKernelGGL((cavv_adj_epi_kernel<NA>), dim3((unsigned)(mb * T)), dim3(256), 0, st,
+                     ws_d(ws, pl.off_xb), in.eps_c, in.eps_a, in.eps_v, in.gamma1, a, o.deps_c,
+                     o.deps_a, o.deps_v, o.ds, o.gE, ws_d(ws, pl.off_g2),
+                     ws_d(ws, pl.off_slots));
+  timer_end(st);
+  return hipGetLastError();
+}
+
+static hipError_t cavv_adj_epi(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                               int m0, int mb, hipStream_t st) {
+  switch (pl.na) {
+    case 1: return cavv_adj_epi_na<1>(pl, in, o, ws, m0, mb, st);
+    case 2: return cavv_adj_epi_na<2>(pl, in, o, ws, m0, mb, st);
+    case 3: return cavv_adj_epi_na<3>(pl, in, o, ws, m0, mb, st);
+    case 4: return cavv_adj_epi_na<4>(pl, in, o, ws, m0, mb, st);
+    case 5: return cavv_adj_epi_na<5>(pl, in, o, ws, m0, mb, st);
+    case 6: return cavv_adj_epi_na<6>(pl, in, o, ws, m0, mb, st);
+    case 7: return cavv_adj_epi_na<7>(pl, in, o, ws, m0, mb, st);
+    case 8: return cavv_adj_epi_na<8>(pl, in, o, ws, m0, mb, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static OpMap op_map(const double *base, int64_t rblk, int64_t rval, int64_t ldrb, int64_t ldr,
@@ -403,12 +570,21 @@ static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, cons
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                  hipStream_t st) {
   hipError_t e;
-  // gradients of eps and s cleared, G2 and G3 (with their eps / s parts) from
-  // the FP64 adjoint tiles
-  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, false, st)) != hipSuccess) return e;
+  const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
+  // gradients of eps and s cleared, G3 (with its eps / s parts) from the FP64
+  // adjoint tiles
+  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, 4, st)) != hipSuccess) return e;
+  if ((e = launch_slices(pl, in, ws, cavv, st)) != hipSuccess) return e;
+  if (cavv) {
+    // G2 and the CAVV eps / s parts from batches of slice-path integrals
+    for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
+      const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
+      if ((e = launch_cavv_x_split(pl, ws, (int)m0, mb, st)) != hipSuccess) return e;
+      if ((e = cavv_adj_epi(pl, in, o, ws, (int)m0, mb, st)) != hipSuccess) return e;
+    }
+  }
   if (pl.terms & 1) {
     // Gs and the CCVV eps / s parts from the slice-path adjoint tiles
-    if ((e = launch_slices(pl, in, ws, false, st)) != hipSuccess) return e;
     CcvvAdjI8Args a;
     a.nc = (int)pl.nc;
     a.nv = (int)pl.nv;
@@ -431,7 +607,6 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
   const int64_t W = pl.ntv * kPanel;             // padded virtual orbitals per orbital
   const int64_t Np = pl.nc * W, N2 = pl.na * W, N3 = pl.nc * kActPanel;
   const int64_t N3p = round_up(N3, kQC);

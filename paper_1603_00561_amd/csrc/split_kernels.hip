@@ -437,6 +437,22 @@ hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, i
   }
 }
 
+hipError_t launch_cavv_x_split(const Plan &pl, void *ws, int m0, int mb, hipStream_t st) {
+  CavvXArgs xa;
+  xa.na = (int)pl.na;
+  xa.ntv_s = (int)pl.ntv_s;
+  xa.nqc = pl.nqc;
+  xa.m0 = m0;
+  xa.mb = mb;
+  timer_begin("cavv_i8_x", st);
+  hipLaunchKernelGGL(cavv_i8_x_kernel,
+                     dim3((unsigned)fulltile_grid((int64_t)mb * pl.na, pl.ntv_s / 2)),
+                     dim3(kI8Threads), 0, st, ws_b(ws, pl.off_s8c), ws_b(ws, pl.off_s8a),
+                     ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_siga), xa, ws_d(ws, pl.off_xb));
+  timer_end(st);
+  return hipGetLastError();
+}
+
 hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st) {
   hipError_t e;
   double *slots = ws_d(ws, pl.off_slots), *acc = ws_d(ws, pl.off_acc);
@@ -477,18 +493,7 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
   if (cavv) {
     for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
       const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
-      CavvXArgs xa;
-      xa.na = (int)pl.na;
-      xa.ntv_s = (int)pl.ntv_s;
-      xa.nqc = pl.nqc;
-      xa.m0 = (int)m0;
-      xa.mb = mb;
-      timer_begin("cavv_i8_x", st);
-      hipLaunchKernelGGL(cavv_i8_x_kernel, dim3((unsigned)fulltile_grid((int64_t)mb * pl.na, pl.ntv_s / 2)), dim3(kI8Threads), 0, st,
-                         ws_b(ws, pl.off_s8c), ws_b(ws, pl.off_s8a), ws_d(ws, pl.off_sigc),
-                         ws_d(ws, pl.off_siga), xa, ws_d(ws, pl.off_xb));
-      timer_end(st);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
+      if ((e = launch_cavv_x_split(pl, ws, (int)m0, mb, st)) != hipSuccess) return e;
       e = launch_cavv_epi(pl, in, ws, (int)m0, mb, st);
       if (e != hipSuccess) return e;
     }
