@@ -60,7 +60,11 @@ def cpu_baseline(p, budget_s=20.0):
     t_used += dt
     parts.append(f"CCVV over core pairs of {nc_s}/{nc} core orbitals")
     if na > 0 and t_used < budget_s:
-        m_s = max(1, min(nc, int(nc * (budget_s - t_used) / max(budget_s, 1e-9) * 0.5)))
+        # one core orbital first, to size the sample to the rest of the budget
+        t = time.perf_counter()
+        O.energy_cavv(p.B_cv[:, :1], p.B_av, p.eps_c[:1], p.eps_a, p.eps_v, p.gamma1, p.s)
+        t1 = max(time.perf_counter() - t, 1e-6)
+        m_s = max(1, min(nc, int((budget_s - t_used) / t1)))
         t = time.perf_counter()
         O.energy_cavv(p.B_cv[:, :m_s], p.B_av, p.eps_c[:m_s], p.eps_a, p.eps_v, p.gamma1, p.s)
         O.energy_ccav(p.B_cv[:, :m_s], p.B_ca[:, :m_s], p.eps_c[:m_s], p.eps_a, p.eps_v,
