@@ -16,10 +16,6 @@
 
 namespace dsrg {
 
-static inline double *ws_d(void *ws, size_t off) {
-  return reinterpret_cast<double *>(static_cast<char *>(ws) + off);
-}
-
 __global__ void zero_fill_kernel(double *p, int64_t n) {
   for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256)
     p[k] = 0.0;

@@ -335,10 +335,6 @@ __global__ void zero_kernel(double *p, int n) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static inline double *ws_d(void *ws, size_t off) {
-  return reinterpret_cast<double *>(static_cast<char *>(ws) + off);
-}
-
 static hipError_t pack_one(const double *B, double *P, int64_t nrow, int64_t ncol, int64_t naux,
                            int64_t naux_p, int64_t ntile, int width, hipStream_t st) {
   const int64_t total = nrow * ntile * naux_p * width;

@@ -10,13 +10,6 @@ namespace dsrg {
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef int i16v __attribute__((ext_vector_type(16)));
 
-static inline double *ws_d(void *ws, size_t off) {
-  return reinterpret_cast<double *>(static_cast<char *>(ws) + off);
-}
-static inline int8_t *ws_b(void *ws, size_t off) {
-  return reinterpret_cast<int8_t *>(static_cast<char *>(ws) + off);
-}
-
 // v_mfma_i32_32x32x32_i8: lane l supplies 16 bytes of row l % 32 of A (and of
 // column l % 32 of B) for the k-range 16 (l / 32) .. +15; result register r
 // of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].

@@ -24,6 +24,13 @@ constexpr int64_t kSliceXsDoubles = 512 * 32;
 constexpr size_t kSliceCounterBytes = 64;
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// typed views of a workspace section
+inline double *ws_d(void *ws, size_t off) {
+  return reinterpret_cast<double *>(static_cast<char *>(ws) + off);
+}
+inline int8_t *ws_b(void *ws, size_t off) {
+  return reinterpret_cast<int8_t *>(static_cast<char *>(ws) + off);
+}
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 
 // Everything the launchers need, derived once on the host from the problem.
