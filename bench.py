@@ -30,6 +30,10 @@ PEAK_TFLOPS = {"fp64": 78.6, "split_bf16": 2500.0, "ozaki": 5000.0}
 PEAK_HBM_GBS = 8000.0
 
 
+# int8 slice products per multiply-add of the slice path (four slices, levels <= 3)
+SLICE_PRODUCTS = 10.0
+
+
 def alg_flops(nc, na, nv, naux, terms=("ccvv", "cavv", "ccav")):
     f = {"ccvv": 2.0 * naux * (nc * (nc + 1) / 2) * nv * nv,
          "cavv": 2.0 * naux * nc * na * nv * nv,
@@ -188,15 +192,15 @@ def main():
             dom, unit, mult = "gemm_adj_fp64", "TFLOP/s", 1.0
         else:
             gm = per_kernel.get("gemm_adj_i8", [])
-            dom, unit, mult = "gemm_adj_i8", "TOP/s", 15.0
+            dom, unit, mult = "gemm_adj_i8", "TOP/s", SLICE_PRODUCTS
         avg[dom] = float(np.sum(gm)) / args.steps if gm else None
         Fparts = dict(Fparts)
         Fparts["ccvv"] = 2.0 / 3.0 * F
     elif args.precision == "fp64":
         dom, unit, mult = "ccvv_fp64", "TFLOP/s", 1.0
     else:
-        # int8 slices: 15 exact int8 products per algorithmic multiply-add
-        dom, unit, mult = "ccvv_i8", "TOP/s", 15.0
+        # int8 slices: SLICE_PRODUCTS exact int8 products per algorithmic multiply-add
+        dom, unit, mult = "ccvv_i8", "TOP/s", SLICE_PRODUCTS
     dom_ms = avg.get(dom)
     ach = mult * Fparts["ccvv"] / (dom_ms * 1e-3) / 1e12 if dom_ms else None
     peak = PEAK_TFLOPS[args.precision]

@@ -63,6 +63,13 @@ typedef enum {
   DSRG_SPLIT_BF16 = 1,  /* B = hi + lo in BF16, three products, FP32 accumulate  */
   DSRG_SPLIT_OZAKI = 2  /* error-free int8 slices of B, exact int32 accumulate   */
 } dsrg_precision;
+/* DSRG_SPLIT_BF16 returns DSRG_ERR_UNSUPPORTED (three BF16 products cannot
+ * reach 1e-6 Eh on these sizes). DSRG_SPLIT_OZAKI splits every column of B
+ * (a vector over the auxiliary index) into four int8 slices and keeps the
+ * ten slice products of levels <= 3; its int32 sums are exact for naux <=
+ * DSRG_DF_MAX_SLICE_NAUX (larger naux returns DSRG_ERR_UNSUPPORTED). Its
+ * gradient splits the longer adjoint contractions into segments. */
+#define DSRG_DF_MAX_SLICE_NAUX 33000
 
 /* Term mask bits (argument `terms`). */
 enum {

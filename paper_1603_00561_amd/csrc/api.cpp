@@ -81,15 +81,10 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
                 (long long)p->nc, (long long)p->nv, (long long)p->naux);
   if (precision == DSRG_SPLIT_BF16)
     return fail(DSRG_ERR_UNSUPPORTED, "precision %d is not available in this build", precision);
-  if (precision == DSRG_SPLIT_OZAKI && with_grad &&
-      p->nc * ceil_div(p->nv, kPanel) * kPanel > 100000)
+  if (precision == DSRG_SPLIT_OZAKI && p->naux > DSRG_DF_MAX_SLICE_NAUX)
     return fail(DSRG_ERR_UNSUPPORTED,
-                "nc * padded nv = %lld exceeds 100000, the longest int8 adjoint contraction",
-                (long long)(p->nc * ceil_div(p->nv, kPanel) * kPanel));
-  if (precision == DSRG_SPLIT_OZAKI && p->naux > 100000)
-    return fail(DSRG_ERR_UNSUPPORTED,
-                "naux = %lld exceeds 100000, beyond which int32 slice sums could overflow",
-                (long long)p->naux);
+                "naux = %lld exceeds %d, beyond which int32 slice sums could overflow",
+                (long long)p->naux, DSRG_DF_MAX_SLICE_NAUX);
 
   pl.nc = p->nc;
   pl.na = p->na;
@@ -119,11 +114,11 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   const bool has_ccav = (term_bits & DSRG_TERM_CCAV) && pl.na > 0;
   pl.nqc = ceil_div(pl.naux, 32);
   // forward CAVV (both precisions) goes through batches of (me|uf) integrals
-  // of at most 512 MB
+  // of at most 4 GiB (one batch up to nc = 23, na = 6, nv = 1100 and beyond)
   const bool xbatch = has_cavv && (!pl.with_grad || split);
   if (xbatch) {
     const int64_t per_m = pl.na * pl.xld * pl.xld * 8;
-    pl.cavv_mb = ((int64_t)512 << 20) / per_m;
+    pl.cavv_mb = ((int64_t)4 << 30) / per_m;
     if (pl.cavv_mb < 1) pl.cavv_mb = 1;
     if (pl.cavv_mb > pl.nc) pl.cavv_mb = pl.nc;
   } else {

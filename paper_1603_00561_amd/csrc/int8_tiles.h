@@ -23,7 +23,7 @@ __device__ __forceinline__ i16v mfma_i8(i4v a, i4v b, i16v c) {
 // column c; the two 16-byte halves of column c are swapped when (c >> 3) & 1
 // (bank-conflict-free fragment reads). sig[(p * ntv * 64) + e] = sigma.
 // ---------------------------------------------------------------------------
-constexpr int kSlices = 5;
+constexpr int kSlices = 4;
 constexpr int kQC = 32;                                  // auxiliary indices per chunk
 constexpr int kSlicePanelChunk = kSlices * kPanel * kQC; // bytes per (panel, chunk)
 
@@ -32,21 +32,21 @@ constexpr int kSlicePanelChunk = kSlices * kPanel * kQC; // bytes per (panel, ch
 // K[a][b] = sum_Q L^Q_a R^Q_b for a 128 x 128 output tile: rows from two
 // 64-column slice panels (r0, r1), columns from two more (c0, c1). Wave w
 // owns rows 64 (w >> 2) .. +63 (two 32-row blocks q = 0, 1) and columns
-// 32 (w & 3) .. +31, with five int32 level accumulators per block (160
+// 32 (w & 3) .. +31, with four int32 level accumulators per block (128
 // registers). A stage is one 32-index auxiliary chunk of the four panels
-// (4 x 10 KB); stages are copied global -> LDS directly (global_load_lds,
-// 16 bytes per lane) into a ring of four, three stages ahead of the matrix
+// (4 x 8 KB); stages are copied global -> LDS directly (global_load_lds,
+// 16 bytes per lane) into a ring of five, four stages ahead of the matrix
 // cores.
 // ---------------------------------------------------------------------------
 constexpr int kI8Threads = 512;
 constexpr int kI8Tile = 128;
-constexpr int kI8Ring = 4;
-constexpr int kI8Stage = 4 * kSlicePanelChunk;       // 40 KB
+constexpr int kI8Ring = 5;
+constexpr int kI8Stage = 4 * kSlicePanelChunk;       // 32 KB
 constexpr int kI8LdsRing = kI8Ring * kI8Stage;       // 160 KB
 constexpr int kI8Blocks = 2;                         // 32 x 32 blocks per wave
 constexpr int kI8Out = kI8Blocks * 16;               // outputs per lane
 static_assert(kI8Threads * kI8Out == kSliceXsDoubles, "x slot size");
-constexpr int kI8CopiesPerStage = 4 * (kSlicePanelChunk / 16) / kI8Threads;   // 5
+constexpr int kI8CopiesPerStage = 4 * (kSlicePanelChunk / 16) / kI8Threads;   // 4
 
 __device__ __forceinline__ i4v frag_i8(const int8_t *panel, int s, int row, int h) {
   const int off = (s * kPanel + row) * kQC + (((h ^ (row >> 3)) & 1) << 4);
@@ -100,77 +100,107 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Products of one stage are taken in five rounds: round r multiplies row
-// slice r with column slices 0 .. 4-r into the levels r .. 4, so two products
+// The K loop of one tile product through the LDS ring: rows from the slice
+// panels (Ra, Rb), columns from (Ca, Cb), stages s = 0 .. nqc-1 of 32
+// auxiliary indices each (a panel's chunks are consecutive).
+//
+// Products of one stage are taken in four rounds: round r multiplies row
+// slice r with column slices 0 .. 3-r into the levels r .. 3, so two products
 // into one accumulator are at least four instructions apart, and after round
-// r the fragments of row slice r and column slice 4-r are dead: the next
+// r the fragments of row slice r and column slice 3-r are dead: the next
 // stage's copies of exactly those are read into them at once. The LDS reads
 // of a stage thus overlap the matrix products of the previous one, which
 // needs the next stage in LDS one stage earlier than the products do.
-__device__ __forceinline__ void i8_tile_product(const int8_t *r0, const int8_t *r1,
-                                                const int8_t *c0, const int8_t *c1, int64_t nqc,
-                                                int8_t *lds, i16v (&acc)[kI8Blocks][kSlices],
-                                                int wr, int wc, int lane) {
-  constexpr int64_t CH = kSlicePanelChunk;
-  const int row = lane & 31, h = lane >> 5;
-  const int cr = 32 * (wc & 1) + row;
+struct I8Stream {
+  const int8_t *Ra, *Rb, *Ca, *Cb;
+  int64_t nqc;
+  int8_t *lds;
+  int wr, wc, row, h, cr;
+  i4v fa[kI8Blocks][kSlices], fb[kSlices];
+
+  __device__ __forceinline__ I8Stream(const int8_t *ra, const int8_t *rb, const int8_t *ca,
+                                      const int8_t *cb, int64_t nqc_, int8_t *lds_, int wr_,
+                                      int wc_, int lane)
+      : Ra(ra), Rb(rb), Ca(ca), Cb(cb), nqc(nqc_), lds(lds_), wr(wr_), wc(wc_),
+        row(lane & 31), h(lane >> 5), cr(32 * (wc_ & 1) + (lane & 31)) {}
+
+  __device__ __forceinline__ void issue(int64_t s) {
+    constexpr int64_t CH = kSlicePanelChunk;
+    i8_issue_stage(Ra + s * CH, Rb + s * CH, Ca + s * CH, Cb + s * CH,
+                   lds + (int)(s % kI8Ring) * kI8Stage);
+  }
+  // row panel of this wave and its column panel in the ring slot of stage s
+  __device__ __forceinline__ const int8_t *lrow(int64_t s) const {
+    return lds + (int)(s % kI8Ring) * kI8Stage + wr * kSlicePanelChunk;
+  }
+  __device__ __forceinline__ const int8_t *lcol(int64_t s) const {
+    return lds + (int)(s % kI8Ring) * kI8Stage + (2 + (wc >> 1)) * kSlicePanelChunk;
+  }
+
+  __device__ __forceinline__ void run(i16v (&acc)[kI8Blocks][kSlices]) {
+    for (int64_t s = 0; s < kI8Ring - 1 && s < nqc; ++s) issue(s);
+    wait_vm<0>();
+    ring_barrier();
+#pragma unroll
+    for (int k = 0; k < kSlices; ++k) {
+      fb[k] = frag_i8(lcol(0), k, cr, h);
+#pragma unroll
+      for (int q = 0; q < kI8Blocks; ++q) fa[q][k] = frag_i8(lrow(0), k, 32 * q + row, h);
+    }
+    for (int64_t s = 0; s < nqc; ++s) {
+      // the slot of stage s + 4 held stage s - 1, whose fragments were read
+      // during stage s - 2 and consumed before the barrier that ended stage s - 1
+      const bool more = s + kI8Ring - 1 < nqc;
+      if (more) issue(s + kI8Ring - 1);
+      // fragments of stage s + 1 (a stale slot after the last stage: never used)
+      const int8_t *Lr = lrow(s + 1), *Lc = lcol(s + 1);
+#pragma unroll
+      for (int r = 0; r < kSlices; ++r) {
+#pragma unroll
+        for (int Lv = kSlices - 1; Lv >= r; --Lv)
+#pragma unroll
+          for (int q = 0; q < kI8Blocks; ++q)
+            acc[q][Lv] = mfma_i8(fa[q][r], fb[Lv - r], acc[q][Lv]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < kI8Blocks; ++q) fa[q][r] = frag_i8(Lr, r, 32 * q + row, h);
+        fb[kSlices - 1 - r] = frag_i8(Lc, kSlices - 1 - r, cr, h);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // stage s + 2 must have landed (its fragments are read during stage
+      // s + 1); stages s + 3 and s + 4 may still be in flight
+      if (more)
+        wait_vm<(kI8Ring - 3) * kI8CopiesPerStage>();
+      else
+        wait_vm<0>();
+      ring_barrier();
+    }
+  }
+};
+
+__device__ __forceinline__ void i8_clear(i16v (&acc)[kI8Blocks][kSlices]) {
 #pragma unroll
   for (int q = 0; q < kI8Blocks; ++q)
 #pragma unroll
     for (int L = 0; L < kSlices; ++L) acc[q][L] = i16v{};
-  auto issue = [&](int64_t s) {
-    i8_issue_stage(r0 + s * CH, r1 + s * CH, c0 + s * CH, c1 + s * CH,
-                   lds + (int)(s % kI8Ring) * kI8Stage);
-  };
-  // row panel of this wave, column panel, in ring slot b
-  auto lrow = [&](int64_t s) { return lds + (int)(s % kI8Ring) * kI8Stage + wr * CH; };
-  auto lcol = [&](int64_t s) { return lds + (int)(s % kI8Ring) * kI8Stage + (2 + (wc >> 1)) * CH; };
-  for (int64_t s = 0; s < kI8Ring - 1 && s < nqc; ++s) issue(s);
-  wait_vm<0>();
-  ring_barrier();
-  i4v fa[kI8Blocks][kSlices], fb[kSlices];
-#pragma unroll
-  for (int k = 0; k < kSlices; ++k) {
-    fb[k] = frag_i8(lcol(0), k, cr, h);
-#pragma unroll
-    for (int q = 0; q < kI8Blocks; ++q) fa[q][k] = frag_i8(lrow(0), k, 32 * q + row, h);
-  }
-  for (int64_t s = 0; s < nqc; ++s) {
-    // the slot of stage s + 3 held stage s - 1, whose fragments were read
-    // during stage s - 2 and consumed before the barrier that ended stage s - 1
-    const bool more = s + kI8Ring - 1 < nqc;
-    if (more) issue(s + kI8Ring - 1);
-    // fragments of stage s + 1 (a stale slot on the last stage: never used)
-    const int8_t *Lr = lrow(s + 1), *Lc = lcol(s + 1);
-#pragma unroll
-    for (int r = 0; r < kSlices; ++r) {
-#pragma unroll
-      for (int Lv = kSlices - 1; Lv >= r; --Lv)
-#pragma unroll
-        for (int q = 0; q < kI8Blocks; ++q)
-          acc[q][Lv] = mfma_i8(fa[q][r], fb[Lv - r], acc[q][Lv]);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int q = 0; q < kI8Blocks; ++q) fa[q][r] = frag_i8(Lr, r, 32 * q + row, h);
-      fb[kSlices - 1 - r] = frag_i8(Lc, kSlices - 1 - r, cr, h);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    // stage s + 2 must have landed (its fragments are read during stage s + 1);
-    // stage s + 3 may still be in flight
-    if (more)
-      wait_vm<kI8CopiesPerStage>();
-    else
-      wait_vm<0>();
-    ring_barrier();
-  }
 }
 
-// sum_L 2^(-12-7L) I_L, smallest level first
+// One tile product: rows from panels (r0, r1), columns from (c0, c1).
+__device__ __forceinline__ void i8_tile_product(const int8_t *r0, const int8_t *r1,
+                                                const int8_t *c0, const int8_t *c1, int64_t nqc,
+                                                int8_t *lds, i16v (&acc)[kI8Blocks][kSlices],
+                                                int wr, int wc, int lane) {
+  I8Stream st(r0, r1, c0, c1, nqc, lds, wr, wc, lane);
+  i8_clear(acc);
+  st.run(acc);
+}
+
+// sum_L w_L I_L with w_L = 1 / (127^2 254^L), smallest level first (Horner)
 __device__ __forceinline__ double level_value(const i16v (&acc)[kSlices], int r) {
-  double v = 0.0;
+  double v = (double)acc[kSlices - 1][r];
 #pragma unroll
-  for (int L = kSlices - 1; L >= 0; --L) v += ldexp((double)acc[L][r], -12 - 7 * L);
-  return v;
+  for (int L = kSlices - 2; L >= 0; --L) v = v * (1.0 / 254.0) + (double)acc[L][r];
+  return v * (1.0 / 16129.0);
 }
 
 // Row / column inside the 128 x 128 tile of output r of block q of this lane.
@@ -277,9 +307,9 @@ __device__ __forceinline__ void ccvv_i8_item(const int8_t *S8, const double *sig
                                              int8_t *lds, double *xw, int wr, int wc, int lane,
                                              double (&v)[kI8Out]) {
   const int64_t ldv = (int64_t)ntv_s * kPanel;
-  const int64_t ps = nqc * (int64_t)kSlicePanelChunk;
   const double *sri = sig + c.i * ldv + c.A * kI8Tile, *scj = sig + c.j * ldv + c.B * kI8Tile;
   const double *srj = sig + c.j * ldv + c.A * kI8Tile, *sci = sig + c.i * ldv + c.B * kI8Tile;
+  const int64_t ps = nqc * (int64_t)kSlicePanelChunk;
   i16v ac[kI8Blocks][kSlices];
   const int npass = (c.cls == 0) ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {

@@ -2,12 +2,13 @@
 // (gfx950): the adjoint contractions dE/dB = B G on the int8 matrix cores.
 //
 // The adjoint tiles G (Gs for CCVV, G2 for CAVV, G3 for CCAV) are formed in
-// FP64 exactly as in the FP64 backward; each product C[Q][n] = sum_k
-// B^Q_k G[k][n] is then taken on error-free int8 slices: both operands are
-// split per row (Q for B, the output index n for G) into five power-of-two
-// scaled slices, the 15 slice products of levels L <= 4 are exact int32
-// sums over k (|I_L| <= 5 * 4096 * K < 2^31 for K <= 100000), and the
-// levels are recombined in FP64 (the scheme of the forward slice path).
+// FP64 (CCAV) or from the slice-path integrals (CCVV, CAVV); each product
+// C[Q][n] = sum_k B^Q_k G[k][n] is then taken on error-free int8 slices:
+// both operands are split per row (Q for B, the output index n for G) into
+// four scaled slices (the scheme of the forward slice path), the ten slice
+// products of levels L <= 3 are exact int32 sums over segments of at most
+// kGemmSeg contraction indices (|I_L| <= 4 * 127^2 * kGemmSeg < 2^31), and
+// the levels are recombined in FP64, segment sums added in FP64.
 #include "int8_tiles.h"
 
 namespace dsrg {
@@ -98,12 +99,12 @@ __global__ __launch_bounds__(256) void op_pack_kernel(OpMap m, int64_t R, int64_
   int8_t buf[kSlices][kQC];
 #pragma unroll
   for (int j = 0; j < kQC; ++j) {
-    double x = op_next(m, row, w) * inv * 64.0;
+    double x = op_next(m, row, w) * inv * 127.0;
 #pragma unroll
     for (int s = 0; s < kSlices; ++s) {
       const double t = rint(x);
       buf[s][j] = (int8_t)(int)t;
-      x = (x - t) * 128.0;
+      x = (x - t) * 254.0;
     }
   }
   const int c = (int)(r % kPanel);
@@ -122,9 +123,12 @@ __global__ __launch_bounds__(256) void op_pack_kernel(OpMap m, int64_t R, int64_
 // workgroup (A tiles fastest, so the workgroups of one XCD share A panels).
 // Output column n is written at (n / GP) nvalid + n % GP and skipped when
 // n % GP >= nvalid (padding of the column blocks).
+constexpr int64_t kGemmSeg = 32768;   // contraction indices per exact int32 segment
+
 struct I8GemmArgs {
   int64_t tA;                 // 128-row tiles of A
-  int64_t nqc;                // 32-wide contraction chunks
+  int64_t nqc;                // 32-wide contraction chunks of the operand panels
+  int64_t qc0, nseg;          // chunks of this segment
   int64_t M;                  // valid rows of A
   int64_t Ncols, GP, nvalid;  // padded output columns, their block width, valid per block
   int64_t ldc;
@@ -147,9 +151,10 @@ __global__ __launch_bounds__(512) void i8_gemm_kernel(const int8_t *__restrict__
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 2, wc = wave & 3;
   const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
-  const int8_t *r0 = SA + 2 * ta * ps, *c0 = SB + 2 * tb * ps;
+  const int64_t off = a.qc0 * (int64_t)kSlicePanelChunk;
+  const int8_t *r0 = SA + 2 * ta * ps + off, *c0 = SB + 2 * tb * ps + off;
   i16v ac[kI8Blocks][kSlices];
-  i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nqc, lds, ac, wr, wc, lane);
+  i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nseg, lds, ac, wr, wc, lane);
 #pragma unroll
   for (int q = 0; q < kI8Blocks; ++q) {
     double v[16];
@@ -558,13 +563,20 @@ static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, cons
   a.GP = GP;
   a.nvalid = nvalid;
   a.ldc = ldc;
-  a.accumulate = accumulate ? 1 : 0;
   const int64_t grid = a.tA * (RB / kI8Tile);
-  timer_begin("gemm_adj_i8", st);
-  hipLaunchKernelGGL(i8_gemm_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st, SA, sigA, SB,
-                     sigB, a, C);
-  timer_end(st);
-  return hipGetLastError();
+  const int64_t seg = kGemmSeg / kQC;
+  for (int64_t q0 = 0; q0 < a.nqc; q0 += seg) {
+    a.qc0 = q0;
+    a.nseg = (a.nqc - q0 < seg) ? a.nqc - q0 : seg;
+    a.accumulate = (accumulate || q0 > 0) ? 1 : 0;
+    timer_begin("gemm_adj_i8", st);
+    hipLaunchKernelGGL(i8_gemm_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st, SA, sigA,
+                       SB, sigB, a, C);
+    timer_end(st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,

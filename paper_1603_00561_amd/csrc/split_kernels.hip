@@ -2,17 +2,21 @@
 //
 // Each column of B (one core or active orbital p and one virtual orbital e,
 // a vector over the auxiliary index Q) is scaled by a power of two sigma with
-// |B^Q_pe| < sigma and split into five round-to-nearest int8 slices,
-//   B^Q_pe = sigma (s0 2^-6 + s1 2^-13 + s2 2^-20 + s3 2^-27 + s4 2^-34) + r,
-// |s_k| <= 64, |r| <= sigma 2^-35 (the splitting of Ozaki, Ogita, Oishi and
-// Rump, "Error-free transformations of matrix multiplication by using fast
-// routines of matrix multiplication", 2012). A contraction over Q becomes
-//   (pe|qf) = sigma_pe sigma_qf sum_L 2^(-12-7L) I_L,  I_L = sum_{k+l=L} sum_Q s_k s_l,
-// kept for levels L <= 4 (15 slice products). Every I_L is an exact int32
-// sum on the int8 matrix cores (|I_L| <= 5 * 4096 * naux < 2^31 for
-// naux <= 100000), so the only error left is the dropped levels and the
-// residual r. The self-pair diagonal (ia|ia) = sum_Q (B^Q_ia)^2, whose
-// dropped terms all have one sign, is taken in FP64 instead.
+// |B^Q_pe| < sigma and split into four round-to-nearest int8 slices,
+//   B^Q_pe = sigma (s0 / 127 + s1 / (127 254) + s2 / (127 254^2)
+//                   + s3 / (127 254^3) + r),
+// |s_k| <= 127, |r| <= 1 / (2 127 254^3) (the splitting of Ozaki, Ogita,
+// Oishi and Rump, "Error-free transformations of matrix multiplication by
+// using fast routines of matrix multiplication", 2012, with an integer base
+// that fills the int8 range). A contraction over Q becomes
+//   (pe|qf) = sigma_pe sigma_qf sum_L I_L / (127^2 254^L),
+//   I_L = sum_{k+l=L} sum_Q s_k s_l,
+// kept for levels L <= 3 (ten slice products). Every I_L is an exact int32
+// sum on the int8 matrix cores (|I_L| <= 4 * 127^2 * naux < 2^31 for naux <=
+// 33000), so the only error left is the dropped levels and the residual r;
+// the FP64 recombination rounds once per level. The self-pair diagonal
+// (ia|ia) = sum_Q (B^Q_ia)^2, whose dropped terms all have one sign, is taken
+// in FP64 instead.
 #include "int8_tiles.h"
 
 namespace dsrg {
@@ -81,12 +85,12 @@ __global__ __launch_bounds__(256) void slice_pack_kernel(const double *__restric
   for (int j = 0; j < kQC; ++j) {
     const int64_t q = qc * kQC + j;
     double x = 0.0;
-    if (e < nv && q < naux) x = B[(q * nrow + p) * nv + e] * inv * 64.0;
+    if (e < nv && q < naux) x = B[(q * nrow + p) * nv + e] * inv * 127.0;
 #pragma unroll
     for (int s = 0; s < kSlices; ++s) {
       const double r = rint(x);
       buf[s][j] = (int8_t)(int)r;
-      x = (x - r) * 128.0;
+      x = (x - r) * 254.0;
     }
   }
   int8_t *dst = S8 + ((p * ntv + t) * nqc + qc) * (int64_t)kSlicePanelChunk;
