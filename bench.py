@@ -118,8 +118,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (the energy shards over core pairs "
-              "as described in DESIGN.md, but no multi-GPU path is built); use --gpus 1",
+        print("bench.py: runs on one GPU only (the energy would shard over core pairs, "
+              "but no multi-GPU path is built); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -76,6 +76,18 @@ def test_invalid_sizes_and_scalars(lib, field, value, code):
     assert st == code
 
 
+def test_slice_path_limits(lib):
+    """Slice path: int32 level sums are exact up to naux = 33000; the
+    gradient splits its longer contractions and has no such bound."""
+    ok, _ = _ws(_prob(4, 2, 100, 33000), prec=2)
+    assert ok == 0
+    st, _ = _ws(_prob(4, 2, 100, 33001), prec=2)
+    assert st == b.DSRG_ERR_UNSUPPORTED and "33000" in lib.dsrg_df_last_error().decode()
+    assert _ws(_prob(4, 2, 100, 33001), prec=0)[0] == 0
+    assert _ws(_prob(40, 2, 1100, 500), prec=2, grad=1)[0] == 0   # contraction 40*1152
+    assert _ws(_prob(4, 2, 100, 64), prec=1)[0] == b.DSRG_ERR_UNSUPPORTED
+
+
 def test_na_above_max_is_fine_for_ccvv_only(lib):
     p = _prob(na=20)
     st, _ = _ws(p, terms=1)
