@@ -236,6 +236,8 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
     pl.off_opmax = off;
     off = align256(off + sizeof(double) * 32 * std::max(RA, rbmax));
   }
+  pl.off_ctr = off;
+  off = align256(off + 64);
   pl.off_slots = off;
   pl.slot_base[0] = 0;
   pl.slot_base[1] = pl.n_ccvv;

@@ -34,8 +34,9 @@ __global__ __launch_bounds__(256) void pack_panels_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// CCVV (F1). One workgroup per (core pair i <= j, virtual tile pair A <= B),
-// classes in decreasing cost (see decode_ccvv): the tile contributes
+// CCVV (F1). Work items (core pair i <= j, virtual tile pair A <= B) in the
+// order of decode_ccvv_list, taken by a persistent grid from per-XCD
+// counters (two-product items first); the tile contributes
 // weight * R(D) (x^2 - x y + y^2) with x = (ia|jb), y = (ib|ja) and weight
 // 4, 2, 2, 1 for (i<j, A<B), (i<j, A=B), (i=j, A<B), (i=j, A=B).
 // ---------------------------------------------------------------------------
@@ -55,13 +56,19 @@ __device__ __forceinline__ double ccvv_weight(int cls) {
 __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict__ Pcv,
                                                         const double *__restrict__ eps_c,
                                                         const double *__restrict__ eps_v,
-                                                        CcvvArgs a, double *slots,
+                                                        CcvvArgs a, int *ctr, double *slots,
                                                         double *acc) {
   constexpr int W = kPanel;
   __shared__ double lds[kCcvvLds];
-  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.nc * (a.nc + 1) / 2, a.ntv);
-  if (pt.item < 0) return;
-  const CcvvWork c = ccvv_work_from(pt, a.nc);
+  __shared__ int next;
+  const int x = blockIdx.x % 8;   // the XCD this workgroup runs on
+  CcvvWork c;
+  int64_t slot;
+  for (;;) {
+  __syncthreads();   // the previous item is done with the LDS
+  if (threadIdx.x == 0) next = atomicAdd(ctr + x, 1);
+  __syncthreads();
+  if (!decode_ccvv_list(next, x, a.nc, a.ntv, c, slot)) break;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
@@ -94,7 +101,8 @@ __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict
     }
   }
   const double t = block_sum(part, lds) * ccvv_weight(c.cls);
-  emit_partial(t, slots, a.slot_base + pt.item, acc, a.atomic_mode);
+  emit_partial(t, slots, a.slot_base + slot, acc, a.atomic_mode);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -102,7 +110,8 @@ __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict
 // integrals X^{mu}[e][f] = (me|uf) of every virtual tile pair A <= B (the CCVV
 // tile machinery with pair (m, u), left panels B_cv, right panels B_av) are
 // written to Xb[(m - m0)][u][e][f]: block [A,B] from x and block [B,A] from
-// y = X^{mu}[B,A]^T. Step 2 (cavv_epi_kernel) forms the energy.
+// y = X^{mu}[B,A]^T. A persistent grid takes the items of decode_pair_list
+// from per-XCD counters. Step 2 (cavv_epi_kernel) forms the energy.
 // ---------------------------------------------------------------------------
 struct CavvXArgs64 {
   int na, ntv;
@@ -112,17 +121,22 @@ struct CavvXArgs64 {
 
 __global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restrict__ Pcv,
                                                           const double *__restrict__ Pav,
-                                                          CavvXArgs64 a, double *__restrict__ Xb) {
+                                                          CavvXArgs64 a, int *ctr,
+                                                          double *__restrict__ Xb) {
   constexpr int W = kPanel;
   __shared__ double lds[kCcvvLds];
-  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.mb * a.na, a.ntv);
-  if (pt.item < 0) return;
-  const int ml = (int)(pt.p / a.na), u = (int)(pt.p % a.na);
+  __shared__ int next;
+  const int xcd = blockIdx.x % 8;
+  for (;;) {
+  __syncthreads();   // the previous item is done with the LDS
+  if (threadIdx.x == 0) next = atomicAdd(ctr + xcd, 1);
+  __syncthreads();
+  int64_t pp;
   CcvvWork c;
+  if (!decode_pair_list(next, xcd, (int64_t)a.mb * a.na, a.ntv, pp, c.A, c.B)) break;
+  const int ml = (int)(pp / a.na), u = (int)(pp % a.na);
   c.i = a.m0 + ml;
   c.j = u;
-  c.A = pt.A;
-  c.B = pt.B;
   c.cls = (c.A == c.B) ? 2 : 0;   // y is needed only off the diagonal
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -153,6 +167,7 @@ __global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restri
       const int fr = k / W, ec = k % W;
       X[(int64_t)(c.B * W + fr) * ld + c.A * W + ec] = T[ec][fr];
     }
+  }
   }
 }
 
@@ -432,13 +447,17 @@ static hipError_t launch_cavv(const Plan &pl, const Inputs &in, void *ws, hipStr
     xa.naux_p = pl.naux_p;
     xa.m0 = (int)m0;
     xa.mb = mb;
+    const int64_t items = pairtile_grid((int64_t)mb * pl.na, pl.ntv);
+    const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
+    int *ctr = reinterpret_cast<int *>(ws_d(ws, pl.off_ctr));
+    hipError_t e = launch_zero(ws_d(ws, pl.off_ctr), 4, st);
+    if (e != hipSuccess) return e;
     timer_begin("cavv_fp64_x", st);
-    hipLaunchKernelGGL(cavv_fp64_x_kernel, dim3((unsigned)pairtile_grid((int64_t)mb * pl.na, pl.ntv)),
-                       dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), xa,
+    hipLaunchKernelGGL(cavv_fp64_x_kernel, dim3((unsigned)grid), dim3(256), 0, st,
+                       ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), xa, ctr,
                        ws_d(ws, pl.off_xb));
     timer_end(st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_cavv_epi(pl, in, ws, (int)m0, mb, st)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -479,9 +498,15 @@ hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStr
     a.n2 = pl.nc * ntpo;
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
+    // persistent: two workgroups per CU (64 KiB of LDS each), items from
+    // per-XCD counters
+    const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv);
+    const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
+    int *ctr = reinterpret_cast<int *>(ws_d(ws, pl.off_ctr));
+    if ((e = launch_zero(ws_d(ws, pl.off_ctr), 4, st)) != hipSuccess) return e;
     timer_begin("ccvv_fp64", st);
-    hipLaunchKernelGGL(ccvv_fp64_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(256), 0, st,
-                       ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, slots, acc + 0);
+    hipLaunchKernelGGL(ccvv_fp64_kernel, dim3((unsigned)grid), dim3(256), 0, st,
+                       ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, ctr, slots, acc + 0);
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

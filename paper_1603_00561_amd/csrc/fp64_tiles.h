@@ -197,6 +197,96 @@ __device__ __forceinline__ CcvvWork ccvv_work_from(const PairTile &pt, int nc) {
   return c;
 }
 
+// Blocked walk (kTileBlock x kTileBlock blocks) over the strictly ordered
+// tile pairs A < B of nt tiles.
+__device__ __forceinline__ void decode_tile_blocked_lt(int64_t t, int nt, int &A, int &B) {
+  const int nb = (nt + kTileBlock - 1) / kTileBlock;
+  for (int ba = 0; ba < nb; ++ba) {
+    const int na_ = (ba == nb - 1) ? nt - ba * kTileBlock : kTileBlock;
+    for (int bb = ba; bb < nb; ++bb) {
+      const int nb_ = (bb == nb - 1) ? nt - bb * kTileBlock : kTileBlock;
+      const int64_t size = (ba == bb) ? (int64_t)na_ * (na_ - 1) / 2 : (int64_t)na_ * nb_;
+      if (t < size) {
+        int a0, b0;
+        if (ba == bb) {
+          decode_pair_lt(t, na_, a0, b0);
+        } else {
+          a0 = (int)(t / nb_);
+          b0 = (int)(t % nb_);
+        }
+        A = ba * kTileBlock + a0;
+        B = bb * kTileBlock + b0;
+        return;
+      }
+      t -= size;
+    }
+  }
+  A = B = 0;   // not reached for t < nt (nt - 1) / 2
+}
+
+// Work list of the persistent CCVV kernels (nt tiles per orbital) on XCD x (pairs p = x mod 8; pairs
+// 0 .. P0-1 are the i < j pairs in order, P0 + i the self pairs), item kk:
+// first every class-0 item (two products each) of its i < j pairs, then the
+// single-product items (class 1 of its i < j pairs, classes 2 and 3 of its
+// self pairs). The workgroups of one XCD take consecutive items, so each
+// round holds items of equal cost that share panels and stay in step along
+// the auxiliary index. slot = p T + (index of A <= B). Returns false past
+// the end of the list.
+__device__ __forceinline__ bool decode_ccvv_list(int64_t kk, int x, int nc, int nt, CcvvWork &c,
+                                               int64_t &slot) {
+  const int64_t P0 = (int64_t)nc * (nc - 1) / 2;
+  const int64_t T0 = (int64_t)nt * (nt - 1) / 2, T = (int64_t)nt * (nt + 1) / 2;
+  const int64_t nlt = (P0 > x) ? (P0 - x + 7) / 8 : 0;
+  const int64_t first_eq = P0 + ((x - P0 % 8) + 8) % 8;   // first self pair on this XCD
+  const int64_t neq = (first_eq < P0 + nc) ? (P0 + nc - first_eq + 7) / 8 : 0;
+  int64_t p;
+  if (kk < nlt * T0) {
+    p = 8 * (kk / T0) + x;
+    decode_tile_blocked_lt(kk % T0, nt, c.A, c.B);
+    c.cls = 0;
+  } else if ((kk -= nlt * T0) < nlt * nt) {
+    p = 8 * (kk / nt) + x;
+    c.A = c.B = (int)(kk % nt);
+    c.cls = 1;
+  } else if ((kk -= nlt * nt) < neq * T) {
+    p = first_eq + 8 * (kk / T);
+    decode_tile_blocked(kk % T, nt, c.A, c.B);
+    c.cls = (c.A == c.B) ? 3 : 2;
+  } else {
+    return false;
+  }
+  if (p < P0) {
+    decode_pair_lt(p, nc, c.i, c.j);
+  } else {
+    c.i = c.j = (int)(p - P0);
+  }
+  slot = p * T + (int64_t)c.A * nt - (int64_t)c.A * (c.A - 1) / 2 + (c.B - c.A);
+  return true;
+}
+
+
+// Work list of a persistent producer over P pairs (all distinct) and tile
+// pairs A <= B of nt tiles, on XCD x (pairs p = x mod 8): first the A < B
+// items (two products) of its pairs, then the A = B items. Returns false past
+// the end of the list.
+__device__ __forceinline__ bool decode_pair_list(int64_t kk, int x, int64_t P, int nt,
+                                                 int64_t &p, int &A, int &B) {
+  const int64_t T0 = (int64_t)nt * (nt - 1) / 2;
+  const int64_t np = (P > x) ? (P - x + 7) / 8 : 0;
+  if (kk < np * T0) {
+    p = 8 * (kk / T0) + x;
+    decode_tile_blocked_lt(kk % T0, nt, A, B);
+    return true;
+  }
+  kk -= np * T0;
+  if (kk < np * nt) {
+    p = 8 * (kk / nt) + x;
+    A = B = (int)(kk % nt);
+    return true;
+  }
+  return false;
+}
+
 constexpr int kCcvvKC = 16;
 constexpr int kCcvvLds = 2 * 4 * kCcvvKC * kPanel;   // doubles
 

@@ -19,6 +19,7 @@ constexpr int kActPanel = 16;
 // Persistent workgroups of the int8 CCVV kernel, each with an FP64 slot of
 // 512 lanes x 32 values for the first product of a two-product tile.
 constexpr int kSlicePersistWG = 256;
+constexpr int kPersistCU = 256;   // compute units the persistent FP64 CCVV grid is sized for
 constexpr int64_t kSliceXsDoubles = 512 * 32;
 // followed by eight per-XCD work counters (ints; cleared before each launch)
 constexpr size_t kSliceCounterBytes = 64;
@@ -62,6 +63,7 @@ struct Plan {
   size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
   // int8 adjoint products (slice-path gradient): operand slices and scales
   size_t off_SA1, off_SA2, off_SB, off_sigA1, off_sigA2, off_sigB, off_opmax;
+  size_t off_ctr;                     // eight per-XCD work counters (ints)
   size_t off_slots;                   // per-workgroup partial energies
   size_t off_acc;                     // [4] atomic accumulators
   size_t total;

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
     if (threadIdx.x == 0) *next = atomicAdd(ctr + x, 1);
     __syncthreads();
     const int64_t kk = *next;
-    if (!decode_ccvv_i8(kk, x, a.nc, nt, c, slot)) break;
+    if (!decode_ccvv_list(kk, x, a.nc, nt, c, slot)) break;
     double v[kI8Out];
     ccvv_i8_item(S8, sig, c, a.nqc, a.ntv_s, lds, xw, wr, wc, lane, v);
     if (c.cls == 1) {

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void slice_pack_kernel(const double *__restric
 
 // ---------------------------------------------------------------------------
 // CCVV on slices. Work items are (core pair i <= j, 128-tile pair A <= B)
-// in the order of decode_ccvv_i8; classes 0: i<j, A<B (x and y = K^{ji}[A,B]),
+// in the order of decode_ccvv_list; classes 0: i<j, A<B (x and y = K^{ji}[A,B]),
 // 1: i<j, A=B (y = x^T), 2: i=j, A<B and 3: i=j, A=B (y = x). The grid is
 // persistent (kSlicePersistWG workgroups, a multiple of 8, each taking the
 // next item of its XCD's list from that XCD's counter in ctr, which must be
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__
     if (threadIdx.x == 0) *next = atomicAdd(ctr + x, 1);
     __syncthreads();
     const int64_t kk = *next;
-    if (!decode_ccvv_i8(kk, x, a.nc, nt, c, slot)) break;
+    if (!decode_ccvv_list(kk, x, a.nc, nt, c, slot)) break;
     double v[kI8Out];
     ccvv_i8_item(S8, sig, c, a.nqc, a.ntv_s, lds, xw, wr, wc, lane, v);
     double (*T)[kI8Tile + 1] = reinterpret_cast<double (*)[kI8Tile + 1]>(lds);
