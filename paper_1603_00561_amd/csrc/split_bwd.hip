@@ -70,6 +70,33 @@ __global__ __launch_bounds__(256) void op_scale_partial_kernel(OpMap m, int64_t 
   pmax[g * R + r] = mx;
 }
 
+// The same partial maxima for operands whose contraction index is contiguous
+// in memory (ldk = 1): one wave per row, lanes striding over k, so every
+// load instruction reads 64 consecutive elements.
+__global__ __launch_bounds__(256) void op_scale_rows_kernel(OpMap m, int64_t R, int64_t K,
+                                                            double *__restrict__ pmax) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, g = blockIdx.y;
+  if (r >= R) return;
+  const int64_t k0 = K * g / kOpScaleGroups, k1 = K * (g + 1) / kOpScaleGroups;
+  const double *row = op_row(m, r);
+  double mx = 0.0;
+  if (row) {
+    int64_t k = k0 + lane, kb = k / m.kblk, ke = k % m.kblk;
+    for (; k < k1 && k < m.klim; k += 64) {
+      if (ke < m.kval) mx = fmax(mx, fabs(row[kb * m.ldkb + ke * m.ldk]));
+      ke += 64;
+      while (ke >= m.kblk) {
+        ke -= m.kblk;
+        ++kb;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if (lane == 0) pmax[g * R + r] = mx;
+}
+
 // sigma[r] = the smallest power of two above the row maximum (1 for zero rows)
 __global__ __launch_bounds__(256) void op_scale_final_kernel(const double *__restrict__ pmax,
                                                              int64_t R,
@@ -540,8 +567,12 @@ static OpMap op_map(const double *base, int64_t rblk, int64_t rval, int64_t ldrb
 static hipError_t pack_operand(const OpMap &m, int64_t R, int64_t K, double *sig,
                                double *pmax, int8_t *S8, hipStream_t st) {
   timer_begin("op_pack", st);
-  hipLaunchKernelGGL(op_scale_partial_kernel, dim3((unsigned)ceil_div(R, 256), kOpScaleGroups),
-                     dim3(256), 0, st, m, R, K, pmax);
+  if (m.ldk == 1)
+    hipLaunchKernelGGL(op_scale_rows_kernel, dim3((unsigned)ceil_div(R, 4), kOpScaleGroups),
+                       dim3(256), 0, st, m, R, K, pmax);
+  else
+    hipLaunchKernelGGL(op_scale_partial_kernel, dim3((unsigned)ceil_div(R, 256), kOpScaleGroups),
+                       dim3(256), 0, st, m, R, K, pmax);
   hipLaunchKernelGGL(op_scale_final_kernel, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, st,
                      pmax, R, sig);
   const int64_t nqc = K / kQC;
