@@ -54,26 +54,23 @@ __device__ __forceinline__ i4v frag_i8(const int8_t *panel, int s, int row, int 
 }
 
 // Copy one stage (four panel-chunks, in order s0..s3) into the LDS ring slot
-// dst. Each wave moves 64 consecutive 16-byte pieces per instruction; a
-// panel-chunk is 640 pieces, so no wave's pieces straddle two panels, and
-// source base and LDS address are wave-uniform (scalar registers).
+// dst: one instruction per panel-chunk, wave w moving its 64 consecutive
+// 16-byte pieces w * 1 KB .. +1 KB, so source base and LDS address are
+// wave-uniform (scalar registers) with no per-copy selection.
 __device__ __forceinline__ void i8_issue_stage(const int8_t *s0, const int8_t *s1,
                                                const int8_t *s2, const int8_t *s3,
                                                int8_t *dst) {
-  constexpr int PIECES = kSlicePanelChunk / 16;
-  static_assert(PIECES % 64 == 0 && (4 * PIECES) % kI8Threads == 0, "stage split");
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int voff = (threadIdx.x & 63) * 16;
+  static_assert(kSlicePanelChunk == kI8Threads * 16 && kI8CopiesPerStage == 4,
+                "one copy instruction per panel-chunk");
+  const int woff = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 1024;
+  const uint32_t voff = (threadIdx.x & 63) * 16;
+  const int8_t *src[4] = {s0, s1, s2, s3};
 #pragma unroll
-  for (int k = 0; k < kI8CopiesPerStage; ++k) {
-    const int base = wave * 64 + k * kI8Threads;
-    const int p = base / PIECES;
-    const int8_t *src = ((p == 0) ? s0 : (p == 1) ? s1 : (p == 2) ? s2 : s3) +
-                        (base % PIECES) * 16;
+  for (int k = 0; k < 4; ++k)
     __builtin_amdgcn_global_load_lds(
-        reinterpret_cast<const void *>(src + (uint32_t)voff),
-        (__attribute__((address_space(3))) void *)(dst + base * 16), 16, 0, 0);
-  }
+        reinterpret_cast<const void *>(src[k] + woff + voff),
+        (__attribute__((address_space(3))) void *)(dst + k * kSlicePanelChunk + woff), 16, 0,
+        0);
 }
 
 // Workgroup barrier that does not drain the vector-memory counter (the ring
@@ -112,48 +109,64 @@ __device__ __forceinline__ void wait_vm() {
 // of a stage thus overlap the matrix products of the previous one, which
 // needs the next stage in LDS one stage earlier than the products do.
 struct I8Stream {
-  const int8_t *Ra, *Rb, *Ca, *Cb;
-  int64_t nqc;
+  const int8_t *Ra, *Rb, *Ca, *Cb;   // next stage to copy
+  int nqc;
   int8_t *lds;
   int wr, wc, row, h, cr;
   i4v fa[kI8Blocks][kSlices], fb[kSlices];
 
   __device__ __forceinline__ I8Stream(const int8_t *ra, const int8_t *rb, const int8_t *ca,
-                                      const int8_t *cb, int64_t nqc_, int8_t *lds_, int wr_,
+                                      const int8_t *cb, int nqc_, int8_t *lds_, int wr_,
                                       int wc_, int lane)
       : Ra(ra), Rb(rb), Ca(ca), Cb(cb), nqc(nqc_), lds(lds_), wr(wr_), wc(wc_),
         row(lane & 31), h(lane >> 5), cr(32 * (wc_ & 1) + (lane & 31)) {}
 
-  __device__ __forceinline__ void issue(int64_t s) {
-    constexpr int64_t CH = kSlicePanelChunk;
-    i8_issue_stage(Ra + s * CH, Rb + s * CH, Ca + s * CH, Cb + s * CH,
-                   lds + (int)(s % kI8Ring) * kI8Stage);
+  // copies the next stage into the ring slot at byte offset slot
+  __device__ __forceinline__ void issue(int slot) {
+    i8_issue_stage(Ra, Rb, Ca, Cb, lds + slot);
+    Ra += kSlicePanelChunk;
+    Rb += kSlicePanelChunk;
+    Ca += kSlicePanelChunk;
+    Cb += kSlicePanelChunk;
   }
-  // row panel of this wave and its column panel in the ring slot of stage s
-  __device__ __forceinline__ const int8_t *lrow(int64_t s) const {
-    return lds + (int)(s % kI8Ring) * kI8Stage + wr * kSlicePanelChunk;
+  static __device__ __forceinline__ int next_slot(int slot) {
+    return slot + kI8Stage == kI8LdsRing ? 0 : slot + kI8Stage;
   }
-  __device__ __forceinline__ const int8_t *lcol(int64_t s) const {
-    return lds + (int)(s % kI8Ring) * kI8Stage + (2 + (wc >> 1)) * kSlicePanelChunk;
+  // fragments consumed in round r: row slice r, column slice 3 - r
+  __device__ __forceinline__ void read_round(int slot, int r) {
+    const int8_t *Lr = lds + slot + wr * kSlicePanelChunk;
+    const int8_t *Lc = lds + slot + (2 + (wc >> 1)) * kSlicePanelChunk;
+#pragma unroll
+    for (int q = 0; q < kI8Blocks; ++q) fa[q][r] = frag_i8(Lr, r, 32 * q + row, h);
+    fb[kSlices - 1 - r] = frag_i8(Lc, kSlices - 1 - r, cr, h);
   }
 
   __device__ __forceinline__ void run(i16v (&acc)[kI8Blocks][kSlices]) {
-    for (int64_t s = 0; s < kI8Ring - 1 && s < nqc; ++s) issue(s);
+    int wslot = 0;
+    for (int s = 0; s < kI8Ring - 1 && s < nqc; ++s) {
+      issue(wslot);
+      wslot += kI8Stage;
+    }
     wait_vm<0>();
     ring_barrier();
+    // same order as the reads inside the loop, so that the LDS counter
+    // state entering the loop matches the one carried around it
 #pragma unroll
-    for (int k = 0; k < kSlices; ++k) {
-      fb[k] = frag_i8(lcol(0), k, cr, h);
-#pragma unroll
-      for (int q = 0; q < kI8Blocks; ++q) fa[q][k] = frag_i8(lrow(0), k, 32 * q + row, h);
+    for (int r = 0; r < kSlices; ++r) {
+      read_round(0, r);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    for (int64_t s = 0; s < nqc; ++s) {
+    int rslot = 0;
+    for (int s = 0; s < nqc; ++s) {
       // the slot of stage s + 4 held stage s - 1, whose fragments were read
       // during stage s - 2 and consumed before the barrier that ended stage s - 1
       const bool more = s + kI8Ring - 1 < nqc;
-      if (more) issue(s + kI8Ring - 1);
+      if (more) {
+        issue(wslot);
+        wslot = next_slot(wslot);
+      }
       // fragments of stage s + 1 (a stale slot after the last stage: never used)
-      const int8_t *Lr = lrow(s + 1), *Lc = lcol(s + 1);
+      const int nslot = next_slot(rslot);
 #pragma unroll
       for (int r = 0; r < kSlices; ++r) {
 #pragma unroll
@@ -162,9 +175,7 @@ struct I8Stream {
           for (int q = 0; q < kI8Blocks; ++q)
             acc[q][Lv] = mfma_i8(fa[q][r], fb[Lv - r], acc[q][Lv]);
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int q = 0; q < kI8Blocks; ++q) fa[q][r] = frag_i8(Lr, r, 32 * q + row, h);
-        fb[kSlices - 1 - r] = frag_i8(Lc, kSlices - 1 - r, cr, h);
+        read_round(nslot, r);
         __builtin_amdgcn_sched_barrier(0);
       }
       // stage s + 2 must have landed (its fragments are read during stage
@@ -174,6 +185,7 @@ struct I8Stream {
       else
         wait_vm<0>();
       ring_barrier();
+      rslot = nslot;
     }
   }
 };
@@ -187,7 +199,7 @@ __device__ __forceinline__ void i8_clear(i16v (&acc)[kI8Blocks][kSlices]) {
 
 // One tile product: rows from panels (r0, r1), columns from (c0, c1).
 __device__ __forceinline__ void i8_tile_product(const int8_t *r0, const int8_t *r1,
-                                                const int8_t *c0, const int8_t *c1, int64_t nqc,
+                                                const int8_t *c0, const int8_t *c1, int nqc,
                                                 int8_t *lds, i16v (&acc)[kI8Blocks][kSlices],
                                                 int wr, int wc, int lane) {
   I8Stream st(r0, r1, c0, c1, nqc, lds, wr, wc, lane);
@@ -247,7 +259,7 @@ __device__ __forceinline__ void ccvv_i8_item(const int8_t *S8, const double *sig
   for (int pass = 0; pass < npass; ++pass) {
     const int8_t *r0 = slice_panel(S8, pass ? c.j : c.i, 2 * c.A, ntv_s, nqc);
     const int8_t *c0 = slice_panel(S8, pass ? c.i : c.j, 2 * c.B, ntv_s, nqc);
-    i8_tile_product(r0, r0 + ps, c0, c0 + ps, nqc, lds, ac, wr, wc, lane);
+    i8_tile_product(r0, r0 + ps, c0, c0 + ps, (int)nqc, lds, ac, wr, wc, lane);
     if (pass + 1 < npass) {
 #pragma unroll
       for (int q = 0; q < kI8Blocks; ++q) {

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(512) void i8_gemm_kernel(const int8_t *__restrict__
   const int64_t off = a.qc0 * (int64_t)kSlicePanelChunk;
   const int8_t *r0 = SA + 2 * ta * ps + off, *c0 = SB + 2 * tb * ps + off;
   i16v ac[kI8Blocks][kSlices];
-  i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nseg, lds, ac, wr, wc, lane);
+  i8_tile_product(r0, r0 + ps, c0, c0 + ps, (int)a.nseg, lds, ac, wr, wc, lane);
 #pragma unroll
   for (int q = 0; q < kI8Blocks; ++q) {
     double v[16];

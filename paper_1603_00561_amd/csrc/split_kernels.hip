@@ -262,7 +262,7 @@ __global__ __launch_bounds__(512) void cavv_i8_x_kernel(const int8_t *__restrict
   const int8_t *r0 = slice_panel(S8c, m, 2 * A, a.ntv_s, a.nqc);
   const int8_t *c0 = slice_panel(S8a, u, 2 * B, a.ntv_s, a.nqc);
   i16v ac[kI8Blocks][kSlices];
-  i8_tile_product(r0, r0 + ps, c0, c0 + ps, a.nqc, lds, ac, wr, wc, lane);
+  i8_tile_product(r0, r0 + ps, c0, c0 + ps, (int)a.nqc, lds, ac, wr, wc, lane);
   const int64_t ld = (int64_t)a.ntv_s * kPanel;
   double *X = Xb + ((int64_t)ml * a.na + u) * ld * ld + (int64_t)A * kI8Tile * ld + B * kI8Tile;
 #pragma unroll
