@@ -82,20 +82,32 @@ def cpu_baseline(p, budget_s=20.0):
             "sample": "; ".join(parts) + " (FP64 numpy/BLAS oracle, same inputs)"}
 
 
+def kernel_source_sha(src):
+    """sha256 over a kernel's .hip source followed by every header of the
+    library source directory (sorted), so a change to shared tile code also
+    marks the counters stale."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1603_00561_amd", "csrc")
+    for f in [os.path.join(csrc, src)] + sorted(glob.glob(os.path.join(csrc, "*.h"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def load_traffic(kernel, workload):
     """HBM bytes per launch measured with rocprofv3 counters, if the summary
     for this kernel and workload was taken on the current kernel source."""
-    import hashlib
     f = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(f):
         return None
     with open(f) as fh:
         d = json.load(fh)
-    src = os.path.join(ROOT, "paper_1603_00561_amd", "csrc", d.get("source", ""))
-    if not os.path.exists(src):
+    src = d.get("source", "")
+    if not src or not os.path.exists(os.path.join(ROOT, "paper_1603_00561_amd", "csrc", src)):
         return None
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if h != d.get("source_sha256"):
+    if kernel_source_sha(src) != d.get("source_sha256"):
         return None
     return d.get("bytes_per_launch")
 
