@@ -467,61 +467,65 @@ __global__ __launch_bounds__(256) void ccav_adj_fp64_kernel(
 //   A[Q][k]  = Apan[k / PW][Q][k % PW]   (packed panels, Q rows < naux_p)
 //   Bm[k][n] = TB ? G[n * ldg + k] : G[k * ldg + n]
 //   col(n)   = (n / GP) * nvalid + n % GP for n % GP < nvalid (else skipped)
-// 128 x 128 output tile per workgroup, 4 waves of 64 x 64, K chunks of 8
-// double-buffered in LDS.
+// 128 x 128 output tile per workgroup of 8 waves (two per SIMD: the FP64
+// matrix cores need a second wave to issue back to back), wave w owning rows
+// 64 (w >> 2) .. +63 and columns 32 (w & 3) .. +31; K chunks of 16 staged
+// through registers and double-buffered in LDS, one barrier per chunk.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
   int64_t naux, naux_p;   // rows of C / rows stored per panel
-  int64_t K;              // contraction length (multiple of 8)
+  int64_t K;              // contraction length (multiple of 16)
   int PW;                 // panel width of A (16 or 64)
-  int64_t Ncols;          // columns of Bm (padded index space)
+  int64_t Ncols;          // columns of Bm (padded index space, even)
   int64_t ldg;
   int64_t GP, nvalid, ldc;
   int accumulate;
 };
 
-constexpr int kGT = 128, kGK = 8, kGA = kGK + 1;
+constexpr int kGT = 128, kGK = 16, kGA = kGK + 1, kGThreads = 512;
 
 template <bool TB>
-__global__ __launch_bounds__(256) void gemm_adj_fp64_kernel(const double *__restrict__ Apan,
-                                                            const double *__restrict__ G,
-                                                            GemmArgs a, double *__restrict__ C) {
+__global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *__restrict__ Apan,
+                                                                  const double *__restrict__ G,
+                                                                  GemmArgs a,
+                                                                  double *__restrict__ C) {
   __shared__ double sA[2][kGT * kGA];
   __shared__ double sB[2][kGK * kGT];
   const int64_t Q0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 2, wc = wave & 3;
   const int cl = lane & 15, kl = lane >> 4;
 
-  d4 acc[4][4];
+  d4 acc[4][2];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[p][q] = zero4();
+    for (int q = 0; q < 2; ++q) acc[p][q] = zero4();
 
+  // a chunk is 128 x 16 of A and 16 x 128 of Bm: 1024 double2 each, two per thread
   d2v ra[2], rb[2];
   auto gload = [&](int64_t k0) {
     const int64_t pan = k0 / a.PW, c0 = k0 % a.PW;
     const double *Ab = Apan + pan * a.naux_p * a.PW + c0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int idx = t + h * kThreads;       // 512 double2 = 128 rows x 4
-      const int row = idx >> 2, c2 = idx & 3;
+      const int idx = t + h * kGThreads;       // 128 rows x 8 double2
+      const int row = idx >> 3, c2 = idx & 7;
       const int64_t Q = Q0 + row;
       ra[h] = (Q < a.naux_p) ? *reinterpret_cast<const d2v *>(Ab + Q * a.PW + 2 * c2)
                              : d2v{0.0, 0.0};
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int idx = t + h * kThreads;
+      const int idx = t + h * kGThreads;
       if constexpr (!TB) {
-        const int row = idx >> 6, c2 = idx & 63;   // 8 rows x 64 double2
+        const int row = idx >> 6, c2 = idx & 63;   // 16 rows x 64 double2
         const int64_t n = n0 + 2 * c2;
         rb[h] = (n < a.Ncols) ? *reinterpret_cast<const d2v *>(G + (k0 + row) * a.ldg + n)
                               : d2v{0.0, 0.0};
       } else {
-        const int nr = idx >> 2, c2 = idx & 3;     // 128 n-rows x 4 double2
+        const int nr = idx >> 3, c2 = idx & 7;     // 128 n-rows x 8 double2
         const int64_t n = n0 + nr;
         rb[h] = (n < a.Ncols) ? *reinterpret_cast<const d2v *>(G + n * a.ldg + k0 + 2 * c2)
                               : d2v{0.0, 0.0};
@@ -531,19 +535,19 @@ __global__ __launch_bounds__(256) void gemm_adj_fp64_kernel(const double *__rest
   auto sstore = [&](int b) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int idx = t + h * kThreads;
-      const int row = idx >> 2, c2 = idx & 3;
+      const int idx = t + h * kGThreads;
+      const int row = idx >> 3, c2 = idx & 7;
       sA[b][row * kGA + 2 * c2] = ra[h][0];
       sA[b][row * kGA + 2 * c2 + 1] = ra[h][1];
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int idx = t + h * kThreads;
+      const int idx = t + h * kGThreads;
       if constexpr (!TB) {
         const int row = idx >> 6, c2 = idx & 63;
         *reinterpret_cast<d2v *>(&sB[b][row * kGT + ((2 * c2) ^ swz(row))]) = rb[h];
       } else {
-        const int nr = idx >> 2, c2 = idx & 3;
+        const int nr = idx >> 3, c2 = idx & 7;
         const int k0 = 2 * c2, k1 = 2 * c2 + 1;
         sB[b][k0 * kGT + (nr ^ swz(k0))] = rb[h][0];
         sB[b][k1 * kGT + (nr ^ swz(k1))] = rb[h][1];
@@ -561,15 +565,15 @@ __global__ __launch_bounds__(256) void gemm_adj_fp64_kernel(const double *__rest
 #pragma unroll
     for (int kk = 0; kk < kGK / 4; ++kk) {
       const int k = kk * 4 + kl;
-      double fa[4], fb[4];
+      double fa[4], fb[2];
 #pragma unroll
       for (int p = 0; p < 4; ++p) fa[p] = LA[(64 * wr + 16 * p + cl) * kGA + k];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) fb[q] = LB[k * kGT + ((64 * wc + 16 * q + cl) ^ swz(k))];
+      for (int q = 0; q < 2; ++q) fb[q] = LB[k * kGT + ((32 * wc + 16 * q + cl) ^ swz(k))];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[p][q] = mfma64(fa[p], fb[q], acc[p][q]);
+        for (int q = 0; q < 2; ++q) acc[p][q] = mfma64(fa[p], fb[q], acc[p][q]);
     }
     if (k0 + kGK < a.K) {
       sstore(b ^ 1);
@@ -579,8 +583,8 @@ __global__ __launch_bounds__(256) void gemm_adj_fp64_kernel(const double *__rest
     b ^= 1;
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int64_t n = n0 + 64 * wc + 16 * q + cl;
+  for (int q = 0; q < 2; ++q) {
+    const int64_t n = n0 + 32 * wc + 16 * q + cl;
     if (n >= a.Ncols) continue;
     const int64_t grp = n / a.GP, cc = n % a.GP;
     if (cc >= a.nvalid) continue;
@@ -617,7 +621,7 @@ static hipError_t gemm(const Plan &pl, const double *Apan, int PW, int64_t npan,
   a.accumulate = accumulate ? 1 : 0;
   const dim3 grid((unsigned)ceil_div(pl.naux, kGT), (unsigned)ceil_div(Ncols, kGT));
   timer_begin(TB ? "gemm_adj_tb_fp64" : "gemm_adj_fp64", st);
-  hipLaunchKernelGGL(gemm_adj_fp64_kernel<TB>, grid, dim3(256), 0, st, Apan, G, a, C);
+  hipLaunchKernelGGL(gemm_adj_fp64_kernel<TB>, grid, dim3(kGThreads), 0, st, Apan, G, a, C);
   timer_end(st);
   return hipGetLastError();
 }
