@@ -99,7 +99,6 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   pl.ntv = ceil_div(pl.nv, kPanel);
   pl.ntv_s = (precision == DSRG_SPLIT_OZAKI) ? round_up(pl.ntv, 2) : pl.ntv;
   pl.xld = pl.ntv_s * kPanel;
-  pl.cavv_tile = (pl.na <= 2) ? 64 : 32;
 
   const int64_t npo = tri_off(pl.nc), ntpo = tri_off(pl.ntv);
   // one slot per (core pair, tile pair): 64-wide tiles in FP64, 128-wide on slices
@@ -108,14 +107,14 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
               : (precision == DSRG_SPLIT_OZAKI)
                   ? (pl.nc * (pl.nc + 1) / 2) * (nt2 * (nt2 + 1) / 2)
                   : (npo * ntpo + npo * pl.ntv + pl.nc * ntpo + pl.nc * pl.ntv);
-  const int64_t ntw = ceil_div(pl.nv, pl.cavv_tile);
   const bool split = precision == DSRG_SPLIT_OZAKI;
   const bool has_cavv = (term_bits & DSRG_TERM_CAVV) && pl.na > 0;
   const bool has_ccav = (term_bits & DSRG_TERM_CCAV) && pl.na > 0;
   pl.nqc = ceil_div(pl.naux, 32);
-  // forward CAVV (both precisions) goes through batches of (me|uf) integrals
-  // of at most 4 GiB (one batch up to nc = 23, na = 6, nv = 1100 and beyond)
-  const bool xbatch = has_cavv && (!pl.with_grad || split);
+  // CAVV (energy and adjoint, both precisions) goes through batches of
+  // (me|uf) integrals of at most 4 GiB (one batch up to nc = 23, na = 6,
+  // nv = 1100 and beyond)
+  const bool xbatch = has_cavv;
   if (xbatch) {
     const int64_t per_m = pl.na * pl.xld * pl.xld * 8;
     pl.cavv_mb = ((int64_t)4 << 30) / per_m;
@@ -124,9 +123,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   } else {
     pl.cavv_mb = 0;
   }
-  pl.n_cavv = !has_cavv                ? 0
-              : pl.with_grad && !split ? pl.nc * (tri_off(ntw) + ntw)
-                             : pl.nc * (ceil_div(pl.nv, 16) * (ceil_div(pl.nv, 16) + 1) / 2);
+  pl.n_cavv = has_cavv ? pl.nc * (ceil_div(pl.nv, 16) * (ceil_div(pl.nv, 16) + 1) / 2) : 0;
   pl.ccav_cols = round_up(pl.nc * pl.na, 16);
   // forward: one slot per (m <= n, 256 virtual orbitals); adjoint: per (m <= n, 64-tile)
   pl.n_ccav = has_ccav

@@ -8,7 +8,9 @@
 //   Gs[(j,b)][(i,a)] = 2 dL/d(ia|jb)          (CCVV, symmetric N x N)
 //   G2[(m,e)][(w,f)] = dL/d(me|wf)            (CAVV)
 //   G3[(m,e)][(n,w)] = dL/d(me|nw)            (CCAV)
-// with N = nc * ntv * 64 padded core-virtual rows. Step 2 (adjoint GEMMs):
+// with N = nc * ntv * 64 padded core-virtual rows. The CAVV integrals are
+// formed in batches of core orbitals by the forward producer and G2 is written
+// by the adjoint epilogue shared with the slice path. Step 2 (adjoint GEMMs):
 // dB^Q_{pq} = sum over the contracted index pair of B^Q times the adjoint
 // tile (the chain rule through Eq. int_fact):
 //   dB_cv = Pcv . Gs + Pav . G2^T + Pca . G3^T,  dB_av = Pcv . G2,  dB_ca = Pcv . G3.
@@ -182,178 +184,6 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
     atomicAdd(&g.deps_c[c.i], gE0 * tD);
     atomicAdd(&g.deps_c[c.j], gE0 * tD);
     atomicAdd(g.ds, gE0 * tS);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// CAVV adjoint tiles for (m, A <= B). Per (e,f) and active w (X_u = (me|uf),
-// Y_u = (mf|ue) = (me|uf) with e<->f):
-//   A_w  = sum_v Gamma_wv R1_v (2X_v - Y_v),  A'_w = sum_v Gamma_wv R1_v (2Y_v - X_v)
-//   C_w  = sum_u Gamma_uw S_u X_u,            C'_w = sum_u Gamma_uw S_u Y_u
-//   dL/d(me|wf) = gE1 [S_w A_w  + R1_w (2C_w  - C'_w)]   -> G2[(m,e)][(w,f)]
-//   dL/d(mf|we) = gE1 [S_w A'_w + R1_w (2C'_w - C_w )]   -> G2[(m,f)][(w,e)]
-//   dE/dD^{mw}_{ef} = X_w A_w S'_w + (2X_w - Y_w) C_w R1'_w  (+ the (f,e) mirror)
-// Diagonal tiles (A = B) cover both orientations through their own
-// elements, carry weight 1/2 in the sums and write only the first block.
-// ---------------------------------------------------------------------------
-struct CavvAdjArgs {
-  int nc, na, nv, ntv, ntw;
-  int64_t naux_p;
-  double s;
-  int64_t n0;
-  int64_t slot_base;
-  int64_t N2;   // row length of G2 = na * ntv * 64
-};
-
-template <int NA, int TW>
-__global__ __launch_bounds__(256) void cavv_adj_fp64_kernel(
-    const double *__restrict__ Pcv, const double *__restrict__ Pav,
-    const double *__restrict__ eps_c, const double *__restrict__ eps_a,
-    const double *__restrict__ eps_v, const double *__restrict__ gamma1, CavvAdjArgs a,
-    GradOut g, double *__restrict__ G2, double *slots) {
-  using Cfg = CavvCfg<NA, TW>;
-  constexpr int HB = Cfg::HB, HW = Cfg::HW;
-  constexpr int LDSN = (Cfg::LDS > NA * TW * (TW + 1)) ? Cfg::LDS : NA * TW * (TW + 1);
-  __shared__ double lds[LDSN];
-  __shared__ double rsum[TW], csum[TW], asum[NA];
-  const CavvWork c = decode_cavv(blockIdx.x, a.ntw, a.n0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int cl = lane & 15, kl = lane >> 4;
-  d4 X[NA][HB][HB], Y[NA][HB][HB];
-  cavv_compute<NA, TW>(Pcv, Pav, a.naux_p, a.ntv, c, lds, X, Y, wr, wc, cl, kl);
-  if (threadIdx.x < TW) {
-    rsum[threadIdx.x] = 0.0;
-    csum[threadIdx.x] = 0.0;
-  }
-  if (threadIdx.x < NA) asum[threadIdx.x] = 0.0;
-  __syncthreads();
-
-  const double gE1 = g.gE[1];
-  const double wgt = c.diag ? 0.5 : 1.0;
-  double Gm[NA][NA], ea[NA];
-#pragma unroll
-  for (int u = 0; u < NA; ++u) {
-    ea[u] = eps_a[u];
-#pragma unroll
-    for (int v = 0; v < NA; ++v) Gm[u][v] = gamma1[u * NA + v];
-  }
-  const double em = eps_c[c.m];
-  double e_part = 0.0, d_part = 0.0, s_part = 0.0, dw[NA], csl[HB];
-#pragma unroll
-  for (int u = 0; u < NA; ++u) dw[u] = 0.0;
-#pragma unroll
-  for (int q = 0; q < HB; ++q) csl[q] = 0.0;
-  // transposed-orientation values, staged through LDS per w afterwards
-  double gT[NA][HB][HB][4];
-  const int64_t rowM = (int64_t)c.m * a.ntv * kPanel;
-#pragma unroll
-  for (int p = 0; p < HB; ++p) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int el = HW * wr + 16 * p + 4 * r + kl;
-      const int e = c.A * TW + el;
-      double rs = 0.0;
-#pragma unroll
-      for (int q = 0; q < HB; ++q) {
-        const int fl = HW * wc + 16 * q + cl;
-        const int f = c.B * TW + fl;
-        const bool ok = (e < a.nv) && (f < a.nv);
-        double S[NA], R1[NA], dS[NA], dR1[NA], sS[NA], sR1[NA];
-        const double base = em - ((ok ? eps_v[e] : 0.0) + (ok ? eps_v[f] : 0.0));
-#pragma unroll
-        for (int u = 0; u < NA; ++u)
-          reg_S_R1_grad(base + ea[u], a.s, S[u], R1[u], dS[u], dR1[u], sS[u], sR1[u]);
-        double Wv[NA], Wp[NA], Av[NA], Ap[NA], Cv[NA], Cp[NA];
-#pragma unroll
-        for (int v = 0; v < NA; ++v) {
-          const double xv = X[v][p][q][r], yv = Y[v][p][q][r];
-          Wv[v] = 2.0 * xv - yv;
-          Wp[v] = 2.0 * yv - xv;
-        }
-#pragma unroll
-        for (int w = 0; w < NA; ++w) {
-          double sa = 0.0, sp = 0.0, ca = 0.0, cp = 0.0;
-#pragma unroll
-          for (int v = 0; v < NA; ++v) {
-            sa += Gm[w][v] * R1[v] * Wv[v];
-            sp += Gm[w][v] * R1[v] * Wp[v];
-            ca += Gm[v][w] * S[v] * X[v][p][q][r];
-            cp += Gm[v][w] * S[v] * Y[v][p][q][r];
-          }
-          Av[w] = sa;
-          Ap[w] = sp;
-          Cv[w] = ca;
-          Cp[w] = cp;
-        }
-        double dsum = 0.0;
-#pragma unroll
-        for (int w = 0; w < NA; ++w) {
-          const double xw = X[w][p][q][r], yw = Y[w][p][q][r];
-          const double gn = ok ? gE1 * (S[w] * Av[w] + R1[w] * (2.0 * Cv[w] - Cp[w])) : 0.0;
-          const double gt = ok ? gE1 * (S[w] * Ap[w] + R1[w] * (2.0 * Cp[w] - Cv[w])) : 0.0;
-          G2[(rowM + c.A * TW + el) * a.N2 + (int64_t)w * a.ntv * kPanel + c.B * TW + fl] = gn;
-          gT[w][p][q][r] = gt;
-          if (ok) {
-            e_part += wgt * S[w] * (xw * Av[w] + yw * Ap[w]);
-            const double dd = wgt * (xw * Av[w] * dS[w] + Wv[w] * Cv[w] * dR1[w] +
-                                     yw * Ap[w] * dS[w] + Wp[w] * Cp[w] * dR1[w]);
-            s_part += wgt * (xw * Av[w] * sS[w] + Wv[w] * Cv[w] * sR1[w] +
-                             yw * Ap[w] * sS[w] + Wp[w] * Cp[w] * sR1[w]);
-            dw[w] += dd;
-            dsum += dd;
-          }
-        }
-        d_part += dsum;
-        rs += dsum;
-        csl[q] += dsum;
-      }
-      if (rs != 0.0) atomicAdd(&rsum[HW * wr + 16 * p + 4 * r + kl], rs);
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < HB; ++q)
-    if (csl[q] != 0.0) atomicAdd(&csum[HW * wc + 16 * q + cl], csl[q]);
-#pragma unroll
-  for (int w = 0; w < NA; ++w)
-    if (dw[w] != 0.0) atomicAdd(&asum[w], dw[w]);
-  if (!c.diag) {
-    // G2[(m,f)][(w,e)] = gt: stage each w's tile as T_w[e][f] and write transposed
-    double *T = lds;
-#pragma unroll
-    for (int w = 0; w < NA; ++w)
-#pragma unroll
-      for (int p = 0; p < HB; ++p)
-#pragma unroll
-        for (int q = 0; q < HB; ++q)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            T[(w * TW + HW * wr + 16 * p + 4 * r + kl) * (TW + 1) + HW * wc + 16 * q + cl] =
-                gT[w][p][q][r];
-    __syncthreads();
-    for (int k = threadIdx.x; k < NA * TW * TW; k += kThreads) {
-      const int w = k / (TW * TW), rem = k % (TW * TW);
-      const int fl = rem / TW, el = rem % TW;
-      G2[(rowM + c.B * TW + fl) * a.N2 + (int64_t)w * a.ntv * kPanel + c.A * TW + el] =
-          T[(w * TW + el) * (TW + 1) + fl];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < TW) {
-    const int t = threadIdx.x;
-    if (c.A * TW + t < a.nv) atomicAdd(&g.deps_v[c.A * TW + t], -gE1 * rsum[t]);
-    if (c.B * TW + t < a.nv) atomicAdd(&g.deps_v[c.B * TW + t], -gE1 * csum[t]);
-  }
-  if (threadIdx.x < NA) atomicAdd(&g.deps_a[threadIdx.x], gE1 * asum[threadIdx.x]);
-  const double tE = block_sum(e_part, lds);
-  __syncthreads();
-  const double tD = block_sum(d_part, lds);
-  __syncthreads();
-  const double tS = block_sum(s_part, lds);
-  if (threadIdx.x == 0) {
-    slots[a.slot_base + blockIdx.x] = tE;
-    atomicAdd(&g.deps_c[c.m], gE1 * tD);
-    atomicAdd(g.ds, gE1 * tS);
   }
 }
 
@@ -630,34 +460,6 @@ template <int NA>
 static hipError_t launch_adj_act(const Plan &pl, const Inputs &in, const GradOut &g, void *ws,
                                  int mask, hipStream_t st) {
   double *slots = ws_d(ws, pl.off_slots);
-  const int64_t N2 = pl.na * pl.ntv * kPanel;
-  if ((pl.terms & mask & 2)) {
-    CavvAdjArgs a;
-    a.nc = (int)pl.nc;
-    a.na = (int)pl.na;
-    a.nv = (int)pl.nv;
-    a.ntv = (int)pl.ntv;
-    a.ntw = (int)ceil_div(pl.nv, pl.cavv_tile);
-    a.naux_p = pl.naux_p;
-    a.s = pl.s;
-    a.n0 = pl.nc * tri_off(a.ntw);
-    a.slot_base = pl.slot_base[1];
-    a.N2 = N2;
-    timer_begin("cavv_adj_fp64", st);
-    if (pl.cavv_tile == 64) {
-      if constexpr (NA <= 2)
-        hipLaunchKernelGGL((cavv_adj_fp64_kernel<NA, 64>), dim3((unsigned)pl.n_cavv), dim3(256),
-                           0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), in.eps_c,
-                           in.eps_a, in.eps_v, in.gamma1, a, g, ws_d(ws, pl.off_g2), slots);
-    } else {
-      hipLaunchKernelGGL((cavv_adj_fp64_kernel<NA, 32>), dim3((unsigned)pl.n_cavv), dim3(256), 0,
-                         st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), in.eps_c, in.eps_a,
-                         in.eps_v, in.gamma1, a, g, ws_d(ws, pl.off_g2), slots);
-    }
-    timer_end(st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   if ((pl.terms & mask & 4)) {
     CcavAdjArgs a;
     a.nc = (int)pl.nc;
@@ -714,12 +516,18 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (cavv && pl.ntv * kPanel != ceil_div(pl.nv, pl.cavv_tile) * pl.cavv_tile) {
-    // CAVV tiles do not reach the end of the padded panels: clear G2 first
+  if (cavv) {
+    // G2 from batches of FP64 integrals; its padding rows and columns are
+    // never written by the epilogue but are read by the adjoint GEMMs
     if ((e = zero_fill(ws_d(ws, pl.off_g2), Np * pl.na * pl.ntv * kPanel, st)) != hipSuccess)
       return e;
+    for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
+      const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
+      if ((e = launch_cavv_x_fp64(pl, ws, (int)m0, mb, st)) != hipSuccess) return e;
+      if ((e = launch_cavv_adj_epi(pl, in, o, ws, (int)m0, mb, st)) != hipSuccess) return e;
+    }
   }
-  if (cavv || ccav) {
+  if (ccav) {
     switch (pl.na) {
       case 1: e = launch_adj_act<1>(pl, in, g, ws, mask, st); break;
       case 2: e = launch_adj_act<2>(pl, in, g, ws, mask, st); break;

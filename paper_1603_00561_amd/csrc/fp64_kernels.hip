@@ -437,27 +437,31 @@ static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hip
     default: return hipErrorInvalidValue;       \
   }
 
+hipError_t launch_cavv_x_fp64(const Plan &pl, void *ws, int m0, int mb, hipStream_t st) {
+  CavvXArgs64 xa;
+  xa.na = (int)pl.na;
+  xa.ntv = (int)pl.ntv;
+  xa.naux_p = pl.naux_p;
+  xa.m0 = m0;
+  xa.mb = mb;
+  const int64_t items = pairtile_grid((int64_t)mb * pl.na, pl.ntv);
+  const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
+  int *ctr = reinterpret_cast<int *>(ws_d(ws, pl.off_ctr));
+  hipError_t e = launch_zero(ws_d(ws, pl.off_ctr), 4, st);
+  if (e != hipSuccess) return e;
+  timer_begin("cavv_fp64_x", st);
+  hipLaunchKernelGGL(cavv_fp64_x_kernel, dim3((unsigned)grid), dim3(256), 0, st,
+                     ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), xa, ctr, ws_d(ws, pl.off_xb));
+  timer_end(st);
+  return hipGetLastError();
+}
+
 static hipError_t launch_cavv(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                               double *, double *) {
   for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
     const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
-    CavvXArgs64 xa;
-    xa.na = (int)pl.na;
-    xa.ntv = (int)pl.ntv;
-    xa.naux_p = pl.naux_p;
-    xa.m0 = (int)m0;
-    xa.mb = mb;
-    const int64_t items = pairtile_grid((int64_t)mb * pl.na, pl.ntv);
-    const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
-    int *ctr = reinterpret_cast<int *>(ws_d(ws, pl.off_ctr));
-    hipError_t e = launch_zero(ws_d(ws, pl.off_ctr), 4, st);
+    hipError_t e = launch_cavv_x_fp64(pl, ws, (int)m0, mb, st);
     if (e != hipSuccess) return e;
-    timer_begin("cavv_fp64_x", st);
-    hipLaunchKernelGGL(cavv_fp64_x_kernel, dim3((unsigned)grid), dim3(256), 0, st,
-                       ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), xa, ctr,
-                       ws_d(ws, pl.off_xb));
-    timer_end(st);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_cavv_epi(pl, in, ws, (int)m0, mb, st)) != hipSuccess) return e;
   }
   return hipSuccess;

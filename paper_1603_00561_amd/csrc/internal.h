@@ -49,7 +49,6 @@ struct Plan {
 
   // work counts (workgroups) per term
   int64_t n_ccvv, n_cavv, n_ccav;
-  int cavv_tile;    // 32 or 64 columns per CAVV tile side
   int64_t ccav_cols; // padded (n, u) column count of the CCAV integral block
 
   // workspace layout (byte offsets, 256-aligned)
@@ -101,6 +100,12 @@ hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, i
                            hipStream_t st);
 // (me|uf) integral batch Xb for core orbitals m0 .. m0+mb-1 from the slices
 hipError_t launch_cavv_x_split(const Plan &pl, void *ws, int m0, int mb, hipStream_t st);
+// FP64 integrals X^{mu}[e][f] = (me|uf) of core orbitals m0 .. m0+mb-1 into the batch buffer
+hipError_t launch_cavv_x_fp64(const Plan &pl, void *ws, int m0, int mb, hipStream_t st);
+// CAVV adjoint epilogue over one integral batch: G2, the CAVV energy slots and
+// the orbital-energy / flow-parameter gradient parts
+hipError_t launch_cavv_adj_epi(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                               int m0, int mb, hipStream_t st);
 // int8 slices of B_cv (with the FP64 diagonal) and, if with_av, of B_av
 hipError_t launch_slices(const Plan &pl, const Inputs &in, void *ws, bool with_av,
                          hipStream_t st);

@@ -526,7 +526,7 @@ static hipError_t cavv_adj_epi_na(const Plan &pl, const Inputs &in, const BwdOut
   return hipGetLastError();
 }
 
-static hipError_t cavv_adj_epi(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+hipError_t launch_cavv_adj_epi(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                int m0, int mb, hipStream_t st) {
   switch (pl.na) {
     case 1: return cavv_adj_epi_na<1>(pl, in, o, ws, m0, mb, st);
@@ -623,7 +623,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
       const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
       if ((e = launch_cavv_x_split(pl, ws, (int)m0, mb, st)) != hipSuccess) return e;
-      if ((e = cavv_adj_epi(pl, in, o, ws, (int)m0, mb, st)) != hipSuccess) return e;
+      if ((e = launch_cavv_adj_epi(pl, in, o, ws, (int)m0, mb, st)) != hipSuccess) return e;
     }
   }
   if (pl.terms & 1) {
