@@ -104,3 +104,40 @@ def test_cfg3_all_s():
     for s in (0.1, 0.5, 1.0):
         p = make_config("cfg3", s=s)
         check(gpu_E(p), r["E_s%g" % s])
+
+
+def _balanced_digits(v, n=4):
+    """Round-to-nearest digits of v in (-1, 1]: 127 v = d0 + (d1 + (d2 + ...)/254)/254."""
+    r, d = 127.0 * v, []
+    for _ in range(n):
+        s = np.rint(r)
+        d.append(int(s))
+        r = (r - s) * 254.0
+    return d
+
+
+def test_naux_limit_near_worst_case_level_sums():
+    """naux = 33000, the largest contraction the slice path accepts, with every
+    element of B equal to c = 2^-10 (126 + (126 + (126 + 126/254)/254)/254)/127.
+    Every column then has scale 2^-10 and digits (126, 126, 126, 126), so the
+    level-3 int32 sums of the off-diagonal integrals reach
+    2 (126*126 + 126*126) * 33000 = 2.096e9, 97.6 % of 2^31: a wrapped sum
+    would show as an O(1) relative error."""
+    c = (126 + (126 + (126 + 126 / 254) / 254) / 254) / 127
+    d = _balanced_digits(c)
+    assert d == [126, 126, 126, 126]
+    naux = 33000
+    level3 = 2 * (d[0] * d[3] + d[1] * d[2]) * naux
+    assert 0.97 * 2**31 < level3 < 2**31
+    p = make_problem(2, 1, 40, naux, s=0.5, seed=33)
+    v = c * 2.0**-10
+    p.B_cv = np.full_like(p.B_cv, v)
+    p.B_ca = np.full_like(p.B_ca, v)
+    p.B_av = np.full_like(p.B_av, v)
+    Eo = np.array(O.energy_terms(p))
+    assert np.abs(Eo).max() > 0.1
+    check(gpu_E(p), Eo)
+    # the FP64 path on the same input, at its own gate (33000 equal terms per
+    # integral: summation order alone moves the sums by ~1e-12 relative)
+    E64 = _b().energy(*_dev(p), p.s).cpu().numpy()
+    assert np.all(np.abs(E64 - Eo) <= 1e-10), (E64, Eo, np.abs(E64 - Eo))

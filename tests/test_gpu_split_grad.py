@@ -152,3 +152,19 @@ def test_backward_is_deterministic():
     g2 = split_grad(p, (1.0, 1.0, 1.0))
     for k in ("B_cv", "B_ca", "B_av"):
         assert np.array_equal(g1[k], g2[k]), k
+
+
+def test_naux_limit_near_worst_case_level_sums():
+    """The energy test's stress input at naux = 33000 (every B element with
+    digits (126, 126, 126, 126), level-3 int32 sums at 97.6 % of 2^31) through
+    the slice-path adjoint products."""
+    c = (126 + (126 + (126 + 126 / 254) / 254) / 254) / 127
+    p = make_problem(2, 1, 40, 33000, s=0.5, seed=33)
+    v = c * 2.0**-10
+    p.B_cv = np.full_like(p.B_cv, v)
+    p.B_ca = np.full_like(p.B_ca, v)
+    p.B_av = np.full_like(p.B_av, v)
+    gE = (1.0, 0.75, -0.5)
+    g = split_grad(p, gE)
+    compare(g, O.gradients(p, gE))
+    assert np.allclose(g["E"], O.energy_terms(p), rtol=0, atol=1e-6)
