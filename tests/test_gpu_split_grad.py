@@ -168,3 +168,14 @@ def test_naux_limit_near_worst_case_level_sums():
     g = split_grad(p, gE)
     compare(g, O.gradients(p, gE))
     assert np.allclose(g["E"], O.energy_terms(p), rtol=0, atol=1e-6)
+
+
+def test_adjoint_gemm_contraction_segments():
+    """nc = 513 core orbitals with nv = 8: the padded core-virtual index runs to
+    513 * 64 = 32832 > 32768, so the int8 adjoint products over it are taken in
+    two exact int32 segments whose FP64 results are summed."""
+    p = make_problem(513, 1, 8, 8, s=0.5, seed=41)
+    assert p.nc * 64 > 32768
+    gE = (1.0, 0.75, -0.5)
+    g = split_grad(p, gE)
+    compare(g, O.gradients(p, gE))
