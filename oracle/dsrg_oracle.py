@@ -27,6 +27,24 @@ with R(D) = (1 - exp(-2 s D^2)) / D (Eq. expensive),
 R1(D) = (1 - exp(-s D^2)) / D (Eq. T2amp), S(D) = 1 + exp(-s D^2)
 (Eq. v_tilde). At D == 0 the regularisers take their limits R = R1 = 0.
 
+The remaining pieces F4-F8 of Table II (two or more active indices) also
+read the active-active block B_aa[Q][u][v]. With etab = 2 I - Gamma and
+x, y, u, v, w, z active, the same spin summation gives
+
+  F4 = 1/4 sum Gamma_xy Gamma_uv sum_{ef} (xe|uf) S(D^{ef}_{xu})
+                                      [2 (ye|vf) - (yf|ve)] R1(D^{ef}_{yv})
+  F5 = 1/4 sum etab_uv etab_xy sum_{mn} (mv|ny) S(D^{vy}_{mn})
+                                      [2 (mu|nx) - (mx|nu)] R1(D^{ux}_{mn})
+  F6 = sum Gamma_xy etab_uv sum_{me} S(D^{ve}_{mx}) R1(D^{ue}_{my})
+       [K1 K1' + K2 K2' - (K1 K2' + K2 K1') / 2],
+       K1 = (mv|xe), K2 = (me|xv), K1' = (mu|ye), K2' = (me|yu)
+  F7 = 1/4 sum Gamma_yw Gamma_zx etab_uv sum_e (yv|ze) S(D^{ve}_{yz})
+                                      [2 (wu|xe) - (we|xu)] R1(D^{ue}_{wx})
+  F8 = 1/4 sum Gamma_wz etab_uv etab_xy sum_m (mv|wy) S(D^{vy}_{mw})
+                                      [2 (mu|zx) - (mx|zu)] R1(D^{ux}_{mz})
+
+(each pinned against ``brute_force_spinorbital``).
+
 Regularisers use libm ``expm1``; every sum over many elements is a
 ``math.fsum``. Gradients are written out from the same formulas by the chain
 rule, term by term, in separate plain code.
@@ -189,6 +207,111 @@ def energy_terms(p, terms=("ccvv", "cavv", "ccav")) -> Tuple[float, float, float
     e3 = (energy_ccav(p.B_cv, p.B_ca, p.eps_c, p.eps_a, p.eps_v, p.gamma1, p.s)
           if "ccav" in terms else 0.0)
     return e1, e2, e3
+
+
+# ---------------------------------------------------------------------------
+# F4-F8 of Table II (spin-summed forms in the module docstring)
+# ---------------------------------------------------------------------------
+def energy_f4(B_av, eps_a, eps_v, gamma1, s) -> float:
+    """F4: two active hole indices, two virtual particle indices."""
+    naux, na, nv = B_av.shape
+    if na == 0 or s == 0.0:
+        return 0.0
+    # X[x, u][e, f] = (xe|uf)
+    X = np.einsum("Qxe,Quf->xuef", B_av, B_av)
+    D = (eps_a[:, None, None, None] + eps_a[None, :, None, None]
+         - eps_v[None, None, :, None] - eps_v[None, None, None, :])     # D^{ef}_{xu}
+    Z = X * reg_S(D, s)                                                # (xe|uf) S
+    W = (2.0 * X - X.transpose(0, 1, 3, 2)) * reg_R1(D, s)             # [2(ye|vf) - (yf|ve)] R1
+    parts = []
+    for x in range(na):
+        for u in range(na):
+            T = sum(gamma1[x, y] * gamma1[u, v] * W[y, v] for y in range(na) for v in range(na))
+            parts.append(_fsum(Z[x, u] * T))
+    return 0.25 * math.fsum(parts)
+
+
+def energy_f5(B_ca, eps_c, eps_a, gamma1, s) -> float:
+    """F5: two core hole indices, two active particle indices."""
+    naux, nc, na = B_ca.shape
+    if na == 0 or s == 0.0:
+        return 0.0
+    etab = 2.0 * np.eye(na) - gamma1
+    parts = []
+    for m in range(nc):
+        for n in range(nc):
+            K = B_ca[:, m, :].T @ B_ca[:, n, :]                    # K[v, y] = (mv|ny)
+            D = eps_c[m] + eps_c[n] - eps_a[:, None] - eps_a[None, :]   # D^{vy}_{mn}
+            Z = K * reg_S(D, s)
+            W = (2.0 * K - K.T) * reg_R1(D, s)                     # W[u, x] = [2(mu|nx) - (mx|nu)] R1
+            parts.append(_fsum(Z * (etab @ W @ etab)))             # sum etab_vu W_ux etab_xy
+    return 0.25 * math.fsum(parts)
+
+
+def energy_f6(B_cv, B_ca, B_av, B_aa, eps_c, eps_a, eps_v, gamma1, s) -> float:
+    """F6: one core and one active hole index, one active and one virtual
+    particle index."""
+    naux, nc, nv = B_cv.shape
+    na = B_ca.shape[2]
+    if na == 0 or s == 0.0:
+        return 0.0
+    etab = 2.0 * np.eye(na) - gamma1
+    parts = []
+    for m in range(nc):
+        K1 = np.einsum("Qv,Qxe->vxe", B_ca[:, m, :], B_av)        # (mv|xe)
+        K2 = np.einsum("Qe,Qxv->vxe", B_cv[:, m, :], B_aa)        # (me|xv)
+        D = (eps_c[m] + eps_a[None, :, None] - eps_a[:, None, None]
+             - eps_v[None, None, :])                              # D^{ve}_{mx} at [v, x, e]
+        S_, R1_ = reg_S(D, s), reg_R1(D, s)
+        Z1, Z2 = K1 * S_, K2 * S_
+        W1, W2 = K1 * R1_, K2 * R1_                               # at [u, y, e]
+        # sum_{uy} etab_vu W[u, y] Gamma_yx, for each e
+        M1 = np.einsum("vu,uye,yx->vxe", etab, W1, gamma1)
+        M2 = np.einsum("vu,uye,yx->vxe", etab, W2, gamma1)
+        parts.append(_fsum(Z1 * M1 + Z2 * M2 - 0.5 * (Z1 * M2 + Z2 * M1)))
+    return math.fsum(parts)
+
+
+def energy_f7(B_av, B_aa, eps_a, eps_v, gamma1, s) -> float:
+    """F7: two active hole indices, one active and one virtual particle index."""
+    naux, na, nv = B_av.shape
+    if na == 0 or s == 0.0:
+        return 0.0
+    etab = 2.0 * np.eye(na) - gamma1
+    C = np.einsum("Qyv,Qze->yvze", B_aa, B_av)                    # C[y, v, z, e] = (yv|ze)
+    D = (eps_a[:, None, None, None] + eps_a[None, None, :, None]
+         - eps_a[None, :, None, None] - eps_v[None, None, None, :])  # D^{ve}_{yz}
+    Z = C * reg_S(D, s)
+    W = (2.0 * C - C.transpose(2, 1, 0, 3)) * reg_R1(D, s)        # at [w, u, x, e]
+    T = np.einsum("yw,vu,zx,wuxe->yvze", gamma1, etab, gamma1, W)
+    return 0.25 * _fsum(Z * T)
+
+
+def energy_f8(B_ca, B_aa, eps_c, eps_a, gamma1, s) -> float:
+    """F8: one core and one active hole index, two active particle indices."""
+    naux, nc, na = B_ca.shape
+    if na == 0 or s == 0.0:
+        return 0.0
+    etab = 2.0 * np.eye(na) - gamma1
+    parts = []
+    for m in range(nc):
+        E = np.einsum("Qv,Qwy->vwy", B_ca[:, m, :], B_aa)         # E[v, w, y] = (mv|wy)
+        D = (eps_c[m] + eps_a[None, :, None] - eps_a[:, None, None]
+             - eps_a[None, None, :])                              # D^{vy}_{mw}
+        Z = E * reg_S(D, s)
+        W = (2.0 * E - E.transpose(2, 1, 0)) * reg_R1(D, s)       # at [u, z, x]
+        T = np.einsum("vu,wz,yx,uzx->vwy", etab, gamma1, etab, W)
+        parts.append(_fsum(Z * T))
+    return 0.25 * math.fsum(parts)
+
+
+def active_terms(p) -> Tuple[float, float, float, float, float]:
+    """(F4, F5, F6, F7, F8) for a workloads.Problem-like object with B_aa."""
+    return (energy_f4(p.B_av, p.eps_a, p.eps_v, p.gamma1, p.s),
+            energy_f5(p.B_ca, p.eps_c, p.eps_a, p.gamma1, p.s),
+            energy_f6(p.B_cv, p.B_ca, p.B_av, p.B_aa, p.eps_c, p.eps_a, p.eps_v, p.gamma1, p.s),
+            energy_f7(p.B_av, p.B_aa, p.eps_a, p.eps_v, p.gamma1, p.s),
+            energy_f8(p.B_ca, p.B_aa, p.eps_c, p.eps_a, p.gamma1, p.s))
 
 
 def closed_shell_df_mp2(B_cv, eps_c, eps_v) -> float:

@@ -17,9 +17,12 @@ shapes stand in for them:
 * spin-summed active 1-RDM Gamma = O diag(lam) O^T, O from the QR of a
   standard-normal matrix with diag(R) > 0, lam_k = 1 + (v_k - mean v) /
   max(1, max_k |v_k - mean v|), v ~ U[-1, 1]: eigenvalues in [0, 2], trace na.
+* the active-active block B_aa [naux][na][na] (read only by the pieces F4-F8
+  of term F): (G + G^T) / 2 with G ~ N(0,1) * 0.05 * exp(-3 Q / naux), so
+  that it is symmetric in its two orbital indices like every block of B.
 
 One ``numpy.random.default_rng(seed)`` per problem, drawn in exactly the
-order listed above.
+order listed above (B_aa last, so the other inputs do not depend on it).
 """
 from __future__ import annotations
 
@@ -50,6 +53,7 @@ class Problem:
     name: str = "custom"
     seed: Optional[int] = None
     meta: dict = field(default_factory=dict)
+    B_aa: Optional[np.ndarray] = None   # [naux][na][na], symmetric in (u, v)
 
     def arrays(self):
         return (self.B_cv, self.B_ca, self.B_av, self.eps_c, self.eps_a,
@@ -59,7 +63,7 @@ class Problem:
         return Problem(self.nc, self.na, self.nv, self.naux, self.B_cv,
                        self.B_ca, self.B_av, self.eps_c, self.eps_a,
                        self.eps_v, self.gamma1, float(s), self.name,
-                       self.seed, dict(self.meta))
+                       self.seed, dict(self.meta), self.B_aa)
 
 
 # The five workload shapes: (nc, na, nv, naux, s, terms, gradient wanted).
@@ -79,6 +83,11 @@ CONFIGS = {
     "cfg5": dict(nc=23, na=6, nv=1100, naux=3000, s=0.5,
                  terms=("ccvv", "cavv", "ccav"), grad=True),
 }
+
+
+def _b_aa(rng: np.random.Generator, scale: np.ndarray, naux: int, na: int) -> np.ndarray:
+    g = rng.standard_normal((naux, na, na)) * scale
+    return 0.5 * (g + g.transpose(0, 2, 1))
 
 
 def _gamma(rng: np.random.Generator, na: int) -> np.ndarray:
@@ -108,8 +117,9 @@ def make_problem(nc: int, na: int, nv: int, naux: int, s: float = 0.5,
     eps_a = rng.uniform(-0.3, 0.1, size=na)
     eps_v = rng.uniform(0.1, 5.0, size=nv)
     gamma1 = _gamma(rng, na)
+    B_aa = _b_aa(rng, scale, naux, na)
     return Problem(nc, na, nv, naux, B_cv, B_ca, B_av, eps_c, eps_a, eps_v,
-                   gamma1, float(s), name, seed)
+                   gamma1, float(s), name, seed, B_aa=B_aa)
 
 
 def make_config(name: str, seed: int = DEFAULT_SEED, s: Optional[float] = None) -> Problem:
@@ -140,5 +150,6 @@ def make_near_degenerate(nc: int = 3, na: int = 2, nv: int = 20, naux: int = 48,
     pick_a = rng.integers(0, nc, size=na)
     eps_a = eps_c[pick_a] + rng.uniform(-2e-3, 2e-3, size=na)
     gamma1 = _gamma(rng, na)
+    B_aa = _b_aa(rng, scale, naux, na)
     return Problem(nc, na, nv, naux, B_cv, B_ca, B_av, eps_c, eps_a, eps_v,
-                   gamma1, float(s), "near_degenerate", seed)
+                   gamma1, float(s), "near_degenerate", seed, B_aa=B_aa)

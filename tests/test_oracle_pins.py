@@ -251,3 +251,79 @@ def test_cholesky_factor_reproduces_four_index_bruteforce():
     e = O.energy_terms(p)
     for k, v in zip(("F1", "F2", "F3"), e):
         assert abs(r[k] - v) <= 1e-12 * abs(r["F"]), k
+
+
+# --- Table II F4-F8 (two or more active indices) -------------------------------
+def _with_b_aa_bf(p):
+    B = O.full_symmetric_B(p.B_cv, p.B_ca, p.B_av, B_aa=p.B_aa)
+    return _bf(p, B)
+
+
+@pytest.mark.parametrize("shape,seed,s", [((2, 2, 3, 10), 5, 0.5), ((2, 1, 3, 8), 11, 1.0),
+                                          ((1, 3, 2, 9), 12, 0.1), ((3, 2, 2, 7), 13, 2.0),
+                                          ((2, 4, 3, 6), 14, 0.5)])
+def test_active_pieces_equal_spinorbital_table2(shape, seed, s):
+    # F4..F8 of Table II against the spin-orbital brute force of the same B
+    p = make_problem(*shape, s=s, seed=seed)
+    r = _with_b_aa_bf(p)
+    a = O.active_terms(p)
+    for k in range(5):
+        assert abs(r["F%d" % (k + 4)] - a[k]) <= 1e-13 * abs(r["F"]), k
+        assert a[k] != 0.0
+
+
+def test_active_pieces_golden_tiny_bruteforce_values():
+    # the stored brute-force values were taken with the random active-active
+    # block of full_symmetric_B; the spin-summed forms must reproduce them
+    with open(os.path.join(HERE, "golden", "tiny_bruteforce.json")) as f:
+        g = json.load(f)
+    p = make_problem(*g["shape"], s=g["s"], seed=g["seed"])
+    B = O.full_symmetric_B(p.B_cv, p.B_ca, p.B_av)
+    A = slice(p.nc, p.nc + p.na)
+    p.B_aa = np.ascontiguousarray(B[:, A, A])
+    a = O.active_terms(p)
+    for k in range(5):
+        assert abs(a[k] - g["values"]["F%d" % (k + 4)]) <= 1e-14 * abs(g["values"]["F"]), k
+
+
+def test_active_pieces_limits_and_density_structure():
+    p = make_problem(3, 3, 8, 12, s=0.5, seed=40)
+    # Eq. T2amp: s = 0 removes every amplitude
+    assert O.active_terms(p.with_s(0.0)) == (0.0, 0.0, 0.0, 0.0, 0.0)
+    # Fig. 1 structure: an empty active space (Gamma = 0) leaves no active hole
+    # line, a full one (Gamma = 2I, eta = 0) no active particle line
+    q = copy.deepcopy(p)
+    q.gamma1 = np.zeros((3, 3))
+    f = O.active_terms(q)
+    assert f[0] == 0.0 and f[2] == 0.0 and f[3] == 0.0 and f[4] == 0.0 and f[1] != 0.0
+    q.gamma1 = 2.0 * np.eye(3)
+    f = O.active_terms(q)
+    assert f[1] == 0.0 and f[2] == 0.0 and f[3] == 0.0 and f[4] == 0.0 and f[0] != 0.0
+
+
+def test_active_pieces_invariances():
+    p = make_problem(3, 3, 7, 11, s=0.7, seed=41)
+    ref = np.array(O.active_terms(p))
+    # (pq|rs) is quadratic in B: every piece scales as lambda^4
+    q = copy.deepcopy(p)
+    for k in ("B_cv", "B_ca", "B_av", "B_aa"):
+        setattr(q, k, 1.7 * getattr(p, k))
+    assert np.allclose(O.active_terms(q), 1.7 ** 4 * ref, rtol=1e-12, atol=0)
+    # denominators are differences: a common shift of every orbital energy
+    q = copy.deepcopy(p)
+    q.eps_c, q.eps_a, q.eps_v = p.eps_c + 0.3, p.eps_a + 0.3, p.eps_v + 0.3
+    assert np.allclose(O.active_terms(q), ref, rtol=1e-12, atol=0)
+    # orthogonal rotation of the auxiliary index leaves every (pq|rs) unchanged
+    rng = np.random.default_rng(5)
+    Om, _ = np.linalg.qr(rng.standard_normal((p.naux, p.naux)))
+    q = copy.deepcopy(p)
+    for k in ("B_cv", "B_ca", "B_av", "B_aa"):
+        setattr(q, k, np.einsum("PQ,Qpq->Ppq", Om, getattr(p, k)))
+    assert np.allclose(O.active_terms(q), ref, rtol=1e-12, atol=0)
+    # relabelling the active orbitals (with Gamma, B and eps) changes nothing
+    pa = rng.permutation(p.na)
+    q = copy.deepcopy(p)
+    q.B_ca, q.B_av = p.B_ca[:, :, pa], p.B_av[:, pa, :]
+    q.B_aa = p.B_aa[:, pa][:, :, pa]
+    q.eps_a, q.gamma1 = p.eps_a[pa], p.gamma1[np.ix_(pa, pa)]
+    assert np.allclose(O.active_terms(q), ref, rtol=1e-12, atol=0)
