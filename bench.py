@@ -5,7 +5,11 @@ contraction kernels with their fused regulariser epilogues, and the final
 reduction) on seeded synthetic inputs already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
-                    [--precision fp64] [--no-cpu-baseline]
+                    [--precision fp64] [--no-cpu-baseline] [--grad | --active]
+
+With --active a step is one dsrg_df_energy_active call instead (the pieces
+F4-F8 of term F, FP64), measured the same way against its own algorithmic
+work (the contractions over Q that form its integrals).
 
 Prints one JSON line. `value` is algorithmic TFLOP/s of the whole step:
 F_alg = 2 naux [nc(nc+1)/2 nv^2 + nc na nv^2 + nc^2 na nv] (the contractions
@@ -39,6 +43,48 @@ def alg_flops(nc, na, nv, naux, terms=("ccvv", "cavv", "ccav")):
          "cavv": 2.0 * naux * nc * na * nv * nv,
          "ccav": 2.0 * naux * nc * nc * na * nv}
     return sum(f[t] for t in terms), f
+
+
+def active_alg_flops(nc, na, nv, naux):
+    """Contractions over Q that the pieces F4-F8 need: (xe|uf) for F4,
+    (mv|xe) and (me|xv) for F6, (ze|yv) for F7, (mv|ny) for F5, (mv|wy) for F8."""
+    f = {"f4": 2.0 * naux * na * na * nv * nv,
+         "f6": 2.0 * naux * 2 * nc * na * na * nv,
+         "f7": 2.0 * naux * na ** 3 * nv,
+         "f5": 2.0 * naux * nc * nc * na * na,
+         "f8": 2.0 * naux * nc * na ** 3}
+    return sum(f.values()), f
+
+
+def cpu_baseline_active(p, budget_s=20.0):
+    """The oracle's F4-F8 on the first nv_s virtual orbitals, nv_s sized to the
+    budget from a 32-orbital probe (the work scales as nv^2)."""
+    import copy
+    from oracle import dsrg_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+
+    def sub(nv_s):
+        q = copy.copy(p)
+        q.nv, q.B_cv, q.B_av, q.eps_v = nv_s, p.B_cv[:, :, :nv_s], p.B_av[:, :, :nv_s], p.eps_v[:nv_s]
+        return q
+
+    nv0 = min(p.nv, 32)
+    t = time.perf_counter()
+    O.active_terms(sub(nv0))
+    t0 = max(time.perf_counter() - t, 1e-6)
+    nv_s = int(min(p.nv, max(nv0, nv0 * (budget_s / t0) ** 0.5)))
+    t = time.perf_counter()
+    O.active_terms(sub(nv_s))
+    dt = time.perf_counter() - t
+    F, _ = active_alg_flops(p.nc, p.na, nv_s, p.naux)
+    return {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "seconds": round(dt, 3),
+            "sample": f"F4-F8 over the first {nv_s}/{p.nv} virtual orbitals "
+                      "(FP64 numpy/BLAS oracle, same inputs)"}
 
 
 def cpu_baseline(p, budget_s=20.0):
@@ -123,6 +169,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--grad", action="store_true",
                     help="time energy + gradient (dsrg_df_energy_backward) instead of energy")
+    ap.add_argument("--active", action="store_true",
+                    help="time the pieces F4-F8 of term F (dsrg_df_energy_active, FP64)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
                          "hardware byte counters can be scaled")
@@ -147,6 +195,8 @@ def main():
         del x, y
 
     p = make_config(args.config)
+    if args.active:
+        return bench_active(args, p, binding, torch)
     c = CONFIGS[args.config]
     terms = c["terms"]
     dev = torch.device("cuda:0")
@@ -247,6 +297,68 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)
+    print(json.dumps(out))
+
+
+def bench_active(args, p, binding, torch):
+    """--active: one step = one dsrg_df_energy_active call (F4-F8, FP64)."""
+    if args.precision != "fp64" or args.grad:
+        print("bench.py: --active runs the FP64 energy only", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(p, k))).to(dev)
+         for k in ("B_cv", "B_ca", "B_av", "B_aa", "eps_c", "eps_a", "eps_v", "gamma1")}
+    F = torch.empty(5, dtype=torch.float64, device=dev)
+    args_t = (t["B_cv"], t["B_ca"], t["B_av"], t["B_aa"], t["eps_c"], t["eps_a"], t["eps_v"],
+              t["gamma1"], p.s)
+    nbytes = binding.active_workspace_size(p.nc, p.na, p.nv, p.naux)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        binding.energy_active(*args_t, out=F, workspace=ws)
+    torch.cuda.synchronize()
+    binding.kernel_times(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        binding.energy_active(*args_t, out=F, workspace=ws, timing=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = binding.kernel_times(4096)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    per_kernel = {}
+    for name, ms in kt:
+        per_kernel.setdefault(name, []).append(ms)
+    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
+    Ftot, Fparts = active_alg_flops(p.nc, p.na, p.nv, p.naux)
+    dom = "cavv_fp64_x"   # the (xe|uf) producer of F4
+    dom_ms = avg.get(dom)
+    ach = Fparts["f4"] / (dom_ms * 1e-3) / 1e12 if dom_ms else None
+    peak = PEAK_TFLOPS["fp64"]
+    roof = {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": (ach / peak) if ach else None, "avg_launch_ms": dom_ms,
+            "ops_per_launch": Fparts["f4"], "traffic": None}
+    Fg = F.cpu().numpy()
+    err = None
+    refs = os.path.join(ROOT, "tests", "golden", "oracle_refs.json")
+    if os.path.exists(refs):
+        r = json.load(open(refs)).get(args.config, {}).get("F48_s%g" % p.s)
+        if r is not None:
+            err = [abs(float(a) - float(b)) for a, b in zip(Fg, r)]
+    out = {
+        "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
+        "value": Ftot / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "s_per_solve": ms_per_step * 1e-3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: nc={p.nc} na={p.na} nv={p.nv} naux={p.naux} "
+                               f"s={p.s}, energy of F4+F5+F6+F7+F8",
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "kernel_ms": avg,
+        "F_terms": [float(x) for x in Fg],
+        "abs_err_vs_oracle": err,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_active(p, args.cpu_budget)
     print(json.dumps(out))
 
 

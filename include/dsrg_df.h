@@ -1,6 +1,7 @@
 /*
  * dsrg_df.h - C ABI of libdsrgdf, the MI355X (gfx950) library for the
- * density-fitted DSRG-MRPT2 energy terms F1 (CCVV), F2 (CAVV) and F3 (CCAV).
+ * density-fitted DSRG-MRPT2 energy terms F1 (CCVV), F2 (CAVV) and F3 (CCAV),
+ * their gradients, and the remaining pieces F4-F8 of term F.
  *
  * What is computed (Hannon, Li, Evangelista, "An integral-factorized
  * implementation of the driven similarity renormalization group second-order
@@ -141,6 +142,36 @@ dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int
                                     double *deps_c, double *deps_a, double *deps_v,
                                     double *ds, double *E_terms,
                                     void *workspace, size_t ws_bytes, void *stream);
+
+/* ---- The remaining pieces F4..F8 of term F (Table II) ----
+ * The five pieces of Eq. expensive_term with two or more active indices,
+ * after the same spin summation (etab = 2 I - Gamma; x, y, u, v, w, z active):
+ *
+ *   F4 = 1/4 sum Gamma_xy Gamma_uv sum_{ef} (xe|uf) S(D^{ef}_{xu}) [2(ye|vf) - (yf|ve)] R1(D^{ef}_{yv})
+ *   F5 = 1/4 sum etab_uv etab_xy sum_{mn} (mv|ny) S(D^{vy}_{mn}) [2(mu|nx) - (mx|nu)] R1(D^{ux}_{mn})
+ *   F6 = sum Gamma_xy etab_uv sum_{me} S(D^{ve}_{mx}) R1(D^{ue}_{my})
+ *          [(mv|xe)(mu|ye) + (me|xv)(me|yu) - ((mv|xe)(me|yu) + (me|xv)(mu|ye))/2]
+ *   F7 = 1/4 sum Gamma_yw Gamma_zx etab_uv sum_e (yv|ze) S(D^{ve}_{yz}) [2(wu|xe) - (we|xu)] R1(D^{ue}_{wx})
+ *   F8 = 1/4 sum Gamma_wz etab_uv etab_xy sum_m (mv|wy) S(D^{vy}_{mw}) [2(mu|zx) - (mx|zu)] R1(D^{ux}_{mz})
+ *
+ * They read, besides the blocks of *p, the active-active block of B. FP64
+ * only; na <= DSRG_DF_MAX_ACTIVE. */
+
+/* Bytes of device workspace that dsrg_df_energy_active needs for *p (sizes
+ * only, no pointer is dereferenced). */
+dsrg_status dsrg_df_active_workspace_size(const dsrg_df_problem *p, size_t *bytes);
+
+/* F4..F8 of the problem.
+ *   B_aa      device [naux][na][na]  B^Q_{uv}, symmetric in u, v (may be NULL
+ *             when na == 0)
+ *   options   0 or DSRG_OPT_KERNEL_TIMING
+ *   F_terms   device [5]: F4, F5, F6, F7, F8 in Eh (all 0 when na == 0)
+ *   workspace device buffer of at least dsrg_df_active_workspace_size(...)
+ *             bytes, 256-byte aligned; its contents on entry do not matter.
+ * Every term is exactly 0 for s == 0. Errors as for dsrg_df_energy. */
+dsrg_status dsrg_df_energy_active(const dsrg_df_problem *p, const double *B_aa, int options,
+                                  double *F_terms, void *workspace, size_t ws_bytes,
+                                  void *stream);
 
 /* Text of the last error raised on the calling thread ("" if none). Valid
  * until the next dsrg_df_* call on that thread. */

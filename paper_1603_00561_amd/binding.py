@@ -24,6 +24,7 @@ OPT_KERNEL_TIMING = 0x200
 MAX_ACTIVE = 8
 
 EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward",
+            "dsrg_df_active_workspace_size", "dsrg_df_energy_active",
             "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_version")
 
 
@@ -66,6 +67,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_energy_backward.argtypes = [ctypes.POINTER(Problem), i32, i32, vp,
                                             vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dsrg_df_energy_backward.restype = i32
+    lib.dsrg_df_active_workspace_size.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(sz)]
+    lib.dsrg_df_active_workspace_size.restype = i32
+    lib.dsrg_df_energy_active.argtypes = [ctypes.POINTER(Problem), vp, i32, vp, vp, sz, vp]
+    lib.dsrg_df_energy_active.restype = i32
     lib.dsrg_df_last_error.argtypes = []
     lib.dsrg_df_last_error.restype = ctypes.c_char_p
     lib.dsrg_df_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double),
@@ -159,6 +164,15 @@ def workspace_size(nc, na, nv, naux, precision="fp64", terms="all", with_grad=Fa
     return out.value
 
 
+def active_workspace_size(nc, na, nv, naux) -> int:
+    """Workspace bytes of dsrg_df_energy_active for these sizes."""
+    lib = load_library()
+    p = Problem(nc, na, nv, naux, None, None, None, None, None, None, None, 0.5)
+    out = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_active_workspace_size(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
 def _stream_handle(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -189,6 +203,26 @@ def energy(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
                               nbytes.value, _stream_handle(dev)))
     del keep
     return E
+
+
+def energy_active(B_cv, B_ca, B_av, B_aa, eps_c, eps_a, eps_v, gamma1, s,
+                  workspace: Optional[torch.Tensor] = None, timing: bool = False,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """F4..F8 of term F (device tensor [5], float64) via dsrg_df_energy_active."""
+    lib = load_library()
+    p, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s)
+    dev = B_cv.device
+    na = int(p.na)
+    baa = _as_dev(B_aa, "B_aa", (int(p.naux), na, na), dev) if na else None
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_active_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    F = torch.empty(5, dtype=torch.float64, device=dev) if out is None else out
+    _check(lib.dsrg_df_energy_active(ctypes.byref(p), _ptr(baa),
+                                     OPT_KERNEL_TIMING if timing else 0, F.data_ptr(),
+                                     ws.data_ptr(), nbytes.value, _stream_handle(dev)))
+    del keep, baa
+    return F
 
 
 def energy_backward(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, gE, precision="fp64",

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsrgdf.so")
 
-SOURCES = ["api.cpp", "fp64_kernels.hip", "fp64_bwd.hip", "split_kernels.hip", "split_bwd.hip"]
+SOURCES = ["api.cpp", "fp64_kernels.hip", "fp64_bwd.hip", "split_kernels.hip", "split_bwd.hip",
+           "active_terms.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -273,6 +273,77 @@ dsrg_status check_workspace(const dsrg::Plan &pl, void *ws, size_t ws_bytes) {
   return DSRG_OK;
 }
 
+// Plan of the F4-F8 entry point (FP64): sizes, validation of the scalars and
+// the workspace layout.
+dsrg_status make_active_plan(const dsrg_df_problem *p, dsrg::ActivePlan &pl) {
+  using namespace dsrg;
+  if (!p) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  if (p->nc < 1) return fail(DSRG_ERR_ARG, "nc must be >= 1 (got %lld)", (long long)p->nc);
+  if (p->nv < 1) return fail(DSRG_ERR_ARG, "nv must be >= 1 (got %lld)", (long long)p->nv);
+  if (p->naux < 1) return fail(DSRG_ERR_ARG, "naux must be >= 1 (got %lld)", (long long)p->naux);
+  if (p->na < 0) return fail(DSRG_ERR_ARG, "na must be >= 0 (got %lld)", (long long)p->na);
+  if (!(p->s >= 0.0) || !isfinite(p->s))
+    return fail(DSRG_ERR_ARG, "s must be finite and >= 0 (got %g)", p->s);
+  if (p->na > DSRG_DF_MAX_ACTIVE)
+    return fail(DSRG_ERR_UNSUPPORTED, "na = %lld exceeds the compiled maximum %d",
+                (long long)p->na, DSRG_DF_MAX_ACTIVE);
+  if (p->nc > (1 << 20) || p->nv > (1 << 24) || p->naux > (1 << 24))
+    return fail(DSRG_ERR_UNSUPPORTED, "dimensions too large (nc %lld, nv %lld, naux %lld)",
+                (long long)p->nc, (long long)p->nv, (long long)p->naux);
+  pl.nc = p->nc;
+  pl.na = p->na;
+  pl.nv = p->nv;
+  pl.naux = p->naux;
+  pl.s = p->s;
+  pl.naux_p = round_up(pl.naux, kChunk);
+  pl.ntv = ceil_div(pl.nv, kPanel);
+  pl.W = pl.ntv * kPanel;
+  pl.ncC = round_up(pl.nc * pl.na, 16);
+  pl.ncA = round_up(pl.na * pl.na, 16);
+  // F4, F5, F6: at most kActPairGrid workgroups of four waves (elements
+  // (e f), (m n), (m e) taken grid-stride); F7, F8: one workgroup per e, m
+  auto pair_grid = [&](int64_t n) { return std::min(ceil_div(n, 4), kActPairGrid); };
+  const int64_t nslot[5] = {pair_grid(pl.nv * pl.nv), pair_grid(pl.nc * pl.nc),
+                            pair_grid(pl.nc * pl.nv), pl.nv, pl.nc};
+  const int64_t maxgrid = ((int64_t)1 << 31) - 1;
+  int64_t base = 0;
+  for (int t = 0; t < 5; ++t) {
+    if (nslot[t] > maxgrid) return fail(DSRG_ERR_UNSUPPORTED, "work list exceeds one launch grid");
+    pl.slot_base[t] = base;
+    pl.slot_count[t] = pl.na > 0 ? nslot[t] : 0;
+    base += pl.slot_count[t];
+  }
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t at = off;
+    off = align256(off + sizeof(double) * doubles);
+    return at;
+  };
+  const size_t na = (size_t)pl.na, nc = (size_t)pl.nc, W = (size_t)pl.W;
+  const size_t np = (size_t)pl.naux_p, ntv = (size_t)pl.ntv;
+  if (pl.na > 0) {
+    pl.off_pav = take(na * ntv * np * kPanel);
+    pl.off_pcv = take(nc * ntv * np * kPanel);
+    pl.off_pca = take(nc * np * kPanel);
+    pl.off_rca = take(np * (size_t)pl.ncC);
+    pl.off_raa = take(np * (size_t)pl.ncA);
+    pl.off_x = take(na * na * W * W);
+    pl.off_ja1 = take(na * W * (size_t)pl.ncC);
+    pl.off_ja2 = take(nc * W * (size_t)pl.ncA);
+    pl.off_jc1 = take(na * W * (size_t)pl.ncA);
+    pl.off_jk = take(nc * kPanel * (size_t)pl.ncC);
+    pl.off_je = take(nc * kPanel * (size_t)pl.ncA);
+    pl.off_ctr = off;
+    off = align256(off + 64);
+  } else {
+    pl.off_pav = pl.off_pcv = pl.off_pca = pl.off_rca = pl.off_raa = pl.off_x = pl.off_ja1 =
+        pl.off_ja2 = pl.off_jc1 = pl.off_jk = pl.off_je = pl.off_ctr = off;
+  }
+  pl.off_slots = take((size_t)base + 1);
+  pl.total = off;
+  return DSRG_OK;
+}
+
 }  // namespace
 
 namespace dsrg {
@@ -363,6 +434,52 @@ dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int
                      ? dsrg::launch_backward_split(pl, in, o, workspace, hs)
                      : dsrg::launch_backward_fp64(pl, in, o, workspace, hs);
   if (e == hipSuccess && E_terms) e = dsrg::launch_finalize(pl, workspace, E_terms, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_active_workspace_size(const dsrg_df_problem *p, size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::ActivePlan pl;
+  dsrg_status st = make_active_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_energy_active(const dsrg_df_problem *p, const double *B_aa, int options,
+                                  double *F_terms, void *workspace, size_t ws_bytes,
+                                  void *stream) {
+  g_err[0] = 0;
+  dsrg::ActivePlan pl;
+  dsrg_status st = make_active_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  if (options & ~DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "unknown option bits 0x%x", options);
+  if (!F_terms || !aligned8(F_terms)) return fail(DSRG_ERR_ARG, "F_terms is NULL or misaligned");
+  if (pl.na > 0) {
+    const struct {
+      const double *ptr;
+      const char *name;
+    } need[] = {{p->B_cv, "B_cv"},   {p->B_ca, "B_ca"},   {p->B_av, "B_av"},
+                {B_aa, "B_aa"},      {p->eps_c, "eps_c"}, {p->eps_a, "eps_a"},
+                {p->eps_v, "eps_v"}, {p->gamma1, "gamma1"}};
+    for (const auto &n : need)
+      if (!n.ptr || !aligned8(n.ptr)) return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", n.name);
+  }
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!workspace) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+
+  dsrg::ActiveInputs in{p->B_cv, p->B_ca, p->B_av, B_aa, p->eps_c, p->eps_a, p->eps_v,
+                        p->gamma1};
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_active_terms(pl, in, workspace, F_terms, hs);
   if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return DSRG_OK;
 }

@@ -182,7 +182,6 @@ __global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restri
 // (n,m); weight 1 for m < n and 1/2 for m = n.
 // ---------------------------------------------------------------------------
 struct CcavJArgs {
-  int ntv;
   int64_t naux_p;
   int64_t ncols;     // padded column count of J (multiple of 16)
 };
@@ -298,9 +297,10 @@ __global__ __launch_bounds__(256) void ccav_epi_fp64_kernel(
 // the per-workgroup slots in a fixed order, or a copy of the atomic
 // accumulator. Unselected terms are written as 0.
 // ---------------------------------------------------------------------------
+constexpr int kFinTerms = 8;
 struct FinArgs {
-  int64_t base[3], count[3];
-  int selected[3];
+  int64_t base[kFinTerms], count[kFinTerms];
+  int selected[kFinTerms];
   int atomic_mode;
 };
 
@@ -363,6 +363,12 @@ static hipError_t pack_one(const double *B, double *P, int64_t nrow, int64_t nco
   return hipGetLastError();
 }
 
+hipError_t launch_pack_panels(const double *B, double *P, int64_t nrow, int64_t ncol,
+                              int64_t naux, int64_t naux_p, int64_t ntile, int width,
+                              hipStream_t st) {
+  return pack_one(B, P, nrow, ncol, naux, naux_p, ntile, width, st);
+}
+
 hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st) {
   hipError_t e = pack_one(in.B_cv, ws_d(ws, pl.off_pcv), pl.nc, pl.nv, pl.naux, pl.naux_p,
                           pl.ntv, kPanel, st);
@@ -384,27 +390,33 @@ hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStrea
   return hipSuccess;
 }
 
+hipError_t launch_j_fp64(const double *Pleft, int64_t npanels, const double *R, int64_t ncols,
+                         int64_t naux_p, double *J, hipStream_t st) {
+  if (ncols % 16 != 0) return hipErrorInvalidValue;
+  CcavJArgs ja;
+  ja.naux_p = naux_p;
+  ja.ncols = ncols;
+  // column blocks of 16 per workgroup: the largest of 4, 3, 2, 1 that divides
+  // the block count, so no workgroup reads past the last column
+  const int nblk = (int)(ncols / 16);
+  const int NBsel = (nblk % 4 == 0) ? 4 : (nblk % 3 == 0) ? 3 : (nblk % 2 == 0) ? 2 : 1;
+  const dim3 gj((unsigned)npanels, (unsigned)ceil_div(nblk, NBsel));
+  timer_begin("ccav_j_fp64", st);
+  switch (NBsel) {
+    case 1: hipLaunchKernelGGL(ccav_j_fp64_kernel<1>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
+    case 2: hipLaunchKernelGGL(ccav_j_fp64_kernel<2>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
+    case 3: hipLaunchKernelGGL(ccav_j_fp64_kernel<3>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
+    default: hipLaunchKernelGGL(ccav_j_fp64_kernel<4>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
+  }
+  timer_end(st);
+  return hipGetLastError();
+}
+
 template <int NA>
 static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                                  double *slots, double *acc) {
-  CcavJArgs ja;
-  ja.ntv = (int)pl.ntv;
-  ja.naux_p = pl.naux_p;
-  ja.ncols = pl.ccav_cols;
-  // column blocks of 16 per workgroup: the largest of 4, 3, 2, 1 that divides
-  // the block count, so no workgroup reads past the last column
-  const int nblk = (int)(pl.ccav_cols / 16);
-  const int NBsel = (nblk % 4 == 0) ? 4 : (nblk % 3 == 0) ? 3 : (nblk % 2 == 0) ? 2 : 1;
-  const dim3 gj((unsigned)(pl.nc * pl.ntv), (unsigned)ceil_div(nblk, NBsel));
-  timer_begin("ccav_j_fp64", st);
-  switch (NBsel) {
-    case 1: hipLaunchKernelGGL(ccav_j_fp64_kernel<1>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
-    case 2: hipLaunchKernelGGL(ccav_j_fp64_kernel<2>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
-    case 3: hipLaunchKernelGGL(ccav_j_fp64_kernel<3>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
-    default: hipLaunchKernelGGL(ccav_j_fp64_kernel<4>, gj, dim3(256), 0, st, ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), ja, ws_d(ws, pl.off_j)); break;
-  }
-  timer_end(st);
-  hipError_t e = hipGetLastError();
+  hipError_t e = launch_j_fp64(ws_d(ws, pl.off_pcv), pl.nc * pl.ntv, ws_d(ws, pl.off_pca),
+                               pl.ccav_cols, pl.naux_p, ws_d(ws, pl.off_j), st);
   if (e != hipSuccess) return e;
   CcavEpiArgs a;
   a.nc = (int)pl.nc;
@@ -437,23 +449,29 @@ static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hip
     default: return hipErrorInvalidValue;       \
   }
 
-hipError_t launch_cavv_x_fp64(const Plan &pl, void *ws, int m0, int mb, hipStream_t st) {
+hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv,
+                         int64_t naux_p, int m0, int mb, int *ctr, double *Xb, hipStream_t st) {
   CavvXArgs64 xa;
-  xa.na = (int)pl.na;
-  xa.ntv = (int)pl.ntv;
-  xa.naux_p = pl.naux_p;
+  xa.na = nright;
+  xa.ntv = ntv;
+  xa.naux_p = naux_p;
   xa.m0 = m0;
   xa.mb = mb;
-  const int64_t items = pairtile_grid((int64_t)mb * pl.na, pl.ntv);
+  const int64_t items = pairtile_grid((int64_t)mb * nright, ntv);
   const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
-  int *ctr = reinterpret_cast<int *>(ws_d(ws, pl.off_ctr));
-  hipError_t e = launch_zero(ws_d(ws, pl.off_ctr), 4, st);
+  hipError_t e = launch_zero(reinterpret_cast<double *>(ctr), 4, st);
   if (e != hipSuccess) return e;
   timer_begin("cavv_fp64_x", st);
-  hipLaunchKernelGGL(cavv_fp64_x_kernel, dim3((unsigned)grid), dim3(256), 0, st,
-                     ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), xa, ctr, ws_d(ws, pl.off_xb));
+  hipLaunchKernelGGL(cavv_fp64_x_kernel, dim3((unsigned)grid), dim3(256), 0, st, Pleft, Pright,
+                     xa, ctr, Xb);
   timer_end(st);
   return hipGetLastError();
+}
+
+hipError_t launch_cavv_x_fp64(const Plan &pl, void *ws, int m0, int mb, hipStream_t st) {
+  return launch_x_fp64(ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), (int)pl.na, (int)pl.ntv,
+                       pl.naux_p, m0, mb, reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)),
+                       ws_d(ws, pl.off_xb), st);
 }
 
 static hipError_t launch_cavv(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
@@ -524,7 +542,7 @@ hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStr
 }
 
 hipError_t launch_finalize(const Plan &pl, void *ws, double *E_terms, hipStream_t st) {
-  FinArgs f;
+  FinArgs f = {};
   const int64_t counts[3] = {pl.n_ccvv, pl.n_cavv, pl.n_ccav};
   for (int t = 0; t < 3; ++t) {
     f.base[t] = pl.slot_base[t];
@@ -535,6 +553,22 @@ hipError_t launch_finalize(const Plan &pl, void *ws, double *E_terms, hipStream_
   timer_begin("finalize", st);
   hipLaunchKernelGGL(finalize_kernel, dim3(3), dim3(256), 0, st, ws_d(ws, pl.off_slots),
                      ws_d(ws, pl.off_acc), f, E_terms);
+  timer_end(st);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const int64_t *count,
+                                 int nterms, double *E, hipStream_t st) {
+  if (nterms < 1 || nterms > kFinTerms) return hipErrorInvalidValue;
+  FinArgs f = {};
+  for (int t = 0; t < nterms; ++t) {
+    f.base[t] = base[t];
+    f.count[t] = count[t];
+    f.selected[t] = 1;
+  }
+  timer_begin("finalize", st);
+  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)nterms), dim3(256), 0, st, slots, nullptr, f,
+                     E);
   timer_end(st);
   return hipGetLastError();
 }

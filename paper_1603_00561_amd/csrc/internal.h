@@ -84,6 +84,26 @@ struct BwdOut {
 // number of A<B tile pairs, and the closed-form counts of the CCVV work list
 inline int64_t tri_off(int64_t n) { return n * (n - 1) / 2; }
 
+// The pieces F4-F8 of term F (two or more active indices), FP64.
+constexpr int64_t kActPairGrid = 2048;   // workgroups of the F4, F5, F6 element loops
+struct ActivePlan {
+  int64_t nc, na, nv, naux;
+  int64_t naux_p, ntv, W;   // W = ntv kPanel: padded virtual row length
+  double s;
+  int64_t ncC, ncA;         // flattened (m, u) and (u, v) columns, padded to 16
+  size_t off_pav, off_pcv, off_pca, off_rca, off_raa;   // packed operands
+  size_t off_x;             // X[x][u][e][f] = (xe|uf)
+  size_t off_ja1, off_ja2, off_jc1, off_jk, off_je;    // integral blocks with active indices
+  size_t off_ctr, off_slots;
+  int64_t slot_base[5], slot_count[5];
+  size_t total;
+};
+
+struct ActiveInputs {
+  const double *B_cv, *B_ca, *B_av, *B_aa;
+  const double *eps_c, *eps_a, *eps_v, *gamma1;
+};
+
 // ---- per-kernel timing (api.cpp); no-ops unless the call asked for it ----
 void timer_begin(const char *name, hipStream_t st);
 void timer_end(hipStream_t st);
@@ -94,6 +114,24 @@ hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStr
 hipError_t launch_finalize(const Plan &pl, void *ws, double *E_terms, hipStream_t st);
 hipError_t launch_ccav_fp64(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_zero(double *p, int n, hipStream_t st);
+// P[(r ntile + t)][Q][c] = B[Q][r][t width + c] (zero outside), rows Q padded to naux_p
+hipError_t launch_pack_panels(const double *B, double *P, int64_t nrow, int64_t ncol,
+                              int64_t naux, int64_t naux_p, int64_t ntile, int width,
+                              hipStream_t st);
+// X[ml][u][e][f] = sum_Q L^Q_{(m0+ml) e} R^Q_{u f} for ml < mb, u < nright, from
+// 64-wide panels (row length ntv 64); ctr: eight work counters, cleared here
+hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv,
+                         int64_t naux_p, int m0, int mb, int *ctr, double *Xb, hipStream_t st);
+// J[panel 64 + r][c] = sum_Q Pleft[panel][Q][r] R[Q][c], R row-major [naux_p][ncols],
+// ncols a multiple of 16
+hipError_t launch_j_fp64(const double *Pleft, int64_t npanels, const double *R, int64_t ncols,
+                         int64_t naux_p, double *J, hipStream_t st);
+// compensated sums of slot ranges: E[t] = sum of slots[base[t] .. base[t] + count[t])
+hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const int64_t *count,
+                                 int nterms, double *E, hipStream_t st);
+// ---- F4-F8 (active_terms.hip) ----
+hipError_t launch_active_terms(const ActivePlan &pl, const ActiveInputs &in, void *ws,
+                               double *F, hipStream_t st);
 // ---- int8 slice path (split_kernels.hip) ----
 hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipStream_t st);
 hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, int mb,

@@ -4,6 +4,10 @@ gradients and the norms of the B gradients) on the seeded synthetic
 workloads. Calls only the oracle and the seeded generator.
 
     python tests/golden/make_oracle_refs.py [cfg ...]
+    python tests/golden/make_oracle_refs.py --active [cfg ...]
+
+With --active only the pieces F4-F8 of term F are computed (key "F48_s<s>")
+and merged into the existing entries.
 """
 import json
 import os
@@ -56,14 +60,26 @@ def run(name):
     return out
 
 
+def run_active(name, entry):
+    p = make_config(name)
+    t = time.time()
+    f = O.active_terms(p)
+    entry["F48_s%g" % p.s] = list(f)
+    entry["t_F48_s%g" % p.s] = time.time() - t
+    print(name, "F4-F8", f, time.time() - t, flush=True)
+    return entry
+
+
 def main():
-    names = sys.argv[1:] or list(CONFIGS)
+    args = sys.argv[1:]
+    active = "--active" in args
+    names = [a for a in args if a != "--active"] or list(CONFIGS)
     refs = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             refs = json.load(f)
     for n in names:
-        refs[n] = run(n)
+        refs[n] = run_active(n, refs.get(n, {})) if active else run(n)
         with open(OUT, "w") as f:
             json.dump(refs, f, indent=1)
 

@@ -153,3 +153,37 @@ def test_python_binding_refuses_cpu_tensors():
     t = [torch.from_numpy(x) for x in p.arrays()]
     with pytest.raises(ValueError, match="GPU"):
         b.energy(*t, p.s)
+
+
+def _active(p, B_aa=0x30000, options=0, F=0x20000, ws=0x40000, ws_bytes=1 << 40):
+    return b.load_library().dsrg_df_energy_active(
+        ctypes.byref(p), ctypes.c_void_p(B_aa) if B_aa else None, options,
+        ctypes.c_void_p(F) if F else None, ctypes.c_void_p(ws) if ws else None, ws_bytes, None)
+
+
+def test_active_terms_entry_point_validation(lib):
+    """F4-F8 entry point: workspace sizing and host-side rejection of every
+    invalid argument (nothing is dereferenced or enqueued)."""
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_active_workspace_size(ctypes.byref(_prob(23, 6, 1100, 3000)),
+                                             ctypes.byref(out)) == 0
+    # (xe|uf) for all active pairs dominates: na^2 (64 ceil(nv/64))^2 doubles
+    assert out.value >= 8 * 36 * 1152 * 1152
+    small = ctypes.c_size_t(0)
+    assert lib.dsrg_df_active_workspace_size(ctypes.byref(_prob(23, 0, 1100, 3000)),
+                                             ctypes.byref(small)) == 0
+    assert 0 < small.value < 4096
+    assert lib.dsrg_df_active_workspace_size(ctypes.byref(_prob()), None) == b.DSRG_ERR_ARG
+    for field, value, code in (("nc", 0, b.DSRG_ERR_ARG), ("na", -1, b.DSRG_ERR_ARG),
+                               ("s", float("nan"), b.DSRG_ERR_ARG),
+                               ("na", 9, b.DSRG_ERR_UNSUPPORTED)):
+        p = _prob()
+        setattr(p, field, value)
+        assert _active(p) == code, field
+        assert lib.dsrg_df_last_error().decode()
+    assert _active(_prob(), B_aa=0) == b.DSRG_ERR_ARG                  # B_aa missing
+    assert _active(_prob(), B_aa=0x30004) == b.DSRG_ERR_ARG            # misaligned
+    assert _active(_prob(), F=0) == b.DSRG_ERR_ARG
+    assert _active(_prob(), options=0x100) == b.DSRG_ERR_ARG           # not an option here
+    assert _active(_prob(), ws_bytes=16) == b.DSRG_ERR_WORKSPACE
+    assert _active(_prob(), ws=0x40010) == b.DSRG_ERR_WORKSPACE        # not 256-aligned
