@@ -46,9 +46,10 @@ def alg_flops(nc, na, nv, naux, terms=("ccvv", "cavv", "ccav")):
 
 
 def active_alg_flops(nc, na, nv, naux):
-    """Contractions over Q that the pieces F4-F8 need: (xe|uf) for F4,
-    (mv|xe) and (me|xv) for F6, (ze|yv) for F7, (mv|ny) for F5, (mv|wy) for F8."""
-    f = {"f4": 2.0 * naux * na * na * nv * nv,
+    """Contractions over Q that the pieces F4-F8 need: (xe|uf) for F4 over its
+    distinct pairs x <= u ((xe|uf) = (uf|xe)), (mv|xe) and (me|xv) for F6,
+    (ze|yv) for F7, (mv|ny) for F5, (mv|wy) for F8."""
+    f = {"f4": 2.0 * naux * (na * (na + 1) / 2) * nv * nv,
          "f6": 2.0 * naux * 2 * nc * na * na * nv,
          "f7": 2.0 * naux * na ** 3 * nv,
          "f5": 2.0 * naux * nc * nc * na * na,

@@ -13,7 +13,8 @@
 //
 // Integrals (Eq. int_fact) come from the FP64 matrix-core producers: the
 // (xe|uf) tiles of the CAVV integral producer with the active panels on both
-// sides, and the contractions over Q of packed panels with the flattened
+// sides (pairs x <= u only: (xe|uf) = (uf|xe)), and the contractions over Q
+// of packed panels with the flattened
 // active blocks (B_ca, B_aa) for everything with at most one virtual index.
 // Each piece is then a small contraction over active indices per element
 // (e f, m n, m e, e or m), done with one wave (pair pieces) or one workgroup
@@ -69,14 +70,22 @@ __device__ __forceinline__ double sandwich(double z, double w, const double *L,
 // the element contributes 1/4 sum z (M W M), M = Gamma (F4) or etab (F5).
 //   F4: element (e, f), A_pq = X^{pq}_{ef} = (pe|qf), bsign = -1, M = Gamma
 //   F5: element (m, n), A_vy = (mv|ny), bsign = +1, M = etab
+// Both satisfy A_pq(r, c) = A_qp(c, r); with tri set only the blocks p <= q
+// are stored and the others are read through that symmetry.
 // ---------------------------------------------------------------------------
 struct ActPairArgs {
   int64_t count, ncol;
   int64_t rs, cs, sp, sq;
   double bsign, s;
-  int use_eta;
+  int use_eta, tri;
   int64_t slot_base;
 };
+
+__device__ __forceinline__ double pair_entry(const double *A, const ActPairArgs &a, int64_t r,
+                                             int64_t c, int p, int q) {
+  if (a.tri && p > q) return A[c * a.rs + r * a.cs + q * a.sp + p * a.sq];
+  return A[r * a.rs + c * a.cs + p * a.sp + q * a.sq];
+}
 
 template <int NA>
 __global__ __launch_bounds__(256) void act_pair_kernel(const double *__restrict__ A,
@@ -98,8 +107,7 @@ __global__ __launch_bounds__(256) void act_pair_kernel(const double *__restrict_
     if (el < a.count && lane < NA * NA) {
       const int64_t r = el / a.ncol, c = el % a.ncol;
       const int p = lane / NA, q = lane % NA;
-      const double *Ae = A + r * a.rs + c * a.cs;
-      const double x = Ae[p * a.sp + q * a.sq], xt = Ae[q * a.sp + p * a.sq];
+      const double x = pair_entry(A, a, r, c, p, q), xt = pair_entry(A, a, r, c, q, p);
       const double D = a.bsign * ((eps_rc[r] + eps_rc[c]) - (eps_a[p] + eps_a[q]));
       double S, R1;
       reg_S_R1(D, a.s, S, R1);
@@ -261,6 +269,7 @@ static hipError_t launch_active_na(const ActivePlan &pl, const ActiveInputs &in,
     a.bsign = -1.0;
     a.s = pl.s;
     a.use_eta = 0;
+    a.tri = 1;
     a.slot_base = pl.slot_base[0];
     timer_begin("act_f4", st);
     hipLaunchKernelGGL(act_pair_kernel<NA>, dim3((unsigned)pl.slot_count[0]), dim3(256), 0, st,
@@ -279,6 +288,7 @@ static hipError_t launch_active_na(const ActivePlan &pl, const ActiveInputs &in,
     a.bsign = 1.0;
     a.s = pl.s;
     a.use_eta = 1;
+    a.tri = 0;
     a.slot_base = pl.slot_base[1];
     timer_begin("act_f5", st);
     hipLaunchKernelGGL(act_pair_kernel<NA>, dim3((unsigned)pl.slot_count[1]), dim3(256), 0, st,
@@ -362,8 +372,8 @@ hipError_t launch_active_terms(const ActivePlan &pl, const ActiveInputs &in, voi
     return e;
   // integrals: X[x][u][e][f] = (xe|uf); (xe|mv); (me|xv); (ze|yv); (mv|ny); (mv|wy)
   if ((e = launch_x_fp64(Pav, Pav, (int)pl.na, (int)pl.ntv, pl.naux_p, 0, (int)pl.na,
-                         reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)), ws_d(ws, pl.off_x), st)) !=
-      hipSuccess)
+                         reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)), ws_d(ws, pl.off_x), true,
+                         st)) != hipSuccess)
     return e;
   if ((e = launch_j_fp64(Pav, pl.na * pl.ntv, Rca, pl.ncC, pl.naux_p, ws_d(ws, pl.off_ja1), st)) !=
       hipSuccess)

@@ -111,12 +111,14 @@ __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict
 // tile machinery with pair (m, u), left panels B_cv, right panels B_av) are
 // written to Xb[(m - m0)][u][e][f]: block [A,B] from x and block [B,A] from
 // y = X^{mu}[B,A]^T. A persistent grid takes the items of decode_pair_list
-// from per-XCD counters. Step 2 (cavv_epi_kernel) forms the energy.
+// from per-XCD counters. Step 2 (cavv_epi_kernel) forms the energy. With
+// tri set (the same panels on both sides), only the pairs m <= u are formed.
 // ---------------------------------------------------------------------------
 struct CavvXArgs64 {
   int na, ntv;
   int64_t naux_p;
   int m0, mb;
+  int tri;   // left and right panels are the same orbitals: only the pairs ml <= u
 };
 
 __global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restrict__ Pcv,
@@ -133,8 +135,15 @@ __global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restri
   __syncthreads();
   int64_t pp;
   CcvvWork c;
-  if (!decode_pair_list(next, xcd, (int64_t)a.mb * a.na, a.ntv, pp, c.A, c.B)) break;
-  const int ml = (int)(pp / a.na), u = (int)(pp % a.na);
+  const int64_t npairs = a.tri ? (int64_t)a.na * (a.na + 1) / 2 : (int64_t)a.mb * a.na;
+  if (!decode_pair_list(next, xcd, npairs, a.ntv, pp, c.A, c.B)) break;
+  int ml, u;
+  if (a.tri) {
+    decode_pair_le(pp, a.na, ml, u);
+  } else {
+    ml = (int)(pp / a.na);
+    u = (int)(pp % a.na);
+  }
   c.i = a.m0 + ml;
   c.j = u;
   c.cls = (c.A == c.B) ? 2 : 0;   // y is needed only off the diagonal
@@ -450,14 +459,18 @@ static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hip
   }
 
 hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv,
-                         int64_t naux_p, int m0, int mb, int *ctr, double *Xb, hipStream_t st) {
+                         int64_t naux_p, int m0, int mb, int *ctr, double *Xb, bool tri,
+                         hipStream_t st) {
+  if (tri && (m0 != 0 || mb != nright || Pleft != Pright)) return hipErrorInvalidValue;
   CavvXArgs64 xa;
   xa.na = nright;
   xa.ntv = ntv;
   xa.naux_p = naux_p;
   xa.m0 = m0;
   xa.mb = mb;
-  const int64_t items = pairtile_grid((int64_t)mb * nright, ntv);
+  xa.tri = tri ? 1 : 0;
+  const int64_t npairs = tri ? (int64_t)nright * (nright + 1) / 2 : (int64_t)mb * nright;
+  const int64_t items = pairtile_grid(npairs, ntv);
   const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
   hipError_t e = launch_zero(reinterpret_cast<double *>(ctr), 4, st);
   if (e != hipSuccess) return e;
@@ -471,7 +484,7 @@ hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, 
 hipError_t launch_cavv_x_fp64(const Plan &pl, void *ws, int m0, int mb, hipStream_t st) {
   return launch_x_fp64(ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), (int)pl.na, (int)pl.ntv,
                        pl.naux_p, m0, mb, reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)),
-                       ws_d(ws, pl.off_xb), st);
+                       ws_d(ws, pl.off_xb), false, st);
 }
 
 static hipError_t launch_cavv(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,

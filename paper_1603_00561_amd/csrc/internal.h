@@ -119,9 +119,11 @@ hipError_t launch_pack_panels(const double *B, double *P, int64_t nrow, int64_t 
                               int64_t naux, int64_t naux_p, int64_t ntile, int width,
                               hipStream_t st);
 // X[ml][u][e][f] = sum_Q L^Q_{(m0+ml) e} R^Q_{u f} for ml < mb, u < nright, from
-// 64-wide panels (row length ntv 64); ctr: eight work counters, cleared here
+// 64-wide panels (row length ntv 64); ctr: eight work counters, cleared here.
+// tri (L = R, m0 = 0, mb = nright): only the blocks ml <= u are written.
 hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv,
-                         int64_t naux_p, int m0, int mb, int *ctr, double *Xb, hipStream_t st);
+                         int64_t naux_p, int m0, int mb, int *ctr, double *Xb, bool tri,
+                         hipStream_t st);
 // J[panel 64 + r][c] = sum_Q Pleft[panel][Q][r] R[Q][c], R row-major [naux_p][ncols],
 // ncols a multiple of 16
 hipError_t launch_j_fp64(const double *Pleft, int64_t npanels, const double *R, int64_t ncols,
