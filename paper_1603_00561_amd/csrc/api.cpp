@@ -80,7 +80,9 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
     return fail(DSRG_ERR_UNSUPPORTED, "dimensions too large (nc %lld, nv %lld, naux %lld)",
                 (long long)p->nc, (long long)p->nv, (long long)p->naux);
   if (precision == DSRG_SPLIT_BF16)
-    return fail(DSRG_ERR_UNSUPPORTED, "precision %d is not available in this build", precision);
+    return fail(DSRG_ERR_UNSUPPORTED,
+                "precision %d is not implemented (three BF16 products cannot reach 1e-6 Eh)",
+                precision);
   if (precision == DSRG_SPLIT_OZAKI && p->naux > DSRG_DF_MAX_SLICE_NAUX)
     return fail(DSRG_ERR_UNSUPPORTED,
                 "naux = %lld exceeds %d, beyond which int32 slice sums could overflow",

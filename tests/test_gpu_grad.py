@@ -1,7 +1,7 @@
 """GPU parity of dsrg_df_energy_backward (FP64 path) against the CPU oracle's
 analytic gradient, central finite differences and the gradient identities.
 
-Gate (the benchmark spec): relative gradient error <= 1e-6; the FP64 path is held to
+Gate: relative gradient error <= 1e-6; the FP64 path is held to
 1e-9 relative (norm-wise and per entry against the largest entry)."""
 import copy
 import json

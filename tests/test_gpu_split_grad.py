@@ -1,7 +1,7 @@
 """GPU parity of dsrg_df_energy_backward on the int8 slice path (precision
 "ozaki"): the adjoint products dE/dB run on error-free int8 slices.
 
-Gate (the benchmark spec): relative gradient error <= 1e-6, norm-wise and per entry
+Gate: relative gradient error <= 1e-6, norm-wise and per entry
 against the largest entry of each output, against the CPU oracle's analytic
 gradient; the energies the backward call returns are held to the split-path
 gate of 1e-6 Eh per term."""
