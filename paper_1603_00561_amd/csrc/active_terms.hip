@@ -375,19 +375,20 @@ hipError_t launch_active_terms(const ActivePlan &pl, const ActiveInputs &in, voi
                          reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)), ws_d(ws, pl.off_x), true,
                          st)) != hipSuccess)
     return e;
-  if ((e = launch_j_fp64(Pav, pl.na * pl.ntv, Rca, pl.ncC, pl.naux_p, ws_d(ws, pl.off_ja1), st)) !=
+  double *jp = ws_d(ws, pl.off_jpart);
+  if ((e = launch_j_fp64(Pav, pl.na * pl.ntv, Rca, pl.ncC, pl.naux_p, ws_d(ws, pl.off_ja1), jp,
+                         st)) != hipSuccess)
+    return e;
+  if ((e = launch_j_fp64(Pcv, pl.nc * pl.ntv, Raa, pl.ncA, pl.naux_p, ws_d(ws, pl.off_ja2), jp,
+                         st)) != hipSuccess)
+    return e;
+  if ((e = launch_j_fp64(Pav, pl.na * pl.ntv, Raa, pl.ncA, pl.naux_p, ws_d(ws, pl.off_jc1), jp,
+                         st)) != hipSuccess)
+    return e;
+  if ((e = launch_j_fp64(Pca, pl.nc, Rca, pl.ncC, pl.naux_p, ws_d(ws, pl.off_jk), jp, st)) !=
       hipSuccess)
     return e;
-  if ((e = launch_j_fp64(Pcv, pl.nc * pl.ntv, Raa, pl.ncA, pl.naux_p, ws_d(ws, pl.off_ja2), st)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_j_fp64(Pav, pl.na * pl.ntv, Raa, pl.ncA, pl.naux_p, ws_d(ws, pl.off_jc1), st)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_j_fp64(Pca, pl.nc, Rca, pl.ncC, pl.naux_p, ws_d(ws, pl.off_jk), st)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_j_fp64(Pca, pl.nc, Raa, pl.ncA, pl.naux_p, ws_d(ws, pl.off_je), st)) !=
+  if ((e = launch_j_fp64(Pca, pl.nc, Raa, pl.ncA, pl.naux_p, ws_d(ws, pl.off_je), jp, st)) !=
       hipSuccess)
     return e;
   switch (pl.na) {

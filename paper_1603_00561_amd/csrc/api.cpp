@@ -335,11 +335,18 @@ dsrg_status make_active_plan(const dsrg_df_problem *p, dsrg::ActivePlan &pl) {
     pl.off_jc1 = take(na * W * (size_t)pl.ncA);
     pl.off_jk = take(nc * kPanel * (size_t)pl.ncC);
     pl.off_je = take(nc * kPanel * (size_t)pl.ncA);
+    // scratch of the segmented integral blocks: the largest segments x block
+    const int64_t jb[5][2] = {{pl.na * pl.ntv, pl.ncC}, {pl.nc * pl.ntv, pl.ncA},
+                              {pl.na * pl.ntv, pl.ncA}, {pl.nc, pl.ncC}, {pl.nc, pl.ncA}};
+    size_t jpart = 0;
+    for (const auto &b : jb)
+      jpart = std::max(jpart, (size_t)(j_segments(b[0], b[1], pl.naux_p) * b[0] * kPanel * b[1]));
+    pl.off_jpart = take(jpart);
     pl.off_ctr = off;
     off = align256(off + 64);
   } else {
     pl.off_pav = pl.off_pcv = pl.off_pca = pl.off_rca = pl.off_raa = pl.off_x = pl.off_ja1 =
-        pl.off_ja2 = pl.off_jc1 = pl.off_jk = pl.off_je = pl.off_ctr = off;
+        pl.off_ja2 = pl.off_jc1 = pl.off_jk = pl.off_je = pl.off_jpart = pl.off_ctr = off;
   }
   pl.off_slots = take((size_t)base + 1);
   pl.total = off;

@@ -6,6 +6,8 @@
 // with L and R packed panels [Q][64 columns]; the (pq|rs) tiles live only in
 // registers and are reduced into energies in the same kernel (section III:
 // no four-index storage).
+#include <algorithm>
+
 #include "fp64_tiles.h"
 
 namespace dsrg {
@@ -193,6 +195,8 @@ __global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restri
 struct CcavJArgs {
   int64_t naux_p;
   int64_t ncols;     // padded column count of J (multiple of 16)
+  int64_t qseg;      // auxiliary rows per segment (blockIdx.z), a multiple of 16
+  int64_t jstride;   // doubles between the outputs of two segments
 };
 
 template <int NB>   // column blocks of 16 per workgroup
@@ -204,8 +208,11 @@ __global__ __launch_bounds__(256) void ccav_j_fp64_kernel(const double *__restri
   __shared__ double lb[2 * KC * WB];
   const int64_t panel = blockIdx.x;                 // (m, T) panel index
   const int64_t c0 = (int64_t)blockIdx.y * WB;      // first column of this workgroup
-  const double *srcv[1] = {Pcv + panel * a.naux_p * W};
-  const double *srcb[1] = {Pca2 + c0};
+  const int64_t qb = (int64_t)blockIdx.z * a.qseg;  // first auxiliary row of this segment
+  const int64_t nq = (a.naux_p - qb < a.qseg) ? a.naux_p - qb : a.qseg;
+  const double *srcv[1] = {Pcv + panel * a.naux_p * W + qb * W};
+  const double *srcb[1] = {Pca2 + qb * a.ncols + c0};
+  J += (int64_t)blockIdx.z * a.jstride;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane & 15, kl = lane >> 4;
   d4 acc[NB];
@@ -217,13 +224,13 @@ __global__ __launch_bounds__(256) void ccav_j_fp64_kernel(const double *__restri
   sb.load(srcb, a.ncols, 0);
   sv.store(lv);
   sb.store(lb);
-  if (a.naux_p > KC) {
+  if (nq > KC) {
     sv.load(srcv, W, KC);
     sb.load(srcb, a.ncols, KC);
   }
   __syncthreads();
   int b = 0;
-  for (int64_t q0 = 0; q0 < a.naux_p; q0 += KC) {
+  for (int64_t q0 = 0; q0 < nq; q0 += KC) {
     const double *LV = lv + b * (KC * W), *LB = lb + b * (KC * WB);
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
@@ -232,10 +239,10 @@ __global__ __launch_bounds__(256) void ccav_j_fp64_kernel(const double *__restri
 #pragma unroll
       for (int q = 0; q < NB; ++q) acc[q] = mfma64(fa, LB[k * WB + lcol<WB>(16 * q + cl, k)], acc[q]);
     }
-    if (q0 + KC < a.naux_p) {
+    if (q0 + KC < nq) {
       sv.store(lv + (b ^ 1) * (KC * W));
       sb.store(lb + (b ^ 1) * (KC * WB));
-      if (q0 + 2 * KC < a.naux_p) {
+      if (q0 + 2 * KC < nq) {
         sv.load(srcv, W, q0 + 2 * KC);
         sb.load(srcb, a.ncols, q0 + 2 * KC);
       }
@@ -399,23 +406,43 @@ hipError_t launch_pack_fp64(const Plan &pl, const Inputs &in, void *ws, hipStrea
   return hipSuccess;
 }
 
+// out[i] = sum over segments z = 0 .. nseg-1 of part[z stride + i], in that order
+__global__ __launch_bounds__(256) void sum_segments_kernel(const double *__restrict__ part,
+                                                           int nseg, int64_t n, int64_t stride,
+                                                           double *__restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    double v = part[i];
+    for (int z = 1; z < nseg; ++z) v += part[z * stride + i];
+    out[i] = v;
+  }
+}
+
 hipError_t launch_j_fp64(const double *Pleft, int64_t npanels, const double *R, int64_t ncols,
-                         int64_t naux_p, double *J, hipStream_t st) {
-  if (ncols % 16 != 0) return hipErrorInvalidValue;
+                         int64_t naux_p, double *J, double *scratch, hipStream_t st) {
+  if (ncols % 16 != 0 || naux_p % kChunk != 0) return hipErrorInvalidValue;
   CcavJArgs ja;
   ja.naux_p = naux_p;
   ja.ncols = ncols;
-  // column blocks of 16 per workgroup: the largest of 4, 3, 2, 1 that divides
-  // the block count, so no workgroup reads past the last column
-  const int nblk = (int)(ncols / 16);
-  const int NBsel = (nblk % 4 == 0) ? 4 : (nblk % 3 == 0) ? 3 : (nblk % 2 == 0) ? 2 : 1;
-  const dim3 gj((unsigned)npanels, (unsigned)ceil_div(nblk, NBsel));
+  ja.qseg = round_up(ceil_div(naux_p, scratch ? j_segments(npanels, ncols, naux_p) : 1), kChunk);
+  // every segment starts inside the auxiliary range (and holds >= one chunk)
+  const int nseg = (int)ceil_div(naux_p, ja.qseg);
+  ja.jstride = npanels * kPanel * ncols;
+  const int NBsel = j_column_blocks(ncols);
+  const dim3 gj((unsigned)npanels, (unsigned)(ncols / (16 * NBsel)), (unsigned)nseg);
+  double *out = nseg > 1 ? scratch : J;
   timer_begin("ccav_j_fp64", st);
   switch (NBsel) {
-    case 1: hipLaunchKernelGGL(ccav_j_fp64_kernel<1>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
-    case 2: hipLaunchKernelGGL(ccav_j_fp64_kernel<2>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
-    case 3: hipLaunchKernelGGL(ccav_j_fp64_kernel<3>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
-    default: hipLaunchKernelGGL(ccav_j_fp64_kernel<4>, gj, dim3(256), 0, st, Pleft, R, ja, J); break;
+    case 1: hipLaunchKernelGGL(ccav_j_fp64_kernel<1>, gj, dim3(256), 0, st, Pleft, R, ja, out); break;
+    case 2: hipLaunchKernelGGL(ccav_j_fp64_kernel<2>, gj, dim3(256), 0, st, Pleft, R, ja, out); break;
+    case 3: hipLaunchKernelGGL(ccav_j_fp64_kernel<3>, gj, dim3(256), 0, st, Pleft, R, ja, out); break;
+    default: hipLaunchKernelGGL(ccav_j_fp64_kernel<4>, gj, dim3(256), 0, st, Pleft, R, ja, out); break;
+  }
+  if (nseg > 1) {
+    const int64_t n = ja.jstride;
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 4096);
+    hipLaunchKernelGGL(sum_segments_kernel, dim3((unsigned)blocks), dim3(256), 0, st, scratch,
+                       nseg, n, ja.jstride, J);
   }
   timer_end(st);
   return hipGetLastError();
@@ -425,7 +452,7 @@ template <int NA>
 static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                                  double *slots, double *acc) {
   hipError_t e = launch_j_fp64(ws_d(ws, pl.off_pcv), pl.nc * pl.ntv, ws_d(ws, pl.off_pca),
-                               pl.ccav_cols, pl.naux_p, ws_d(ws, pl.off_j), st);
+                               pl.ccav_cols, pl.naux_p, ws_d(ws, pl.off_j), nullptr, st);
   if (e != hipSuccess) return e;
   CcavEpiArgs a;
   a.nc = (int)pl.nc;

@@ -94,6 +94,7 @@ struct ActivePlan {
   size_t off_pav, off_pcv, off_pca, off_rca, off_raa;   // packed operands
   size_t off_x;             // X[x][u][e][f] = (xe|uf)
   size_t off_ja1, off_ja2, off_jc1, off_jk, off_je;    // integral blocks with active indices
+  size_t off_jpart;         // per-segment partial integral blocks (the largest of the five)
   size_t off_ctr, off_slots;
   int64_t slot_base[5], slot_count[5];
   size_t total;
@@ -124,10 +125,27 @@ hipError_t launch_pack_panels(const double *B, double *P, int64_t nrow, int64_t 
 hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv,
                          int64_t naux_p, int m0, int mb, int *ctr, double *Xb, bool tri,
                          hipStream_t st);
+// Column blocks of 16 per workgroup of the J contraction: the largest of 4,
+// 3, 2, 1 that divides the block count, so no workgroup reads past the end.
+inline int j_column_blocks(int64_t ncols) {
+  const int64_t nblk = ncols / 16;
+  return (nblk % 4 == 0) ? 4 : (nblk % 3 == 0) ? 3 : (nblk % 2 == 0) ? 2 : 1;
+}
+// Auxiliary-index segments of a J contraction with a scratch buffer: enough
+// to give about 1024 workgroups, each segment at least four 16-row chunks.
+inline int64_t j_segments(int64_t npanels, int64_t ncols, int64_t naux_p) {
+  const int64_t wgs = npanels * (ncols / (16 * j_column_blocks(ncols)));
+  int64_t nseg = ceil_div(1024, wgs > 0 ? wgs : 1);
+  const int64_t cap = naux_p / (4 * kChunk);
+  if (nseg > cap) nseg = cap;
+  return nseg < 1 ? 1 : nseg;
+}
 // J[panel 64 + r][c] = sum_Q Pleft[panel][Q][r] R[Q][c], R row-major [naux_p][ncols],
-// ncols a multiple of 16
+// ncols a multiple of 16. With scratch (j_segments(...) npanels 64 ncols doubles)
+// the auxiliary range is split into segments whose partial J are summed in a
+// fixed order; without it (nullptr) one pass.
 hipError_t launch_j_fp64(const double *Pleft, int64_t npanels, const double *R, int64_t ncols,
-                         int64_t naux_p, double *J, hipStream_t st);
+                         int64_t naux_p, double *J, double *scratch, hipStream_t st);
 // compensated sums of slot ranges: E[t] = sum of slots[base[t] .. base[t] + count[t])
 hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const int64_t *count,
                                  int nterms, double *E, hipStream_t st);
