@@ -533,6 +533,33 @@ def brute_force_spinorbital(eri, nc, na, nv, eps, gamma1, s):
     return dict(F=F, F1=F1, F2=F2, F3=F3, F4=F4, F5=F5, F6=F6, F7=F7, F8=F8)
 
 
+# ---------------------------------------------------------------------------
+# density-fitting factors (Eq. int_fact, DF definition of section II.C)
+# ---------------------------------------------------------------------------
+def df_factors(ao3, J, C, nfrz, nc, na, nv) -> Dict[str, np.ndarray]:
+    """B^Q_pq for the blocks the energy reads, from AO three-index integrals.
+
+    (pq|P) = sum_{mu nu} C_{mu p} C_{nu q} (mu nu|P) (the MO three-index
+    integrals), then B^Q_pq = sum_P [L^{-1}]_{QP} (pq|P) with J = L L^T the
+    Cholesky factor of the metric: sum_Q B^Q_pq B^Q_rs = (pq|P) J^{-1} (P|rs),
+    the DF integrals of Eq. int_fact (the symmetric J^{-1/2} of the paper gives
+    the same factors up to an orthogonal rotation of Q). Returns B_cv, B_ca,
+    B_av, B_aa in the [Q][p][q] layout of the energy kernels."""
+    o_c = nfrz
+    o_a = nfrz + nc
+    o_v = nfrz + nc + na
+    Cc, Ca, Cv = C[:, o_c:o_a], C[:, o_a:o_v], C[:, o_v:o_v + nv]
+    L = np.linalg.cholesky(J)
+    Linv = np.linalg.solve(L, np.eye(J.shape[0]))      # lower triangular L^{-1}
+
+    def block(Cp, Cq):
+        Y = np.einsum("Pmn,mp,nq->Ppq", ao3, Cp, Cq, optimize=True)   # (pq|P)
+        return np.einsum("QP,Ppq->Qpq", Linv, Y, optimize=True)
+
+    return {"B_cv": block(Cc, Cv), "B_ca": block(Cc, Ca), "B_av": block(Ca, Cv),
+            "B_aa": block(Ca, Ca)}
+
+
 def pivoted_cholesky(M: np.ndarray, tol: float = 0.0) -> np.ndarray:
     """Pivoted Cholesky of a symmetric PSD matrix M ~= L L^T (the numerical
     decomposition that generates CD factors, section II.C). Stops when the

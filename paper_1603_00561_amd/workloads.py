@@ -153,3 +153,47 @@ def make_near_degenerate(nc: int = 3, na: int = 2, nv: int = 20, naux: int = 48,
     B_aa = _b_aa(rng, scale, naux, na)
     return Problem(nc, na, nv, naux, B_cv, B_ca, B_av, eps_c, eps_a, eps_v,
                    gamma1, float(s), "near_degenerate", seed, B_aa=B_aa)
+
+
+@dataclass
+class DFGenProblem:
+    """Inputs of the density-fitting factor build (Eq. int_fact and the DF
+    definition of section II.C): AO three-index integrals (mu nu|P), the
+    two-centre metric J and the MO coefficients, orbitals ordered frozen core |
+    core | active | virtual (host arrays, float64, C order)."""
+
+    nfrz: int
+    nc: int
+    na: int
+    nv: int
+    naux: int
+    nao: int
+    ao3: np.ndarray           # [naux][nao][nao], symmetric in (mu, nu)
+    J: np.ndarray             # [naux][naux], symmetric positive definite
+    C: np.ndarray             # [nao][nmo], nmo = nfrz + nc + na + nv
+    seed: Optional[int] = None
+
+
+def make_dfgen_problem(nfrz: int, nc: int, na: int, nv: int, naux: int,
+                       seed: int = DEFAULT_SEED) -> DFGenProblem:
+    """Seeded synthetic DF-build inputs with nao = nmo: (mu nu|P) symmetric,
+    N(0,1) * 0.05 * exp(-3 P / naux); J = L0 L0^T with L0 lower triangular,
+    unit-order diagonal U[1, 2] and N(0,1) * 0.1 / sqrt(naux) below it (well
+    conditioned); C orthogonal (QR of a standard-normal matrix, column signs
+    fixed). Drawn in that order from one default_rng(seed)."""
+    nmo = nfrz + nc + na + nv
+    nao = nmo
+    rng = np.random.default_rng(seed)
+    q = np.arange(naux, dtype=np.float64)
+    g = rng.standard_normal((naux, nao, nao)) * (0.05 * np.exp(-3.0 * q / naux))[:, None, None]
+    ao3 = 0.5 * (g + g.transpose(0, 2, 1))
+    L0 = np.tril(rng.standard_normal((naux, naux)) * (0.1 / np.sqrt(naux)), -1)
+    L0 += np.diag(rng.uniform(1.0, 2.0, size=naux))
+    J = L0 @ L0.T
+    J = 0.5 * (J + J.T)
+    m = rng.standard_normal((nao, nmo))
+    Cq, r = np.linalg.qr(m)
+    C = Cq * np.sign(np.diag(r))[None, :]
+    return DFGenProblem(nfrz, nc, na, nv, naux, nao, np.ascontiguousarray(ao3),
+                        np.ascontiguousarray(J), np.ascontiguousarray(C), seed)
+

@@ -327,3 +327,47 @@ def test_active_pieces_invariances():
     q.B_aa = p.B_aa[:, pa][:, :, pa]
     q.eps_a, q.gamma1 = p.eps_a[pa], p.gamma1[np.ix_(pa, pa)]
     assert np.allclose(O.active_terms(q), ref, rtol=1e-12, atol=0)
+
+
+# --- DF factors (Eq. int_fact, DF definition of section II.C) ----------------
+def test_df_factors_recover_a_known_factor():
+    # (mu nu|P) built from a known factor B0 through a known metric factor L0 and
+    # orthogonal MO coefficients: the build must return B0 itself
+    from paper_1603_00561_amd.workloads import make_dfgen_problem
+    g = make_dfgen_problem(1, 2, 2, 3, 9, seed=3)
+    nmo = g.nfrz + g.nc + g.na + g.nv
+    rng = np.random.default_rng(4)
+    B0 = rng.standard_normal((g.naux, nmo, nmo))
+    B0 = 0.5 * (B0 + B0.transpose(0, 2, 1))
+    L0 = np.linalg.cholesky(g.J)
+    mo3 = np.einsum("PQ,Qpq->Ppq", L0, B0)                       # (pq|P)
+    ao3 = np.einsum("mp,Ppq,nq->Pmn", g.C, mo3, g.C)              # C (pq|P) C^T
+    f = O.df_factors(ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv)
+    c, a, v = slice(1, 3), slice(3, 5), slice(5, 8)
+    for k, (P, Q) in {"B_cv": (c, v), "B_ca": (c, a), "B_av": (a, v), "B_aa": (a, a)}.items():
+        assert np.allclose(f[k], B0[:, P, Q], rtol=0, atol=1e-12), k
+
+
+def test_df_factors_reproduce_df_integrals_and_energies():
+    # independent route: (pq|rs) = (pq|P) J^{-1} (P|rs) by a linear solve, and
+    # the symmetric J^{-1/2} (eigen-decomposition) gives the same energies
+    from paper_1603_00561_amd.workloads import make_dfgen_problem, make_problem
+    g = make_dfgen_problem(2, 3, 2, 5, 12, seed=5)
+    f = O.df_factors(g.ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv)
+    o = g.nfrz
+    Cc, Cv = g.C[:, o:o + 3], g.C[:, o + 5:o + 10]
+    Y = np.einsum("Pmn,mp,nq->Ppq", g.ao3, Cc, Cv)
+    eri = np.einsum("Ppq,PR,Rrs->pqrs", Y, np.linalg.solve(g.J, np.eye(g.naux)), Y)
+    assert np.allclose(np.einsum("Qpq,Qrs->pqrs", f["B_cv"], f["B_cv"]), eri, rtol=1e-12,
+                       atol=1e-15)
+    w, V = np.linalg.eigh(g.J)
+    Jmh = (V / np.sqrt(w)) @ V.T
+    p = make_problem(3, 2, 5, 12, s=0.5, seed=6)
+    p.B_cv, p.B_ca, p.B_av = f["B_cv"], f["B_ca"], f["B_av"]
+    e_chol = np.array(O.energy_terms(p))
+    for k in ("B_cv", "B_ca", "B_av"):
+        Pb, Qb = {"B_cv": ((o, o + 3), (o + 5, o + 10)), "B_ca": ((o, o + 3), (o + 3, o + 5)),
+                  "B_av": ((o + 3, o + 5), (o + 5, o + 10))}[k]
+        Ym = np.einsum("Pmn,mp,nq->Ppq", g.ao3, g.C[:, Pb[0]:Pb[1]], g.C[:, Qb[0]:Qb[1]])
+        setattr(p, k, np.einsum("QP,Ppq->Qpq", Jmh, Ym))
+    assert np.allclose(O.energy_terms(p), e_chol, rtol=1e-12, atol=0)
