@@ -1,7 +1,8 @@
 /*
  * dsrg_df.h - C ABI of libdsrgdf, the MI355X (gfx950) library for the
  * density-fitted DSRG-MRPT2 energy terms F1 (CCVV), F2 (CAVV) and F3 (CCAV),
- * their gradients, and the remaining pieces F4-F8 of term F.
+ * their gradients, the remaining pieces F4-F8 of term F, and the
+ * density-fitting factors B themselves.
  *
  * What is computed (Hannon, Li, Evangelista, "An integral-factorized
  * implementation of the driven similarity renormalization group second-order
@@ -172,6 +173,36 @@ dsrg_status dsrg_df_active_workspace_size(const dsrg_df_problem *p, size_t *byte
 dsrg_status dsrg_df_energy_active(const dsrg_df_problem *p, const double *B_aa, int options,
                                   double *F_terms, void *workspace, size_t ws_bytes,
                                   void *stream);
+
+/* ---- Density-fitting factors (Eq. int_fact and the DF definition of
+ * section II.C): B^Q_pq = sum_P [J^{-1/2}]_{QP} (pq|P) with the MO
+ * three-index integrals (pq|P) = sum_{mu nu} C_{mu p} C_{nu q} (mu nu|P).
+ * The factor of J^{-1} taken here is L^{-1} with J = L L^T (Cholesky): the
+ * factors differ from the symmetric-root ones by an orthogonal rotation of
+ * Q, so every (pq|rs) = sum_Q B^Q_pq B^Q_rs and every energy is the same. */
+typedef struct {
+  int64_t nao;           /* AO basis functions, >= 1                                */
+  int64_t nmo;           /* molecular orbitals (columns of C), >= nfrz+nc+na+nv    */
+  int64_t naux;          /* auxiliary basis functions, >= 1                         */
+  int64_t nfrz, nc, na, nv; /* frozen core, correlated core, active, virtual MOs    */
+  const double *ao3;     /* [naux][nao][nao] (mu nu|P), symmetric in mu, nu         */
+  const double *J;       /* [naux][naux] two-centre metric, symmetric positive
+                            definite (otherwise the factors contain NaN)            */
+  const double *C;       /* [nao][nmo] MO coefficients; columns ordered frozen core
+                            | core | active | virtual (| any further orbitals)      */
+} dsrg_dfgen_problem;
+
+/* Bytes of device workspace that dsrg_df_factors needs (sizes only). */
+dsrg_status dsrg_df_factors_workspace_size(const dsrg_dfgen_problem *p, size_t *bytes);
+
+/* The blocks of B that the energies read, in the layout of dsrg_df_problem:
+ *   B_cv [naux][nc][nv], B_ca [naux][nc][na], B_av [naux][na][nv],
+ *   B_aa [naux][na][na] (device; the last three may be NULL when na == 0)
+ *   options  0 or DSRG_OPT_KERNEL_TIMING
+ * FP64 throughout. Errors as for dsrg_df_energy. */
+dsrg_status dsrg_df_factors(const dsrg_dfgen_problem *p, int options, double *B_cv,
+                            double *B_ca, double *B_av, double *B_aa, void *workspace,
+                            size_t ws_bytes, void *stream);
 
 /* Text of the last error raised on the calling thread ("" if none). Valid
  * until the next dsrg_df_* call on that thread. */

@@ -25,6 +25,7 @@ MAX_ACTIVE = 8
 
 EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward",
             "dsrg_df_active_workspace_size", "dsrg_df_energy_active",
+            "dsrg_df_factors_workspace_size", "dsrg_df_factors",
             "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_version")
 
 
@@ -42,6 +43,15 @@ class Problem(ctypes.Structure):
         ("eps_c", ctypes.c_void_p), ("eps_a", ctypes.c_void_p), ("eps_v", ctypes.c_void_p),
         ("gamma1", ctypes.c_void_p),
         ("s", ctypes.c_double),
+    ]
+
+
+class DFGenProblem(ctypes.Structure):
+    _fields_ = [
+        ("nao", ctypes.c_int64), ("nmo", ctypes.c_int64), ("naux", ctypes.c_int64),
+        ("nfrz", ctypes.c_int64), ("nc", ctypes.c_int64), ("na", ctypes.c_int64),
+        ("nv", ctypes.c_int64),
+        ("ao3", ctypes.c_void_p), ("J", ctypes.c_void_p), ("C", ctypes.c_void_p),
     ]
 
 
@@ -71,6 +81,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_active_workspace_size.restype = i32
     lib.dsrg_df_energy_active.argtypes = [ctypes.POINTER(Problem), vp, i32, vp, vp, sz, vp]
     lib.dsrg_df_energy_active.restype = i32
+    lib.dsrg_df_factors_workspace_size.argtypes = [ctypes.POINTER(DFGenProblem),
+                                                   ctypes.POINTER(sz)]
+    lib.dsrg_df_factors_workspace_size.restype = i32
+    lib.dsrg_df_factors.argtypes = [ctypes.POINTER(DFGenProblem), i32, vp, vp, vp, vp, vp, sz,
+                                    vp]
+    lib.dsrg_df_factors.restype = i32
     lib.dsrg_df_last_error.argtypes = []
     lib.dsrg_df_last_error.restype = ctypes.c_char_p
     lib.dsrg_df_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double),
@@ -223,6 +239,41 @@ def energy_active(B_cv, B_ca, B_av, B_aa, eps_c, eps_a, eps_v, gamma1, s,
                                      ws.data_ptr(), nbytes.value, _stream_handle(dev)))
     del keep, baa
     return F
+
+
+def df_factors(ao3, J, C, nfrz, nc, na, nv, workspace: Optional[torch.Tensor] = None,
+               timing: bool = False):
+    """B_cv, B_ca, B_av, B_aa (device tensors, float64) via dsrg_df_factors
+    from the AO three-index integrals ao3 [naux][nao][nao], the metric J
+    [naux][naux] and the MO coefficients C [nao][nmo]."""
+    lib = load_library()
+    naux, nao, _ = ao3.shape
+    nmo = C.shape[1]
+    dev = ao3.device
+    keep = [_as_dev(ao3, "ao3", (naux, nao, nao), dev), _as_dev(J, "J", (naux, naux), dev),
+            _as_dev(C, "C", (nao, nmo), dev)]
+    p = DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, *[_ptr(t) for t in keep])
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_factors_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    out = {"B_cv": torch.empty(naux, nc, nv, dtype=torch.float64, device=dev),
+           "B_ca": torch.empty(naux, nc, na, dtype=torch.float64, device=dev),
+           "B_av": torch.empty(naux, na, nv, dtype=torch.float64, device=dev),
+           "B_aa": torch.empty(naux, na, na, dtype=torch.float64, device=dev)}
+    ptrs = [out[k].data_ptr() if (k == "B_cv" or na > 0) else None
+            for k in ("B_cv", "B_ca", "B_av", "B_aa")]
+    _check(lib.dsrg_df_factors(ctypes.byref(p), OPT_KERNEL_TIMING if timing else 0, *ptrs,
+                               ws.data_ptr(), nbytes.value, _stream_handle(dev)))
+    del keep
+    return out
+
+
+def df_factors_workspace_size(nao, nmo, naux, nfrz, nc, na, nv) -> int:
+    lib = load_library()
+    p = DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, None, None, None)
+    out = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_factors_workspace_size(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
 
 
 def energy_backward(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, gE, precision="fp64",

@@ -353,6 +353,43 @@ dsrg_status make_active_plan(const dsrg_df_problem *p, dsrg::ActivePlan &pl) {
   return DSRG_OK;
 }
 
+// Plan of the density-fitting factor build: validation of the sizes and the
+// workspace layout.
+dsrg_status make_df_plan(const dsrg_dfgen_problem *p, dsrg::DFPlan &pl) {
+  using namespace dsrg;
+  if (!p) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  if (p->nao < 1 || p->naux < 1 || p->nc < 1 || p->nv < 1 || p->na < 0 || p->nfrz < 0)
+    return fail(DSRG_ERR_ARG, "sizes must satisfy nao, naux, nc, nv >= 1 and na, nfrz >= 0");
+  if (p->nmo < p->nfrz + p->nc + p->na + p->nv)
+    return fail(DSRG_ERR_ARG, "nmo = %lld is smaller than nfrz + nc + na + nv",
+                (long long)p->nmo);
+  if (p->nao > (1 << 20) || p->naux > (1 << 20) || p->nmo > (1 << 20))
+    return fail(DSRG_ERR_UNSUPPORTED, "dimensions too large");
+  pl.nao = p->nao;
+  pl.nmo = p->nmo;
+  pl.naux = p->naux;
+  pl.nfrz = p->nfrz;
+  pl.nc = p->nc;
+  pl.na = p->na;
+  pl.nv = p->nv;
+  const size_t np = (size_t)(pl.nc + pl.na), nq = (size_t)(pl.na + pl.nv);
+  const size_t nx = (size_t)pl.naux;
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t at = off;
+    off = align256(off + sizeof(double) * doubles);
+    return at;
+  };
+  pl.off_t = take(nx * (size_t)pl.nao * nq);
+  pl.off_y = take(nx * np * nq);
+  pl.off_l = take(nx * nx);
+  pl.off_x = take(nx * nx);
+  pl.off_tmp = take(64 * nx);
+  pl.off_bf = take(nx * np * nq);
+  pl.total = off;
+  return DSRG_OK;
+}
+
 }  // namespace
 
 namespace dsrg {
@@ -489,6 +526,50 @@ dsrg_status dsrg_df_energy_active(const dsrg_df_problem *p, const double *B_aa, 
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
   hipError_t e = dsrg::launch_active_terms(pl, in, workspace, F_terms, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_factors_workspace_size(const dsrg_dfgen_problem *p, size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::DFPlan pl;
+  dsrg_status st = make_df_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_factors(const dsrg_dfgen_problem *p, int options, double *B_cv,
+                            double *B_ca, double *B_av, double *B_aa, void *workspace,
+                            size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  dsrg::DFPlan pl;
+  dsrg_status st = make_df_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  if (options & ~DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "unknown option bits 0x%x", options);
+  const struct {
+    const void *ptr;
+    const char *name;
+    bool need;
+  } chk[] = {{p->ao3, "ao3", true},     {p->J, "J", true},          {p->C, "C", true},
+             {B_cv, "B_cv", true},       {B_ca, "B_ca", pl.na > 0}, {B_av, "B_av", pl.na > 0},
+             {B_aa, "B_aa", pl.na > 0}};
+  for (const auto &c : chk)
+    if (c.need && (!c.ptr || !aligned8(c.ptr)))
+      return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", c.name);
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!workspace) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  dsrg::DFInputs in{p->ao3, p->J, p->C};
+  dsrg::DFOutputs o{B_cv, B_ca, B_av, B_aa};
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_df_factors(pl, in, o, workspace, hs);
   if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return DSRG_OK;
 }

@@ -105,6 +105,19 @@ struct ActiveInputs {
   const double *eps_c, *eps_a, *eps_v, *gamma1;
 };
 
+// The density-fitting factor build (FP64).
+struct DFPlan {
+  int64_t nao, nmo, naux, nfrz, nc, na, nv;
+  size_t off_t, off_y, off_l, off_x, off_tmp, off_bf;
+  size_t total;
+};
+struct DFInputs {
+  const double *ao3, *J, *C;
+};
+struct DFOutputs {
+  double *B_cv, *B_ca, *B_av, *B_aa;
+};
+
 // ---- per-kernel timing (api.cpp); no-ops unless the call asked for it ----
 void timer_begin(const char *name, hipStream_t st);
 void timer_end(hipStream_t st);
@@ -149,6 +162,9 @@ hipError_t launch_j_fp64(const double *Pleft, int64_t npanels, const double *R, 
 // compensated sums of slot ranges: E[t] = sum of slots[base[t] .. base[t] + count[t])
 hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const int64_t *count,
                                  int nterms, double *E, hipStream_t st);
+// ---- density-fitting factors (dfgen.hip) ----
+hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutputs &o, void *ws,
+                             hipStream_t st);
 // ---- F4-F8 (active_terms.hip) ----
 hipError_t launch_active_terms(const ActivePlan &pl, const ActiveInputs &in, void *ws,
                                double *F, hipStream_t st);

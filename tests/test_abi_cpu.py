@@ -187,3 +187,33 @@ def test_active_terms_entry_point_validation(lib):
     assert _active(_prob(), options=0x100) == b.DSRG_ERR_ARG           # not an option here
     assert _active(_prob(), ws_bytes=16) == b.DSRG_ERR_WORKSPACE
     assert _active(_prob(), ws=0x40010) == b.DSRG_ERR_WORKSPACE        # not 256-aligned
+
+
+def test_df_factors_entry_point_validation(lib):
+    """DF-factor entry point: workspace sizing and host-side rejection."""
+    def prob(**kw):
+        d = dict(nao=40, nmo=40, naux=30, nfrz=2, nc=5, na=3, nv=30)
+        d.update(kw)
+        a = 0x10000
+        return b.DFGenProblem(d["nao"], d["nmo"], d["naux"], d["nfrz"], d["nc"], d["na"],
+                              d["nv"], a, a, a)
+
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_factors_workspace_size(ctypes.byref(prob()), ctypes.byref(out)) == 0
+    # the half-transformed integrals dominate: naux nao (na + nv) doubles
+    assert out.value >= 8 * 30 * 40 * 33
+
+    def call(p, B=(0x20000, 0x20000, 0x20000, 0x20000), opts=0, ws=0x40000, nb=1 << 40):
+        return lib.dsrg_df_factors(ctypes.byref(p), opts,
+                                   *[ctypes.c_void_p(x) if x else None for x in B],
+                                   ctypes.c_void_p(ws) if ws else None, nb, None)
+
+    for kw in (dict(nao=0), dict(naux=0), dict(nc=0), dict(nv=0), dict(na=-1),
+               dict(nmo=39)):
+        assert call(prob(**kw)) == b.DSRG_ERR_ARG, kw
+        assert lib.dsrg_df_last_error().decode()
+    assert call(prob(), B=(0, 0x20000, 0x20000, 0x20000)) == b.DSRG_ERR_ARG
+    assert call(prob(), B=(0x20000, 0, 0x20000, 0x20000)) == b.DSRG_ERR_ARG
+    assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG
+    assert call(prob(), nb=16) == b.DSRG_ERR_WORKSPACE
+    assert call(prob(), ws=0x40008) == b.DSRG_ERR_WORKSPACE
