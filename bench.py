@@ -5,11 +5,13 @@ contraction kernels with their fused regulariser epilogues, and the final
 reduction) on seeded synthetic inputs already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
-                    [--precision fp64] [--no-cpu-baseline] [--grad | --active]
+                    [--precision fp64] [--no-cpu-baseline] [--grad | --active | --dfgen]
 
 With --active a step is one dsrg_df_energy_active call instead (the pieces
 F4-F8 of term F, FP64), measured the same way against its own algorithmic
-work (the contractions over Q that form its integrals).
+work (the contractions over Q that form its integrals). With --dfgen a step
+is one dsrg_df_factors call (the density-fitting factors B from AO
+three-index integrals, FP64) for the config's orbital spaces.
 
 Prints one JSON line. `value` is algorithmic TFLOP/s of the whole step:
 F_alg = 2 naux [nc(nc+1)/2 nv^2 + nc na nv^2 + nc^2 na nv] (the contractions
@@ -85,6 +87,42 @@ def cpu_baseline_active(p, budget_s=20.0):
     return {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
             "seconds": round(dt, 3),
             "sample": f"F4-F8 over the first {nv_s}/{p.nv} virtual orbitals "
+                      "(FP64 numpy/BLAS oracle, same inputs)"}
+
+
+def dfgen_alg_flops(nao, naux, nc, na, nv):
+    """The density-fitting build: the two MO-transform contractions, the
+    Cholesky factor and inverse of the metric, and the triangular application."""
+    npp, nq = nc + na, na + nv
+    f = {"half1": 2.0 * naux * nao * nao * nq,
+         "half2": 2.0 * naux * npp * nao * nq,
+         "metric": 2.0 * naux ** 3 / 3.0,
+         "apply": 1.0 * naux * naux * npp * nq}
+    return sum(f.values()), f
+
+
+def cpu_baseline_dfgen(g, budget_s=20.0):
+    """The oracle's factor build on the first naux_s auxiliary functions,
+    naux_s sized to the budget from a probe (the work is linear in naux for
+    the transform, which dominates)."""
+    from oracle import dsrg_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    n0 = min(g.naux, 16)
+    t = time.perf_counter()
+    O.df_factors(g.ao3[:n0], g.J[:n0, :n0], g.C, g.nfrz, g.nc, g.na, g.nv)
+    t0 = max(time.perf_counter() - t, 1e-6)
+    ns = int(min(g.naux, max(n0, n0 * budget_s / t0)))
+    t = time.perf_counter()
+    O.df_factors(g.ao3[:ns], g.J[:ns, :ns], g.C, g.nfrz, g.nc, g.na, g.nv)
+    dt = time.perf_counter() - t
+    F, _ = dfgen_alg_flops(g.nao, ns, g.nc, g.na, g.nv)
+    return {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "seconds": round(dt, 3),
+            "sample": f"DF factor build over the first {ns}/{g.naux} auxiliary functions "
                       "(FP64 numpy/BLAS oracle, same inputs)"}
 
 
@@ -172,6 +210,9 @@ def main():
                     help="time energy + gradient (dsrg_df_energy_backward) instead of energy")
     ap.add_argument("--active", action="store_true",
                     help="time the pieces F4-F8 of term F (dsrg_df_energy_active, FP64)")
+    ap.add_argument("--dfgen", action="store_true",
+                    help="time the density-fitting factor build (dsrg_df_factors, FP64) for the "
+                         "orbital spaces of the config with 10 frozen core orbitals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
                          "hardware byte counters can be scaled")
@@ -195,6 +236,8 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
+    if args.dfgen:
+        return bench_dfgen(args, binding, torch)
     p = make_config(args.config)
     if args.active:
         return bench_active(args, p, binding, torch)
@@ -360,6 +403,65 @@ def bench_active(args, p, binding, torch):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_active(p, args.cpu_budget)
+    print(json.dumps(out))
+
+
+def bench_dfgen(args, binding, torch):
+    """--dfgen: one step = one dsrg_df_factors call (FP64)."""
+    from paper_1603_00561_amd.workloads import CONFIGS, make_dfgen_problem
+    from oracle import dsrg_oracle as O
+    if args.precision != "fp64" or args.grad or args.active:
+        print("bench.py: --dfgen runs the FP64 factor build only", file=sys.stderr)
+        sys.exit(2)
+    c = CONFIGS[args.config]
+    nfrz = 10
+    g = make_dfgen_problem(nfrz, c["nc"], c["na"], c["nv"], c["naux"])
+    dev = torch.device("cuda:0")
+    ao3, J, C = (torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (g.ao3, g.J, g.C))
+    nbytes = binding.df_factors_workspace_size(g.nao, g.C.shape[1], g.naux, g.nfrz, g.nc, g.na,
+                                               g.nv)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        f = binding.df_factors(ao3, J, C, g.nfrz, g.nc, g.na, g.nv, workspace=ws)
+    torch.cuda.synchronize()
+    binding.kernel_times(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f = binding.df_factors(ao3, J, C, g.nfrz, g.nc, g.na, g.nv, workspace=ws, timing=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = binding.kernel_times(4096)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    per_kernel = {}
+    for name, ms in kt:
+        per_kernel.setdefault(name, []).append(ms)
+    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
+    Ftot, Fparts = dfgen_alg_flops(g.nao, g.naux, g.nc, g.na, g.nv)
+    dom = "df_half1"
+    dom_ms = avg.get(dom)
+    ach = Fparts["half1"] / (dom_ms * 1e-3) / 1e12 if dom_ms else None
+    peak = PEAK_TFLOPS["fp64"]
+    roof = {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+            "frac": (ach / peak) if ach else None, "avg_launch_ms": dom_ms,
+            "ops_per_launch": Fparts["half1"], "traffic": None}
+    ref = O.df_factors(g.ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv)
+    err = {k: float(np.abs(f[k].cpu().numpy() - ref[k]).max() / np.abs(ref[k]).max())
+           for k in ref if ref[k].size}
+    out = {
+        "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
+        "value": Ftot / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "s_per_solve": ms_per_step * 1e-3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config} orbital spaces: nfrz={g.nfrz} nc={g.nc} na={g.na} "
+                               f"nv={g.nv} nao={g.nao} naux={g.naux}, density-fitting factors",
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "kernel_ms": avg,
+        "rel_err_vs_oracle": err,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_dfgen(g, args.cpu_budget)
     print(json.dumps(out))
 
 
