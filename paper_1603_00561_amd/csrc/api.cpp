@@ -380,11 +380,11 @@ dsrg_status make_df_plan(const dsrg_dfgen_problem *p, dsrg::DFPlan &pl) {
     off = align256(off + sizeof(double) * doubles);
     return at;
   };
-  pl.off_t = take(nx * (size_t)pl.nao * nq);
+  pl.off_t = take(nx * np * (size_t)pl.nao);
   pl.off_y = take(nx * np * nq);
   pl.off_l = take(nx * nx);
   pl.off_x = take(nx * nx);
-  pl.off_tmp = take(64 * nx);
+  pl.off_tmp = take(nx * nx);   // L21 blocks of the recursive metric factor, at their positions
   pl.off_bf = take(nx * np * nq);
   pl.total = off;
   return DSRG_OK;

@@ -8,11 +8,11 @@
 // for p in core | active and q in active | virtual (the blocks B_cv, B_ca,
 // B_av, B_aa that the energy reads). The symmetric J^{-1/2} of the paper gives
 // the same factors up to an orthogonal rotation of Q, which leaves every
-// (pq|rs) unchanged. Steps: T[(P mu)][q] = (mu nu|P) C_{nu q} (one GEMM over
-// all P and mu), Y[P][p][q] = C_{mu p} T[P][mu][q] (batched over P), the
-// blocked Cholesky factor of J and its blocked inverse, B = L^{-1} Y (one GEMM
-// whose contraction stops at the diagonal), and a scatter into the four
-// output blocks.
+// (pq|rs) unchanged. Steps: T[P][p][nu] = C_{mu p} (mu nu|P) (batched over
+// P, the short core | active index first), Y[(P p)][q] = T[(P p)][nu] C_{nu q}
+// (one GEMM over all P and p), the Cholesky factor of J and its inverse by
+// recursive blocking, B = L^{-1} Y (one GEMM whose contraction stops at the
+// diagonal), and a scatter into the four output blocks.
 #include <algorithm>
 
 #include "common_device.h"
@@ -24,12 +24,20 @@ namespace dsrg {
 // C[b] = alpha op(A[b]) op(B[b]) + beta C[b] for b = blockIdx.z, row-major:
 //   op(A)(m, k) = TA ? A[k lda + m] : A[m lda + k]
 //   op(B)(k, n) = TB ? B[n ldb + k] : B[k ldb + n]
-// 128 x 128 tile per workgroup of 8 waves (two per SIMD), wave w owning rows
-// 64 (w >> 2) .. +63 and columns 32 (w & 3) .. +31; K chunks of 16 staged
-// through registers into LDS ([k][m] and [k][n] rows of 128, odd rows with
-// their 16-column halves swapped), one barrier per chunk. Out-of-range
-// elements read as zero. With ktri set the contraction of row tile t stops
-// at k = 128 (t + 1) (A lower triangular).
+// One TM x TN tile per workgroup of WR x WC x KS waves, each wave owning a
+// (TM / WR) x (TN / WC) block of 16 x 16 FP64 MFMA fragments and every KS-th
+// group of four k of each chunk; K chunks of KC staged through registers into
+// LDS, one barrier per chunk; with KS > 1 the KS partial tiles are summed
+// through LDS in a fixed order at the end. Each operand is
+// read along its contiguous index: an operand contiguous in k is staged as
+// [row][k] rows of KC + 1 (one pad), one contiguous in m or n as [k][row]
+// rows whose odd rows have their 16-element halves swapped. Out-of-range elements
+// read as zero. With ktri set the contraction of the row tile starting at m0
+// stops at k = m0 + TM (A lower triangular). Four shapes: 128 x 128 (8 waves)
+// for large products, 32 x 128 (4 waves) for products with at most 32 rows,
+// 64 x 64 (4 waves, K chunks of 32) and 32 x 32 with K split over 4 waves (K
+// chunks of 64) to spread smaller ones over more SIMDs: one FP64 MFMA wave
+// needs about a microsecond per 32 x 32 x 32 block.
 // ---------------------------------------------------------------------------
 struct GemmGArgs {
   int64_t M, N, K;
@@ -39,97 +47,166 @@ struct GemmGArgs {
   int ktri;
 };
 
-constexpr int kGG = 128, kGGK = 16, kGGThreads = 512;
+template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1>
+struct GTile {
+  static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_, KC = KC_, KP = KC_ + 1;
+  static constexpr int KS = KS_;                     // waves splitting each chunk's k
+  static constexpr int WM = TM / WR, WN = TN / WC;   // wave block
+  static constexpr int FP = WM / 16, FQ = WN / 16;   // fragments per wave
+  static constexpr int NT = 64 * WR * WC * KS;       // threads
+  static constexpr int JA = TM * KC / NT, JB = TN * KC / NT;
+  static_assert(WM % 16 == 0 && WN % 16 == 0 && KC % 4 == 0, "whole fragments");
+  static_assert(TM * KC % NT == 0 && TN * KC % NT == 0, "chunk split evenly");
+  static_assert(TM >= 32 && TN >= 32, "half swap needs rows of at least 32");
+  static_assert(KC % (4 * KS) == 0, "k groups split evenly over the waves");
+  static_assert((KS - 1) * 64 * FP * FQ * 4 <= 2 * TM * KP, "reduction fits the A stage");
+};
+using GBig = GTile<128, 128, 2, 4, 16>;
+using GMid = GTile<64, 64, 2, 2, 32>;
+using GThin = GTile<32, 128, 1, 4, 16>;
+using GSplit = GTile<32, 32, 1, 1, 64, 4>;
 
 __device__ __forceinline__ int gswz(int k) { return (k & 1) << 4; }
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(kGGThreads) void gemm_g_kernel(const double *__restrict__ A,
-                                                          const double *__restrict__ B,
-                                                          GemmGArgs a, double *__restrict__ C) {
-  __shared__ double sA[2][kGGK * kGG];
-  __shared__ double sB[2][kGGK * kGG];
-  const int64_t m0 = (int64_t)blockIdx.x * kGG, n0 = (int64_t)blockIdx.y * kGG;
+// element j of thread t's share of an R x KC operand chunk: (row, k) and the
+// LDS index; KFAST: the operand is contiguous in k
+template <bool KFAST, int R, int NT, int KC>
+__device__ __forceinline__ void chunk_slot(int t, int j, int &row, int &k, int &lidx) {
+  const int e = t + NT * j;
+  if (KFAST) {
+    row = e / KC;
+    k = e % KC;
+    lidx = row * (KC + 1) + k;
+  } else {
+    k = e / R;
+    row = e % R;
+    lidx = k * R + (row ^ gswz(k));
+  }
+}
+
+template <bool KFAST, int R, int KC>
+__device__ __forceinline__ double frag(const double *L, int row, int k) {
+  return KFAST ? L[row * (KC + 1) + k] : L[k * R + (row ^ gswz(k))];
+}
+
+template <bool TA, bool TB, class G>
+__global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict__ A,
+                                                      const double *__restrict__ B, GemmGArgs a,
+                                                      double *__restrict__ C) {
+  constexpr bool AK = !TA, BK = TB;   // operands contiguous in k
+  constexpr int TM = G::TM, TN = G::TN, NT = G::NT, KC = G::KC;
+  __shared__ double sA[2][TM * G::KP];
+  __shared__ double sB[2][TN * G::KP];
+  const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
   A += (int64_t)blockIdx.z * a.sa;
   B += (int64_t)blockIdx.z * a.sb;
   C += (int64_t)blockIdx.z * a.sc;
-  const int64_t K = a.ktri ? std::min(a.K, m0 + kGG) : a.K;
+  const int64_t K = a.ktri ? std::min(a.K, m0 + TM) : a.K;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 2, wc = wave & 3;
+  const int ks = wave / (G::WR * G::WC), wrc = wave % (G::WR * G::WC);
+  const int wr = wrc / G::WC, wc = wrc % G::WC;
   const int cl = lane & 15, kl = lane >> 4;
-  d4 acc[4][2];
+  d4 acc[G::FP][G::FQ];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < G::FP; ++p)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < G::FQ; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
 
-  // chunk element e = t + 512 j (j < 4): row k = e / 128, column c = e % 128
-  double ra[4], rb[4];
+  double ra[G::JA], rb[G::JB];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int e = t + kGGThreads * j;
-      const int64_t k = k0 + e / kGG;
-      const int64_t m = m0 + e % kGG, n = n0 + e % kGG;
-      double va = 0.0, vb = 0.0;
-      if (k < K) {
-        if (m < a.M) va = TA ? A[k * a.lda + m] : A[m * a.lda + k];
-        if (n < a.N) vb = TB ? B[n * a.ldb + k] : B[k * a.ldb + n];
-      }
-      ra[j] = va;
-      rb[j] = vb;
+    for (int j = 0; j < G::JA; ++j) {
+      int row, k, li;
+      chunk_slot<AK, TM, NT, KC>(t, j, row, k, li);
+      const int64_t m = m0 + row, ka = k0 + k;
+      ra[j] = (ka < K && m < a.M) ? (TA ? A[ka * a.lda + m] : A[m * a.lda + ka]) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < G::JB; ++j) {
+      int row, k, li;
+      chunk_slot<BK, TN, NT, KC>(t, j, row, k, li);
+      const int64_t n = n0 + row, kb = k0 + k;
+      rb[j] = (kb < K && n < a.N) ? (TB ? B[n * a.ldb + kb] : B[kb * a.ldb + n]) : 0.0;
     }
   };
   auto sstore = [&](int b) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int e = t + kGGThreads * j;
-      const int k = e / kGG, c = e % kGG;
-      sA[b][k * kGG + (c ^ gswz(k))] = ra[j];
-      sB[b][k * kGG + (c ^ gswz(k))] = rb[j];
+    for (int j = 0; j < G::JA; ++j) {
+      int row, k, li;
+      chunk_slot<AK, TM, NT, KC>(t, j, row, k, li);
+      sA[b][li] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < G::JB; ++j) {
+      int row, k, li;
+      chunk_slot<BK, TN, NT, KC>(t, j, row, k, li);
+      sB[b][li] = rb[j];
     }
   };
 
   if (K > 0) {
     gload(0);
     sstore(0);
-    if (K > kGGK) gload(kGGK);
+    if (K > KC) gload(KC);
   }
   __syncthreads();
   int b = 0;
-  for (int64_t k0 = 0; k0 < K; k0 += kGGK) {
+  for (int64_t k0 = 0; k0 < K; k0 += KC) {
     const double *LA = sA[b], *LB = sB[b];
 #pragma unroll
-    for (int kk = 0; kk < kGGK / 4; ++kk) {
-      const int k = kk * 4 + kl;
-      double fa[4], fb[2];
+    for (int kg = 0; kg < KC / (4 * G::KS); ++kg) {
+      const int k = (kg * G::KS + ks) * 4 + kl;
+      double fa[G::FP], fb[G::FQ];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) fa[p] = LA[k * kGG + ((64 * wr + 16 * p + cl) ^ gswz(k))];
+      for (int p = 0; p < G::FP; ++p) fa[p] = frag<AK, TM, KC>(LA, G::WM * wr + 16 * p + cl, k);
 #pragma unroll
-      for (int q = 0; q < 2; ++q) fb[q] = LB[k * kGG + ((32 * wc + 16 * q + cl) ^ gswz(k))];
+      for (int q = 0; q < G::FQ; ++q) fb[q] = frag<BK, TN, KC>(LB, G::WN * wc + 16 * q + cl, k);
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+      for (int p = 0; p < G::FP; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < G::FQ; ++q)
           acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[p], fb[q], acc[p][q], 0, 0, 0);
     }
-    if (k0 + kGGK < K) {
+    if (k0 + KC < K) {
       sstore(b ^ 1);
-      if (k0 + 2 * kGGK < K) gload(k0 + 2 * kGGK);
+      if (k0 + 2 * KC < K) gload(k0 + 2 * KC);
     }
     __syncthreads();
     b ^= 1;
   }
+  if constexpr (G::KS > 1) {
+    double *red = &sA[0][0];
+    constexpr int NV = G::FP * G::FQ * 4;
+    if (ks > 0) {
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int64_t n = n0 + 32 * wc + 16 * q + cl;
+      for (int p = 0; p < G::FP; ++p)
+#pragma unroll
+        for (int q = 0; q < G::FQ; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            red[((ks - 1) * NV + (p * G::FQ + q) * 4 + r) * 64 + lane] = acc[p][q][r];
+    }
+    __syncthreads();
+    if (ks > 0) return;
+    for (int w = 1; w < G::KS; ++w)
+#pragma unroll
+      for (int p = 0; p < G::FP; ++p)
+#pragma unroll
+        for (int q = 0; q < G::FQ; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[p][q][r] += red[((w - 1) * NV + (p * G::FQ + q) * 4 + r) * 64 + lane];
+  }
+#pragma unroll
+  for (int q = 0; q < G::FQ; ++q) {
+    const int64_t n = n0 + G::WN * wc + 16 * q + cl;
     if (n >= a.N) continue;
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < G::FP; ++p)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + 64 * wr + 16 * p + 4 * r + kl;
+        const int64_t m = m0 + G::WM * wr + 16 * p + 4 * r + kl;
         if (m >= a.M) continue;
         double *dst = C + m * a.ldc + n;
         const double v = a.alpha * acc[p][q][r];
@@ -138,118 +215,168 @@ __global__ __launch_bounds__(kGGThreads) void gemm_g_kernel(const double *__rest
   }
 }
 
+template <class G>
+static void gemm_g_launch(bool ta, bool tb, const GemmGArgs &a, int64_t batch, const double *A,
+                          const double *B, double *C, hipStream_t st) {
+  const dim3 grid((unsigned)ceil_div(a.M, G::TM), (unsigned)ceil_div(a.N, G::TN), (unsigned)batch);
+  const dim3 block(G::NT);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_g_kernel<false, false, G>), grid, block, 0, st, A, B, a, C);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_g_kernel<true, false, G>), grid, block, 0, st, A, B, a, C);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_g_kernel<false, true, G>), grid, block, 0, st, A, B, a, C);
+  else
+    hipLaunchKernelGGL((gemm_g_kernel<true, true, G>), grid, block, 0, st, A, B, a, C);
+}
+
+// tile shape: 32 x 128 for at most 32 rows when that gives a tile per CU,
+// else 128 x 128 when that gives a few hundred tiles, else 64 x 64 when that
+// gives a tile per CU, else 32 x 32 with K split over four waves
 static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                          const double *A, int64_t lda, int64_t sa, const double *B, int64_t ldb,
                          int64_t sb, double beta, double *C, int64_t ldc, int64_t sc,
                          int64_t batch, bool ktri, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0};
-  const dim3 grid((unsigned)ceil_div(M, kGG), (unsigned)ceil_div(N, kGG), (unsigned)batch);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_g_kernel<false, false>), grid, dim3(kGGThreads), 0, st, A, B, a, C);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_g_kernel<true, false>), grid, dim3(kGGThreads), 0, st, A, B, a, C);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_g_kernel<false, true>), grid, dim3(kGGThreads), 0, st, A, B, a, C);
+  auto tiles = [&](int tm, int tn) { return ceil_div(M, tm) * ceil_div(N, tn) * batch; };
+  if (M <= GThin::TM && tiles(GThin::TM, GThin::TN) >= 256)
+    gemm_g_launch<GThin>(ta, tb, a, batch, A, B, C, st);
+  else if (tiles(GBig::TM, GBig::TN) >= 384)
+    gemm_g_launch<GBig>(ta, tb, a, batch, A, B, C, st);
+  else if (tiles(GMid::TM, GMid::TN) >= 256)
+    gemm_g_launch<GMid>(ta, tb, a, batch, A, B, C, st);
   else
-    hipLaunchKernelGGL((gemm_g_kernel<true, true>), grid, dim3(kGGThreads), 0, st, A, B, a, C);
+    gemm_g_launch<GSplit>(ta, tb, a, batch, A, B, C, st);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Blocked Cholesky J = L L^T in place (lower triangle; the strict upper
-// triangle of each diagonal block is cleared), block width kDB. A metric that
-// is not positive definite gives NaN in L (square root of a negative pivot).
+// Cholesky factor and inverse of the metric, J = L L^T, X = L^{-1}, by
+// recursive 2 x 2 blocking (split at a multiple of kDB):
+//   (L11, X11) of J11;  L21 = J21 X11^T;  J22 -= L21 L21^T;  (L22, X22) of J22;
+//   X21 = -X22 (L21 X11)
+// so the large GEMMs sit at the top of the recursion; leaves of at most kDB
+// rows are factored and inverted by one workgroup each. Only the lower triangle of
+// the working copy of J is read, and the copy is overwritten; X is written
+// lower triangular (the caller clears it). A metric that is not positive
+// definite gives NaN (square root of a negative pivot).
 // ---------------------------------------------------------------------------
 constexpr int kDB = 64;
 
-// factor the nb x nb diagonal block at (k0, k0) (one workgroup)
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double *__restrict__ Am, int64_t lda,
-                                                         int64_t k0, int nb) {
-  __shared__ double a[kDB][kDB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int i = e / nb, j = e % nb;
-    a[i][j] = Am[(k0 + i) * lda + k0 + j];
-  }
-  __syncthreads();
+// leaf: the nb x nb diagonal block at (r0, r0) of the working matrix A (its
+// lower triangle) is factored, L L^T, and inverted in one sweep over the
+// columns j: the pivot d = sqrt(a_jj) and column j of L (a_ij / d) come from
+// the trailing matrix, which then loses L_ij L_lj; in the same step forward
+// substitution on L X = I takes row j of X (b_j / d, b starting as the
+// identity) and removes L_ij x_j from the rows below. L itself is never
+// stored. 256 threads; thread (ty, tx) holds in registers the elements
+// (ty + 16 a, tx + 16 b), a, b < 4, of the trailing matrix and of b; rows and
+// columns past nb hold the identity. Two barriers per column (the pivot, then
+// column j of L and row j of X, double-buffered in LDS).
+constexpr int kLeafT = 256;
+
+__global__ __launch_bounds__(kLeafT) void chol_inv_leaf_kernel(const double *__restrict__ A,
+                                                               double *__restrict__ X, int64_t ld,
+                                                               int64_t r0, int nb) {
+  __shared__ double colL[2][kDB], rowX[2][kDB], piv[2];
+  const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
+  double e[4][4], x[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ty + 16 * a, l = tx + 16 * b;
+      double v = (i == l) ? 1.0 : 0.0;
+      if (i < nb && l < nb) v = (l <= i) ? A[(r0 + i) * ld + r0 + l] : A[(r0 + l) * ld + r0 + i];
+      e[a][b] = v;
+      x[a][b] = (i == l) ? 1.0 : 0.0;
+    }
   for (int j = 0; j < nb; ++j) {
-    if (threadIdx.x == 0) a[j][j] = sqrt(a[j][j]);
-    __syncthreads();
-    const double d = a[j][j];
-    for (int i = j + 1 + threadIdx.x; i < nb; i += 256) a[i][j] /= d;
-    __syncthreads();
-    // trailing a[i][l] -= a[i][j] a[l][j] for j < l <= i
-    const int w = nb - j - 1;
-    for (int e = threadIdx.x; e < w * w; e += 256) {
-      const int i = j + 1 + e / w, l = j + 1 + e % w;
-      if (l <= i) a[i][l] -= a[i][j] * a[l][j];
+    const int jb = j >> 4, jr = j & 15, bf = j & 1;
+    if (ty == jr && tx == jr) {
+      double p = e[0][0];
+#pragma unroll
+      for (int a = 1; a < 4; ++a) p = (a == jb) ? e[a][a] : p;
+      piv[bf] = p;
     }
     __syncthreads();
-  }
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int i = e / nb, j = e % nb;
-    Am[(k0 + i) * lda + k0 + j] = (j <= i) ? a[i][j] : 0.0;
-  }
-}
-
-// rows i in [k0 + nb, n): L[i][k0 .. k0+nb) = A[i][k0 .. k0+nb) L_kk^{-T}
-__global__ __launch_bounds__(256) void trsm_panel_kernel(double *__restrict__ Am, int64_t lda,
-                                                         int64_t k0, int nb, int64_t n) {
-  __shared__ double l[kDB][kDB + 1];
-  for (int e = threadIdx.x; e < nb * nb; e += 256) {
-    const int i = e / nb, j = e % nb;
-    l[i][j] = Am[(k0 + i) * lda + k0 + j];
-  }
-  __syncthreads();
-  const int64_t i = k0 + nb + (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  double *row = Am + i * lda + k0;
-  double x[kDB];
+    const double d = sqrt(piv[bf]);
+    const double rd = 1.0 / d;
+    if (tx == jr) {
 #pragma unroll
-  for (int j = 0; j < kDB; ++j) {
-    if (j < nb) {
-      double v = row[j];
-      for (int c = 0; c < j; ++c) v -= x[c] * l[j][c];
-      x[j] = v / l[j][j];
-    }
-  }
+      for (int a = 0; a < 4; ++a) {
+        double v = e[a][0];
 #pragma unroll
-  for (int j = 0; j < kDB; ++j)
-    if (j < nb) row[j] = x[j];
-}
-
-// inverse of each lower-triangular diagonal block of L into X (block b per
-// workgroup; thread c solves column c of L_bb X_bb = I)
-__global__ __launch_bounds__(64) void trinv_diag_kernel(const double *__restrict__ L,
-                                                        double *__restrict__ X, int64_t ld,
-                                                        int64_t n) {
-  __shared__ double l[kDB][kDB + 1];
-  const int64_t k0 = (int64_t)blockIdx.x * kDB;
-  const int nb = (int)std::min<int64_t>(kDB, n - k0);
-  for (int e = threadIdx.x; e < nb * nb; e += 64) {
-    const int i = e / nb, j = e % nb;
-    l[i][j] = L[(k0 + i) * ld + k0 + j];
-  }
-  __syncthreads();
-  const int c = threadIdx.x;
-  if (c >= nb) return;
-  double x[kDB];
-#pragma unroll
-  for (int r = 0; r < kDB; ++r) {
-    if (r < nb) {
-      double v = (r == c) ? 1.0 : 0.0;
-      if (r < c) {
-        v = 0.0;
-      } else {
-        for (int q = c; q < r; ++q) v -= l[r][q] * x[q];
-        v /= l[r][r];
+        for (int b = 1; b < 4; ++b) v = (b == jb) ? e[a][b] : v;
+        const int i = ty + 16 * a;
+        colL[bf][i] = (i > j) ? v * rd : 0.0;
       }
-      x[r] = v;
     }
+    if (ty == jr) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        double v = x[0][b];
+#pragma unroll
+        for (int a = 1; a < 4; ++a) v = (a == jb) ? x[a][b] : v;
+        rowX[bf][tx + 16 * b] = v * rd;
+      }
+    }
+    __syncthreads();
+    double ci[4], cl[4], rx[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) ci[a] = colL[bf][ty + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      cl[b] = colL[bf][tx + 16 * b];
+      rx[b] = rowX[bf][tx + 16 * b];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        e[a][b] = fma(-ci[a], cl[b], e[a][b]);
+        x[a][b] = (ty + 16 * a == j) ? rx[b] : fma(-ci[a], rx[b], x[a][b]);
+      }
   }
 #pragma unroll
-  for (int r = 0; r < kDB; ++r)
-    if (r < nb) X[(k0 + r) * ld + k0 + c] = x[r];
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ty + 16 * a, l = tx + 16 * b;
+      if (i < nb && l < nb) X[(r0 + i) * ld + r0 + l] = x[a][b];
+    }
+}
+
+// (L, X) of the block [r0, r0 + n) of the working matrix A (leading dimension
+// ld). W has A's shape: the L21 block of each split is written there at its
+// own position (disjoint from every other split's), and A's J21 block, no
+// longer needed once L21 is formed, takes the product L21 X11.
+static hipError_t chol_inv(double *A, double *X, double *W, int64_t ld, int64_t r0, int64_t n,
+                           hipStream_t st) {
+  hipError_t e;
+  if (n <= kDB) {
+    hipLaunchKernelGGL(chol_inv_leaf_kernel, dim3(1), dim3(kLeafT), 0, st, A, X, ld, r0, (int)n);
+    return hipGetLastError();
+  }
+  const int64_t n1 = round_up(ceil_div(n, 2), kDB), n2 = n - n1;
+  if ((e = chol_inv(A, X, W, ld, r0, n1, st)) != hipSuccess) return e;
+  const int64_t o21 = (r0 + n1) * ld + r0, o22 = (r0 + n1) * ld + r0 + n1, o11 = r0 * ld + r0;
+  // L21 = J21 X11^T
+  if ((e = gemm_g(false, true, n2, n1, n1, 1.0, A + o21, ld, 0, X + o11, ld, 0, 0.0, W + o21, ld,
+                  0, 1, false, st)) != hipSuccess)
+    return e;
+  // J22 -= L21 L21^T
+  if ((e = gemm_g(false, true, n2, n2, n1, -1.0, W + o21, ld, 0, W + o21, ld, 0, 1.0, A + o22, ld,
+                  0, 1, false, st)) != hipSuccess)
+    return e;
+  if ((e = chol_inv(A, X, W, ld, r0 + n1, n2, st)) != hipSuccess) return e;
+  // X21 = -X22 (L21 X11)
+  if ((e = gemm_g(false, false, n2, n1, n1, 1.0, W + o21, ld, 0, X + o11, ld, 0, 0.0, A + o21, ld,
+                  0, 1, false, st)) != hipSuccess)
+    return e;
+  return gemm_g(false, false, n2, n1, n2, -1.0, X + o22, ld, 0, A + o21, ld, 0, 0.0, X + o21, ld,
+                0, 1, false, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -296,52 +423,28 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
   const int64_t np = pl.nc + pl.na, nq = pl.na + pl.nv;
   const int64_t oc = pl.nfrz, oa = pl.nfrz + pl.nc;
   double *T = ws_d(ws, pl.off_t), *Y = ws_d(ws, pl.off_y), *Lm = ws_d(ws, pl.off_l);
-  double *X = ws_d(ws, pl.off_x), *Tmp = ws_d(ws, pl.off_tmp), *Bf = ws_d(ws, pl.off_bf);
-  // T[(P mu)][q] = sum_nu (mu nu|P) C[nu][oa + q]
+  double *X = ws_d(ws, pl.off_x), *W = ws_d(ws, pl.off_tmp), *Bf = ws_d(ws, pl.off_bf);
+  // T[P][p][nu] = sum_mu C[mu][oc + p] (mu nu|P), batched over P: the small
+  // (core | active) index first, so the second step contracts nao over
+  // naux np rows instead of naux nao
   timer_begin("df_half1", st);
-  e = gemm_g(false, false, naux * nao, nq, nao, 1.0, in.ao3, nao, 0, in.C + oa, nmo, 0, 0.0, T,
-             nq, 0, 1, false, st);
+  e = gemm_g(true, false, np, nao, nao, 1.0, in.C + oc, nmo, 0, in.ao3, nao, nao * nao, 0.0, T,
+             nao, np * nao, naux, false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
-  // Y[P][p][q] = sum_mu C[mu][oc + p] T[P][mu][q]
+  // Y[(P p)][q] = sum_nu T[(P p)][nu] C[nu][oa + q], one GEMM over all P and p
   timer_begin("df_half2", st);
-  e = gemm_g(true, false, np, nq, nao, 1.0, in.C + oc, nmo, 0, T, nq, nao * nq, 0.0, Y, nq,
-             np * nq, naux, false, st);
+  e = gemm_g(false, false, naux * np, nq, nao, 1.0, T, nao, 0, in.C + oa, nmo, 0, 0.0, Y, nq, 0,
+             1, false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
-  // Cholesky factor of J (copy into L), then X = L^{-1}
+  // Cholesky factor of J (in a copy) and its inverse X = L^{-1}
   timer_begin("df_metric", st);
   if ((e = hipMemcpyAsync(Lm, in.J, sizeof(double) * naux * naux, hipMemcpyDeviceToDevice, st)) !=
       hipSuccess)
     return e;
-  for (int64_t k0 = 0; k0 < naux; k0 += kDB) {
-    const int nb = (int)std::min<int64_t>(kDB, naux - k0);
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, Lm, naux, k0, nb);
-    const int64_t rest = naux - k0 - nb;
-    if (rest > 0) {
-      hipLaunchKernelGGL(trsm_panel_kernel, dim3((unsigned)ceil_div(rest, 256)), dim3(256), 0, st,
-                         Lm, naux, k0, nb, naux);
-      // trailing J[i][j] -= L[i][panel] L[j][panel]^T for i, j >= k0 + nb
-      double *Lp = Lm + (k0 + nb) * naux + k0;
-      e = gemm_g(false, true, rest, rest, nb, -1.0, Lp, naux, 0, Lp, naux, 0, 1.0,
-                 Lm + (k0 + nb) * naux + k0 + nb, naux, 0, 1, false, st);
-      if (e != hipSuccess) return e;
-    }
-  }
-  // X: clear, diagonal block inverses, then block rows
-  //   X[i, 0:i] = -X_ii (L[i, 0:i] X[0:i, 0:i])
   if ((e = launch_zero_fill(X, naux * naux, st)) != hipSuccess) return e;
-  const int64_t nblk = ceil_div(naux, kDB);
-  hipLaunchKernelGGL(trinv_diag_kernel, dim3((unsigned)nblk), dim3(64), 0, st, Lm, X, naux, naux);
-  for (int64_t i = 1; i < nblk; ++i) {
-    const int64_t r0 = i * kDB, nr = std::min<int64_t>(kDB, naux - r0);
-    e = gemm_g(false, false, nr, r0, r0, 1.0, Lm + r0 * naux, naux, 0, X, naux, 0, 0.0, Tmp, naux,
-               0, 1, false, st);
-    if (e != hipSuccess) return e;
-    e = gemm_g(false, false, nr, r0, nr, -1.0, X + r0 * naux + r0, naux, 0, Tmp, naux, 0, 0.0,
-               X + r0 * naux, naux, 0, 1, false, st);
-    if (e != hipSuccess) return e;
-  }
+  if ((e = chol_inv(Lm, X, W, naux, 0, naux, st)) != hipSuccess) return e;
   timer_end(st);
   // B[Q][(p q)] = sum_{P <= Q} X[Q][P] Y[P][(p q)]
   timer_begin("df_metric_apply", st);

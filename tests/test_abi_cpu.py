@@ -200,8 +200,9 @@ def test_df_factors_entry_point_validation(lib):
 
     out = ctypes.c_size_t(0)
     assert lib.dsrg_df_factors_workspace_size(ctypes.byref(prob()), ctypes.byref(out)) == 0
-    # the half-transformed integrals dominate: naux nao (na + nv) doubles
-    assert out.value >= 8 * 30 * 40 * 33
+    # at least the half-transformed integrals, naux (nc + na) nao doubles, the
+    # transformed ones, naux (nc + na) (na + nv), and three naux x naux metrics
+    assert out.value >= 8 * (30 * 8 * 40 + 30 * 8 * 33 + 3 * 30 * 30)
 
     def call(p, B=(0x20000, 0x20000, 0x20000, 0x20000), opts=0, ws=0x40000, nb=1 << 40):
         return lib.dsrg_df_factors(ctypes.byref(p), opts,
