@@ -30,8 +30,9 @@ namespace dsrg {
 // LDS, one barrier per chunk; with KS > 1 the KS partial tiles are summed
 // through LDS in a fixed order at the end. Each operand is
 // read along its contiguous index: an operand contiguous in k is staged as
-// [row][k] rows of KC + 1 (one pad), one contiguous in m or n as [k][row]
-// rows whose odd rows have their 16-element halves swapped. Out-of-range elements
+// [row][k] rows of KC + 2 (two pads: the 16 x 4 fragment read then touches
+// each bank pair at most twice), one contiguous in m or n as [k][row] rows
+// whose odd rows have their 16-element halves swapped. Out-of-range elements
 // read as zero. With ktri set the contraction of the row tile starting at m0
 // stops at k = m0 + TM (A lower triangular). Four shapes: 128 x 128 (8 waves)
 // for large products, 32 x 128 (4 waves) for products with at most 32 rows,
@@ -45,11 +46,14 @@ struct GemmGArgs {
   int64_t sa, sb, sc;      // batch strides
   double alpha, beta;
   int ktri;
+  // folded batch (FOLD kernels): column n is column n % nin of batch n / nin,
+  // which adds (n / nin) * fb to its B offset and (n / nin) * fc to its C offset
+  int64_t nin, fb, fc;
 };
 
 template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1>
 struct GTile {
-  static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_, KC = KC_, KP = KC_ + 1;
+  static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_, KC = KC_, KP = KC_ + 2;
   static constexpr int KS = KS_;                     // waves splitting each chunk's k
   static constexpr int WM = TM / WR, WN = TN / WC;   // wave block
   static constexpr int FP = WM / 16, FQ = WN / 16;   // fragments per wave
@@ -61,7 +65,7 @@ struct GTile {
   static_assert(KC % (4 * KS) == 0, "k groups split evenly over the waves");
   static_assert((KS - 1) * 64 * FP * FQ * 4 <= 2 * TM * KP, "reduction fits the A stage");
 };
-using GBig = GTile<128, 128, 2, 4, 16>;
+using GBig = GTile<128, 128, 2, 4, 32>;
 using GMid = GTile<64, 64, 2, 2, 32>;
 using GThin = GTile<32, 128, 1, 4, 16>;
 using GSplit = GTile<32, 32, 1, 1, 64, 4>;
@@ -76,7 +80,7 @@ __device__ __forceinline__ void chunk_slot(int t, int j, int &row, int &k, int &
   if (KFAST) {
     row = e / KC;
     k = e % KC;
-    lidx = row * (KC + 1) + k;
+    lidx = row * (KC + 2) + k;
   } else {
     k = e / R;
     row = e % R;
@@ -86,13 +90,14 @@ __device__ __forceinline__ void chunk_slot(int t, int j, int &row, int &k, int &
 
 template <bool KFAST, int R, int KC>
 __device__ __forceinline__ double frag(const double *L, int row, int k) {
-  return KFAST ? L[row * (KC + 1) + k] : L[k * R + (row ^ gswz(k))];
+  return KFAST ? L[row * (KC + 2) + k] : L[k * R + (row ^ gswz(k))];
 }
 
-template <bool TA, bool TB, class G>
+template <bool TA, bool TB, class G, bool FOLD = false>
 __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict__ A,
                                                       const double *__restrict__ B, GemmGArgs a,
                                                       double *__restrict__ C) {
+  static_assert(!FOLD || (!TB && G::NT % G::TN == 0), "folded B: n-contiguous, one column per thread");
   constexpr bool AK = !TA, BK = TB;   // operands contiguous in k
   constexpr int TM = G::TM, TN = G::TN, NT = G::NT, KC = G::KC;
   __shared__ double sA[2][TM * G::KP];
@@ -114,6 +119,11 @@ __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict_
     for (int q = 0; q < G::FQ; ++q) acc[p][q] = d4{0.0, 0.0, 0.0, 0.0};
 
   double ra[G::JA], rb[G::JB];
+  int64_t bcol = -1;   // FOLD: this thread's B column offset (-1 past N)
+  if constexpr (FOLD) {
+    const int64_t n = n0 + t % G::TN;
+    if (n < a.N) bcol = n + (n / a.nin) * a.fb;
+  }
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int j = 0; j < G::JA; ++j) {
@@ -127,7 +137,10 @@ __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict_
       int row, k, li;
       chunk_slot<BK, TN, NT, KC>(t, j, row, k, li);
       const int64_t n = n0 + row, kb = k0 + k;
-      rb[j] = (kb < K && n < a.N) ? (TB ? B[n * a.ldb + kb] : B[kb * a.ldb + n]) : 0.0;
+      if constexpr (FOLD)
+        rb[j] = (kb < K && bcol >= 0) ? B[kb * a.ldb + bcol] : 0.0;
+      else
+        rb[j] = (kb < K && n < a.N) ? (TB ? B[n * a.ldb + kb] : B[kb * a.ldb + n]) : 0.0;
     }
   };
   auto sstore = [&](int b) {
@@ -202,13 +215,14 @@ __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict_
   for (int q = 0; q < G::FQ; ++q) {
     const int64_t n = n0 + G::WN * wc + 16 * q + cl;
     if (n >= a.N) continue;
+    const int64_t cn = FOLD ? n + (n / a.nin) * a.fc : n;
 #pragma unroll
     for (int p = 0; p < G::FP; ++p)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + G::WM * wr + 16 * p + 4 * r + kl;
         if (m >= a.M) continue;
-        double *dst = C + m * a.ldc + n;
+        double *dst = C + m * a.ldc + cn;
         const double v = a.alpha * acc[p][q][r];
         *dst = (a.beta != 0.0) ? v + a.beta * *dst : v;
       }
@@ -238,7 +252,7 @@ static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
                          int64_t sb, double beta, double *C, int64_t ldc, int64_t sc,
                          int64_t batch, bool ktri, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0};
+  GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0, 0, 0, 0};
   auto tiles = [&](int tm, int tn) { return ceil_div(M, tm) * ceil_div(N, tn) * batch; };
   if (M <= GThin::TM && tiles(GThin::TM, GThin::TN) >= 256)
     gemm_g_launch<GThin>(ta, tb, a, batch, A, B, C, st);
@@ -248,6 +262,33 @@ static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
     gemm_g_launch<GMid>(ta, tb, a, batch, A, B, C, st);
   else
     gemm_g_launch<GSplit>(ta, tb, a, batch, A, B, C, st);
+  return hipGetLastError();
+}
+
+// C = alpha op(A) B over a batch folded into the columns: B[b] (ldb, batch
+// stride sb) holds columns [b nin, (b + 1) nin) and C[b] (ldc, stride sc)
+// takes them; at most 32 rows, so the 32 x 128 tile runs over nbatch * nin
+// columns with no per-batch ragged tile; folded_fits says whether a product
+// has that form.
+static bool folded_fits(int64_t M, int64_t nin, int64_t nbatch) {
+  return M <= GThin::TM && ceil_div(nin * nbatch, GThin::TN) <= 65535;
+}
+
+static hipError_t gemm_g_folded(bool ta, int64_t M, int64_t nin, int64_t K, double alpha,
+                                const double *A, int64_t lda, const double *B, int64_t ldb,
+                                int64_t sb, double *C, int64_t ldc, int64_t sc, int64_t nbatch,
+                                hipStream_t st) {
+  const int64_t N = nin * nbatch;
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (!folded_fits(M, nin, nbatch)) return hipErrorInvalidValue;
+  GemmGArgs a{M, N, K, lda, ldb, ldc, 0, 0, 0, alpha, 0.0, 0, nin, sb - nin, sc - nin};
+  const dim3 grid(1, (unsigned)ceil_div(N, GThin::TN), 1);
+  if (ta)
+    hipLaunchKernelGGL((gemm_g_kernel<true, false, GThin, true>), grid, dim3(GThin::NT), 0, st, A,
+                       B, a, C);
+  else
+    hipLaunchKernelGGL((gemm_g_kernel<false, false, GThin, true>), grid, dim3(GThin::NT), 0, st,
+                       A, B, a, C);
   return hipGetLastError();
 }
 
@@ -428,8 +469,12 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
   // (core | active) index first, so the second step contracts nao over
   // naux np rows instead of naux nao
   timer_begin("df_half1", st);
-  e = gemm_g(true, false, np, nao, nao, 1.0, in.C + oc, nmo, 0, in.ao3, nao, nao * nao, 0.0, T,
-             nao, np * nao, naux, false, st);
+  if (folded_fits(np, nao, naux))
+    e = gemm_g_folded(true, np, nao, nao, 1.0, in.C + oc, nmo, in.ao3, nao, nao * nao, T, nao,
+                      np * nao, naux, st);
+  else
+    e = gemm_g(true, false, np, nao, nao, 1.0, in.C + oc, nmo, 0, in.ao3, nao, nao * nao, 0.0, T,
+               nao, np * nao, naux, false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
   // Y[(P p)][q] = sum_nu T[(P p)][nu] C[nu][oa + q], one GEMM over all P and p

@@ -47,10 +47,11 @@ def compare(f, ref):
 
 @pytest.mark.parametrize("shape", [(1, 3, 2, 10, 20), (2, 5, 3, 40, 70), (0, 4, 0, 30, 33),
                                    (3, 8, 4, 130, 200), (1, 2, 1, 5, 65), (2, 10, 6, 300, 300),
-                                   (0, 1, 1, 1, 1)])
+                                   (0, 1, 1, 1, 1), (1, 30, 5, 40, 50), (2, 33, 0, 20, 129)])
 def test_small_shapes(shape):
-    # GEMM tiles of 128 with ragged tails, metric blocks of 64 with ragged tails,
-    # na = 0, one orbital per space
+    # GEMM tiles with ragged tails, metric leaves of 64 with ragged tails, na = 0,
+    # one orbital per space; more than 32 core + active orbitals (the first
+    # transform batched over P instead of folded into one product)
     g = make_dfgen_problem(*shape, seed=sum(shape) + 5)
     compare(gpu_factors(g), O.df_factors(g.ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv))
 
