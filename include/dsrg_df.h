@@ -185,7 +185,8 @@ typedef struct {
   int64_t nmo;           /* molecular orbitals (columns of C), >= nfrz+nc+na+nv    */
   int64_t naux;          /* auxiliary basis functions, >= 1                         */
   int64_t nfrz, nc, na, nv; /* frozen core, correlated core, active, virtual MOs    */
-  const double *ao3;     /* [naux][nao][nao] (mu nu|P), symmetric in mu, nu         */
+  const double *ao3;     /* [naux][nao][nao] (mu nu|P) (symmetric in mu, nu by its
+                            definition; the build does not rely on it)              */
   const double *J;       /* [naux][naux] two-centre metric, symmetric positive
                             definite (otherwise the factors contain NaN)            */
   const double *C;       /* [nao][nmo] MO coefficients; columns ordered frozen core
