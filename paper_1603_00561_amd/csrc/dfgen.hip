@@ -34,8 +34,8 @@ namespace dsrg {
 // each bank pair at most twice), one contiguous in m or n as [k][row] rows
 // whose odd rows have their 16-element halves swapped. Out-of-range elements
 // read as zero. With ktri set the contraction of the row tile starting at m0
-// stops at k = m0 + TM (A lower triangular). Four shapes: 128 x 128 (8 waves)
-// for large products, 32 x 128 (4 waves) for products with at most 32 rows,
+// stops at k = m0 + TM (A lower triangular). Four shapes: 128 x 128 (8 waves,
+// K chunks of 32) for large products, 32 x 128 (4 waves) for products with at most 32 rows,
 // 64 x 64 (4 waves, K chunks of 32) and 32 x 32 with K split over 4 waves (K
 // chunks of 64) to spread smaller ones over more SIMDs: one FP64 MFMA wave
 // needs about a microsecond per 32 x 32 x 32 block.
@@ -49,12 +49,14 @@ struct GemmGArgs {
   // folded batch (FOLD kernels): column n is column n % nin of batch n / nin,
   // which adds (n / nin) * fb to its B offset and (n / nin) * fc to its C offset
   int64_t nin, fb, fc;
+  int colfast;   // tile walk: column tiles fastest (A the larger operand)
 };
 
-template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1>
+template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1, int MINW_ = 1>
 struct GTile {
   static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_, KC = KC_, KP = KC_ + 2;
   static constexpr int KS = KS_;                     // waves splitting each chunk's k
+  static constexpr int MINW = MINW_;                 // waves per SIMD the registers must allow
   static constexpr int WM = TM / WR, WN = TN / WC;   // wave block
   static constexpr int FP = WM / 16, FQ = WN / 16;   // fragments per wave
   static constexpr int NT = 64 * WR * WC * KS;       // threads
@@ -93,16 +95,47 @@ __device__ __forceinline__ double frag(const double *L, int row, int k) {
   return KFAST ? L[row * (KC + 2) + k] : L[k * R + (row ^ gswz(k))];
 }
 
-template <bool TA, bool TB, class G, bool FOLD = false>
-__global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict__ A,
+// pair j (two neighbours along the contiguous index) of thread t's share of
+// an R x KC operand chunk: the first element's (row, k) and LDS index
+template <bool KFAST, int R, int NT, int KC>
+__device__ __forceinline__ void pair_slot(int t, int j, int &row, int &k, int &lidx) {
+  const int e = t + NT * j;
+  if (KFAST) {
+    row = e / (KC / 2);
+    k = 2 * (e % (KC / 2));
+    lidx = row * (KC + 2) + k;
+  } else {
+    k = e / (R / 2);
+    row = 2 * (e % (R / 2));
+    lidx = k * R + (row ^ gswz(k));
+  }
+}
+
+// PAIR: operands read and staged as 16-byte pairs along their contiguous
+// index (the host checks that both operands' base pointers, leading
+// dimensions, batch strides and contiguous extents are even, so every pair is
+// aligned and lies wholly inside or outside the operand)
+template <bool TA, bool TB, class G, bool FOLD = false, bool PAIR = false>
+__global__ __launch_bounds__(G::NT, G::MINW) void gemm_g_kernel(const double *__restrict__ A,
                                                       const double *__restrict__ B, GemmGArgs a,
                                                       double *__restrict__ C) {
   static_assert(!FOLD || (!TB && G::NT % G::TN == 0), "folded B: n-contiguous, one column per thread");
+  static_assert(!(FOLD && PAIR), "folded products read single elements");
+  static_assert(G::JA % 2 == 0 && G::JB % 2 == 0, "whole pairs per thread");
   constexpr bool AK = !TA, BK = TB;   // operands contiguous in k
   constexpr int TM = G::TM, TN = G::TN, NT = G::NT, KC = G::KC;
-  __shared__ double sA[2][TM * G::KP];
-  __shared__ double sB[2][TN * G::KP];
-  const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+  __shared__ __align__(16) double sA[2][TM * G::KP];
+  __shared__ __align__(16) double sB[2][TN * G::KP];
+  // XCD-aware tile order: the hardware deals workgroup id (x fastest) to XCD
+  // id % 8; XCD k takes a contiguous range of tiles, walked so that the
+  // workgroups reading one tile of the larger operand run side by side (row
+  // tiles fastest when B is the larger, column tiles fastest when A is): they
+  // share that XCD's L2 and the tile leaves HBM about once
+  const int64_t nx = gridDim.x, ny = gridDim.y, per = nx * ny;
+  const int64_t id = blockIdx.x + nx * blockIdx.y, xcd = id % 8;
+  const int64_t tl = xcd * (per / 8) + std::min<int64_t>(xcd, per % 8) + id / 8;
+  const int64_t m0 = (a.colfast ? tl / ny : tl % nx) * TM;
+  const int64_t n0 = (a.colfast ? tl % ny : tl / nx) * TN;
   A += (int64_t)blockIdx.z * a.sa;
   B += (int64_t)blockIdx.z * a.sb;
   C += (int64_t)blockIdx.z * a.sc;
@@ -125,6 +158,31 @@ __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict_
     if (n < a.N) bcol = n + (n / a.nin) * a.fb;
   }
   auto gload = [&](int64_t k0) {
+    if constexpr (PAIR) {
+#pragma unroll
+      for (int j = 0; j < G::JA / 2; ++j) {
+        int row, k, li;
+        pair_slot<AK, TM, NT, KC>(t, j, row, k, li);
+        const int64_t m = m0 + row, ka = k0 + k;
+        d2v v = {0.0, 0.0};
+        if (ka < K && m < a.M)
+          v = *reinterpret_cast<const d2v *>(TA ? A + ka * a.lda + m : A + m * a.lda + ka);
+        ra[2 * j] = v[0];
+        ra[2 * j + 1] = v[1];
+      }
+#pragma unroll
+      for (int j = 0; j < G::JB / 2; ++j) {
+        int row, k, li;
+        pair_slot<BK, TN, NT, KC>(t, j, row, k, li);
+        const int64_t n = n0 + row, kb = k0 + k;
+        d2v v = {0.0, 0.0};
+        if (kb < K && n < a.N)
+          v = *reinterpret_cast<const d2v *>(TB ? B + n * a.ldb + kb : B + kb * a.ldb + n);
+        rb[2 * j] = v[0];
+        rb[2 * j + 1] = v[1];
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < G::JA; ++j) {
       int row, k, li;
@@ -144,6 +202,21 @@ __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict_
     }
   };
   auto sstore = [&](int b) {
+    if constexpr (PAIR) {
+#pragma unroll
+      for (int j = 0; j < G::JA / 2; ++j) {
+        int row, k, li;
+        pair_slot<AK, TM, NT, KC>(t, j, row, k, li);
+        *reinterpret_cast<d2v *>(&sA[b][li]) = d2v{ra[2 * j], ra[2 * j + 1]};
+      }
+#pragma unroll
+      for (int j = 0; j < G::JB / 2; ++j) {
+        int row, k, li;
+        pair_slot<BK, TN, NT, KC>(t, j, row, k, li);
+        *reinterpret_cast<d2v *>(&sB[b][li]) = d2v{rb[2 * j], rb[2 * j + 1]};
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < G::JA; ++j) {
       int row, k, li;
@@ -229,34 +302,53 @@ __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict_
   }
 }
 
-template <class G>
-static void gemm_g_launch(bool ta, bool tb, const GemmGArgs &a, int64_t batch, const double *A,
-                          const double *B, double *C, hipStream_t st) {
+template <class G, bool PAIR>
+static void gemm_g_launch_p(bool ta, bool tb, const GemmGArgs &a, int64_t batch, const double *A,
+                            const double *B, double *C, hipStream_t st) {
   const dim3 grid((unsigned)ceil_div(a.M, G::TM), (unsigned)ceil_div(a.N, G::TN), (unsigned)batch);
   const dim3 block(G::NT);
   if (!ta && !tb)
-    hipLaunchKernelGGL((gemm_g_kernel<false, false, G>), grid, block, 0, st, A, B, a, C);
+    hipLaunchKernelGGL((gemm_g_kernel<false, false, G, false, PAIR>), grid, block, 0, st, A, B, a, C);
   else if (ta && !tb)
-    hipLaunchKernelGGL((gemm_g_kernel<true, false, G>), grid, block, 0, st, A, B, a, C);
+    hipLaunchKernelGGL((gemm_g_kernel<true, false, G, false, PAIR>), grid, block, 0, st, A, B, a, C);
   else if (!ta && tb)
-    hipLaunchKernelGGL((gemm_g_kernel<false, true, G>), grid, block, 0, st, A, B, a, C);
+    hipLaunchKernelGGL((gemm_g_kernel<false, true, G, false, PAIR>), grid, block, 0, st, A, B, a, C);
   else
-    hipLaunchKernelGGL((gemm_g_kernel<true, true, G>), grid, block, 0, st, A, B, a, C);
+    hipLaunchKernelGGL((gemm_g_kernel<true, true, G, false, PAIR>), grid, block, 0, st, A, B, a, C);
+}
+
+// pairs when both operands allow them: 16-byte-aligned bases, even leading
+// dimensions and batch strides, and an even extent along each contiguous
+// index (k for row-major A and transposed B, m for transposed A, n for B)
+static bool pairs_fit(bool ta, bool tb, const GemmGArgs &a, const double *A, const double *B) {
+  const bool aligned = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+  const bool even = a.lda % 2 == 0 && a.ldb % 2 == 0 && a.sa % 2 == 0 && a.sb % 2 == 0;
+  const bool ext = (ta ? a.M : a.K) % 2 == 0 && (tb ? a.K : a.N) % 2 == 0;
+  return aligned && even && ext;
+}
+
+template <class G>
+static void gemm_g_launch(bool ta, bool tb, const GemmGArgs &a, int64_t batch, const double *A,
+                          const double *B, double *C, hipStream_t st) {
+  if (pairs_fit(ta, tb, a, A, B))
+    gemm_g_launch_p<G, true>(ta, tb, a, batch, A, B, C, st);
+  else
+    gemm_g_launch_p<G, false>(ta, tb, a, batch, A, B, C, st);
 }
 
 // tile shape: 32 x 128 for at most 32 rows when that gives a tile per CU,
-// else 128 x 128 when that gives a few hundred tiles, else 64 x 64 when that
+// else 128 x 128 when that gives three or more tiles per CU, else 64 x 64 when that
 // gives a tile per CU, else 32 x 32 with K split over four waves
 static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                          const double *A, int64_t lda, int64_t sa, const double *B, int64_t ldb,
                          int64_t sb, double beta, double *C, int64_t ldc, int64_t sc,
                          int64_t batch, bool ktri, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0, 0, 0, 0};
+  GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0, 0, 0, 0, M > N ? 1 : 0};
   auto tiles = [&](int tm, int tn) { return ceil_div(M, tm) * ceil_div(N, tn) * batch; };
   if (M <= GThin::TM && tiles(GThin::TM, GThin::TN) >= 256)
     gemm_g_launch<GThin>(ta, tb, a, batch, A, B, C, st);
-  else if (tiles(GBig::TM, GBig::TN) >= 384)
+  else if (tiles(GBig::TM, GBig::TN) >= 768)
     gemm_g_launch<GBig>(ta, tb, a, batch, A, B, C, st);
   else if (tiles(GMid::TM, GMid::TN) >= 256)
     gemm_g_launch<GMid>(ta, tb, a, batch, A, B, C, st);
@@ -281,7 +373,7 @@ static hipError_t gemm_g_folded(bool ta, int64_t M, int64_t nin, int64_t K, doub
   const int64_t N = nin * nbatch;
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!folded_fits(M, nin, nbatch)) return hipErrorInvalidValue;
-  GemmGArgs a{M, N, K, lda, ldb, ldc, 0, 0, 0, alpha, 0.0, 0, nin, sb - nin, sc - nin};
+  GemmGArgs a{M, N, K, lda, ldb, ldc, 0, 0, 0, alpha, 0.0, 0, nin, sb - nin, sc - nin, 0};
   const dim3 grid(1, (unsigned)ceil_div(N, GThin::TN), 1);
   if (ta)
     hipLaunchKernelGGL((gemm_g_kernel<true, false, GThin, true>), grid, dim3(GThin::NT), 0, st, A,
