@@ -45,6 +45,11 @@ x, y, u, v, w, z active, the same spin summation gives
 
 (each pinned against ``brute_force_spinorbital``).
 
+Upstream of the energies: ``df_factors`` builds the blocks of B from AO
+three-index integrals, the metric and the MO coefficients, and
+``generalized_fock`` the generalized Fock matrix of Eq. gen_fock over all
+orbitals from the same DF integrals (both pinned in the test-suite).
+
 Regularisers use libm ``expm1``; every sum over many elements is a
 ``math.fsum``. Gradients are written out from the same formulas by the chain
 rule, term by term, in separate plain code.
@@ -558,6 +563,31 @@ def df_factors(ao3, J, C, nfrz, nc, na, nv) -> Dict[str, np.ndarray]:
 
     return {"B_cv": block(Cc, Cv), "B_ca": block(Cc, Ca), "B_av": block(Ca, Cv),
             "B_aa": block(Ca, Ca)}
+
+
+def generalized_fock(ao3, J, C, h, gamma1, nfrz, nc, na) -> np.ndarray:
+    """Generalized Fock matrix of Eq. gen_fock over all MOs, with the DF
+    integrals (pq|rs) = sum_PQ (pq|P) [J^{-1}]_PQ (Q|rs) (Eq. int_fact, DF
+    definition of section II.C, J^{-1} applied by a linear solve).
+
+    In spin orbitals f_pq = h_pq + sum_rs <pr||qs> gamma_sr; with doubly
+    occupied frozen + core orbitals and the spin-summed active density
+    (gamma = Gamma / 2 per spin) this is f = h + J[D] - K[D] / 2 with the MO
+    density D (2 on the doubly occupied diagonal, Gamma on the active block),
+    J[D]_pq = sum_rs (pq|rs) D_rs and K[D]_pq = sum_rs (pr|qs) D_rs."""
+    nmo = C.shape[1]
+    no = nfrz + nc + na
+    naux = J.shape[0]
+    D = np.zeros((no, no))
+    D[np.arange(nfrz + nc), np.arange(nfrz + nc)] = 2.0
+    D[nfrz + nc:, nfrz + nc:] = gamma1
+    Y = np.einsum("Pmn,mp,nq->Ppq", ao3, C, C, optimize=True)          # (pq|P)
+    Yo = np.ascontiguousarray(Y[:, :, :no])                               # (p r|P), r occupied
+    So = np.linalg.solve(J, Yo.reshape(naux, -1)).reshape(Yo.shape)     # J^{-1} (P|q s)
+    d = np.einsum("Prs,rs->P", So[:, :no, :], D)                          # sum_Q J^-1_PQ (Q|rs) D_rs
+    Jm = np.einsum("Ppq,P->pq", Y, d)
+    Km = np.einsum("Ppr,rs,Pqs->pq", Yo, D, So, optimize=True)
+    return h + Jm - 0.5 * Km
 
 
 def pivoted_cholesky(M: np.ndarray, tol: float = 0.0) -> np.ndarray:

@@ -174,16 +174,34 @@ class DFGenProblem:
     seed: Optional[int] = None
 
 
-def make_dfgen_problem(nfrz: int, nc: int, na: int, nv: int, naux: int,
-                       seed: int = DEFAULT_SEED) -> DFGenProblem:
-    """Seeded synthetic DF-build inputs with nao = nmo: (mu nu|P) symmetric,
-    N(0,1) * 0.05 * exp(-3 P / naux); J = L0 L0^T with L0 lower triangular,
-    unit-order diagonal U[1, 2] and N(0,1) * 0.1 / sqrt(naux) below it (well
-    conditioned); C orthogonal (QR of a standard-normal matrix, column signs
-    fixed). Drawn in that order from one default_rng(seed)."""
+@dataclass
+class FockProblem(DFGenProblem):
+    """Inputs of the generalized Fock build (Eq. gen_fock): the DF-build inputs
+    plus the one-electron integrals h[nmo][nmo] in the MO basis (symmetric) and
+    the spin-summed active 1-RDM gamma1[na][na]."""
+
+    h: np.ndarray = None
+    gamma1: np.ndarray = None
+
+
+def make_fock_problem(nfrz: int, nc: int, na: int, nv: int, naux: int,
+                      seed: int = DEFAULT_SEED) -> FockProblem:
+    """The DF-build inputs of make_dfgen_problem (same seed, same draws), then
+    h = diag(U[-5, -0.5]) + 0.05 (G + G^T) with G ~ N(0,1), then Gamma as in
+    make_problem."""
     nmo = nfrz + nc + na + nv
-    nao = nmo
     rng = np.random.default_rng(seed)
+    ao3, J, C = _dfgen_draws(rng, nmo, naux)
+    G = rng.standard_normal((nmo, nmo))
+    h = np.diag(rng.uniform(-5.0, -0.5, size=nmo)) + 0.05 * (G + G.T)
+    gamma1 = _gamma(rng, na)
+    return FockProblem(nfrz, nc, na, nv, naux, nmo, np.ascontiguousarray(ao3),
+                       np.ascontiguousarray(J), np.ascontiguousarray(C), seed,
+                       np.ascontiguousarray(h), np.ascontiguousarray(gamma1))
+
+
+def _dfgen_draws(rng: np.random.Generator, nmo: int, naux: int):
+    nao = nmo
     q = np.arange(naux, dtype=np.float64)
     g = rng.standard_normal((naux, nao, nao)) * (0.05 * np.exp(-3.0 * q / naux))[:, None, None]
     ao3 = 0.5 * (g + g.transpose(0, 2, 1))
@@ -194,6 +212,20 @@ def make_dfgen_problem(nfrz: int, nc: int, na: int, nv: int, naux: int,
     m = rng.standard_normal((nao, nmo))
     Cq, r = np.linalg.qr(m)
     C = Cq * np.sign(np.diag(r))[None, :]
+    return ao3, J, C
+
+
+def make_dfgen_problem(nfrz: int, nc: int, na: int, nv: int, naux: int,
+                       seed: int = DEFAULT_SEED) -> DFGenProblem:
+    """Seeded synthetic DF-build inputs with nao = nmo: (mu nu|P) symmetric,
+    N(0,1) * 0.05 * exp(-3 P / naux); J = L0 L0^T with L0 lower triangular,
+    unit-order diagonal U[1, 2] and N(0,1) * 0.1 / sqrt(naux) below it (well
+    conditioned); C orthogonal (QR of a standard-normal matrix, column signs
+    fixed). Drawn in that order from one default_rng(seed)."""
+    nmo = nfrz + nc + na + nv
+    nao = nmo
+    rng = np.random.default_rng(seed)
+    ao3, J, C = _dfgen_draws(rng, nmo, naux)
     return DFGenProblem(nfrz, nc, na, nv, naux, nao, np.ascontiguousarray(ao3),
                         np.ascontiguousarray(J), np.ascontiguousarray(C), seed)
 

@@ -371,3 +371,103 @@ def test_df_factors_reproduce_df_integrals_and_energies():
         Ym = np.einsum("Pmn,mp,nq->Ppq", g.ao3, g.C[:, Pb[0]:Pb[1]], g.C[:, Qb[0]:Qb[1]])
         setattr(p, k, np.einsum("QP,Ppq->Qpq", Jmh, Ym))
     assert np.allclose(O.energy_terms(p), e_chol, rtol=1e-12, atol=0)
+
+
+# --- generalized Fock matrix (Eq. gen_fock) ------------------------------------
+def _df_eri(g):
+    # (pq|rs) over all MOs by brute force: the DF definition with J^{-1} from an
+    # explicit inverse (not the oracle's solve)
+    Y = np.einsum("Pmn,mp,nq->Ppq", g.ao3, g.C, g.C)
+    return np.einsum("Ppq,PQ,Qrs->pqrs", Y, np.linalg.inv(g.J), Y)
+
+
+@pytest.mark.parametrize("shape", [(0, 2, 1, 3, 7), (1, 2, 2, 3, 9), (2, 1, 3, 2, 6), (0, 1, 0, 4, 5)])
+def test_fock_equals_spinorbital_definition(shape):
+    # f_pq = h_pq + sum_rs <pr||qs> gamma_sr over spin orbitals (spin-orbital
+    # gamma: 1 on doubly occupied orbitals, Gamma / 2 in each active spin block);
+    # the alpha-alpha block must equal the spin-adapted oracle
+    from paper_1603_00561_amd.workloads import make_fock_problem
+    g = make_fock_problem(*shape, seed=sum(shape) + 40)
+    nmo = g.C.shape[1]
+    eri = _df_eri(g)
+    n2 = 2 * nmo
+    sp = np.arange(n2) % 2                    # spin of spin orbital P = 2 p + sigma
+    orb = np.arange(n2) // 2
+    same = sp[:, None] == sp[None, :]
+    # <pr|qs> = (pq|rs) delta(sp_p, sp_q) delta(sp_r, sp_s)
+    phys = eri[np.ix_(orb, orb, orb, orb)].transpose(0, 2, 1, 3)   # [p][r][q][s] = (pq|rs)
+    phys = phys * same[:, None, :, None] * same[None, :, None, :]
+    anti = phys - phys.transpose(0, 1, 3, 2)
+    gam = np.zeros((n2, n2))
+    ndocc = g.nfrz + g.nc
+    for P in range(n2):
+        if orb[P] < ndocc:
+            gam[P, P] = 1.0
+    a0 = ndocc
+    for P in range(n2):
+        for Q in range(n2):
+            if a0 <= orb[P] < a0 + g.na and a0 <= orb[Q] < a0 + g.na and sp[P] == sp[Q]:
+                gam[P, Q] = 0.5 * g.gamma1[orb[P] - a0, orb[Q] - a0]
+    hso = g.h[np.ix_(orb, orb)] * same
+    fso = hso + np.einsum("prqs,sr->pq", anti, gam)
+    f = O.generalized_fock(g.ao3, g.J, g.C, g.h, g.gamma1, g.nfrz, g.nc, g.na)
+    assert np.allclose(fso[0::2, 0::2], f, rtol=0, atol=1e-12)
+    assert np.allclose(fso[1::2, 1::2], f, rtol=0, atol=1e-12)
+    assert np.allclose(fso[0::2, 1::2], 0.0, atol=1e-14)
+
+
+def test_fock_closed_shell_equals_ao_route():
+    # na = 0: f = h + C^T (J_AO[D] - K_AO[D] / 2) C with the AO density
+    # D = 2 C_occ C_occ^T and the AO Coulomb/exchange matrices built from the
+    # three-index integrals and the symmetric root of J (another route)
+    from paper_1603_00561_amd.workloads import make_fock_problem
+    g = make_fock_problem(2, 3, 0, 6, 15, seed=7)
+    no = g.nfrz + g.nc
+    Dao = 2.0 * g.C[:, :no] @ g.C[:, :no].T
+    w, V = np.linalg.eigh(g.J)
+    Jmh = (V / np.sqrt(w)) @ V.T
+    Bao = np.einsum("QP,Pmn->Qmn", Jmh, g.ao3)
+    Jao = np.einsum("Qmn,Qls,ls->mn", Bao, Bao, Dao)
+    Kao = np.einsum("Qml,Qns,ls->mn", Bao, Bao, Dao)
+    ref = g.h + g.C.T @ (Jao - 0.5 * Kao) @ g.C
+    f = O.generalized_fock(g.ao3, g.J, g.C, g.h, g.gamma1, g.nfrz, g.nc, g.na)
+    assert np.allclose(f, ref, rtol=0, atol=1e-12)
+
+
+def test_fock_active_limits_and_invariances():
+    from paper_1603_00561_amd.workloads import make_fock_problem
+    g = make_fock_problem(1, 2, 3, 5, 12, seed=9)
+    F = lambda gg, nc, na, gam: O.generalized_fock(gg.ao3, gg.J, gg.C, gg.h, gam, gg.nfrz, nc, na)
+    f = F(g, g.nc, g.na, g.gamma1)
+    assert np.allclose(f, f.T, atol=1e-14)
+    # Gamma = 2I: the active orbitals are doubly occupied; Gamma = 0: empty
+    assert np.allclose(F(g, g.nc, g.na, 2.0 * np.eye(3)), F(g, g.nc + 3, 0, np.zeros((0, 0))),
+                       atol=1e-13)
+    assert np.allclose(F(g, g.nc, g.na, np.zeros((3, 3))), F(g, g.nc, 0, np.zeros((0, 0))),
+                       atol=1e-13)
+    # a rotation U among the doubly occupied orbitals changes f by U^T f U on
+    # that block and leaves the density; among the active ones with Gamma -> U^T Gamma U
+    rng = np.random.default_rng(10)
+    q = copy.deepcopy(g)
+    U, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    q.C = g.C.copy()
+    q.C[:, :3] = g.C[:, :3] @ U
+    R = np.eye(g.C.shape[1])
+    R[:3, :3] = U
+    q.h = R.T @ g.h @ R
+    assert np.allclose(F(q, q.nc, q.na, g.gamma1), R.T @ f @ R, atol=1e-12)
+    Ua, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = copy.deepcopy(g)
+    q.C = g.C.copy()
+    q.C[:, 3:6] = g.C[:, 3:6] @ Ua
+    R = np.eye(g.C.shape[1])
+    R[3:6, 3:6] = Ua
+    q.h = R.T @ g.h @ R
+    assert np.allclose(F(q, q.nc, q.na, Ua.T @ g.gamma1 @ Ua), R.T @ f @ R, atol=1e-12)
+    # f - h is quadratic in the three-index integrals and inverse in the metric
+    q = copy.deepcopy(g)
+    q.ao3 = 1.7 * g.ao3
+    assert np.allclose(F(q, q.nc, q.na, g.gamma1) - g.h, 1.7 ** 2 * (f - g.h), atol=1e-12)
+    q = copy.deepcopy(g)
+    q.J = 2.5 * g.J
+    assert np.allclose(F(q, q.nc, q.na, g.gamma1) - g.h, (f - g.h) / 2.5, atol=1e-12)
