@@ -5,13 +5,16 @@ contraction kernels with their fused regulariser epilogues, and the final
 reduction) on seeded synthetic inputs already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
-                    [--precision fp64] [--no-cpu-baseline] [--grad | --active | --dfgen]
+                    [--precision fp64] [--no-cpu-baseline]
+                    [--grad | --active | --dfgen | --fock]
 
 With --active a step is one dsrg_df_energy_active call instead (the pieces
 F4-F8 of term F, FP64), measured the same way against its own algorithmic
 work (the contractions over Q that form its integrals). With --dfgen a step
 is one dsrg_df_factors call (the density-fitting factors B from AO
-three-index integrals, FP64) for the config's orbital spaces.
+three-index integrals, FP64) for the config's orbital spaces; with --fock one
+dsrg_df_fock call (the generalized Fock matrix of Eq. gen_fock from the same
+DF integrals, FP64).
 
 Prints one JSON line. `value` is algorithmic TFLOP/s of the whole step:
 F_alg = 2 naux [nc(nc+1)/2 nv^2 + nc na nv^2 + nc^2 na nv] (the contractions
@@ -109,6 +112,66 @@ def dfgen_alg_bytes(nao, naux, nc, na, nv):
     return {"half1": 8.0 * (naux * nao * nao + naux * npp * nao),
             "half2": 8.0 * (naux * npp * nao + naux * npp * nq),
             "apply": 8.0 * (naux * naux / 2.0 + 2.0 * naux * npp * nq)}
+
+
+def stage_roofline(avg, stages):
+    """Roofline of the longest single-launch stage: stages maps a timer name to
+    its (algorithmic flops, algorithmic HBM bytes); the stage is priced against
+    the FP64 matrix-core peak or the HBM peak, whichever its flops-to-bytes
+    ratio puts it under."""
+    dom = max(stages, key=lambda k: avg.get(k, 0.0))
+    dom_ms = avg.get(dom)
+    ops, nbytes = stages[dom]
+    peak_f, peak_b = PEAK_TFLOPS["fp64"], PEAK_HBM_GBS
+    if nbytes / (peak_b * 1e9) > ops / (peak_f * 1e12):
+        ach = nbytes / (dom_ms * 1e-3) / 1e9 if dom_ms else None
+        return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": peak_b, "unit": "GB/s",
+                "frac": (ach / peak_b) if ach else None, "avg_launch_ms": dom_ms,
+                "bytes_per_launch": nbytes, "flops_per_launch": ops, "traffic": None}
+    ach = ops / (dom_ms * 1e-3) / 1e12 if dom_ms else None
+    return {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": peak_f, "unit": "TFLOP/s",
+            "frac": (ach / peak_f) if ach else None, "avg_launch_ms": dom_ms,
+            "ops_per_launch": ops, "bytes_per_launch": nbytes, "traffic": None}
+
+
+def fock_alg_work(nao, naux, nfrz, nc, na, nv):
+    """Algorithmic flops and single-launch HBM bytes of the generalized Fock
+    build: the two transforms of the occupied-row integrals, the metric factor
+    and inverse, its triangular application, the Coulomb part (the contraction
+    of the fitted density with (mu nu|P) and the AO-to-MO transform) and the
+    exchange product over the auxiliary and occupied indices."""
+    nmo = nfrz + nc + na + nv
+    no = nfrz + nc + na
+    f = {"half1": 2.0 * naux * no * nao * nao,
+         "half2": 2.0 * naux * no * nao * nmo,
+         "metric": 2.0 * naux ** 3 / 3.0,
+         "apply": 1.0 * naux * naux * no * nmo,
+         "coulomb": 2.0 * naux * nao * nao + 2.0 * nao * nao * nmo + 2.0 * nao * nmo * nmo,
+         "exchange": 2.0 * naux * no * nmo * nmo}
+    b = {"half1": 8.0 * (naux * nao * nao + naux * no * nao),
+         "half2": 8.0 * (naux * no * nao + naux * no * nmo),
+         "apply": 8.0 * (naux * naux / 2.0 + 2.0 * naux * no * nmo),
+         "exchange": 8.0 * (2.0 * naux * no * nmo + nmo * nmo)}
+    return sum(f.values()), f, b
+
+
+def cpu_baseline_fock(g, budget_s=20.0):
+    """The oracle's generalized Fock build on the whole workload (a few
+    seconds at the configs' sizes; the budget is not needed)."""
+    from oracle import dsrg_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    t = time.perf_counter()
+    O.generalized_fock(g.ao3, g.J, g.C, g.h, g.gamma1, g.nfrz, g.nc, g.na)
+    dt = time.perf_counter() - t
+    F, _, _ = fock_alg_work(g.nao, g.naux, g.nfrz, g.nc, g.na, g.nv)
+    return {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "seconds": round(dt, 3),
+            "sample": f"the whole generalized Fock build (naux={g.naux}, nmo={g.C.shape[1]}; "
+                      "FP64 numpy/BLAS oracle, same inputs)"}
 
 
 def cpu_baseline_dfgen(g, budget_s=20.0):
@@ -223,6 +286,9 @@ def main():
     ap.add_argument("--dfgen", action="store_true",
                     help="time the density-fitting factor build (dsrg_df_factors, FP64) for the "
                          "orbital spaces of the config with 10 frozen core orbitals")
+    ap.add_argument("--fock", action="store_true",
+                    help="time the generalized Fock build (dsrg_df_fock, FP64) for the orbital "
+                         "spaces of the config with 10 frozen core orbitals")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
                          "hardware byte counters can be scaled")
@@ -248,6 +314,8 @@ def main():
 
     if args.dfgen:
         return bench_dfgen(args, binding, torch)
+    if args.fock:
+        return bench_fock(args, binding, torch)
     p = make_config(args.config)
     if args.active:
         return bench_active(args, p, binding, torch)
@@ -447,25 +515,10 @@ def bench_dfgen(args, binding, torch):
         per_kernel.setdefault(name, []).append(ms)
     avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
     Ftot, Fparts = dfgen_alg_flops(g.nao, g.naux, g.nc, g.na, g.nv)
-    # the dominant single-launch stage (the metric is a chain of launches),
-    # priced against the bound its flops-to-bytes ratio puts it under
-    single = {"df_half1": "half1", "df_half2": "half2", "df_metric_apply": "apply"}
-    dom = max(single, key=lambda k: avg.get(k, 0.0))
-    dom_ms = avg.get(dom)
-    ops = Fparts[single[dom]]
-    nbytes = dfgen_alg_bytes(g.nao, g.naux, g.nc, g.na, g.nv)[single[dom]]
-    peak_f, peak_b = PEAK_TFLOPS["fp64"], PEAK_HBM_GBS
-    if nbytes / (peak_b * 1e9) > ops / (peak_f * 1e12):
-        ach = nbytes / (dom_ms * 1e-3) / 1e9 if dom_ms else None
-        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": peak_b, "unit": "GB/s",
-                "frac": (ach / peak_b) if ach else None, "avg_launch_ms": dom_ms,
-                "bytes_per_launch": nbytes, "flops_per_launch": ops, "traffic": None}
-    else:
-        ach = ops / (dom_ms * 1e-3) / 1e12 if dom_ms else None
-        roof = {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": peak_f,
-                "unit": "TFLOP/s", "frac": (ach / peak_f) if ach else None,
-                "avg_launch_ms": dom_ms, "ops_per_launch": ops, "bytes_per_launch": nbytes,
-                "traffic": None}
+    Bparts = dfgen_alg_bytes(g.nao, g.naux, g.nc, g.na, g.nv)
+    roof = stage_roofline(avg, {"df_half1": (Fparts["half1"], Bparts["half1"]),
+                                "df_half2": (Fparts["half2"], Bparts["half2"]),
+                                "df_metric_apply": (Fparts["apply"], Bparts["apply"])})
     ref = O.df_factors(g.ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv)
     err = {k: float(np.abs(f[k].cpu().numpy() - ref[k]).max() / np.abs(ref[k]).max())
            for k in ref if ref[k].size}
@@ -484,6 +537,64 @@ def bench_dfgen(args, binding, torch):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_dfgen(g, args.cpu_budget)
+    print(json.dumps(out))
+
+
+
+def bench_fock(args, binding, torch):
+    """--fock: one step = one dsrg_df_fock call (FP64)."""
+    from paper_1603_00561_amd.workloads import CONFIGS, make_fock_problem
+    from oracle import dsrg_oracle as O
+    if args.precision != "fp64" or args.grad or args.active:
+        print("bench.py: --fock runs the FP64 Fock build only", file=sys.stderr)
+        sys.exit(2)
+    c = CONFIGS[args.config]
+    g = make_fock_problem(10, c["nc"], c["na"], c["nv"], c["naux"])
+    dev = torch.device("cuda:0")
+    ao3, J, C, h = (torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+                    for x in (g.ao3, g.J, g.C, g.h))
+    g1 = torch.from_numpy(np.ascontiguousarray(g.gamma1)).to(dev) if g.na > 0 else None
+    nmo = g.C.shape[1]
+    nbytes = binding.df_fock_workspace_size(g.nao, nmo, g.naux, g.nfrz, g.nc, g.na, g.nv)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    call = lambda timing: binding.df_fock(ao3, J, C, h, g1, g.nfrz, g.nc, g.na, g.nv,  # noqa: E731
+                                          workspace=ws, timing=timing)
+    for _ in range(args.warmup):
+        F = call(False)
+    torch.cuda.synchronize()
+    binding.kernel_times(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        F = call(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = binding.kernel_times(4096)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    per_kernel = {}
+    for name, ms in kt:
+        per_kernel.setdefault(name, []).append(ms)
+    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
+    Ftot, Fp, Bp = fock_alg_work(g.nao, g.naux, g.nfrz, g.nc, g.na, g.nv)
+    roof = stage_roofline(avg, {"fock_half1": (Fp["half1"], Bp["half1"]),
+                                "fock_half2": (Fp["half2"], Bp["half2"]),
+                                "fock_metric_apply": (Fp["apply"], Bp["apply"])})
+    ref = O.generalized_fock(g.ao3, g.J, g.C, g.h, g.gamma1, g.nfrz, g.nc, g.na)
+    err = float(np.abs(F.cpu().numpy() - ref).max() / np.abs(ref).max())
+    out = {
+        "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
+        "value": Ftot / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "s_per_solve": ms_per_step * 1e-3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config} orbital spaces: nfrz={g.nfrz} nc={g.nc} na={g.na} "
+                               f"nv={g.nv} nao={g.nao} naux={g.naux}, generalized Fock matrix",
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "kernel_ms": avg,
+        "rel_err_vs_oracle": err,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_fock(g, args.cpu_budget)
     print(json.dumps(out))
 
 

@@ -205,6 +205,31 @@ dsrg_status dsrg_df_factors(const dsrg_dfgen_problem *p, int options, double *B_
                             double *B_ca, double *B_av, double *B_aa, void *workspace,
                             size_t ws_bytes, void *stream);
 
+/* ---- Generalized Fock matrix (Eq. gen_fock) over all MOs from the same DF
+ * integrals (pq|rs) = sum_PQ (pq|P) [J^{-1}]_PQ (Q|rs):
+ *   f_pq = h_pq + sum_{i in frozen+core} [2 (pq|ii) - (pi|qi)]
+ *        + sum_{uv in active} Gamma_uv [(pq|uv) - (pu|qv) / 2]
+ * (the spin-orbital f_pq = h_pq + sum_rs <pr||qs> gamma_sr with doubly
+ * occupied frozen and core orbitals and the spin-summed active density
+ * Gamma; spin-orbital gamma = Gamma / 2 in each spin block). */
+typedef struct {
+  dsrg_dfgen_problem df; /* sizes, ao3, J and C as for dsrg_df_factors; here the
+                            symmetry of ao3 in mu, nu is relied on             */
+  const double *h;       /* [nmo][nmo] one-electron integrals, MO basis          */
+  const double *gamma1;  /* [na][na] spin-summed active 1-RDM (NULL if na == 0)  */
+} dsrg_fock_problem;
+
+/* Bytes of device workspace that dsrg_df_fock needs (sizes only). */
+dsrg_status dsrg_df_fock_workspace_size(const dsrg_fock_problem *p, size_t *bytes);
+
+/* F [nmo][nmo] (device): the generalized Fock matrix, FP64.
+ *   options   0 or DSRG_OPT_KERNEL_TIMING
+ *   workspace device buffer of at least dsrg_df_fock_workspace_size(...)
+ *             bytes, 256-byte aligned; its contents on entry do not matter.
+ * Errors as for dsrg_df_energy. */
+dsrg_status dsrg_df_fock(const dsrg_fock_problem *p, int options, double *F, void *workspace,
+                         size_t ws_bytes, void *stream);
+
 /* Text of the last error raised on the calling thread ("" if none). Valid
  * until the next dsrg_df_* call on that thread. */
 const char *dsrg_df_last_error(void);

@@ -26,6 +26,7 @@ MAX_ACTIVE = 8
 EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward",
             "dsrg_df_active_workspace_size", "dsrg_df_energy_active",
             "dsrg_df_factors_workspace_size", "dsrg_df_factors",
+            "dsrg_df_fock_workspace_size", "dsrg_df_fock",
             "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_version")
 
 
@@ -53,6 +54,10 @@ class DFGenProblem(ctypes.Structure):
         ("nv", ctypes.c_int64),
         ("ao3", ctypes.c_void_p), ("J", ctypes.c_void_p), ("C", ctypes.c_void_p),
     ]
+
+
+class FockProblem(ctypes.Structure):
+    _fields_ = [("df", DFGenProblem), ("h", ctypes.c_void_p), ("gamma1", ctypes.c_void_p)]
 
 
 _lib = None
@@ -87,6 +92,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_factors.argtypes = [ctypes.POINTER(DFGenProblem), i32, vp, vp, vp, vp, vp, sz,
                                     vp]
     lib.dsrg_df_factors.restype = i32
+    lib.dsrg_df_fock_workspace_size.argtypes = [ctypes.POINTER(FockProblem), ctypes.POINTER(sz)]
+    lib.dsrg_df_fock_workspace_size.restype = i32
+    lib.dsrg_df_fock.argtypes = [ctypes.POINTER(FockProblem), i32, vp, vp, sz, vp]
+    lib.dsrg_df_fock.restype = i32
     lib.dsrg_df_last_error.argtypes = []
     lib.dsrg_df_last_error.restype = ctypes.c_char_p
     lib.dsrg_df_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double),
@@ -266,6 +275,40 @@ def df_factors(ao3, J, C, nfrz, nc, na, nv, workspace: Optional[torch.Tensor] = 
                                ws.data_ptr(), nbytes.value, _stream_handle(dev)))
     del keep
     return out
+
+
+def df_fock(ao3, J, C, h, gamma1, nfrz, nc, na, nv, workspace: Optional[torch.Tensor] = None,
+            timing: bool = False):
+    """The generalized Fock matrix F [nmo][nmo] (device, float64) via
+    dsrg_df_fock from ao3 [naux][nao][nao], J [naux][naux], C [nao][nmo], the
+    MO one-electron integrals h [nmo][nmo] and the active 1-RDM gamma1."""
+    lib = load_library()
+    naux, nao, _ = ao3.shape
+    nmo = C.shape[1]
+    dev = ao3.device
+    keep = [_as_dev(ao3, "ao3", (naux, nao, nao), dev), _as_dev(J, "J", (naux, naux), dev),
+            _as_dev(C, "C", (nao, nmo), dev), _as_dev(h, "h", (nmo, nmo), dev)]
+    g1 = _as_dev(gamma1, "gamma1", (na, na), dev) if na > 0 else None
+    if g1 is not None:
+        keep.append(g1)
+    p = FockProblem(DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, *[_ptr(t) for t in keep[:3]]),
+                    _ptr(keep[3]), None if g1 is None else _ptr(g1))
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_fock_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    F = torch.empty(nmo, nmo, dtype=torch.float64, device=dev)
+    _check(lib.dsrg_df_fock(ctypes.byref(p), OPT_KERNEL_TIMING if timing else 0, F.data_ptr(),
+                            ws.data_ptr(), nbytes.value, _stream_handle(dev)))
+    del keep
+    return F
+
+
+def df_fock_workspace_size(nao, nmo, naux, nfrz, nc, na, nv) -> int:
+    lib = load_library()
+    p = FockProblem(DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, None, None, None), None, None)
+    out = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_fock_workspace_size(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
 
 
 def df_factors_workspace_size(nao, nmo, naux, nfrz, nc, na, nv) -> int:

@@ -574,6 +574,86 @@ dsrg_status dsrg_df_factors(const dsrg_dfgen_problem *p, int options, double *B_
   return DSRG_OK;
 }
 
+namespace {
+dsrg_status make_fock_plan(const dsrg_fock_problem *p, dsrg::FockPlan &pl) {
+  if (!p) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  dsrg::DFPlan dp;
+  dsrg_status st = make_df_plan(&p->df, dp);
+  if (st != DSRG_OK) return st;
+  pl.nao = dp.nao;
+  pl.nmo = dp.nmo;
+  pl.naux = dp.naux;
+  pl.nfrz = dp.nfrz;
+  pl.nc = dp.nc;
+  pl.na = dp.na;
+  pl.nv = dp.nv;
+  pl.nd = pl.nfrz + pl.nc;
+  pl.no = pl.nd + pl.na;
+  const size_t nx = (size_t)pl.naux, no = (size_t)pl.no, nmo = (size_t)pl.nmo,
+               nao = (size_t)pl.nao;
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t at = off;
+    off = align256(off + sizeof(double) * doubles);
+    return at;
+  };
+  pl.off_t = take(nx * no * nao);
+  pl.off_y = take(nx * no * nmo);   // later the right operand of the exchange product
+  pl.off_l = take(nx * nx);
+  pl.off_x = take(nx * nx);
+  pl.off_w = take(nx * nx);
+  pl.off_bo = take(nx * no * nmo);
+  pl.off_d = take(nx);
+  pl.off_c = take(nx);
+  pl.off_jao = take(nao * nao);
+  pl.off_tj = take(nao * nmo);
+  pl.off_part = take(32 * nmo * nmo);   // split-K partial products of the exchange part (32 at most)
+  pl.total = off;
+  return DSRG_OK;
+}
+}  // namespace
+
+dsrg_status dsrg_df_fock_workspace_size(const dsrg_fock_problem *p, size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::FockPlan pl;
+  dsrg_status st = make_fock_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_fock(const dsrg_fock_problem *p, int options, double *F, void *workspace,
+                         size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  dsrg::FockPlan pl;
+  dsrg_status st = make_fock_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  if (options & ~DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "unknown option bits 0x%x", options);
+  const struct {
+    const void *ptr;
+    const char *name;
+    bool need;
+  } chk[] = {{p->df.ao3, "ao3", true}, {p->df.J, "J", true},  {p->df.C, "C", true},
+             {p->h, "h", true},        {p->gamma1, "gamma1", pl.na > 0}, {F, "F", true}};
+  for (const auto &c : chk)
+    if (c.need && (!c.ptr || !aligned8(c.ptr)))
+      return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", c.name);
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!workspace) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  dsrg::FockInputs in{p->df.ao3, p->df.J, p->df.C, p->h, p->gamma1};
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_df_fock(pl, in, F, workspace, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
 const char *dsrg_df_last_error(void) { return g_err; }
 
 int dsrg_df_kernel_times(double *ms, const char **names, int cap) {

@@ -50,6 +50,9 @@ struct GemmGArgs {
   // which adds (n / nin) * fb to its B offset and (n / nin) * fc to its C offset
   int64_t nin, fb, fc;
   int colfast;   // tile walk: column tiles fastest (A the larger operand)
+  // split K (ktotal > 0): batch z contracts k in [z K, min((z + 1) K, ktotal)),
+  // its operands advanced by the batch strides
+  int64_t ktotal;
 };
 
 template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1, int MINW_ = 1>
@@ -63,7 +66,7 @@ struct GTile {
   static constexpr int JA = TM * KC / NT, JB = TN * KC / NT;
   static_assert(WM % 16 == 0 && WN % 16 == 0 && KC % 4 == 0, "whole fragments");
   static_assert(TM * KC % NT == 0 && TN * KC % NT == 0, "chunk split evenly");
-  static_assert(TM >= 32 && TN >= 32, "half swap needs rows of at least 32");
+  static_assert(TM % 16 == 0 && TN % 16 == 0, "whole 16-row fragments");
   static_assert(KC % (4 * KS) == 0, "k groups split evenly over the waves");
   static_assert((KS - 1) * 64 * FP * FQ * 4 <= 2 * TM * KP, "reduction fits the A stage");
 };
@@ -71,8 +74,14 @@ using GBig = GTile<128, 128, 2, 4, 32>;
 using GMid = GTile<64, 64, 2, 2, 32>;
 using GThin = GTile<32, 128, 1, 4, 16>;
 using GSplit = GTile<32, 32, 1, 1, 64, 4>;
+using GThin48 = GTile<48, 128, 1, 4, 16>;   // folded products of 33..48 rows
+using GThin64 = GTile<64, 128, 1, 4, 16>;   // folded products of 49..64 rows
 
-__device__ __forceinline__ int gswz(int k) { return (k & 1) << 4; }
+// half swap of the k-major layout: odd k rows exchange their 16-element
+// halves within each group of 32; rows of R not a multiple of 32 are stored
+// plainly
+template <int R>
+__device__ __forceinline__ int gswz(int k) { return (R % 32 == 0) ? ((k & 1) << 4) : 0; }
 
 // element j of thread t's share of an R x KC operand chunk: (row, k) and the
 // LDS index; KFAST: the operand is contiguous in k
@@ -86,13 +95,13 @@ __device__ __forceinline__ void chunk_slot(int t, int j, int &row, int &k, int &
   } else {
     k = e / R;
     row = e % R;
-    lidx = k * R + (row ^ gswz(k));
+    lidx = k * R + (row ^ gswz<R>(k));
   }
 }
 
 template <bool KFAST, int R, int KC>
 __device__ __forceinline__ double frag(const double *L, int row, int k) {
-  return KFAST ? L[row * (KC + 2) + k] : L[k * R + (row ^ gswz(k))];
+  return KFAST ? L[row * (KC + 2) + k] : L[k * R + (row ^ gswz<R>(k))];
 }
 
 // pair j (two neighbours along the contiguous index) of thread t's share of
@@ -107,7 +116,7 @@ __device__ __forceinline__ void pair_slot(int t, int j, int &row, int &k, int &l
   } else {
     k = e / (R / 2);
     row = 2 * (e % (R / 2));
-    lidx = k * R + (row ^ gswz(k));
+    lidx = k * R + (row ^ gswz<R>(k));
   }
 }
 
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(G::NT, G::MINW) void gemm_g_kernel(const double *__
                                                       double *__restrict__ C) {
   static_assert(!FOLD || (!TB && G::NT % G::TN == 0), "folded B: n-contiguous, one column per thread");
   static_assert(!(FOLD && PAIR), "folded products read single elements");
-  static_assert(G::JA % 2 == 0 && G::JB % 2 == 0, "whole pairs per thread");
+  static_assert(!PAIR || (G::JA % 2 == 0 && G::JB % 2 == 0), "whole pairs per thread");
   constexpr bool AK = !TA, BK = TB;   // operands contiguous in k
   constexpr int TM = G::TM, TN = G::TN, NT = G::NT, KC = G::KC;
   __shared__ __align__(16) double sA[2][TM * G::KP];
@@ -139,7 +148,8 @@ __global__ __launch_bounds__(G::NT, G::MINW) void gemm_g_kernel(const double *__
   A += (int64_t)blockIdx.z * a.sa;
   B += (int64_t)blockIdx.z * a.sb;
   C += (int64_t)blockIdx.z * a.sc;
-  const int64_t K = a.ktri ? std::min(a.K, m0 + TM) : a.K;
+  const int64_t Kb = a.ktotal > 0 ? std::min(a.K, a.ktotal - (int64_t)blockIdx.z * a.K) : a.K;
+  const int64_t K = a.ktri ? std::min(Kb, m0 + TM) : Kb;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int ks = wave / (G::WR * G::WC), wrc = wave % (G::WR * G::WC);
@@ -344,7 +354,8 @@ static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
                          int64_t sb, double beta, double *C, int64_t ldc, int64_t sc,
                          int64_t batch, bool ktri, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
-  GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0, 0, 0, 0, M > N ? 1 : 0};
+  GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0, 0, 0, 0, M > N ? 1 : 0,
+              0};
   auto tiles = [&](int tm, int tn) { return ceil_div(M, tm) * ceil_div(N, tn) * batch; };
   if (M <= GThin::TM && tiles(GThin::TM, GThin::TN) >= 256)
     gemm_g_launch<GThin>(ta, tb, a, batch, A, B, C, st);
@@ -357,13 +368,73 @@ static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
   return hipGetLastError();
 }
 
+// C = sum_{s < nseg} P[s] with P[s] = op(A) op(B) over the s-th of nseg
+// contiguous ranges of K (one launch, the segments as its batch index; the
+// partial products land in part[nseg][M][N]); then C = alpha sum_s P[s] +
+// beta C, the segments added in order. For products whose output is too small
+// to fill the chip on its own.
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double *__restrict__ part,
+                                                        int64_t nseg, int64_t n, double alpha,
+                                                        double beta, double *__restrict__ C) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    double v = 0.0;
+    for (int64_t s = 0; s < nseg; ++s) v += part[s * n + e];
+    C[e] = alpha * v + (beta != 0.0 ? beta * C[e] : 0.0);
+  }
+}
+
+static hipError_t gemm_g_splitk(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                                const double *A, int64_t lda, const double *B, int64_t ldb,
+                                double beta, double *C, double *part, int64_t nseg,
+                                hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  nseg = std::max<int64_t>(1, std::min(nseg, K));
+  const int64_t kseg = ceil_div(K, nseg);
+  nseg = ceil_div(K, kseg);
+  GemmGArgs a{M, N, kseg, lda, ldb, N, (ta ? kseg * lda : kseg), (tb ? kseg : kseg * ldb), M * N,
+              1.0, 0.0, 0, 0, 0, 0, M > N ? 1 : 0, K};
+  auto tiles = [&](int tm, int tn) { return ceil_div(M, tm) * ceil_div(N, tn) * nseg; };
+  if (tiles(GBig::TM, GBig::TN) >= 768)
+    gemm_g_launch<GBig>(ta, tb, a, nseg, A, B, part, st);
+  else if (tiles(GMid::TM, GMid::TN) >= 256)
+    gemm_g_launch<GMid>(ta, tb, a, nseg, A, B, part, st);
+  else
+    gemm_g_launch<GSplit>(ta, tb, a, nseg, A, B, part, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(M * N, 256), 4096)),
+                     dim3(256), 0, st, part, nseg, M * N, alpha, beta, C);
+  return hipGetLastError();
+}
+
+// segments of a long contraction with a small output: enough 64 x 64 tiles
+// for about eight per CU, each segment at least 1024 long, at most
+// kMaxSegments (the partial buffer holds that many products)
+constexpr int64_t kMaxSegments = 32;
+static int64_t splitk_segments(int64_t M, int64_t N, int64_t K) {
+  const int64_t t = ceil_div(M, 64) * ceil_div(N, 64);
+  return std::max<int64_t>(1, std::min({ceil_div(2048, t), K / 1024, kMaxSegments}));
+}
+
 // C = alpha op(A) B over a batch folded into the columns: B[b] (ldb, batch
 // stride sb) holds columns [b nin, (b + 1) nin) and C[b] (ldc, stride sc)
 // takes them; at most 32 rows, so the 32 x 128 tile runs over nbatch * nin
-// columns with no per-batch ragged tile; folded_fits says whether a product
-// has that form.
+// columns with no per-batch ragged tile (32, 48 or 64 rows per tile, the
+// smallest that holds M); folded_fits says whether a product has that form.
 static bool folded_fits(int64_t M, int64_t nin, int64_t nbatch) {
-  return M <= GThin::TM && ceil_div(nin * nbatch, GThin::TN) <= 65535;
+  return M <= GThin64::TM && ceil_div(nin * nbatch, GThin::TN) <= 65535;
+}
+
+template <class G>
+static void folded_launch(bool ta, const GemmGArgs &a, const double *A, const double *B,
+                          double *C, hipStream_t st) {
+  const dim3 grid(1, (unsigned)ceil_div(a.N, G::TN), 1);
+  if (ta)
+    hipLaunchKernelGGL((gemm_g_kernel<true, false, G, true>), grid, dim3(G::NT), 0, st, A, B, a,
+                       C);
+  else
+    hipLaunchKernelGGL((gemm_g_kernel<false, false, G, true>), grid, dim3(G::NT), 0, st, A, B, a,
+                       C);
 }
 
 static hipError_t gemm_g_folded(bool ta, int64_t M, int64_t nin, int64_t K, double alpha,
@@ -373,14 +444,13 @@ static hipError_t gemm_g_folded(bool ta, int64_t M, int64_t nin, int64_t K, doub
   const int64_t N = nin * nbatch;
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!folded_fits(M, nin, nbatch)) return hipErrorInvalidValue;
-  GemmGArgs a{M, N, K, lda, ldb, ldc, 0, 0, 0, alpha, 0.0, 0, nin, sb - nin, sc - nin, 0};
-  const dim3 grid(1, (unsigned)ceil_div(N, GThin::TN), 1);
-  if (ta)
-    hipLaunchKernelGGL((gemm_g_kernel<true, false, GThin, true>), grid, dim3(GThin::NT), 0, st, A,
-                       B, a, C);
+  GemmGArgs a{M, N, K, lda, ldb, ldc, 0, 0, 0, alpha, 0.0, 0, nin, sb - nin, sc - nin, 0, 0};
+  if (M <= GThin::TM)
+    folded_launch<GThin>(ta, a, A, B, C, st);
+  else if (M <= GThin48::TM)
+    folded_launch<GThin48>(ta, a, A, B, C, st);
   else
-    hipLaunchKernelGGL((gemm_g_kernel<false, false, GThin, true>), grid, dim3(GThin::NT), 0, st,
-                       A, B, a, C);
+    folded_launch<GThin64>(ta, a, A, B, C, st);
   return hipGetLastError();
 }
 
@@ -595,6 +665,137 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
   hipLaunchKernelGGL(df_scatter_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 65536)),
                      dim3(256), 0, st, Bf, sa, o.B_cv, o.B_ca, o.B_av, o.B_aa);
   timer_end(st);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Generalized Fock matrix (Eq. gen_fock) from the DF integrals. With o the
+// frozen + core + active orbitals, B^Q_mq (m in o, q all) the DF factors of
+// (m q|P) (as in the factor build, L^{-1} of the metric applied) and the MO
+// density D (2 on the frozen + core diagonal, Gamma on the active block):
+//   Coulomb:  d^Q = sum_rs D_rs B^Q_rs, c = X^T d (X = L^{-1}),
+//             J_AO = sum_P c_P (mu nu|P), J_MO = C^T J_AO C
+//   exchange: K/2 = sum_{Q, m} B^Q_mp Bh^Q_mq with Bh^Q_iq = B^Q_iq for the
+//             doubly occupied i and Bh^Q_uq = (1/2) sum_v Gamma_uv B^Q_vq
+//   F = h + J_MO - K/2
+// The first transform contracts the occupied index on the left of (mu nu|P),
+// so (m q|P) = (q m|P) rests on the symmetry of the AO integrals in mu, nu.
+// ---------------------------------------------------------------------------
+
+// d^Q = 2 sum_{i < nd} B^Q_ii + sum_{uv} Gamma_uv B^Q_{nd+u, nd+v}, one thread per Q
+__global__ __launch_bounds__(256) void fock_density_kernel(const double *__restrict__ Bo,
+                                                           const double *__restrict__ gamma1,
+                                                           int64_t naux, int64_t no, int64_t nmo,
+                                                           int64_t nd, int64_t na,
+                                                           double *__restrict__ d) {
+  for (int64_t Q = (int64_t)blockIdx.x * 256 + threadIdx.x; Q < naux;
+       Q += (int64_t)gridDim.x * 256) {
+    const double *b = Bo + Q * no * nmo;
+    double s = 0.0;
+    for (int64_t i = 0; i < nd; ++i) s += 2.0 * b[i * nmo + i];
+    for (int64_t u = 0; u < na; ++u)
+      for (int64_t v = 0; v < na; ++v) s += gamma1[u * na + v] * b[(nd + u) * nmo + nd + v];
+    d[Q] = s;
+  }
+}
+
+// Bh^Q_mq: B^Q_mq for m < nd, (1/2) sum_v Gamma_{m-nd, v} B^Q_{nd+v, q} for the
+// active rows; one thread per element
+__global__ __launch_bounds__(256) void fock_exchange_rhs_kernel(const double *__restrict__ Bo,
+                                                                const double *__restrict__ gamma1,
+                                                                int64_t naux, int64_t no,
+                                                                int64_t nmo, int64_t nd,
+                                                                int64_t na,
+                                                                double *__restrict__ Bh) {
+  const int64_t total = naux * no * nmo;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t q = e % nmo, m = (e / nmo) % no, Q = e / (no * nmo);
+    double v;
+    if (m < nd) {
+      v = Bo[e];
+    } else {
+      const double *b = Bo + (Q * no + nd) * nmo + q;
+      const double *g = gamma1 + (m - nd) * na;
+      v = 0.0;
+      for (int64_t w = 0; w < na; ++w) v += g[w] * b[w * nmo];
+      v *= 0.5;
+    }
+    Bh[e] = v;
+  }
+}
+
+hipError_t launch_df_fock(const FockPlan &pl, const FockInputs &in, double *F, void *ws,
+                          hipStream_t st) {
+  hipError_t e;
+  const int64_t nao = pl.nao, nmo = pl.nmo, naux = pl.naux, no = pl.no, nd = pl.nd, na = pl.na;
+  double *T = ws_d(ws, pl.off_t), *Y = ws_d(ws, pl.off_y), *Lm = ws_d(ws, pl.off_l);
+  double *X = ws_d(ws, pl.off_x), *W = ws_d(ws, pl.off_w), *Bo = ws_d(ws, pl.off_bo);
+  double *dv = ws_d(ws, pl.off_d), *cv = ws_d(ws, pl.off_c), *Jao = ws_d(ws, pl.off_jao);
+  double *Tj = ws_d(ws, pl.off_tj), *Part = ws_d(ws, pl.off_part);
+  // T[P][m][nu] = sum_mu C[mu][m] (mu nu|P), m occupied
+  timer_begin("fock_half1", st);
+  if (folded_fits(no, nao, naux))
+    e = gemm_g_folded(true, no, nao, nao, 1.0, in.C, nmo, in.ao3, nao, nao * nao, T, nao,
+                      no * nao, naux, st);
+  else
+    e = gemm_g(true, false, no, nao, nao, 1.0, in.C, nmo, 0, in.ao3, nao, nao * nao, 0.0, T, nao,
+               no * nao, naux, false, st);
+  timer_end(st);
+  if (e != hipSuccess) return e;
+  // Y[(P m)][q] = sum_nu T[(P m)][nu] C[nu][q], q over all MOs
+  timer_begin("fock_half2", st);
+  e = gemm_g(false, false, naux * no, nmo, nao, 1.0, T, nao, 0, in.C, nmo, 0, 0.0, Y, nmo, 0, 1,
+             false, st);
+  timer_end(st);
+  if (e != hipSuccess) return e;
+  timer_begin("fock_metric", st);
+  if ((e = hipMemcpyAsync(Lm, in.J, sizeof(double) * naux * naux, hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_zero_fill(X, naux * naux, st)) != hipSuccess) return e;
+  if ((e = chol_inv(Lm, X, W, naux, 0, naux, st)) != hipSuccess) return e;
+  timer_end(st);
+  // B[Q][(m q)] = sum_{P <= Q} X[Q][P] Y[P][(m q)]
+  timer_begin("fock_metric_apply", st);
+  e = gemm_g(false, false, naux, no * nmo, naux, 1.0, X, naux, 0, Y, no * nmo, 0, 0.0, Bo,
+             no * nmo, 0, 1, true, st);
+  timer_end(st);
+  if (e != hipSuccess) return e;
+  // Coulomb part, through the AO basis
+  timer_begin("fock_coulomb", st);
+  hipLaunchKernelGGL(fock_density_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(naux, 256), 1024)),
+                     dim3(256), 0, st, Bo, in.gamma1, naux, no, nmo, nd, na, dv);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = gemm_g(true, false, naux, 1, naux, 1.0, X, naux, 0, dv, 1, 0, 0.0, cv, 1, 0, 1, false,
+                  st)) != hipSuccess)
+    return e;
+  if ((e = gemm_g(false, false, 1, nao * nao, naux, 1.0, cv, naux, 0, in.ao3, nao * nao, 0, 0.0,
+                  Jao, nao * nao, 0, 1, false, st)) != hipSuccess)
+    return e;
+  if ((e = gemm_g(false, false, nao, nmo, nao, 1.0, Jao, nao, 0, in.C, nmo, 0, 0.0, Tj, nmo, 0, 1,
+                  false, st)) != hipSuccess)
+    return e;
+  // F = h, then F += C^T (J_AO C)
+  if ((e = hipMemcpyAsync(F, in.h, sizeof(double) * nmo * nmo, hipMemcpyDeviceToDevice, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = gemm_g(true, false, nmo, nmo, nao, 1.0, in.C, nmo, 0, Tj, nmo, 0, 1.0, F, nmo, 0, 1,
+                  false, st)) != hipSuccess)
+    return e;
+  timer_end(st);
+  // exchange part: F -= sum_{(Q m)} B[(Q m)][p] Bh[(Q m)][q]
+  timer_begin("fock_exchange", st);
+  double *Bh = Y;   // Y is no longer needed
+  const int64_t total = naux * no * nmo;
+  hipLaunchKernelGGL(fock_exchange_rhs_kernel,
+                     dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 65536)), dim3(256), 0,
+                     st, Bo, in.gamma1, naux, no, nmo, nd, na, Bh);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = gemm_g_splitk(true, false, nmo, nmo, naux * no, -1.0, Bo, nmo, Bh, nmo, 1.0, F, Part,
+                    splitk_segments(nmo, nmo, naux * no), st);
+  timer_end(st);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -165,6 +165,18 @@ hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const
 // ---- density-fitting factors (dfgen.hip) ----
 hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutputs &o, void *ws,
                              hipStream_t st);
+// ---- generalized Fock matrix (dfgen.hip) ----
+struct FockPlan {
+  int64_t nao, nmo, naux, nfrz, nc, na, nv;
+  int64_t no, nd;   // occupied (frozen + core + active), doubly occupied (frozen + core)
+  size_t off_t, off_y, off_l, off_x, off_w, off_bo, off_d, off_c, off_jao, off_tj, off_part;
+  size_t total;
+};
+struct FockInputs {
+  const double *ao3, *J, *C, *h, *gamma1;
+};
+hipError_t launch_df_fock(const FockPlan &pl, const FockInputs &in, double *F, void *ws,
+                          hipStream_t st);
 // ---- F4-F8 (active_terms.hip) ----
 hipError_t launch_active_terms(const ActivePlan &pl, const ActiveInputs &in, void *ws,
                                double *F, hipStream_t st);

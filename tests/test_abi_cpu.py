@@ -218,3 +218,36 @@ def test_df_factors_entry_point_validation(lib):
     assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG
     assert call(prob(), nb=16) == b.DSRG_ERR_WORKSPACE
     assert call(prob(), ws=0x40008) == b.DSRG_ERR_WORKSPACE
+
+
+def test_fock_entry_point_validation(lib):
+    """Generalized-Fock entry point: workspace sizing and host-side rejection
+    (no device work is launched: every call fails before the first launch)."""
+    def prob(h=0x10000, g1=0x10000, **kw):
+        d = dict(nao=40, nmo=40, naux=30, nfrz=2, nc=5, na=3, nv=30)
+        d.update(kw)
+        a = 0x10000
+        return b.FockProblem(b.DFGenProblem(d["nao"], d["nmo"], d["naux"], d["nfrz"], d["nc"],
+                                            d["na"], d["nv"], a, a, a), h, g1)
+
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_fock_workspace_size(ctypes.byref(prob()), ctypes.byref(out)) == 0
+    # at least the occupied-row integrals and factors, (10 occupied) x 40 MOs
+    # per auxiliary function, three of them, and three naux x naux metrics
+    assert out.value >= 8 * (3 * 30 * 10 * 40 + 3 * 30 * 30)
+    assert lib.dsrg_df_fock_workspace_size(None, ctypes.byref(out)) == b.DSRG_ERR_ARG
+
+    def call(p, F=0x20000, opts=0, ws=0x40000, nb=1 << 40):
+        return lib.dsrg_df_fock(ctypes.byref(p), opts, ctypes.c_void_p(F) if F else None,
+                                ctypes.c_void_p(ws) if ws else None, nb, None)
+
+    for kw in (dict(nao=0), dict(naux=0), dict(nc=0), dict(nv=0), dict(na=-1), dict(nmo=39)):
+        assert call(prob(**kw)) == b.DSRG_ERR_ARG, kw
+        assert lib.dsrg_df_last_error().decode()
+    assert call(prob(h=0)) == b.DSRG_ERR_ARG
+    assert call(prob(g1=0)) == b.DSRG_ERR_ARG            # na > 0 needs gamma1
+    assert call(prob(g1=0x10004)) == b.DSRG_ERR_ARG      # misaligned
+    assert call(prob(), F=0) == b.DSRG_ERR_ARG
+    assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG
+    assert call(prob(), nb=16) == b.DSRG_ERR_WORKSPACE
+    assert call(prob(), ws=0x40008) == b.DSRG_ERR_WORKSPACE
