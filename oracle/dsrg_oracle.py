@@ -48,7 +48,8 @@ x, y, u, v, w, z active, the same spin summation gives
 Upstream of the energies: ``df_factors`` builds the blocks of B from AO
 three-index integrals, the metric and the MO coefficients, and
 ``generalized_fock`` the generalized Fock matrix of Eq. gen_fock over all
-orbitals from the same DF integrals (both pinned in the test-suite).
+orbitals from the same DF integrals, and ``semicanonicalize`` the rotation to
+semicanonical orbitals (all pinned in the test-suite).
 
 Regularisers use libm ``expm1``; every sum over many elements is a
 ``math.fsum``. Gradients are written out from the same formulas by the chain
@@ -588,6 +589,28 @@ def generalized_fock(ao3, J, C, h, gamma1, nfrz, nc, na) -> np.ndarray:
     Jm = np.einsum("Ppq,P->pq", Y, d)
     Km = np.einsum("Ppr,rs,Pqs->pq", Yo, D, So, optimize=True)
     return h + Jm - 0.5 * Km
+
+
+def semicanonicalize(F, nfrz, nc, na, nv) -> Tuple[np.ndarray, np.ndarray]:
+    """Semicanonical orbitals (section II.B): the rotation U that diagonalizes
+    the core, active and virtual diagonal blocks of the generalized Fock matrix
+    F, and the orbital energies eps = diag(U^T F U). Frozen core orbitals are
+    left as they are (U = I there, eps = their diagonal of F). Within each
+    block the eigenvalues ascend and every eigenvector has its component of
+    largest magnitude positive. Returns (eps [nmo], U [nmo][nmo])."""
+    nmo = F.shape[0]
+    U = np.eye(nmo)
+    eps = np.diag(F).copy()
+    o = nfrz
+    for n in (nc, na, nv):
+        if n > 0:
+            w, V = np.linalg.eigh(F[o:o + n, o:o + n])
+            k = np.argmax(np.abs(V), axis=0)
+            V = V * np.sign(V[k, np.arange(n)])[None, :]
+            U[o:o + n, o:o + n] = V
+            eps[o:o + n] = w
+        o += n
+    return eps, U
 
 
 def pivoted_cholesky(M: np.ndarray, tol: float = 0.0) -> np.ndarray:

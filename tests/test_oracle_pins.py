@@ -471,3 +471,46 @@ def test_fock_active_limits_and_invariances():
     q = copy.deepcopy(g)
     q.J = 2.5 * g.J
     assert np.allclose(F(q, q.nc, q.na, g.gamma1) - g.h, (f - g.h) / 2.5, atol=1e-12)
+
+
+# --- semicanonical orbitals (section II.B) -------------------------------------
+@pytest.mark.parametrize("shape", [(0, 3, 2, 5), (2, 4, 0, 7), (1, 1, 1, 1), (3, 6, 4, 40)])
+def test_semicanonical_rotation_satisfies_its_definition(shape):
+    # U orthogonal and block-diagonal over frozen | core | active | virtual;
+    # U^T F U diagonal within the core, active and virtual blocks with eps on
+    # its diagonal (F U = U diag(eps) there); the frozen block untouched; traces
+    # kept; eigenvalues ascending per block; sign convention
+    nfrz, nc, na, nv = shape
+    nmo = sum(shape)
+    rng = np.random.default_rng(nmo)
+    G = rng.standard_normal((nmo, nmo))
+    F = np.diag(rng.uniform(-3, 3, nmo)) + 0.3 * (G + G.T)
+    eps, U = O.semicanonicalize(F, nfrz, nc, na, nv)
+    assert np.allclose(U.T @ U, np.eye(nmo), atol=1e-13)
+    Fs = U.T @ F @ U
+    o = 0
+    for n, rotated in ((nfrz, False), (nc, True), (na, True), (nv, True)):
+        blk = slice(o, o + n)
+        assert np.allclose(U[blk, :o], 0) and np.allclose(U[blk, o + n:], 0)
+        if rotated and n:
+            assert np.allclose(Fs[blk, blk], np.diag(eps[blk]), atol=1e-12)
+            assert np.allclose(F[blk, blk] @ U[blk, blk], U[blk, blk] * eps[blk][None, :],
+                               atol=1e-12)
+            assert np.all(np.diff(eps[blk]) >= 0)
+            assert math.isclose(eps[blk].sum(), np.trace(F[blk, blk]), rel_tol=0, abs_tol=1e-12)
+            V = U[blk, blk]
+            k = np.argmax(np.abs(V), axis=0)
+            assert np.all(V[k, np.arange(n)] > 0)
+        elif n:
+            assert np.array_equal(U[blk, blk], np.eye(n))
+            assert np.array_equal(eps[blk], np.diag(F)[blk])
+        o += n
+
+
+def test_semicanonical_of_diagonal_blocks_is_a_sort():
+    # already diagonal blocks: U permutes each block into ascending order
+    F = np.diag([5.0, -1.0, 3.0, 0.5, 2.0, -4.0, 7.0])
+    F[0, 3] = F[3, 0] = 9.0      # coupling between blocks is not touched
+    eps, U = O.semicanonicalize(F, 0, 3, 1, 3)
+    assert np.array_equal(eps, [-1.0, 3.0, 5.0, 0.5, -4.0, 2.0, 7.0])
+    assert np.array_equal(np.abs(U[:3, :3]), [[0, 0, 1], [1, 0, 0], [0, 1, 0]])
