@@ -6,7 +6,7 @@ reduction) on seeded synthetic inputs already resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
                     [--precision fp64] [--no-cpu-baseline]
-                    [--grad | --active | --dfgen | --fock]
+                    [--grad | --active | --dfgen | --fock | --semican]
 
 With --active a step is one dsrg_df_energy_active call instead (the pieces
 F4-F8 of term F, FP64), measured the same way against its own algorithmic
@@ -14,7 +14,8 @@ work (the contractions over Q that form its integrals). With --dfgen a step
 is one dsrg_df_factors call (the density-fitting factors B from AO
 three-index integrals, FP64) for the config's orbital spaces; with --fock one
 dsrg_df_fock call (the generalized Fock matrix of Eq. gen_fock from the same
-DF integrals, FP64).
+DF integrals, FP64); with --semican one dsrg_df_semicanonicalize call (the
+semicanonical rotation of that Fock matrix and C U, FP64).
 
 Prints one JSON line. `value` is algorithmic TFLOP/s of the whole step:
 F_alg = 2 naux [nc(nc+1)/2 nv^2 + nc na nv^2 + nc^2 na nv] (the contractions
@@ -155,9 +156,10 @@ def fock_alg_work(nao, naux, nfrz, nc, na, nv):
     return sum(f.values()), f, b
 
 
-def cpu_baseline_fock(g, budget_s=20.0):
+def cpu_baseline_fock(g, budget_s=20.0, F_gpu=None):
     """The oracle's generalized Fock build on the whole workload (a few
-    seconds at the configs' sizes; the budget is not needed)."""
+    seconds at the configs' sizes; the budget is not needed), and the largest
+    deviation of the device's F from it relative to max |F|."""
     from oracle import dsrg_oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -165,19 +167,55 @@ def cpu_baseline_fock(g, budget_s=20.0):
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
     t = time.perf_counter()
-    O.generalized_fock(g.ao3, g.J, g.C, g.h, g.gamma1, g.nfrz, g.nc, g.na)
+    ref = O.generalized_fock(g.ao3, g.J, g.C, g.h, g.gamma1, g.nfrz, g.nc, g.na)
     dt = time.perf_counter() - t
     F, _, _ = fock_alg_work(g.nao, g.naux, g.nfrz, g.nc, g.na, g.nv)
-    return {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "seconds": round(dt, 3),
-            "sample": f"the whole generalized Fock build (naux={g.naux}, nmo={g.C.shape[1]}; "
-                      "FP64 numpy/BLAS oracle, same inputs)"}
+    out = {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+           "seconds": round(dt, 3),
+           "sample": f"the whole generalized Fock build (naux={g.naux}, nmo={g.C.shape[1]}; "
+                     "FP64 numpy/BLAS oracle, same inputs)"}
+    if F_gpu is not None:
+        out["rel_err_vs_oracle"] = float(np.abs(F_gpu - ref).max() / np.abs(ref).max())
+    return out
 
 
-def cpu_baseline_dfgen(g, budget_s=20.0):
+def semican_alg_work(nao, nfrz, nc, na, nv):
+    """Conventional work of the semicanonical rotation: 9 n^3 per symmetric
+    eigen-decomposition with eigenvectors (the usual count for reduction to
+    tridiagonal form, the eigenvector iteration and the back-transformation;
+    Jacobi does not have a fixed count of its own) for the core, active and
+    virtual blocks, and 2 nao nmo^2 for C U."""
+    nmo = nfrz + nc + na + nv
+    return 9.0 * (nc ** 3 + na ** 3 + nv ** 3) + 2.0 * nao * nmo * nmo
+
+
+def cpu_baseline_semican(F, shape, nao, eps_gpu=None, U_gpu=None):
+    """The oracle's semicanonical rotation (numpy eigen-decompositions) of the
+    same Fock matrix, and the device's largest deviations from it."""
+    from oracle import dsrg_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    t = time.perf_counter()
+    e_ref, U_ref = O.semicanonicalize(F, *shape)
+    dt = time.perf_counter() - t
+    out = {"value": semican_alg_work(nao, *shape) / dt / 1e12, "unit": "TFLOP/s",
+           "cores": int(cores), "kind": "oracle", "seconds": round(dt, 4),
+           "sample": "the whole rotation without C U (FP64 numpy/LAPACK oracle, same F)"}
+    if eps_gpu is not None:
+        out["eps_err_rel"] = float(np.abs(eps_gpu - e_ref).max() / np.abs(F).max())
+        out["U_err"] = float(np.abs(U_gpu - U_ref).max())
+    return out
+
+
+def cpu_baseline_dfgen(g, budget_s=20.0, f_gpu=None):
     """The oracle's factor build on the first naux_s auxiliary functions,
     naux_s sized to the budget from a probe (the work is linear in naux for
-    the transform, which dominates)."""
+    the transform, which dominates); when the sample is the whole problem, the
+    largest deviation of the device's factors from it, relative to each
+    block's max |B|."""
     from oracle import dsrg_oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -190,13 +228,17 @@ def cpu_baseline_dfgen(g, budget_s=20.0):
     t0 = max(time.perf_counter() - t, 1e-6)
     ns = int(min(g.naux, max(n0, n0 * budget_s / t0)))
     t = time.perf_counter()
-    O.df_factors(g.ao3[:ns], g.J[:ns, :ns], g.C, g.nfrz, g.nc, g.na, g.nv)
+    ref = O.df_factors(g.ao3[:ns], g.J[:ns, :ns], g.C, g.nfrz, g.nc, g.na, g.nv)
     dt = time.perf_counter() - t
     F, _ = dfgen_alg_flops(g.nao, ns, g.nc, g.na, g.nv)
-    return {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "seconds": round(dt, 3),
-            "sample": f"DF factor build over the first {ns}/{g.naux} auxiliary functions "
-                      "(FP64 numpy/BLAS oracle, same inputs)"}
+    out = {"value": F / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+           "seconds": round(dt, 3),
+           "sample": f"DF factor build over the first {ns}/{g.naux} auxiliary functions "
+                     "(FP64 numpy/BLAS oracle, same inputs)"}
+    if f_gpu is not None and ns == g.naux:
+        out["rel_err_vs_oracle"] = {k: float(np.abs(f_gpu[k] - ref[k]).max() / np.abs(ref[k]).max())
+                                    for k in ref if ref[k].size}
+    return out
 
 
 def cpu_baseline(p, budget_s=20.0):
@@ -289,6 +331,9 @@ def main():
     ap.add_argument("--fock", action="store_true",
                     help="time the generalized Fock build (dsrg_df_fock, FP64) for the orbital "
                          "spaces of the config with 10 frozen core orbitals")
+    ap.add_argument("--semican", action="store_true",
+                    help="time the semicanonical rotation (dsrg_df_semicanonicalize, FP64) of the "
+                         "generalized Fock matrix of the --fock workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
                          "hardware byte counters can be scaled")
@@ -316,6 +361,8 @@ def main():
         return bench_dfgen(args, binding, torch)
     if args.fock:
         return bench_fock(args, binding, torch)
+    if args.semican:
+        return bench_semican(args, binding, torch)
     p = make_config(args.config)
     if args.active:
         return bench_active(args, p, binding, torch)
@@ -487,7 +534,6 @@ def bench_active(args, p, binding, torch):
 def bench_dfgen(args, binding, torch):
     """--dfgen: one step = one dsrg_df_factors call (FP64)."""
     from paper_1603_00561_amd.workloads import CONFIGS, make_dfgen_problem
-    from oracle import dsrg_oracle as O
     if args.precision != "fp64" or args.grad or args.active:
         print("bench.py: --dfgen runs the FP64 factor build only", file=sys.stderr)
         sys.exit(2)
@@ -519,9 +565,6 @@ def bench_dfgen(args, binding, torch):
     roof = stage_roofline(avg, {"df_half1": (Fparts["half1"], Bparts["half1"]),
                                 "df_half2": (Fparts["half2"], Bparts["half2"]),
                                 "df_metric_apply": (Fparts["apply"], Bparts["apply"])})
-    ref = O.df_factors(g.ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv)
-    err = {k: float(np.abs(f[k].cpu().numpy() - ref[k]).max() / np.abs(ref[k]).max())
-           for k in ref if ref[k].size}
     out = {
         "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
         "value": Ftot / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
@@ -532,11 +575,13 @@ def bench_dfgen(args, binding, torch):
                                f"nv={g.nv} nao={g.nao} naux={g.naux}, density-fitting factors",
                    "precision": "fp64", "parallelism": "single-gpu"},
         "kernel_ms": avg,
-        "rel_err_vs_oracle": err,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_dfgen(g, args.cpu_budget)
+        cb = cpu_baseline_dfgen(g, args.cpu_budget, {k: v.cpu().numpy() for k, v in f.items()})
+        if "rel_err_vs_oracle" in cb:
+            out["rel_err_vs_oracle"] = cb.pop("rel_err_vs_oracle")
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 
@@ -544,7 +589,6 @@ def bench_dfgen(args, binding, torch):
 def bench_fock(args, binding, torch):
     """--fock: one step = one dsrg_df_fock call (FP64)."""
     from paper_1603_00561_amd.workloads import CONFIGS, make_fock_problem
-    from oracle import dsrg_oracle as O
     if args.precision != "fp64" or args.grad or args.active:
         print("bench.py: --fock runs the FP64 Fock build only", file=sys.stderr)
         sys.exit(2)
@@ -578,8 +622,6 @@ def bench_fock(args, binding, torch):
     roof = stage_roofline(avg, {"fock_half1": (Fp["half1"], Bp["half1"]),
                                 "fock_half2": (Fp["half2"], Bp["half2"]),
                                 "fock_metric_apply": (Fp["apply"], Bp["apply"])})
-    ref = O.generalized_fock(g.ao3, g.J, g.C, g.h, g.gamma1, g.nfrz, g.nc, g.na)
-    err = float(np.abs(F.cpu().numpy() - ref).max() / np.abs(ref).max())
     out = {
         "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
         "value": Ftot / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
@@ -590,11 +632,74 @@ def bench_fock(args, binding, torch):
                                f"nv={g.nv} nao={g.nao} naux={g.naux}, generalized Fock matrix",
                    "precision": "fp64", "parallelism": "single-gpu"},
         "kernel_ms": avg,
-        "rel_err_vs_oracle": err,
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline_fock(g, args.cpu_budget)
+        cb = cpu_baseline_fock(g, args.cpu_budget, F.cpu().numpy())
+        out["rel_err_vs_oracle"] = cb.pop("rel_err_vs_oracle")
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+
+def bench_semican(args, binding, torch):
+    """--semican: one step = one dsrg_df_semicanonicalize call (FP64) on the
+    generalized Fock matrix of the --fock workload, formed once on the GPU."""
+    from paper_1603_00561_amd.workloads import CONFIGS, make_fock_problem
+    if args.precision != "fp64" or args.grad or args.active:
+        print("bench.py: --semican runs the FP64 rotation only", file=sys.stderr)
+        sys.exit(2)
+    c = CONFIGS[args.config]
+    g = make_fock_problem(10, c["nc"], c["na"], c["nv"], c["naux"])
+    dev = torch.device("cuda:0")
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    F = binding.df_fock(d(g.ao3), d(g.J), d(g.C), d(g.h), d(g.gamma1) if g.na else None, g.nfrz,
+                        g.nc, g.na, g.nv)
+    F = 0.5 * (F + F.T).contiguous()
+    C = d(g.C)
+    shape = (g.nfrz, g.nc, g.na, g.nv)
+    nmo = g.C.shape[1]
+    for _ in range(args.warmup):
+        eps, U, Cs = binding.semicanonicalize(F, *shape, C=C)
+    torch.cuda.synchronize()
+    binding.kernel_times(1)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eps, U, Cs = binding.semicanonicalize(F, *shape, C=C, timing=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = binding.kernel_times(4096)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    per_kernel = {}
+    for name, ms in kt:
+        per_kernel.setdefault(name, []).append(ms)
+    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
+    work = semican_alg_work(g.nao, *shape)
+    dom = max(avg, key=avg.get)
+    roof = {"bound": "latency", "kernel": dom, "avg_launch_ms": avg[dom],
+            "note": "a chain of Jacobi rounds (three launches each); frac is the whole step's "
+                    "conventional work rate against the FP64 matrix-core peak",
+            "achieved": work / (ms_per_step * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp64"],
+            "unit": "TFLOP/s", "frac": work / (ms_per_step * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+            "traffic": None}
+    out = {
+        "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
+        "value": work / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "s_per_solve": ms_per_step * 1e-3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config} orbital spaces: nfrz={g.nfrz} nc={g.nc} na={g.na} "
+                               f"nv={g.nv} nao={g.nao}, semicanonical rotation of the generalized "
+                               "Fock matrix", "precision": "fp64", "parallelism": "single-gpu"},
+        "kernel_ms": avg,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline_semican(F.cpu().numpy(), shape, g.nao, eps.cpu().numpy(),
+                                  U.cpu().numpy())
+        out["eps_err_rel"] = cb.pop("eps_err_rel")
+        out["U_err"] = cb.pop("U_err")
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 

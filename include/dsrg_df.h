@@ -230,6 +230,32 @@ dsrg_status dsrg_df_fock_workspace_size(const dsrg_fock_problem *p, size_t *byte
 dsrg_status dsrg_df_fock(const dsrg_fock_problem *p, int options, double *F, void *workspace,
                          size_t ws_bytes, void *stream);
 
+/* ---- Semicanonical orbitals (section II.B): the orthogonal U that
+ * diagonalizes the core, active and virtual diagonal blocks of a generalized
+ * Fock matrix F, eps = diag(U^T F U), and optionally C U. U is block-diagonal
+ * over frozen | core | active | virtual, the identity on the frozen core (whose
+ * eps are the diagonal of F); within each block the eigenvalues ascend and
+ * each eigenvector has its component of largest magnitude positive. */
+typedef struct {
+  int64_t nao;              /* rows of C (ignored when C is NULL)               */
+  int64_t nmo;              /* order of F, >= nfrz + nc + na + nv               */
+  int64_t nfrz, nc, na, nv; /* frozen core, core, active, virtual orbitals      */
+  const double *F;          /* [nmo][nmo] symmetric generalized Fock matrix    */
+  const double *C;          /* [nao][nmo] MO coefficients, or NULL              */
+} dsrg_semican_problem;
+
+/* Bytes of device workspace that dsrg_df_semicanonicalize needs. */
+dsrg_status dsrg_df_semicanonicalize_workspace_size(const dsrg_semican_problem *p,
+                                                    size_t *bytes);
+
+/* U [nmo][nmo], eps [nmo] and, when C and Cs are both given, Cs = C U
+ * [nao][nmo] (device, FP64). Jacobi rotations to an off-diagonal norm below
+ * 1e-15 of the block's norm, or 15 sweeps at most (blocks of up to 64
+ * orbitals: 40 inner sweeps at most). Errors as for dsrg_df_energy. */
+dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options, double *U,
+                                     double *eps, double *Cs, void *workspace, size_t ws_bytes,
+                                     void *stream);
+
 /* Text of the last error raised on the calling thread ("" if none). Valid
  * until the next dsrg_df_* call on that thread. */
 const char *dsrg_df_last_error(void);

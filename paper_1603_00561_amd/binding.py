@@ -27,6 +27,7 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward
             "dsrg_df_active_workspace_size", "dsrg_df_energy_active",
             "dsrg_df_factors_workspace_size", "dsrg_df_factors",
             "dsrg_df_fock_workspace_size", "dsrg_df_fock",
+            "dsrg_df_semicanonicalize_workspace_size", "dsrg_df_semicanonicalize",
             "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_version")
 
 
@@ -58,6 +59,14 @@ class DFGenProblem(ctypes.Structure):
 
 class FockProblem(ctypes.Structure):
     _fields_ = [("df", DFGenProblem), ("h", ctypes.c_void_p), ("gamma1", ctypes.c_void_p)]
+
+
+class SemicanProblem(ctypes.Structure):
+    _fields_ = [
+        ("nao", ctypes.c_int64), ("nmo", ctypes.c_int64), ("nfrz", ctypes.c_int64),
+        ("nc", ctypes.c_int64), ("na", ctypes.c_int64), ("nv", ctypes.c_int64),
+        ("F", ctypes.c_void_p), ("C", ctypes.c_void_p),
+    ]
 
 
 _lib = None
@@ -96,6 +105,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_fock_workspace_size.restype = i32
     lib.dsrg_df_fock.argtypes = [ctypes.POINTER(FockProblem), i32, vp, vp, sz, vp]
     lib.dsrg_df_fock.restype = i32
+    lib.dsrg_df_semicanonicalize_workspace_size.argtypes = [ctypes.POINTER(SemicanProblem),
+                                                            ctypes.POINTER(sz)]
+    lib.dsrg_df_semicanonicalize_workspace_size.restype = i32
+    lib.dsrg_df_semicanonicalize.argtypes = [ctypes.POINTER(SemicanProblem), i32, vp, vp, vp, vp,
+                                             sz, vp]
+    lib.dsrg_df_semicanonicalize.restype = i32
     lib.dsrg_df_last_error.argtypes = []
     lib.dsrg_df_last_error.restype = ctypes.c_char_p
     lib.dsrg_df_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double),
@@ -301,6 +316,31 @@ def df_fock(ao3, J, C, h, gamma1, nfrz, nc, na, nv, workspace: Optional[torch.Te
                             ws.data_ptr(), nbytes.value, _stream_handle(dev)))
     del keep
     return F
+
+
+def semicanonicalize(F, nfrz, nc, na, nv, C=None, workspace: Optional[torch.Tensor] = None,
+                     timing: bool = False):
+    """(eps [nmo], U [nmo][nmo], Cs = C U or None) via dsrg_df_semicanonicalize
+    from the generalized Fock matrix F [nmo][nmo] (device tensors, float64)."""
+    lib = load_library()
+    nmo = F.shape[0]
+    dev = F.device
+    Fd = _as_dev(F, "F", (nmo, nmo), dev)
+    nao = C.shape[0] if C is not None else 0
+    Cd = _as_dev(C, "C", (nao, nmo), dev) if C is not None else None
+    p = SemicanProblem(nao, nmo, nfrz, nc, na, nv, _ptr(Fd), _ptr(Cd))
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_semicanonicalize_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    f64 = dict(dtype=torch.float64, device=dev)
+    U = torch.empty(nmo, nmo, **f64)
+    eps = torch.empty(nmo, **f64)
+    Cs = torch.empty(nao, nmo, **f64) if Cd is not None else None
+    _check(lib.dsrg_df_semicanonicalize(ctypes.byref(p), OPT_KERNEL_TIMING if timing else 0,
+                                        U.data_ptr(), eps.data_ptr(), _ptr(Cs), ws.data_ptr(),
+                                        nbytes.value, _stream_handle(dev)))
+    del Fd, Cd
+    return eps, U, Cs
 
 
 def df_fock_workspace_size(nao, nmo, naux, nfrz, nc, na, nv) -> int:

@@ -654,6 +654,78 @@ dsrg_status dsrg_df_fock(const dsrg_fock_problem *p, int options, double *F, voi
   return DSRG_OK;
 }
 
+namespace {
+dsrg_status make_semican_plan(const dsrg_semican_problem *p, dsrg::SemicanPlan &pl) {
+  if (!p) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  if (p->nmo < 1 || p->nfrz < 0 || p->nc < 0 || p->na < 0 || p->nv < 0 || p->nao < 0)
+    return fail(DSRG_ERR_ARG, "sizes must satisfy nmo >= 1 and nao, nfrz, nc, na, nv >= 0");
+  if (p->nmo < p->nfrz + p->nc + p->na + p->nv)
+    return fail(DSRG_ERR_ARG, "nmo = %lld is smaller than nfrz + nc + na + nv",
+                (long long)p->nmo);
+  if (p->nmo > (1 << 16)) return fail(DSRG_ERR_UNSUPPORTED, "nmo too large");
+  pl.nao = p->nao;
+  pl.nmo = p->nmo;
+  pl.nfrz = p->nfrz;
+  pl.nc = p->nc;
+  pl.na = p->na;
+  pl.nv = p->nv;
+  const size_t np = (size_t)dsrg::semican_npad(std::max({p->nc, p->na, p->nv, (int64_t)1}));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  pl.off_a = take(sizeof(double) * np * np);
+  pl.off_v = take(sizeof(double) * np * np);
+  pl.off_q = take(sizeof(double) * (np / 64) * 64 * 64);   // one 64 x 64 rotation per pair
+  pl.off_part = take(sizeof(double) * 2 * dsrg::kSemicanParts);
+  pl.off_flag = take(sizeof(int));
+  pl.total = off;
+  return DSRG_OK;
+}
+}  // namespace
+
+dsrg_status dsrg_df_semicanonicalize_workspace_size(const dsrg_semican_problem *p,
+                                                    size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::SemicanPlan pl;
+  dsrg_status st = make_semican_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options, double *U,
+                                     double *eps, double *Cs, void *workspace, size_t ws_bytes,
+                                     void *stream) {
+  g_err[0] = 0;
+  dsrg::SemicanPlan pl;
+  dsrg_status st = make_semican_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  if (options & ~DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "unknown option bits 0x%x", options);
+  if (!p->F || !aligned8(p->F)) return fail(DSRG_ERR_ARG, "F is NULL or misaligned");
+  if (!U || !aligned8(U)) return fail(DSRG_ERR_ARG, "U is NULL or misaligned");
+  if (!eps || !aligned8(eps)) return fail(DSRG_ERR_ARG, "eps is NULL or misaligned");
+  if ((Cs != nullptr) != (p->C != nullptr))
+    return fail(DSRG_ERR_ARG, "C and Cs must be given together");
+  if (Cs && (!aligned8(Cs) || !aligned8(p->C) || p->nao < 1))
+    return fail(DSRG_ERR_ARG, "C or Cs misaligned, or nao < 1 with C given");
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!workspace) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_semican(pl, p->F, p->C, U, eps, Cs, workspace, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
 const char *dsrg_df_last_error(void) { return g_err; }
 
 int dsrg_df_kernel_times(double *ms, const char **names, int cap) {

@@ -368,6 +368,12 @@ static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
   return hipGetLastError();
 }
 
+hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                    const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                    double *C, int64_t ldc, hipStream_t st) {
+  return gemm_g(ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, false, st);
+}
+
 // C = sum_{s < nseg} P[s] with P[s] = op(A) op(B) over the s-th of nseg
 // contiguous ranges of K (one launch, the segments as its batch index; the
 // partial products land in part[nseg][M][N]); then C = alpha sum_s P[s] +

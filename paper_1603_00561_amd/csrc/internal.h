@@ -165,6 +165,20 @@ hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const
 // ---- density-fitting factors (dfgen.hip) ----
 hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutputs &o, void *ws,
                              hipStream_t st);
+// ---- semicanonical orbitals (semican.hip) ----
+struct SemicanPlan {
+  int64_t nao, nmo, nfrz, nc, na, nv;
+  size_t off_a, off_v, off_q, off_part, off_flag;
+  size_t total;
+};
+int64_t semican_npad(int64_t n);   // order of the padded Jacobi matrix of an n-orbital block
+constexpr int64_t kSemicanParts = 64;
+hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *C, double *U,
+                          double *eps, double *Cs, void *ws, hipStream_t st);
+// C = alpha op(A) op(B) + beta C, row-major FP64 on the matrix cores (dfgen.hip)
+hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                    const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                    double *C, int64_t ldc, hipStream_t st);
 // ---- generalized Fock matrix (dfgen.hip) ----
 struct FockPlan {
   int64_t nao, nmo, naux, nfrz, nc, na, nv;

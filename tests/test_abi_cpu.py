@@ -251,3 +251,35 @@ def test_fock_entry_point_validation(lib):
     assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG
     assert call(prob(), nb=16) == b.DSRG_ERR_WORKSPACE
     assert call(prob(), ws=0x40008) == b.DSRG_ERR_WORKSPACE
+
+
+def test_semicanonicalize_entry_point_validation(lib):
+    """Semicanonicalization entry point: workspace sizing and host-side
+    rejection (every call below fails before the first launch)."""
+    def prob(F=0x10000, C=0, **kw):
+        d = dict(nao=0, nmo=40, nfrz=2, nc=5, na=3, nv=30)
+        d.update(kw)
+        return b.SemicanProblem(d["nao"], d["nmo"], d["nfrz"], d["nc"], d["na"], d["nv"], F, C)
+
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_semicanonicalize_workspace_size(ctypes.byref(prob()),
+                                                       ctypes.byref(out)) == 0
+    # two padded 64 x 64 Jacobi matrices at least
+    assert out.value >= 2 * 8 * 64 * 64
+
+    def call(p, U=0x20000, eps=0x30000, Cs=0, opts=0, ws=0x40000, nb=1 << 40):
+        v = lambda x: ctypes.c_void_p(x) if x else None  # noqa: E731
+        return lib.dsrg_df_semicanonicalize(ctypes.byref(p), opts, v(U), v(eps), v(Cs), v(ws),
+                                            nb, None)
+
+    for kw in (dict(nmo=0), dict(nc=-1), dict(nmo=39)):
+        assert call(prob(**kw)) == b.DSRG_ERR_ARG, kw
+        assert lib.dsrg_df_last_error().decode()
+    assert call(prob(F=0)) == b.DSRG_ERR_ARG
+    assert call(prob(), U=0) == b.DSRG_ERR_ARG
+    assert call(prob(), eps=0x30004) == b.DSRG_ERR_ARG
+    assert call(prob(), Cs=0x50000) == b.DSRG_ERR_ARG                  # Cs without C
+    assert call(prob(C=0x50000, nao=40)) == b.DSRG_ERR_ARG             # C without Cs
+    assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG
+    assert call(prob(), nb=16) == b.DSRG_ERR_WORKSPACE
+    assert call(prob(), ws=0x40008) == b.DSRG_ERR_WORKSPACE
