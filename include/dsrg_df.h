@@ -250,8 +250,8 @@ dsrg_status dsrg_df_semicanonicalize_workspace_size(const dsrg_semican_problem *
 
 /* U [nmo][nmo], eps [nmo] and, when C and Cs are both given, Cs = C U
  * [nao][nmo] (device, FP64). Jacobi rotations to an off-diagonal norm below
- * 1e-15 of the block's norm, or 15 sweeps at most (blocks of up to 64
- * orbitals: 40 inner sweeps at most). Errors as for dsrg_df_energy. */
+ * 1e-14 of the block's norm, or 12 block sweeps at most (blocks of up to 32
+ * orbitals: 40 sweeps at most). Errors as for dsrg_df_energy. */
 dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options, double *U,
                                      double *eps, double *Cs, void *workspace, size_t ws_bytes,
                                      void *stream);

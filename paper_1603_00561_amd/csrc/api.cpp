@@ -677,8 +677,9 @@ dsrg_status make_semican_plan(const dsrg_semican_problem *p, dsrg::SemicanPlan &
     return at;
   };
   pl.off_a = take(sizeof(double) * np * np);
+  pl.off_a2 = take(sizeof(double) * np * np);   // the matrix of the next Jacobi round
   pl.off_v = take(sizeof(double) * np * np);
-  pl.off_q = take(sizeof(double) * (np / 64) * 64 * 64);   // one 64 x 64 rotation per pair
+  pl.off_q = take(sizeof(double) * (np / 32) * 32 * 32);   // one 32 x 32 rotation per pair
   pl.off_part = take(sizeof(double) * 2 * dsrg::kSemicanParts);
   pl.off_flag = take(sizeof(int));
   pl.total = off;

@@ -168,7 +168,7 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
 // ---- semicanonical orbitals (semican.hip) ----
 struct SemicanPlan {
   int64_t nao, nmo, nfrz, nc, na, nv;
-  size_t off_a, off_v, off_q, off_part, off_flag;
+  size_t off_a, off_a2, off_v, off_q, off_part, off_flag;
   size_t total;
 };
 int64_t semican_npad(int64_t n);   // order of the padded Jacobi matrix of an n-orbital block

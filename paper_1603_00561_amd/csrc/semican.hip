@@ -4,19 +4,22 @@
 // coefficients C U. Frozen core orbitals keep U = I and their diagonal of F.
 //
 // Each block is diagonalized by two-sided block Jacobi (gfx950, FP64): the
-// block, zero-padded to a multiple of 64, is cut into 32-wide blocks; a sweep
+// block, zero-padded to a multiple of 32, is cut into 16-wide blocks; a sweep
 // runs the circle-method rounds over those blocks, and a round (i) solves
 // every disjoint pair of blocks approximately, as one parallel Jacobi sweep
-// over its 64 x 64 submatrix in LDS (one workgroup per pair, 32 disjoint
-// rotations at a time), and (ii) applies each pair's 64 x 64 rotation to the
-// pair's columns of the whole matrix and of the eigenvector matrix, then to
-// the pair's rows. Padded rows and columns never couple (their off-diagonal
+// over its 32 x 32 submatrix in LDS (one workgroup per pair, 16 disjoint
+// rotations at a time, each thread taking one 2 x 2 block through both
+// sides), and (ii) forms
+// every block of the new matrix as Q_P^T A_PP' Q_P' from the old one (a second
+// buffer, so the update is one fully parallel launch) and rotates the pair's
+// columns of the eigenvector matrix. Padded rows and columns never couple (their off-diagonal
 // entries stay exactly zero), so they keep their unit eigenvectors. After
 // each sweep the off-diagonal norm is compared with the whole norm (partial
 // sums over 64 workgroups, added in order) and a device flag is set when
-// their ratio is below 1e-15; the launches of the
-// remaining sweeps (at most kMaxSweeps in all) then return at once, so
-// nothing waits on the host. Blocks of at most 64 orbitals are solved in one
+// their ratio is below 1e-14; the launches of the
+// remaining sweeps (at most kMaxSweeps in all) then return at once (the
+// matrix update only copies), so nothing waits on the host. Blocks of at most
+// 32 orbitals are solved in one
 // workgroup with inner sweeps repeated to the same criterion. The eigenvalues
 // are finally ranked (ascending) and each eigenvector signed so that its
 // component of largest magnitude is positive.
@@ -27,13 +30,13 @@
 
 namespace dsrg {
 
-constexpr int kJB = 32;             // Jacobi block width
+constexpr int kJB = 16;             // Jacobi block width
 constexpr int kJP = 2 * kJB;        // pair submatrix order
 constexpr int kJP1 = kJP + 1;       // LDS row pitch
 constexpr int kJT = 256;            // threads per workgroup
-constexpr int kMaxSweeps = 15;      // block Jacobi sweeps at most
-constexpr int kSmallSweeps = 40;    // inner sweeps at most for blocks of <= 64
-constexpr double kJacTol2 = 1e-30;  // (off-diagonal / whole)^2 at convergence
+constexpr int kMaxSweeps = 12;      // block Jacobi sweeps at most
+constexpr int kSmallSweeps = 40;    // inner sweeps at most for blocks of <= kJP
+constexpr double kJacTol2 = 1e-28;  // (off-diagonal / whole)^2 at convergence
 
 // pair k of round r of the circle method over np (even) players
 __device__ __forceinline__ void circle_pair(int np, int r, int k, int &i, int &j) {
@@ -63,17 +66,21 @@ __device__ __forceinline__ void jac_rot(double spp, double sqq, double spq, doub
 }
 
 struct JacLds {
-  double S[kJP][kJP1];
-  double Q[kJP][kJP1];
+  double S[kJP][kJP1];   // submatrix, rotated in place
+  double Q[kJP][kJP1];   // accumulated rotation
   double c[kJP / 2], s[kJP / 2];
   int p[kJP / 2], q[kJP / 2];
   double red[kJT];
 };
 
-// one parallel Jacobi sweep over the 64 x 64 symmetric S, the rotations
-// accumulated into Q (Q <- Q J)
+// one parallel Jacobi sweep over the symmetric S, accumulating Q <- Q J. In a
+// round the kJP / 2 disjoint rotations split the indices into pairs, so the
+// 2 x 2 blocks {p_a, q_a} x {p_b, q_b} partition S: thread (a, b) takes block
+// (a, b) through J_a^T (.) J_b in registers and writes it back in place, and
+// the row pairs of Q through J_b likewise.
 __device__ void jac_inner_sweep(JacLds &L) {
   const int t = threadIdx.x;
+  static_assert((kJP / 2) * (kJP / 2) == kJT, "one 2 x 2 block of S per thread");
   for (int ri = 0; ri < kJP - 1; ++ri) {
     if (t < kJP / 2) {
       int p, q;
@@ -86,25 +93,25 @@ __device__ void jac_inner_sweep(JacLds &L) {
       L.s[t] = s;
     }
     __syncthreads();
-    // columns of S and of Q
-    for (int e = t; e < 2 * (kJP / 2) * kJP; e += kJT) {
-      const int k = (e / kJP) % (kJP / 2), a = e % kJP;
-      double(*M)[kJP1] = (e < (kJP / 2) * kJP) ? L.S : L.Q;
-      const int p = L.p[k], q = L.q[k];
-      const double c = L.c[k], s = L.s[k];
-      const double x = M[a][p], y = M[a][q];
-      M[a][p] = c * x - s * y;
-      M[a][q] = s * x + c * y;
-    }
-    __syncthreads();
-    // rows of S
-    for (int e = t; e < (kJP / 2) * kJP; e += kJT) {
-      const int k = e / kJP, b = e % kJP;
-      const int p = L.p[k], q = L.q[k];
-      const double c = L.c[k], s = L.s[k];
-      const double x = L.S[p][b], y = L.S[q][b];
-      L.S[p][b] = c * x - s * y;
-      L.S[q][b] = s * x + c * y;
+    {
+      const int ka = t / (kJP / 2), kb = t % (kJP / 2);
+      const int pa = L.p[ka], qa = L.q[ka], pb = L.p[kb], qb = L.q[kb];
+      const double ca = L.c[ka], sa = L.s[ka], cb = L.c[kb], sb = L.s[kb];
+      const double m00 = L.S[pa][pb], m01 = L.S[pa][qb], m10 = L.S[qa][pb], m11 = L.S[qa][qb];
+      // rows: new p = c p - s q, new q = s p + c q
+      const double t00 = ca * m00 - sa * m10, t01 = ca * m01 - sa * m11;
+      const double t10 = sa * m00 + ca * m10, t11 = sa * m01 + ca * m11;
+      // columns likewise
+      L.S[pa][pb] = t00 * cb - t01 * sb;
+      L.S[pa][qb] = t00 * sb + t01 * cb;
+      L.S[qa][pb] = t10 * cb - t11 * sb;
+      L.S[qa][qb] = t10 * sb + t11 * cb;
+      // Q: rows (2 per thread) through J_b
+      for (int a = t / (kJP / 2); a < kJP; a += kJT / (kJP / 2)) {
+        const double x = L.Q[a][pb], y = L.Q[a][qb];
+        L.Q[a][pb] = cb * x - sb * y;
+        L.Q[a][qb] = sb * x + cb * y;
+      }
     }
     __syncthreads();
   }
@@ -127,13 +134,13 @@ __global__ void jac_reset_kernel(int *done) {
   if (threadIdx.x == 0) *done = 0;
 }
 
-// global index of row a (0..63) of the pair (I, J)
+// global index of row a (0..kJP-1) of the pair (I, J)
 __device__ __forceinline__ int64_t pair_index(int I, int J, int a) {
   return a < kJB ? (int64_t)I * kJB + a : (int64_t)J * kJB + (a - kJB);
 }
 
 // one workgroup per pair of round r: one inner sweep on the pair's submatrix,
-// the accumulated 64 x 64 rotation written to Qout[pair]
+// the accumulated kJP x kJP rotation written to Qout[pair]
 __global__ __launch_bounds__(kJT) void jac_pair_kernel(const double *__restrict__ A, int64_t npad,
                                                        int nb, int r, double *__restrict__ Qout,
                                                        const int *__restrict__ done) {
@@ -153,62 +160,107 @@ __global__ __launch_bounds__(kJT) void jac_pair_kernel(const double *__restrict_
   for (int e = t; e < kJP * kJP; e += kJT) Qo[e] = L.Q[e / kJP][e % kJP];
 }
 
-// columns of the pairs of round r: M[:, pair] <- M[:, pair] Q for M = A
-// (blockIdx.z = 0) and M = V (1); one workgroup per 64-row tile and pair
-__global__ __launch_bounds__(kJT) void jac_cols_kernel(double *__restrict__ A,
-                                                       double *__restrict__ V, int64_t npad,
-                                                       int nb, int r, const double *__restrict__ Qall,
-                                                       const int *__restrict__ done) {
+// Anew[P, P'] = Q_P^T Aold[P, P'] Q_P' for every pair P, P' of round r (the
+// pairs cover every block, so Anew is written whole); once converged the
+// blocks are copied unchanged
+__global__ __launch_bounds__(kJT) void jac_update_a_kernel(const double *__restrict__ Aold,
+                                                           double *__restrict__ Anew,
+                                                           int64_t npad, int nb, int r,
+                                                           const double *__restrict__ Qall,
+                                                           const int *__restrict__ done) {
+  __shared__ double X[kJP][kJP1], Y[kJP][kJP1], Qa[kJP][kJP1], Qb[kJP][kJP1];
+  int I, J, K, M;
+  circle_pair(nb, r, blockIdx.x, I, J);
+  circle_pair(nb, r, blockIdx.y, K, M);
+  const int t = threadIdx.x;
+  if (*done) {
+    for (int e = t; e < kJP * kJP; e += kJT) {
+      const int64_t g = pair_index(I, J, e / kJP) * npad + pair_index(K, M, e % kJP);
+      Anew[g] = Aold[g];
+    }
+    return;
+  }
+  const double *QP = Qall + (int64_t)blockIdx.x * kJP * kJP;
+  const double *QQ = Qall + (int64_t)blockIdx.y * kJP * kJP;
+  for (int e = t; e < kJP * kJP; e += kJT) {
+    const int a = e / kJP, b = e % kJP;
+    X[a][b] = Aold[pair_index(I, J, a) * npad + pair_index(K, M, b)];
+    Qa[a][b] = QP[e];
+    Qb[a][b] = QQ[e];
+  }
+  __syncthreads();
+  // each thread a 2 x 2 block of outputs (rows a0, a0 + 16, columns b0, b0 + 16)
+  const int a0 = t / (kJP / 2), b0 = t % (kJP / 2), h = kJP / 2;
+  {   // Y = Q_P^T X
+    double y00 = 0.0, y01 = 0.0, y10 = 0.0, y11 = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kJP; ++k) {
+      const double q0 = Qa[k][a0], q1 = Qa[k][a0 + h], x0 = X[k][b0], x1 = X[k][b0 + h];
+      y00 = fma(q0, x0, y00);
+      y01 = fma(q0, x1, y01);
+      y10 = fma(q1, x0, y10);
+      y11 = fma(q1, x1, y11);
+    }
+    Y[a0][b0] = y00;
+    Y[a0][b0 + h] = y01;
+    Y[a0 + h][b0] = y10;
+    Y[a0 + h][b0 + h] = y11;
+  }
+  __syncthreads();
+  {   // Anew = Y Q_P'
+    double z00 = 0.0, z01 = 0.0, z10 = 0.0, z11 = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kJP; ++k) {
+      const double y0 = Y[a0][k], y1 = Y[a0 + h][k], q0 = Qb[k][b0], q1 = Qb[k][b0 + h];
+      z00 = fma(y0, q0, z00);
+      z01 = fma(y0, q1, z01);
+      z10 = fma(y1, q0, z10);
+      z11 = fma(y1, q1, z11);
+    }
+    const int64_t r0 = pair_index(I, J, a0) * npad, r1 = pair_index(I, J, a0 + h) * npad;
+    const int64_t c0 = pair_index(K, M, b0), c1 = pair_index(K, M, b0 + h);
+    Anew[r0 + c0] = z00;
+    Anew[r0 + c1] = z01;
+    Anew[r1 + c0] = z10;
+    Anew[r1 + c1] = z11;
+  }
+}
+
+// V[rows, P] <- V[rows, P] Q_P for the pairs of round r; one workgroup per
+// kJP-row tile and pair
+__global__ __launch_bounds__(kJT) void jac_update_v_kernel(double *__restrict__ V, int64_t npad,
+                                                           int nb, int r,
+                                                           const double *__restrict__ Qall,
+                                                           const int *__restrict__ done) {
   if (*done) return;
   __shared__ double X[kJP][kJP1], Qs[kJP][kJP1];
   int I, J;
   circle_pair(nb, r, blockIdx.y, I, J);
-  double *M = blockIdx.z ? V : A;
   const int64_t r0 = (int64_t)blockIdx.x * kJP;
   const double *Qp = Qall + (int64_t)blockIdx.y * kJP * kJP;
   const int t = threadIdx.x;
   for (int e = t; e < kJP * kJP; e += kJT) {
     const int a = e / kJP, b = e % kJP;
-    X[a][b] = M[(r0 + a) * npad + pair_index(I, J, b)];
+    X[a][b] = V[(r0 + a) * npad + pair_index(I, J, b)];
     Qs[a][b] = Qp[e];
   }
   __syncthreads();
-  // X and Qs live in LDS and the results go to global memory, so each
-  // result is stored as soon as it is formed
-  for (int j = 0; j < kJP * kJP / kJT; ++j) {
-    const int e = t + kJT * j, a = e / kJP, c = e % kJP;
-    double v = 0.0;
-#pragma unroll 16
-    for (int b = 0; b < kJP; ++b) v = fma(X[a][b], Qs[b][c], v);
-    M[(r0 + a) * npad + pair_index(I, J, c)] = v;
+  // X and Qs live in LDS and the results go to global memory; each thread a
+  // 2 x 2 block of outputs
+  const int a0 = t / (kJP / 2), c0 = t % (kJP / 2), h = kJP / 2;
+  double z00 = 0.0, z01 = 0.0, z10 = 0.0, z11 = 0.0;
+#pragma unroll 8
+  for (int b = 0; b < kJP; ++b) {
+    const double x0 = X[a0][b], x1 = X[a0 + h][b], q0 = Qs[b][c0], q1 = Qs[b][c0 + h];
+    z00 = fma(x0, q0, z00);
+    z01 = fma(x0, q1, z01);
+    z10 = fma(x1, q0, z10);
+    z11 = fma(x1, q1, z11);
   }
-}
-
-// rows of the pairs of round r: A[pair, :] <- Q^T A[pair, :]; one workgroup
-// per 64-column tile and pair
-__global__ __launch_bounds__(kJT) void jac_rows_kernel(double *__restrict__ A, int64_t npad,
-                                                       int nb, int r, const double *__restrict__ Qall,
-                                                       const int *__restrict__ done) {
-  if (*done) return;
-  __shared__ double X[kJP][kJP1], Qs[kJP][kJP1];
-  int I, J;
-  circle_pair(nb, r, blockIdx.y, I, J);
-  const int64_t c0 = (int64_t)blockIdx.x * kJP;
-  const double *Qp = Qall + (int64_t)blockIdx.y * kJP * kJP;
-  const int t = threadIdx.x;
-  for (int e = t; e < kJP * kJP; e += kJT) {
-    const int a = e / kJP, b = e % kJP;
-    X[a][b] = A[pair_index(I, J, a) * npad + c0 + b];
-    Qs[a][b] = Qp[e];
-  }
-  __syncthreads();
-  for (int j = 0; j < kJP * kJP / kJT; ++j) {
-    const int e = t + kJT * j, a = e / kJP, c = e % kJP;
-    double v = 0.0;
-#pragma unroll 16
-    for (int b = 0; b < kJP; ++b) v = fma(Qs[b][a], X[b][c], v);
-    A[pair_index(I, J, a) * npad + c0 + c] = v;
-  }
+  V[(r0 + a0) * npad + pair_index(I, J, c0)] = z00;
+  V[(r0 + a0) * npad + pair_index(I, J, c0 + h)] = z01;
+  V[(r0 + a0 + h) * npad + pair_index(I, J, c0)] = z10;
+  V[(r0 + a0 + h) * npad + pair_index(I, J, c0 + h)] = z11;
 }
 
 // fixed-order sum over the workgroup (kJT threads)
@@ -262,8 +314,9 @@ __global__ void jac_check_final_kernel(const double *__restrict__ part, int *__r
   if (off <= kJacTol2 * tot) *done = 1;
 }
 
-// blocks of at most 64 (npad == 64): inner sweeps in one workgroup until the
-// same criterion holds (at most kSmallSweeps), then A and V written back
+// blocks of at most kJP orbitals (npad == kJP): inner sweeps in one workgroup
+// until the same criterion holds (at most kSmallSweeps), then A and V written
+// back
 __global__ __launch_bounds__(kJT) void jac_small_kernel(double *__restrict__ A,
                                                         double *__restrict__ V) {
   __shared__ JacLds L;
@@ -340,7 +393,8 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
                           double *eps, double *Cs, void *ws, hipStream_t st) {
   hipError_t e;
   const int64_t nmo = pl.nmo;
-  double *A = ws_d(ws, pl.off_a), *V = ws_d(ws, pl.off_v), *Qb = ws_d(ws, pl.off_q);
+  double *Ab[2] = {ws_d(ws, pl.off_a), ws_d(ws, pl.off_a2)};
+  double *V = ws_d(ws, pl.off_v), *Qb = ws_d(ws, pl.off_q);
   double *Pt = ws_d(ws, pl.off_part);
   int *done = reinterpret_cast<int *>(static_cast<char *>(ws) + pl.off_flag);
   hipLaunchKernelGGL(semican_init_kernel,
@@ -350,39 +404,41 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
   const char *names[3] = {"semican_core", "semican_active", "semican_virtual"};
   const int64_t sizes[3] = {pl.nc, pl.na, pl.nv};
   int64_t o = pl.nfrz;
-  for (int b = 0; b < 3; ++b) {
-    const int64_t n = sizes[b];
+  for (int blk = 0; blk < 3; ++blk) {
+    const int64_t n = sizes[blk];
     if (n == 0) continue;
     const int64_t npad = semican_npad(n);
     const int nb = (int)(npad / kJB);
-    timer_begin(names[b], st);
+    timer_begin(names[blk], st);
+    int cur = 0;
     hipLaunchKernelGGL(jac_load_kernel,
                        dim3((unsigned)std::min<int64_t>(ceil_div(npad * npad, 256), 4096)),
-                       dim3(256), 0, st, F, nmo, o, n, npad, A, V);
+                       dim3(256), 0, st, F, nmo, o, n, npad, Ab[0], V);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (npad == kJP) {
-      hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(kJT), 0, st, A, V);
+      hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(kJT), 0, st, Ab[0], V);
     } else {
       hipLaunchKernelGGL(jac_reset_kernel, dim3(1), dim3(64), 0, st, done);
       const int npairs = nb / 2;
       const unsigned tiles = (unsigned)(npad / kJP);
       for (int sw = 0; sw < kMaxSweeps; ++sw) {
         for (int r = 0; r < nb - 1; ++r) {
-          hipLaunchKernelGGL(jac_pair_kernel, dim3(npairs), dim3(kJT), 0, st, A, npad, nb, r, Qb,
-                             done);
-          hipLaunchKernelGGL(jac_cols_kernel, dim3(tiles, npairs, 2), dim3(kJT), 0, st, A, V,
-                             npad, nb, r, Qb, done);
-          hipLaunchKernelGGL(jac_rows_kernel, dim3(tiles, npairs), dim3(kJT), 0, st, A, npad, nb,
+          hipLaunchKernelGGL(jac_pair_kernel, dim3(npairs), dim3(kJT), 0, st, Ab[cur], npad, nb,
                              r, Qb, done);
+          hipLaunchKernelGGL(jac_update_a_kernel, dim3(npairs, npairs), dim3(kJT), 0, st,
+                             Ab[cur], Ab[cur ^ 1], npad, nb, r, Qb, done);
+          hipLaunchKernelGGL(jac_update_v_kernel, dim3(tiles, npairs), dim3(kJT), 0, st, V, npad,
+                             nb, r, Qb, done);
+          cur ^= 1;
         }
-        hipLaunchKernelGGL(jac_check_part_kernel, dim3(kJacParts), dim3(kJT), 0, st, A, npad,
-                           Pt, done);
+        hipLaunchKernelGGL(jac_check_part_kernel, dim3(kJacParts), dim3(kJT), 0, st, Ab[cur],
+                           npad, Pt, done);
         hipLaunchKernelGGL(jac_check_final_kernel, dim3(1), dim3(64), 0, st, Pt, done);
       }
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(jac_finalize_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, A,
-                       V, npad, n, o, nmo, U, eps);
+    hipLaunchKernelGGL(jac_finalize_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st,
+                       Ab[cur], V, npad, n, o, nmo, U, eps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     timer_end(st);
     o += n;

@@ -264,8 +264,8 @@ def test_semicanonicalize_entry_point_validation(lib):
     out = ctypes.c_size_t(0)
     assert lib.dsrg_df_semicanonicalize_workspace_size(ctypes.byref(prob()),
                                                        ctypes.byref(out)) == 0
-    # two padded 64 x 64 Jacobi matrices at least
-    assert out.value >= 2 * 8 * 64 * 64
+    # three padded 32 x 32 Jacobi matrices at least
+    assert out.value >= 3 * 8 * 32 * 32
 
     def call(p, U=0x20000, eps=0x30000, Cs=0, opts=0, ws=0x40000, nb=1 << 40):
         v = lambda x: ctypes.c_void_p(x) if x else None  # noqa: E731

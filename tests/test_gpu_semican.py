@@ -59,7 +59,7 @@ def check(F, shape, C=None, **kw):
                                    (0, 20, 6, 64), (2, 10, 3, 65), (0, 40, 8, 130),
                                    (1, 23, 2, 200)])
 def test_small_and_ragged_blocks(shape):
-    # blocks of 1 .. 64 (one workgroup), 65 and more (block Jacobi, ragged pad)
+    # blocks of 1 .. 32 (one workgroup), 33 and more (block Jacobi, ragged pad)
     F = synthetic_F(sum(shape), seed=sum(shape) + 3)
     check(F, shape)
 
@@ -74,7 +74,7 @@ def test_fock_matrix_from_the_gpu_and_rotated_coefficients():
 
 
 def test_cfg2_sized_virtual_block():
-    # 380 virtual orbitals (twelve 32-wide Jacobi blocks)
+    # 380 virtual orbitals (twenty-four 16-wide Jacobi blocks)
     F = synthetic_F(10 + 23 + 2 + 380, seed=1603)
     check(F, (10, 23, 2, 380))
 
