@@ -233,8 +233,8 @@ dsrg_status dsrg_df_fock(const dsrg_fock_problem *p, int options, double *F, voi
 /* ---- Semicanonical orbitals (section II.B): the orthogonal U that
  * diagonalizes the core, active and virtual diagonal blocks of a generalized
  * Fock matrix F, eps = diag(U^T F U), and optionally C U. U is block-diagonal
- * over frozen | core | active | virtual, the identity on the frozen core (whose
- * eps are the diagonal of F); within each block the eigenvalues ascend and
+ * over frozen | core | active | virtual, the identity on the frozen core and
+ * on any orbitals past the virtual space (whose eps are the diagonal of F); within each block the eigenvalues ascend and
  * each eigenvector has its component of largest magnitude positive. */
 typedef struct {
   int64_t nao;              /* rows of C (ignored when C is NULL)               */

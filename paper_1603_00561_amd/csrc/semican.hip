@@ -61,7 +61,7 @@ __device__ __forceinline__ void jac_rot(double spp, double sqq, double spq, doub
   }
   const double tau = (sqq - spp) / (2.0 * spq);
   const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + t * t);
+  c = rsqrt(1.0 + t * t);
   s = t * c;
 }
 
@@ -344,16 +344,17 @@ __global__ __launch_bounds__(kJT) void jac_small_kernel(double *__restrict__ A,
   }
 }
 
-// U = 0 with the frozen block the identity; eps = diag(F) (the rotated blocks
-// are overwritten later)
+// U = 0 with the identity on the orbitals that are not rotated (the frozen
+// core, i < nfrz, and any beyond the virtual space, i >= nrot); eps = diag(F)
+// (the rotated blocks are overwritten later)
 __global__ __launch_bounds__(256) void semican_init_kernel(const double *__restrict__ F,
-                                                           int64_t nmo, int64_t nfrz,
+                                                           int64_t nmo, int64_t nfrz, int64_t nrot,
                                                            double *__restrict__ U,
                                                            double *__restrict__ eps) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nmo * nmo;
        e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / nmo, j = e % nmo;
-    U[e] = (i == j && i < nfrz) ? 1.0 : 0.0;
+    U[e] = (i == j && (i < nfrz || i >= nrot)) ? 1.0 : 0.0;
     if (i == j) eps[i] = F[e];
   }
 }
@@ -399,7 +400,7 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
   int *done = reinterpret_cast<int *>(static_cast<char *>(ws) + pl.off_flag);
   hipLaunchKernelGGL(semican_init_kernel,
                      dim3((unsigned)std::min<int64_t>(ceil_div(nmo * nmo, 256), 4096)), dim3(256),
-                     0, st, F, nmo, pl.nfrz, U, eps);
+                     0, st, F, nmo, pl.nfrz, pl.nfrz + pl.nc + pl.na + pl.nv, U, eps);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const char *names[3] = {"semican_core", "semican_active", "semican_virtual"};
   const int64_t sizes[3] = {pl.nc, pl.na, pl.nv};

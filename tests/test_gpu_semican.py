@@ -73,6 +73,19 @@ def test_fock_matrix_from_the_gpu_and_rotated_coefficients():
     check(F, (g.nfrz, g.nc, g.na, g.nv), C=g.C)
 
 
+def test_orbitals_past_the_virtual_space_are_left_alone():
+    # nmo larger than nfrz + nc + na + nv: the extra orbitals keep U = I and
+    # their diagonal of F, like the frozen core
+    F = synthetic_F(50, seed=31)
+    print("[gpu-semican] nfrz=2 nc=5 na=3 nv=30 nmo=50 (10 extra)", flush=True)
+    eps, U, _ = _b().semicanonicalize(_dev(F), 2, 5, 3, 30)
+    eps, U = eps.cpu().numpy(), U.cpu().numpy()
+    e_ref, U_ref = O.semicanonicalize(F, 2, 5, 3, 30)
+    assert np.array_equal(U[40:, 40:], np.eye(10)) and np.array_equal(eps[40:], np.diag(F)[40:])
+    assert np.abs(eps - e_ref).max() <= 1e-11 * np.abs(F).max()
+    assert np.abs(U - U_ref).max() <= 1e-8
+
+
 def test_cfg2_sized_virtual_block():
     # 380 virtual orbitals (twenty-four 16-wide Jacobi blocks)
     F = synthetic_F(10 + 23 + 2 + 380, seed=1603)

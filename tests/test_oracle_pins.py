@@ -507,6 +507,14 @@ def test_semicanonical_rotation_satisfies_its_definition(shape):
         o += n
 
 
+def test_semicanonical_leaves_orbitals_past_the_virtual_space():
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((12, 12))
+    F = G + G.T
+    eps, U = O.semicanonicalize(F, 1, 2, 2, 4)
+    assert np.array_equal(U[9:, :], np.eye(12)[9:, :]) and np.array_equal(eps[9:], np.diag(F)[9:])
+
+
 def test_semicanonical_of_diagonal_blocks_is_a_sort():
     # already diagonal blocks: U permutes each block into ascending order
     F = np.diag([5.0, -1.0, 3.0, 0.5, 2.0, -4.0, 7.0])
