@@ -28,17 +28,21 @@ namespace dsrg {
 // (TM / WR) x (TN / WC) block of 16 x 16 FP64 MFMA fragments and every KS-th
 // group of four k of each chunk; K chunks of KC staged through registers into
 // LDS, one barrier per chunk; with KS > 1 the KS partial tiles are summed
-// through LDS in a fixed order at the end. Each operand is
-// read along its contiguous index: an operand contiguous in k is staged as
-// [row][k] rows of KC + 2 (two pads: the 16 x 4 fragment read then touches
-// each bank pair at most twice), one contiguous in m or n as [k][row] rows
-// whose odd rows have their 16-element halves swapped. Out-of-range elements
-// read as zero. With ktri set the contraction of the row tile starting at m0
-// stops at k = m0 + TM (A lower triangular). Four shapes: 128 x 128 (8 waves,
-// K chunks of 32) for large products, 32 x 128 (4 waves) for products with at most 32 rows,
-// 64 x 64 (4 waves, K chunks of 32) and 32 x 32 with K split over 4 waves (K
-// chunks of 64) to spread smaller ones over more SIMDs: one FP64 MFMA wave
-// needs about a microsecond per 32 x 32 x 32 block.
+// through LDS in a fixed order at the end. Each operand is read along its
+// contiguous index (as 16-byte pairs when both operands are aligned for it):
+// an operand contiguous in k is staged as [row][k] rows of KC + 2 (two pads:
+// the 16 x 4 fragment read then touches each bank pair at most twice), one
+// contiguous in m or n as [k][row] rows whose odd rows have their 16-element
+// halves swapped within groups of 32 (plain when the tile height is not a
+// multiple of 32). Out-of-range elements read as zero. With ktri set the
+// contraction of the row tile starting at m0 stops at k = m0 + TM (A lower
+// triangular). Tiles are walked XCD by XCD (see the kernel). Shapes: 128 x 128
+// (8 waves, K chunks of 32) for large products; 32 x 128, 48 x 128 and
+// 64 x 128 (4 waves) for products of few rows, also with a batch folded into
+// the columns; 64 x 64 (4 waves, K chunks of 32) and 32 x 32 with K split over
+// 4 waves (K chunks of 64) to spread smaller ones over more SIMDs (one FP64
+// MFMA wave needs about a microsecond per 32 x 32 x 32 block); long products
+// with small outputs are also split over K across workgroups.
 // ---------------------------------------------------------------------------
 struct GemmGArgs {
   int64_t M, N, K;
@@ -55,11 +59,10 @@ struct GemmGArgs {
   int64_t ktotal;
 };
 
-template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1, int MINW_ = 1>
+template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1>
 struct GTile {
   static constexpr int TM = TM_, TN = TN_, WR = WR_, WC = WC_, KC = KC_, KP = KC_ + 2;
   static constexpr int KS = KS_;                     // waves splitting each chunk's k
-  static constexpr int MINW = MINW_;                 // waves per SIMD the registers must allow
   static constexpr int WM = TM / WR, WN = TN / WC;   // wave block
   static constexpr int FP = WM / 16, FQ = WN / 16;   // fragments per wave
   static constexpr int NT = 64 * WR * WC * KS;       // threads
@@ -125,7 +128,7 @@ __device__ __forceinline__ void pair_slot(int t, int j, int &row, int &k, int &l
 // dimensions, batch strides and contiguous extents are even, so every pair is
 // aligned and lies wholly inside or outside the operand)
 template <bool TA, bool TB, class G, bool FOLD = false, bool PAIR = false>
-__global__ __launch_bounds__(G::NT, G::MINW) void gemm_g_kernel(const double *__restrict__ A,
+__global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict__ A,
                                                       const double *__restrict__ B, GemmGArgs a,
                                                       double *__restrict__ C) {
   static_assert(!FOLD || (!TB && G::NT % G::TN == 0), "folded B: n-contiguous, one column per thread");
