@@ -478,20 +478,25 @@ constexpr int kDB = 64;
 
 // leaf: the nb x nb diagonal block at (r0, r0) of the working matrix A (its
 // lower triangle) is factored, L L^T, and inverted in one sweep over the
-// columns j: the pivot d = sqrt(a_jj) and column j of L (a_ij / d) come from
-// the trailing matrix, which then loses L_ij L_lj; in the same step forward
-// substitution on L X = I takes row j of X (b_j / d, b starting as the
-// identity) and removes L_ij x_j from the rows below. L itself is never
-// stored. 256 threads; thread (ty, tx) holds in registers the elements
-// (ty + 16 a, tx + 16 b), a, b < 4, of the trailing matrix and of b; rows and
-// columns past nb hold the identity. Two barriers per column (the pivot, then
-// column j of L and row j of X, double-buffered in LDS).
+// columns, two at a time (j, j + 1): the 2 x 2 pivot block gives d1 = sqrt(a_jj),
+// l = a_{j+1,j} / d1 and d2 = sqrt(a_{j+1,j+1} - l^2); columns j and j + 1 of L
+// are a_ij / d1 and (a_{i,j+1} - L_ij l) / d2, and the trailing matrix loses
+// their rank-2 product. In the same step forward substitution on L X = I
+// (b starting as the identity) takes rows j and j + 1 of X, b_j / d1 and
+// (b_{j+1} - l X_j) / d2, and removes L_ij X_j + L_{i,j+1} X_{j+1} from the rows
+// below. L itself is never stored. 256 threads; thread (ty, tx) holds in
+// registers the elements (ty + 16 a, tx + 16 b), a, b < 4, of the trailing
+// matrix and of b; rows and columns past nb hold the identity (so an odd last
+// column pairs with an identity one). One barrier per two columns: the
+// threads holding columns j, j + 1 and rows j, j + 1 of b publish them
+// unscaled to LDS (double-buffered), and every thread forms the pivot block
+// and the scaled columns and rows it needs from there.
 constexpr int kLeafT = 256;
 
 __global__ __launch_bounds__(kLeafT) void chol_inv_leaf_kernel(const double *__restrict__ A,
                                                                double *__restrict__ X, int64_t ld,
                                                                int64_t r0, int nb) {
-  __shared__ double colL[2][kDB], rowX[2][kDB], piv[2];
+  __shared__ double col[2][2][kDB], row[2][2][kDB];   // [buffer][column j / j + 1][index]
   const int t = threadIdx.x, ty = t >> 4, tx = t & 15;
   double e[4][4], x[4][4];
 #pragma unroll
@@ -504,52 +509,63 @@ __global__ __launch_bounds__(kLeafT) void chol_inv_leaf_kernel(const double *__r
       e[a][b] = v;
       x[a][b] = (i == l) ? 1.0 : 0.0;
     }
-  for (int j = 0; j < nb; ++j) {
-    const int jb = j >> 4, jr = j & 15, bf = j & 1;
-    if (ty == jr && tx == jr) {
-      double p = e[0][0];
+  for (int j = 0; j < nb; j += 2) {
+    const int bf = (j >> 1) & 1;
 #pragma unroll
-      for (int a = 1; a < 4; ++a) p = (a == jb) ? e[a][a] : p;
-      piv[bf] = p;
-    }
-    __syncthreads();
-    const double d = sqrt(piv[bf]);
-    const double rd = 1.0 / d;
-    if (tx == jr) {
+    for (int h = 0; h < 2; ++h) {   // columns j, j + 1 and rows j, j + 1 of b, as they stand
+      const int jj = j + h, jb = jj >> 4, jr = jj & 15;
+      if (tx == jr) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        double v = e[a][0];
+        for (int a = 0; a < 4; ++a) {
+          double v = e[a][0];
 #pragma unroll
-        for (int b = 1; b < 4; ++b) v = (b == jb) ? e[a][b] : v;
-        const int i = ty + 16 * a;
-        colL[bf][i] = (i > j) ? v * rd : 0.0;
+          for (int b = 1; b < 4; ++b) v = (b == jb) ? e[a][b] : v;
+          col[bf][h][ty + 16 * a] = v;
+        }
       }
-    }
-    if (ty == jr) {
+      if (ty == jr) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        double v = x[0][b];
+        for (int b = 0; b < 4; ++b) {
+          double v = x[0][b];
 #pragma unroll
-        for (int a = 1; a < 4; ++a) v = (a == jb) ? x[a][b] : v;
-        rowX[bf][tx + 16 * b] = v * rd;
+          for (int a = 1; a < 4; ++a) v = (a == jb) ? x[a][b] : v;
+          row[bf][h][tx + 16 * b] = v;
+        }
       }
     }
     __syncthreads();
-    double ci[4], cl[4], rx[4];
+    const double d1 = sqrt(col[bf][0][j]);
+    const double rd1 = 1.0 / d1;
+    const double l10 = col[bf][0][j + 1] * rd1;
+    const double d2 = sqrt(col[bf][1][j + 1] - l10 * l10);
+    const double rd2 = 1.0 / d2;
+    double ci0[4], ci1[4], cl0[4], cl1[4], rx0[4], rx1[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) ci[a] = colL[bf][ty + 16 * a];
+    for (int a = 0; a < 4; ++a) {
+      const int i = ty + 16 * a;
+      const double L0 = col[bf][0][i] * rd1;
+      ci0[a] = (i > j) ? L0 : 0.0;
+      ci1[a] = (i > j + 1) ? (col[bf][1][i] - L0 * l10) * rd2 : 0.0;
+    }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      cl[b] = colL[bf][tx + 16 * b];
-      rx[b] = rowX[bf][tx + 16 * b];
+      const int l = tx + 16 * b;
+      const double L0 = col[bf][0][l] * rd1;
+      cl0[b] = (l > j) ? L0 : 0.0;
+      cl1[b] = (l > j + 1) ? (col[bf][1][l] - L0 * l10) * rd2 : 0.0;
+      rx0[b] = row[bf][0][l] * rd1;
+      rx1[b] = (row[bf][1][l] - l10 * rx0[b]) * rd2;
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+      const int i = ty + 16 * a;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        e[a][b] = fma(-ci[a], cl[b], e[a][b]);
-        x[a][b] = (ty + 16 * a == j) ? rx[b] : fma(-ci[a], rx[b], x[a][b]);
+        e[a][b] = fma(-ci1[a], cl1[b], fma(-ci0[a], cl0[b], e[a][b]));
+        const double upd = fma(-ci1[a], rx1[b], fma(-ci0[a], rx0[b], x[a][b]));
+        x[a][b] = (i == j) ? rx0[b] : ((i == j + 1) ? rx1[b] : upd);
       }
+    }
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
