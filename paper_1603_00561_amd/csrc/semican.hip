@@ -11,8 +11,8 @@
 // rotations at a time, each thread taking one 2 x 2 block through both
 // sides), and (ii) forms
 // every block of the new matrix as Q_P^T A_PP' Q_P' from the old one (a second
-// buffer, so the update is one fully parallel launch) and rotates the pair's
-// columns of the eigenvector matrix. Padded rows and columns never couple (their off-diagonal
+// buffer, so the update is fully parallel) and rotates the pair's columns of
+// the eigenvector matrix, both in one launch. Padded rows and columns never couple (their off-diagonal
 // entries stay exactly zero), so they keep their unit eigenvectors. After
 // each sweep the off-diagonal norm is compared with the whole norm (partial
 // sums over 64 workgroups, added in order) and a device flag is set when
@@ -160,19 +160,53 @@ __global__ __launch_bounds__(kJT) void jac_pair_kernel(const double *__restrict_
   for (int e = t; e < kJP * kJP; e += kJT) Qo[e] = L.Q[e / kJP][e % kJP];
 }
 
-// Anew[P, P'] = Q_P^T Aold[P, P'] Q_P' for every pair P, P' of round r (the
-// pairs cover every block, so Anew is written whole); once converged the
-// blocks are copied unchanged
-__global__ __launch_bounds__(kJT) void jac_update_a_kernel(const double *__restrict__ Aold,
-                                                           double *__restrict__ Anew,
-                                                           int64_t npad, int nb, int r,
-                                                           const double *__restrict__ Qall,
-                                                           const int *__restrict__ done) {
+// one launch per round for both updates: workgroups (x, y < npairs) form
+// Anew[P, P'] = Q_P^T Aold[P, P'] Q_P' for the pairs P = x, P' = y of round r
+// (the pairs cover every block, so Anew is written whole; once converged the
+// blocks are copied unchanged); workgroups (x, y >= npairs) rotate the
+// eigenvector columns of pair x in the kJP-row tile y - npairs,
+// V[rows, P] <- V[rows, P] Q_P (nothing once converged)
+__global__ __launch_bounds__(kJT) void jac_update_kernel(const double *__restrict__ Aold,
+                                                         double *__restrict__ Anew,
+                                                         double *__restrict__ V, int64_t npad,
+                                                         int nb, int r,
+                                                         const double *__restrict__ Qall,
+                                                         const int *__restrict__ done) {
   __shared__ double X[kJP][kJP1], Y[kJP][kJP1], Qa[kJP][kJP1], Qb[kJP][kJP1];
-  int I, J, K, M;
-  circle_pair(nb, r, blockIdx.x, I, J);
-  circle_pair(nb, r, blockIdx.y, K, M);
+  const int npairs = nb / 2;
   const int t = threadIdx.x;
+  const int a0 = t / (kJP / 2), b0 = t % (kJP / 2), h = kJP / 2;
+  int I, J;
+  circle_pair(nb, r, blockIdx.x, I, J);
+  const double *QP = Qall + (int64_t)blockIdx.x * kJP * kJP;
+  if ((int)blockIdx.y >= npairs) {   // eigenvector columns
+    if (*done) return;
+    const int64_t r0 = (int64_t)(blockIdx.y - npairs) * kJP;
+    for (int e = t; e < kJP * kJP; e += kJT) {
+      const int a = e / kJP, b = e % kJP;
+      X[a][b] = V[(r0 + a) * npad + pair_index(I, J, b)];
+      Qa[a][b] = QP[e];
+    }
+    __syncthreads();
+    // X and Qa live in LDS and the results go to global memory; each thread
+    // a 2 x 2 block of outputs
+    double z00 = 0.0, z01 = 0.0, z10 = 0.0, z11 = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < kJP; ++k) {
+      const double x0 = X[a0][k], x1 = X[a0 + h][k], q0 = Qa[k][b0], q1 = Qa[k][b0 + h];
+      z00 = fma(x0, q0, z00);
+      z01 = fma(x0, q1, z01);
+      z10 = fma(x1, q0, z10);
+      z11 = fma(x1, q1, z11);
+    }
+    V[(r0 + a0) * npad + pair_index(I, J, b0)] = z00;
+    V[(r0 + a0) * npad + pair_index(I, J, b0 + h)] = z01;
+    V[(r0 + a0 + h) * npad + pair_index(I, J, b0)] = z10;
+    V[(r0 + a0 + h) * npad + pair_index(I, J, b0 + h)] = z11;
+    return;
+  }
+  int K, M;
+  circle_pair(nb, r, blockIdx.y, K, M);
   if (*done) {
     for (int e = t; e < kJP * kJP; e += kJT) {
       const int64_t g = pair_index(I, J, e / kJP) * npad + pair_index(K, M, e % kJP);
@@ -180,7 +214,6 @@ __global__ __launch_bounds__(kJT) void jac_update_a_kernel(const double *__restr
     }
     return;
   }
-  const double *QP = Qall + (int64_t)blockIdx.x * kJP * kJP;
   const double *QQ = Qall + (int64_t)blockIdx.y * kJP * kJP;
   for (int e = t; e < kJP * kJP; e += kJT) {
     const int a = e / kJP, b = e % kJP;
@@ -189,8 +222,6 @@ __global__ __launch_bounds__(kJT) void jac_update_a_kernel(const double *__restr
     Qb[a][b] = QQ[e];
   }
   __syncthreads();
-  // each thread a 2 x 2 block of outputs (rows a0, a0 + 16, columns b0, b0 + 16)
-  const int a0 = t / (kJP / 2), b0 = t % (kJP / 2), h = kJP / 2;
   {   // Y = Q_P^T X
     double y00 = 0.0, y01 = 0.0, y10 = 0.0, y11 = 0.0;
 #pragma unroll 8
@@ -224,43 +255,6 @@ __global__ __launch_bounds__(kJT) void jac_update_a_kernel(const double *__restr
     Anew[r1 + c0] = z10;
     Anew[r1 + c1] = z11;
   }
-}
-
-// V[rows, P] <- V[rows, P] Q_P for the pairs of round r; one workgroup per
-// kJP-row tile and pair
-__global__ __launch_bounds__(kJT) void jac_update_v_kernel(double *__restrict__ V, int64_t npad,
-                                                           int nb, int r,
-                                                           const double *__restrict__ Qall,
-                                                           const int *__restrict__ done) {
-  if (*done) return;
-  __shared__ double X[kJP][kJP1], Qs[kJP][kJP1];
-  int I, J;
-  circle_pair(nb, r, blockIdx.y, I, J);
-  const int64_t r0 = (int64_t)blockIdx.x * kJP;
-  const double *Qp = Qall + (int64_t)blockIdx.y * kJP * kJP;
-  const int t = threadIdx.x;
-  for (int e = t; e < kJP * kJP; e += kJT) {
-    const int a = e / kJP, b = e % kJP;
-    X[a][b] = V[(r0 + a) * npad + pair_index(I, J, b)];
-    Qs[a][b] = Qp[e];
-  }
-  __syncthreads();
-  // X and Qs live in LDS and the results go to global memory; each thread a
-  // 2 x 2 block of outputs
-  const int a0 = t / (kJP / 2), c0 = t % (kJP / 2), h = kJP / 2;
-  double z00 = 0.0, z01 = 0.0, z10 = 0.0, z11 = 0.0;
-#pragma unroll 8
-  for (int b = 0; b < kJP; ++b) {
-    const double x0 = X[a0][b], x1 = X[a0 + h][b], q0 = Qs[b][c0], q1 = Qs[b][c0 + h];
-    z00 = fma(x0, q0, z00);
-    z01 = fma(x0, q1, z01);
-    z10 = fma(x1, q0, z10);
-    z11 = fma(x1, q1, z11);
-  }
-  V[(r0 + a0) * npad + pair_index(I, J, c0)] = z00;
-  V[(r0 + a0) * npad + pair_index(I, J, c0 + h)] = z01;
-  V[(r0 + a0 + h) * npad + pair_index(I, J, c0)] = z10;
-  V[(r0 + a0 + h) * npad + pair_index(I, J, c0 + h)] = z11;
 }
 
 // fixed-order sum over the workgroup (kJT threads)
@@ -426,10 +420,8 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
         for (int r = 0; r < nb - 1; ++r) {
           hipLaunchKernelGGL(jac_pair_kernel, dim3(npairs), dim3(kJT), 0, st, Ab[cur], npad, nb,
                              r, Qb, done);
-          hipLaunchKernelGGL(jac_update_a_kernel, dim3(npairs, npairs), dim3(kJT), 0, st,
-                             Ab[cur], Ab[cur ^ 1], npad, nb, r, Qb, done);
-          hipLaunchKernelGGL(jac_update_v_kernel, dim3(tiles, npairs), dim3(kJT), 0, st, V, npad,
-                             nb, r, Qb, done);
+          hipLaunchKernelGGL(jac_update_kernel, dim3(npairs, npairs + tiles), dim3(kJT), 0, st,
+                             Ab[cur], Ab[cur ^ 1], V, npad, nb, r, Qb, done);
           cur ^= 1;
         }
         hipLaunchKernelGGL(jac_check_part_kernel, dim3(kJacParts), dim3(kJT), 0, st, Ab[cur],
