@@ -353,33 +353,45 @@ __global__ __launch_bounds__(256) void semican_init_kernel(const double *__restr
   }
 }
 
-// eigenvalue i goes to position rank(i) of the block (ascending, ties by
-// index); its eigenvector, signed so that its largest component (the first
-// such) is positive, to column o + rank(i) of U
-__global__ __launch_bounds__(256) void jac_finalize_kernel(const double *__restrict__ A,
+// eigenvalue i (one workgroup each) goes to position rank(i) of the block
+// (ascending, ties by index); its eigenvector, signed so that its largest
+// component (the first such) is positive, to column o + rank(i) of U
+__global__ __launch_bounds__(kJT) void jac_finalize_kernel(const double *__restrict__ A,
                                                            const double *__restrict__ V,
                                                            int64_t npad, int64_t n, int64_t o,
                                                            int64_t nmo, double *__restrict__ U,
                                                            double *__restrict__ eps) {
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * 256) {
-    const double lam = A[i * npad + i];
-    int64_t rank = 0;
-    for (int64_t j = 0; j < n; ++j) {
-      const double mu = A[j * npad + j];
-      rank += (mu < lam || (mu == lam && j < i)) ? 1 : 0;
+  __shared__ double red[kJT];
+  __shared__ double bv[kJT];
+  __shared__ int64_t bi[kJT];
+  const int t = threadIdx.x;
+  const int64_t i = blockIdx.x;
+  const double lam = A[i * npad + i];
+  double cnt = 0.0, best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t j = t; j < n; j += kJT) {
+    const double mu = A[j * npad + j];
+    cnt += (mu < lam || (mu == lam && j < i)) ? 1.0 : 0.0;
+    const double v = fabs(V[j * npad + i]);
+    if (v > best) {   // j ascends within the thread: the first largest is kept
+      best = v;
+      bidx = j;
     }
-    double best = -1.0, sg = 1.0;
-    for (int64_t r = 0; r < n; ++r) {
-      const double v = V[r * npad + i];
-      if (fabs(v) > best) {
-        best = fabs(v);
-        sg = v < 0.0 ? -1.0 : 1.0;
-      }
-    }
-    eps[o + rank] = lam;
-    for (int64_t r = 0; r < n; ++r) U[(o + r) * nmo + o + rank] = sg * V[r * npad + i];
   }
+  const int64_t rank = (int64_t)jac_block_sum(cnt, red);
+  bv[t] = best;
+  bi[t] = bidx;
+  __syncthreads();
+  for (int w = kJT / 2; w > 0; w >>= 1) {   // largest |v|, the smallest index among equals
+    if (t < w && (bv[t + w] > bv[t] || (bv[t + w] == bv[t] && bi[t + w] < bi[t]))) {
+      bv[t] = bv[t + w];
+      bi[t] = bi[t + w];
+    }
+    __syncthreads();
+  }
+  const double sg = V[bi[0] * npad + i] < 0.0 ? -1.0 : 1.0;
+  if (t == 0) eps[o + rank] = lam;
+  for (int64_t r = t; r < n; r += kJT) U[(o + r) * nmo + o + rank] = sg * V[r * npad + i];
 }
 
 int64_t semican_npad(int64_t n) { return std::max<int64_t>(kJP, round_up(n, kJP)); }
@@ -430,8 +442,8 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
       }
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(jac_finalize_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st,
-                       Ab[cur], V, npad, n, o, nmo, U, eps);
+    hipLaunchKernelGGL(jac_finalize_kernel, dim3((unsigned)n), dim3(kJT), 0, st, Ab[cur], V,
+                       npad, n, o, nmo, U, eps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     timer_end(st);
     o += n;
