@@ -51,70 +51,79 @@ __device__ __forceinline__ void circle_pair(int np, int r, int k, int &i, int &j
 }
 
 // rotation (c, s) in the (p, q) plane that zeroes the (p, q) entry of a
-// symmetric matrix under S -> J^T S J, J = [[c, s], [-s, c]] on (p, q)
+// symmetric matrix under S -> J^T S J, J = [[c, s], [-s, c]] on (p, q): the
+// smaller of the two angles, tan = sgn |e| / (|d| + r) with d = s_qq - s_pp,
+// e = 2 s_pq, r = sqrt(d^2 + e^2) and sgn the sign of d e.
+// Since (|d| + r)^2 + e^2 = 2 r (|d| + r), both c = (|d| + r) w and
+// |s| = |e| w follow from w = 1 / sqrt(2 r (|d| + r)): two inverse square
+// roots and no division on the dependent chain. The rotation does not change
+// when d and e are scaled by one factor, so both are first scaled by a power
+// of two to bring the larger into [1/2, 1) and d^2 + e^2 into [1/4, 2).
+// Branch-free, so that a thread's two rotations are scheduled together.
 __device__ __forceinline__ void jac_rot(double spp, double sqq, double spq, double &c,
                                         double &s) {
-  if (spq == 0.0) {
-    c = 1.0;
-    s = 0.0;
-    return;
-  }
-  const double tau = (sqq - spp) / (2.0 * spq);
-  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = rsqrt(1.0 + t * t);
-  s = t * c;
+  const double d0 = sqq - spp, e0 = 2.0 * spq;
+  int k;
+  (void)frexp(fmax(fabs(d0), fabs(e0)), &k);
+  const double d = ldexp(d0, -k), e = ldexp(e0, -k);
+  const double q2 = d * d + e * e;
+  const double r = q2 * rsqrt(q2);
+  const double u = fabs(d) + r;
+  const double w = rsqrt(2.0 * r * u);
+  const double se = copysign(fabs(e), d * e);   // sgn |e| (d = 0: either sign zeroes the entry)
+  const bool zero = (spq == 0.0);
+  c = zero ? 1.0 : u * w;
+  s = zero ? 0.0 : se * w;
 }
 
 struct JacLds {
-  double S[kJP][kJP1];   // submatrix, rotated in place
-  double Q[kJP][kJP1];   // accumulated rotation
-  double c[kJP / 2], s[kJP / 2];
-  int p[kJP / 2], q[kJP / 2];
+  double S[2][kJP][kJP1];   // submatrix, read from one buffer and written to the other
+  double Q[kJP][kJP1];      // accumulated rotation
   double red[kJT];
 };
 
-// one parallel Jacobi sweep over the symmetric S, accumulating Q <- Q J. In a
-// round the kJP / 2 disjoint rotations split the indices into pairs, so the
-// 2 x 2 blocks {p_a, q_a} x {p_b, q_b} partition S: thread (a, b) takes block
-// (a, b) through J_a^T (.) J_b in registers and writes it back in place, and
-// the row pairs of Q through J_b likewise.
-__device__ void jac_inner_sweep(JacLds &L) {
+// one parallel Jacobi sweep over the symmetric submatrix in S[cur],
+// accumulating Q <- Q J; returns the buffer that holds the rotated matrix. In
+// a round the kJP / 2 disjoint rotations split the indices into pairs, so the
+// 2 x 2 blocks {p_a, q_a} x {p_b, q_b} partition S: thread (a, b) forms the
+// rotations a and b itself from the diagonal and pivot entries of the
+// current buffer, takes block (a, b) through J_a^T (.) J_b into the other
+// buffer, and the rows a, a + kJP / 2 of Q at columns p_b, q_b (which no
+// other thread touches in this round) through J_b in place. One barrier per
+// round: nothing a thread writes is read by another thread before it.
+__device__ int jac_inner_sweep(JacLds &L, int cur) {
   const int t = threadIdx.x;
   static_assert((kJP / 2) * (kJP / 2) == kJT, "one 2 x 2 block of S per thread");
+  const int ka = t / (kJP / 2), kb = t % (kJP / 2);
+#pragma unroll 1   // a rolled loop keeps the kernel within the instruction cache
   for (int ri = 0; ri < kJP - 1; ++ri) {
-    if (t < kJP / 2) {
-      int p, q;
-      circle_pair(kJP, ri, t, p, q);
-      double c, s;
-      jac_rot(L.S[p][p], L.S[q][q], L.S[p][q], c, s);
-      L.p[t] = p;
-      L.q[t] = q;
-      L.c[t] = c;
-      L.s[t] = s;
+    const double (*S)[kJP1] = L.S[cur];
+    double (*T)[kJP1] = L.S[cur ^ 1];
+    int pa, qa, pb, qb;
+    circle_pair(kJP, ri, ka, pa, qa);
+    circle_pair(kJP, ri, kb, pb, qb);
+    const double m00 = S[pa][pb], m01 = S[pa][qb], m10 = S[qa][pb], m11 = S[qa][qb];
+    double ca, sa, cb, sb;   // two independent chains
+    jac_rot(S[pa][pa], S[qa][qa], S[pa][qa], ca, sa);
+    jac_rot(S[pb][pb], S[qb][qb], S[pb][qb], cb, sb);
+    // rows: new p = c p - s q, new q = s p + c q
+    const double t00 = ca * m00 - sa * m10, t01 = ca * m01 - sa * m11;
+    const double t10 = sa * m00 + ca * m10, t11 = sa * m01 + ca * m11;
+    // columns likewise
+    T[pa][pb] = t00 * cb - t01 * sb;
+    T[pa][qb] = t00 * sb + t01 * cb;
+    T[qa][pb] = t10 * cb - t11 * sb;
+    T[qa][qb] = t10 * sb + t11 * cb;
+#pragma unroll
+    for (int a = ka; a < kJP; a += kJP / 2) {
+      const double x = L.Q[a][pb], y = L.Q[a][qb];
+      L.Q[a][pb] = cb * x - sb * y;
+      L.Q[a][qb] = sb * x + cb * y;
     }
     __syncthreads();
-    {
-      const int ka = t / (kJP / 2), kb = t % (kJP / 2);
-      const int pa = L.p[ka], qa = L.q[ka], pb = L.p[kb], qb = L.q[kb];
-      const double ca = L.c[ka], sa = L.s[ka], cb = L.c[kb], sb = L.s[kb];
-      const double m00 = L.S[pa][pb], m01 = L.S[pa][qb], m10 = L.S[qa][pb], m11 = L.S[qa][qb];
-      // rows: new p = c p - s q, new q = s p + c q
-      const double t00 = ca * m00 - sa * m10, t01 = ca * m01 - sa * m11;
-      const double t10 = sa * m00 + ca * m10, t11 = sa * m01 + ca * m11;
-      // columns likewise
-      L.S[pa][pb] = t00 * cb - t01 * sb;
-      L.S[pa][qb] = t00 * sb + t01 * cb;
-      L.S[qa][pb] = t10 * cb - t11 * sb;
-      L.S[qa][qb] = t10 * sb + t11 * cb;
-      // Q: rows (2 per thread) through J_b
-      for (int a = t / (kJP / 2); a < kJP; a += kJT / (kJP / 2)) {
-        const double x = L.Q[a][pb], y = L.Q[a][qb];
-        L.Q[a][pb] = cb * x - sb * y;
-        L.Q[a][qb] = sb * x + cb * y;
-      }
-    }
-    __syncthreads();
+    cur ^= 1;
   }
+  return cur;
 }
 
 // A [npad][npad] = the n x n block of F at (o, o), zero-padded; V = I
@@ -151,11 +160,11 @@ __global__ __launch_bounds__(kJT) void jac_pair_kernel(const double *__restrict_
   const int t = threadIdx.x;
   for (int e = t; e < kJP * kJP; e += kJT) {
     const int a = e / kJP, b = e % kJP;
-    L.S[a][b] = A[pair_index(I, J, a) * npad + pair_index(I, J, b)];
+    L.S[0][a][b] = A[pair_index(I, J, a) * npad + pair_index(I, J, b)];
     L.Q[a][b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
-  jac_inner_sweep(L);
+  (void)jac_inner_sweep(L, 0);
   double *Qo = Qout + (int64_t)blockIdx.x * kJP * kJP;
   for (int e = t; e < kJP * kJP; e += kJT) Qo[e] = L.Q[e / kJP][e % kJP];
 }
@@ -316,24 +325,25 @@ __global__ __launch_bounds__(kJT) void jac_small_kernel(double *__restrict__ A,
   __shared__ JacLds L;
   const int t = threadIdx.x;
   for (int e = t; e < kJP * kJP; e += kJT) {
-    L.S[e / kJP][e % kJP] = A[e];
+    L.S[0][e / kJP][e % kJP] = A[e];
     L.Q[e / kJP][e % kJP] = (e / kJP == e % kJP) ? 1.0 : 0.0;
   }
   __syncthreads();
+  int cur = 0;
   for (int sw = 0; sw < kSmallSweeps; ++sw) {
     double off = 0.0, tot = 0.0;
     for (int e = t; e < kJP * kJP; e += kJT) {
-      const double v = L.S[e / kJP][e % kJP] * L.S[e / kJP][e % kJP];
+      const double v = L.S[cur][e / kJP][e % kJP] * L.S[cur][e / kJP][e % kJP];
       tot += v;
       if (e / kJP != e % kJP) off += v;
     }
     off = jac_block_sum(off, L.red);
     tot = jac_block_sum(tot, L.red);
     if (off <= kJacTol2 * tot) break;   // the same value in every thread
-    jac_inner_sweep(L);
+    cur = jac_inner_sweep(L, cur);
   }
   for (int e = t; e < kJP * kJP; e += kJT) {
-    A[e] = L.S[e / kJP][e % kJP];
+    A[e] = L.S[cur][e / kJP][e % kJP];
     V[e] = L.Q[e / kJP][e % kJP];
   }
 }
