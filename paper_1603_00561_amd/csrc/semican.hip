@@ -16,9 +16,10 @@
 // entries stay exactly zero), so they keep their unit eigenvectors. After
 // each sweep the off-diagonal norm is compared with the whole norm (partial
 // sums over 64 workgroups, added in order) and a device flag is set when
-// their ratio is below 1e-14; the launches of the
-// remaining sweeps (at most kMaxSweeps in all) then return at once (the
-// matrix update only copies), so nothing waits on the host. Blocks of at most
+// their ratio is below 1e-14, recording which of the two matrix buffers holds
+// the converged matrix; the launches of the remaining sweeps (at most
+// kMaxSweeps in all) then return at once, so nothing waits on the host, and
+// the final ordering reads the buffer the flag names. Blocks of at most
 // 32 orbitals are solved in one
 // workgroup with inner sweeps repeated to the same criterion. The eigenvalues
 // are finally ranked (ascending) and each eigenvector signed so that its
@@ -171,10 +172,9 @@ __global__ __launch_bounds__(kJT) void jac_pair_kernel(const double *__restrict_
 
 // one launch per round for both updates: workgroups (x, y < npairs) form
 // Anew[P, P'] = Q_P^T Aold[P, P'] Q_P' for the pairs P = x, P' = y of round r
-// (the pairs cover every block, so Anew is written whole; once converged the
-// blocks are copied unchanged); workgroups (x, y >= npairs) rotate the
-// eigenvector columns of pair x in the kJP-row tile y - npairs,
-// V[rows, P] <- V[rows, P] Q_P (nothing once converged)
+// (the pairs cover every block, so Anew is written whole); workgroups
+// (x, y >= npairs) rotate the eigenvector columns of pair x in the kJP-row
+// tile y - npairs, V[rows, P] <- V[rows, P] Q_P. Nothing once converged.
 __global__ __launch_bounds__(kJT) void jac_update_kernel(const double *__restrict__ Aold,
                                                          double *__restrict__ Anew,
                                                          double *__restrict__ V, int64_t npad,
@@ -188,8 +188,8 @@ __global__ __launch_bounds__(kJT) void jac_update_kernel(const double *__restric
   int I, J;
   circle_pair(nb, r, blockIdx.x, I, J);
   const double *QP = Qall + (int64_t)blockIdx.x * kJP * kJP;
+  if (*done) return;   // converged: the flag names the buffer that holds the matrix
   if ((int)blockIdx.y >= npairs) {   // eigenvector columns
-    if (*done) return;
     const int64_t r0 = (int64_t)(blockIdx.y - npairs) * kJP;
     for (int e = t; e < kJP * kJP; e += kJT) {
       const int a = e / kJP, b = e % kJP;
@@ -216,13 +216,6 @@ __global__ __launch_bounds__(kJT) void jac_update_kernel(const double *__restric
   }
   int K, M;
   circle_pair(nb, r, blockIdx.y, K, M);
-  if (*done) {
-    for (int e = t; e < kJP * kJP; e += kJT) {
-      const int64_t g = pair_index(I, J, e / kJP) * npad + pair_index(K, M, e % kJP);
-      Anew[g] = Aold[g];
-    }
-    return;
-  }
   const double *QQ = Qall + (int64_t)blockIdx.y * kJP * kJP;
   for (int e = t; e < kJP * kJP; e += kJT) {
     const int a = e / kJP, b = e % kJP;
@@ -283,7 +276,7 @@ __device__ double jac_block_sum(double v, double *red) {
 // convergence check, in two launches: kJacParts workgroups each sum the
 // squared off-diagonal and all squared entries of a strided share of the rows
 // into part[2 * wg]; one workgroup adds the partial sums in order and sets
-// done = (off <= tol2 * all)
+// done = 1 + which (the index of the buffer checked) when off <= tol2 * all
 constexpr int kJacParts = (int)kSemicanParts;
 
 __global__ __launch_bounds__(kJT) void jac_check_part_kernel(const double *__restrict__ A,
@@ -307,14 +300,15 @@ __global__ __launch_bounds__(kJT) void jac_check_part_kernel(const double *__res
   }
 }
 
-__global__ void jac_check_final_kernel(const double *__restrict__ part, int *__restrict__ done) {
+__global__ void jac_check_final_kernel(const double *__restrict__ part, int which,
+                                       int *__restrict__ done) {
   if (threadIdx.x != 0 || *done) return;
   double off = 0.0, tot = 0.0;
   for (int k = 0; k < kJacParts; ++k) {
     off += part[2 * k];
     tot += part[2 * k + 1];
   }
-  if (off <= kJacTol2 * tot) *done = 1;
+  if (off <= kJacTol2 * tot) *done = 1 + which;
 }
 
 // blocks of at most kJP orbitals (npad == kJP): inner sweeps in one workgroup
@@ -365,8 +359,12 @@ __global__ __launch_bounds__(256) void semican_init_kernel(const double *__restr
 
 // eigenvalue i (one workgroup each) goes to position rank(i) of the block
 // (ascending, ties by index); its eigenvector, signed so that its largest
-// component (the first such) is positive, to column o + rank(i) of U
-__global__ __launch_bounds__(kJT) void jac_finalize_kernel(const double *__restrict__ A,
+// component (the first such) is positive, to column o + rank(i) of U. The
+// matrix is read from buffer A1 if the convergence flag (when given) names
+// it, else from buffer cur when the flag is absent or unset.
+__global__ __launch_bounds__(kJT) void jac_finalize_kernel(const double *__restrict__ A0,
+                                                           const double *__restrict__ A1,
+                                                           int cur, const int *__restrict__ done,
                                                            const double *__restrict__ V,
                                                            int64_t npad, int64_t n, int64_t o,
                                                            int64_t nmo, double *__restrict__ U,
@@ -376,6 +374,8 @@ __global__ __launch_bounds__(kJT) void jac_finalize_kernel(const double *__restr
   __shared__ int64_t bi[kJT];
   const int t = threadIdx.x;
   const int64_t i = blockIdx.x;
+  const int flag = done ? *done : 0;
+  const double *__restrict__ A = (flag ? flag == 2 : cur == 1) ? A1 : A0;
   const double lam = A[i * npad + i];
   double cnt = 0.0, best = -1.0;
   int64_t bidx = 0;
@@ -448,12 +448,12 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
         }
         hipLaunchKernelGGL(jac_check_part_kernel, dim3(kJacParts), dim3(kJT), 0, st, Ab[cur],
                            npad, Pt, done);
-        hipLaunchKernelGGL(jac_check_final_kernel, dim3(1), dim3(64), 0, st, Pt, done);
+        hipLaunchKernelGGL(jac_check_final_kernel, dim3(1), dim3(64), 0, st, Pt, cur, done);
       }
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(jac_finalize_kernel, dim3((unsigned)n), dim3(kJT), 0, st, Ab[cur], V,
-                       npad, n, o, nmo, U, eps);
+    hipLaunchKernelGGL(jac_finalize_kernel, dim3((unsigned)n), dim3(kJT), 0, st, Ab[0], Ab[1],
+                       cur, npad == kJP ? nullptr : done, V, npad, n, o, nmo, U, eps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     timer_end(st);
     o += n;
