@@ -513,57 +513,73 @@ __global__ __launch_bounds__(kLeafT) void chol_inv_leaf_kernel(const double *__r
     const int bf = (j >> 1) & 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // columns j, j + 1 and rows j, j + 1 of b, as they stand
-      const int jj = j + h, jb = jj >> 4, jr = jj & 15;
+      const int jj = j + h, jb = jj >> 4, jr = jj & 15;   // jb is the same in every thread
       if (tx == jr) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          double v = e[a][0];
-#pragma unroll
-          for (int b = 1; b < 4; ++b) v = (b == jb) ? e[a][b] : v;
-          col[bf][h][ty + 16 * a] = v;
+        switch (jb) {
+#define DSRG_LEAF_COL(B)                                                    \
+  case B:                                                                   \
+    _Pragma("unroll") for (int a = 0; a < 4; ++a) col[bf][h][ty + 16 * a] = e[a][B]; \
+    break;
+          DSRG_LEAF_COL(0)
+          DSRG_LEAF_COL(1)
+          DSRG_LEAF_COL(2)
+          DSRG_LEAF_COL(3)
+#undef DSRG_LEAF_COL
         }
       }
       if (ty == jr) {
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          double v = x[0][b];
-#pragma unroll
-          for (int a = 1; a < 4; ++a) v = (a == jb) ? x[a][b] : v;
-          row[bf][h][tx + 16 * b] = v;
+        switch (jb) {
+#define DSRG_LEAF_ROW(A)                                                    \
+  case A:                                                                   \
+    _Pragma("unroll") for (int b = 0; b < 4; ++b) row[bf][h][tx + 16 * b] = x[A][b]; \
+    break;
+          DSRG_LEAF_ROW(0)
+          DSRG_LEAF_ROW(1)
+          DSRG_LEAF_ROW(2)
+          DSRG_LEAF_ROW(3)
+#undef DSRG_LEAF_ROW
         }
       }
     }
     __syncthreads();
-    const double d1 = sqrt(col[bf][0][j]);
-    const double rd1 = 1.0 / d1;
-    const double l10 = col[bf][0][j + 1] * rd1;
-    const double d2 = sqrt(col[bf][1][j + 1] - l10 * l10);
-    const double rd2 = 1.0 / d2;
-    double ci0[4], ci1[4], cl0[4], cl1[4], rx0[4], rx1[4];
+    // only the reciprocals of the pivots are used: with the pivot block
+    // [[p, q], [q, r]], rd1 = 1 / sqrt(p), l = q rd1 and
+    // rd2 = 1 / sqrt(r - l^2) = p rd1 / sqrt(p r - q^2); the two inverse
+    // square roots do not wait for each other
+    const double pp = col[bf][0][j], pq = col[bf][0][j + 1], pr = col[bf][1][j + 1];
+    const double rd1 = rsqrt(pp);
+    const double rdet = rsqrt(fma(pp, pr, -pq * pq));
+    const double l10 = pq * rd1;
+    const double rd2 = (pp * rd1) * rdet;
+    double ci0[4], ci1[4], cl0[4], cl1[4], rx0[4], sc[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       const int i = ty + 16 * a;
       const double L0 = col[bf][0][i] * rd1;
       ci0[a] = (i > j) ? L0 : 0.0;
       ci1[a] = (i > j + 1) ? (col[bf][1][i] - L0 * l10) * rd2 : 0.0;
+      // rows j and j + 1 of b become rows of X: b_j / d1 and (b_{j+1} - l X_j) / d2
+      sc[a] = (i == j) ? rd1 : ((i == j + 1) ? rd2 : 1.0);
     }
+    // columns l <= j + 1 of the trailing matrix are finished and never read
+    // again, so the column factors need no mask
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int l = tx + 16 * b;
       const double L0 = col[bf][0][l] * rd1;
-      cl0[b] = (l > j) ? L0 : 0.0;
-      cl1[b] = (l > j + 1) ? (col[bf][1][l] - L0 * l10) * rd2 : 0.0;
+      cl0[b] = L0;
+      cl1[b] = (col[bf][1][l] - L0 * l10) * rd2;
       rx0[b] = row[bf][0][l] * rd1;
-      rx1[b] = (row[bf][1][l] - l10 * rx0[b]) * rd2;
     }
+    double rx1[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rx1[b] = fma(-l10, rx0[b], row[bf][1][tx + 16 * b]) * rd2;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      const int i = ty + 16 * a;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         e[a][b] = fma(-ci1[a], cl1[b], fma(-ci0[a], cl0[b], e[a][b]));
-        const double upd = fma(-ci1[a], rx1[b], fma(-ci0[a], rx0[b], x[a][b]));
-        x[a][b] = (i == j) ? rx0[b] : ((i == j + 1) ? rx1[b] : upd);
+        x[a][b] = fma(-ci1[a], rx1[b], fma(-ci0[a], rx0[b], x[a][b])) * sc[a];
       }
     }
   }
