@@ -268,6 +268,14 @@ const char *dsrg_df_last_error(void);
  * (-1 if an event could not be read). Entries are in launch order. */
 int dsrg_df_kernel_times(double *ms, const char **names, int cap);
 
+/* Restricts the kernels that DSRG_OPT_KERNEL_TIMING records on the calling
+ * thread to those named in `names`, a comma-separated list of the names
+ * dsrg_df_kernel_times() reports (e.g. "ccvv_fp64"); NULL or "" records every
+ * kernel again. Fewer event pairs leave the timed calls closer to their
+ * untimed cost. The list is copied; DSRG_ERR_ARG if it is 256 characters or
+ * longer (the filter is then unchanged). */
+dsrg_status dsrg_df_timing_filter(const char *names);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int dsrg_df_version(void);
 

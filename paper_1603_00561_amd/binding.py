@@ -28,7 +28,8 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward
             "dsrg_df_factors_workspace_size", "dsrg_df_factors",
             "dsrg_df_fock_workspace_size", "dsrg_df_fock",
             "dsrg_df_semicanonicalize_workspace_size", "dsrg_df_semicanonicalize",
-            "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_version")
+            "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_timing_filter",
+            "dsrg_df_version")
 
 
 class DsrgError(RuntimeError):
@@ -116,6 +117,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_kernel_times.argtypes = [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_char_p), i32]
     lib.dsrg_df_kernel_times.restype = i32
+    lib.dsrg_df_timing_filter.argtypes = [ctypes.c_char_p]
+    lib.dsrg_df_timing_filter.restype = i32
     lib.dsrg_df_version.argtypes = []
     lib.dsrg_df_version.restype = i32
     _lib = lib
@@ -142,6 +145,17 @@ def kernel_times(cap: int = 32):
     if n < 0:
         raise DsrgError(DSRG_ERR_HIP, "could not read kernel timing events")
     return [(names[k].decode(), ms[k]) for k in range(min(n, cap))]
+
+
+def timing_filter(names: Optional[Sequence[str]] = None) -> None:
+    """Record only the named kernels (names as kernel_times reports them) in
+    later calls made with timing=True on this thread; None or () records
+    every kernel again."""
+    lib = load_library()
+    arg = ",".join(names).encode() if names else None
+    st = lib.dsrg_df_timing_filter(arg)
+    if st != 0:
+        raise DsrgError(st, lib.dsrg_df_last_error().decode())
 
 
 def _terms_mask(terms: Union[str, int, Sequence[str]], atomic: bool, timing: bool = False) -> int:

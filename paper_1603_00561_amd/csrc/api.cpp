@@ -23,17 +23,34 @@ dsrg_status fail(dsrg_status code, const char *fmt, ...) {
 }
 
 // ---- per-kernel timing: one table per host thread ----
-// Calls that set DSRG_OPT_KERNEL_TIMING append an event pair per kernel;
+// Calls that set DSRG_OPT_KERNEL_TIMING append an event pair per kernel
+// (only the kernels the filter names, when one is set);
 // dsrg_df_kernel_times() reads and clears the table.
 struct TimerTable {
   static constexpr int kMax = 512;
+  static constexpr int kFilter = 256;
   hipEvent_t ev[2 * kMax] = {};
   const char *name[kMax] = {};
   int n = 0;          // kernels recorded since the last read
   int created = 0;    // events created so far
   int device = -1;
   bool active = false;
+  bool skip = false;  // the kernel between timer_begin and timer_end is not recorded
+  char filter[kFilter] = {};   // comma-separated kernel names; empty: every kernel
 };
+
+// name is one of the comma-separated entries of list
+bool in_list(const char *list, const char *name) {
+  const size_t len = strlen(name);
+  for (const char *p = list; *p;) {
+    const char *q = strchr(p, ',');
+    const size_t n = q ? (size_t)(q - p) : strlen(p);
+    if (n == len && strncmp(p, name, n) == 0) return true;
+    if (!q) break;
+    p = q + 1;
+  }
+  return false;
+}
 thread_local TimerTable g_timer;
 
 void timer_reset(bool on) {
@@ -395,7 +412,8 @@ dsrg_status make_df_plan(const dsrg_dfgen_problem *p, dsrg::DFPlan &pl) {
 namespace dsrg {
 void timer_begin(const char *name, hipStream_t st) {
   TimerTable &t = g_timer;
-  if (!t.active || t.n >= TimerTable::kMax) return;
+  t.skip = t.active && t.filter[0] != '\0' && !in_list(t.filter, name);
+  if (!t.active || t.skip || t.n >= TimerTable::kMax) return;
   while (t.created < 2 * (t.n + 1)) {
     if (hipEventCreate(&t.ev[t.created]) != hipSuccess) {
       t.active = false;
@@ -408,6 +426,10 @@ void timer_begin(const char *name, hipStream_t st) {
 }
 void timer_end(hipStream_t st) {
   TimerTable &t = g_timer;
+  if (t.skip) {
+    t.skip = false;
+    return;
+  }
   if (!t.active || t.n >= TimerTable::kMax) return;
   (void)hipEventRecord(t.ev[2 * t.n + 1], st);
   ++t.n;
@@ -741,6 +763,20 @@ int dsrg_df_kernel_times(double *ms, const char **names, int cap) {
     if (names) names[k] = t.name[k];
   }
   return n;
+}
+
+dsrg_status dsrg_df_timing_filter(const char *names) {
+  g_err[0] = '\0';
+  TimerTable &t = g_timer;
+  if (!names) {
+    t.filter[0] = '\0';
+    return DSRG_OK;
+  }
+  if (strlen(names) >= sizeof(t.filter))
+    return fail(DSRG_ERR_ARG, "timing filter longer than %d characters",
+                (int)sizeof(t.filter) - 1);
+  strcpy(t.filter, names);
+  return DSRG_OK;
 }
 
 int dsrg_df_version(void) { return 100; }

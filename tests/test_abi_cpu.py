@@ -146,6 +146,21 @@ def test_last_error_is_cleared_by_a_good_call(lib):
     assert lib.dsrg_df_last_error().decode() == ""
 
 
+def test_timing_filter_is_host_only_and_bounded(lib):
+    # setting and clearing the filter touches no device; an over-long list is
+    # refused and leaves the filter as it was
+    assert lib.dsrg_df_timing_filter(b"ccvv_fp64,cavv_fp64_x") == 0
+    assert lib.dsrg_df_timing_filter(b"x" * 300) == b.DSRG_ERR_ARG
+    assert "255" in lib.dsrg_df_last_error().decode()
+    assert lib.dsrg_df_timing_filter(b"") == 0
+    assert lib.dsrg_df_timing_filter(None) == 0
+    assert lib.dsrg_df_last_error().decode() == ""
+    b.timing_filter(["ccvv_fp64"])
+    b.timing_filter(None)
+    with pytest.raises(b.DsrgError):
+        b.timing_filter(["y" * 300])
+
+
 def test_python_binding_refuses_cpu_tensors():
     import torch
     from paper_1603_00561_amd.workloads import make_problem

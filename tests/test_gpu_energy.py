@@ -136,6 +136,29 @@ def test_deterministic_reduction_is_bitwise_reproducible_and_atomic_agrees():
     assert np.all(np.abs(Ea - E1) <= 1e-14 * np.abs(E1))
 
 
+def test_timing_records_every_kernel_or_only_the_filtered_ones():
+    p = make_problem(5, 2, 120, 50, seed=11)
+    t = _dev(p)
+    b = _b()
+    E0 = b.energy(*t, p.s).cpu().numpy()
+    b.kernel_times(1)   # clear the record
+    try:
+        E1 = b.energy(*t, p.s, timing=True).cpu().numpy()
+        every = [n for n, _ in b.kernel_times(64)]
+        assert {"ccvv_fp64", "cavv_fp64_x", "finalize"} <= set(every), every
+        b.timing_filter(["ccvv_fp64"])
+        E2 = b.energy(*t, p.s, timing=True).cpu().numpy()
+        only = b.kernel_times(64)
+        assert [n for n, _ in only] == ["ccvv_fp64"], only
+        assert only[0][1] > 0.0
+    finally:
+        b.timing_filter(None)
+    E3 = b.energy(*t, p.s, timing=True).cpu().numpy()
+    assert [n for n, _ in b.kernel_times(64)] == every
+    for E in (E1, E2, E3):   # timing changes no result
+        assert np.array_equal(E, E0)
+
+
 def test_non_default_stream_and_caller_workspace():
     p = make_problem(5, 2, 120, 50, seed=10)
     t = _dev(p)
