@@ -115,13 +115,59 @@ def dfgen_alg_bytes(nao, naux, nc, na, nv):
             "apply": 8.0 * (naux * naux / 2.0 + 2.0 * naux * npp * nq)}
 
 
-def stage_roofline(avg, stages):
+def kernel_table(binding, torch, call, n):
+    """Average duration per launch of every kernel (HIP events), from n calls
+    of call(True) made outside the timed region."""
+    binding.kernel_times(1)
+    for _ in range(n):
+        call(True)
+    torch.cuda.synchronize()
+    per = {}
+    for name, ms in binding.kernel_times(4096):
+        per.setdefault(name, []).append(ms)
+    return {k: float(np.mean(v)) for k, v in per.items()}
+
+
+def timed_region(binding, torch, call, steps, names):
+    """Wall time per call over `steps` calls of call(True), with HIP events
+    around the named kernels only; returns (ms per call, average ms per launch
+    of the named kernels)."""
+    binding.kernel_times(1)
+    binding.timing_filter(names)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = binding.kernel_times(4096)
+    finally:
+        binding.timing_filter(None)
+    launches = [ms for name, ms in kt if name in names]
+    return (t1 - t0) * 1e3 / steps, (float(np.mean(launches)) if launches else None)
+
+
+def table_steps(args):
+    return max(1, min(args.steps, 5))
+
+
+def table_note(args):
+    return ("every kernel timed with HIP events in %d calls outside the timed region, "
+            "which records the roofline kernel alone" % table_steps(args))
+
+
+def longest_stage(avg, stages):
+    return max(stages, key=lambda k: avg.get(k, 0.0))
+
+
+def stage_roofline(avg, stages, dom_ms=None):
     """Roofline of the longest single-launch stage: stages maps a timer name to
     its (algorithmic flops, algorithmic HBM bytes); the stage is priced against
     the FP64 matrix-core peak or the HBM peak, whichever its flops-to-bytes
-    ratio puts it under."""
-    dom = max(stages, key=lambda k: avg.get(k, 0.0))
-    dom_ms = avg.get(dom)
+    ratio puts it under. dom_ms: its launch time from the timed region."""
+    dom = longest_stage(avg, stages)
+    dom_ms = avg.get(dom) if dom_ms is None else dom_ms
     ops, nbytes = stages[dom]
     peak_f, peak_b = PEAK_TFLOPS["fp64"], PEAK_HBM_GBS
     if nbytes / (peak_b * 1e9) > ops / (peak_f * 1e12):
@@ -476,8 +522,7 @@ def main():
                                + " of " + "+".join(t.upper() for t in terms),
                    "precision": args.precision, "parallelism": "single-gpu"},
         "kernel_ms": avg,
-        "kernel_ms_from": "every kernel timed with HIP events in %d steps after the timed "
-                          "region, which times the roofline kernel alone" % max(1, min(args.steps, 5)),
+        "kernel_ms_from": table_note(args),
         "E_terms": [float(x) for x in Eg],
         "abs_err_vs_oracle": err,
         "roofline": roof,
@@ -500,24 +545,15 @@ def bench_active(args, p, binding, torch):
               t["gamma1"], p.s)
     nbytes = binding.active_workspace_size(p.nc, p.na, p.nv, p.naux)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    call = lambda timing: binding.energy_active(*args_t, out=F, workspace=ws,  # noqa: E731
+                                                timing=timing)
     for _ in range(args.warmup):
-        binding.energy_active(*args_t, out=F, workspace=ws)
+        call(False)
     torch.cuda.synchronize()
-    binding.kernel_times(1)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        binding.energy_active(*args_t, out=F, workspace=ws, timing=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = binding.kernel_times(4096)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    per_kernel = {}
-    for name, ms in kt:
-        per_kernel.setdefault(name, []).append(ms)
-    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
-    Ftot, Fparts = active_alg_flops(p.nc, p.na, p.nv, p.naux)
+    avg = kernel_table(binding, torch, call, table_steps(args))
     dom = "cavv_fp64_x"   # the (xe|uf) producer of F4
-    dom_ms = avg.get(dom)
+    ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps, [dom])
+    Ftot, Fparts = active_alg_flops(p.nc, p.na, p.nv, p.naux)
     ach = Fparts["f4"] / (dom_ms * 1e-3) / 1e12 if dom_ms else None
     peak = PEAK_TFLOPS["fp64"]
     roof = {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
@@ -540,6 +576,7 @@ def bench_active(args, p, binding, torch):
                                f"s={p.s}, energy of F4+F5+F6+F7+F8",
                    "precision": "fp64", "parallelism": "single-gpu"},
         "kernel_ms": avg,
+        "kernel_ms_from": table_note(args),
         "F_terms": [float(x) for x in Fg],
         "abs_err_vs_oracle": err,
         "roofline": roof,
@@ -563,26 +600,24 @@ def bench_dfgen(args, binding, torch):
     nbytes = binding.df_factors_workspace_size(g.nao, g.C.shape[1], g.naux, g.nfrz, g.nc, g.na,
                                                g.nv)
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    res = {}
+
+    def call(timing):
+        res["f"] = binding.df_factors(ao3, J, C, g.nfrz, g.nc, g.na, g.nv, workspace=ws,
+                                      timing=timing)
     for _ in range(args.warmup):
-        f = binding.df_factors(ao3, J, C, g.nfrz, g.nc, g.na, g.nv, workspace=ws)
+        call(False)
     torch.cuda.synchronize()
-    binding.kernel_times(1)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        f = binding.df_factors(ao3, J, C, g.nfrz, g.nc, g.na, g.nv, workspace=ws, timing=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = binding.kernel_times(4096)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    per_kernel = {}
-    for name, ms in kt:
-        per_kernel.setdefault(name, []).append(ms)
-    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
     Ftot, Fparts = dfgen_alg_flops(g.nao, g.naux, g.nc, g.na, g.nv)
     Bparts = dfgen_alg_bytes(g.nao, g.naux, g.nc, g.na, g.nv)
-    roof = stage_roofline(avg, {"df_half1": (Fparts["half1"], Bparts["half1"]),
-                                "df_half2": (Fparts["half2"], Bparts["half2"]),
-                                "df_metric_apply": (Fparts["apply"], Bparts["apply"])})
+    stages = {"df_half1": (Fparts["half1"], Bparts["half1"]),
+              "df_half2": (Fparts["half2"], Bparts["half2"]),
+              "df_metric_apply": (Fparts["apply"], Bparts["apply"])}
+    avg = kernel_table(binding, torch, call, table_steps(args))
+    ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps,
+                                       [longest_stage(avg, stages)])
+    roof = stage_roofline(avg, stages, dom_ms)
+    f = res["f"]
     out = {
         "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
         "value": Ftot / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
@@ -593,6 +628,7 @@ def bench_dfgen(args, binding, torch):
                                f"nv={g.nv} nao={g.nao} naux={g.naux}, density-fitting factors",
                    "precision": "fp64", "parallelism": "single-gpu"},
         "kernel_ms": avg,
+        "kernel_ms_from": table_note(args),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -624,22 +660,15 @@ def bench_fock(args, binding, torch):
     for _ in range(args.warmup):
         F = call(False)
     torch.cuda.synchronize()
-    binding.kernel_times(1)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        F = call(True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = binding.kernel_times(4096)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    per_kernel = {}
-    for name, ms in kt:
-        per_kernel.setdefault(name, []).append(ms)
-    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
     Ftot, Fp, Bp = fock_alg_work(g.nao, g.naux, g.nfrz, g.nc, g.na, g.nv)
-    roof = stage_roofline(avg, {"fock_half1": (Fp["half1"], Bp["half1"]),
-                                "fock_half2": (Fp["half2"], Bp["half2"]),
-                                "fock_metric_apply": (Fp["apply"], Bp["apply"])})
+    stages = {"fock_half1": (Fp["half1"], Bp["half1"]),
+              "fock_half2": (Fp["half2"], Bp["half2"]),
+              "fock_metric_apply": (Fp["apply"], Bp["apply"])}
+    avg = kernel_table(binding, torch, call, table_steps(args))
+    ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps,
+                                       [longest_stage(avg, stages)])
+    roof = stage_roofline(avg, stages, dom_ms)
+    F = call(False)
     out = {
         "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
         "value": Ftot / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
@@ -650,6 +679,7 @@ def bench_fock(args, binding, torch):
                                f"nv={g.nv} nao={g.nao} naux={g.naux}, generalized Fock matrix",
                    "precision": "fp64", "parallelism": "single-gpu"},
         "kernel_ms": avg,
+        "kernel_ms_from": table_note(args),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -677,24 +707,19 @@ def bench_semican(args, binding, torch):
     C = d(g.C)
     shape = (g.nfrz, g.nc, g.na, g.nv)
     nmo = g.C.shape[1]
+    res = {}
+
+    def call(timing):
+        res["r"] = binding.semicanonicalize(F, *shape, C=C, timing=timing)
     for _ in range(args.warmup):
-        eps, U, Cs = binding.semicanonicalize(F, *shape, C=C)
+        call(False)
     torch.cuda.synchronize()
-    binding.kernel_times(1)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        eps, U, Cs = binding.semicanonicalize(F, *shape, C=C, timing=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kt = binding.kernel_times(4096)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    per_kernel = {}
-    for name, ms in kt:
-        per_kernel.setdefault(name, []).append(ms)
-    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
-    work = semican_alg_work(g.nao, *shape)
+    avg = kernel_table(binding, torch, call, table_steps(args))
     dom = max(avg, key=avg.get)
-    roof = {"bound": "latency", "kernel": dom, "avg_launch_ms": avg[dom],
+    ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps, [dom])
+    eps, U, Cs = res["r"]
+    work = semican_alg_work(g.nao, *shape)
+    roof = {"bound": "latency", "kernel": dom, "avg_launch_ms": dom_ms,
             "note": "a chain of Jacobi rounds (three launches each); frac is the whole step's "
                     "conventional work rate against the FP64 matrix-core peak",
             "achieved": work / (ms_per_step * 1e-3) / 1e12, "peak": PEAK_TFLOPS["fp64"],
@@ -710,6 +735,7 @@ def bench_semican(args, binding, torch):
                                f"nv={g.nv} nao={g.nao}, semicanonical rotation of the generalized "
                                "Fock matrix", "precision": "fp64", "parallelism": "single-gpu"},
         "kernel_ms": avg,
+        "kernel_ms_from": table_note(args),
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
