@@ -136,7 +136,9 @@ dsrg_status dsrg_df_energy(const dsrg_df_problem *p, int precision, int terms,
  *   deps_c, deps_a, deps_v  device [nc], [na], [nv]
  *   ds                   device [1]
  *   E_terms              optional device [3] (NULL = not wanted): the energies
- * Terms outside `terms` contribute nothing. */
+ * Terms outside `terms` contribute nothing. dB and the energies are bitwise
+ * reproducible run to run; deps_* and ds are summed with FP64 atomics and
+ * can differ in the last bits between runs. */
 dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int terms,
                                     const double *gE,
                                     double *dB_cv, double *dB_ca, double *dB_av,
