@@ -172,6 +172,15 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       pl.off_j = off;
       off = align256(off + sizeof(double) *
                                (size_t)(pl.nc * pl.ntv * kPanel) * (size_t)pl.ccav_cols);
+      // with few 64-row panels (nc ntv of them) the contraction is split over
+      // auxiliary segments, summed in a fixed order, to fill the chip
+      const int64_t nseg = j_segments(pl.nc * pl.ntv, pl.ccav_cols, pl.naux_p);
+      if (nseg > 1) {
+        pl.ccav_split = true;
+        pl.off_jscr = off;
+        off = align256(off + sizeof(double) * (size_t)nseg *
+                                 (size_t)(pl.nc * pl.ntv * kPanel) * (size_t)pl.ccav_cols);
+      }
     }
   }
   pl.off_s8c = pl.off_s8a = pl.off_sigc = pl.off_siga = pl.off_diag = pl.off_xb = pl.off_scr =

@@ -452,7 +452,8 @@ template <int NA>
 static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hipStream_t st,
                                  double *slots, double *acc) {
   hipError_t e = launch_j_fp64(ws_d(ws, pl.off_pcv), pl.nc * pl.ntv, ws_d(ws, pl.off_pca),
-                               pl.ccav_cols, pl.naux_p, ws_d(ws, pl.off_j), nullptr, st);
+                               pl.ccav_cols, pl.naux_p, ws_d(ws, pl.off_j),
+                               pl.ccav_split ? ws_d(ws, pl.off_jscr) : nullptr, st);
   if (e != hipSuccess) return e;
   CcavEpiArgs a;
   a.nc = (int)pl.nc;

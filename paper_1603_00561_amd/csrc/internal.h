@@ -54,6 +54,8 @@ struct Plan {
   // workspace layout (byte offsets, 256-aligned)
   size_t off_pcv, off_pav, off_pca;   // packed FP64 panels
   size_t off_j;                       // CCAV integrals (me|nu)
+  size_t off_jscr = 0;                // their per-segment partial sums (energy path)
+  bool ccav_split = false;            // the CCAV contraction is split over Q segments
   // int8 slice path
   int64_t nqc;                        // chunks of 32 auxiliary indices
   int64_t cavv_mb;                    // core orbitals per CAVV integral batch
