@@ -660,6 +660,66 @@ __global__ __launch_bounds__(256) void df_scatter_kernel(const double *__restric
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// The metric factor depends on J alone, so the builds run it on a second
+// stream beside the two MO transforms: a latency-bound chain of small
+// launches next to two chip-filling products. One side stream (non-blocking,
+// default priority) and a fork / join event pair per host thread and device,
+// made on first use; the caller's stream waits for the join before anything
+// reads the factor, so the call still enqueues only on the caller's stream as
+// far as the caller can tell (and can be captured in a graph).
+// ---------------------------------------------------------------------------
+struct SideStream {
+  int device = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+thread_local SideStream g_side;
+
+static hipError_t side_stream(SideStream *&out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  SideStream &ss = g_side;
+  if (ss.device != dev) {
+    if (ss.s) {   // made on another device: that device's objects are dropped
+      (void)hipEventDestroy(ss.fork);
+      (void)hipEventDestroy(ss.join);
+      (void)hipStreamDestroy(ss.s);
+      ss = SideStream{};
+    }
+    if ((e = hipStreamCreateWithFlags(&ss.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&ss.join, hipEventDisableTiming)) != hipSuccess) return e;
+    ss.device = dev;
+  }
+  out = &ss;
+  return hipSuccess;
+}
+
+// Cholesky factor of J (in the copy Lm) and its inverse X = L^{-1} on the side
+// stream, after everything already enqueued on st; st waits for it only at
+// the join (side_join)
+static hipError_t metric_forked(const char *name, const double *J, double *Lm, double *X,
+                                double *W, int64_t naux, hipStream_t st, SideStream *&ss) {
+  hipError_t e = side_stream(ss);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(ss->fork, st)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
+  timer_begin(name, ss->s);
+  if ((e = hipMemcpyAsync(Lm, J, sizeof(double) * naux * naux, hipMemcpyDeviceToDevice,
+                          ss->s)) != hipSuccess)
+    return e;
+  if ((e = launch_zero_fill(X, naux * naux, ss->s)) != hipSuccess) return e;
+  if ((e = chol_inv(Lm, X, W, naux, 0, naux, ss->s)) != hipSuccess) return e;
+  timer_end(ss->s);
+  return hipEventRecord(ss->join, ss->s);
+}
+
+static hipError_t side_join(const SideStream *ss, hipStream_t st) {
+  return hipStreamWaitEvent(st, ss->join, 0);
+}
+
 hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutputs &o, void *ws,
                              hipStream_t st) {
   hipError_t e;
@@ -668,6 +728,10 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
   const int64_t oc = pl.nfrz, oa = pl.nfrz + pl.nc;
   double *T = ws_d(ws, pl.off_t), *Y = ws_d(ws, pl.off_y), *Lm = ws_d(ws, pl.off_l);
   double *X = ws_d(ws, pl.off_x), *W = ws_d(ws, pl.off_tmp), *Bf = ws_d(ws, pl.off_bf);
+  // the metric factor and inverse, beside the transforms (disjoint buffers:
+  // Lm, X, W there; T, Y here)
+  SideStream *ss = nullptr;
+  if ((e = metric_forked("df_metric", in.J, Lm, X, W, naux, st, ss)) != hipSuccess) return e;
   // T[P][p][nu] = sum_mu C[mu][oc + p] (mu nu|P), batched over P: the small
   // (core | active) index first, so the second step contracts nao over
   // naux np rows instead of naux nao
@@ -686,14 +750,7 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
              1, false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
-  // Cholesky factor of J (in a copy) and its inverse X = L^{-1}
-  timer_begin("df_metric", st);
-  if ((e = hipMemcpyAsync(Lm, in.J, sizeof(double) * naux * naux, hipMemcpyDeviceToDevice, st)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_zero_fill(X, naux * naux, st)) != hipSuccess) return e;
-  if ((e = chol_inv(Lm, X, W, naux, 0, naux, st)) != hipSuccess) return e;
-  timer_end(st);
+  if ((e = side_join(ss, st)) != hipSuccess) return e;
   // B[Q][(p q)] = sum_{P <= Q} X[Q][P] Y[P][(p q)]
   timer_begin("df_metric_apply", st);
   e = gemm_g(false, false, naux, np * nq, naux, 1.0, X, naux, 0, Y, np * nq, 0, 0.0, Bf, np * nq,
@@ -774,6 +831,10 @@ hipError_t launch_df_fock(const FockPlan &pl, const FockInputs &in, double *F, v
   double *X = ws_d(ws, pl.off_x), *W = ws_d(ws, pl.off_w), *Bo = ws_d(ws, pl.off_bo);
   double *dv = ws_d(ws, pl.off_d), *cv = ws_d(ws, pl.off_c), *Jao = ws_d(ws, pl.off_jao);
   double *Tj = ws_d(ws, pl.off_tj), *Part = ws_d(ws, pl.off_part);
+  // the metric factor and inverse, beside the transforms (Lm, X, W there;
+  // T, Y here)
+  SideStream *ss = nullptr;
+  if ((e = metric_forked("fock_metric", in.J, Lm, X, W, naux, st, ss)) != hipSuccess) return e;
   // T[P][m][nu] = sum_mu C[mu][m] (mu nu|P), m occupied
   timer_begin("fock_half1", st);
   if (folded_fits(no, nao, naux))
@@ -790,13 +851,7 @@ hipError_t launch_df_fock(const FockPlan &pl, const FockInputs &in, double *F, v
              false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
-  timer_begin("fock_metric", st);
-  if ((e = hipMemcpyAsync(Lm, in.J, sizeof(double) * naux * naux, hipMemcpyDeviceToDevice, st)) !=
-      hipSuccess)
-    return e;
-  if ((e = launch_zero_fill(X, naux * naux, st)) != hipSuccess) return e;
-  if ((e = chol_inv(Lm, X, W, naux, 0, naux, st)) != hipSuccess) return e;
-  timer_end(st);
+  if ((e = side_join(ss, st)) != hipSuccess) return e;
   // B[Q][(m q)] = sum_{P <= Q} X[Q][P] Y[P][(m q)]
   timer_begin("fock_metric_apply", st);
   e = gemm_g(false, false, naux, no * nmo, naux, 1.0, X, naux, 0, Y, no * nmo, 0, 0.0, Bo,
