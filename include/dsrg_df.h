@@ -30,7 +30,11 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Calls only enqueue work on it: they never synchronise and never
  *     allocate device memory. The caller keeps inputs, outputs and the
- *     workspace alive until that work completes.
+ *     workspace alive until that work completes. (dsrg_df_factors and
+ *     dsrg_df_fock run the metric factor on one internal stream per host
+ *     thread and device, forked from `stream` and joined back to it with
+ *     events before anything reads it: to the caller their work is ordered
+ *     on `stream`, and capturing `stream` in a graph captures it.)
  *   - Outputs are overwritten, never accumulated into.
  *   - Every argument is validated on the host before anything is enqueued.
  *     On any error the call returns a non-zero status, enqueues nothing and
