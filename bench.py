@@ -461,7 +461,8 @@ def main():
     binding.kernel_times(1)   # clear the record
 
     # timed region: HIP events around the roofline kernel's launches only (an
-    # event pair around every kernel adds about 3 % to a cfg2 step)
+    # event pair around every kernel adds about 3 % to the energy step at
+    # nc = 23, nv = 380, naux = 1100)
     binding.timing_filter(dom_names)
     try:
         torch.cuda.synchronize()
