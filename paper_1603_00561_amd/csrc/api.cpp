@@ -227,6 +227,29 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       pl.off_g3 = off;
       off = align256(off + sizeof(double) * Np * (size_t)(pl.nc * kActPanel));
     }
+    if (!split) {
+      // the FP64 adjoint products with too few output tiles are split over K
+      // into segments (partial products summed in a fixed order): room for
+      // the largest. Shapes (ncols, GP, nvalid, K) as the products take them.
+      const int64_t np = (int64_t)Np, gp = pl.ntv * kPanel, kcv = pl.nc * pl.ntv * kPanel;
+      const int64_t n2 = pl.na * pl.ntv * kPanel, n3 = pl.nc * kActPanel;
+      const int64_t shapes[5][4] = {{np, gp, pl.nv, kcv},
+                                    {np, gp, pl.nv, pl.na * pl.ntv * kPanel},
+                                    {n2, gp, pl.nv, kcv},
+                                    {np, gp, pl.nv, pl.nc * kActPanel},
+                                    {n3, kActPanel, pl.na, kcv}};
+      int64_t most = 0;
+      for (const auto &sh : shapes) {
+        if (sh[0] <= 0 || sh[3] <= 0) continue;
+        const int64_t nseg = adj_segments(pl.naux, sh[0], sh[3]);
+        if (nseg > 1) most = std::max(most, nseg * pl.naux * adj_out_cols(sh[0], sh[1], sh[2]));
+      }
+      if (most > 0) {
+        pl.off_gpart = off;
+        pl.gpart_doubles = most;
+        off = align256(off + sizeof(double) * (size_t)most);
+      }
+    }
   }
   pl.off_SA1 = pl.off_SA2 = pl.off_SB = pl.off_sigA1 = pl.off_sigA2 = pl.off_sigB =
       pl.off_opmax = off;

@@ -310,6 +310,8 @@ struct GemmArgs {
   int64_t ldg;
   int64_t GP, nvalid, ldc;
   int accumulate;
+  int64_t kseg;      // contraction indices per segment (blockIdx.z), a multiple of kGK
+  int64_t zstride;   // doubles between the outputs of two segments
 };
 
 constexpr int kGT = 128, kGK = 16, kGA = kGK + 1, kGThreads = 512;
@@ -322,6 +324,10 @@ __global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *
   __shared__ double sA[2][kGT * kGA];
   __shared__ double sB[2][kGK * kGT];
   const int64_t Q0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+  // this workgroup's segment of the contraction, [kb, ke)
+  const int64_t kb = (int64_t)blockIdx.z * a.kseg;
+  const int64_t ke = (kb + a.kseg < a.K) ? kb + a.kseg : a.K;
+  C += (int64_t)blockIdx.z * a.zstride;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wr = wave >> 2, wc = wave & 3;
@@ -385,12 +391,12 @@ __global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *
     }
   };
 
-  gload(0);
+  gload(kb);
   sstore(0);
-  if (a.K > kGK) gload(kGK);
+  if (kb + kGK < ke) gload(kb + kGK);
   __syncthreads();
   int b = 0;
-  for (int64_t k0 = 0; k0 < a.K; k0 += kGK) {
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
     const double *LA = sA[b], *LB = sB[b];
 #pragma unroll
     for (int kk = 0; kk < kGK / 4; ++kk) {
@@ -405,9 +411,9 @@ __global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[p][q] = mfma64(fa[p], fb[q], acc[p][q]);
     }
-    if (k0 + kGK < a.K) {
+    if (k0 + kGK < ke) {
       sstore(b ^ 1);
-      if (k0 + 2 * kGK < a.K) gload(k0 + 2 * kGK);
+      if (k0 + 2 * kGK < ke) gload(k0 + 2 * kGK);
     }
     __syncthreads();
     b ^= 1;
@@ -434,8 +440,28 @@ __global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// C[Q][col] (+)= sum over the segments z = 0 .. nseg-1 of P[z][Q][col], in that
+// order, for Q < rows, col < ncol
+__global__ __launch_bounds__(256) void adj_sum_kernel(const double *__restrict__ P, int nseg,
+                                                      int64_t rows, int64_t ncol,
+                                                      int64_t zstride, double *__restrict__ C,
+                                                      int64_t ldc, int accumulate) {
+  const int64_t n = rows * ncol;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * 256) {
+    double v = P[i];
+    for (int z = 1; z < nseg; ++z) v += P[z * zstride + i];
+    double *dst = C + (i / ncol) * ldc + i % ncol;
+    *dst = accumulate ? *dst + v : v;
+  }
+}
+
+// C (+)= A Bm with A the packed panels (K = npan PW) and Bm = G (TB: G^T). A
+// product with too few 128 x 128 output tiles for the chip is split over K
+// (adj_segments) when the plan holds room for the partial products, which
+// adj_sum_kernel then adds in a fixed order.
 template <bool TB>
-static hipError_t gemm(const Plan &pl, const double *Apan, int PW, int64_t npan,
+static hipError_t gemm(const Plan &pl, void *ws, const double *Apan, int PW, int64_t npan,
                        const double *G, int64_t Ncols, int64_t ldg, int64_t GP, int64_t nvalid,
                        double *C, int64_t ldc, bool accumulate, hipStream_t st) {
   GemmArgs a;
@@ -449,9 +475,34 @@ static hipError_t gemm(const Plan &pl, const double *Apan, int PW, int64_t npan,
   a.nvalid = nvalid;
   a.ldc = ldc;
   a.accumulate = accumulate ? 1 : 0;
-  const dim3 grid((unsigned)ceil_div(pl.naux, kGT), (unsigned)ceil_div(Ncols, kGT));
+  a.kseg = a.K;
+  a.zstride = 0;
+  const int64_t ncol = adj_out_cols(Ncols, GP, nvalid);
+  int64_t nseg = adj_segments(pl.naux, Ncols, a.K);
+  if (nseg > 1) {
+    a.kseg = round_up(ceil_div(a.K, nseg), kGK);
+    nseg = ceil_div(a.K, a.kseg);
+  }
+  const bool split = nseg > 1 && pl.gpart_doubles > 0 && nseg * pl.naux * ncol <= pl.gpart_doubles;
+  double *out = C;
+  if (split) {
+    out = ws_d(ws, pl.off_gpart);
+    a.ldc = ncol;
+    a.accumulate = 0;
+    a.zstride = pl.naux * ncol;
+  } else {
+    a.kseg = a.K;
+    nseg = 1;
+  }
+  const dim3 grid((unsigned)ceil_div(pl.naux, kGT), (unsigned)ceil_div(Ncols, kGT),
+                  (unsigned)nseg);
   timer_begin(TB ? "gemm_adj_tb_fp64" : "gemm_adj_fp64", st);
-  hipLaunchKernelGGL(gemm_adj_fp64_kernel<TB>, grid, dim3(kGThreads), 0, st, Apan, G, a, C);
+  hipLaunchKernelGGL(gemm_adj_fp64_kernel<TB>, grid, dim3(kGThreads), 0, st, Apan, G, a, out);
+  if (split) {
+    const int64_t blocks = std::min<int64_t>(ceil_div(pl.naux * ncol, 256), 4096);
+    hipLaunchKernelGGL(adj_sum_kernel, dim3((unsigned)blocks), dim3(256), 0, st, out, (int)nseg,
+                       pl.naux, ncol, a.zstride, C, ldc, accumulate ? 1 : 0);
+  }
   timer_end(st);
   return hipGetLastError();
 }
@@ -554,18 +605,18 @@ hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &
   const int64_t ldcv = pl.nc * pl.nv;
   bool first = true;
   if (pl.terms & 1) {
-    e = gemm<false>(pl, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_gs), Np,
+    e = gemm<false>(pl, ws, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_gs), Np,
                     Np, pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, false, st);
     if (e != hipSuccess) return e;
     first = false;
   }
   if (cavv) {
     const int64_t N2 = pl.na * pl.ntv * kPanel;
-    e = gemm<true>(pl, ws_d(ws, pl.off_pav), kPanel, pl.na * pl.ntv, ws_d(ws, pl.off_g2), Np,
+    e = gemm<true>(pl, ws, ws_d(ws, pl.off_pav), kPanel, pl.na * pl.ntv, ws_d(ws, pl.off_g2), Np,
                    N2, pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, !first, st);
     if (e != hipSuccess) return e;
     first = false;
-    e = gemm<false>(pl, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g2), N2,
+    e = gemm<false>(pl, ws, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g2), N2,
                     N2, pl.ntv * kPanel, pl.nv, o.dB_av, pl.na * pl.nv, false, st);
     if (e != hipSuccess) return e;
   } else if (o.dB_av) {
@@ -573,11 +624,11 @@ hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &
   }
   if (ccav) {
     const int64_t N3 = pl.nc * kActPanel;
-    e = gemm<true>(pl, ws_d(ws, pl.off_pca), kActPanel, pl.nc, ws_d(ws, pl.off_g3), Np, N3,
+    e = gemm<true>(pl, ws, ws_d(ws, pl.off_pca), kActPanel, pl.nc, ws_d(ws, pl.off_g3), Np, N3,
                    pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, !first, st);
     if (e != hipSuccess) return e;
     first = false;
-    e = gemm<false>(pl, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g3), N3,
+    e = gemm<false>(pl, ws, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g3), N3,
                     N3, kActPanel, pl.na, o.dB_ca, pl.nc * pl.na, false, st);
     if (e != hipSuccess) return e;
   } else if (o.dB_ca) {

@@ -33,6 +33,20 @@ inline int8_t *ws_b(void *ws, size_t off) {
   return reinterpret_cast<int8_t *>(static_cast<char *>(ws) + off);
 }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+// K segments of an FP64 adjoint product with a rows x ncols output (128 x 128
+// tiles): enough for about 1024 workgroups, each segment at least 512 long
+inline int64_t adj_segments(int64_t rows, int64_t ncols, int64_t K) {
+  const int64_t tiles = ceil_div(rows, 128) * ceil_div(ncols, 128);
+  int64_t n = ceil_div(1024, tiles > 0 ? tiles : 1);
+  if (n > K / 512) n = K / 512;
+  return n < 1 ? 1 : n;
+}
+// output columns of an adjoint product whose ncols columns come in groups of
+// GP of which the first nvalid are kept
+inline int64_t adj_out_cols(int64_t ncols, int64_t GP, int64_t nvalid) {
+  const int64_t rem = ncols % GP;
+  return (ncols / GP) * nvalid + (rem < nvalid ? rem : nvalid);
+}
 
 // Everything the launchers need, derived once on the host from the problem.
 struct Plan {
@@ -62,6 +76,8 @@ struct Plan {
   size_t off_s8c, off_s8a, off_sigc, off_siga, off_diag, off_xb, off_scr;
   size_t off_xs;                      // per-workgroup x slots of the int8 CCVV kernel, then its work counters
   size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
+  size_t off_gpart = 0;               // per-segment partial adjoint products (FP64 gradient)
+  int64_t gpart_doubles = 0;          // their capacity; 0: products are not split
   // int8 adjoint products (slice-path gradient): operand slices and scales
   size_t off_SA1, off_SA2, off_SB, off_sigA1, off_sigA2, off_sigB, off_opmax;
   size_t off_ctr;                     // eight per-XCD work counters (ints)
