@@ -227,8 +227,8 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       pl.off_g3 = off;
       off = align256(off + sizeof(double) * Np * (size_t)(pl.nc * kActPanel));
     }
-    if (!split) {
-      // the FP64 adjoint products with too few output tiles are split over K
+    {
+      // the adjoint products (FP64 or int8) with too few output tiles are split over K
       // into segments (partial products summed in a fixed order): room for
       // the largest. Shapes (ncols, GP, nvalid, K) as the products take them.
       const int64_t np = (int64_t)Np, gp = pl.ntv * kPanel, kcv = pl.nc * pl.ntv * kPanel;

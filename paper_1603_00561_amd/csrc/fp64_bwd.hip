@@ -456,6 +456,15 @@ __global__ __launch_bounds__(256) void adj_sum_kernel(const double *__restrict__
   }
 }
 
+// the same sum for the int8 adjoint products (split_bwd.hip)
+hipError_t launch_adj_sum(const double *P, int nseg, int64_t rows, int64_t ncol, int64_t zstride,
+                          double *C, int64_t ldc, bool accumulate, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>(ceil_div(rows * ncol, 256), 4096);
+  hipLaunchKernelGGL(adj_sum_kernel, dim3((unsigned)blocks), dim3(256), 0, st, P, nseg, rows,
+                     ncol, zstride, C, ldc, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
 // C (+)= A Bm with A the packed panels (K = npan PW) and Bm = G (TB: G^T). A
 // product with too few 128 x 128 output tiles for the chip is split over K
 // (adj_segments) when the plan holds room for the partial products, which

@@ -155,7 +155,9 @@ constexpr int64_t kGemmSeg = 32768;   // contraction indices per exact int32 seg
 struct I8GemmArgs {
   int64_t tA;                 // 128-row tiles of A
   int64_t nqc;                // 32-wide contraction chunks of the operand panels
-  int64_t qc0, nseg;          // chunks of this segment
+  int64_t qc0, nseg;          // chunks of this segment (segment blockIdx.y starts
+                              // segc chunks further; the last one may be shorter)
+  int64_t segc, zstride;      // with several segments: their length, output stride
   int64_t M;                  // valid rows of A
   int64_t Ncols, GP, nvalid;  // padded output columns, their block width, valid per block
   int64_t ldc;
@@ -178,10 +180,13 @@ __global__ __launch_bounds__(512) void i8_gemm_kernel(const int8_t *__restrict__
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 2, wc = wave & 3;
   const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
-  const int64_t off = a.qc0 * (int64_t)kSlicePanelChunk;
+  const int64_t qc0 = a.qc0 + (int64_t)blockIdx.y * a.segc;
+  const int64_t nsg = (a.nqc - qc0 < a.nseg) ? a.nqc - qc0 : a.nseg;
+  C += (int64_t)blockIdx.y * a.zstride;
+  const int64_t off = qc0 * (int64_t)kSlicePanelChunk;
   const int8_t *r0 = SA + 2 * ta * ps + off, *c0 = SB + 2 * tb * ps + off;
   i16v ac[kI8Blocks][kSlices];
-  i8_tile_product(r0, r0 + ps, c0, c0 + ps, (int)a.nseg, lds, ac, wr, wc, lane);
+  i8_tile_product(r0, r0 + ps, c0, c0 + ps, (int)nsg, lds, ac, wr, wc, lane);
 #pragma unroll
   for (int q = 0; q < kI8Blocks; ++q) {
     double v[16];
@@ -582,10 +587,18 @@ static hipError_t pack_operand(const OpMap &m, int64_t R, int64_t K, double *sig
   return hipGetLastError();
 }
 
+hipError_t launch_adj_sum(const double *P, int nseg, int64_t rows, int64_t ncol, int64_t zstride,
+                          double *C, int64_t ldc, bool accumulate, hipStream_t st);
+
+// C (+)= the exact int8 product, over K in segments of at most kGemmSeg. A
+// product with too few output tiles for the chip runs its segments side by
+// side (blockIdx.y, at most kGemmSeg long, at least 512) into partial
+// products in part (capacity part_doubles) that launch_adj_sum adds in a
+// fixed order; otherwise the segments follow each other, accumulating in C.
 static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, const int8_t *SB,
                           const double *sigB, int64_t RB, int64_t K, int64_t M, int64_t Ncols,
                           int64_t GP, int64_t nvalid, double *C, int64_t ldc, bool accumulate,
-                          hipStream_t st) {
+                          double *part, int64_t part_doubles, hipStream_t st) {
   I8GemmArgs a;
   a.tA = RA / kI8Tile;
   a.nqc = K / kQC;
@@ -594,8 +607,32 @@ static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, cons
   a.GP = GP;
   a.nvalid = nvalid;
   a.ldc = ldc;
+  a.segc = 0;
+  a.zstride = 0;
   const int64_t grid = a.tA * (RB / kI8Tile);
   const int64_t seg = kGemmSeg / kQC;
+  {
+    const int64_t want = adj_segments(M, Ncols, K);
+    const int64_t segc = std::min<int64_t>(seg, ceil_div(a.nqc, want));
+    const int64_t nz = ceil_div(a.nqc, segc);
+    const int64_t ncol = adj_out_cols(Ncols, GP, nvalid);
+    if (want > 1 && nz > 1 && part && nz * M * ncol <= part_doubles) {
+      a.qc0 = 0;
+      a.nseg = segc;
+      a.segc = segc;
+      a.ldc = ncol;
+      a.accumulate = 0;
+      a.zstride = M * ncol;
+      timer_begin("gemm_adj_i8", st);
+      hipLaunchKernelGGL(i8_gemm_kernel, dim3((unsigned)grid, (unsigned)nz), dim3(kI8Threads), 0,
+                         st, SA, sigA, SB, sigB, a, part);
+      hipError_t e = hipGetLastError();
+      if (e == hipSuccess)
+        e = launch_adj_sum(part, (int)nz, M, ncol, a.zstride, C, ldc, accumulate, st);
+      timer_end(st);
+      return e;
+    }
+  }
   for (int64_t q0 = 0; q0 < a.nqc; q0 += seg) {
     a.qc0 = q0;
     a.nseg = (a.nqc - q0 < seg) ? a.nqc - q0 : seg;
@@ -613,6 +650,7 @@ static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, cons
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                  hipStream_t st) {
   hipError_t e;
+  double *part = pl.gpart_doubles > 0 ? ws_d(ws, pl.off_gpart) : nullptr;   // split products
   const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
   // gradients of eps and s cleared, G3 (with its eps / s parts) from the FP64
   // adjoint tiles
@@ -673,7 +711,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const OpMap Bs = op_map(Gs, W, pl.nv, W, 1, Np, W, pl.nv, W * Np, Np, Np);
     if ((e = pack_operand(Bs, RB, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
     if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB, Np, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
-                     false, st)) != hipSuccess)
+                     false, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
     first = false;
   }
@@ -686,7 +724,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const OpMap B2t = op_map(G2, W, pl.nv, W * N2, N2, Np, W, pl.nv, W, 1, N2);
     if ((e = pack_operand(B2t, RB, N2, sigB, pmax, SB, st)) != hipSuccess) return e;
     if ((e = i8_gemm(SA2, sigA2, RA, SB, sigB, RB, N2, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
-                     !first, st)) != hipSuccess)
+                     !first, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
     first = false;
     // dB_av[Q][(w,f)] = sum_(m,e) B_cv[Q][(m,e)] G2[(m,e)][(w,f)]
@@ -694,7 +732,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const OpMap B2 = op_map(G2, W, pl.nv, W, 1, N2, W, pl.nv, W * N2, N2, Np);
     if ((e = pack_operand(B2, RB2, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
     if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB2, Np, pl.naux, N2, W, pl.nv, o.dB_av,
-                     pl.na * pl.nv, false, st)) != hipSuccess)
+                     pl.na * pl.nv, false, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
   } else if (o.dB_av) {
     if ((e = launch_zero_fill(o.dB_av, pl.naux * pl.na * pl.nv, st)) != hipSuccess) return e;
@@ -708,7 +746,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const OpMap B3t = op_map(G3, W, pl.nv, W * N3, N3, Np, kActPanel, pl.na, kActPanel, 1, N3);
     if ((e = pack_operand(B3t, RB, N3p, sigB, pmax, SB, st)) != hipSuccess) return e;
     if ((e = i8_gemm(SA2, sigA2, RA, SB, sigB, RB, N3p, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
-                     !first, st)) != hipSuccess)
+                     !first, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
     first = false;
     // dB_ca[Q][(n,u)] = sum_(m,e) B_cv[Q][(m,e)] G3[(m,e)][(n,u)]
@@ -716,7 +754,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const OpMap B3 = op_map(G3, kActPanel, pl.na, kActPanel, 1, N3, W, pl.nv, W * N3, N3, Np);
     if ((e = pack_operand(B3, RB3, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
     if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB3, Np, pl.naux, N3, kActPanel, pl.na, o.dB_ca,
-                     pl.nc * pl.na, false, st)) != hipSuccess)
+                     pl.nc * pl.na, false, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
   } else if (o.dB_ca) {
     if ((e = launch_zero_fill(o.dB_ca, pl.naux * pl.nc * pl.na, st)) != hipSuccess) return e;
