@@ -1,29 +1,38 @@
 """Throughput of the DF-DSRG-MRPT2 F1-F3 hot path on one MI355X.
 
-One step = one dsrg_df_energy call (panel packing, the CCVV, CAVV and CCAV
-contraction kernels with their fused regulariser epilogues, and the final
-reduction) on seeded synthetic inputs already resident in HBM.
+Default step: one dsrg_df_energy_backward call in FP64 on the largest
+workload (nc=23, na=6, nv=1100, naux=3000, s=0.5: quintuple-zeta-shaped),
+which recomputes the CCVV, CAVV and CCAV integral tiles, forms the three
+energies and every gradient (dE/dB, dE/deps, dE/ds) through the adjoint
+products, on seeded synthetic inputs already resident in HBM. The same
+workload is then timed on the int8 slice path (energy + gradient, and the
+energy alone for the CCVV slice kernel's rate) and reported under
+"compare".
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg2]
-                    [--precision fp64] [--no-cpu-baseline]
-                    [--grad | --active | --dfgen | --fock | --semican]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg5]
+                    [--precision fp64] [--energy] [--no-compare]
+                    [--no-cpu-baseline]
+                    [--active | --dfgen | --fock | --semican]
 
-With --active a step is one dsrg_df_energy_active call instead (the pieces
-F4-F8 of term F, FP64), measured the same way against its own algorithmic
-work (the contractions over Q that form its integrals). With --dfgen a step
-is one dsrg_df_factors call (the density-fitting factors B from AO
-three-index integrals, FP64) for the config's orbital spaces; with --fock one
-dsrg_df_fock call (the generalized Fock matrix of Eq. gen_fock from the same
-DF integrals, FP64); with --semican one dsrg_df_semicanonicalize call (the
-semicanonical rotation of that Fock matrix and C U, FP64).
+--energy times dsrg_df_energy alone. With --active a step is one
+dsrg_df_energy_active call instead (the pieces F4-F8 of term F, FP64),
+measured the same way against its own algorithmic work (the contractions
+over Q that form its integrals). With --dfgen a step is one dsrg_df_factors
+call (the density-fitting factors B from AO three-index integrals, FP64) for
+the config's orbital spaces; with --fock one dsrg_df_fock call (the
+generalized Fock matrix of Eq. gen_fock from the same DF integrals, FP64);
+with --semican one dsrg_df_semicanonicalize call (the semicanonical rotation
+of that Fock matrix and C U, FP64).
 
 Prints one JSON line. `value` is algorithmic TFLOP/s of the whole step:
 F_alg = 2 naux [nc(nc+1)/2 nv^2 + nc na nv^2 + nc^2 na nv] (the contractions
-the method must perform; epilogue exponentials are not counted) divided by
-the measured time per step. `roofline` reports the dominant kernel (CCVV)
-against the FP64 matrix-core peak, timed with HIP events on the stream it
-runs on. `cpu_baseline` times the CPU oracle on a bounded sample of the same
-workload on this host.
+the method must perform; epilogue exponentials are not counted), times 3 for
+energy + gradient, divided by the measured time per step. `roofline`
+reports the dominant kernel (the adjoint products with the gradient, the
+CCVV contraction for the energy) against the matrix-core peak of its
+datatype, timed with HIP events on the stream it runs on. `cpu_baseline`
+times the CPU oracle on a bounded sample of the same workload on this host,
+on every BLAS thread and on one.
 """
 import argparse
 import json
@@ -42,6 +51,9 @@ PEAK_HBM_GBS = 8000.0
 
 # int8 slice products per multiply-add of the slice path (four slices, levels <= 3)
 SLICE_PRODUCTS = 10.0
+# upstream weights dL/dE_t of the timed gradient (those of the stored oracle
+# gradient references, so the result can be checked against them)
+BENCH_GE = (1.0, 0.75, -0.5)
 
 
 def alg_flops(nc, na, nv, naux, terms=("ccvv", "cavv", "ccav")):
@@ -287,45 +299,94 @@ def cpu_baseline_dfgen(g, budget_s=20.0, f_gpu=None):
     return out
 
 
-def cpu_baseline(p, budget_s=20.0):
-    """Time the oracle on a bounded sample: whole terms while the budget
-    allows, core pairs / core orbitals of the CCVV and CAVV loops otherwise."""
-    import math
-    from oracle import dsrg_oracle as O
+def host_info():
+    """CPU model, logical CPU count and the BLAS library numpy calls."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    blas = None
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        for i in threadpool_info():
+            if i.get("user_api") == "blas":
+                blas = f"{i.get('internal_api')} {i.get('version')} ({i.get('threading_layer', '')})"
+                break
     except Exception:  # pragma: no cover
-        cores = os.cpu_count() or 1
-    flops_done, t_used, parts = 0.0, 0.0, []
-    nc, na, nv, naux = p.nc, p.na, p.nv, p.naux
-    # CCVV over the first core orbitals (pairs i <= j < nc_s)
-    t = time.perf_counter()
-    nc_s = nc
-    while nc_s > 1 and (nc_s * (nc_s + 1) / 2) * 2.0 * naux * nv * nv / 40e9 > budget_s / 2:
-        nc_s -= 1
-    O.energy_ccvv(p.B_cv[:, :nc_s], p.eps_c[:nc_s], p.eps_v, p.s)
-    dt = time.perf_counter() - t
-    flops_done += 2.0 * naux * (nc_s * (nc_s + 1) / 2) * nv * nv
-    t_used += dt
-    parts.append(f"CCVV over core pairs of {nc_s}/{nc} core orbitals")
-    if na > 0 and t_used < budget_s:
-        # one core orbital first, to size the sample to the rest of the budget
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "blas": blas}
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()
+                    if i.get("user_api") == "blas"] or [1])
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def _sub_problem(p, nc_s):
+    """The problem restricted to its first nc_s core orbitals (same active,
+    virtual and auxiliary spaces)."""
+    import copy
+    q = copy.copy(p)
+    q.nc = nc_s
+    q.B_cv = np.ascontiguousarray(p.B_cv[:, :nc_s])
+    q.B_ca = np.ascontiguousarray(p.B_ca[:, :nc_s])
+    q.eps_c = p.eps_c[:nc_s]
+    return q
+
+
+def cpu_baseline(p, budget_s=20.0, grad=False):
+    """Time the oracle on a bounded sample of the same workload: the problem
+    restricted to its first nc_s core orbitals, nc_s sized from a one-orbital
+    probe so the run takes about budget_s; energy (and, with grad, the
+    analytic gradient) of all three terms. Run once on every BLAS thread and
+    once on one thread (a smaller sample)."""
+    from oracle import dsrg_oracle as O
+    from threadpoolctl import threadpool_limits
+
+    def work(nc_s):
+        f, _ = alg_flops(nc_s, p.na, p.nv, p.naux)
+        return 3.0 * f if grad else f
+
+    def run(nc_s):
+        q = _sub_problem(p, nc_s)
         t = time.perf_counter()
-        O.energy_cavv(p.B_cv[:, :1], p.B_av, p.eps_c[:1], p.eps_a, p.eps_v, p.gamma1, p.s)
-        t1 = max(time.perf_counter() - t, 1e-6)
-        m_s = max(1, min(nc, int((budget_s - t_used) / t1)))
-        t = time.perf_counter()
-        O.energy_cavv(p.B_cv[:, :m_s], p.B_av, p.eps_c[:m_s], p.eps_a, p.eps_v, p.gamma1, p.s)
-        O.energy_ccav(p.B_cv[:, :m_s], p.B_ca[:, :m_s], p.eps_c[:m_s], p.eps_a, p.eps_v,
-                      p.gamma1, p.s)
-        dt = time.perf_counter() - t
-        flops_done += 2.0 * naux * m_s * na * nv * nv + 2.0 * naux * m_s * m_s * na * nv
-        t_used += dt
-        parts.append(f"CAVV and CCAV over {m_s}/{nc} core orbitals")
-    return {"value": flops_done / t_used / 1e12, "unit": "TFLOP/s", "cores": int(cores),
-            "kind": "oracle", "seconds": round(t_used, 3),
-            "sample": "; ".join(parts) + " (FP64 numpy/BLAS oracle, same inputs)"}
+        O.energy_terms(q)
+        if grad:
+            O.gradients(q, (1.0, 1.0, 1.0))
+        return time.perf_counter() - t
+
+    def sample(budget):
+        t1 = max(run(1), 1e-6)
+        nc_s = 1
+        while nc_s < p.nc and t1 * work(nc_s + 1) / work(1) <= budget:
+            nc_s += 1
+        dt = run(nc_s) if nc_s > 1 else t1
+        return nc_s, dt
+
+    what = "energy + gradient" if grad else "energy"
+    nc_all, dt_all = sample(budget_s)
+    cores = _blas_threads()
+    with threadpool_limits(limits=1, user_api="blas"):
+        nc_one, dt_one = sample(budget_s / 2)
+    out = {"value": work(nc_all) / dt_all / 1e12, "unit": "TFLOP/s", "cores": int(cores),
+           "kind": "oracle", "seconds": round(dt_all, 3),
+           "sample": f"{what} of CCVV+CAVV+CCAV over the first {nc_all}/{p.nc} core orbitals "
+                     "(all virtual, active and auxiliary functions; FP64 numpy/BLAS oracle, "
+                     "same inputs)",
+           "one_thread": {"value": work(nc_one) / dt_one / 1e12, "unit": "TFLOP/s", "cores": 1,
+                          "seconds": round(dt_one, 3),
+                          "sample": f"{what} over the first {nc_one}/{p.nc} core orbitals"}}
+    out.update(host_info())
+    return out
 
 
 def kernel_source_sha(src):
@@ -358,17 +419,143 @@ def load_traffic(kernel, workload):
     return d.get("bytes_per_launch")
 
 
+def roofline_kernel(precision, grad):
+    """The kernel the roofline is taken on, the names its launches are timed
+    under, its unit and the executed operations per algorithmic multiply-add.
+    Energy: the CCVV contraction. Gradient: the adjoint products (2/3 of the
+    work, several launches per step, summed per step)."""
+    if grad:
+        if precision == "fp64":
+            return "gemm_adj_fp64", ["gemm_adj_fp64", "gemm_adj_tb_fp64"], "TFLOP/s", 1.0
+        return "gemm_adj_i8", ["gemm_adj_i8"], "TOP/s", SLICE_PRODUCTS
+    if precision == "fp64":
+        return "ccvv_fp64", ["ccvv_fp64"], "TFLOP/s", 1.0
+    return "ccvv_i8", ["ccvv_i8"], "TOP/s", SLICE_PRODUCTS
+
+
+def run_energy_path(binding, torch, p, t_in, terms, precision, grad, steps, warmup, ntable):
+    """Time `steps` calls of the energy (or energy + gradient) entry point
+    after `warmup` untimed ones. HIP events surround the roofline kernel's
+    launches only inside the timed region; every kernel is timed in ntable
+    further calls for the per-kernel table. Returns the measurements and the
+    last call's outputs (on the host)."""
+    dev = t_in[0].device
+    nbytes = binding.workspace_size(p.nc, p.na, p.nv, p.naux, precision=precision,
+                                    terms=list(terms), with_grad=grad)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    E = torch.empty(3, dtype=torch.float64, device=dev)
+    gE = torch.tensor(BENCH_GE, dtype=torch.float64, device=dev)
+    out = {}
+
+    def step(timing):
+        if grad:
+            g = binding.energy_backward(*t_in, p.s, gE, precision=precision, terms=list(terms),
+                                        workspace=ws, timing=timing)
+            E.copy_(g["E"])
+            out["g"] = g
+        else:
+            binding.energy(*t_in, p.s, precision=precision, terms=list(terms), workspace=ws,
+                           out=E, timing=timing)
+
+    dom, dom_names, unit, mult = roofline_kernel(precision, grad)
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    binding.kernel_times(1)   # clear the record
+    # timed region: HIP events around the roofline kernel's launches only (an
+    # event pair around every kernel adds about 3 % to the energy step at
+    # nc = 23, nv = 380, naux = 1100)
+    binding.timing_filter(dom_names)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt_dom = binding.kernel_times(1 << 16)
+    finally:
+        binding.timing_filter(None)
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    # every kernel, in a short pass after the timed region (the per-kernel table)
+    for _ in range(ntable):
+        step(True)
+    torch.cuda.synchronize()
+    per_kernel = {}
+    for name, ms in binding.kernel_times(1 << 16):
+        per_kernel.setdefault(name, []).append(ms)
+    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
+    launches = [ms for name, ms in kt_dom if name in dom_names]
+    dom_ms = sum(launches) / steps if launches else None
+    res = {"ms_per_step": ms_per_step, "dom": dom, "dom_names": dom_names, "unit": unit,
+           "mult": mult, "dom_ms": dom_ms, "dom_launches_per_step": len(launches) / steps,
+           "kernel_ms": avg, "workspace_bytes": int(nbytes),
+           "E": E.cpu().numpy()}
+    if grad:
+        res["grad"] = {k: v.cpu().numpy() for k, v in out["g"].items()}
+    del ws
+    return res
+
+
+def path_flops(p, terms, grad):
+    """Algorithmic flops of one step and of the roofline kernel's share: the
+    CCVV contraction for the energy; for energy + gradient the whole step is
+    3 F_alg (recompute once, two adjoint contractions) and the adjoint
+    products carry 2 F_alg."""
+    F, parts = alg_flops(p.nc, p.na, p.nv, p.naux, terms)
+    if grad:
+        return 3.0 * F, 2.0 * F
+    return F, parts["ccvv"]
+
+
+def oracle_refs(config, s):
+    refs = os.path.join(ROOT, "tests", "golden", "oracle_refs.json")
+    if not os.path.exists(refs):
+        return {}
+    return json.load(open(refs)).get(config, {})
+
+
+def energy_errors(config, s, E):
+    r = oracle_refs(config, s).get("E_s%g" % s)
+    if r is None:
+        return None
+    return [abs(float(a) - float(b)) for a, b in zip(E, r)]
+
+
+def sampled_grad_error(config, g):
+    """Largest deviation of the sampled dE/dB entries and of dE/deps, dE/ds from
+    the oracle's (stored by the reference generator with the same upstream
+    weights), relative to each output's largest oracle entry."""
+    r = oracle_refs(config, None).get("grad")
+    if r is None or list(r["gE"]) != list(BENCH_GE):
+        return None
+    ren = {"B_cv": "dB_cv", "B_ca": "dB_ca", "B_av": "dB_av", "eps_c": "deps_c",
+           "eps_a": "deps_a", "eps_v": "deps_v", "s": "ds"}
+    worst = 0.0
+    for k in ("B_cv", "B_ca", "B_av"):
+        vals = np.array([g[ren[k]][tuple(i)] for i in r[k]["idx"]])
+        worst = max(worst, float(np.abs(vals - np.array(r[k]["val"])).max() / r[k]["absmax"]))
+    for k in ("eps_c", "eps_a", "eps_v", "s"):
+        ref = np.array(r[k])
+        worst = max(worst, float(np.abs(g[ren[k]] - ref).max() / np.abs(ref).max()))
+    return worst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--config", default="cfg5")
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--energy", action="store_true",
+                    help="time the energy alone (dsrg_df_energy) instead of energy + gradient")
     ap.add_argument("--grad", action="store_true",
-                    help="time energy + gradient (dsrg_df_energy_backward) instead of energy")
+                    help="energy + gradient (the default; kept for older command lines)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the same workload in the other precision")
     ap.add_argument("--active", action="store_true",
                     help="time the pieces F4-F8 of term F (dsrg_df_energy_active, FP64)")
     ap.add_argument("--dfgen", action="store_true",
@@ -412,124 +599,91 @@ def main():
     p = make_config(args.config)
     if args.active:
         return bench_active(args, p, binding, torch)
+    grad = not args.energy
     c = CONFIGS[args.config]
     terms = c["terms"]
     dev = torch.device("cuda:0")
     t_in = [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in p.arrays()]
-    nbytes = binding.workspace_size(p.nc, p.na, p.nv, p.naux, precision=args.precision,
-                                    terms=list(terms))
-    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    E = torch.empty(3, dtype=torch.float64, device=dev)
+    ntable = table_steps(args)
 
-    gE = torch.tensor([1.0, 1.0, 1.0], dtype=torch.float64, device=dev)
-    if args.grad:
-        nbytes = binding.workspace_size(p.nc, p.na, p.nv, p.naux, precision=args.precision,
-                                        terms=list(terms), with_grad=True)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-        gout = {}
-
-    def step(timing):
-        if args.grad:
-            g = binding.energy_backward(*t_in, p.s, gE, precision=args.precision,
-                                        terms=list(terms), workspace=ws, timing=timing)
-            E.copy_(g["E"])
-            gout["g"] = g
-        else:
-            binding.energy(*t_in, p.s, precision=args.precision, terms=list(terms),
-                           workspace=ws, out=E, timing=timing)
-
-    # the kernel the roofline is taken on: the CCVV contraction, or with the
-    # gradient the adjoint GEMM (2/3 of the work, several launches per step)
-    if args.grad:
-        if args.precision == "fp64":
-            dom, unit, mult = "gemm_adj_fp64", "TFLOP/s", 1.0
-            dom_names = ["gemm_adj_fp64", "gemm_adj_tb_fp64"]
-        else:
-            dom, unit, mult = "gemm_adj_i8", "TOP/s", SLICE_PRODUCTS
-            dom_names = ["gemm_adj_i8"]
-    elif args.precision == "fp64":
-        dom, unit, mult = "ccvv_fp64", "TFLOP/s", 1.0
-        dom_names = [dom]
-    else:
-        # int8 slices: SLICE_PRODUCTS exact int8 products per algorithmic multiply-add
-        dom, unit, mult = "ccvv_i8", "TOP/s", SLICE_PRODUCTS
-        dom_names = [dom]
-
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    binding.kernel_times(1)   # clear the record
-
-    # timed region: HIP events around the roofline kernel's launches only (an
-    # event pair around every kernel adds about 3 % to the energy step at
-    # nc = 23, nv = 380, naux = 1100)
-    binding.timing_filter(dom_names)
-    try:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step(True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        kt_dom = binding.kernel_times(4096)
-    finally:
-        binding.timing_filter(None)
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-
-    # every kernel, in a short pass after the timed region (the per-kernel table)
-    for _ in range(max(1, min(args.steps, 5))):
-        step(True)
-    torch.cuda.synchronize()
-    per_kernel = {}
-    for name, ms in binding.kernel_times(4096):
-        per_kernel.setdefault(name, []).append(ms)
-    avg = {k: float(np.mean(v)) for k, v in per_kernel.items()}
-
-    F, Fparts = alg_flops(p.nc, p.na, p.nv, p.naux, terms)
-    if args.grad:
-        # recompute (1x) plus the two adjoint contractions (2x) of every term
-        F, Fparts = 3.0 * F, {k: 3.0 * v for k, v in Fparts.items()}
-        Fparts = dict(Fparts)
-        Fparts["ccvv"] = 2.0 / 3.0 * F
-    value = F / (ms_per_step * 1e-3) / 1e12
-    # per step: all launches of the roofline kernel in the timed region
-    dom_ms = sum(ms for name, ms in kt_dom if name in dom_names) / args.steps if kt_dom else None
-    if args.grad:
-        avg[dom] = dom_ms   # the per-step total of its launches
-    ach = mult * Fparts["ccvv"] / (dom_ms * 1e-3) / 1e12 if dom_ms else None
+    r = run_energy_path(binding, torch, p, t_in, terms, args.precision, grad, args.steps,
+                        args.warmup, ntable)
+    F, Fdom = path_flops(p, terms, grad)
+    value = F / (r["ms_per_step"] * 1e-3) / 1e12
+    dom_ms = r["dom_ms"]
+    ach = r["mult"] * Fdom / (dom_ms * 1e-3) / 1e12 if dom_ms else None
     peak = PEAK_TFLOPS[args.precision]
-    roof = {"bound": "mfma", "kernel": dom, "achieved": ach, "peak": peak, "unit": unit,
+    if grad:
+        r["kernel_ms"][r["dom"]] = dom_ms   # the per-step total of its launches
+    roof = {"bound": "mfma", "kernel": r["dom"], "achieved": ach, "peak": peak, "unit": r["unit"],
             "frac": (ach / peak) if ach else None, "avg_launch_ms": dom_ms,
-            "ops_per_launch": mult * Fparts["ccvv"],
-            "algorithmic_tflops_per_launch": Fparts["ccvv"] / (dom_ms * 1e-3) / 1e12 if dom_ms else None,
-            "traffic": load_traffic(dom, args.config)}
-
-    Eg = E.cpu().numpy()
-    err = None
-    refs = os.path.join(ROOT, "tests", "golden", "oracle_refs.json")
-    if os.path.exists(refs):
-        r = json.load(open(refs)).get(args.config, {}).get("E_s%g" % p.s)
-        if r is not None:
-            err = [abs(float(a) - float(b)) for a, b in zip(Eg, r)]
-
+            "launches_per_step": r["dom_launches_per_step"],
+            "ops_per_launch": r["mult"] * Fdom,
+            "per_launch_note": ("the adjoint products of one step taken together: their "
+                                "algorithmic flops (2 F_alg) over the summed duration of their "
+                                "launches in the timed region") if grad else
+                               "one launch: the CCVV contraction's algorithmic flops",
+            "algorithmic_tflops_per_launch": Fdom / (dom_ms * 1e-3) / 1e12 if dom_ms else None,
+            "traffic": load_traffic(r["dom"], args.config)}
+    what = "energy+gradient" if grad else "energy"
     out = {
         "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
         "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "s_per_solve": ms_per_step * 1e-3,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "s_per_solve": r["ms_per_step"] * 1e-3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "i8 slices (int32 exact) + f64", "data": "synthetic",
+        "dtype": "f64" if args.precision == "fp64" else "i8 slices (int32 exact) + f64",
+        "data": "synthetic",
         "config": {"workload": f"{args.config}: nc={p.nc} na={p.na} nv={p.nv} naux={p.naux} "
-                               f"s={p.s}, " + ("energy+gradient" if args.grad else "energy")
-                               + " of " + "+".join(t.upper() for t in terms),
+                               f"s={p.s}, {what} of " + "+".join(t.upper() for t in terms),
                    "precision": args.precision, "parallelism": "single-gpu"},
-        "kernel_ms": avg,
+        "flops_per_step": F,
+        "kernel_ms": r["kernel_ms"],
         "kernel_ms_from": table_note(args),
-        "E_terms": [float(x) for x in Eg],
-        "abs_err_vs_oracle": err,
+        "workspace_bytes": r["workspace_bytes"],
+        "E_terms": [float(x) for x in r["E"]],
+        "abs_err_vs_oracle": energy_errors(args.config, p.s, r["E"]),
         "roofline": roof,
     }
+    if grad:
+        out["grad_sampled_rel_err_vs_oracle"] = sampled_grad_error(args.config, r["grad"])
+
+    if not args.no_compare:
+        # the same workload in the other precision, and on slices the CCVV
+        # energy kernel's rate against the int8 matrix-core peak
+        other = "ozaki" if args.precision == "fp64" else "fp64"
+        r2 = run_energy_path(binding, torch, p, t_in, terms, other, grad, args.steps,
+                             args.warmup, 0)
+        cmp_ = {"precision": other, "ms_per_step": r2["ms_per_step"],
+                "value": F / (r2["ms_per_step"] * 1e-3) / 1e12, "unit": "TFLOP/s",
+                "workspace_bytes": r2["workspace_bytes"],
+                "E_terms": [float(x) for x in r2["E"]],
+                "abs_err_vs_oracle": energy_errors(args.config, p.s, r2["E"])}
+        split_ms = r2["ms_per_step"] if other == "ozaki" else r["ms_per_step"]
+        fp64_ms = r["ms_per_step"] if other == "ozaki" else r2["ms_per_step"]
+        cmp_["speedup_slices_over_fp64"] = fp64_ms / split_ms
+        d_ms = r2["dom_ms"]
+        if d_ms:
+            a2 = r2["mult"] * Fdom / (d_ms * 1e-3) / 1e12
+            cmp_["roofline"] = {"kernel": r2["dom"], "avg_launch_ms": d_ms, "achieved": a2,
+                                "unit": r2["unit"], "peak": PEAK_TFLOPS[other],
+                                "frac": a2 / PEAK_TFLOPS[other]}
+        if grad:
+            cmp_["grad_sampled_rel_err_vs_oracle"] = sampled_grad_error(args.config, r2["grad"])
+        if "ozaki" in (args.precision, other):
+            r3 = run_energy_path(binding, torch, p, t_in, terms, "ozaki", False, args.steps,
+                                 args.warmup, 0)
+            Fe, Fccvv = path_flops(p, terms, False)
+            a3 = SLICE_PRODUCTS * Fccvv / (r3["dom_ms"] * 1e-3) / 1e12 if r3["dom_ms"] else None
+            cmp_["slice_energy"] = {
+                "ms_per_step": r3["ms_per_step"], "value": Fe / (r3["ms_per_step"] * 1e-3) / 1e12,
+                "abs_err_vs_oracle": energy_errors(args.config, p.s, r3["E"]),
+                "ccvv_i8": {"avg_launch_ms": r3["dom_ms"], "executed_TOPs": a3,
+                            "peak": PEAK_TFLOPS["ozaki"],
+                            "frac": (a3 / PEAK_TFLOPS["ozaki"]) if a3 else None}}
+        out["compare"] = cmp_
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_budget, grad=grad)
     print(json.dumps(out))
 
 

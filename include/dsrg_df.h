@@ -257,10 +257,17 @@ dsrg_status dsrg_df_semicanonicalize_workspace_size(const dsrg_semican_problem *
 /* U [nmo][nmo], eps [nmo] and, when C and Cs are both given, Cs = C U
  * [nao][nmo] (device, FP64). Jacobi rotations to an off-diagonal norm below
  * 1e-14 of the block's norm, or 12 block sweeps at most (blocks of up to 32
- * orbitals: 40 sweeps at most). Errors as for dsrg_df_energy. */
+ * orbitals: 40 sweeps at most).
+ *   info  optional device int [1] (NULL = not wanted, 4-byte aligned): once
+ *         the call's work has run, the bit mask of the blocks whose
+ *         off-diagonal norm never met the criterion (bit 0 core, bit 1
+ *         active, bit 2 virtual; 0 = every block converged). Written by
+ *         kernels on `stream`: read it after synchronising, the call itself
+ *         never waits. U and eps are returned in either case.
+ * Errors as for dsrg_df_energy. */
 dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options, double *U,
-                                     double *eps, double *Cs, void *workspace, size_t ws_bytes,
-                                     void *stream);
+                                     double *eps, double *Cs, int *info, void *workspace,
+                                     size_t ws_bytes, void *stream);
 
 /* Text of the last error raised on the calling thread ("" if none). Valid
  * until the next dsrg_df_* call on that thread. */
@@ -281,6 +288,23 @@ int dsrg_df_kernel_times(double *ms, const char **names, int cap);
  * untimed cost. The list is copied; DSRG_ERR_ARG if it is 256 characters or
  * longer (the filter is then unchanged). */
 dsrg_status dsrg_df_timing_filter(const char *names);
+
+/* The gradient (dsrg_df_energy_backward) forms its adjoint tiles per block of
+ * core orbitals: the CCVV tiles of one block pair (gb 64 ceil(nv/64))^2
+ * doubles, or the CAVV integrals and adjoint rows of one block, in one
+ * workspace region, never the tiles of all nc^2 core pairs at once (section
+ * III: no four-index storage). gb is the largest number of core orbitals
+ * whose region fits `bytes` (at least one orbital, so a bound below one
+ * orbital's need is exceeded), balanced over the blocks. 0 restores the
+ * default of 1 GiB. Process-wide; it changes what dsrg_df_workspace_size
+ * reports for the gradient, so set it before querying the size (a call
+ * whose workspace has become too small returns DSRG_ERR_WORKSPACE). Smaller
+ * blocks trade memory for shorter adjoint products; the results differ from
+ * those of other block sizes only by the order of FP64 additions.
+ * DSRG_ERR_ARG for a bound above 2^50 bytes. */
+dsrg_status dsrg_df_set_gradient_block_bytes(size_t bytes);
+/* The bound in force. */
+size_t dsrg_df_gradient_block_bytes(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int dsrg_df_version(void);

@@ -29,6 +29,7 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward
             "dsrg_df_fock_workspace_size", "dsrg_df_fock",
             "dsrg_df_semicanonicalize_workspace_size", "dsrg_df_semicanonicalize",
             "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_timing_filter",
+            "dsrg_df_set_gradient_block_bytes", "dsrg_df_gradient_block_bytes",
             "dsrg_df_version")
 
 
@@ -110,7 +111,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                             ctypes.POINTER(sz)]
     lib.dsrg_df_semicanonicalize_workspace_size.restype = i32
     lib.dsrg_df_semicanonicalize.argtypes = [ctypes.POINTER(SemicanProblem), i32, vp, vp, vp, vp,
-                                             sz, vp]
+                                             vp, sz, vp]
     lib.dsrg_df_semicanonicalize.restype = i32
     lib.dsrg_df_last_error.argtypes = []
     lib.dsrg_df_last_error.restype = ctypes.c_char_p
@@ -119,6 +120,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_kernel_times.restype = i32
     lib.dsrg_df_timing_filter.argtypes = [ctypes.c_char_p]
     lib.dsrg_df_timing_filter.restype = i32
+    lib.dsrg_df_set_gradient_block_bytes.argtypes = [sz]
+    lib.dsrg_df_set_gradient_block_bytes.restype = i32
+    lib.dsrg_df_gradient_block_bytes.argtypes = []
+    lib.dsrg_df_gradient_block_bytes.restype = sz
     lib.dsrg_df_version.argtypes = []
     lib.dsrg_df_version.restype = i32
     _lib = lib
@@ -156,6 +161,17 @@ def timing_filter(names: Optional[Sequence[str]] = None) -> None:
     st = lib.dsrg_df_timing_filter(arg)
     if st != 0:
         raise DsrgError(st, lib.dsrg_df_last_error().decode())
+
+
+def set_gradient_block_bytes(nbytes: int = 0) -> int:
+    """Bound the gradient's per-block adjoint-tile region (0 = the default);
+    returns the bound that was in force before."""
+    lib = load_library()
+    old = int(lib.dsrg_df_gradient_block_bytes())
+    st = lib.dsrg_df_set_gradient_block_bytes(int(nbytes))
+    if st != 0:
+        raise DsrgError(st, lib.dsrg_df_last_error().decode())
+    return old
 
 
 def _terms_mask(terms: Union[str, int, Sequence[str]], atomic: bool, timing: bool = False) -> int:
@@ -333,9 +349,11 @@ def df_fock(ao3, J, C, h, gamma1, nfrz, nc, na, nv, workspace: Optional[torch.Te
 
 
 def semicanonicalize(F, nfrz, nc, na, nv, C=None, workspace: Optional[torch.Tensor] = None,
-                     timing: bool = False):
+                     timing: bool = False, info: Optional[torch.Tensor] = None):
     """(eps [nmo], U [nmo][nmo], Cs = C U or None) via dsrg_df_semicanonicalize
-    from the generalized Fock matrix F [nmo][nmo] (device tensors, float64)."""
+    from the generalized Fock matrix F [nmo][nmo] (device tensors, float64).
+    info: optional device int32 tensor [1] that receives the convergence bit
+    mask (0 = every block met the criterion) once the work has run."""
     lib = load_library()
     nmo = F.shape[0]
     dev = F.device
@@ -350,9 +368,11 @@ def semicanonicalize(F, nfrz, nc, na, nv, C=None, workspace: Optional[torch.Tens
     U = torch.empty(nmo, nmo, **f64)
     eps = torch.empty(nmo, **f64)
     Cs = torch.empty(nao, nmo, **f64) if Cd is not None else None
+    if info is not None and (info.device != dev or info.dtype != torch.int32 or info.numel() < 1):
+        raise ValueError("info must be an int32 tensor of at least one element on the device of F")
     _check(lib.dsrg_df_semicanonicalize(ctypes.byref(p), OPT_KERNEL_TIMING if timing else 0,
-                                        U.data_ptr(), eps.data_ptr(), _ptr(Cs), ws.data_ptr(),
-                                        nbytes.value, _stream_handle(dev)))
+                                        U.data_ptr(), eps.data_ptr(), _ptr(Cs), _ptr(info),
+                                        ws.data_ptr(), nbytes.value, _stream_handle(dev)))
     del Fd, Cd
     return eps, U, Cs
 

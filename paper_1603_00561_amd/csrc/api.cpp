@@ -5,6 +5,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 #include <algorithm>
+#include <atomic>
 #include <string.h>
 
 #include "../../include/dsrg_df.h"
@@ -13,6 +14,9 @@
 namespace {
 
 thread_local char g_err[512] = "";
+
+// bound on the gradient's per-block adjoint-tile region (process-wide)
+std::atomic<int64_t> g_grad_block_bytes{dsrg::kGradBlockBytes};
 
 dsrg_status fail(dsrg_status code, const char *fmt, ...) {
   va_list ap;
@@ -130,10 +134,10 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   const bool has_cavv = (term_bits & DSRG_TERM_CAVV) && pl.na > 0;
   const bool has_ccav = (term_bits & DSRG_TERM_CCAV) && pl.na > 0;
   pl.nqc = ceil_div(pl.naux, 32);
-  // CAVV (energy and adjoint, both precisions) goes through batches of
-  // (me|uf) integrals of at most 4 GiB (one batch up to nc = 23, na = 6,
-  // nv = 1100 and beyond)
+  // CAVV energy: batches of (me|uf) integrals of at most 4 GiB (one batch up
+  // to nc = 23, na = 6, nv = 1100 and beyond)
   const bool xbatch = has_cavv;
+  const int64_t Wg = pl.ntv * kPanel;   // padded virtual orbitals per orbital (FP64 tiles)
   if (xbatch) {
     const int64_t per_m = pl.na * pl.xld * pl.xld * 8;
     pl.cavv_mb = ((int64_t)4 << 30) / per_m;
@@ -141,6 +145,31 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
     if (pl.cavv_mb > pl.nc) pl.cavv_mb = pl.nc;
   } else {
     pl.cavv_mb = 0;
+  }
+  // Gradient: the adjoint tiles are formed per block of gb core orbitals (the
+  // CCVV tiles of one block pair, the CAVV integrals and adjoint rows of one
+  // block) in one region of at most kGradBlockBytes, so the workspace holds
+  // O(gb^2 nv^2 + gb na nv^2) values, never the nc^2 nv^2 of all pairs.
+  size_t gblk_bytes = 0;
+  if (pl.with_grad) {
+    const bool ccvv = (term_bits & DSRG_TERM_CCVV) != 0;
+    auto need = [&](int64_t b) {
+      size_t n = 0;
+      if (ccvv) n = sizeof(double) * (size_t)(b * Wg) * (size_t)(b * Wg);
+      if (has_cavv) {
+        const size_t xb = sizeof(double) * (size_t)(b * pl.na) * (size_t)pl.xld * (size_t)pl.xld;
+        const size_t g2 = sizeof(double) * (size_t)(b * Wg) * (size_t)(pl.na * Wg);
+        n = std::max(n, align256(xb) + g2);
+      }
+      return n;
+    };
+    const size_t budget = (size_t)g_grad_block_bytes.load();
+    int64_t b = pl.nc;
+    while (b > 1 && need(b) > budget) --b;
+    pl.ngb = ceil_div(pl.nc, b);
+    pl.gb = ceil_div(pl.nc, pl.ngb);   // balanced blocks, the last one no larger
+    gblk_bytes = need(pl.gb);
+    if (has_cavv) pl.cavv_mb = pl.gb;
   }
   pl.n_cavv = has_cavv ? pl.nc * (ceil_div(pl.nv, 16) * (ceil_div(pl.nv, 16) + 1) / 2) : 0;
   pl.ccav_cols = round_up(pl.nc * pl.na, 16);
@@ -203,7 +232,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       off = align256(off + sizeof(double) * cola);
     }
   }
-  if (xbatch) {
+  if (xbatch && !pl.with_grad) {
     pl.off_xb = off;
     off = align256(off + sizeof(double) * (size_t)(pl.cavv_mb * pl.na) * (size_t)pl.xld *
                              (size_t)pl.xld);
@@ -214,35 +243,50 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
                    kSliceCounterBytes);
   pl.off_gs = pl.off_g2 = pl.off_g3 = off;
   if (pl.with_grad) {
-    const size_t Np = (size_t)(pl.nc * pl.ntv * kPanel);
-    if (term_bits & DSRG_TERM_CCVV) {
-      pl.off_gs = off;
-      off = align256(off + sizeof(double) * Np * Np);
-    }
-    if (pl.na > 0 && (term_bits & DSRG_TERM_CAVV)) {
-      pl.off_g2 = off;
-      off = align256(off + sizeof(double) * Np * (size_t)(pl.na * pl.ntv * kPanel));
-    }
+    // one region: the CCVV tiles of a block pair (off_gs), or the CAVV
+    // integral batch (off_xb) followed by the adjoint rows G2 of the block
+    // (off_g2); the phases run one after the other on the stream
+    pl.off_gs = pl.off_xb = off;
+    pl.off_g2 = off;
+    if (xbatch)
+      pl.off_g2 = align256(off + sizeof(double) * (size_t)(pl.gb * pl.na) * (size_t)pl.xld *
+                                     (size_t)pl.xld);
+    off = align256(off + gblk_bytes);
+    const int64_t Np = pl.nc * Wg;
     if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV)) {
       pl.off_g3 = off;
-      off = align256(off + sizeof(double) * Np * (size_t)(pl.nc * kActPanel));
+      off = align256(off + sizeof(double) * (size_t)Np * (size_t)(pl.nc * kActPanel));
     }
     {
-      // the adjoint products (FP64 or int8) with too few output tiles are split over K
-      // into segments (partial products summed in a fixed order): room for
-      // the largest. Shapes (ncols, GP, nvalid, K) as the products take them.
-      const int64_t np = (int64_t)Np, gp = pl.ntv * kPanel, kcv = pl.nc * pl.ntv * kPanel;
-      const int64_t n2 = pl.na * pl.ntv * kPanel, n3 = pl.nc * kActPanel;
-      const int64_t shapes[5][4] = {{np, gp, pl.nv, kcv},
-                                    {np, gp, pl.nv, pl.na * pl.ntv * kPanel},
-                                    {n2, gp, pl.nv, kcv},
-                                    {np, gp, pl.nv, pl.nc * kActPanel},
-                                    {n3, kActPanel, pl.na, kcv}};
+      // adjoint products with too few output tiles are split over K into
+      // segments (partial products summed in a fixed order); on slices every
+      // product longer than one exact int32 segment is split too: room for
+      // the largest. Shapes (ncols, GP, nvalid, K) as the products take them,
+      // for the full-size and the last (smaller) core block.
+      const int64_t gp = Wg, n2 = pl.na * Wg, n3 = pl.nc * kActPanel;
+      const int64_t n3p = round_up(n3, kQChunk);
+      const int64_t blast = pl.nc - (pl.ngb - 1) * pl.gb;
       int64_t most = 0;
-      for (const auto &sh : shapes) {
-        if (sh[0] <= 0 || sh[3] <= 0) continue;
-        const int64_t nseg = adj_segments(pl.naux, sh[0], sh[3]);
-        if (nseg > 1) most = std::max(most, nseg * pl.naux * adj_out_cols(sh[0], sh[1], sh[2]));
+      auto consider = [&](int64_t ncols, int64_t GPc, int64_t nvalid, int64_t K) {
+        if (ncols <= 0 || K <= 0) return;
+        int64_t nseg = adj_segments(pl.naux, ncols, K);
+        if (split) {
+          int64_t segc = 0;
+          nseg = i8_segments(pl.naux, ncols, K, segc);
+        }
+        if (nseg > 1) most = std::max(most, nseg * pl.naux * adj_out_cols(ncols, GPc, nvalid));
+      };
+      for (const int64_t bi : {pl.gb, blast})
+        for (const int64_t bj : {pl.gb, blast}) {
+          if (term_bits & DSRG_TERM_CCVV) consider(bj * gp, gp, pl.nv, bi * gp);
+          if (has_cavv) {
+            consider(bi * gp, gp, pl.nv, n2);
+            consider(n2, gp, pl.nv, bi * gp);
+          }
+        }
+      if (has_ccav) {
+        consider(Np, gp, pl.nv, split ? n3p : n3);
+        consider(n3, kActPanel, pl.na, Np);
       }
       if (most > 0) {
         pl.off_gpart = off;
@@ -260,12 +304,13 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
                  N2 = (size_t)pl.na * W, N3 = (size_t)(pl.nc * kActPanel);
     const size_t N3p = (size_t)round_up((int64_t)N3, 32);
     const size_t RA = (size_t)round_up(pl.naux, 128);
+    const size_t Nb = (size_t)pl.gb * W;   // rows of one block of core orbitals
     auto r128 = [](size_t n) { return (size_t)round_up((int64_t)n, 128); };
     const bool act = pl.na > 0 && (term_bits & (DSRG_TERM_CAVV | DSRG_TERM_CCAV));
     size_t sb = 0, rbmax = 0;
-    if (term_bits & DSRG_TERM_CCVV) sb = std::max(sb, r128(Np) * Np);
+    if (term_bits & DSRG_TERM_CCVV) sb = std::max(sb, r128(Nb) * Nb);
     if (pl.na > 0 && (term_bits & DSRG_TERM_CAVV))
-      sb = std::max(sb, std::max(r128(Np) * N2, r128(N2) * Np));
+      sb = std::max(sb, std::max(r128(Nb) * N2, r128(N2) * Nb));
     if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV))
       sb = std::max(sb, std::max(r128(Np) * N3p, r128(N3) * Np));
     rbmax = std::max(r128(Np), std::max(r128(N2), r128(N3)));
@@ -753,8 +798,8 @@ dsrg_status dsrg_df_semicanonicalize_workspace_size(const dsrg_semican_problem *
 }
 
 dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options, double *U,
-                                     double *eps, double *Cs, void *workspace, size_t ws_bytes,
-                                     void *stream) {
+                                     double *eps, double *Cs, int *info, void *workspace,
+                                     size_t ws_bytes, void *stream) {
   g_err[0] = 0;
   dsrg::SemicanPlan pl;
   dsrg_status st = make_semican_plan(p, pl);
@@ -768,6 +813,8 @@ dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options,
     return fail(DSRG_ERR_ARG, "C and Cs must be given together");
   if (Cs && (!aligned8(Cs) || !aligned8(p->C) || p->nao < 1))
     return fail(DSRG_ERR_ARG, "C or Cs misaligned, or nao < 1 with C given");
+  if (info && (reinterpret_cast<uintptr_t>(info) & 3u))
+    return fail(DSRG_ERR_ARG, "info is misaligned");
   if (ws_bytes < pl.total)
     return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
                 ws_bytes, pl.total);
@@ -776,7 +823,7 @@ dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options,
     return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
   timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
-  hipError_t e = dsrg::launch_semican(pl, p->F, p->C, U, eps, Cs, workspace, hs);
+  hipError_t e = dsrg::launch_semican(pl, p->F, p->C, U, eps, Cs, info, workspace, hs);
   if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return DSRG_OK;
 }
@@ -811,6 +858,15 @@ dsrg_status dsrg_df_timing_filter(const char *names) {
   return DSRG_OK;
 }
 
-int dsrg_df_version(void) { return 100; }
+dsrg_status dsrg_df_set_gradient_block_bytes(size_t bytes) {
+  g_err[0] = '\0';
+  if (bytes > ((size_t)1 << 50)) return fail(DSRG_ERR_ARG, "bound of %zu bytes is too large", bytes);
+  g_grad_block_bytes.store(bytes == 0 ? dsrg::kGradBlockBytes : (int64_t)bytes);
+  return DSRG_OK;
+}
+
+size_t dsrg_df_gradient_block_bytes(void) { return (size_t)g_grad_block_bytes.load(); }
+
+int dsrg_df_version(void) { return 200; }
 
 }  // extern "C"

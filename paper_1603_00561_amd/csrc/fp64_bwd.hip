@@ -59,10 +59,28 @@ struct CcvvAdjArgs {
   int nc, nv, ntv;
   int64_t naux_p;
   double s;
-  int64_t n0, n1, n2;
-  int64_t slot_base;
-  int64_t Np;   // row length of Gs
+  int64_t slot_base;   // first energy slot of this block pair
+  // block pair of core orbitals: rows of the G block are (i, a) for i in
+  // [r0, r0 + nr), columns (j, b) for j in [c0, c0 + ncb); r0 == c0 is a
+  // diagonal block (pairs i <= j inside it, both orientations stored), else
+  // r0 + nr <= c0 (pairs i in the row block, j in the column block, only the
+  // entries whose row orbital is in the row block stored)
+  int r0, nr, c0, ncb;
+  int64_t ld;   // row length of the G block (ncb 64 ntv)
 };
+
+// pair p of a block pair -> (i, j), i <= j
+__device__ __forceinline__ void block_pair(const CcvvAdjArgs &a, int64_t p, int &i, int &j) {
+  if (a.r0 == a.c0) {
+    int il, jl;
+    decode_pair_le(p, a.nr, il, jl);
+    i = a.r0 + il;
+    j = a.r0 + jl;
+  } else {
+    i = a.r0 + (int)(p / a.ncb);
+    j = a.c0 + (int)(p % a.ncb);
+  }
+}
 
 __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
     const double *__restrict__ Pcv, const double *__restrict__ eps_c,
@@ -71,9 +89,15 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
   constexpr int W = kPanel;
   __shared__ double lds[kCcvvLds];
   __shared__ double rsum[W], csum[W];
-  const PairTile pt = decode_pairtile(blockIdx.x, (int64_t)a.nc * (a.nc + 1) / 2, a.ntv);
+  const int64_t npair = (a.r0 == a.c0) ? (int64_t)a.nr * (a.nr + 1) / 2 : (int64_t)a.nr * a.ncb;
+  const PairTile pt = decode_pairtile(blockIdx.x, npair, a.ntv);
   if (pt.item < 0) return;
-  const CcvvWork c = ccvv_work_from(pt, a.nc);
+  CcvvWork c;
+  block_pair(a, pt.p, c.i, c.j);
+  c.A = pt.A;
+  c.B = pt.B;
+  c.cls = (c.i == c.j) ? (c.A == c.B ? 3 : 2) : (c.A == c.B ? 1 : 0);
+  const bool diag = a.r0 == a.c0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
@@ -130,8 +154,16 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
   for (int q = 0; q < 2; ++q)
     if (csl[q] != 0.0) atomicAdd(&csum[32 * wc + 16 * q + cl], csl[q]);
 
-  // natural-orientation blocks: Gs[(i,A)][(j,B)] = g1 and Gs[(j,A)][(i,B)] = g2
-  const int64_t rowI = (int64_t)c.i * a.ntv * W, rowJ = (int64_t)c.j * a.ntv * W;
+  // G block entries: row (x, a) at (x - r0) 64 ntv + a, column (y, b) at
+  // (y - c0) 64 ntv + b. Natural orientation: G[(i,A)][(j,B)] = g1 and, in a
+  // diagonal block, G[(j,A)][(i,B)] = g2 (classes 0, 1); transposed (classes
+  // 0 and 2, through LDS): G[(j,B)][(i,A)] = g1^T in a diagonal block and
+  // G[(i,B)][(j,A)] = g2^T (class 0). An off-diagonal block keeps only the
+  // entries with row orbital i: the others are their transposes, which the
+  // adjoint products read from the same block.
+  const int64_t WT = (int64_t)a.ntv * W;
+  const int64_t rowI = (int64_t)(c.i - a.r0) * WT, colJ = (int64_t)(c.j - a.c0) * WT;
+  const int64_t rowJ = (int64_t)(c.j - a.r0) * WT, colI = (int64_t)(c.i - a.c0) * WT;
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -140,23 +172,24 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
       for (int r = 0; r < 4; ++r) {
         const int64_t ra = c.A * W + 32 * wr + 16 * p + 4 * r + kl;
         const int64_t cb = c.B * W + 32 * wc + 16 * q + cl;
-        Gs[(rowI + ra) * a.Np + rowJ + cb] = g1[p][q][r];
-        if (c.cls == 0 || c.cls == 1) Gs[(rowJ + ra) * a.Np + rowI + cb] = g2[p][q][r];
+        Gs[(rowI + ra) * a.ld + colJ + cb] = g1[p][q][r];
+        if (diag && (c.cls == 0 || c.cls == 1)) Gs[(rowJ + ra) * a.ld + colI + cb] = g2[p][q][r];
       }
-  // transposed blocks (classes 0 and 2): Gs[(j,B)][(i,A)] = g1^T, Gs[(i,B)][(j,A)] = g2^T
-  if (c.cls == 0 || c.cls == 2) {
+  if ((diag && c.cls == 2) || c.cls == 0) {
     double (*T)[W + 1] = reinterpret_cast<double (*)[W + 1]>(lds);
+    if (diag) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+      for (int p = 0; p < 2; ++p)
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          T[32 * wr + 16 * p + 4 * r + kl][32 * wc + 16 * q + cl] = g1[p][q][r];
-    __syncthreads();
-    store_transposed64(T, Gs + (rowJ + c.B * W) * a.Np + rowI + c.A * W, a.Np);
-    if (c.cls == 0) {
+          for (int r = 0; r < 4; ++r)
+            T[32 * wr + 16 * p + 4 * r + kl][32 * wc + 16 * q + cl] = g1[p][q][r];
       __syncthreads();
+      store_transposed64(T, Gs + (rowJ + c.B * W) * a.ld + colI + c.A * W, a.ld);
+      __syncthreads();
+    }
+    if (c.cls == 0) {
 #pragma unroll
       for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -165,7 +198,7 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
           for (int r = 0; r < 4; ++r)
             T[32 * wr + 16 * p + 4 * r + kl][32 * wc + 16 * q + cl] = g2[p][q][r];
       __syncthreads();
-      store_transposed64(T, Gs + (rowI + c.B * W) * a.Np + rowJ + c.A * W, a.Np);
+      store_transposed64(T, Gs + (rowI + c.B * W) * a.ld + colJ + c.A * W, a.ld);
     }
   }
   __syncthreads();
@@ -543,10 +576,11 @@ static hipError_t launch_adj_act(const Plan &pl, const Inputs &in, const GradOut
 
 hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st) { return zero_fill(p, n, st); }
 
-// Adjoint tiles Gs, G2, G3 (recomputed integrals, FP64) with the energies
-// and the orbital-energy and flow-parameter gradients.
-hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const BwdOut &o,
-                                     void *ws, int mask, hipStream_t st) {
+// Gradients of eps and s cleared, the FP64 panels packed, and the CCAV
+// adjoint tiles G3 (whole: nc 64 ntv rows of nc 16) with their energies and
+// eps / s parts.
+hipError_t launch_adjoint_start_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                     hipStream_t st) {
   hipError_t e;
   GradOut g{o.deps_c, o.deps_a, o.deps_v, o.ds, o.gE};
   if ((e = zero_fill(o.deps_c, pl.nc, st)) != hipSuccess) return e;
@@ -554,49 +588,16 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
   if ((e = zero_fill(o.deps_v, pl.nv, st)) != hipSuccess) return e;
   if ((e = zero_fill(o.ds, 1, st)) != hipSuccess) return e;
   if ((e = launch_pack_fp64(pl, in, ws, st)) != hipSuccess) return e;
-  const bool cavv = (pl.terms & mask & 2) && pl.na > 0, ccav = (pl.terms & mask & 4) && pl.na > 0;
-  const int64_t Np = pl.nc * pl.ntv * kPanel;
-  if (pl.terms & mask & 1) {
-    CcvvAdjArgs a;
-    a.nc = (int)pl.nc;
-    a.nv = (int)pl.nv;
-    a.ntv = (int)pl.ntv;
-    a.naux_p = pl.naux_p;
-    a.s = pl.s;
-    const int64_t npo = tri_off(pl.nc), ntpo = tri_off(pl.ntv);
-    a.n0 = npo * ntpo;
-    a.n1 = npo * pl.ntv;
-    a.n2 = pl.nc * ntpo;
-    a.slot_base = pl.slot_base[0];
-    a.Np = Np;
-    timer_begin("ccvv_adj_fp64", st);
-    hipLaunchKernelGGL(ccvv_adj_fp64_kernel, dim3((unsigned)pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv)), dim3(256), 0, st,
-                       ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, g, ws_d(ws, pl.off_gs),
-                       ws_d(ws, pl.off_slots));
-    timer_end(st);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  if (cavv) {
-    // G2 from batches of FP64 integrals; its padding rows and columns are
-    // never written by the epilogue but are read by the adjoint GEMMs
-    if ((e = zero_fill(ws_d(ws, pl.off_g2), Np * pl.na * pl.ntv * kPanel, st)) != hipSuccess)
-      return e;
-    for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
-      const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
-      if ((e = launch_cavv_x_fp64(pl, ws, (int)m0, mb, st)) != hipSuccess) return e;
-      if ((e = launch_cavv_adj_epi(pl, in, o, ws, (int)m0, mb, st)) != hipSuccess) return e;
-    }
-  }
-  if (ccav) {
+  if ((pl.terms & 4) && pl.na > 0) {
     switch (pl.na) {
-      case 1: e = launch_adj_act<1>(pl, in, g, ws, mask, st); break;
-      case 2: e = launch_adj_act<2>(pl, in, g, ws, mask, st); break;
-      case 3: e = launch_adj_act<3>(pl, in, g, ws, mask, st); break;
-      case 4: e = launch_adj_act<4>(pl, in, g, ws, mask, st); break;
-      case 5: e = launch_adj_act<5>(pl, in, g, ws, mask, st); break;
-      case 6: e = launch_adj_act<6>(pl, in, g, ws, mask, st); break;
-      case 7: e = launch_adj_act<7>(pl, in, g, ws, mask, st); break;
-      case 8: e = launch_adj_act<8>(pl, in, g, ws, mask, st); break;
+      case 1: e = launch_adj_act<1>(pl, in, g, ws, 4, st); break;
+      case 2: e = launch_adj_act<2>(pl, in, g, ws, 4, st); break;
+      case 3: e = launch_adj_act<3>(pl, in, g, ws, 4, st); break;
+      case 4: e = launch_adj_act<4>(pl, in, g, ws, 4, st); break;
+      case 5: e = launch_adj_act<5>(pl, in, g, ws, 4, st); break;
+      case 6: e = launch_adj_act<6>(pl, in, g, ws, 4, st); break;
+      case 7: e = launch_adj_act<7>(pl, in, g, ws, 4, st); break;
+      case 8: e = launch_adj_act<8>(pl, in, g, ws, 4, st); break;
       default: e = hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
@@ -604,46 +605,124 @@ hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const Bwd
   return hipSuccess;
 }
 
+// First energy slot of the CCVV block pair (I, J), I <= J: the pairs of the
+// block pairs before it in the order (0,0), (0,1), .., (0,ngb-1), (1,1), ..
+// times the tile pairs per core pair.
+int64_t ccvv_block_slot(const Plan &pl, int64_t I, int64_t J, int64_t tiles_per_pair) {
+  int64_t pairs = 0;
+  for (int64_t a = 0; a <= I; ++a)
+    for (int64_t b = a; b < pl.ngb; ++b) {
+      if (a == I && b == J) return pl.slot_base[0] + pairs * tiles_per_pair;
+      const int64_t na_ = std::min(pl.gb, pl.nc - a * pl.gb);
+      const int64_t nb_ = std::min(pl.gb, pl.nc - b * pl.gb);
+      pairs += (a == b) ? na_ * (na_ + 1) / 2 : na_ * nb_;
+    }
+  return -1;
+}
+
+// CCVV adjoint tiles of the core-orbital block pair (I, J) into the G block
+// (FP64 integrals), with their energies and eps / s parts.
+static hipError_t ccvv_adj_block_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                      int64_t I, int64_t J, hipStream_t st) {
+  GradOut g{o.deps_c, o.deps_a, o.deps_v, o.ds, o.gE};
+  CcvvAdjArgs a;
+  a.nc = (int)pl.nc;
+  a.nv = (int)pl.nv;
+  a.ntv = (int)pl.ntv;
+  a.naux_p = pl.naux_p;
+  a.s = pl.s;
+  a.r0 = (int)(I * pl.gb);
+  a.nr = (int)std::min(pl.gb, pl.nc - I * pl.gb);
+  a.c0 = (int)(J * pl.gb);
+  a.ncb = (int)std::min(pl.gb, pl.nc - J * pl.gb);
+  a.ld = (int64_t)a.ncb * pl.ntv * kPanel;
+  const int64_t T = pl.ntv * (pl.ntv + 1) / 2;
+  a.slot_base = ccvv_block_slot(pl, I, J, T);
+  const int64_t npair = (I == J) ? (int64_t)a.nr * (a.nr + 1) / 2 : (int64_t)a.nr * a.ncb;
+  timer_begin("ccvv_adj_fp64", st);
+  hipLaunchKernelGGL(ccvv_adj_fp64_kernel, dim3((unsigned)pairtile_grid(npair, pl.ntv)), dim3(256),
+                     0, st, ws_d(ws, pl.off_pcv), in.eps_c, in.eps_v, a, g, ws_d(ws, pl.off_gs),
+                     ws_d(ws, pl.off_slots));
+  timer_end(st);
+  return hipGetLastError();
+}
+
+// dB_cv = the adjoint products of the CCVV, CAVV and CCAV tiles (FP64): per
+// core block I the CAVV rows G2_I (dB_cv[I] += B_av G2_I^T, dB_av += B_cv[I]
+// G2_I), per block pair (I, J) the CCVV block G_IJ (dB_cv[J] += B_cv[I] G_IJ
+// and, off the diagonal, dB_cv[I] += B_cv[J] G_IJ^T), then the CCAV tiles G3
+// (dB_cv += B_ca G3^T, dB_ca = B_cv G3). Every output element is first
+// written, then accumulated in a fixed order.
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st) {
   hipError_t e;
-  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, kAllTerms, st)) != hipSuccess) return e;
+  if ((e = launch_adjoint_start_fp64(pl, in, o, ws, st)) != hipSuccess) return e;
   const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
-  const int64_t Np = pl.nc * pl.ntv * kPanel;
-  // ---- adjoint GEMMs ----
+  const int64_t W = pl.ntv * kPanel;
+  const int64_t Np = pl.nc * W, N2 = pl.na * W;
   const int64_t ldcv = pl.nc * pl.nv;
-  bool first = true;
-  if (pl.terms & 1) {
-    e = gemm<false>(pl, ws, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_gs), Np,
-                    Np, pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, false, st);
-    if (e != hipSuccess) return e;
-    first = false;
-  }
+  const int64_t pstride = pl.ntv * pl.naux_p * kPanel;   // doubles per core orbital of Pcv
+  const double *Pcv = ws_d(ws, pl.off_pcv);
+  bool written = false;   // dB_cv holds a first product in every block
+  auto blk = [&](int64_t I, int64_t &b0, int64_t &nb) {
+    b0 = I * pl.gb;
+    nb = std::min(pl.gb, pl.nc - b0);
+  };
   if (cavv) {
-    const int64_t N2 = pl.na * pl.ntv * kPanel;
-    e = gemm<true>(pl, ws, ws_d(ws, pl.off_pav), kPanel, pl.na * pl.ntv, ws_d(ws, pl.off_g2), Np,
-                   N2, pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, !first, st);
-    if (e != hipSuccess) return e;
-    first = false;
-    e = gemm<false>(pl, ws, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g2), N2,
-                    N2, pl.ntv * kPanel, pl.nv, o.dB_av, pl.na * pl.nv, false, st);
-    if (e != hipSuccess) return e;
+    double *G2 = ws_d(ws, pl.off_g2);
+    for (int64_t I = 0; I < pl.ngb; ++I) {
+      int64_t m0, mb;
+      blk(I, m0, mb);
+      // padding rows of G2 are read by the products, never written by the epilogue
+      if ((e = zero_fill(G2, mb * W * N2, st)) != hipSuccess) return e;
+      if ((e = launch_cavv_x_fp64(pl, ws, (int)m0, (int)mb, st)) != hipSuccess) return e;
+      if ((e = launch_cavv_adj_epi(pl, in, o, ws, (int)m0, (int)mb, st)) != hipSuccess) return e;
+      e = gemm<true>(pl, ws, ws_d(ws, pl.off_pav), kPanel, pl.na * pl.ntv, G2, mb * W, N2, W,
+                     pl.nv, o.dB_cv + m0 * pl.nv, ldcv, false, st);
+      if (e != hipSuccess) return e;
+      e = gemm<false>(pl, ws, Pcv + m0 * pstride, kPanel, mb * pl.ntv, G2, N2, N2, W, pl.nv,
+                      o.dB_av, pl.na * pl.nv, I > 0, st);
+      if (e != hipSuccess) return e;
+    }
+    written = true;
   } else if (o.dB_av) {
     if ((e = zero_fill(o.dB_av, pl.naux * pl.na * pl.nv, st)) != hipSuccess) return e;
+  }
+  if (pl.terms & 1) {
+    const double *G = ws_d(ws, pl.off_gs);
+    for (int64_t I = 0; I < pl.ngb; ++I)
+      for (int64_t J = I; J < pl.ngb; ++J) {
+        int64_t i0, ni, j0, nj;
+        blk(I, i0, ni);
+        blk(J, j0, nj);
+        if ((e = ccvv_adj_block_fp64(pl, in, o, ws, I, J, st)) != hipSuccess) return e;
+        // dB_cv[(j,b)] (+)= sum_(i,a) B_cv[(i,a)] G[(i,a)][(j,b)]; block J is
+        // first written by the pair (0, J)
+        e = gemm<false>(pl, ws, Pcv + i0 * pstride, kPanel, ni * pl.ntv, G, nj * W, nj * W, W,
+                        pl.nv, o.dB_cv + j0 * pl.nv, ldcv, written || I > 0, st);
+        if (e != hipSuccess) return e;
+        if (J > I) {
+          // dB_cv[(i,a)] += sum_(j,b) B_cv[(j,b)] G[(i,a)][(j,b)]
+          e = gemm<true>(pl, ws, Pcv + j0 * pstride, kPanel, nj * pl.ntv, G, ni * W, nj * W, W,
+                         pl.nv, o.dB_cv + i0 * pl.nv, ldcv, true, st);
+          if (e != hipSuccess) return e;
+        }
+      }
+    written = true;
   }
   if (ccav) {
     const int64_t N3 = pl.nc * kActPanel;
     e = gemm<true>(pl, ws, ws_d(ws, pl.off_pca), kActPanel, pl.nc, ws_d(ws, pl.off_g3), Np, N3,
-                   pl.ntv * kPanel, pl.nv, o.dB_cv, ldcv, !first, st);
+                   W, pl.nv, o.dB_cv, ldcv, written, st);
     if (e != hipSuccess) return e;
-    first = false;
-    e = gemm<false>(pl, ws, ws_d(ws, pl.off_pcv), kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g3), N3,
-                    N3, kActPanel, pl.na, o.dB_ca, pl.nc * pl.na, false, st);
+    written = true;
+    e = gemm<false>(pl, ws, Pcv, kPanel, pl.nc * pl.ntv, ws_d(ws, pl.off_g3), N3, N3, kActPanel,
+                    pl.na, o.dB_ca, pl.nc * pl.na, false, st);
     if (e != hipSuccess) return e;
   } else if (o.dB_ca) {
     if ((e = zero_fill(o.dB_ca, pl.naux * pl.nc * pl.na, st)) != hipSuccess) return e;
   }
-  if (first) {
+  if (!written) {
     if ((e = zero_fill(o.dB_cv, pl.naux * ldcv, st)) != hipSuccess) return e;
   }
   return hipSuccess;

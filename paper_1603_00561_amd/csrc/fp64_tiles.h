@@ -265,6 +265,54 @@ __device__ __forceinline__ bool decode_ccvv_list(int64_t kk, int x, int nc, int 
 }
 
 
+// The same work list over the core pairs of one block pair of core orbitals
+// (rows r0 .. r0+nr-1, columns c0 .. c0+ncb-1): a diagonal block (r0 == c0)
+// has the i < j pairs inside it and its self pairs, an off-diagonal block
+// (r0 + nr <= c0) the nr ncb pairs i < j across. slot counts from the block
+// pair's first item.
+__device__ __forceinline__ bool decode_ccvv_block_list(int64_t kk, int x, int r0, int nr, int c0,
+                                                       int ncb, int nt, CcvvWork &c,
+                                                       int64_t &slot) {
+  const bool diag = r0 == c0;
+  const int64_t P0 = diag ? (int64_t)nr * (nr - 1) / 2 : (int64_t)nr * ncb;
+  const int64_t nself = diag ? nr : 0;
+  const int64_t T0 = (int64_t)nt * (nt - 1) / 2, T = (int64_t)nt * (nt + 1) / 2;
+  const int64_t nlt = (P0 > x) ? (P0 - x + 7) / 8 : 0;
+  const int64_t first_eq = P0 + ((x - P0 % 8) + 8) % 8;   // first self pair on this XCD
+  const int64_t neq = (first_eq < P0 + nself) ? (P0 + nself - first_eq + 7) / 8 : 0;
+  int64_t p;
+  if (kk < nlt * T0) {
+    p = 8 * (kk / T0) + x;
+    decode_tile_blocked_lt(kk % T0, nt, c.A, c.B);
+    c.cls = 0;
+  } else if ((kk -= nlt * T0) < nlt * nt) {
+    p = 8 * (kk / nt) + x;
+    c.A = c.B = (int)(kk % nt);
+    c.cls = 1;
+  } else if ((kk -= nlt * nt) < neq * T) {
+    p = first_eq + 8 * (kk / T);
+    decode_tile_blocked(kk % T, nt, c.A, c.B);
+    c.cls = (c.A == c.B) ? 3 : 2;
+  } else {
+    return false;
+  }
+  if (p < P0) {
+    if (diag) {
+      int il, jl;
+      decode_pair_lt(p, nr, il, jl);
+      c.i = r0 + il;
+      c.j = r0 + jl;
+    } else {
+      c.i = r0 + (int)(p / ncb);
+      c.j = c0 + (int)(p % ncb);
+    }
+  } else {
+    c.i = c.j = r0 + (int)(p - P0);
+  }
+  slot = p * T + (int64_t)c.A * nt - (int64_t)c.A * (c.A - 1) / 2 + (c.B - c.A);
+  return true;
+}
+
 // Work list of a persistent producer over P pairs (all distinct) and tile
 // pairs A <= B of nt tiles, on XCD x (pairs p = x mod 8): first the A < B
 // items (two products) of its pairs, then the A = B items. Returns false past

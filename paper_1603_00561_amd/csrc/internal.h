@@ -47,6 +47,27 @@ inline int64_t adj_out_cols(int64_t ncols, int64_t GP, int64_t nvalid) {
   const int64_t rem = ncols % GP;
   return (ncols / GP) * nvalid + (rem < nvalid ? rem : nvalid);
 }
+// contraction indices per exact int32 segment of the int8 adjoint products
+// (|I_L| <= 4 127^2 kGemmSeg < 2^31)
+constexpr int64_t kGemmSeg = 32768;
+constexpr int64_t kQChunk = 32;   // contraction chunk of the int8 operand panels
+// K segments of an int8 adjoint product (128 x 128 output tiles): at least
+// enough for exact int32 sums, more when the output has too few tiles to
+// fill the chip; they always run side by side (partial products summed in a
+// fixed order). Returns the segment count and their length in chunks.
+inline int64_t i8_segments(int64_t rows, int64_t ncols, int64_t K, int64_t &segc) {
+  const int64_t nqc = ceil_div(K, kQChunk);
+  const int64_t want = adj_segments(rows, ncols, K);
+  const int64_t seg = kGemmSeg / kQChunk;
+  segc = ceil_div(nqc, want);
+  if (segc > seg) segc = seg;
+  if (segc < 1) segc = 1;
+  return ceil_div(nqc, segc);
+}
+// Bytes for the adjoint tiles of one block of core orbitals in the gradient:
+// the CCVV tiles of a block pair and the CAVV integrals with their adjoint
+// rows share one region, whose size bounds the core orbitals per block.
+constexpr int64_t kGradBlockBytes = (int64_t)1 << 30;
 
 // Everything the launchers need, derived once on the host from the problem.
 struct Plan {
@@ -75,7 +96,9 @@ struct Plan {
   int64_t cavv_mb;                    // core orbitals per CAVV integral batch
   size_t off_s8c, off_s8a, off_sigc, off_siga, off_diag, off_xb, off_scr;
   size_t off_xs;                      // per-workgroup x slots of the int8 CCVV kernel, then its work counters
-  size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only)
+  size_t off_gs, off_g2, off_g3;      // adjoint tiles (gradient only): Gs and G2 of one
+                                      // block of core orbitals (aliased with off_xb), G3 whole
+  int64_t gb = 0, ngb = 0;            // gradient: core orbitals per block, number of blocks
   size_t off_gpart = 0;               // per-segment partial adjoint products (FP64 gradient)
   int64_t gpart_doubles = 0;          // their capacity; 0: products are not split
   // int8 adjoint products (slice-path gradient): operand slices and scales
@@ -192,7 +215,7 @@ struct SemicanPlan {
 int64_t semican_npad(int64_t n);   // order of the padded Jacobi matrix of an n-orbital block
 constexpr int64_t kSemicanParts = 64;
 hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *C, double *U,
-                          double *eps, double *Cs, void *ws, hipStream_t st);
+                          double *eps, double *Cs, int *info, void *ws, hipStream_t st);
 // C = alpha op(A) op(B) + beta C, row-major FP64 on the matrix cores (dfgen.hip)
 hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                     const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
@@ -220,8 +243,9 @@ hipError_t launch_cavv_epi(const Plan &pl, const Inputs &in, void *ws, int m0, i
 hipError_t launch_cavv_x_split(const Plan &pl, void *ws, int m0, int mb, hipStream_t st);
 // FP64 integrals X^{mu}[e][f] = (me|uf) of core orbitals m0 .. m0+mb-1 into the batch buffer
 hipError_t launch_cavv_x_fp64(const Plan &pl, void *ws, int m0, int mb, hipStream_t st);
-// CAVV adjoint epilogue over one integral batch: G2, the CAVV energy slots and
-// the orbital-energy / flow-parameter gradient parts
+// CAVV adjoint epilogue over one integral batch: G2 (rows of the batch's core
+// orbitals only, (m - m0) 64 ntv + e), the CAVV energy slots and the
+// orbital-energy / flow-parameter gradient parts
 hipError_t launch_cavv_adj_epi(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                int m0, int mb, hipStream_t st);
 // int8 slices of B_cv (with the FP64 diagonal) and, if with_av, of B_av
@@ -229,8 +253,11 @@ hipError_t launch_slices(const Plan &pl, const Inputs &in, void *ws, bool with_a
                          hipStream_t st);
 // ---- adjoint (fp64_bwd.hip, split_bwd.hip) ----
 hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st);
-hipError_t launch_adjoint_tiles_fp64(const Plan &pl, const Inputs &in, const BwdOut &o,
-                                     void *ws, int mask, hipStream_t st);
+// gradients of eps and s cleared, FP64 panels packed, the CCAV adjoint tiles G3
+hipError_t launch_adjoint_start_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
+                                     hipStream_t st);
+// first energy slot of the CCVV block pair (I, J) with tiles_per_pair tile pairs per core pair
+int64_t ccvv_block_slot(const Plan &pl, int64_t I, int64_t J, int64_t tiles_per_pair);
 hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                 hipStream_t st);
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,

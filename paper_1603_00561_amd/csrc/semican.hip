@@ -144,6 +144,18 @@ __global__ void jac_reset_kernel(int *done) {
   if (threadIdx.x == 0) *done = 0;
 }
 
+// convergence status: info = 0 before the first block (a kernel, not a
+// memset, so the call can be captured in a graph)
+__global__ void jac_info_clear_kernel(int *info) {
+  if (threadIdx.x == 0) *info = 0;
+}
+
+// after the sweeps of a block: its bit of info set when the criterion was
+// never met (the flag is still clear)
+__global__ void jac_info_kernel(const int *__restrict__ done, int *__restrict__ info, int bit) {
+  if (threadIdx.x == 0 && *done == 0) atomicOr(info, bit);
+}
+
 // global index of row a (0..kJP-1) of the pair (I, J)
 __device__ __forceinline__ int64_t pair_index(int I, int J, int a) {
   return a < kJB ? (int64_t)I * kJB + a : (int64_t)J * kJB + (a - kJB);
@@ -315,7 +327,8 @@ __global__ void jac_check_final_kernel(const double *__restrict__ part, int whic
 // until the same criterion holds (at most kSmallSweeps), then A and V written
 // back
 __global__ __launch_bounds__(kJT) void jac_small_kernel(double *__restrict__ A,
-                                                        double *__restrict__ V) {
+                                                        double *__restrict__ V,
+                                                        int *__restrict__ info, int bit) {
   __shared__ JacLds L;
   const int t = threadIdx.x;
   for (int e = t; e < kJP * kJP; e += kJT) {
@@ -324,7 +337,8 @@ __global__ __launch_bounds__(kJT) void jac_small_kernel(double *__restrict__ A,
   }
   __syncthreads();
   int cur = 0;
-  for (int sw = 0; sw < kSmallSweeps; ++sw) {
+  bool conv = false;
+  for (int sw = 0; sw <= kSmallSweeps; ++sw) {
     double off = 0.0, tot = 0.0;
     for (int e = t; e < kJP * kJP; e += kJT) {
       const double v = L.S[cur][e / kJP][e % kJP] * L.S[cur][e / kJP][e % kJP];
@@ -333,9 +347,14 @@ __global__ __launch_bounds__(kJT) void jac_small_kernel(double *__restrict__ A,
     }
     off = jac_block_sum(off, L.red);
     tot = jac_block_sum(tot, L.red);
-    if (off <= kJacTol2 * tot) break;   // the same value in every thread
+    if (off <= kJacTol2 * tot) {   // the same value in every thread
+      conv = true;
+      break;
+    }
+    if (sw == kSmallSweeps) break;
     cur = jac_inner_sweep(L, cur);
   }
+  if (t == 0 && !conv && info) atomicOr(info, bit);
   for (int e = t; e < kJP * kJP; e += kJT) {
     A[e] = L.S[cur][e / kJP][e % kJP];
     V[e] = L.Q[e / kJP][e % kJP];
@@ -407,7 +426,7 @@ __global__ __launch_bounds__(kJT) void jac_finalize_kernel(const double *__restr
 int64_t semican_npad(int64_t n) { return std::max<int64_t>(kJP, round_up(n, kJP)); }
 
 hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *C, double *U,
-                          double *eps, double *Cs, void *ws, hipStream_t st) {
+                          double *eps, double *Cs, int *info, void *ws, hipStream_t st) {
   hipError_t e;
   const int64_t nmo = pl.nmo;
   double *Ab[2] = {ws_d(ws, pl.off_a), ws_d(ws, pl.off_a2)};
@@ -418,6 +437,10 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
                      dim3((unsigned)std::min<int64_t>(ceil_div(nmo * nmo, 256), 4096)), dim3(256),
                      0, st, F, nmo, pl.nfrz, pl.nfrz + pl.nc + pl.na + pl.nv, U, eps);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (info) {
+    hipLaunchKernelGGL(jac_info_clear_kernel, dim3(1), dim3(64), 0, st, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const char *names[3] = {"semican_core", "semican_active", "semican_virtual"};
   const int64_t sizes[3] = {pl.nc, pl.na, pl.nv};
   int64_t o = pl.nfrz;
@@ -433,7 +456,7 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
                        dim3(256), 0, st, F, nmo, o, n, npad, Ab[0], V);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (npad == kJP) {
-      hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(kJT), 0, st, Ab[0], V);
+      hipLaunchKernelGGL(jac_small_kernel, dim3(1), dim3(kJT), 0, st, Ab[0], V, info, 1 << blk);
     } else {
       hipLaunchKernelGGL(jac_reset_kernel, dim3(1), dim3(64), 0, st, done);
       const int npairs = nb / 2;
@@ -450,6 +473,7 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
                            npad, Pt, done);
         hipLaunchKernelGGL(jac_check_final_kernel, dim3(1), dim3(64), 0, st, Pt, cur, done);
       }
+      if (info) hipLaunchKernelGGL(jac_info_kernel, dim3(1), dim3(64), 0, st, done, info, 1 << blk);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(jac_finalize_kernel, dim3((unsigned)n), dim3(kJT), 0, st, Ab[0], Ab[1],

@@ -150,14 +150,12 @@ __global__ __launch_bounds__(256) void op_pack_kernel(OpMap m, int64_t R, int64_
 // workgroup (A tiles fastest, so the workgroups of one XCD share A panels).
 // Output column n is written at (n / GP) nvalid + n % GP and skipped when
 // n % GP >= nvalid (padding of the column blocks).
-constexpr int64_t kGemmSeg = 32768;   // contraction indices per exact int32 segment
-
 struct I8GemmArgs {
   int64_t tA;                 // 128-row tiles of A
-  int64_t nqc;                // 32-wide contraction chunks of the operand panels
-  int64_t qc0, nseg;          // chunks of this segment (segment blockIdx.y starts
-                              // segc chunks further; the last one may be shorter)
-  int64_t segc, zstride;      // with several segments: their length, output stride
+  int64_t nqc;                // 32-wide contraction chunks of the product (and of B's panels)
+  int64_t nqcA, qcA;          // chunks of A's panels, and A's chunk of contraction index 0
+  int64_t segc, zstride;      // segment blockIdx.y: chunks [y segc, (y + 1) segc) (the last
+                              // one may be shorter), output at y zstride
   int64_t M;                  // valid rows of A
   int64_t Ncols, GP, nvalid;  // padded output columns, their block width, valid per block
   int64_t ldc;
@@ -179,14 +177,14 @@ __global__ __launch_bounds__(512) void i8_gemm_kernel(const int8_t *__restrict__
   const int64_t ta = blockIdx.x % a.tA, tb = blockIdx.x / a.tA;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wr = wave >> 2, wc = wave & 3;
-  const int64_t ps = a.nqc * (int64_t)kSlicePanelChunk;
-  const int64_t qc0 = a.qc0 + (int64_t)blockIdx.y * a.segc;
-  const int64_t nsg = (a.nqc - qc0 < a.nseg) ? a.nqc - qc0 : a.nseg;
+  const int64_t psA = a.nqcA * (int64_t)kSlicePanelChunk, psB = a.nqc * (int64_t)kSlicePanelChunk;
+  const int64_t qc0 = (int64_t)blockIdx.y * a.segc;
+  const int64_t nsg = (a.nqc - qc0 < a.segc) ? a.nqc - qc0 : a.segc;
   C += (int64_t)blockIdx.y * a.zstride;
-  const int64_t off = qc0 * (int64_t)kSlicePanelChunk;
-  const int8_t *r0 = SA + 2 * ta * ps + off, *c0 = SB + 2 * tb * ps + off;
+  const int8_t *r0 = SA + 2 * ta * psA + (a.qcA + qc0) * (int64_t)kSlicePanelChunk;
+  const int8_t *c0 = SB + 2 * tb * psB + qc0 * (int64_t)kSlicePanelChunk;
   i16v ac[kI8Blocks][kSlices];
-  i8_tile_product(r0, r0 + ps, c0, c0 + ps, (int)nsg, lds, ac, wr, wc, lane);
+  i8_tile_product(r0, r0 + psA, c0, c0 + psB, (int)nsg, lds, ac, wr, wc, lane);
 #pragma unroll
   for (int q = 0; q < kI8Blocks; ++q) {
     double v[16];
@@ -223,8 +221,12 @@ struct CcvvAdjI8Args {
   int nc, nv, ntv_s;
   int64_t nqc;
   double s;
-  int64_t slot_base;
-  int64_t W, Np;   // Gs: padded virtual orbitals per core orbital, row length
+  int64_t slot_base;   // first energy slot of this block pair
+  int64_t W, ld;       // G block: padded virtual orbitals per core orbital, row length
+  // block pair of core orbitals (as for the FP64 adjoint tiles): rows (i, a)
+  // for i in [r0, r0 + nr), columns (j, b) for j in [c0, c0 + ncb); r0 == c0
+  // is a diagonal block, else only entries with row orbital i are stored
+  int r0, nr, c0, ncb;
 };
 
 __device__ __forceinline__ void store_transposed128(const double (*T)[kI8Tile + 1], double *dst,
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
   scalar_here(a.ntv_s);
   scalar_here(a.s);
   scalar_here(a.W);
-  scalar_here(a.Np);
+  scalar_here(a.ld);
   double (*T)[kI8Tile + 1] = reinterpret_cast<double (*)[kI8Tile + 1]>(lds);
   double *rsum = reinterpret_cast<double *>(lds) + kI8Tile * (kI8Tile + 1);
   double *csum = rsum + kI8Tile;
@@ -275,7 +277,7 @@ __global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
     if (threadIdx.x == 0) *next = atomicAdd(ctr + x, 1);
     __syncthreads();
     const int64_t kk = *next;
-    if (!decode_ccvv_list(kk, x, a.nc, nt, c, slot)) break;
+    if (!decode_ccvv_block_list(kk, x, a.r0, a.nr, a.c0, a.ncb, nt, c, slot)) break;
     double v[kI8Out];
     ccvv_i8_item(S8, sig, c, a.nqc, a.ntv_s, lds, xw, wr, wc, lane, v);
     if (c.cls == 1) {
@@ -289,7 +291,10 @@ __global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
     const double gE0 = gE[0];
     const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
     const double eij = eps_c[c.i] + eps_c[c.j];
-    const int64_t rowI = (int64_t)c.i * a.W, rowJ = (int64_t)c.j * a.W;
+    // G block rows (x, a) at (x - r0) W + a, columns (y, b) at (y - c0) W + b
+    const bool dblk = a.r0 == a.c0;   // a diagonal block
+    const int64_t rowI = (int64_t)(c.i - a.r0) * a.W, colJ = (int64_t)(c.j - a.c0) * a.W;
+    const int64_t rowJ = (int64_t)(c.j - a.r0) * a.W, colI = (int64_t)(c.i - a.c0) * a.W;
     double e_part = 0.0, d_part = 0.0, s_part = 0.0;
     double g1v[kI8Out], g2v[kI8Out];
 #pragma unroll
@@ -330,32 +335,36 @@ __global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
         const double g2 = 4.0 * gE0 * R * (2.0 * yv - xv);
         g1v[q * 16 + r] = g1;
         g2v[q * 16 + r] = g2;
-        Gs[(rowI + arow) * a.Np + rowJ + bcol] = g1;
-        if (c.cls <= 1) Gs[(rowJ + arow) * a.Np + rowI + bcol] = g2;
+        Gs[(rowI + arow) * a.ld + colJ + bcol] = g1;
+        if (dblk && c.cls <= 1) Gs[(rowJ + arow) * a.ld + colI + bcol] = g2;
       }
       if (cs != 0.0) atomicAdd(&csum[cl], cs);
     }
     const int rvalid = min(kI8Tile, a.nv - c.A * kI8Tile);
     const int cvalid = min(kI8Tile, a.nv - c.B * kI8Tile);
-    if (c.cls == 0 || c.cls == 2) {
-      // transposed blocks: Gs[(j,B)][(i,A)] = g1^T, then (class 0) Gs[(i,B)][(j,A)] = g2^T
+    if (c.cls == 0 || (dblk && c.cls == 2)) {
+      // transposed blocks: (diagonal block) G[(j,B)][(i,A)] = g1^T, then
+      // (class 0) G[(i,B)][(j,A)] = g2^T
       __syncthreads();   // class 1 has read T
+      if (dblk) {
 #pragma unroll
-      for (int q = 0; q < kI8Blocks; ++q)
+        for (int q = 0; q < kI8Blocks; ++q)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) T[i8_row(wr, q, lane, r)][i8_col(wc, q, lane)] = g1v[q * 16 + r];
-      __syncthreads();
-      store_transposed128(T, Gs + (rowJ + c.B * kI8Tile) * a.Np + rowI + c.A * kI8Tile, a.Np,
-                          rvalid, cvalid);
-      if (c.cls == 0) {
+          for (int r = 0; r < 16; ++r)
+            T[i8_row(wr, q, lane, r)][i8_col(wc, q, lane)] = g1v[q * 16 + r];
         __syncthreads();
+        store_transposed128(T, Gs + (rowJ + c.B * kI8Tile) * a.ld + colI + c.A * kI8Tile, a.ld,
+                            rvalid, cvalid);
+        __syncthreads();
+      }
+      if (c.cls == 0) {
 #pragma unroll
         for (int q = 0; q < kI8Blocks; ++q)
 #pragma unroll
           for (int r = 0; r < 16; ++r)
             T[i8_row(wr, q, lane, r)][i8_col(wc, q, lane)] = g2v[q * 16 + r];
         __syncthreads();
-        store_transposed128(T, Gs + (rowI + c.B * kI8Tile) * a.Np + rowJ + c.A * kI8Tile, a.Np,
+        store_transposed128(T, Gs + (rowI + c.B * kI8Tile) * a.ld + colJ + c.A * kI8Tile, a.ld,
                             rvalid, cvalid);
       }
     }
@@ -472,8 +481,9 @@ __global__ __launch_bounds__(256) void cavv_adj_epi_kernel(
       Cv[w] = ca;
       Cp[w] = cp;
     }
-    double *Gn = G2 + ((int64_t)m * a.W + e) * a.N2 + f;   // + w W
-    double *Gt = G2 + ((int64_t)m * a.W + f) * a.N2 + e;
+    // rows of the batch's core orbitals: (m - m0) W + e
+    double *Gn = G2 + ((int64_t)ml * a.W + e) * a.N2 + f;   // + w W
+    double *Gt = G2 + ((int64_t)ml * a.W + f) * a.N2 + e;
 #pragma unroll
     for (int w = 0; w < NA; ++w) {
       const double Wv = 2.0 * Xv[w] - Yv[w], Wp = 2.0 * Yv[w] - Xv[w];
@@ -590,61 +600,54 @@ static hipError_t pack_operand(const OpMap &m, int64_t R, int64_t K, double *sig
 hipError_t launch_adj_sum(const double *P, int nseg, int64_t rows, int64_t ncol, int64_t zstride,
                           double *C, int64_t ldc, bool accumulate, hipStream_t st);
 
-// C (+)= the exact int8 product, over K in segments of at most kGemmSeg. A
-// product with too few output tiles for the chip runs its segments side by
-// side (blockIdx.y, at most kGemmSeg long, at least 512) into partial
-// products in part (capacity part_doubles) that launch_adj_sum adds in a
-// fixed order; otherwise the segments follow each other, accumulating in C.
-static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, const int8_t *SB,
-                          const double *sigB, int64_t RB, int64_t K, int64_t M, int64_t Ncols,
-                          int64_t GP, int64_t nvalid, double *C, int64_t ldc, bool accumulate,
-                          double *part, int64_t part_doubles, hipStream_t st) {
+// C (+)= the exact int8 product of A (row panels SA, chunk stride nqcA, the
+// product's contraction starting at A's chunk qcA) and B (SB, K / 32 chunks),
+// over K in segments (i8_segments: at most kGemmSeg long for exact int32
+// sums, more when the output has too few tiles for the chip). With one
+// segment the product goes to C directly; with several they run side by side
+// (blockIdx.y) into partial products in part, which launch_adj_sum adds in a
+// fixed order.
+static hipError_t i8_gemm(const int8_t *SA, const double *sigA, int64_t RA, int64_t nqcA,
+                          int64_t qcA, const int8_t *SB, const double *sigB, int64_t RB,
+                          int64_t K, int64_t M, int64_t Ncols, int64_t GP, int64_t nvalid,
+                          double *C, int64_t ldc, bool accumulate, double *part,
+                          int64_t part_doubles, hipStream_t st) {
   I8GemmArgs a;
   a.tA = RA / kI8Tile;
   a.nqc = K / kQC;
+  a.nqcA = nqcA;
+  a.qcA = qcA;
   a.M = M;
   a.Ncols = Ncols;
   a.GP = GP;
   a.nvalid = nvalid;
   a.ldc = ldc;
-  a.segc = 0;
   a.zstride = 0;
   const int64_t grid = a.tA * (RB / kI8Tile);
-  const int64_t seg = kGemmSeg / kQC;
-  {
-    const int64_t want = adj_segments(M, Ncols, K);
-    const int64_t segc = std::min<int64_t>(seg, ceil_div(a.nqc, want));
-    const int64_t nz = ceil_div(a.nqc, segc);
-    const int64_t ncol = adj_out_cols(Ncols, GP, nvalid);
-    if (want > 1 && nz > 1 && part && nz * M * ncol <= part_doubles) {
-      a.qc0 = 0;
-      a.nseg = segc;
-      a.segc = segc;
-      a.ldc = ncol;
-      a.accumulate = 0;
-      a.zstride = M * ncol;
-      timer_begin("gemm_adj_i8", st);
-      hipLaunchKernelGGL(i8_gemm_kernel, dim3((unsigned)grid, (unsigned)nz), dim3(kI8Threads), 0,
-                         st, SA, sigA, SB, sigB, a, part);
-      hipError_t e = hipGetLastError();
-      if (e == hipSuccess)
-        e = launch_adj_sum(part, (int)nz, M, ncol, a.zstride, C, ldc, accumulate, st);
-      timer_end(st);
-      return e;
-    }
-  }
-  for (int64_t q0 = 0; q0 < a.nqc; q0 += seg) {
-    a.qc0 = q0;
-    a.nseg = (a.nqc - q0 < seg) ? a.nqc - q0 : seg;
-    a.accumulate = (accumulate || q0 > 0) ? 1 : 0;
-    timer_begin("gemm_adj_i8", st);
+  int64_t segc = 0;
+  const int64_t nz = i8_segments(M, Ncols, K, segc);
+  const int64_t ncol = adj_out_cols(Ncols, GP, nvalid);
+  a.segc = segc;
+  timer_begin("gemm_adj_i8", st);
+  hipError_t e;
+  if (nz == 1) {
+    a.accumulate = accumulate ? 1 : 0;
     hipLaunchKernelGGL(i8_gemm_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st, SA, sigA,
                        SB, sigB, a, C);
-    timer_end(st);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    e = hipGetLastError();
+  } else if (part && nz * M * ncol <= part_doubles) {
+    a.ldc = ncol;
+    a.accumulate = 0;
+    a.zstride = M * ncol;
+    hipLaunchKernelGGL(i8_gemm_kernel, dim3((unsigned)grid, (unsigned)nz), dim3(kI8Threads), 0,
+                       st, SA, sigA, SB, sigB, a, part);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_adj_sum(part, (int)nz, M, ncol, a.zstride, C, ldc, accumulate, st);
+  } else {
+    e = hipErrorInvalidValue;   // the plan sizes part for every product it makes
   }
-  return hipSuccess;
+  timer_end(st);
+  return e;
 }
 
 hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
@@ -654,40 +657,8 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
   const bool cavv = (pl.terms & 2) && pl.na > 0, ccav = (pl.terms & 4) && pl.na > 0;
   // gradients of eps and s cleared, G3 (with its eps / s parts) from the FP64
   // adjoint tiles
-  if ((e = launch_adjoint_tiles_fp64(pl, in, o, ws, 4, st)) != hipSuccess) return e;
+  if ((e = launch_adjoint_start_fp64(pl, in, o, ws, st)) != hipSuccess) return e;
   if ((e = launch_slices(pl, in, ws, cavv, st)) != hipSuccess) return e;
-  if (cavv) {
-    // G2 and the CAVV eps / s parts from batches of slice-path integrals
-    for (int64_t m0 = 0; m0 < pl.nc; m0 += pl.cavv_mb) {
-      const int mb = (int)((pl.nc - m0) < pl.cavv_mb ? (pl.nc - m0) : pl.cavv_mb);
-      if ((e = launch_cavv_x_split(pl, ws, (int)m0, mb, st)) != hipSuccess) return e;
-      if ((e = launch_cavv_adj_epi(pl, in, o, ws, (int)m0, mb, st)) != hipSuccess) return e;
-    }
-  }
-  if (pl.terms & 1) {
-    // Gs and the CCVV eps / s parts from the slice-path adjoint tiles
-    CcvvAdjI8Args a;
-    a.nc = (int)pl.nc;
-    a.nv = (int)pl.nv;
-    a.ntv_s = (int)pl.ntv_s;
-    a.nqc = pl.nqc;
-    a.s = pl.s;
-    a.slot_base = pl.slot_base[0];
-    a.W = pl.ntv * kPanel;
-    a.Np = pl.nc * a.W;
-    const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv_s / 2);
-    const int64_t grid = items < kSlicePersistWG ? items : kSlicePersistWG;
-    double *xs = ws_d(ws, pl.off_xs);
-    int *ctr = reinterpret_cast<int *>(xs + (size_t)kSlicePersistWG * kSliceXsDoubles);
-    if ((e = launch_zero(reinterpret_cast<double *>(ctr), 4, st)) != hipSuccess) return e;
-    timer_begin("ccvv_adj_i8", st);
-    hipLaunchKernelGGL(ccvv_adj_i8_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st,
-                       ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
-                       in.eps_c, in.eps_v, a, xs, ctr, o.deps_c, o.deps_v, o.ds, o.gE,
-                       ws_d(ws, pl.off_gs), ws_d(ws, pl.off_slots));
-    timer_end(st);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
   const int64_t W = pl.ntv * kPanel;             // padded virtual orbitals per orbital
   const int64_t Np = pl.nc * W, N2 = pl.na * W, N3 = pl.nc * kActPanel;
   const int64_t N3p = round_up(N3, kQC);
@@ -697,45 +668,110 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
   double *sigA1 = ws_d(ws, pl.off_sigA1), *sigA2 = ws_d(ws, pl.off_sigA2);
   double *sigB = ws_d(ws, pl.off_sigB);
   int8_t *SA1 = ws_b(ws, pl.off_SA1), *SA2 = ws_b(ws, pl.off_SA2), *SB = ws_b(ws, pl.off_SB);
-  const double *Gs = ws_d(ws, pl.off_gs), *G2 = ws_d(ws, pl.off_g2), *G3 = ws_d(ws, pl.off_g3);
+  const double *G3 = ws_d(ws, pl.off_g3);
   const int64_t ldcv = pl.nc * pl.nv;
+  const int64_t nqcp = Np / kQC;                 // chunks of A1 (a multiple of 2 per orbital)
+  auto blk = [&](int64_t I, int64_t &b0, int64_t &nb) {
+    b0 = I * pl.gb;
+    nb = std::min(pl.gb, pl.nc - b0);
+  };
 
-  // A1 = B_cv with rows Q and contraction index (m, e) over the padded range Np
+  // A1 = B_cv with rows Q and contraction index (m, e) over the padded range Np;
+  // a block of core orbitals is a contiguous range of its chunks
   const OpMap Acv = op_map(in.B_cv, big, pl.naux, 0, ldcv, pl.naux, W, pl.nv, pl.nv, 1, Np);
   if ((e = pack_operand(Acv, RA, Np, sigA1, pmax, SA1, st)) != hipSuccess) return e;
 
-  bool first = true;
-  if (pl.terms & 1) {
-    // dB_cv[Q][(m,e)] = sum_(j,b) B_cv[Q][(j,b)] Gs[(j,b)][(m,e)]   (Gs symmetric)
-    const int64_t RB = round_up(Np, kI8Tile);
-    const OpMap Bs = op_map(Gs, W, pl.nv, W, 1, Np, W, pl.nv, W * Np, Np, Np);
-    if ((e = pack_operand(Bs, RB, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
-    if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB, Np, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
-                     false, part, pl.gpart_doubles, st)) != hipSuccess)
-      return e;
-    first = false;
-  }
+  bool written = false;   // dB_cv holds a first product in every block
   if (cavv) {
-    // dB_cv[Q][(m,e)] += sum_(w,f) B_av[Q][(w,f)] G2[(m,e)][(w,f)]
+    // A2 = B_av with contraction index (w, f)
     const OpMap Aav = op_map(in.B_av, big, pl.naux, 0, pl.na * pl.nv, pl.naux, W, pl.nv, pl.nv,
                              1, N2);
     if ((e = pack_operand(Aav, RA, N2, sigA2, pmax, SA2, st)) != hipSuccess) return e;
-    const int64_t RB = round_up(Np, kI8Tile);
-    const OpMap B2t = op_map(G2, W, pl.nv, W * N2, N2, Np, W, pl.nv, W, 1, N2);
-    if ((e = pack_operand(B2t, RB, N2, sigB, pmax, SB, st)) != hipSuccess) return e;
-    if ((e = i8_gemm(SA2, sigA2, RA, SB, sigB, RB, N2, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
-                     !first, part, pl.gpart_doubles, st)) != hipSuccess)
-      return e;
-    first = false;
-    // dB_av[Q][(w,f)] = sum_(m,e) B_cv[Q][(m,e)] G2[(m,e)][(w,f)]
-    const int64_t RB2 = round_up(N2, kI8Tile);
-    const OpMap B2 = op_map(G2, W, pl.nv, W, 1, N2, W, pl.nv, W * N2, N2, Np);
-    if ((e = pack_operand(B2, RB2, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
-    if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB2, Np, pl.naux, N2, W, pl.nv, o.dB_av,
-                     pl.na * pl.nv, false, part, pl.gpart_doubles, st)) != hipSuccess)
-      return e;
+    const double *G2 = ws_d(ws, pl.off_g2);
+    for (int64_t I = 0; I < pl.ngb; ++I) {
+      int64_t m0, mb;
+      blk(I, m0, mb);
+      // G2 rows of this block and the CAVV eps / s parts from slice-path integrals
+      if ((e = launch_cavv_x_split(pl, ws, (int)m0, (int)mb, st)) != hipSuccess) return e;
+      if ((e = launch_cavv_adj_epi(pl, in, o, ws, (int)m0, (int)mb, st)) != hipSuccess) return e;
+      const int64_t Nb = mb * W;
+      // dB_cv[Q][(m,e)] (+)= sum_(w,f) B_av[Q][(w,f)] G2[(m,e)][(w,f)], m in the block
+      const int64_t RB = round_up(Nb, kI8Tile);
+      const OpMap B2t = op_map(G2, W, pl.nv, W * N2, N2, Nb, W, pl.nv, W, 1, N2);
+      if ((e = pack_operand(B2t, RB, N2, sigB, pmax, SB, st)) != hipSuccess) return e;
+      if ((e = i8_gemm(SA2, sigA2, RA, N2 / kQC, 0, SB, sigB, RB, N2, pl.naux, Nb, W, pl.nv,
+                       o.dB_cv + m0 * pl.nv, ldcv, false, part, pl.gpart_doubles, st)) != hipSuccess)
+        return e;
+      // dB_av[Q][(w,f)] (+)= sum_(m,e) B_cv[Q][(m,e)] G2[(m,e)][(w,f)], m in the block
+      const int64_t RB2 = round_up(N2, kI8Tile);
+      const OpMap B2 = op_map(G2, W, pl.nv, W, 1, N2, W, pl.nv, W * N2, N2, Nb);
+      if ((e = pack_operand(B2, RB2, Nb, sigB, pmax, SB, st)) != hipSuccess) return e;
+      if ((e = i8_gemm(SA1, sigA1, RA, nqcp, m0 * W / kQC, SB, sigB, RB2, Nb, pl.naux, N2, W,
+                       pl.nv, o.dB_av, pl.na * pl.nv, I > 0, part, pl.gpart_doubles, st)) !=
+          hipSuccess)
+        return e;
+    }
+    written = true;
   } else if (o.dB_av) {
     if ((e = launch_zero_fill(o.dB_av, pl.naux * pl.na * pl.nv, st)) != hipSuccess) return e;
+  }
+  if (pl.terms & 1) {
+    double *G = ws_d(ws, pl.off_gs);
+    const int64_t T = (pl.ntv_s / 2) * (pl.ntv_s / 2 + 1) / 2;
+    double *xs = ws_d(ws, pl.off_xs);
+    int *ctr = reinterpret_cast<int *>(xs + (size_t)kSlicePersistWG * kSliceXsDoubles);
+    for (int64_t I = 0; I < pl.ngb; ++I)
+      for (int64_t J = I; J < pl.ngb; ++J) {
+        int64_t i0, ni, j0, nj;
+        blk(I, i0, ni);
+        blk(J, j0, nj);
+        // the block's adjoint tiles and its CCVV eps / s parts from slice-path integrals
+        CcvvAdjI8Args a;
+        a.nc = (int)pl.nc;
+        a.nv = (int)pl.nv;
+        a.ntv_s = (int)pl.ntv_s;
+        a.nqc = pl.nqc;
+        a.s = pl.s;
+        a.slot_base = ccvv_block_slot(pl, I, J, T);
+        a.W = W;
+        a.ld = nj * W;
+        a.r0 = (int)i0;
+        a.nr = (int)ni;
+        a.c0 = (int)j0;
+        a.ncb = (int)nj;
+        const int64_t npair = (I == J) ? ni * (ni + 1) / 2 : ni * nj;
+        const int64_t items = pairtile_grid(npair, pl.ntv_s / 2);
+        const int64_t grid = items < kSlicePersistWG ? items : kSlicePersistWG;
+        if ((e = launch_zero(reinterpret_cast<double *>(ctr), 4, st)) != hipSuccess) return e;
+        timer_begin("ccvv_adj_i8", st);
+        hipLaunchKernelGGL(ccvv_adj_i8_kernel, dim3((unsigned)grid), dim3(kI8Threads), 0, st,
+                           ws_b(ws, pl.off_s8c), ws_d(ws, pl.off_sigc), ws_d(ws, pl.off_diag),
+                           in.eps_c, in.eps_v, a, xs, ctr, o.deps_c, o.deps_v, o.ds, o.gE, G,
+                           ws_d(ws, pl.off_slots));
+        timer_end(st);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t Ni = ni * W, Nj = nj * W, ld = Nj;
+        // dB_cv[Q][(j,b)] (+)= sum_(i,a) B_cv[Q][(i,a)] G[(i,a)][(j,b)]; block J is
+        // first written by the pair (0, J)
+        const int64_t RBj = round_up(Nj, kI8Tile);
+        const OpMap Bn = op_map(G, W, pl.nv, W, 1, Nj, W, pl.nv, W * ld, ld, Ni);
+        if ((e = pack_operand(Bn, RBj, Ni, sigB, pmax, SB, st)) != hipSuccess) return e;
+        if ((e = i8_gemm(SA1, sigA1, RA, nqcp, i0 * W / kQC, SB, sigB, RBj, Ni, pl.naux, Nj, W,
+                         pl.nv, o.dB_cv + j0 * pl.nv, ldcv, written || I > 0, part,
+                         pl.gpart_doubles, st)) != hipSuccess)
+          return e;
+        if (J > I) {
+          // dB_cv[Q][(i,a)] += sum_(j,b) B_cv[Q][(j,b)] G[(i,a)][(j,b)]
+          const int64_t RBi = round_up(Ni, kI8Tile);
+          const OpMap Bt = op_map(G, W, pl.nv, W * ld, ld, Ni, W, pl.nv, W, 1, Nj);
+          if ((e = pack_operand(Bt, RBi, Nj, sigB, pmax, SB, st)) != hipSuccess) return e;
+          if ((e = i8_gemm(SA1, sigA1, RA, nqcp, j0 * W / kQC, SB, sigB, RBi, Nj, pl.naux, Ni, W,
+                           pl.nv, o.dB_cv + i0 * pl.nv, ldcv, true, part, pl.gpart_doubles,
+                           st)) != hipSuccess)
+            return e;
+        }
+      }
+    written = true;
   }
   if (ccav) {
     // dB_cv[Q][(m,e)] += sum_(n,u) B_ca[Q][(n,u)] G3[(m,e)][(n,u)]
@@ -745,21 +781,21 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const int64_t RB = round_up(Np, kI8Tile);
     const OpMap B3t = op_map(G3, W, pl.nv, W * N3, N3, Np, kActPanel, pl.na, kActPanel, 1, N3);
     if ((e = pack_operand(B3t, RB, N3p, sigB, pmax, SB, st)) != hipSuccess) return e;
-    if ((e = i8_gemm(SA2, sigA2, RA, SB, sigB, RB, N3p, pl.naux, Np, W, pl.nv, o.dB_cv, ldcv,
-                     !first, part, pl.gpart_doubles, st)) != hipSuccess)
+    if ((e = i8_gemm(SA2, sigA2, RA, N3p / kQC, 0, SB, sigB, RB, N3p, pl.naux, Np, W, pl.nv,
+                     o.dB_cv, ldcv, written, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
-    first = false;
+    written = true;
     // dB_ca[Q][(n,u)] = sum_(m,e) B_cv[Q][(m,e)] G3[(m,e)][(n,u)]
     const int64_t RB3 = round_up(N3, kI8Tile);
     const OpMap B3 = op_map(G3, kActPanel, pl.na, kActPanel, 1, N3, W, pl.nv, W * N3, N3, Np);
     if ((e = pack_operand(B3, RB3, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
-    if ((e = i8_gemm(SA1, sigA1, RA, SB, sigB, RB3, Np, pl.naux, N3, kActPanel, pl.na, o.dB_ca,
-                     pl.nc * pl.na, false, part, pl.gpart_doubles, st)) != hipSuccess)
+    if ((e = i8_gemm(SA1, sigA1, RA, nqcp, 0, SB, sigB, RB3, Np, pl.naux, N3, kActPanel, pl.na,
+                     o.dB_ca, pl.nc * pl.na, false, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
   } else if (o.dB_ca) {
     if ((e = launch_zero_fill(o.dB_ca, pl.naux * pl.nc * pl.na, st)) != hipSuccess) return e;
   }
-  if (first) {
+  if (!written) {
     if ((e = launch_zero_fill(o.dB_cv, pl.naux * ldcv, st)) != hipSuccess) return e;
   }
   return hipSuccess;

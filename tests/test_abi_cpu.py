@@ -282,10 +282,10 @@ def test_semicanonicalize_entry_point_validation(lib):
     # three padded 32 x 32 Jacobi matrices at least
     assert out.value >= 3 * 8 * 32 * 32
 
-    def call(p, U=0x20000, eps=0x30000, Cs=0, opts=0, ws=0x40000, nb=1 << 40):
+    def call(p, U=0x20000, eps=0x30000, Cs=0, opts=0, ws=0x40000, nb=1 << 40, info=0):
         v = lambda x: ctypes.c_void_p(x) if x else None  # noqa: E731
-        return lib.dsrg_df_semicanonicalize(ctypes.byref(p), opts, v(U), v(eps), v(Cs), v(ws),
-                                            nb, None)
+        return lib.dsrg_df_semicanonicalize(ctypes.byref(p), opts, v(U), v(eps), v(Cs), v(info),
+                                            v(ws), nb, None)
 
     for kw in (dict(nmo=0), dict(nc=-1), dict(nmo=39)):
         assert call(prob(**kw)) == b.DSRG_ERR_ARG, kw
@@ -293,6 +293,7 @@ def test_semicanonicalize_entry_point_validation(lib):
     assert call(prob(F=0)) == b.DSRG_ERR_ARG
     assert call(prob(), U=0) == b.DSRG_ERR_ARG
     assert call(prob(), eps=0x30004) == b.DSRG_ERR_ARG
+    assert call(prob(), info=0x50002) == b.DSRG_ERR_ARG   # info must be 4-byte aligned
     assert call(prob(), Cs=0x50000) == b.DSRG_ERR_ARG                  # Cs without C
     assert call(prob(C=0x50000, nao=40)) == b.DSRG_ERR_ARG             # C without Cs
     assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG

@@ -93,6 +93,16 @@ def test_cfg2_sized_build():
     compare(gpu_factors(g), O.df_factors(g.ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv))
 
 
+def test_cfg3_orbital_spaces_large_tiles():
+    # the orbital spaces of the larger triple-zeta-shaped workload (10 frozen,
+    # 23 core, 2 active, 700 virtual: nao = nmo = 735) with 800 auxiliary
+    # functions: the second transform (20000 x 702) and the triangular
+    # application (800 x 17550) both take the 128 x 128 tile, as at the full
+    # 2000 auxiliary functions, with ragged tails in every index
+    g = make_dfgen_problem(10, 23, 2, 700, 800, seed=1603)
+    compare(gpu_factors(g), O.df_factors(g.ao3, g.J, g.C, g.nfrz, g.nc, g.na, g.nv))
+
+
 def test_reproducible_and_timing_option():
     g = make_dfgen_problem(2, 5, 3, 40, 70, seed=3)
     f1 = gpu_factors(g)

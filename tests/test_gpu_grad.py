@@ -57,6 +57,11 @@ def compare(g, ref, rel=REL):
     ((5, 6, 65, 33), (1.0, 0.75, -0.5)),
     ((1, 8, 40, 8), (1.0, 1.0, 1.0)),
     ((3, 0, 100, 24), (1.0, 1.0, 1.0)),
+    # adjoint products split over K (contraction nc 64 ceil(nv/64) >= 1024 with
+    # few output tiles): four equal segments in the CCVV, CAVV and CCAV
+    # products; then K = 1600 in segments 544 / 544 / 512 (a short last one)
+    ((9, 2, 200, 300), (1.0, 0.75, -0.5)),
+    ((5, 2, 300, 200), (1.0, 1.0, 1.0)),
 ])
 def test_small_gradients_against_oracle(shape, gE):
     p = make_problem(*shape, s=0.5, seed=sum(shape) + 11)
@@ -165,3 +170,38 @@ def test_autograd_function_matches_backward_entry_point():
                                                     "eps_v"), t[:6])}
     got["s"] = np.array([s.grad.item()])
     compare(got, ref)
+
+
+@pytest.mark.parametrize("shape,budget", [
+    ((7, 3, 100, 40), 2_400_000),     # CAVV-bound: blocks of 3, 3, 1 core orbitals
+    ((7, 0, 100, 40), 600_000),       # CCVV only: blocks of 2, 2, 2, 1
+    ((6, 2, 140, 70), 3_500_000),     # blocks of 2, 2, 2
+    ((9, 2, 200, 300), 8_000_000),    # blocks of 3, 3, 3; the CCAV products split over K
+])
+def test_gradient_in_core_blocks(shape, budget):
+    """A small bound on the gradient's adjoint-tile region splits the core
+    orbitals into blocks (block pairs for CCVV, blocks for CAVV); every
+    element against the oracle, and bitwise equal to itself run to run."""
+    b = _b()
+    old = b.set_gradient_block_bytes(budget)
+    try:
+        p = make_problem(*shape, s=0.5, seed=sum(shape) + 5)
+        gE = (1.0, 0.75, -0.5)
+        g = gpu_grad(p, gE)
+        g2 = gpu_grad(p, gE)
+    finally:
+        b.set_gradient_block_bytes(old)
+    compare(g, O.gradients(p, gE))
+    assert np.allclose(g["E"], O.energy_terms(p), rtol=0, atol=1e-12)
+    for k in ("B_cv", "B_ca", "B_av"):
+        assert np.array_equal(g[k], g2[k]), k
+
+
+def test_workspace_bound_and_block_count():
+    """The gradient workspace at the quintuple-zeta-shaped size stays far
+    below the nc^2 nv^2 doubles that all pair tiles would take."""
+    b = _b()
+    nc, na, nv, naux = 23, 6, 1100, 3000
+    ws = b.workspace_size(nc, na, nv, naux, with_grad=True)
+    all_tiles = 8 * (nc * 64 * 18) ** 2
+    assert ws < 2.5e9 < all_tiles, (ws, all_tiles)

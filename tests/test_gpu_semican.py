@@ -32,9 +32,11 @@ def synthetic_F(nmo, seed):
 def check(F, shape, C=None, **kw):
     nfrz, nc, na, nv = shape
     print(f"[gpu-semican] nfrz={nfrz} nc={nc} na={na} nv={nv} nmo={F.shape[0]} {kw}", flush=True)
+    info = torch.full((1,), -1, dtype=torch.int32, device="cuda")
     eps, U, Cs = _b().semicanonicalize(_dev(F), nfrz, nc, na, nv,
-                                       C=None if C is None else _dev(C), **kw)
+                                       C=None if C is None else _dev(C), info=info, **kw)
     torch.cuda.synchronize()
+    assert int(info.item()) == 0, int(info.item())   # every block met the criterion
     eps, U = eps.cpu().numpy(), U.cpu().numpy()
     e_ref, U_ref = O.semicanonicalize(F, nfrz, nc, na, nv)
     scale = np.abs(F).max()
@@ -100,3 +102,73 @@ def test_reproducible_and_timing_option():
     names = [n for n, _ in _b().kernel_times(64)]
     for k in ("semican_core", "semican_active", "semican_virtual"):
         assert k in names, (k, names)
+
+
+def test_cfg5_sized_virtual_block():
+    # 1100 virtual orbitals (seventy 16-wide Jacobi blocks) beside 23 core and
+    # 6 active orbitals
+    F = synthetic_F(10 + 23 + 6 + 1100, seed=1605)
+    check(F, (10, 23, 6, 1100))
+
+
+def degenerate_F(shape, seed):
+    """A Fock matrix whose core, active and virtual blocks have exactly
+    repeated and tightly clustered eigenvalues (random orthogonal eigenvectors),
+    with random couplings between the blocks and to the frozen orbitals."""
+    rng = np.random.default_rng(seed)
+    nfrz, nc, na, nv = shape
+    n = sum(shape)
+    F = 0.05 * rng.standard_normal((n, n))
+    F = F + F.T
+    o = nfrz
+    for k in (nc, na, nv):
+        if k:
+            lam = np.sort(rng.uniform(-3, 3, k))
+            lam[k // 4:k // 4 + max(1, k // 5)] = lam[k // 4]           # an exact multiplet
+            if k > 6:
+                lam[-4:] = lam[-4] + np.array([0.0, 1e-13, 2e-12, 3e-10])   # a tight cluster
+            Q, R = np.linalg.qr(rng.standard_normal((k, k)))
+            F[o:o + k, o:o + k] = (Q * lam) @ Q.T
+            F[o:o + k, o:o + k] = 0.5 * (F[o:o + k, o:o + k] + F[o:o + k, o:o + k].T)
+        o += k
+    return F
+
+
+@pytest.mark.parametrize("shape", [(2, 12, 4, 30), (1, 40, 6, 150), (0, 23, 2, 380)])
+def test_degenerate_and_clustered_spectra_validity(shape):
+    """Where eigenvalues repeat, many U are correct: judge U by what defines it
+    (F U = U diag(eps) per block, orthogonality, block structure, ascending
+    order, the sign convention, frozen orbitals untouched) and eps against the
+    oracle's eigenvalues, not U against the oracle's U."""
+    nfrz, nc, na, nv = shape
+    F = degenerate_F(shape, seed=sum(shape))
+    n = F.shape[0]
+    print(f"[gpu-semican] degenerate nfrz={nfrz} nc={nc} na={na} nv={nv}", flush=True)
+    info = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+    eps, U, _ = _b().semicanonicalize(_dev(F), nfrz, nc, na, nv, info=info)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0, int(info.item())
+    eps, U = eps.cpu().numpy(), U.cpu().numpy()
+    e_ref, _ = O.semicanonicalize(F, nfrz, nc, na, nv)
+    scale = np.abs(F).max()
+    assert np.abs(eps - e_ref).max() <= 1e-11 * scale, np.abs(eps - e_ref).max()
+    assert np.abs(U.T @ U - np.eye(n)).max() <= 1e-12
+    assert np.array_equal(U[:nfrz, :], np.eye(n)[:nfrz, :])
+    assert np.array_equal(eps[:nfrz], np.diag(F)[:nfrz])
+    o = nfrz
+    for k in (nc, na, nv):
+        b = slice(o, o + k)
+        Ub = U[b, b]
+        # block-diagonal: nothing couples this block to another one
+        off = U[b, :].copy()
+        off[:, b] = 0.0
+        assert np.abs(off).max(initial=0.0) == 0.0
+        resid = F[b, b] @ Ub - Ub * eps[b][None, :]
+        assert np.abs(resid).max(initial=0.0) <= 1e-11 * scale, np.abs(resid).max()
+        assert np.all(np.diff(eps[b]) >= 0.0)
+        for c in range(k):
+            col = np.abs(Ub[:, c])
+            top = np.sort(col)[-2:] if k > 1 else col
+            if k == 1 or top[-1] - top[0] > 1e-9:   # a unique largest component
+                assert Ub[np.argmax(col), c] > 0.0
+        o += k

@@ -172,10 +172,32 @@ def test_naux_limit_near_worst_case_level_sums():
 
 def test_adjoint_gemm_contraction_segments():
     """nc = 513 core orbitals with nv = 8: the padded core-virtual index runs to
-    513 * 64 = 32832 > 32768, so the int8 adjoint products over it are taken in
-    two exact int32 segments whose FP64 results are summed."""
+    513 * 64 = 32832 > 32768, so the int8 product dE/dB_ca over it is split
+    into exact int32 segments (run side by side, their FP64 results summed in
+    order); the CCVV tiles come in three blocks of 171 core orbitals."""
     p = make_problem(513, 1, 8, 8, s=0.5, seed=41)
     assert p.nc * 64 > 32768
     gE = (1.0, 0.75, -0.5)
     g = split_grad(p, gE)
     compare(g, O.gradients(p, gE))
+
+
+@pytest.mark.parametrize("shape,budget,blocks", [
+    ((7, 3, 100, 40), 2_400_000, (3, 3, 1)),     # CAVV-bound: three blocks, a ragged last one
+    ((7, 0, 100, 40), 600_000, (2, 2, 2, 1)),    # CCVV only: four blocks
+    ((6, 2, 140, 70), 3_500_000, (2, 2, 2)),
+])
+def test_gradient_in_core_blocks(shape, budget, blocks):
+    """A small bound on the gradient's adjoint-tile region splits the core
+    orbitals into blocks (block pairs for CCVV, blocks for CAVV); every
+    element against the oracle."""
+    b = _b()
+    old = b.set_gradient_block_bytes(budget)
+    try:
+        p = make_problem(*shape, s=0.5, seed=sum(shape) + 5)
+        gE = (1.0, 0.75, -0.5)
+        g = split_grad(p, gE)
+    finally:
+        b.set_gradient_block_bytes(old)
+    compare(g, O.gradients(p, gE))
+    assert np.allclose(g["E"], O.energy_terms(p), rtol=0, atol=1e-6)
