@@ -256,8 +256,10 @@ dsrg_status dsrg_df_semicanonicalize_workspace_size(const dsrg_semican_problem *
 
 /* U [nmo][nmo], eps [nmo] and, when C and Cs are both given, Cs = C U
  * [nao][nmo] (device, FP64). Jacobi rotations to an off-diagonal norm below
- * 1e-14 of the block's norm, or 12 block sweeps at most (blocks of up to 32
- * orbitals: 40 sweeps at most).
+ * 1e-14 of the block's norm, or 40 block sweeps at most (a random spectrum
+ * takes about 8, one with large exactly degenerate multiplets converges
+ * linearly and takes 20-25; blocks of up to 32 orbitals: 40 inner sweeps at
+ * most). The launches of the sweeps after convergence return at once.
  *   info  optional device int [1] (NULL = not wanted, 4-byte aligned): once
  *         the call's work has run, the bit mask of the blocks whose
  *         off-diagonal norm never met the criterion (bit 0 core, bit 1
