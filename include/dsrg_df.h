@@ -131,6 +131,25 @@ dsrg_status dsrg_df_energy(const dsrg_df_problem *p, int precision, int terms,
                            double *E_terms, void *workspace, size_t ws_bytes,
                            void *stream);
 
+/* dsrg_df_energy without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation). The workspace is the library's own
+ * static device array of DSRG_DF_NOALLOC_SCRATCH_BYTES per GPU, which each
+ * GPU the library runs on holds until the process ends; the call allocates
+ * nothing (the array's device address is looked up once per device, on the
+ * first call made with that device current).
+ *   E_terms  device [3], as for dsrg_df_energy.
+ * Problems whose workspace (dsrg_df_workspace_size with with_grad == 0)
+ * exceeds the array return DSRG_ERR_UNSUPPORTED without enqueuing anything.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (on different streams or host threads) race and must not be
+ * made; calls ordered on one stream are safe (each clears what it needs).
+ * DSRG_OPT_KERNEL_TIMING is refused (DSRG_ERR_ARG). Otherwise as
+ * dsrg_df_energy, with the same results. */
+#define DSRG_DF_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+dsrg_status dsrg_df_energy_noalloc(const dsrg_df_problem *p, int precision, int terms,
+                                   double *E_terms, void *stream);
+
 /* Gradient of L = sum_t gE[t] * E_t with respect to every input that the
  * energy depends on (the adjoint of dsrg_df_energy; amplitudes are
  * recomputed, never stored).

@@ -23,7 +23,8 @@ OPT_ATOMIC_REDUCE = 0x100
 OPT_KERNEL_TIMING = 0x200
 MAX_ACTIVE = 8
 
-EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_backward",
+EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_noalloc",
+            "dsrg_df_energy_backward",
             "dsrg_df_active_workspace_size", "dsrg_df_energy_active",
             "dsrg_df_factors_workspace_size", "dsrg_df_factors",
             "dsrg_df_fock_workspace_size", "dsrg_df_fock",
@@ -90,6 +91,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_workspace_size.restype = i32
     lib.dsrg_df_energy.argtypes = [ctypes.POINTER(Problem), i32, i32, vp, vp, sz, vp]
     lib.dsrg_df_energy.restype = i32
+    lib.dsrg_df_energy_noalloc.argtypes = [ctypes.POINTER(Problem), i32, i32, vp, vp]
+    lib.dsrg_df_energy_noalloc.restype = i32
     lib.dsrg_df_energy_backward.argtypes = [ctypes.POINTER(Problem), i32, i32, vp,
                                             vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dsrg_df_energy_backward.restype = i32
@@ -271,6 +274,21 @@ def energy(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
     E = torch.empty(3, dtype=torch.float64, device=dev) if out is None else out
     _check(lib.dsrg_df_energy(ctypes.byref(p), prec, mask, E.data_ptr(), ws.data_ptr(),
                               nbytes.value, _stream_handle(dev)))
+    del keep
+    return E
+
+
+def energy_noalloc(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
+                   terms="all", atomic=False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """E_CCVV, E_CAVV, E_CCAV via dsrg_df_energy_noalloc (the library's static
+    device scratch instead of a workspace; out, when given, is written in place)."""
+    lib = load_library()
+    p, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s)
+    dev = B_cv.device
+    mask = _terms_mask(terms, atomic, False)
+    E = torch.empty(3, dtype=torch.float64, device=dev) if out is None else out
+    _check(lib.dsrg_df_energy_noalloc(ctypes.byref(p), PRECISIONS[precision], mask, E.data_ptr(),
+                                      _stream_handle(dev)))
     del keep
     return E
 

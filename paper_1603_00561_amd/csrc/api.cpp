@@ -15,6 +15,9 @@ namespace {
 
 thread_local char g_err[512] = "";
 
+static_assert(DSRG_DF_NOALLOC_SCRATCH_BYTES == dsrg::kNoAllocScratchBytes,
+              "the header states the static scratch size");
+
 // bound on the gradient's per-block adjoint-tile region (process-wide)
 std::atomic<int64_t> g_grad_block_bytes{dsrg::kGradBlockBytes};
 
@@ -542,6 +545,35 @@ dsrg_status dsrg_df_energy(const dsrg_df_problem *p, int precision, int terms, d
   hipError_t e = (precision == DSRG_SPLIT_OZAKI) ? dsrg::launch_energy_split(pl, in, workspace, hs)
                                                  : dsrg::launch_energy_fp64(pl, in, workspace, hs);
   if (e == hipSuccess) e = dsrg::launch_finalize(pl, workspace, E_terms, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_energy_noalloc(const dsrg_df_problem *p, int precision, int terms,
+                                   double *E_terms, void *stream) {
+  g_err[0] = 0;
+  if (terms & DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "DSRG_OPT_KERNEL_TIMING is not available without allocation");
+  dsrg::Plan pl;
+  dsrg_status st = make_plan(p, precision, terms, 0, pl);
+  if (st != DSRG_OK) return st;
+  if ((st = check_inputs(p, pl)) != DSRG_OK) return st;
+  if (!E_terms || !aligned8(E_terms)) return fail(DSRG_ERR_ARG, "E_terms is NULL or misaligned");
+  if (pl.total > dsrg::kNoAllocScratchBytes)
+    return fail(DSRG_ERR_UNSUPPORTED,
+                "problem needs %zu bytes of workspace, more than the %zu of the static scratch "
+                "(use dsrg_df_energy with a workspace)",
+                pl.total, dsrg::kNoAllocScratchBytes);
+  void *ws = nullptr;
+  hipError_t e = dsrg::noalloc_scratch(&ws);
+  if (e != hipSuccess)
+    return fail(DSRG_ERR_HIP, "static scratch lookup failed: %s", hipGetErrorString(e));
+  dsrg::Inputs in{p->B_cv, p->B_ca, p->B_av, p->eps_c, p->eps_a, p->eps_v, p->gamma1};
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset(false);
+  e = (precision == DSRG_SPLIT_OZAKI) ? dsrg::launch_energy_split(pl, in, ws, hs)
+                                      : dsrg::launch_energy_fp64(pl, in, ws, hs);
+  if (e == hipSuccess) e = dsrg::launch_finalize(pl, ws, E_terms, hs);
   if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return DSRG_OK;
 }

@@ -159,6 +159,12 @@ struct DFOutputs {
   double *B_cv, *B_ca, *B_av, *B_aa;
 };
 
+// ---- the library's static device scratch (noalloc.hip) ----
+// Capacity of the array behind dsrg_df_energy_noalloc (bytes, per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+// Device address of the current device's array (looked up once per device).
+hipError_t noalloc_scratch(void **ptr);
+
 // ---- per-kernel timing (api.cpp); no-ops unless the call asked for it ----
 void timer_begin(const char *name, hipStream_t st);
 void timer_end(hipStream_t st);
