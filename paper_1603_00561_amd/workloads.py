@@ -155,6 +155,80 @@ def make_near_degenerate(nc: int = 3, na: int = 2, nv: int = 20, naux: int = 48,
                    gamma1, float(s), "near_degenerate", seed, B_aa=B_aa)
 
 
+def _annihilators(n: int):
+    """Annihilation operators a_p (p < n) on the 2^n-dimensional Fock space in
+    the occupation-number basis (Jordan-Wigner signs), as sparse matrices."""
+    import scipy.sparse as sp
+    dim = 1 << n
+    st = np.arange(dim)
+    ops = []
+    for p in range(n):
+        cols = st[((st >> p) & 1) == 1]
+        below = np.array([bin(int(c) & ((1 << p) - 1)).count("1") for c in cols], dtype=np.int64)
+        vals = np.where(below % 2 == 1, -1.0, 1.0)
+        ops.append(sp.csr_matrix((vals, (cols ^ (1 << p), cols)), shape=(dim, dim)))
+    return ops
+
+
+def cas_reference_rdms(rng: np.random.Generator, na: int, nel: int):
+    """Reduced density matrices of a random singlet reference of nel (even)
+    electrons in na active orbitals, over the spin orbitals 2u + s (s = 0
+    alpha, 1 beta): a standard-normal vector over the determinants with equal
+    alpha and beta counts, projected onto the kernel of the spin-raising
+    operator sum_u a+_{u alpha} a_{u beta} (total spin 0) and normalized.
+    Returns rdm1[p,q] = <a+_p a_q>, rdm2[p,q,r,s] = <a+_p a+_q a_s a_r> and
+    rdm3[p,q,r,s,t,u] = <a+_p a+_q a+_r a_u a_t a_s>."""
+    if nel % 2 or not 0 <= nel <= 2 * na:
+        raise ValueError("a singlet needs an even electron count between 0 and 2 na")
+    n = 2 * na
+    if n == 0:
+        return np.zeros((0, 0)), np.zeros((0,) * 4), np.zeros((0,) * 6)
+    a = _annihilators(n)
+    st = np.arange(1 << n)
+    nal = np.array([bin(int(x) & int("01" * na, 2)).count("1") for x in st])
+    nbe = np.array([bin(int(x)).count("1") for x in st]) - nal
+    sector = np.nonzero((nal + nbe == nel) & (nal == nbe))[0]
+    raised = np.nonzero((nal + nbe == nel) & (nal == nbe + 2))[0]
+    psi_s = rng.standard_normal(len(sector))
+    if len(raised):
+        splus = sum(a[2 * u].T @ a[2 * u + 1] for u in range(na)).tocsr()
+        S = splus[raised][:, sector].toarray()
+        _, sv, vt = np.linalg.svd(S, full_matrices=True)
+        null = vt[int(np.sum(sv > 1e-10 * sv.max())):]
+        psi_s = null.T @ (null @ psi_s)
+    psi = np.zeros(1 << n)
+    psi[sector] = psi_s / np.linalg.norm(psi_s)
+    V1 = np.array([a[x] @ psi for x in range(n)])
+    V2 = np.array([a[y] @ V1[x] for x in range(n) for y in range(n)])
+    V3 = np.array([a[z] @ V2[x * n + y] for x in range(n) for y in range(n) for z in range(n)])
+    rdm1 = V1 @ V1.T
+    rdm2 = (V2 @ V2.T).reshape((n,) * 4)
+    rdm3 = (V3 @ V3.T).reshape((n,) * 6)
+    return rdm1, rdm2, rdm3
+
+
+def make_rest_problem(nc: int, na: int, nv: int, naux: int, s: float = 0.5,
+                      seed: int = DEFAULT_SEED, nel: Optional[int] = None,
+                      name: str = "custom") -> Problem:
+    """Inputs of the Table I terms A-E and G-K: the problem of make_problem
+    (same seed, same draws), then from default_rng([seed, 2]) the first-order
+    Fock blocks f_ca [nc][na], f_cv [nc][nv], f_av [na][nv] ~ N(0,1) * 0.05
+    (the off-diagonal blocks of the generalized Fock matrix in the
+    semicanonical basis) and a random singlet reference of nel electrons
+    (default na, half filling as in the paper's CAS(n,n)) in the active
+    orbitals, whose spin-orbital density matrices rdm1, rdm2, rdm3 are stored
+    and whose spin-summed one-body density replaces gamma1."""
+    p = make_problem(nc, na, nv, naux, s=s, seed=seed, name=name)
+    rng = np.random.default_rng([seed, 2])
+    p.f_ca = rng.standard_normal((nc, na)) * 0.05
+    p.f_cv = rng.standard_normal((nc, nv)) * 0.05
+    p.f_av = rng.standard_normal((na, nv)) * 0.05
+    nel = na if nel is None else nel
+    p.rdm1, p.rdm2, p.rdm3 = cas_reference_rdms(rng, na, nel)
+    p.gamma1 = np.ascontiguousarray(p.rdm1[0::2, 0::2] + p.rdm1[1::2, 1::2])
+    return p
+
+
 @dataclass
 class DFGenProblem:
     """Inputs of the density-fitting factor build (Eq. int_fact and the DF
