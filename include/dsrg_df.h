@@ -199,6 +199,59 @@ dsrg_status dsrg_df_energy_active(const dsrg_df_problem *p, const double *B_aa, 
                                   double *F_terms, void *workspace, size_t ws_bytes,
                                   void *stream);
 
+/* ---- The other terms of the second-order energy (Table I): A, B, C, D, E,
+ * G, H, I, J, K ----
+ * With X_{p..}^{q..} the coefficient of a+_p .. a_q .. (lower indices
+ * created, upper annihilated), gamma_p^q = <a+_p a_q>, eta = 1 - gamma, the
+ * two- and three-body cumulants lambda of section II.A, holes i, j, k, l in
+ * C + A, particles a, b, c, d in A + V, core m, virtual e, active u..z, the
+ * terms are, in spin orbitals (2k + s for spatial orbital k and spin s),
+ *   A = f~_j^b t_a^i gamma_j^i eta_a^b
+ *   B = 1/2 v~_{xy}^{ev} t_e^u lambda_{xy}^{uv}    C = -1/2 v~_{my}^{uv} t_x^m lambda_{xy}^{uv}
+ *   D = 1/2 f~_x^e t_{ey}^{uv} lambda_{xy}^{uv}    E = -1/2 f~_m^v t_{xy}^{um} lambda_{xy}^{uv}
+ *   G = 1/8 v~_{xy}^{cd} t_{ab}^{uv} eta_a^c eta_b^d lambda_{xy}^{uv}
+ *   H = 1/8 v~_{kl}^{uv} t_{xy}^{ij} gamma_k^i gamma_l^j lambda_{xy}^{uv}
+ *   I = v~_{jx}^{bu} t_{ay}^{iv} gamma_j^i eta_a^b lambda_{xy}^{uv}
+ *   J = 1/4 v~_{mz}^{uv} t_{xy}^{mw} lambda_{xyz}^{uvw}   K = 1/4 v~_{xy}^{we} t_{ez}^{uv} lambda_{xyz}^{uvw}
+ * with t_{ab}^{ij} = <ab||ij> R1(D^{ij}_{ab}) (Eq. T2amp), v~ = <ab||ij>
+ * S(D^{ij}_{ab}) (Eq. v_tilde), t_a^i = [f_a^i + sum_ux D_u^x t_{ax}^{iu}
+ * gamma_x^u] R1(D_a^i) (Eq. T1amp, D_u^x = e_x - e_u), f~_a^i = f_a^i S(D) +
+ * [sum_ux D_u^x t_{ax}^{iu} gamma_x^u] exp(-s D^2) (Eq. f_tilde), the all-
+ * active amplitudes excluded, restricted orbitals (<pq||rs> from (pq|rs) =
+ * sum_Q B^Q_pq B^Q_rs). Term F is dsrg_df_energy plus dsrg_df_energy_active
+ * (F1..F8). FP64. */
+typedef struct {
+  dsrg_df_problem base;     /* sizes, B_cv, B_ca, B_av, eps_c, eps_a, eps_v and s as for
+                               dsrg_df_energy (gamma1 is not read)                        */
+  const double *B_aa;       /* [naux][na][na] B^Q_{uv}, symmetric in u, v                  */
+  const double *f_ca;       /* [nc][na] first-order Fock elements f_{mu}: the off-diagonal */
+  const double *f_cv;       /* [nc][nv] blocks of the generalized Fock matrix in the       */
+  const double *f_av;       /* [na][nv] semicanonical basis                                */
+  const double *rdm1;       /* [2na][2na] active spin-orbital <a+_p a_q> (p = 2u + spin)   */
+  const double *lambda2;    /* [2na]^4 lambda_{pq}^{rs} at [p][q][r][s]                    */
+  const double *lambda3;    /* [2na]^6 lambda_{pqr}^{stu} at [p][q][r][s][t][u]            */
+} dsrg_df_rest_problem;
+
+/* Bytes of device workspace that dsrg_df_energy_rest needs (sizes only). */
+dsrg_status dsrg_df_rest_workspace_size(const dsrg_df_rest_problem *p, size_t *bytes);
+
+/* terms device [10]: A, B, C, D, E, G, H, I, J, K in Eh (all 0 when na == 0).
+ * options 0 or DSRG_OPT_KERNEL_TIMING. na <= DSRG_DF_MAX_ACTIVE. Errors as
+ * for dsrg_df_energy. */
+dsrg_status dsrg_df_energy_rest(const dsrg_df_rest_problem *p, int options, double *terms,
+                                void *workspace, size_t ws_bytes, void *stream);
+
+/* Cumulants of section II.A from the active spin-orbital reduced density
+ * matrices (2 na spin orbitals, device arrays):
+ *   rdm1 [2na][2na] <a+_p a_q>, rdm2 [2na]^4 <a+_p a+_q a_s a_r> at [p][q][r][s],
+ *   rdm3 [2na]^6 <a+_p a+_q a+_r a_u a_t a_s> at [p][q][r][s][t][u];
+ *   lambda2 = rdm2 - rdm1 ^ rdm1, lambda3 = rdm3 - (antisymmetrized rdm1
+ *   lambda2) - (antisymmetrized rdm1 rdm1 rdm1), written to lambda2 [2na]^4 and
+ *   lambda3 [2na]^6 (device). 1 <= na <= DSRG_DF_MAX_ACTIVE. */
+dsrg_status dsrg_df_cumulants(int64_t na, const double *rdm1, const double *rdm2,
+                              const double *rdm3, double *lambda2, double *lambda3,
+                              void *stream);
+
 /* ---- Density-fitting factors (Eq. int_fact and the DF definition of
  * section II.C): B^Q_pq = sum_P [J^{-1/2}]_{QP} (pq|P) with the MO
  * three-index integrals (pq|P) = sum_{mu nu} C_{mu p} C_{nu q} (mu nu|P).

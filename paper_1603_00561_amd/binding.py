@@ -31,6 +31,7 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_noalloc"
             "dsrg_df_semicanonicalize_workspace_size", "dsrg_df_semicanonicalize",
             "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_timing_filter",
             "dsrg_df_set_gradient_block_bytes", "dsrg_df_gradient_block_bytes",
+            "dsrg_df_rest_workspace_size", "dsrg_df_energy_rest", "dsrg_df_cumulants",
             "dsrg_df_version")
 
 
@@ -49,6 +50,15 @@ class Problem(ctypes.Structure):
         ("gamma1", ctypes.c_void_p),
         ("s", ctypes.c_double),
     ]
+
+
+class RestProblem(ctypes.Structure):
+    _fields_ = [("base", Problem), ("B_aa", ctypes.c_void_p), ("f_ca", ctypes.c_void_p),
+                ("f_cv", ctypes.c_void_p), ("f_av", ctypes.c_void_p), ("rdm1", ctypes.c_void_p),
+                ("lambda2", ctypes.c_void_p), ("lambda3", ctypes.c_void_p)]
+
+
+REST_TERMS = ("A", "B", "C", "D", "E", "G", "H", "I", "J", "K")
 
 
 class DFGenProblem(ctypes.Structure):
@@ -123,6 +133,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_kernel_times.restype = i32
     lib.dsrg_df_timing_filter.argtypes = [ctypes.c_char_p]
     lib.dsrg_df_timing_filter.restype = i32
+    lib.dsrg_df_rest_workspace_size.argtypes = [ctypes.POINTER(RestProblem), ctypes.POINTER(sz)]
+    lib.dsrg_df_rest_workspace_size.restype = i32
+    lib.dsrg_df_energy_rest.argtypes = [ctypes.POINTER(RestProblem), i32, vp, vp, sz, vp]
+    lib.dsrg_df_energy_rest.restype = i32
+    lib.dsrg_df_cumulants.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.dsrg_df_cumulants.restype = i32
     lib.dsrg_df_set_gradient_block_bytes.argtypes = [sz]
     lib.dsrg_df_set_gradient_block_bytes.restype = i32
     lib.dsrg_df_gradient_block_bytes.argtypes = []
@@ -291,6 +307,71 @@ def energy_noalloc(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="
                                       _stream_handle(dev)))
     del keep
     return E
+
+
+def cumulants(rdm1, rdm2, rdm3):
+    """(lambda2, lambda3) device tensors from the active spin-orbital reduced
+    density matrices (device float64 tensors [n]^2, [n]^4, [n]^6, n = 2 na)
+    via dsrg_df_cumulants."""
+    lib = load_library()
+    n = rdm1.shape[0]
+    dev = rdm1.device
+    g1 = _as_dev(rdm1, "rdm1", (n, n), dev)
+    g2 = _as_dev(rdm2, "rdm2", (n,) * 4, dev)
+    g3 = _as_dev(rdm3, "rdm3", (n,) * 6, dev)
+    l2 = torch.empty((n,) * 4, dtype=torch.float64, device=dev)
+    l3 = torch.empty((n,) * 6, dtype=torch.float64, device=dev)
+    _check(lib.dsrg_df_cumulants(n // 2, g1.data_ptr(), g2.data_ptr(), g3.data_ptr(),
+                                 l2.data_ptr(), l3.data_ptr(), _stream_handle(dev)))
+    return l2, l3
+
+
+def rest_problem_struct(B_cv, B_ca, B_av, B_aa, eps_c, eps_a, eps_v, f_ca, f_cv, f_av, rdm1,
+                        lambda2, lambda3, s):
+    naux, nc, nv = B_cv.shape
+    na = 0 if B_ca is None else B_ca.shape[2]
+    dev = B_cv.device
+    base, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, None, s)
+    n = 2 * na
+    extra = [
+        _as_dev(B_aa, "B_aa", (naux, na, na), dev) if na else None,
+        _as_dev(f_ca, "f_ca", (nc, na), dev) if na else None,
+        _as_dev(f_cv, "f_cv", (nc, nv), dev) if na else None,
+        _as_dev(f_av, "f_av", (na, nv), dev) if na else None,
+        _as_dev(rdm1, "rdm1", (n, n), dev) if na else None,
+        _as_dev(lambda2, "lambda2", (n,) * 4, dev) if na else None,
+        _as_dev(lambda3, "lambda3", (n,) * 6, dev) if na else None,
+    ]
+    return RestProblem(base, *[_ptr(t) for t in extra]), keep + extra
+
+
+def energy_rest(B_cv, B_ca, B_av, B_aa, eps_c, eps_a, eps_v, f_ca, f_cv, f_av, rdm1, lambda2,
+                lambda3, s, workspace: Optional[torch.Tensor] = None, timing: bool = False,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Table I terms A, B, C, D, E, G, H, I, J, K (device tensor [10], float64)
+    via dsrg_df_energy_rest."""
+    lib = load_library()
+    p, keep = rest_problem_struct(B_cv, B_ca, B_av, B_aa, eps_c, eps_a, eps_v, f_ca, f_cv, f_av,
+                                  rdm1, lambda2, lambda3, s)
+    dev = B_cv.device
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_rest_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    T = torch.empty(10, dtype=torch.float64, device=dev) if out is None else out
+    _check(lib.dsrg_df_energy_rest(ctypes.byref(p), OPT_KERNEL_TIMING if timing else 0,
+                                   T.data_ptr(), ws.data_ptr(), nbytes.value,
+                                   _stream_handle(dev)))
+    del keep
+    return T
+
+
+def rest_workspace_size(nc, na, nv, naux) -> int:
+    lib = load_library()
+    base = Problem(nc, na, nv, naux, None, None, None, None, None, None, None, 0.5)
+    p = RestProblem(base, None, None, None, None, None, None, None)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_rest_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+    return int(nbytes.value)
 
 
 def energy_active(B_cv, B_ca, B_av, B_aa, eps_c, eps_a, eps_v, gamma1, s,

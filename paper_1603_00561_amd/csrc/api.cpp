@@ -860,6 +860,138 @@ dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options,
   return DSRG_OK;
 }
 
+namespace {
+dsrg_status make_rest_plan(const dsrg_df_rest_problem *rp, dsrg::RestPlan &pl) {
+  using namespace dsrg;
+  if (!rp) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  const dsrg_df_problem *p = &rp->base;
+  if (p->nc < 1 || p->nv < 1 || p->naux < 1 || p->na < 0)
+    return fail(DSRG_ERR_ARG, "sizes must satisfy nc, nv, naux >= 1 and na >= 0");
+  if (!(p->s >= 0.0) || !isfinite(p->s))
+    return fail(DSRG_ERR_ARG, "s must be finite and >= 0 (got %g)", p->s);
+  if (p->na > DSRG_DF_MAX_ACTIVE)
+    return fail(DSRG_ERR_UNSUPPORTED, "na = %lld exceeds the compiled maximum %d",
+                (long long)p->na, DSRG_DF_MAX_ACTIVE);
+  if (p->nc > (1 << 16) || p->nv > (1 << 20) || p->naux > (1 << 24))
+    return fail(DSRG_ERR_UNSUPPORTED, "dimensions too large");
+  pl.nc = p->nc;
+  pl.na = p->na;
+  pl.nv = p->nv;
+  pl.naux = p->naux;
+  pl.s = p->s;
+  const size_t nc = (size_t)pl.nc, na = (size_t)pl.na, nv = (size_t)pl.nv;
+  const size_t sC = 2 * nc, sA = 2 * na, sV = 2 * nv, sH = sC + sA, sP = sA + sV;
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t at = off;
+    off = align256(off + sizeof(double) * std::max<size_t>(doubles, 1));
+    return at;
+  };
+  if (pl.na > 0) {
+    pl.off_pcv = take(nc * nv * na * na);
+    pl.off_pav = take(na * nv * na * na);
+    pl.off_pca = take(nc * na * na * na);
+    pl.off_paa = take(na * na * na * na);
+    pl.off_qvc = take(na * nv * nc * na);
+    pl.off_kcc = take(nc * na * nc * na);
+    pl.off_x = take(na * nv * na * nv);
+    pl.off_wt = take(sH * sA * sP * sA);
+    pl.off_wv = take(sH * sA * sP * sA);
+    pl.off_tcc = take(sC * sC * sA * sA);
+    pl.off_vcc = take(sC * sC * sA * sA);
+    pl.off_t1 = take(sH * sP);
+    pl.off_ft = take(sH * sP);
+    pl.off_y = take(sA * sA * sV * sA);
+    pl.off_tp = take(sH * sA * sP * sA);
+    pl.off_ak = take(sA * sA * sA * sV);
+    pl.off_bk = take(sA * sA * sA * sV);
+    pl.off_y2 = take(sA * sA * sA * sA * sA * sA);
+    rest_grids(pl.nc, pl.na, pl.nv, pl.grid);
+    int64_t nslot = 0;
+    for (int k = 0; k < kRestKernels; ++k) {
+      pl.slot[k] = nslot;
+      nslot += pl.grid[k];
+    }
+    pl.off_slots = take((size_t)nslot);
+  } else {
+    pl.off_pcv = pl.off_pav = pl.off_pca = pl.off_paa = pl.off_qvc = pl.off_kcc = pl.off_x =
+        pl.off_wt = pl.off_wv = pl.off_tcc = pl.off_vcc = pl.off_t1 = pl.off_ft = pl.off_y =
+            pl.off_tp = pl.off_ak = pl.off_bk = pl.off_y2 = pl.off_slots = 0;
+    off = 256;
+  }
+  pl.total = off;
+  return DSRG_OK;
+}
+}  // namespace
+
+dsrg_status dsrg_df_rest_workspace_size(const dsrg_df_rest_problem *p, size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::RestPlan pl;
+  dsrg_status st = make_rest_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_energy_rest(const dsrg_df_rest_problem *p, int options, double *terms,
+                                void *workspace, size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  dsrg::RestPlan pl;
+  dsrg_status st = make_rest_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  if (options & ~DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "unknown option bits 0x%x", options);
+  if (!terms || !aligned8(terms)) return fail(DSRG_ERR_ARG, "terms is NULL or misaligned");
+  if (pl.na > 0) {
+    const struct {
+      const double *ptr;
+      const char *name;
+    } need[] = {{p->base.B_cv, "B_cv"}, {p->base.B_ca, "B_ca"}, {p->base.B_av, "B_av"},
+                {p->B_aa, "B_aa"},      {p->base.eps_c, "eps_c"}, {p->base.eps_a, "eps_a"},
+                {p->base.eps_v, "eps_v"}, {p->f_ca, "f_ca"},  {p->f_cv, "f_cv"},
+                {p->f_av, "f_av"},      {p->rdm1, "rdm1"},    {p->lambda2, "lambda2"},
+                {p->lambda3, "lambda3"}};
+    for (const auto &n : need)
+      if (!n.ptr || !aligned8(n.ptr)) return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", n.name);
+  }
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!workspace) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  dsrg::RestInputs in{p->base.B_cv, p->base.B_ca, p->base.B_av, p->B_aa, p->base.eps_c,
+                      p->base.eps_a, p->base.eps_v, p->f_ca, p->f_cv, p->f_av, p->rdm1,
+                      p->lambda2, p->lambda3};
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_rest_terms(pl, in, workspace, terms, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_cumulants(int64_t na, const double *rdm1, const double *rdm2,
+                              const double *rdm3, double *lambda2, double *lambda3,
+                              void *stream) {
+  g_err[0] = 0;
+  if (na < 1) return fail(DSRG_ERR_ARG, "na must be >= 1 (got %lld)", (long long)na);
+  if (na > DSRG_DF_MAX_ACTIVE)
+    return fail(DSRG_ERR_UNSUPPORTED, "na = %lld exceeds the compiled maximum %d", (long long)na,
+                DSRG_DF_MAX_ACTIVE);
+  const struct {
+    const void *ptr;
+    const char *name;
+  } need[] = {{rdm1, "rdm1"}, {rdm2, "rdm2"}, {rdm3, "rdm3"}, {lambda2, "lambda2"},
+              {lambda3, "lambda3"}};
+  for (const auto &n : need)
+    if (!n.ptr || !aligned8(n.ptr)) return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", n.name);
+  hipError_t e = dsrg::launch_cumulants((int)(2 * na), rdm1, rdm2, rdm3, lambda2, lambda3,
+                                        reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
 const char *dsrg_df_last_error(void) { return g_err; }
 
 int dsrg_df_kernel_times(double *ms, const char **names, int cap) {

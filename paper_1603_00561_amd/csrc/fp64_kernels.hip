@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void ccav_epi_fp64_kernel(
 // the per-workgroup slots in a fixed order, or a copy of the atomic
 // accumulator. Unselected terms are written as 0.
 // ---------------------------------------------------------------------------
-constexpr int kFinTerms = 8;
+constexpr int kFinTerms = 12;
 struct FinArgs {
   int64_t base[kFinTerms], count[kFinTerms];
   int selected[kFinTerms];

@@ -159,6 +159,28 @@ struct DFOutputs {
   double *B_cv, *B_ca, *B_av, *B_aa;
 };
 
+// ---- Table I terms A-E, G-K (rest_terms.hip) ----
+constexpr int kRestTerms = 10;     // A, B, C, D, E, G, H, I, J, K
+constexpr int kRestKernels = 12;   // reduction kernels (G and H in two pieces each)
+struct RestPlan {
+  int64_t nc, na, nv, naux;
+  double s;
+  size_t off_pcv, off_pav, off_pca, off_paa, off_qvc, off_kcc, off_x, off_wt, off_wv, off_tcc,
+      off_vcc, off_t1, off_ft, off_y, off_tp, off_ak, off_bk, off_y2, off_slots;
+  int64_t grid[kRestKernels], slot[kRestKernels];   // workgroups and first slot per kernel
+  size_t total;
+};
+struct RestInputs {
+  const double *B_cv, *B_ca, *B_av, *B_aa, *eps_c, *eps_a, *eps_v, *f_ca, *f_cv, *f_av, *rdm1,
+      *lambda2, *lambda3;
+};
+hipError_t launch_rest_terms(const RestPlan &pl, const RestInputs &in, void *ws, double *out,
+                             hipStream_t st);
+void rest_grids(int64_t nc, int64_t na, int64_t nv, int64_t *grid);
+// lambda2, lambda3 from the spin-orbital RDMs of n active spin orbitals
+hipError_t launch_cumulants(int n, const double *g1, const double *g2, const double *g3,
+                            double *l2, double *l3, hipStream_t st);
+
 // ---- the library's static device scratch (noalloc.hip) ----
 // Capacity of the array behind dsrg_df_energy_noalloc (bytes, per device).
 constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
