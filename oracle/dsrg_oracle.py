@@ -49,7 +49,9 @@ Upstream of the energies: ``df_factors`` builds the blocks of B from AO
 three-index integrals, the metric and the MO coefficients, and
 ``generalized_fock`` the generalized Fock matrix of Eq. gen_fock over all
 orbitals from the same DF integrals, and ``semicanonicalize`` the rotation to
-semicanonical orbitals (all pinned in the test-suite).
+semicanonical orbitals; ``pivoted_cholesky_steps`` and ``cd_factors`` give
+the CD variant of the factors (section II.C), which ``df_factors`` and
+``generalized_fock`` take with J = None (all pinned in the test-suite).
 
 Regularisers use libm ``expm1``; every sum over many elements is a
 ``math.fsum``. Gradients are written out from the same formulas by the chain
@@ -550,16 +552,25 @@ def df_factors(ao3, J, C, nfrz, nc, na, nv) -> Dict[str, np.ndarray]:
     Cholesky factor of the metric: sum_Q B^Q_pq B^Q_rs = (pq|P) J^{-1} (P|rs),
     the DF integrals of Eq. int_fact (the symmetric J^{-1/2} of the paper gives
     the same factors up to an orthogonal rotation of Q). Returns B_cv, B_ca,
-    B_av, B_aa in the [Q][p][q] layout of the energy kernels."""
+    B_av, B_aa in the [Q][p][q] layout of the energy kernels.
+
+    J = None means ao3 already holds factors of the AO integrals (the CD
+    vectors B^Q_{mu nu} of ``cd_factors``): no metric, B^Q_pq is their MO
+    transform."""
     o_c = nfrz
     o_a = nfrz + nc
     o_v = nfrz + nc + na
     Cc, Ca, Cv = C[:, o_c:o_a], C[:, o_a:o_v], C[:, o_v:o_v + nv]
-    L = np.linalg.cholesky(J)
-    Linv = np.linalg.solve(L, np.eye(J.shape[0]))      # lower triangular L^{-1}
+    if J is None:
+        Linv = None
+    else:
+        L = np.linalg.cholesky(J)
+        Linv = np.linalg.solve(L, np.eye(J.shape[0]))      # lower triangular L^{-1}
 
     def block(Cp, Cq):
         Y = np.einsum("Pmn,mp,nq->Ppq", ao3, Cp, Cq, optimize=True)   # (pq|P)
+        if Linv is None:
+            return Y
         return np.einsum("QP,Ppq->Qpq", Linv, Y, optimize=True)
 
     return {"B_cv": block(Cc, Cv), "B_ca": block(Cc, Ca), "B_av": block(Ca, Cv),
@@ -575,16 +586,20 @@ def generalized_fock(ao3, J, C, h, gamma1, nfrz, nc, na) -> np.ndarray:
     occupied frozen + core orbitals and the spin-summed active density
     (gamma = Gamma / 2 per spin) this is f = h + J[D] - K[D] / 2 with the MO
     density D (2 on the doubly occupied diagonal, Gamma on the active block),
-    J[D]_pq = sum_rs (pq|rs) D_rs and K[D]_pq = sum_rs (pr|qs) D_rs."""
+    J[D]_pq = sum_rs (pq|rs) D_rs and K[D]_pq = sum_rs (pr|qs) D_rs.
+    J = None takes ao3 as CD factors (pq|rs) = sum_Q B^Q_pq B^Q_rs (no metric)."""
     nmo = C.shape[1]
     no = nfrz + nc + na
-    naux = J.shape[0]
+    naux = ao3.shape[0]
     D = np.zeros((no, no))
     D[np.arange(nfrz + nc), np.arange(nfrz + nc)] = 2.0
     D[nfrz + nc:, nfrz + nc:] = gamma1
     Y = np.einsum("Pmn,mp,nq->Ppq", ao3, C, C, optimize=True)          # (pq|P)
     Yo = np.ascontiguousarray(Y[:, :, :no])                               # (p r|P), r occupied
-    So = np.linalg.solve(J, Yo.reshape(naux, -1)).reshape(Yo.shape)     # J^{-1} (P|q s)
+    if J is None:                                                         # CD factors: J = 1
+        So = Yo
+    else:
+        So = np.linalg.solve(J, Yo.reshape(naux, -1)).reshape(Yo.shape)  # J^{-1} (P|q s)
     d = np.einsum("Prs,rs->P", So[:, :no, :], D)                          # sum_Q J^-1_PQ (Q|rs) D_rs
     Jm = np.einsum("Ppq,P->pq", Y, d)
     Km = np.einsum("Ppr,rs,Pqs->pq", Yo, D, So, optimize=True)
@@ -613,23 +628,60 @@ def semicanonicalize(F, nfrz, nc, na, nv) -> Tuple[np.ndarray, np.ndarray]:
     return eps, U
 
 
-def pivoted_cholesky(M: np.ndarray, tol: float = 0.0) -> np.ndarray:
-    """Pivoted Cholesky of a symmetric PSD matrix M ~= L L^T (the numerical
-    decomposition that generates CD factors, section II.C). Stops when the
-    largest remaining diagonal is <= tol. Returns L with shape (n, rank)."""
+def pivoted_cholesky_steps(M: np.ndarray, tol: float = 0.0, max_rank=None):
+    """Pivoted Cholesky of a symmetric positive semidefinite M ~= L L^T, the
+    numerical decomposition that generates the CD factors (section II.C).
+
+    Greedy: keep the diagonal d of the residual M - L L^T; at every step take
+    the row p of the largest d (the first one on ties) and stop if d[p] <= tol
+    (the CD threshold, which bounds every element of the PSD residual) or once
+    max_rank vectors exist; otherwise the new vector is the residual's column
+    p scaled by 1 / sqrt(d[p]): L[:, k] = (M[:, p] - sum_{j<k} L[:, j] L[p, j])
+    / sqrt(d[p]), and d -= L[:, k]^2 with d[p] = 0.
+
+    Returns (L [n][rank], pivots [rank], dmax) with dmax the largest remaining
+    diagonal when it stopped (<= tol unless max_rank ended it)."""
     M = np.array(M, dtype=np.float64)
     n = M.shape[0]
+    cap = n if max_rank is None else min(int(max_rank), n)
     d = np.diag(M).copy()
-    cols = []
-    for _ in range(n):
-        p = int(np.argmax(d))
-        if d[p] <= tol:
+    cols, piv = [], []
+    dmax = float(d.max()) if n else 0.0
+    while True:
+        p = int(np.argmax(d)) if n else 0
+        dmax = float(d[p]) if n else 0.0
+        if n == 0 or d[p] <= tol or len(cols) >= cap:
             break
         col = M[:, p].copy()
         for c in cols:
             col -= c * c[p]
         col /= math.sqrt(d[p])
         cols.append(col)
+        piv.append(p)
         d -= col * col
         d[p] = 0.0
-    return np.array(cols).T if cols else np.zeros((n, 0))
+    L = np.array(cols).T if cols else np.zeros((n, 0))
+    return L, np.array(piv, dtype=np.int64), dmax
+
+
+def pivoted_cholesky(M: np.ndarray, tol: float = 0.0) -> np.ndarray:
+    """The Cholesky vectors of ``pivoted_cholesky_steps`` alone, as an
+    (n, rank) array."""
+    return pivoted_cholesky_steps(M, tol)[0]
+
+
+def cd_factors(M: np.ndarray, nao: int, tol: float, max_rank=None):
+    """CD factors B^Q_{mu nu} of the AO two-electron integrals (CD approach of
+    section II.C, Eq. int_fact with M terms fixed by the threshold).
+
+    M is the integral matrix over packed AO pairs, M[(mu nu)][(la si)] =
+    (mu nu|la si) with the pair index mu (mu + 1) / 2 + nu for mu >= nu. Its
+    pivoted Cholesky vectors, unpacked symmetrically, are the factors:
+    (mu nu|la si) ~= sum_Q B^Q_{mu nu} B^Q_{la si}. Returns (B [rank][nao][nao],
+    pivots, dmax) as in ``pivoted_cholesky_steps``."""
+    L, piv, dmax = pivoted_cholesky_steps(M, tol, max_rank)
+    mu, nu = np.tril_indices(nao)          # row-major lower triangle: mu (mu+1)/2 + nu
+    B = np.zeros((L.shape[1], nao, nao))
+    B[:, mu, nu] = L.T
+    B[:, nu, mu] = L.T
+    return B, piv, dmax

@@ -303,3 +303,119 @@ def make_dfgen_problem(nfrz: int, nc: int, na: int, nv: int, naux: int,
     return DFGenProblem(nfrz, nc, na, nv, naux, nao, np.ascontiguousarray(ao3),
                         np.ascontiguousarray(J), np.ascontiguousarray(C), seed)
 
+
+
+# ---------------------------------------------------------------------------
+# Cholesky-decomposition inputs (CD approach of section II.C)
+# ---------------------------------------------------------------------------
+@dataclass
+class CDProblem:
+    """AO two-electron integrals for the CD factor build and the orbital data
+    of an energy on top of it (host arrays, float64, C order).
+
+    M[(mu nu)][(la si)] = (mu nu|la si) over packed AO pairs mu >= nu with the
+    pair index mu (mu + 1) / 2 + nu; C [nao][nmo] orthogonal with nmo = nao,
+    columns frozen core | core | active | virtual."""
+
+    nao: int
+    nfrz: int
+    nc: int
+    na: int
+    nv: int
+    M: np.ndarray
+    centers: np.ndarray       # [nao][3] centre of each basis function (bohr)
+    alphas: np.ndarray        # [nao] Gaussian exponents
+    C: np.ndarray
+    eps_c: np.ndarray
+    eps_a: np.ndarray
+    eps_v: np.ndarray
+    gamma1: np.ndarray
+    s: float
+    seed: Optional[int] = None
+
+
+def s_gaussian_eri(centers: np.ndarray, alphas: np.ndarray, rows: int = 256) -> np.ndarray:
+    """Electron repulsion integrals (ab|cd) of normalized s-type Gaussians
+    exp(-alpha |r - A|^2) (2 alpha / pi)^(3/4), over packed pairs a >= b, from
+    the closed form for s functions: with p = a + b exponents, P the weighted
+    centre and K_ab = exp(-alpha_a alpha_b / p |A - B|^2),
+      (ab|cd) = N_a N_b N_c N_d K_ab K_cd 2 pi^(5/2) / (p q sqrt(p + q))
+                F0(p q / (p + q) |P - Q|^2),
+    F0(T) = sqrt(pi / T) erf(sqrt T) / 2 (F0(0) = 1). The matrix is symmetric
+    positive semidefinite (a Coulomb metric over pair densities)."""
+    from scipy.special import erf
+    nao = len(alphas)
+    mu, nu = np.tril_indices(nao)
+    a, b = alphas[mu], alphas[nu]
+    A, B = centers[mu], centers[nu]
+    p = a + b
+    P = (a[:, None] * A + b[:, None] * B) / p[:, None]
+    K = np.exp(-a * b / p * ((A - B) ** 2).sum(1))
+    pref = (2.0 * a / np.pi) ** 0.75 * (2.0 * b / np.pi) ** 0.75 * K
+    npair = len(p)
+    M = np.empty((npair, npair))
+    for r0 in range(0, npair, rows):
+        r1 = min(npair, r0 + rows)
+        pp, qq = p[r0:r1, None], p[None, :]
+        R2 = ((P[r0:r1, None, :] - P[None, :, :]) ** 2).sum(-1)
+        T = pp * qq / (pp + qq) * R2
+        st = np.sqrt(np.maximum(T, 1e-300))
+        F0 = np.where(T < 1e-12, 1.0 - T / 3.0, 0.5 * np.sqrt(np.pi) * erf(st) / st)
+        M[r0:r1] = (pref[r0:r1, None] * pref[None, :] * 2.0 * np.pi ** 2.5
+                    / (pp * qq * np.sqrt(pp + qq)) * F0)
+    return 0.5 * (M + M.T)
+
+
+def make_cd_problem(n_heavy: int = 10, n_light: int = 6, per_heavy: int = 14,
+                    per_light: int = 5, nfrz: int = 0, nc: int = 30, na: int = 2,
+                    s: float = 0.5, seed: int = DEFAULT_SEED,
+                    spacing: float = 2.6) -> CDProblem:
+    """Seeded s-Gaussian "molecule" for the CD build. n_heavy + n_light atoms
+    placed one by one uniformly in a flat box (half-widths 1.5, 1.0, 0.3 times
+    spacing * sqrt(atoms)), a draw rejected while it comes closer than
+    `spacing` bohr to an atom already placed; per_heavy even-tempered s
+    functions 0.08 * 2.6^k on each heavy atom and per_light functions 0.12 *
+    3^k on each light one, so nao = n_heavy per_heavy + n_light per_light
+    (the default 170 is the cc-pVDZ size of C10H6). Then C orthogonal (QR of a
+    standard-normal matrix, column signs fixed), orbital energies and Gamma as
+    in make_problem, nv = nao - nfrz - nc - na. One default_rng(seed), drawn
+    in that order."""
+    rng = np.random.default_rng(seed)
+    nat = n_heavy + n_light
+    half = spacing * np.sqrt(nat) * np.array([1.5, 1.0, 0.3])
+    pts = []
+    while len(pts) < nat:
+        x = rng.uniform(-1.0, 1.0, 3) * half
+        if all(np.linalg.norm(x - q) > spacing for q in pts):
+            pts.append(x)
+    centers, alphas = [], []
+    for i, x in enumerate(pts):
+        heavy = i < n_heavy
+        k, base, r = (per_heavy, 0.08, 2.6) if heavy else (per_light, 0.12, 3.0)
+        for j in range(k):
+            centers.append(x)
+            alphas.append(base * r ** j)
+    centers, alphas = np.array(centers), np.array(alphas)
+    nao = len(alphas)
+    nv = nao - nfrz - nc - na
+    if nv < 1:
+        raise ValueError("nao = %d leaves no virtual orbitals" % nao)
+    M = s_gaussian_eri(centers, alphas)
+    m = rng.standard_normal((nao, nao))
+    Cq, r = np.linalg.qr(m)
+    C = Cq * np.sign(np.diag(r))[None, :]
+    eps_c = rng.uniform(-2.0, -0.3, size=nc)
+    eps_a = rng.uniform(-0.3, 0.1, size=na)
+    eps_v = rng.uniform(0.1, 5.0, size=nv)
+    gamma1 = _gamma(rng, na)
+    return CDProblem(nao, nfrz, nc, na, nv, np.ascontiguousarray(M), centers, alphas,
+                     np.ascontiguousarray(C), eps_c, eps_a, eps_v, gamma1, float(s), seed)
+
+
+def make_psd_lowrank(n: int, rank: int, seed: int = DEFAULT_SEED, decay: float = 4.0) -> np.ndarray:
+    """Symmetric positive semidefinite n x n matrix of exact rank `rank`:
+    G G^T with G [n][rank] ~ N(0,1) scaled by exp(-decay k / rank) in column k."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, rank)) * np.exp(-decay * np.arange(rank) / max(rank, 1))[None, :]
+    M = G @ G.T
+    return 0.5 * (M + M.T)
