@@ -266,7 +266,10 @@ typedef struct {
   const double *ao3;     /* [naux][nao][nao] (mu nu|P) (symmetric in mu, nu by its
                             definition; the build does not rely on it)              */
   const double *J;       /* [naux][naux] two-centre metric, symmetric positive
-                            definite (otherwise the factors contain NaN)            */
+                            definite (otherwise the factors contain NaN); or NULL:
+                            ao3 then holds factors of the AO integrals already
+                            (the CD vectors B^Q_{mu nu} of dsrg_df_cholesky, naux
+                            of them) and no metric is applied                      */
   const double *C;       /* [nao][nmo] MO coefficients; columns ordered frozen core
                             | core | active | virtual (| any further orbitals)      */
 } dsrg_dfgen_problem;
@@ -282,6 +285,44 @@ dsrg_status dsrg_df_factors_workspace_size(const dsrg_dfgen_problem *p, size_t *
 dsrg_status dsrg_df_factors(const dsrg_dfgen_problem *p, int options, double *B_cv,
                             double *B_ca, double *B_av, double *B_aa, void *workspace,
                             size_t ws_bytes, void *stream);
+
+/* ---- Cholesky-decomposition factors (CD approach of section II.C): a
+ * pivoted Cholesky decomposition of the AO two-electron integrals stopped at
+ * a threshold, (mu nu|la si) ~= sum_{Q < rank} B^Q_{mu nu} B^Q_{la si}.
+ * Greedy pivoting: step k takes the pair p with the largest diagonal d of the
+ * residual M - sum_{Q<k} L^Q L^Q^T (the smallest pair index on ties) and stops
+ * if d_p <= tol; otherwise L^k = (M_{p .} - sum_{Q<k} L^Q L^Q_p) / sqrt(d_p).
+ * The residual of a positive semidefinite M stays positive semidefinite, so
+ * on convergence every integral is reproduced to within tol. */
+#define DSRG_CD_MAX_NAO 16384
+typedef struct {
+  int64_t nao;        /* AO basis functions, 1 .. DSRG_CD_MAX_NAO; npair =
+                         nao (nao + 1) / 2                                          */
+  const double *M;    /* [npair][npair] (mu nu|la si) over packed pairs mu >= nu,
+                         pair index mu (mu + 1) / 2 + nu (device); symmetric
+                         positive semidefinite; only its diagonal and the pivot
+                         rows are read                                              */
+  double tol;         /* CD threshold >= 0 (Eh), e.g. 1e-5                          */
+  int64_t max_rank;   /* most vectors, 0 .. npair; one kernel launch per vector is
+                         enqueued, so keep it near the rank expected            */
+} dsrg_cd_problem;
+
+/* Bytes of device workspace that dsrg_df_cholesky needs (sizes only). */
+dsrg_status dsrg_df_cholesky_workspace_size(const dsrg_cd_problem *p, size_t *bytes);
+
+/* B [max_rank][nao][nao] (device): B^Q_{mu nu} = B^Q_{nu mu} for Q < rank,
+ * zero for rank <= Q < max_rank (may be NULL when max_rank == 0).
+ *   rank    device int64: vectors made; < max_rank means converged, == max_rank
+ *           means converged only if *dmax <= tol
+ *   dmax    device double: the largest residual diagonal when it stopped
+ *   pivots  device int64 [max_rank] (or NULL): the pair index of each step
+ *   options 0 or DSRG_OPT_KERNEL_TIMING
+ * rank and dmax are written on the stream like every output: read them after
+ * the stream has reached this call's end. FP64 throughout. Errors as for
+ * dsrg_df_energy (nao too large: DSRG_ERR_UNSUPPORTED). */
+dsrg_status dsrg_df_cholesky(const dsrg_cd_problem *p, int options, double *B, int64_t *rank,
+                             double *dmax, int64_t *pivots, void *workspace, size_t ws_bytes,
+                             void *stream);
 
 /* ---- Generalized Fock matrix (Eq. gen_fock) over all MOs from the same DF
  * integrals (pq|rs) = sum_PQ (pq|P) [J^{-1}]_PQ (Q|rs):

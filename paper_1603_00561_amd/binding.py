@@ -32,6 +32,7 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_noalloc"
             "dsrg_df_last_error", "dsrg_df_kernel_times", "dsrg_df_timing_filter",
             "dsrg_df_set_gradient_block_bytes", "dsrg_df_gradient_block_bytes",
             "dsrg_df_rest_workspace_size", "dsrg_df_energy_rest", "dsrg_df_cumulants",
+            "dsrg_df_cholesky_workspace_size", "dsrg_df_cholesky",
             "dsrg_df_version")
 
 
@@ -68,6 +69,11 @@ class DFGenProblem(ctypes.Structure):
         ("nv", ctypes.c_int64),
         ("ao3", ctypes.c_void_p), ("J", ctypes.c_void_p), ("C", ctypes.c_void_p),
     ]
+
+
+class CDProblem(ctypes.Structure):
+    _fields_ = [("nao", ctypes.c_int64), ("M", ctypes.c_void_p), ("tol", ctypes.c_double),
+                ("max_rank", ctypes.c_int64)]
 
 
 class FockProblem(ctypes.Structure):
@@ -143,6 +149,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_set_gradient_block_bytes.restype = i32
     lib.dsrg_df_gradient_block_bytes.argtypes = []
     lib.dsrg_df_gradient_block_bytes.restype = sz
+    lib.dsrg_df_cholesky_workspace_size.argtypes = [ctypes.POINTER(CDProblem),
+                                                    ctypes.POINTER(sz)]
+    lib.dsrg_df_cholesky_workspace_size.restype = i32
+    lib.dsrg_df_cholesky.argtypes = [ctypes.POINTER(CDProblem), i32, vp, vp, vp, vp, vp, sz, vp]
+    lib.dsrg_df_cholesky.restype = i32
     lib.dsrg_df_version.argtypes = []
     lib.dsrg_df_version.restype = i32
     _lib = lib
@@ -398,12 +409,14 @@ def df_factors(ao3, J, C, nfrz, nc, na, nv, workspace: Optional[torch.Tensor] = 
                timing: bool = False):
     """B_cv, B_ca, B_av, B_aa (device tensors, float64) via dsrg_df_factors
     from the AO three-index integrals ao3 [naux][nao][nao], the metric J
-    [naux][naux] and the MO coefficients C [nao][nmo]."""
+    [naux][naux] and the MO coefficients C [nao][nmo]. J = None: ao3 holds
+    factors of the AO integrals already (CD vectors), no metric applied."""
     lib = load_library()
     naux, nao, _ = ao3.shape
     nmo = C.shape[1]
     dev = ao3.device
-    keep = [_as_dev(ao3, "ao3", (naux, nao, nao), dev), _as_dev(J, "J", (naux, naux), dev),
+    keep = [_as_dev(ao3, "ao3", (naux, nao, nao), dev),
+            None if J is None else _as_dev(J, "J", (naux, naux), dev),
             _as_dev(C, "C", (nao, nmo), dev)]
     p = DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, *[_ptr(t) for t in keep])
     nbytes = ctypes.c_size_t(0)
@@ -425,12 +438,14 @@ def df_fock(ao3, J, C, h, gamma1, nfrz, nc, na, nv, workspace: Optional[torch.Te
             timing: bool = False):
     """The generalized Fock matrix F [nmo][nmo] (device, float64) via
     dsrg_df_fock from ao3 [naux][nao][nao], J [naux][naux], C [nao][nmo], the
-    MO one-electron integrals h [nmo][nmo] and the active 1-RDM gamma1."""
+    MO one-electron integrals h [nmo][nmo] and the active 1-RDM gamma1 (J =
+    None: ao3 holds CD vectors, no metric)."""
     lib = load_library()
     naux, nao, _ = ao3.shape
     nmo = C.shape[1]
     dev = ao3.device
-    keep = [_as_dev(ao3, "ao3", (naux, nao, nao), dev), _as_dev(J, "J", (naux, naux), dev),
+    keep = [_as_dev(ao3, "ao3", (naux, nao, nao), dev),
+            None if J is None else _as_dev(J, "J", (naux, naux), dev),
             _as_dev(C, "C", (nao, nmo), dev), _as_dev(h, "h", (nmo, nmo), dev)]
     g1 = _as_dev(gamma1, "gamma1", (na, na), dev) if na > 0 else None
     if g1 is not None:
@@ -476,20 +491,68 @@ def semicanonicalize(F, nfrz, nc, na, nv, C=None, workspace: Optional[torch.Tens
     return eps, U, Cs
 
 
-def df_fock_workspace_size(nao, nmo, naux, nfrz, nc, na, nv) -> int:
+# stands for a metric in the size queries, which read no array
+_SOME_METRIC = ctypes.c_void_p(256)
+
+
+def df_fock_workspace_size(nao, nmo, naux, nfrz, nc, na, nv, metric: bool = True) -> int:
     lib = load_library()
-    p = FockProblem(DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, None, None, None), None, None)
+    p = FockProblem(DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, None,
+                                 _SOME_METRIC if metric else None, None), None, None)
     out = ctypes.c_size_t(0)
     _check(lib.dsrg_df_fock_workspace_size(ctypes.byref(p), ctypes.byref(out)))
     return out.value
 
 
-def df_factors_workspace_size(nao, nmo, naux, nfrz, nc, na, nv) -> int:
+def df_factors_workspace_size(nao, nmo, naux, nfrz, nc, na, nv, metric: bool = True) -> int:
     lib = load_library()
-    p = DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, None, None, None)
+    p = DFGenProblem(nao, nmo, naux, nfrz, nc, na, nv, None,
+                     _SOME_METRIC if metric else None, None)
     out = ctypes.c_size_t(0)
     _check(lib.dsrg_df_factors_workspace_size(ctypes.byref(p), ctypes.byref(out)))
     return out.value
+
+
+def cholesky_workspace_size(nao: int, max_rank: int, tol: float = 0.0) -> int:
+    lib = load_library()
+    p = CDProblem(nao, None, tol, max_rank)
+    out = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_cholesky_workspace_size(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def cholesky(M, nao: int, tol: float, max_rank: int, workspace: Optional[torch.Tensor] = None,
+             timing: bool = False, with_pivots: bool = True, sync: bool = True):
+    """CD vectors of the AO integrals via dsrg_df_cholesky. M: [npair][npair]
+    (mu nu|la si) over packed pairs (device, float64). Returns a dict with
+    B [rank][nao][nao] (a view of the [max_rank] output; the whole output as
+    "B_full"), rank, dmax (Python numbers, read after a stream sync unless
+    sync=False, then the device tensors "rank_t", "dmax_t") and pivots
+    [rank] (device int64)."""
+    lib = load_library()
+    npair = nao * (nao + 1) // 2
+    dev = M.device
+    Md = _as_dev(M, "M", (npair, npair), dev)
+    p = CDProblem(nao, Md.data_ptr(), float(tol), int(max_rank))
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_cholesky_workspace_size(ctypes.byref(p), ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    B = torch.empty(max_rank, nao, nao, dtype=torch.float64, device=dev)
+    rank_t = torch.empty(1, dtype=torch.int64, device=dev)
+    dmax_t = torch.empty(1, dtype=torch.float64, device=dev)
+    piv = torch.empty(max(max_rank, 1), dtype=torch.int64, device=dev) if with_pivots else None
+    _check(lib.dsrg_df_cholesky(ctypes.byref(p), OPT_KERNEL_TIMING if timing else 0,
+                                B.data_ptr() if max_rank > 0 else None, rank_t.data_ptr(),
+                                dmax_t.data_ptr(), _ptr(piv), ws.data_ptr(), nbytes.value,
+                                _stream_handle(dev)))
+    out = {"B_full": B, "rank_t": rank_t, "dmax_t": dmax_t, "pivots_full": piv}
+    if sync:
+        torch.cuda.current_stream(dev).synchronize()
+        r = int(rank_t.item())
+        out.update(rank=r, dmax=float(dmax_t.item()), B=B[:r],
+                   pivots=None if piv is None else piv[:r])
+    del Md
+    return out
 
 
 def energy_backward(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, gE, precision="fp64",

@@ -2,6 +2,7 @@
 // and kernel launches. Nothing here allocates device memory or waits on the
 // device; every error is found before the first launch.
 #include <math.h>
+#include <cmath>
 #include <stdarg.h>
 #include <stdio.h>
 #include <algorithm>
@@ -477,12 +478,17 @@ dsrg_status make_df_plan(const dsrg_dfgen_problem *p, dsrg::DFPlan &pl) {
     off = align256(off + sizeof(double) * doubles);
     return at;
   };
+  pl.metric = p->J != nullptr;
   pl.off_t = take(nx * np * (size_t)pl.nao);
   pl.off_y = take(nx * np * nq);
-  pl.off_l = take(nx * nx);
-  pl.off_x = take(nx * nx);
-  pl.off_tmp = take(nx * nx);   // L21 blocks of the recursive metric factor, at their positions
-  pl.off_bf = take(nx * np * nq);
+  if (pl.metric) {
+    pl.off_l = take(nx * nx);
+    pl.off_x = take(nx * nx);
+    pl.off_tmp = take(nx * nx);   // L21 blocks of the recursive metric factor, at their positions
+    pl.off_bf = take(nx * np * nq);
+  } else {
+    pl.off_l = pl.off_x = pl.off_tmp = pl.off_bf = off;
+  }
   pl.total = off;
   return DSRG_OK;
 }
@@ -684,11 +690,11 @@ dsrg_status dsrg_df_factors(const dsrg_dfgen_problem *p, int options, double *B_
     const void *ptr;
     const char *name;
     bool need;
-  } chk[] = {{p->ao3, "ao3", true},     {p->J, "J", true},          {p->C, "C", true},
+  } chk[] = {{p->ao3, "ao3", true},     {p->J, "J", false},         {p->C, "C", true},
              {B_cv, "B_cv", true},       {B_ca, "B_ca", pl.na > 0}, {B_av, "B_av", pl.na > 0},
              {B_aa, "B_aa", pl.na > 0}};
   for (const auto &c : chk)
-    if (c.need && (!c.ptr || !aligned8(c.ptr)))
+    if ((c.need && !c.ptr) || (c.ptr && !aligned8(c.ptr)))
       return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", c.name);
   if (ws_bytes < pl.total)
     return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
@@ -728,11 +734,16 @@ dsrg_status make_fock_plan(const dsrg_fock_problem *p, dsrg::FockPlan &pl) {
     off = align256(off + sizeof(double) * doubles);
     return at;
   };
+  pl.metric = dp.metric;
   pl.off_t = take(nx * no * nao);
   pl.off_y = take(nx * no * nmo);   // later the right operand of the exchange product
-  pl.off_l = take(nx * nx);
-  pl.off_x = take(nx * nx);
-  pl.off_w = take(nx * nx);
+  if (pl.metric) {
+    pl.off_l = take(nx * nx);
+    pl.off_x = take(nx * nx);
+    pl.off_w = take(nx * nx);
+  } else {
+    pl.off_l = pl.off_x = pl.off_w = off;
+  }
   pl.off_bo = take(nx * no * nmo);
   pl.off_d = take(nx);
   pl.off_c = take(nx);
@@ -766,10 +777,10 @@ dsrg_status dsrg_df_fock(const dsrg_fock_problem *p, int options, double *F, voi
     const void *ptr;
     const char *name;
     bool need;
-  } chk[] = {{p->df.ao3, "ao3", true}, {p->df.J, "J", true},  {p->df.C, "C", true},
+  } chk[] = {{p->df.ao3, "ao3", true}, {p->df.J, "J", false}, {p->df.C, "C", true},
              {p->h, "h", true},        {p->gamma1, "gamma1", pl.na > 0}, {F, "F", true}};
   for (const auto &c : chk)
-    if (c.need && (!c.ptr || !aligned8(c.ptr)))
+    if ((c.need && !c.ptr) || (c.ptr && !aligned8(c.ptr)))
       return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", c.name);
   if (ws_bytes < pl.total)
     return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
@@ -988,6 +999,84 @@ dsrg_status dsrg_df_cumulants(int64_t na, const double *rdm1, const double *rdm2
     if (!n.ptr || !aligned8(n.ptr)) return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", n.name);
   hipError_t e = dsrg::launch_cumulants((int)(2 * na), rdm1, rdm2, rdm3, lambda2, lambda3,
                                         reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
+namespace {
+// Plan of the CD factor build: validation and the workspace layout.
+dsrg_status make_cd_plan(const dsrg_cd_problem *p, dsrg::CdPlan &pl) {
+  using namespace dsrg;
+  if (!p) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  if (p->nao < 1) return fail(DSRG_ERR_ARG, "nao must be >= 1 (got %lld)", (long long)p->nao);
+  if (p->nao > DSRG_CD_MAX_NAO)
+    return fail(DSRG_ERR_UNSUPPORTED, "nao = %lld exceeds %d", (long long)p->nao,
+                DSRG_CD_MAX_NAO);
+  if (!(p->tol >= 0.0) || !std::isfinite(p->tol))
+    return fail(DSRG_ERR_ARG, "tol must be finite and >= 0");
+  pl.nao = p->nao;
+  pl.npair = p->nao * (p->nao + 1) / 2;
+  if (p->max_rank < 0 || p->max_rank > pl.npair)
+    return fail(DSRG_ERR_ARG, "max_rank = %lld is outside [0, %lld]", (long long)p->max_rank,
+                (long long)pl.npair);
+  pl.max_rank = p->max_rank;
+  pl.tol = p->tol;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  const size_t nblk = (size_t)ceil_div(pl.npair, 16);   // the most workgroups of any launch
+  pl.off_d = take(sizeof(double) * (size_t)pl.npair);
+  pl.off_pv = take(sizeof(double) * nblk);
+  pl.off_pi = take(sizeof(int64_t) * nblk);
+  pl.off_sel = off;
+  pl.off_state = off + 2 * sizeof(CdSel);
+  pl.off_end = pl.off_state + sizeof(CdState);
+  off = align256(pl.off_end);
+  pl.total = off;
+  return DSRG_OK;
+}
+}  // namespace
+
+dsrg_status dsrg_df_cholesky_workspace_size(const dsrg_cd_problem *p, size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::CdPlan pl;
+  dsrg_status st = make_cd_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_cholesky(const dsrg_cd_problem *p, int options, double *B, int64_t *rank,
+                             double *dmax, int64_t *pivots, void *workspace, size_t ws_bytes,
+                             void *stream) {
+  g_err[0] = 0;
+  dsrg::CdPlan pl;
+  dsrg_status st = make_cd_plan(p, pl);
+  if (st != DSRG_OK) return st;
+  if (options & ~DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "unknown option bits 0x%x", options);
+  const struct {
+    const void *ptr;
+    const char *name;
+    bool need;
+  } chk[] = {{p->M, "M", true},       {B, "B", pl.max_rank > 0}, {rank, "rank", true},
+             {dmax, "dmax", true},    {pivots, "pivots", false}};
+  for (const auto &c : chk)
+    if ((c.need && !c.ptr) || (c.ptr && !aligned8(c.ptr)))
+      return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", c.name);
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!workspace) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_cholesky(pl, p->M, B, rank, dmax, pivots, workspace, hs);
   if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
   return DSRG_OK;
 }

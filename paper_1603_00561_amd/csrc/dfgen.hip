@@ -729,9 +729,11 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
   double *T = ws_d(ws, pl.off_t), *Y = ws_d(ws, pl.off_y), *Lm = ws_d(ws, pl.off_l);
   double *X = ws_d(ws, pl.off_x), *W = ws_d(ws, pl.off_tmp), *Bf = ws_d(ws, pl.off_bf);
   // the metric factor and inverse, beside the transforms (disjoint buffers:
-  // Lm, X, W there; T, Y here)
+  // Lm, X, W there; T, Y here); none for factors that need no metric
   SideStream *ss = nullptr;
-  if ((e = metric_forked("df_metric", in.J, Lm, X, W, naux, st, ss)) != hipSuccess) return e;
+  if (pl.metric &&
+      (e = metric_forked("df_metric", in.J, Lm, X, W, naux, st, ss)) != hipSuccess)
+    return e;
   // T[P][p][nu] = sum_mu C[mu][oc + p] (mu nu|P), batched over P: the small
   // (core | active) index first, so the second step contracts nao over
   // naux np rows instead of naux nao
@@ -750,13 +752,17 @@ hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutpu
              1, false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
-  if ((e = side_join(ss, st)) != hipSuccess) return e;
-  // B[Q][(p q)] = sum_{P <= Q} X[Q][P] Y[P][(p q)]
-  timer_begin("df_metric_apply", st);
-  e = gemm_g(false, false, naux, np * nq, naux, 1.0, X, naux, 0, Y, np * nq, 0, 0.0, Bf, np * nq,
-             0, 1, true, st);
-  timer_end(st);
-  if (e != hipSuccess) return e;
+  if (pl.metric) {
+    if ((e = side_join(ss, st)) != hipSuccess) return e;
+    // B[Q][(p q)] = sum_{P <= Q} X[Q][P] Y[P][(p q)]
+    timer_begin("df_metric_apply", st);
+    e = gemm_g(false, false, naux, np * nq, naux, 1.0, X, naux, 0, Y, np * nq, 0, 0.0, Bf,
+               np * nq, 0, 1, true, st);
+    timer_end(st);
+    if (e != hipSuccess) return e;
+  } else {
+    Bf = Y;   // the transformed factors are B already
+  }
   ScatterArgs sa{naux, pl.nc, pl.na, pl.nv};
   const int64_t total = naux * np * nq;
   timer_begin("df_scatter", st);
@@ -832,9 +838,11 @@ hipError_t launch_df_fock(const FockPlan &pl, const FockInputs &in, double *F, v
   double *dv = ws_d(ws, pl.off_d), *cv = ws_d(ws, pl.off_c), *Jao = ws_d(ws, pl.off_jao);
   double *Tj = ws_d(ws, pl.off_tj), *Part = ws_d(ws, pl.off_part);
   // the metric factor and inverse, beside the transforms (Lm, X, W there;
-  // T, Y here)
+  // T, Y here); none for factors that need no metric
   SideStream *ss = nullptr;
-  if ((e = metric_forked("fock_metric", in.J, Lm, X, W, naux, st, ss)) != hipSuccess) return e;
+  if (pl.metric &&
+      (e = metric_forked("fock_metric", in.J, Lm, X, W, naux, st, ss)) != hipSuccess)
+    return e;
   // T[P][m][nu] = sum_mu C[mu][m] (mu nu|P), m occupied
   timer_begin("fock_half1", st);
   if (folded_fits(no, nao, naux))
@@ -845,27 +853,34 @@ hipError_t launch_df_fock(const FockPlan &pl, const FockInputs &in, double *F, v
                no * nao, naux, false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
-  // Y[(P m)][q] = sum_nu T[(P m)][nu] C[nu][q], q over all MOs
+  // Y[(P m)][q] = sum_nu T[(P m)][nu] C[nu][q], q over all MOs (straight into
+  // B when there is no metric)
   timer_begin("fock_half2", st);
-  e = gemm_g(false, false, naux * no, nmo, nao, 1.0, T, nao, 0, in.C, nmo, 0, 0.0, Y, nmo, 0, 1,
-             false, st);
+  e = gemm_g(false, false, naux * no, nmo, nao, 1.0, T, nao, 0, in.C, nmo, 0, 0.0,
+             pl.metric ? Y : Bo, nmo, 0, 1, false, st);
   timer_end(st);
   if (e != hipSuccess) return e;
-  if ((e = side_join(ss, st)) != hipSuccess) return e;
-  // B[Q][(m q)] = sum_{P <= Q} X[Q][P] Y[P][(m q)]
-  timer_begin("fock_metric_apply", st);
-  e = gemm_g(false, false, naux, no * nmo, naux, 1.0, X, naux, 0, Y, no * nmo, 0, 0.0, Bo,
-             no * nmo, 0, 1, true, st);
-  timer_end(st);
-  if (e != hipSuccess) return e;
-  // Coulomb part, through the AO basis
+  if (pl.metric) {
+    if ((e = side_join(ss, st)) != hipSuccess) return e;
+    // B[Q][(m q)] = sum_{P <= Q} X[Q][P] Y[P][(m q)]
+    timer_begin("fock_metric_apply", st);
+    e = gemm_g(false, false, naux, no * nmo, naux, 1.0, X, naux, 0, Y, no * nmo, 0, 0.0, Bo,
+               no * nmo, 0, 1, true, st);
+    timer_end(st);
+    if (e != hipSuccess) return e;
+  }
+  // Coulomb part, through the AO basis (c = X^T d, or d itself with no metric)
   timer_begin("fock_coulomb", st);
   hipLaunchKernelGGL(fock_density_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(naux, 256), 1024)),
                      dim3(256), 0, st, Bo, in.gamma1, naux, no, nmo, nd, na, dv);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = gemm_g(true, false, naux, 1, naux, 1.0, X, naux, 0, dv, 1, 0, 0.0, cv, 1, 0, 1, false,
-                  st)) != hipSuccess)
-    return e;
+  if (pl.metric) {
+    if ((e = gemm_g(true, false, naux, 1, naux, 1.0, X, naux, 0, dv, 1, 0, 0.0, cv, 1, 0, 1,
+                    false, st)) != hipSuccess)
+      return e;
+  } else {
+    cv = dv;
+  }
   if ((e = gemm_g(false, false, 1, nao * nao, naux, 1.0, cv, naux, 0, in.ao3, nao * nao, 0, 0.0,
                   Jao, nao * nao, 0, 1, false, st)) != hipSuccess)
     return e;

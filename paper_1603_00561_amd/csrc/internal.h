@@ -149,6 +149,7 @@ struct ActiveInputs {
 // The density-fitting factor build (FP64).
 struct DFPlan {
   int64_t nao, nmo, naux, nfrz, nc, na, nv;
+  bool metric;   // false: ao3 holds factors already (CD vectors), no J applied
   size_t off_t, off_y, off_l, off_x, off_tmp, off_bf;
   size_t total;
 };
@@ -234,6 +235,25 @@ hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const
 // ---- density-fitting factors (dfgen.hip) ----
 hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutputs &o, void *ws,
                              hipStream_t st);
+// ---- CD factors of the AO integrals (cholesky.hip) ----
+struct CdSel {     // pivot of the next step: largest residual diagonal, its pair
+  double dmax;
+  int64_t p;
+};
+struct CdState {   // done flag, rank and final maximum; ticket of the argmax reduction
+  int64_t done, rank;
+  unsigned int ticket, pad;
+  double dmax;
+};
+struct CdPlan {
+  int64_t nao, npair, max_rank;
+  double tol;
+  size_t off_d, off_pv, off_pi, off_sel, off_state, off_end;
+  size_t total;
+};
+int cd_rows_per_block(int64_t npair);   // pair rows per workgroup of a step launch
+hipError_t launch_cholesky(const CdPlan &pl, const double *M, double *B, int64_t *rank,
+                           double *dmax, int64_t *pivots, void *ws, hipStream_t st);
 // ---- semicanonical orbitals (semican.hip) ----
 struct SemicanPlan {
   int64_t nao, nmo, nfrz, nc, na, nv;
@@ -251,6 +271,7 @@ hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double al
 // ---- generalized Fock matrix (dfgen.hip) ----
 struct FockPlan {
   int64_t nao, nmo, naux, nfrz, nc, na, nv;
+  bool metric;      // as in DFPlan
   int64_t no, nd;   // occupied (frozen + core + active), doubly occupied (frozen + core)
   size_t off_t, off_y, off_l, off_x, off_w, off_bo, off_d, off_c, off_jao, off_tj, off_part;
   size_t total;

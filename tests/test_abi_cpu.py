@@ -299,3 +299,58 @@ def test_semicanonicalize_entry_point_validation(lib):
     assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG
     assert call(prob(), nb=16) == b.DSRG_ERR_WORKSPACE
     assert call(prob(), ws=0x40008) == b.DSRG_ERR_WORKSPACE
+
+
+def test_cholesky_entry_point_validation(lib):
+    """CD-factor entry point: workspace sizing and host-side rejection (every
+    call below fails before the first launch)."""
+    def prob(nao=20, M=0x10000, tol=1e-5, max_rank=50):
+        return b.CDProblem(nao, M, tol, max_rank)
+
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_cholesky_workspace_size(ctypes.byref(prob()), ctypes.byref(out)) == 0
+    # at least the residual diagonal over the 210 pairs
+    assert out.value >= 8 * 210
+    assert b.cholesky_workspace_size(20, 50) == out.value
+
+    def call(p, B=0x20000, rank=0x30000, dmax=0x30100, piv=0x30200, opts=0, ws=0x40000,
+             nb=1 << 40):
+        v = lambda x: ctypes.c_void_p(x) if x else None
+        return lib.dsrg_df_cholesky(ctypes.byref(p), opts, v(B), v(rank), v(dmax), v(piv), v(ws),
+                                    nb, None)
+
+    for kw in (dict(nao=0), dict(tol=-1.0), dict(tol=float("nan")), dict(tol=float("inf")),
+               dict(max_rank=-1), dict(max_rank=211)):
+        assert call(prob(**kw)) == b.DSRG_ERR_ARG, kw
+        assert lib.dsrg_df_last_error().decode()
+    assert call(prob(nao=b_max_nao() + 1)) == b.DSRG_ERR_UNSUPPORTED
+    assert call(prob(M=0)) == b.DSRG_ERR_ARG
+    assert call(prob(M=0x10004)) == b.DSRG_ERR_ARG                    # misaligned
+    assert call(prob(), B=0) == b.DSRG_ERR_ARG
+    assert call(prob(), rank=0) == b.DSRG_ERR_ARG
+    assert call(prob(), dmax=0) == b.DSRG_ERR_ARG
+    assert call(prob(), piv=0x30204) == b.DSRG_ERR_ARG                # optional, but aligned
+    assert call(prob(), opts=0x100) == b.DSRG_ERR_ARG
+    assert call(prob(), nb=16) == b.DSRG_ERR_WORKSPACE
+    assert call(prob(), ws=0x40008) == b.DSRG_ERR_WORKSPACE
+    assert call(prob(), ws=0) == b.DSRG_ERR_WORKSPACE
+
+
+def b_max_nao():
+    text = open(HEADER).read()
+    return int(re.search(r"#define DSRG_CD_MAX_NAO (\d+)", text).group(1))
+
+
+def test_factor_build_without_metric_sizes(lib):
+    """J = NULL (CD vectors in ao3): smaller workspaces, same validation."""
+    assert b.df_factors_workspace_size(40, 40, 30, 2, 5, 3, 30, metric=False) < \
+        b.df_factors_workspace_size(40, 40, 30, 2, 5, 3, 30)
+    assert b.df_fock_workspace_size(40, 40, 30, 2, 5, 3, 30, metric=False) < \
+        b.df_fock_workspace_size(40, 40, 30, 2, 5, 3, 30)
+    a = 0x10000
+    p = b.DFGenProblem(40, 40, 30, 2, 5, 3, 30, a, ctypes.c_void_p(0x10004), a)
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_factors_workspace_size(ctypes.byref(p), ctypes.byref(out)) == 0
+    st = lib.dsrg_df_factors(ctypes.byref(p), 0, *[ctypes.c_void_p(0x20000)] * 4,
+                             ctypes.c_void_p(0x40000), 1 << 40, None)
+    assert st == b.DSRG_ERR_ARG                                        # misaligned J
