@@ -12,7 +12,7 @@ energy alone for the CCVV slice kernel's rate) and reported under
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg5]
                     [--precision fp64] [--energy] [--no-compare]
                     [--no-cpu-baseline]
-                    [--active | --dfgen | --fock | --semican]
+                    [--active | --dfgen | --fock | --semican | --rest | --cd]
 
 --energy times dsrg_df_energy alone. With --active a step is one
 dsrg_df_energy_active call instead (the pieces F4-F8 of term F, FP64),
@@ -22,7 +22,11 @@ call (the density-fitting factors B from AO three-index integrals, FP64) for
 the config's orbital spaces; with --fock one dsrg_df_fock call (the
 generalized Fock matrix of Eq. gen_fock from the same DF integrals, FP64);
 with --semican one dsrg_df_semicanonicalize call (the semicanonical rotation
-of that Fock matrix and C U, FP64).
+of that Fock matrix and C U, FP64); with --rest one dsrg_df_energy_rest call
+(the Table I terms A-E and G-K with the cumulants, FP64) for the config's
+orbital spaces; with --cd one dsrg_df_cholesky call (the CD factors of an
+s-Gaussian integral matrix of nao = 170 AO functions, the cc-pVDZ size of
+C10H6, to the threshold 1e-5 Eh, FP64).
 
 Prints one JSON line. `value` is algorithmic TFLOP/s of the whole step:
 F_alg = 2 naux [nc(nc+1)/2 nv^2 + nc na nv^2 + nc^2 na nv] (the contractions
@@ -567,6 +571,14 @@ def main():
     ap.add_argument("--semican", action="store_true",
                     help="time the semicanonical rotation (dsrg_df_semicanonicalize, FP64) of the "
                          "generalized Fock matrix of the --fock workload")
+    ap.add_argument("--rest", action="store_true",
+                    help="time the Table I terms A-E, G-K (dsrg_df_energy_rest, FP64) for the "
+                         "orbital spaces of the config")
+    ap.add_argument("--cd", action="store_true",
+                    help="time the CD factor build (dsrg_df_cholesky, FP64) of the nao = 170 "
+                         "s-Gaussian integral matrix to 1e-5 Eh")
+    ap.add_argument("--cd-max-rank", type=int, default=0,
+                    help="max_rank of the --cd call (default 6 nao)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
                          "hardware byte counters can be scaled")
@@ -596,6 +608,10 @@ def main():
         return bench_fock(args, binding, torch)
     if args.semican:
         return bench_semican(args, binding, torch)
+    if args.rest:
+        return bench_rest(args, binding, torch)
+    if args.cd:
+        return bench_cd(args, binding, torch)
     p = make_config(args.config)
     if args.active:
         return bench_active(args, p, binding, torch)
@@ -899,6 +915,159 @@ def bench_semican(args, binding, torch):
         out["eps_err_rel"] = cb.pop("eps_err_rel")
         out["U_err"] = cb.pop("U_err")
         out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+
+def rest_alg_work(nc, na, nv, naux):
+    """Algorithmic flops and HBM bytes of the integral stage of the Table I
+    terms: the seven products over the auxiliary index that form (pq|rs)
+    with two or more active indices (the largest, (xe|yf), reads B_av twice
+    and writes na^2 nv^2 values)."""
+    na2 = na * na
+    prods = [(nc * nv, na2), (na * nv, na2), (nc * na, na2), (na2, na2), (na * nv, nc * na),
+             (nc * na, nc * na), (na * nv, na * nv)]
+    flops = sum(2.0 * naux * m * n for m, n in prods)
+    nbytes = sum(8.0 * (naux * (m + n) + m * n) for m, n in prods)
+    return flops, nbytes
+
+
+def bench_rest(args, binding, torch):
+    """--rest: one step = one dsrg_df_energy_rest call (Table I terms A-E,
+    G-K, FP64) on make_rest_problem inputs of the config's orbital spaces."""
+    from paper_1603_00561_amd.workloads import CONFIGS, make_rest_problem
+    if args.precision != "fp64" or args.grad or args.active:
+        print("bench.py: --rest runs the FP64 energy only", file=sys.stderr)
+        sys.exit(2)
+    c = CONFIGS[args.config]
+    p = make_rest_problem(c["nc"], c["na"], c["nv"], c["naux"], s=c["s"])
+    dev = torch.device("cuda:0")
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    l2, l3 = binding.cumulants(d(p.rdm1), d(p.rdm2), d(p.rdm3))
+    t = [d(x) for x in (p.B_cv, p.B_ca, p.B_av, p.B_aa, p.eps_c, p.eps_a, p.eps_v, p.f_ca,
+                        p.f_cv, p.f_av, p.rdm1)]
+    nbytes = binding.rest_workspace_size(p.nc, p.na, p.nv, p.naux)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    res = {}
+
+    def call(timing):
+        res["T"] = binding.energy_rest(*t, l2, l3, p.s, workspace=ws, timing=timing)
+    for _ in range(args.warmup):
+        call(False)
+    torch.cuda.synchronize()
+    avg = kernel_table(binding, torch, call, table_steps(args))
+    flops, nb = rest_alg_work(p.nc, p.na, p.nv, p.naux)
+    stages = {"rest_integrals": (flops, nb)}
+    ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps, ["rest_integrals"])
+    roof = stage_roofline(avg, stages, dom_ms)
+    T = res["T"].cpu().numpy()
+    out = {
+        "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
+        "value": flops / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "s_per_solve": ms_per_step * 1e-3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config} orbital spaces: nc={p.nc} na={p.na} nv={p.nv} "
+                               f"naux={p.naux} s={p.s}, Table I terms A-E and G-K "
+                               "(value counts the integral products only)",
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "terms": dict(zip(binding.REST_TERMS, [float(x) for x in T])),
+        "kernel_ms": avg,
+        "kernel_ms_from": table_note(args),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import dsrg_table1 as OT
+        cores = _blas_threads()
+        t0 = time.perf_counter()
+        ref = OT.rest_terms(p)
+        dt = time.perf_counter() - t0
+        refv = np.array([ref[k] for k in binding.REST_TERMS])
+        out["abs_err_vs_oracle"] = [float(x) for x in np.abs(T - refv)]
+        out["cpu_baseline"] = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores,
+                               "kind": "oracle", "seconds": dt,
+                               "sample": "the whole workload (spin-orbital blocked oracle, "
+                                         "numpy on every BLAS thread)",
+                               "host": host_info()}
+    print(json.dumps(out))
+
+
+def cd_alg_bytes(npair, rank):
+    """Algorithmic HBM bytes of the rank step launches of the CD build: step k
+    reads the k earlier vectors on every pair and the pivot's integral row,
+    reads and writes the residual diagonal, and writes its vector unpacked
+    (both triangles): (k + 5) npair doubles."""
+    return 8.0 * npair * (rank * (rank - 1) / 2.0 + 5.0 * rank)
+
+
+def bench_cd(args, binding, torch):
+    """--cd: one step = one dsrg_df_cholesky call (FP64) on the s-Gaussian
+    integral matrix of make_cd_problem (nao = 170) to the threshold 1e-5."""
+    from paper_1603_00561_amd.workloads import make_cd_problem
+    if args.precision != "fp64" or args.grad or args.active:
+        print("bench.py: --cd runs the FP64 factor build only", file=sys.stderr)
+        sys.exit(2)
+    tol = 1e-5
+    p = make_cd_problem()
+    nao, npair = p.nao, p.M.shape[0]
+    max_rank = args.cd_max_rank or 6 * nao
+    dev = torch.device("cuda:0")
+    M = torch.from_numpy(p.M).to(dev)
+    ws = torch.empty(binding.cholesky_workspace_size(nao, max_rank, tol), dtype=torch.uint8,
+                     device=dev)
+    res = {}
+
+    def call(timing):
+        res["r"] = binding.cholesky(M, nao, tol, max_rank, workspace=ws, timing=timing,
+                                    sync=False)
+    for _ in range(args.warmup):
+        call(False)
+    torch.cuda.synchronize()
+    avg = kernel_table(binding, torch, call, table_steps(args))
+    ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps, ["cd_step"])
+    rank = int(res["r"]["rank_t"].item())
+    dmax = float(res["r"]["dmax_t"].item())
+    flops = 2.0 * npair * rank * (rank - 1) / 2.0      # the products against earlier vectors
+    nbytes = cd_alg_bytes(npair, rank)
+    ach = nbytes / (dom_ms * 1e-3) / 1e9 if dom_ms else None
+    roof = {"bound": "hbm", "kernel": "cd_step", "achieved": ach, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": (ach / PEAK_HBM_GBS) if ach else None,
+            "avg_launch_ms": dom_ms,
+            "note": "cd_step is the sequence of max_rank step launches of one call (one timer "
+                    "pair around them); bytes are those of the rank steps that do work",
+            "bytes_per_launch": nbytes, "traffic": None}
+    out = {
+        "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
+        "value": flops / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "s_per_solve": ms_per_step * 1e-3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"CD of (mu nu|la si): nao={nao} (npair={npair}) s-Gaussian "
+                               f"functions, threshold {tol:g} Eh, max_rank={max_rank}",
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "rank": rank, "dmax": dmax,
+        "kernel_ms": avg,
+        "kernel_ms_from": table_note(args),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import dsrg_oracle as O
+        from scipy.linalg import lapack
+        cores = _blas_threads()
+        t0 = time.perf_counter()
+        L, piv, dm = O.pivoted_cholesky_steps(p.M, tol, max_rank)
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, pvt, lrank, _ = lapack.dpstrf(p.M.copy(), lower=1, tol=tol)
+        dl = time.perf_counter() - t0
+        out["pivots_equal_oracle"] = bool(
+            np.array_equal(res["r"]["pivots_full"][:rank].cpu().numpy(), piv))
+        out["cpu_baseline"] = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores,
+                               "kind": "oracle", "seconds": dt, "rank": int(L.shape[1]),
+                               "sample": "the whole workload (greedy pivoted Cholesky, one "
+                                         "numpy vector update per earlier vector)",
+                               "host": host_info()}
+        out["cpu_lapack_dpstrf"] = {"seconds": dl, "rank": int(lrank), "cores": cores}
     print(json.dumps(out))
 
 

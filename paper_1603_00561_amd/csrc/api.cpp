@@ -1027,14 +1027,13 @@ dsrg_status make_cd_plan(const dsrg_cd_problem *p, dsrg::CdPlan &pl) {
     off = align256(off + bytes);
     return at;
   };
-  const size_t nblk = (size_t)ceil_div(pl.npair, 16);   // the most workgroups of any launch
+  // the most workgroups of any launch: the init kernel's one per 256 pairs or
+  // a step's one per cd_rows_per_block pairs
+  pl.pstride = std::max(ceil_div(pl.npair, 256), ceil_div(pl.npair, cd_rows_per_block(pl.npair)));
   pl.off_d = take(sizeof(double) * (size_t)pl.npair);
-  pl.off_pv = take(sizeof(double) * nblk);
-  pl.off_pi = take(sizeof(int64_t) * nblk);
-  pl.off_sel = off;
-  pl.off_state = off + 2 * sizeof(CdSel);
-  pl.off_end = pl.off_state + sizeof(CdState);
-  off = align256(pl.off_end);
+  pl.off_pv = take(sizeof(double) * 2 * (size_t)pl.pstride);
+  pl.off_pi = take(sizeof(int64_t) * 2 * (size_t)pl.pstride);
+  pl.off_state = take(sizeof(CdState));
   pl.total = off;
   return DSRG_OK;
 }

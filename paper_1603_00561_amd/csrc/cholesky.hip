@@ -16,12 +16,12 @@
 // on every element of vector k). Each launch streams the k earlier vectors
 // once (a matrix-vector product against the pivot's row, HBM-bound), with the
 // pair rows spread over the workgroups and the earlier vectors over the
-// waves of a workgroup. The argmax of the updated diagonal is reduced in the
-// same launch: every workgroup publishes its local maximum, and the last
-// workgroup to arrive (an atomic ticket, no waiting) reduces them and leaves
-// the next pivot for the following launch. Launches past convergence return
-// at once (a done flag in the workspace). Every sum runs in a fixed order, so
-// results repeat bit for bit.
+// waves of a workgroup. Every workgroup publishes the maximum of the updated
+// diagonal over its rows (double-buffered by step parity); the next launch
+// starts with every workgroup reducing those maxima itself, in workgroup
+// order, to the same pivot (no atomics, no inter-workgroup waits). Launches
+// past convergence return at once (a done flag in the workspace). Every sum
+// runs in a fixed order, so results repeat bit for bit.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -32,19 +32,19 @@ namespace dsrg {
 
 namespace {
 
-constexpr int kCdT = 256;     // threads per workgroup
+constexpr int kCdT = 256;     // threads per workgroup of the init and finish kernels
 constexpr int kCdLp = 2048;   // pivot-row values of the earlier vectors staged per LDS chunk
+constexpr int kCdU = 8;       // earlier vectors loaded back to back per thread
 
 struct CdArgs {
   const double *M;   // [N][N] integrals over packed pairs
   double *B;         // [max_rank][nao][nao] vectors, unpacked
   double *d;         // [N] residual diagonal
-  double *part_v;    // [nblk] per-workgroup maxima of d
-  int64_t *part_i;   // [nblk] their pair indices
-  CdSel *sel;        // [2] pivot for the next step, by step parity
+  double *part_v;    // [2][pstride] per-workgroup maxima of d, by step parity
+  int64_t *part_i;   // [2][pstride] their pair indices
   CdState *state;
   int64_t *pivots;   // [max_rank] or nullptr
-  int64_t nao, npair;
+  int64_t nao, npair, pstride;
   double tol;
 };
 
@@ -70,64 +70,77 @@ __device__ inline double sub_square(double d, double c) {
   return d - c * c;
 }
 
-// Workgroup argmax of (v, i) over all threads into thread 0's return value.
+// Workgroup argmax of (v, i) over all T threads, returned to every thread:
+// a butterfly over the 64 lanes of each wave (the order is total, so every
+// lane ends with the same maximum), then the T / 64 wave maxima in order. A
+// NaN value takes no part (it is never a maximum).
+template <int T>
 __device__ inline void block_argmax(double &v, int64_t &i, double *sv, int64_t *si) {
-  const int t = threadIdx.x;
-  sv[t] = v;
-  si[t] = i;
-  __syncthreads();
-  for (int h = kCdT / 2; h > 0; h >>= 1) {
-    if (t < h && beats(sv[t + h], si[t + h], sv[t], si[t])) {
-      sv[t] = sv[t + h];
-      si[t] = si[t + h];
-    }
-    __syncthreads();
+  if (!(v == v)) {
+    v = -INFINITY;
+    i = INT64_MAX;
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int64_t oi = __shfl_xor(i, off);
+    if (beats(ov, oi, v, i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();   // earlier readers of sv / si are done
+  if ((threadIdx.x & 63) == 0) {
+    sv[w] = v;
+    si[w] = i;
+  }
+  __syncthreads();
   v = sv[0];
   i = si[0];
+#pragma unroll
+  for (int q = 1; q < T / 64; ++q)
+    if (beats(sv[q], si[q], v, i)) {
+      v = sv[q];
+      i = si[q];
+    }
 }
 
-// Publish this workgroup's maximum; the last workgroup of the launch to
-// arrive reduces all of them (in index order of the workgroups, so the
-// result does not depend on arrival order) into sel_out and rearms the
-// ticket. Called by every thread of every workgroup.
-__device__ void publish_max(const CdArgs &a, double v, int64_t i, CdSel *sel_out, double *sv,
-                            int64_t *si) {
-  __shared__ int s_last;
-  const int t = threadIdx.x;
-  const unsigned nblk = gridDim.x;
-  block_argmax(v, i, sv, si);
-  if (t == 0) {
-    a.part_v[blockIdx.x] = v;
-    a.part_i[blockIdx.x] = i;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned ticket =
-        __hip_atomic_fetch_add(&a.state->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (ticket == nblk - 1);
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// The pivot of the next step: the maximum over the n maxima that the
+// previous launch published at parity `par`, reduced by every workgroup to
+// the same (value, index) (the order of the comparisons is fixed).
+template <int T>
+__device__ inline void reduce_published(const CdArgs &a, int par, int64_t n, double &v,
+                                        int64_t &i, double *sv, int64_t *si) {
+  const double *pv = a.part_v + par * a.pstride;
+  const int64_t *pi = a.part_i + par * a.pstride;
   double bv = -INFINITY;
   int64_t bi = INT64_MAX;
-  for (unsigned b = t; b < nblk; b += kCdT) {
-    const double w = a.part_v[b];
-    const int64_t j = a.part_i[b];
+  for (int64_t b = threadIdx.x; b < n; b += T) {
+    const double w = pv[b];
+    const int64_t j = pi[b];
     if (beats(w, j, bv, bi)) {
       bv = w;
       bi = j;
     }
   }
-  __syncthreads();
-  block_argmax(bv, bi, sv, si);
-  if (t == 0) {
-    sel_out->dmax = bv;
-    sel_out->p = bi;
-    a.state->ticket = 0;
+  block_argmax<T>(bv, bi, sv, si);
+  v = bv;
+  i = bi;
+}
+
+// publish this workgroup's maximum (v, i) at parity `par`
+template <int T>
+__device__ inline void publish(const CdArgs &a, int par, double v, int64_t i, double *sv,
+                               int64_t *si) {
+  block_argmax<T>(v, i, sv, si);
+  if (threadIdx.x == 0) {
+    a.part_v[par * a.pstride + blockIdx.x] = v;
+    a.part_i[par * a.pstride + blockIdx.x] = i;
   }
 }
 
-// d = diag(M) and the first pivot; one thread per pair
+// d = diag(M), its maxima published at parity 0; one thread per pair
 __global__ __launch_bounds__(kCdT) void cd_init_kernel(CdArgs a) {
   __shared__ double sv[kCdT];
   __shared__ int64_t si[kCdT];
@@ -139,58 +152,74 @@ __global__ __launch_bounds__(kCdT) void cd_init_kernel(CdArgs a) {
     vi = i;
     a.d[i] = v;
   }
-  publish_max(a, v, vi, &a.sel[0], sv, si);
+  publish<kCdT>(a, 0, v, vi, sv, si);
 }
 
-// Cholesky vector k: R pair rows per workgroup, 256 / R groups of earlier
-// vectors per row
-template <int R>
-__global__ __launch_bounds__(kCdT) void cd_step_kernel(CdArgs a, int64_t k) {
-  constexpr int G = kCdT / R;
+// Cholesky vector k: R pair rows per workgroup of T threads, G = T / R
+// groups of earlier vectors per row (vector j in group j mod G, summed in
+// increasing j within a group, then over the groups in order); nprev maxima
+// published by the previous launch
+template <int R, int T>
+__global__ __launch_bounds__(T) void cd_step_kernel(CdArgs a, int64_t k, int64_t nprev) {
+  constexpr int G = T / R;
   __shared__ double lp[kCdLp];
-  __shared__ double sv[kCdT];
-  __shared__ int64_t si[kCdT];
+  __shared__ double sv[T];
+  __shared__ int64_t si[T];
   if (a.state->done) return;
-  const CdSel s = a.sel[k & 1];
-  if (!(s.dmax > a.tol)) {   // converged (or nothing left): rank = k
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      a.state->done = 1;
-      a.state->rank = k;
-      a.state->dmax = s.dmax;
-    }
-    return;
-  }
   const int64_t nao = a.nao, nao2 = a.nao * a.nao, N = a.npair;
-  const int64_t p = s.p;
-  int64_t pm, pn;
-  pair_of(p, pm, pn);
-  const int64_t poff = pm * nao + pn;
   const int t = threadIdx.x, r = t % R, g = t / R;
   const int64_t i = (int64_t)blockIdx.x * R + r;
   const bool valid = i < N;
+  const bool owner = g == 0 && valid;   // the thread that finishes row i
   int64_t mu = 0, nu = 0;
   if (valid) pair_of(i, mu, nu);
   const int64_t ioff = mu * nao + nu;
+  // loads that do not depend on the pivot go out before its reduction: the
+  // residual diagonal of row i and the first round of earlier-vector values
+  const double d_i = owner ? a.d[i] : 0.0;
+  const int cn0 = (int)(k < kCdLp ? k : kCdLp);
+  double x0[kCdU];
+#pragma unroll
+  for (int u = 0; u < kCdU; ++u) {
+    const int jj = g + u * G;
+    x0[u] = (valid && jj < cn0) ? a.B[(int64_t)jj * nao2 + ioff] : 0.0;
+  }
+  double dmax;
+  int64_t p;
+  reduce_published<T>(a, (int)(k & 1), nprev, dmax, p, sv, si);
+  if (!(dmax > a.tol)) {   // converged (or nothing left): rank = k
+    if (blockIdx.x == 0 && t == 0) {
+      a.state->done = 1;
+      a.state->rank = k;
+      a.state->dmax = dmax;
+    }
+    return;
+  }
+  int64_t pm, pn;
+  pair_of(p, pm, pn);
+  const int64_t poff = pm * nao + pn;
+  const double m_pi = owner ? a.M[p * N + i] : 0.0;   // issued beside the pivot-row staging
   double acc = 0.0;
   for (int64_t c0 = 0; c0 < k; c0 += kCdLp) {
     const int cn = (int)((k - c0) < kCdLp ? (k - c0) : kCdLp);
     __syncthreads();
-    for (int j = t; j < cn; j += kCdT) lp[j] = a.B[(c0 + j) * nao2 + poff];
+    for (int j = t; j < cn; j += T) lp[j] = a.B[(c0 + j) * nao2 + poff];
     __syncthreads();
     if (valid) {
+      // rounds of kCdU loads, the last one predicated (no serial tail)
       const double *Lc = a.B + c0 * nao2 + ioff;
-      int j = g;
-      for (; j + 3 * G < cn; j += 4 * G) {
-        const double x0 = Lc[(int64_t)j * nao2];
-        const double x1 = Lc[(int64_t)(j + G) * nao2];
-        const double x2 = Lc[(int64_t)(j + 2 * G) * nao2];
-        const double x3 = Lc[(int64_t)(j + 3 * G) * nao2];
-        acc = fma(x0, lp[j], acc);
-        acc = fma(x1, lp[j + G], acc);
-        acc = fma(x2, lp[j + 2 * G], acc);
-        acc = fma(x3, lp[j + 3 * G], acc);
+      for (int j = g; j < cn; j += kCdU * G) {
+        double x[kCdU], w[kCdU];
+        const bool first = c0 == 0 && j == g;
+#pragma unroll
+        for (int u = 0; u < kCdU; ++u) {
+          const int jj = j + u * G;
+          x[u] = first ? x0[u] : (jj < cn ? Lc[(int64_t)jj * nao2] : 0.0);
+          w[u] = jj < cn ? lp[jj] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kCdU; ++u) acc = fma(x[u], w[u], acc);
       }
-      for (; j < cn; j += G) acc = fma(Lc[(int64_t)j * nao2], lp[j], acc);
     }
   }
   __syncthreads();
@@ -198,41 +227,55 @@ __global__ __launch_bounds__(kCdT) void cd_step_kernel(CdArgs a, int64_t k) {
   __syncthreads();
   double cand = -INFINITY;
   int64_t ci = INT64_MAX;
-  if (g == 0 && valid) {
+  if (owner) {
     double sum = 0.0;
     for (int q = 0; q < G; ++q) sum += sv[r + q * R];
-    const double col = (a.M[p * N + i] - sum) / sqrt(s.dmax);
+    const double col = (m_pi - sum) / sqrt(dmax);
     double *Bk = a.B + k * nao2;
     Bk[mu * nao + nu] = col;
     Bk[nu * nao + mu] = col;
-    const double dn = (i == p) ? 0.0 : sub_square(a.d[i], col);
+    const double dn = (i == p) ? 0.0 : sub_square(d_i, col);
     a.d[i] = dn;
     cand = dn;
     ci = i;
   }
   if (blockIdx.x == 0 && t == 0 && a.pivots) a.pivots[k] = p;
-  __syncthreads();
-  publish_max(a, cand, ci, &a.sel[(k + 1) & 1], sv, si);
+  publish<T>(a, (int)((k + 1) & 1), cand, ci, sv, si);
 }
 
-// rank and final residual maximum (a single thread, after the last step)
-__global__ void cd_finish_kernel(CdArgs a, int64_t max_rank, int64_t *rank, double *dmax) {
+// rank and final residual maximum (one workgroup, after the last step)
+__global__ __launch_bounds__(kCdT) void cd_finish_kernel(CdArgs a, int64_t max_rank,
+                                                         int64_t nlast, int64_t *rank,
+                                                         double *dmax) {
+  __shared__ double sv[kCdT];
+  __shared__ int64_t si[kCdT];
   if (a.state->done) {
-    *rank = a.state->rank;
-    *dmax = a.state->dmax;
-  } else {
+    if (threadIdx.x == 0) {
+      *rank = a.state->rank;
+      *dmax = a.state->dmax;
+    }
+    return;
+  }
+  double v;
+  int64_t i;
+  reduce_published<kCdT>(a, (int)(max_rank & 1), nlast, v, i, sv, si);
+  if (threadIdx.x == 0) {
     *rank = max_rank;
-    *dmax = a.sel[max_rank & 1].dmax;
+    *dmax = v;
   }
 }
 
 }  // namespace
 
 int cd_rows_per_block(int64_t npair) {
-  // the most pair rows per workgroup that still leave about 512 workgroups
-  if (ceil_div(npair, 64) >= 512) return 64;
-  if (ceil_div(npair, 32) >= 512) return 32;
-  return 16;
+  // few, wide workgroups: the fixed cost of a step (the reduction of the
+  // published maxima, the pivot-row staging) grows with their number
+  return npair >= 64 * 64 ? 64 : 16;
+}
+
+int cd_threads_per_block(int64_t npair) {
+  (void)npair;
+  return 256;
 }
 
 hipError_t launch_cholesky(const CdPlan &pl, const double *M, double *B, int64_t *rank,
@@ -244,37 +287,45 @@ hipError_t launch_cholesky(const CdPlan &pl, const double *M, double *B, int64_t
   a.d = ws_d(ws, pl.off_d);
   a.part_v = ws_d(ws, pl.off_pv);
   a.part_i = reinterpret_cast<int64_t *>(static_cast<char *>(ws) + pl.off_pi);
-  a.sel = reinterpret_cast<CdSel *>(static_cast<char *>(ws) + pl.off_sel);
   a.state = reinterpret_cast<CdState *>(static_cast<char *>(ws) + pl.off_state);
   a.pivots = pivots;
   a.nao = pl.nao;
   a.npair = pl.npair;
+  a.pstride = pl.pstride;
   a.tol = pl.tol;
-  // vectors past the rank stay zero; ticket, done flag and selection cleared
+  // vectors past the rank stay zero; the done flag cleared
   timer_begin("cd_init", st);
   if ((e = launch_zero_fill(B, pl.max_rank * pl.nao * pl.nao, st)) != hipSuccess) return e;
-  if ((e = launch_zero_fill(reinterpret_cast<double *>(a.sel),
-                            (int64_t)((pl.off_end - pl.off_sel) / sizeof(double)), st)) !=
-      hipSuccess)
+  if ((e = launch_zero_fill(reinterpret_cast<double *>(a.state),
+                            (int64_t)(sizeof(CdState) / sizeof(double)), st)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(cd_init_kernel, dim3((unsigned)ceil_div(pl.npair, kCdT)), dim3(kCdT), 0, st,
-                     a);
+  const int64_t ninit = ceil_div(pl.npair, kCdT);
+  hipLaunchKernelGGL(cd_init_kernel, dim3((unsigned)ninit), dim3(kCdT), 0, st, a);
   timer_end(st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int R = cd_rows_per_block(pl.npair);
-  const dim3 grid((unsigned)ceil_div(pl.npair, R));
+  const int R = cd_rows_per_block(pl.npair), T = cd_threads_per_block(pl.npair);
+  const int64_t nblk = ceil_div(pl.npair, R);
+  const dim3 grid((unsigned)nblk);
+  auto step = [&](int64_t k, int64_t nprev) {
+    if (R == 128)
+      hipLaunchKernelGGL((cd_step_kernel<128, 256>), grid, dim3(T), 0, st, a, k, nprev);
+    else if (R == 64 && T == 512)
+      hipLaunchKernelGGL((cd_step_kernel<64, 512>), grid, dim3(T), 0, st, a, k, nprev);
+    else if (R == 64)
+      hipLaunchKernelGGL((cd_step_kernel<64, 256>), grid, dim3(T), 0, st, a, k, nprev);
+    else if (R == 32)
+      hipLaunchKernelGGL((cd_step_kernel<32, 256>), grid, dim3(T), 0, st, a, k, nprev);
+    else
+      hipLaunchKernelGGL((cd_step_kernel<16, 256>), grid, dim3(T), 0, st, a, k, nprev);
+  };
   timer_begin("cd_step", st);
   for (int64_t k = 0; k < pl.max_rank; ++k) {
-    if (R == 64)
-      hipLaunchKernelGGL(cd_step_kernel<64>, grid, dim3(kCdT), 0, st, a, k);
-    else if (R == 32)
-      hipLaunchKernelGGL(cd_step_kernel<32>, grid, dim3(kCdT), 0, st, a, k);
-    else
-      hipLaunchKernelGGL(cd_step_kernel<16>, grid, dim3(kCdT), 0, st, a, k);
+    step(k, k == 0 ? ninit : nblk);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   timer_end(st);
-  hipLaunchKernelGGL(cd_finish_kernel, dim3(1), dim3(1), 0, st, a, pl.max_rank, rank, dmax);
+  hipLaunchKernelGGL(cd_finish_kernel, dim3(1), dim3(kCdT), 0, st, a, pl.max_rank,
+                     pl.max_rank == 0 ? ninit : nblk, rank, dmax);
   return hipGetLastError();
 }
 

@@ -236,22 +236,19 @@ hipError_t launch_finalize_terms(const double *slots, const int64_t *base, const
 hipError_t launch_df_factors(const DFPlan &pl, const DFInputs &in, const DFOutputs &o, void *ws,
                              hipStream_t st);
 // ---- CD factors of the AO integrals (cholesky.hip) ----
-struct CdSel {     // pivot of the next step: largest residual diagonal, its pair
-  double dmax;
-  int64_t p;
-};
-struct CdState {   // done flag, rank and final maximum; ticket of the argmax reduction
+struct CdState {   // done flag, rank and residual maximum at convergence
   int64_t done, rank;
-  unsigned int ticket, pad;
-  double dmax;
+  double dmax, pad;
 };
 struct CdPlan {
   int64_t nao, npair, max_rank;
+  int64_t pstride;   // published maxima per parity (the most workgroups of a launch)
   double tol;
-  size_t off_d, off_pv, off_pi, off_sel, off_state, off_end;
+  size_t off_d, off_pv, off_pi, off_state;
   size_t total;
 };
-int cd_rows_per_block(int64_t npair);   // pair rows per workgroup of a step launch
+int cd_rows_per_block(int64_t npair);     // pair rows per workgroup of a step launch
+int cd_threads_per_block(int64_t npair);  // its threads (a multiple of the rows)
 hipError_t launch_cholesky(const CdPlan &pl, const double *M, double *B, int64_t *rank,
                            double *dmax, int64_t *pivots, void *ws, hipStream_t st);
 // ---- semicanonical orbitals (semican.hip) ----

@@ -417,30 +417,49 @@ __global__ __launch_bounds__(kRT) void rest_gva_kernel(RestDims d, const double 
   rest_emit(acc, 0.25, slots);
 }
 
-// G, virtual-virtual part: per workgroup a partial M(x,y,u,v) over chunks of
-// 64 virtual f for one virtual e, from X[(x,e)][(y,f)] = (xe|yf); the slot
-// receives 1/2 sum L(x,y,u,v) M_partial(x,y,u,v)
+// G, virtual-virtual part: M(x,y,u,v) = sum_{e,f} Z1[(e,f)][xy] Z2[(e,f)][uv]
+// with Z1 = (xe|yf) S(D^{xy}_{ef}) and Z2 = (ue|vf) R1(D^{uv}_{ef}), from
+// X[(x,e)][(y,f)] = (xe|yf). A workgroup takes items of one e and 64 f: it
+// forms the item's Z1 and Z2 in LDS (the regularisers once per element), then
+// accumulates 4 x 4 register tiles of M, one per thread, with the 64 f split
+// over groups of threads when the tiles do not fill the workgroup. At the end
+// the groups' tiles are summed in group order and the slot receives
+// 1/2 sum Lambda(x,y,u,v) M_partial(x,y,u,v).
 constexpr int kGvvF = 64;
 constexpr int kMaxNa = DSRG_DF_MAX_ACTIVE;
-constexpr int kGvvPer = (kMaxNa * kMaxNa * kMaxNa * kMaxNa + kRT - 1) / kRT;   // outputs per thread
+constexpr int kMaxNp = kMaxNa * kMaxNa;   // active pairs (x, y)
+constexpr int kGvvT = 4;                  // register tile edge
 
 __global__ __launch_bounds__(kRT) void rest_gvv_kernel(RestDims d, const double *__restrict__ X,
                                                        const double *__restrict__ ea,
                                                        const double *__restrict__ ev,
                                                        const double *__restrict__ l2,
                                                        double *slots) {
-  __shared__ double z1[kMaxNa * kMaxNa][kGvvF + 1];
-  __shared__ double z2[kMaxNa * kMaxNa][kGvvF + 1];
-  const int na = d.na, nv = d.nv, np = na * na, nout = np * np;
+  __shared__ double z1[kGvvF][kMaxNp + 1];
+  __shared__ double z2[kGvvF][kMaxNp + 1];
+  const int na = d.na, nv = d.nv, np = na * na;
+  const int nt = (np + kGvvT - 1) / kGvvT;   // tiles per edge of M
+  const int ntiles = nt * nt;                // <= 256 (np <= 64)
+  const int ngroups = kRT / ntiles;          // >= 1
+  const int tid = threadIdx.x, grp = tid / ntiles, tile = tid % ntiles;
+  const bool active = grp < ngroups;
+  const int ta = (tile / nt) * kGvvT, tb = (tile % nt) * kGvvT;
   const int64_t ld = (int64_t)na * nv;   // row length of X
-  double acc[kGvvPer];
+  double acc[kGvvT][kGvvT];
 #pragma unroll
-  for (int q = 0; q < kGvvPer; ++q) acc[q] = 0.0;
+  for (int a = 0; a < kGvvT; ++a)
+#pragma unroll
+    for (int b = 0; b < kGvvT; ++b) acc[a][b] = 0.0;
+  // pad columns of the tiles past np stay zero
+  for (int q = tid; q < kGvvF * (kMaxNp + 1); q += kRT) {
+    (&z1[0][0])[q] = 0.0;
+    (&z2[0][0])[q] = 0.0;
+  }
   const int nfc = (nv + kGvvF - 1) / kGvvF;
   for (int64_t item = blockIdx.x; item < (int64_t)nv * nfc; item += gridDim.x) {
     const int e = (int)(item / nfc), f0 = (int)(item % nfc) * kGvvF;
     __syncthreads();
-    for (int q = threadIdx.x; q < np * kGvvF; q += kRT) {
+    for (int q = tid; q < np * kGvvF; q += kRT) {
       const int xy = q / kGvvF, fl = q % kGvvF, f = f0 + fl;
       double a = 0.0, b = 0.0;
       if (f < nv) {
@@ -451,32 +470,52 @@ __global__ __launch_bounds__(kRT) void rest_gvv_kernel(RestDims d, const double 
         a = xv * S;
         b = xv * R1;
       }
-      z1[xy][fl] = a;
-      z2[xy][fl] = b;
+      z1[fl][xy] = a;
+      z2[fl][xy] = b;
     }
     __syncthreads();
+    if (active) {
+      for (int fl = grp; fl < kGvvF; fl += ngroups) {
+        double za[kGvvT], zb[kGvvT];
 #pragma unroll
-    for (int q = 0; q < kGvvPer; ++q) {
-      const int o = threadIdx.x + q * kRT;
-      if (o >= nout) break;
-      const int xy = o / np, uv = o % np;
-      double c = 0.0;
-      for (int fl = 0; fl < kGvvF; ++fl) c += z1[xy][fl] * z2[uv][fl];
-      acc[q] += c;
+        for (int a = 0; a < kGvvT; ++a) za[a] = z1[fl][ta + a];
+#pragma unroll
+        for (int b = 0; b < kGvvT; ++b) zb[b] = z2[fl][tb + b];
+#pragma unroll
+        for (int a = 0; a < kGvvT; ++a)
+#pragma unroll
+          for (int b = 0; b < kGvvT; ++b) acc[a][b] = fma(za[a], zb[b], acc[a][b]);
+      }
     }
   }
+  // the groups' tiles, summed in group order by the threads of group 0
+  __syncthreads();
+  double *red = &z1[0][0];   // ngroups * ntiles * 16 <= 4096 doubles
+  if (active) {
+#pragma unroll
+    for (int a = 0; a < kGvvT; ++a)
+#pragma unroll
+      for (int b = 0; b < kGvvT; ++b)
+        red[((int64_t)grp * ntiles + tile) * kGvvT * kGvvT + a * kGvvT + b] = acc[a][b];
+  }
+  __syncthreads();
   double part = 0.0;
   const int n = d.sA;
-#pragma unroll
-  for (int q = 0; q < kGvvPer; ++q) {
-    const int o = threadIdx.x + q * kRT;
-    if (o >= nout) break;
-    const int xy = o / np, uv = o % np;
-    const int x = xy / na, y = xy % na, u = uv / na, v = uv % na;
-    double L = 0.0;
-    for (int s1 = 0; s1 < 2; ++s1)
-      for (int s2 = 0; s2 < 2; ++s2) L += l2at(l2, n, 2 * x + s1, 2 * y + s2, 2 * u + s1, 2 * v + s2);
-    part += L * acc[q];
+  if (tid < ntiles) {
+    for (int a = 0; a < kGvvT; ++a)
+      for (int b = 0; b < kGvvT; ++b) {
+        const int xy = ta + a, uv = tb + b;
+        if (xy >= np || uv >= np) continue;
+        double m = 0.0;
+        for (int gq = 0; gq < ngroups; ++gq)
+          m += red[((int64_t)gq * ntiles + tid) * kGvvT * kGvvT + a * kGvvT + b];
+        const int x = xy / na, y = xy % na, u = uv / na, v = uv % na;
+        double L = 0.0;
+        for (int s1 = 0; s1 < 2; ++s1)
+          for (int s2 = 0; s2 < 2; ++s2)
+            L += l2at(l2, n, 2 * x + s1, 2 * y + s2, 2 * u + s1, 2 * v + s2);
+        part += L * m;
+      }
   }
   rest_emit(part, 0.5, slots);
 }
