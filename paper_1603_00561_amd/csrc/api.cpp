@@ -914,6 +914,8 @@ dsrg_status make_rest_plan(const dsrg_df_rest_problem *rp, dsrg::RestPlan &pl) {
     pl.off_ft = take(sH * sP);
     pl.off_y = take(sA * sA * sV * sA);
     pl.off_tp = take(sH * sA * sP * sA);
+    pl.off_lp = take(sA * sA * sA * sA);
+    pl.off_ci = take(sH * sP * sA * sA);
     pl.off_ak = take(sA * sA * sA * sV);
     pl.off_bk = take(sA * sA * sA * sV);
     pl.off_y2 = take(sA * sA * sA * sA * sA * sA);
@@ -927,7 +929,8 @@ dsrg_status make_rest_plan(const dsrg_df_rest_problem *rp, dsrg::RestPlan &pl) {
   } else {
     pl.off_pcv = pl.off_pav = pl.off_pca = pl.off_paa = pl.off_qvc = pl.off_kcc = pl.off_x =
         pl.off_wt = pl.off_wv = pl.off_tcc = pl.off_vcc = pl.off_t1 = pl.off_ft = pl.off_y =
-            pl.off_tp = pl.off_ak = pl.off_bk = pl.off_y2 = pl.off_slots = 0;
+            pl.off_tp = pl.off_lp = pl.off_ci = pl.off_ak = pl.off_bk = pl.off_y2 =
+                pl.off_slots = 0;
     off = 256;
   }
   pl.total = off;

@@ -167,7 +167,7 @@ struct RestPlan {
   int64_t nc, na, nv, naux;
   double s;
   size_t off_pcv, off_pav, off_pca, off_paa, off_qvc, off_kcc, off_x, off_wt, off_wv, off_tcc,
-      off_vcc, off_t1, off_ft, off_y, off_tp, off_ak, off_bk, off_y2, off_slots;
+      off_vcc, off_t1, off_ft, off_y, off_tp, off_lp, off_ci, off_ak, off_bk, off_y2, off_slots;
   int64_t grid[kRestKernels], slot[kRestKernels];   // workgroups and first slot per kernel
   size_t total;
 };

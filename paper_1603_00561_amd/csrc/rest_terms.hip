@@ -567,18 +567,20 @@ __global__ __launch_bounds__(kRT) void rest_hca_kernel(RestDims d, const double 
   rest_emit(acc, 0.25, slots);
 }
 
-// I: Tp[j][v][b][y] = sum_{i, a} gamma_H[j][i] eta_P[a][b] t2[i,v,a,y], then
-// v~[j,x,b,u] sum_{v,y} Tp[j][v][b][y] lambda2[x,y,u,v]
+// I, in three steps: Tp[(j,b)][(v,y)] = sum_{i, a} gamma_H[j][i] eta_P[a][b]
+// t2[i,v,a,y]; then the product C[(j,b)][(x,u)] = sum_{(v,y)} Tp[(j,b)][(v,y)]
+// Lp[(v,y)][(x,u)] with Lp[(v,y)][(x,u)] = lambda2[x,y,u,v] (a GEMM over the
+// n^2 active spin-orbital pairs); then sum v~[j,x,b,u] C[(j,b)][(x,u)]
 __global__ __launch_bounds__(kRT) void rest_i_tp_kernel(RestDims d, const double *__restrict__ Wt,
                                                         const double *__restrict__ g1,
                                                         double *__restrict__ Tp) {
   const int n = d.sA;
-  REST_LOOP((int64_t)d.sH * n * d.sP * n) {
+  REST_LOOP((int64_t)d.sH * d.sP * n * n) {
     const int y = (int)(k % n);
     int64_t t = k / n;
-    const int b = (int)(t % d.sP);
-    t /= d.sP;
-    const int v = (int)(t % n), j = (int)(t / n);
+    const int v = (int)(t % n);
+    t /= n;
+    const int b = (int)(t % d.sP), j = (int)(t / d.sP);
     const bool ja = j >= d.sC, ba = b < d.sA;
     const int i0 = ja ? d.sC : j, i1 = ja ? d.sH : j + 1;
     const int a0 = ba ? 0 : b, a1 = ba ? d.sA : b + 1;
@@ -595,24 +597,29 @@ __global__ __launch_bounds__(kRT) void rest_i_tp_kernel(RestDims d, const double
   }
 }
 
+// Lp[(v,y)][(x,u)] = lambda2[x,y,u,v]
+__global__ __launch_bounds__(kRT) void rest_i_lam_kernel(RestDims d, const double *__restrict__ l2,
+                                                         double *__restrict__ Lp) {
+  const int n = d.sA;
+  REST_LOOP((int64_t)n * n * n * n) {
+    const int u = (int)(k % n), x = (int)((k / n) % n), y = (int)((k / n / n) % n);
+    const int v = (int)(k / n / n / n);
+    Lp[k] = l2at(l2, n, x, y, u, v);
+  }
+}
+
 __global__ __launch_bounds__(kRT) void rest_i_kernel(RestDims d, const double *__restrict__ Wv,
-                                                     const double *__restrict__ Tp,
-                                                     const double *__restrict__ l2,
+                                                     const double *__restrict__ C,
                                                      double *slots) {
   const int n = d.sA;
   double acc = 0.0;
   REST_LOOP((int64_t)d.sH * n * d.sP * n) {
-    const double w = Wv[k];
-    if (w == 0.0) continue;
     const int u = (int)(k % n);
     int64_t t = k / n;
     const int b = (int)(t % d.sP);
     t /= d.sP;
     const int x = (int)(t % n), j = (int)(t / n);
-    double c = 0.0;
-    for (int v = 0; v < n; ++v)
-      for (int y = 0; y < n; ++y) c += Tp[widx(d, j, v, b, y)] * l2at(l2, n, x, y, u, v);
-    acc += w * c;
+    acc += Wv[k] * C[(((int64_t)j * d.sP + b) * n + x) * n + u];
   }
   rest_emit(acc, 1.0, slots);
 }
@@ -708,7 +715,8 @@ hipError_t launch_rest_terms(const RestPlan &pl, const RestInputs &in, void *ws,
   double *Wt = ws_d(ws, pl.off_wt), *Wv = ws_d(ws, pl.off_wv);
   double *Tcc = ws_d(ws, pl.off_tcc), *Vcc = ws_d(ws, pl.off_vcc);
   double *t1 = ws_d(ws, pl.off_t1), *ft = ws_d(ws, pl.off_ft);
-  double *Y = ws_d(ws, pl.off_y), *Tp = ws_d(ws, pl.off_tp);
+  double *Y = ws_d(ws, pl.off_y), *Tp = ws_d(ws, pl.off_tp), *Lp = ws_d(ws, pl.off_lp),
+         *Ci = ws_d(ws, pl.off_ci);
   double *Ak = ws_d(ws, pl.off_ak), *Bk = ws_d(ws, pl.off_bk), *Y2 = ws_d(ws, pl.off_y2);
   double *slots = ws_d(ws, pl.off_slots);
 
@@ -764,7 +772,14 @@ hipError_t launch_rest_terms(const RestPlan &pl, const RestInputs &in, void *ws,
   hipLaunchKernelGGL(rest_hcc_kernel, dim3((unsigned)gr[7]), dim3(kRT), 0, st, d, Tcc, Vcc, l2, slots + sb[7]);
   hipLaunchKernelGGL(rest_hca_kernel, dim3((unsigned)gr[8]), dim3(kRT), 0, st, d, Wt, Wv, g1, l2, slots + sb[8]);
   hipLaunchKernelGGL(rest_i_tp_kernel, dim3((unsigned)grid_for(nW)), dim3(kRT), 0, st, d, Wt, g1, Tp);
-  hipLaunchKernelGGL(rest_i_kernel, dim3((unsigned)gr[9]), dim3(kRT), 0, st, d, Wv, Tp, l2, slots + sb[9]);
+  const int64_t nA2 = (int64_t)d.sA * d.sA;
+  hipLaunchKernelGGL(rest_i_lam_kernel, dim3((unsigned)grid_for(nA2 * nA2)), dim3(kRT), 0, st, d, l2,
+                     Lp);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = gemm_f64(false, false, (int64_t)d.sH * d.sP, nA2, nA2, 1.0, Tp, nA2, Lp, nA2, 0.0, Ci,
+                    nA2, st)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(rest_i_kernel, dim3((unsigned)gr[9]), dim3(kRT), 0, st, d, Wv, Ci, slots + sb[9]);
   hipLaunchKernelGGL(rest_j_kernel, dim3((unsigned)gr[10]), dim3(kRT), 0, st, d, Wt, Wv, l3, slots + sb[10]);
   const int64_t n3 = (int64_t)d.sA * d.sA * d.sA;
   hipLaunchKernelGGL(rest_k_pack_kernel, dim3((unsigned)grid_for(n3 * d.sV)), dim3(kRT), 0, st, d, Wt, Wv, Ak, Bk);
