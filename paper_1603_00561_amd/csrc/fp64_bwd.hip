@@ -350,12 +350,14 @@ struct GemmArgs {
 constexpr int kGT = 128, kGK = 16, kGA = kGK + 1, kGThreads = 512;
 
 template <bool TB>
-__global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *__restrict__ Apan,
+__global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const double *__restrict__ Apan,
                                                                   const double *__restrict__ G,
                                                                   GemmArgs a,
                                                                   double *__restrict__ C) {
   __shared__ double sA[2][kGT * kGA];
-  __shared__ double sB[2][kGK * kGT];
+  // Bm chunk: k-major 16 x 128 (half-swapped odd rows) for G, n-major
+  // 128 x (16 + 1) like sA for G^T (rows stored as loaded, no transpose)
+  __shared__ double sB[2][TB ? kGT * kGA : kGK * kGT];
   const int64_t Q0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
   // this workgroup's segment of the contraction, [kb, ke)
   const int64_t kb = (int64_t)blockIdx.z * a.kseg;
@@ -417,9 +419,8 @@ __global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *
         *reinterpret_cast<d2v *>(&sB[b][row * kGT + ((2 * c2) ^ swz(row))]) = rb[h];
       } else {
         const int nr = idx >> 3, c2 = idx & 7;
-        const int k0 = 2 * c2, k1 = 2 * c2 + 1;
-        sB[b][k0 * kGT + (nr ^ swz(k0))] = rb[h][0];
-        sB[b][k1 * kGT + (nr ^ swz(k1))] = rb[h][1];
+        sB[b][nr * kGA + 2 * c2] = rb[h][0];
+        sB[b][nr * kGA + 2 * c2 + 1] = rb[h][1];
       }
     }
   };
@@ -438,7 +439,9 @@ __global__ __launch_bounds__(kGThreads) void gemm_adj_fp64_kernel(const double *
 #pragma unroll
       for (int p = 0; p < 4; ++p) fa[p] = LA[(64 * wr + 16 * p + cl) * kGA + k];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) fb[q] = LB[k * kGT + ((32 * wc + 16 * q + cl) ^ swz(k))];
+      for (int q = 0; q < 2; ++q)
+        fb[q] = TB ? LB[(32 * wc + 16 * q + cl) * kGA + k]
+                   : LB[k * kGT + ((32 * wc + 16 * q + cl) ^ swz(k))];
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll

@@ -33,13 +33,32 @@ inline int8_t *ws_b(void *ws, size_t off) {
   return reinterpret_cast<int8_t *>(static_cast<char *>(ws) + off);
 }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
-// K segments of an FP64 adjoint product with a rows x ncols output (128 x 128
-// tiles): enough for about 1024 workgroups, each segment at least 512 long
-inline int64_t adj_segments(int64_t rows, int64_t ncols, int64_t K) {
+// K segments of an adjoint product with a rows x ncols output (128 x 128
+// tiles; `slots` workgroups run at once: two per CU for the FP64 product, one
+// for the int8 one), each segment at least 512 long. An output with fewer
+// than 1024 tiles takes enough segments for about 1024 workgroups; a larger
+// one takes the count from 1 to 4 that best fills the last round of
+// workgroups, ceil(tiles n / slots) / n rounds of the whole contraction, with
+// 1.5 % per extra segment for writing and adding the partial products.
+inline int64_t adj_segments(int64_t rows, int64_t ncols, int64_t K, int64_t slots = 512) {
   const int64_t tiles = ceil_div(rows, 128) * ceil_div(ncols, 128);
-  int64_t n = ceil_div(1024, tiles > 0 ? tiles : 1);
-  if (n > K / 512) n = K / 512;
-  return n < 1 ? 1 : n;
+  int64_t kmax = K / 512;
+  if (kmax < 1) kmax = 1;
+  if (tiles < 1024) {
+    int64_t n = ceil_div(1024, tiles > 0 ? tiles : 1);
+    if (n > kmax) n = kmax;
+    return n < 1 ? 1 : n;
+  }
+  int64_t best = 1;
+  double bcost = 1e300;
+  for (int64_t n = 1; n <= 4 && n <= kmax; ++n) {
+    const double cost = (double)ceil_div(tiles * n, slots) / (double)n * (1.0 + 0.015 * (double)(n - 1));
+    if (cost < bcost * (1.0 - 1e-9)) {
+      bcost = cost;
+      best = n;
+    }
+  }
+  return best;
 }
 // output columns of an adjoint product whose ncols columns come in groups of
 // GP of which the first nvalid are kept
@@ -57,7 +76,7 @@ constexpr int64_t kQChunk = 32;   // contraction chunk of the int8 operand panel
 // fixed order). Returns the segment count and their length in chunks.
 inline int64_t i8_segments(int64_t rows, int64_t ncols, int64_t K, int64_t &segc) {
   const int64_t nqc = ceil_div(K, kQChunk);
-  const int64_t want = adj_segments(rows, ncols, K);
+  const int64_t want = adj_segments(rows, ncols, K, 256);
   const int64_t seg = kGemmSeg / kQChunk;
   segc = ceil_div(nqc, want);
   if (segc > seg) segc = seg;
