@@ -34,8 +34,8 @@ inline int8_t *ws_b(void *ws, size_t off) {
 }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // K segments of an adjoint product with a rows x ncols output (128 x 128
-// tiles; `slots` workgroups run at once: two per CU for the FP64 product, one
-// for the int8 one), each segment at least 512 long. An output with fewer
+// tiles; `slots` workgroups run at once: two per CU for the FP64 product),
+// each segment at least 512 long. An output with fewer
 // than 1024 tiles takes enough segments for about 1024 workgroups; a larger
 // one takes the count from 1 to 4 that best fills the last round of
 // workgroups, ceil(tiles n / slots) / n rounds of the whole contraction, with
@@ -76,7 +76,10 @@ constexpr int64_t kQChunk = 32;   // contraction chunk of the int8 operand panel
 // fixed order). Returns the segment count and their length in chunks.
 inline int64_t i8_segments(int64_t rows, int64_t ncols, int64_t K, int64_t &segc) {
   const int64_t nqc = ceil_div(K, kQChunk);
-  const int64_t want = adj_segments(rows, ncols, K, 256);
+  // (the last-round rule of adj_segments is for the FP64 products; an int8
+  // product with 1024 tiles or more keeps one segment unless exactness needs more)
+  const int64_t tiles = ceil_div(rows, 128) * ceil_div(ncols, 128);
+  const int64_t want = tiles < 1024 ? adj_segments(rows, ncols, K) : 1;
   const int64_t seg = kGemmSeg / kQChunk;
   segc = ceil_div(nqc, want);
   if (segc > seg) segc = seg;
