@@ -12,7 +12,8 @@ energy alone for the CCVV slice kernel's rate) and reported under
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config cfg5]
                     [--precision fp64] [--energy] [--no-compare]
                     [--no-cpu-baseline]
-                    [--active | --dfgen | --fock | --semican | --rest | --cd]
+                    [--active | --dfgen | --fock | --semican | --rest | --cd |
+                     --laplace]
 
 --energy times dsrg_df_energy alone. With --active a step is one
 dsrg_df_energy_active call instead (the pieces F4-F8 of term F, FP64),
@@ -26,7 +27,10 @@ of that Fock matrix and C U, FP64); with --rest one dsrg_df_energy_rest call
 (the Table I terms A-E and G-K with the cumulants, FP64) for the config's
 orbital spaces; with --cd one dsrg_df_cholesky call (the CD factors of an
 s-Gaussian integral matrix of nao = 170 AO functions, the cc-pVDZ size of
-C10H6, to the threshold 1e-5 Eh, FP64).
+C10H6, to the threshold 1e-5 Eh, FP64); with --laplace one
+dsrg_df_coulomb_laplace call (the Coulomb part of E_CCVV factorized by a
+16-term exponential sum of the renormalised denominator, FP64) for the
+config, beside the direct CCVV energy kernel on the same inputs.
 
 Prints one JSON line. `value` is algorithmic TFLOP/s of the whole step:
 F_alg = 2 naux [nc(nc+1)/2 nv^2 + nc na nv^2 + nc^2 na nv] (the contractions
@@ -577,6 +581,9 @@ def main():
     ap.add_argument("--cd", action="store_true",
                     help="time the CD factor build (dsrg_df_cholesky, FP64) of the nao = 170 "
                          "s-Gaussian integral matrix to 1e-5 Eh")
+    ap.add_argument("--laplace", action="store_true",
+                    help="time the Laplace-factorized CCVV Coulomb part (dsrg_df_coulomb_laplace, "
+                         "FP64) with a 16-term exponential sum")
     ap.add_argument("--cd-max-rank", type=int, default=0,
                     help="max_rank of the --cd call (default 6 nao)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -612,6 +619,8 @@ def main():
         return bench_rest(args, binding, torch)
     if args.cd:
         return bench_cd(args, binding, torch)
+    if args.laplace:
+        return bench_laplace(args, binding, torch)
     p = make_config(args.config)
     if args.active:
         return bench_active(args, p, binding, torch)
@@ -1068,6 +1077,95 @@ def bench_cd(args, binding, torch):
                                          "numpy vector update per earlier vector)",
                                "host": host_info()}
         out["cpu_lapack_dpstrf"] = {"seconds": dl, "rank": int(lrank), "cores": cores}
+    print(json.dumps(out))
+
+
+
+def bench_laplace(args, binding, torch):
+    """--laplace: one step = one dsrg_df_coulomb_laplace call (FP64) with the
+    library's 16-term fit for the config's orbital energies; the direct FP64
+    CCVV energy (Coulomb and exchange, fifth order) is timed beside it."""
+    from paper_1603_00561_amd.workloads import make_config
+    if args.precision != "fp64" or args.grad or args.active:
+        print("bench.py: --laplace runs FP64 only", file=sys.stderr)
+        sys.exit(2)
+    nq = 16
+    p = make_config(args.config)
+    dev = torch.device("cuda:0")
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    Bcv, ec, ev = d(p.B_cv), d(p.eps_c), d(p.eps_v)
+    lo = 2.0 * (float(p.eps_v.min()) - float(p.eps_c.max()))
+    hi = 2.0 * (float(p.eps_v.max()) - float(p.eps_c.min()))
+    t, w, fit_err = binding.laplace_fit(p.s, lo, hi, nq)
+    ws = torch.empty(binding.laplace_workspace_size(p.nc, p.nv, p.naux, nq), dtype=torch.uint8,
+                     device=dev)
+    res = {}
+
+    def call(timing):
+        res["r"] = binding.coulomb_laplace(Bcv, ec, ev, t, w, workspace=ws, timing=timing)
+    for _ in range(args.warmup):
+        call(False)
+    torch.cuda.synchronize()
+    # launches of the batched product per call (the terms run in batches)
+    binding.kernel_times(1)
+    call(True)
+    torch.cuda.synchronize()
+    gemm_launches = sum(1 for n, _ in binding.kernel_times(4096) if n == "lt_gemm")
+    avg = kernel_table(binding, torch, call, table_steps(args))
+    ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps, ["lt_gemm"])
+    E = float(res["r"][0].item())
+    flops = 2.0 * p.naux * p.naux * p.nc * p.nv * nq
+    gemm_ms = dom_ms * gemm_launches if dom_ms else None
+    ach = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms else None
+    # the direct CCVV energy on the same inputs (Coulomb and exchange)
+    t_in = {k: d(getattr(p, k)) for k in ("B_cv", "B_ca", "B_av", "eps_c", "eps_a", "eps_v",
+                                          "gamma1")}
+
+    def direct():
+        return binding.energy(t_in["B_cv"], t_in["B_ca"], t_in["B_av"], t_in["eps_c"],
+                              t_in["eps_a"], t_in["eps_v"], t_in["gamma1"], p.s, terms="ccvv")
+    direct()
+    torch.cuda.synchronize()
+    nd = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(nd):
+        Ed = direct()
+    torch.cuda.synchronize()
+    direct_ms = (time.perf_counter() - t0) * 1e3 / nd
+    out = {
+        "metric": "DF-DSRG-MRPT2 energy(+grad) TFLOP/s & s/solve, FP64 vs split-BF16 @1µEh",
+        "value": flops / (ms_per_step * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "s_per_solve": ms_per_step * 1e-3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: nc={p.nc} nv={p.nv} naux={p.naux} s={p.s}, "
+                               f"Coulomb part of E_CCVV factorized with {nq} exponential-sum "
+                               "terms", "precision": "fp64", "parallelism": "single-gpu"},
+        "E_J_laplace": E, "fit_max_err": fit_err, "x_range": [lo, hi],
+        "direct_ccvv_energy_ms": direct_ms, "E_CCVV_direct": float(Ed[0].item()),
+        "kernel_ms": avg, "kernel_ms_from": table_note(args),
+        "roofline": {"bound": "mfma", "kernel": "lt_gemm", "avg_launch_ms": dom_ms,
+                     "launches_per_call": gemm_launches, "achieved": ach,
+                     "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": (ach / PEAK_TFLOPS["fp64"]) if ach else None,
+                     "flops_per_call": flops, "traffic": None},
+    }
+    ref_path = os.path.join(ROOT, "tests", "golden", "oracle_refs.json")
+    if os.path.exists(ref_path):
+        r = json.load(open(ref_path)).get(args.config, {}).get("laplace_nq16")
+        if r is not None:
+            out["rel_err_vs_exact_coulomb"] = abs(E - r["E_J"]) / abs(r["E_J"])
+    if not args.no_cpu_baseline:
+        from oracle import dsrg_laplace as L
+        cores = _blas_threads()
+        t0 = time.perf_counter()
+        e_ref, _ = L.coulomb_laplace(p.B_cv, p.eps_c, p.eps_v, t, w)
+        dt = time.perf_counter() - t0
+        out["abs_err_vs_oracle"] = abs(E - e_ref)
+        out["cpu_baseline"] = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": cores,
+                               "kind": "oracle", "seconds": dt,
+                               "sample": "the whole workload (factorized form in numpy, BLAS "
+                                         "on every thread)", "host": host_info()}
     print(json.dumps(out))
 
 

@@ -324,6 +324,45 @@ dsrg_status dsrg_df_cholesky(const dsrg_cd_problem *p, int options, double *B, i
                              double *dmax, int64_t *pivots, void *workspace, size_t ws_bytes,
                              void *stream);
 
+/* ---- Laplace-type factorization of the CCVV Coulomb part (the outlook of
+ * section VI: a decomposition of the renormalised denominators). With
+ * x = e_a + e_b - e_i - e_j > 0 the regulariser of Eq. expensive is
+ * R = -h(x), h(x) = (1 - exp(-2 s x^2)) / x; an exponential sum
+ * h(x) ~ sum_k w_k exp(-t_k x) on an interval holding every x separates over
+ * the four orbital energies, and the Coulomb part of E_CCVV,
+ * E_J = 2 sum_{ij,ab} (ia|jb)^2 R(Delta), becomes
+ *   E_J ~ -2 sum_k w_k S_k,  S_k = sum_PQ (Y_k)_PQ^2,
+ *   Y_k[P][Q] = sum_{ia} B^P_ia B^Q_ia exp(-t_k (e_a - e_i)),
+ * 2 naux^2 nc nv flops per term (fourth order) instead of the fifth-order
+ * pair sum. The exchange part of E_CCVV does not separate this way and is
+ * not computed here. */
+#define DSRG_DF_MAX_LAPLACE_TERMS 64
+
+/* The exponential sum (host, no device work): exponents t_k on a geometric
+ * grid from c1 / x_hi to c2 / x_lo, weights by linear least squares on 600
+ * logarithmically spaced points of [x_lo, x_hi]; (c1, c2) from {0.1, 0.3,
+ * 1.0} x {3, 10, 30}, the pair whose fit has the smallest largest absolute
+ * error max_err on 5000 such points. t, w: host arrays [nq], 1 <= nq <=
+ * DSRG_DF_MAX_LAPLACE_TERMS; 0 < x_lo < x_hi (for a problem: x_lo = 2
+ * (min e_v - max e_c), x_hi = 2 (max e_v - min e_c)); s >= 0 (s = 0: zero
+ * weights). The weights alternate in sign for larger nq: their cancellation
+ * costs up to about 1e6 of the FP64 rounding unit at nq = 20. */
+dsrg_status dsrg_df_laplace_fit(double s, double x_lo, double x_hi, int nq, double *t, double *w,
+                                double *max_err);
+
+/* Bytes of device workspace that dsrg_df_coulomb_laplace needs (sizes only;
+ * up to about 2 GiB of scaled factors and Y_k per batch of terms). */
+dsrg_status dsrg_df_laplace_workspace_size(const dsrg_df_problem *p, int nq, size_t *bytes);
+
+/* E [1] (device): -2 sum_k w_k S_k from B_cv, eps_c and eps_v of p (na, B_ca,
+ * B_av, gamma1 and s are not read); S [nq] (device, or NULL): the S_k.
+ * t, w: host arrays [nq] (t_k > 0), e.g. from dsrg_df_laplace_fit.
+ * options 0 or DSRG_OPT_KERNEL_TIMING. FP64 throughout. Errors as for
+ * dsrg_df_energy. */
+dsrg_status dsrg_df_coulomb_laplace(const dsrg_df_problem *p, int nq, const double *t,
+                                    const double *w, int options, double *E, double *S,
+                                    void *workspace, size_t ws_bytes, void *stream);
+
 /* ---- Generalized Fock matrix (Eq. gen_fock) over all MOs from the same DF
  * integrals (pq|rs) = sum_PQ (pq|P) [J^{-1}]_PQ (Q|rs):
  *   f_pq = h_pq + sum_{i in frozen+core} [2 (pq|ii) - (pi|qi)]

@@ -93,6 +93,21 @@ def coulomb_exact(B_cv, eps_c, eps_v, s) -> float:
     return float(-2.0 * math.fsum((V * V * h_of_x(x, s)).ravel()))
 
 
+def coulomb_exact_pairs(B_cv, eps_c, eps_v, s) -> float:
+    """E_J = 2 sum (ia|jb)^2 R(Delta) pair by pair (any size): for i <= j the
+    integrals K = B_i^T B_j, counted twice for i < j ((ia|jb)^2 and its
+    regulariser are symmetric under (i, a) <-> (j, b))."""
+    nc = B_cv.shape[1]
+    parts = []
+    for i in range(nc):
+        for j in range(i, nc):
+            K = B_cv[:, i, :].T @ B_cv[:, j, :]
+            x = eps_v[:, None] + eps_v[None, :] - eps_c[i] - eps_c[j]
+            v = -2.0 * math.fsum((K * K * h_of_x(x, s)).ravel())
+            parts.append(v if i == j else 2.0 * v)
+    return float(math.fsum(parts))
+
+
 def coulomb_laplace_plain(B_cv, eps_c, eps_v, t, w) -> float:
     """-2 sum_k w_k sum (ia|jb)^2 exp(-t_k x), summed over the quadruples
     (small inputs)."""

@@ -33,6 +33,7 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_noalloc"
             "dsrg_df_set_gradient_block_bytes", "dsrg_df_gradient_block_bytes",
             "dsrg_df_rest_workspace_size", "dsrg_df_energy_rest", "dsrg_df_cumulants",
             "dsrg_df_cholesky_workspace_size", "dsrg_df_cholesky",
+            "dsrg_df_laplace_fit", "dsrg_df_laplace_workspace_size", "dsrg_df_coulomb_laplace",
             "dsrg_df_version")
 
 
@@ -154,6 +155,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_cholesky_workspace_size.restype = i32
     lib.dsrg_df_cholesky.argtypes = [ctypes.POINTER(CDProblem), i32, vp, vp, vp, vp, vp, sz, vp]
     lib.dsrg_df_cholesky.restype = i32
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.dsrg_df_laplace_fit.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                                        dp, dp, dp]
+    lib.dsrg_df_laplace_fit.restype = i32
+    lib.dsrg_df_laplace_workspace_size.argtypes = [ctypes.POINTER(Problem), i32,
+                                                   ctypes.POINTER(sz)]
+    lib.dsrg_df_laplace_workspace_size.restype = i32
+    lib.dsrg_df_coulomb_laplace.argtypes = [ctypes.POINTER(Problem), i32, dp, dp, i32, vp, vp, vp,
+                                            sz, vp]
+    lib.dsrg_df_coulomb_laplace.restype = i32
     lib.dsrg_df_version.argtypes = []
     lib.dsrg_df_version.restype = i32
     _lib = lib
@@ -553,6 +564,60 @@ def cholesky(M, nao: int, tol: float, max_rank: int, workspace: Optional[torch.T
                    pivots=None if piv is None else piv[:r])
     del Md
     return out
+
+
+def laplace_fit(s: float, x_lo: float, x_hi: float, nq: int):
+    """(t [nq], w [nq], max_err) of the exponential sum via dsrg_df_laplace_fit
+    (host computation, numpy float64 arrays)."""
+    import numpy as np
+    lib = load_library()
+    t = np.zeros(nq)
+    w = np.zeros(nq)
+    err = ctypes.c_double(0.0)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.dsrg_df_laplace_fit(float(s), float(x_lo), float(x_hi), int(nq),
+                                   t.ctypes.data_as(dp), w.ctypes.data_as(dp), ctypes.byref(err)))
+    return t, w, err.value
+
+
+def laplace_workspace_size(nc, nv, naux, nq) -> int:
+    lib = load_library()
+    p = Problem(nc, 0, nv, naux, None, None, None, None, None, None, None, 0.5)
+    out = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_laplace_workspace_size(ctypes.byref(p), int(nq), ctypes.byref(out)))
+    return out.value
+
+
+def coulomb_laplace(B_cv, eps_c, eps_v, t, w, workspace: Optional[torch.Tensor] = None,
+                    timing: bool = False, with_terms: bool = True):
+    """(E [1], S [nq] or None) device tensors via dsrg_df_coulomb_laplace: the
+    factorized Coulomb part -2 sum_k w_k S_k of E_CCVV for the exponential
+    sum (t, w) (host sequences)."""
+    import numpy as np
+    lib = load_library()
+    naux, nc, nv = B_cv.shape
+    dev = B_cv.device
+    keep = [_as_dev(B_cv, "B_cv", (naux, nc, nv), dev), _as_dev(eps_c, "eps_c", (nc,), dev),
+            _as_dev(eps_v, "eps_v", (nv,), dev)]
+    p = Problem(nc, 0, nv, naux, _ptr(keep[0]), None, None, _ptr(keep[1]), None, _ptr(keep[2]),
+                None, 0.5)
+    th = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    wh = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    nq = len(th)
+    if len(wh) != nq:
+        raise ValueError("t and w differ in length")
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.dsrg_df_laplace_workspace_size(ctypes.byref(p), nq, ctypes.byref(nbytes)))
+    ws = _workspace(nbytes.value, dev, workspace)
+    E = torch.empty(1, dtype=torch.float64, device=dev)
+    S = torch.empty(nq, dtype=torch.float64, device=dev) if with_terms else None
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.dsrg_df_coulomb_laplace(ctypes.byref(p), nq, th.ctypes.data_as(dp),
+                                       wh.ctypes.data_as(dp), OPT_KERNEL_TIMING if timing else 0,
+                                       E.data_ptr(), _ptr(S), ws.data_ptr(), nbytes.value,
+                                       _stream_handle(dev)))
+    del keep
+    return E, S
 
 
 def energy_backward(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, gE, precision="fp64",

@@ -1083,6 +1083,98 @@ dsrg_status dsrg_df_cholesky(const dsrg_cd_problem *p, int options, double *B, i
   return DSRG_OK;
 }
 
+static_assert(dsrg::kLtMaxTerms == DSRG_DF_MAX_LAPLACE_TERMS, "the header states the term limit");
+
+namespace {
+// Plan of the Laplace-factorized Coulomb part: validation and workspace.
+dsrg_status make_lt_plan(const dsrg_df_problem *p, int nq, dsrg::LtPlan &pl) {
+  using namespace dsrg;
+  if (!p) return fail(DSRG_ERR_ARG, "problem pointer is NULL");
+  if (p->nc < 1 || p->nv < 1 || p->naux < 1)
+    return fail(DSRG_ERR_ARG, "sizes must satisfy nc, nv, naux >= 1");
+  if (nq < 1 || nq > kLtMaxTerms)
+    return fail(DSRG_ERR_ARG, "nq = %d is outside [1, %d]", nq, kLtMaxTerms);
+  pl.nc = p->nc;
+  pl.nv = p->nv;
+  pl.naux = p->naux;
+  pl.nq = nq;
+  const int64_t per_term = pl.naux * pl.nc * pl.nv + pl.naux * pl.naux;   // B D_k and Y_k
+  int64_t kb = (((int64_t)2 << 30) / 8) / std::max<int64_t>(per_term, 1);
+  pl.kb = (int)std::max<int64_t>(1, std::min<int64_t>(kb, nq));
+  pl.nwg = std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(pl.naux * pl.naux, 256)));
+  size_t off = 0;
+  auto take = [&](size_t doubles) {
+    const size_t at = off;
+    off = align256(off + sizeof(double) * doubles);
+    return at;
+  };
+  pl.off_bs = take((size_t)pl.kb * (size_t)(pl.naux * pl.nc * pl.nv));
+  pl.off_y = take((size_t)pl.kb * (size_t)(pl.naux * pl.naux));
+  pl.off_slots = take((size_t)nq * (size_t)pl.nwg);
+  pl.total = off;
+  return DSRG_OK;
+}
+}  // namespace
+
+dsrg_status dsrg_df_laplace_fit(double s, double x_lo, double x_hi, int nq, double *t, double *w,
+                                double *max_err) {
+  g_err[0] = 0;
+  if (!(s >= 0.0) || !std::isfinite(s)) return fail(DSRG_ERR_ARG, "s must be finite and >= 0");
+  if (!(x_lo > 0.0) || !(x_hi > x_lo) || !std::isfinite(x_hi))
+    return fail(DSRG_ERR_ARG, "need 0 < x_lo < x_hi, finite");
+  if (nq < 1 || nq > dsrg::kLtMaxTerms)
+    return fail(DSRG_ERR_ARG, "nq = %d is outside [1, %d]", nq, dsrg::kLtMaxTerms);
+  if (!t || !w || !max_err) return fail(DSRG_ERR_ARG, "t, w and max_err must not be NULL");
+  dsrg::laplace_fit(s, x_lo, x_hi, nq, t, w, max_err);
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_laplace_workspace_size(const dsrg_df_problem *p, int nq, size_t *bytes) {
+  g_err[0] = 0;
+  if (!bytes) return fail(DSRG_ERR_ARG, "bytes pointer is NULL");
+  dsrg::LtPlan pl;
+  dsrg_status st = make_lt_plan(p, nq, pl);
+  if (st != DSRG_OK) return st;
+  *bytes = pl.total;
+  return DSRG_OK;
+}
+
+dsrg_status dsrg_df_coulomb_laplace(const dsrg_df_problem *p, int nq, const double *t,
+                                    const double *w, int options, double *E, double *S,
+                                    void *workspace, size_t ws_bytes, void *stream) {
+  g_err[0] = 0;
+  dsrg::LtPlan pl;
+  dsrg_status st = make_lt_plan(p, nq, pl);
+  if (st != DSRG_OK) return st;
+  if (options & ~DSRG_OPT_KERNEL_TIMING)
+    return fail(DSRG_ERR_ARG, "unknown option bits 0x%x", options);
+  if (!t || !w) return fail(DSRG_ERR_ARG, "t and w (host arrays) must not be NULL");
+  for (int k = 0; k < nq; ++k)
+    if (!(t[k] > 0.0) || !std::isfinite(t[k]) || !std::isfinite(w[k]))
+      return fail(DSRG_ERR_ARG, "term %d: t must be finite and > 0, w finite", k);
+  const struct {
+    const void *ptr;
+    const char *name;
+    bool need;
+  } chk[] = {{p->B_cv, "B_cv", true}, {p->eps_c, "eps_c", true}, {p->eps_v, "eps_v", true},
+             {E, "E", true},          {S, "S", false}};
+  for (const auto &c : chk)
+    if ((c.need && !c.ptr) || (c.ptr && !aligned8(c.ptr)))
+      return fail(DSRG_ERR_ARG, "%s is NULL or misaligned", c.name);
+  if (ws_bytes < pl.total)
+    return fail(DSRG_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required",
+                ws_bytes, pl.total);
+  if (!workspace) return fail(DSRG_ERR_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255u)
+    return fail(DSRG_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  timer_reset((options & DSRG_OPT_KERNEL_TIMING) != 0);
+  hipError_t e = dsrg::launch_coulomb_laplace(pl, p->B_cv, p->eps_c, p->eps_v, t, w, E, S,
+                                              workspace, hs);
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "HIP launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
 const char *dsrg_df_last_error(void) { return g_err; }
 
 int dsrg_df_kernel_times(double *ms, const char **names, int cap) {

@@ -377,6 +377,14 @@ hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double al
   return gemm_g(ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, false, st);
 }
 
+hipError_t gemm_f64_batched(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                            const double *A, int64_t lda, int64_t sa, const double *B,
+                            int64_t ldb, int64_t sb, double beta, double *C, int64_t ldc,
+                            int64_t sc, int64_t batch, hipStream_t st) {
+  return gemm_g(ta, tb, M, N, K, alpha, A, lda, sa, B, ldb, sb, beta, C, ldc, sc, batch, false,
+                st);
+}
+
 // C = sum_{s < nseg} P[s] with P[s] = op(A) op(B) over the s-th of nseg
 // contiguous ranges of K (one launch, the segments as its batch index; the
 // partial products land in part[nseg][M][N]); then C = alpha sum_s P[s] +

@@ -287,6 +287,27 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
 hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                     const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                     double *C, int64_t ldc, hipStream_t st);
+// batch of products C_z = alpha op(A_z) op(B_z) + beta C_z, operands advanced
+// by the strides sa, sb, sc (doubles) per batch index (dfgen.hip)
+hipError_t gemm_f64_batched(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                            const double *A, int64_t lda, int64_t sa, const double *B,
+                            int64_t ldb, int64_t sb, double beta, double *C, int64_t ldc,
+                            int64_t sc, int64_t batch, hipStream_t st);
+// ---- Laplace-type factorization of the CCVV Coulomb part (laplace.hip) ----
+constexpr int kLtMaxTerms = 64;   // exponential-sum terms per call
+struct LtPlan {
+  int64_t nc, nv, naux;
+  int nq, kb;       // terms, terms per batch
+  int64_t nwg;      // sum-of-squares workgroups per term
+  size_t off_bs, off_y, off_slots;
+  size_t total;
+};
+hipError_t launch_coulomb_laplace(const LtPlan &pl, const double *B_cv, const double *eps_c,
+                                  const double *eps_v, const double *t, const double *w,
+                                  double *E, double *S, void *ws, hipStream_t st);
+// host: exponential-sum fit of h(x) = (1 - exp(-2 s x^2)) / x on [x_lo, x_hi]
+int laplace_fit(double s, double x_lo, double x_hi, int nq, double *t, double *w,
+                double *max_err);
 // ---- generalized Fock matrix (dfgen.hip) ----
 struct FockPlan {
   int64_t nao, nmo, naux, nfrz, nc, na, nv;

@@ -7,7 +7,10 @@ workloads. Calls only the oracle and the seeded generator.
     python tests/golden/make_oracle_refs.py --active [cfg ...]
 
 With --active only the pieces F4-F8 of term F are computed (key "F48_s<s>")
-and merged into the existing entries.
+and merged into the existing entries; with --laplace the Laplace-factorized
+Coulomb part of E_CCVV (key "laplace_nq<N>": the oracle's exponential-sum fit
+t, w and its error, the per-term sums S_k, the factorized energy and the
+exact Coulomb part).
 """
 import json
 import os
@@ -19,6 +22,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
+from oracle import dsrg_laplace as L  # noqa: E402
 from oracle import dsrg_oracle as O  # noqa: E402
 from paper_1603_00561_amd.workloads import CONFIGS, make_config  # noqa: E402
 
@@ -72,16 +76,40 @@ def run_active(name, entry):
     return entry
 
 
+LAPLACE_NQ = 16
+
+
+def run_laplace(name, entry):
+    p = make_config(name)
+    lo, hi = L.spectral_range(p.eps_c, p.eps_v)
+    t0 = time.time()
+    t, w, err = L.laplace_fit(p.s, lo, hi, LAPLACE_NQ)
+    e_lt, S = L.coulomb_laplace(p.B_cv, p.eps_c, p.eps_v, t, w)
+    t1 = time.time()
+    e_j = L.coulomb_exact_pairs(p.B_cv, p.eps_c, p.eps_v, p.s)
+    entry["laplace_nq%d" % LAPLACE_NQ] = dict(
+        x_lo=lo, x_hi=hi, t=[float(x) for x in t], w=[float(x) for x in w], max_err=err,
+        S=[float(x) for x in S], E_LT=e_lt, E_J=e_j, t_lt=t1 - t0, t_exact=time.time() - t1)
+    print(name, "laplace", e_lt, e_j, err, time.time() - t0, flush=True)
+    return entry
+
+
 def main():
     args = sys.argv[1:]
     active = "--active" in args
-    names = [a for a in args if a != "--active"] or list(CONFIGS)
+    laplace = "--laplace" in args
+    names = [a for a in args if a not in ("--active", "--laplace")] or list(CONFIGS)
     refs = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             refs = json.load(f)
     for n in names:
-        refs[n] = run_active(n, refs.get(n, {})) if active else {**refs.get(n, {}), **run(n)}
+        if laplace:
+            refs[n] = run_laplace(n, refs.get(n, {}))
+        elif active:
+            refs[n] = run_active(n, refs.get(n, {}))
+        else:
+            refs[n] = {**refs.get(n, {}), **run(n)}
         with open(OUT, "w") as f:
             json.dump(refs, f, indent=1)
 

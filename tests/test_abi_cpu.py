@@ -354,3 +354,55 @@ def test_factor_build_without_metric_sizes(lib):
     st = lib.dsrg_df_factors(ctypes.byref(p), 0, *[ctypes.c_void_p(0x20000)] * 4,
                              ctypes.c_void_p(0x40000), 1 << 40, None)
     assert st == b.DSRG_ERR_ARG                                        # misaligned J
+
+
+def test_laplace_fit_matches_the_oracle_and_validates(lib):
+    """The library's host fit (Householder QR) against the oracle's (numpy
+    least squares): the same exponents, the same largest error, the same
+    fitted function; and the host-side rejection of bad arguments."""
+    import numpy as np
+    from oracle import dsrg_laplace as L
+    for s, nq in ((0.5, 8), (0.5, 16), (1.0, 12), (1e8, 10), (0.0, 4), (0.3, 1)):
+        t, w, err = b.laplace_fit(s, 0.8, 14.0, nq)
+        to, wo, eo = L.laplace_fit(s, 0.8, 14.0, nq)
+        assert np.allclose(t, to, rtol=1e-14, atol=0)
+        assert err == pytest.approx(eo, rel=1e-6, abs=1e-300)
+        xc = np.geomspace(0.8, 14.0, 2000)
+        f = np.exp(-np.outer(xc, t)) @ w
+        fo = np.exp(-np.outer(xc, to)) @ wo
+        assert np.abs(f - fo).max() <= max(1e-3 * eo, 1e-14)
+    d = ctypes.POINTER(ctypes.c_double)
+    buf = (ctypes.c_double * 64)()
+    e = ctypes.c_double(0.0)
+    for args in ((-1.0, 0.8, 14.0, 4), (0.5, 0.0, 14.0, 4), (0.5, 2.0, 1.0, 4),
+                 (0.5, 0.8, 14.0, 0), (0.5, 0.8, 14.0, 65), (float("nan"), 0.8, 14.0, 4)):
+        assert lib.dsrg_df_laplace_fit(*args, buf, buf, ctypes.byref(e)) == b.DSRG_ERR_ARG, args
+    assert lib.dsrg_df_laplace_fit(0.5, 0.8, 14.0, 4, None, buf, ctypes.byref(e)) == b.DSRG_ERR_ARG
+
+
+def test_coulomb_laplace_entry_point_validation(lib):
+    import numpy as np
+    p = _prob(nc=4, na=0, nv=30, naux=20)
+    out = ctypes.c_size_t(0)
+    assert lib.dsrg_df_laplace_workspace_size(ctypes.byref(p), 8, ctypes.byref(out)) == 0
+    assert out.value >= 8 * (20 * 4 * 30 + 20 * 20)
+    for nq in (0, 65):
+        assert lib.dsrg_df_laplace_workspace_size(ctypes.byref(p), nq, ctypes.byref(out)) == \
+            b.DSRG_ERR_ARG
+    d = ctypes.POINTER(ctypes.c_double)
+    t = np.array([0.1, 1.0, 3.0])
+    w = np.array([1.0, -0.5, 0.25])
+
+    def call(p, t=t, w=w, opts=0, E=0x20000, S=0, ws=0x40000, nb=1 << 40):
+        v = lambda x: ctypes.c_void_p(x) if x else None
+        return lib.dsrg_df_coulomb_laplace(ctypes.byref(p), len(t), t.ctypes.data_as(d),
+                                           w.ctypes.data_as(d), opts, v(E), v(S), v(ws), nb, None)
+
+    assert call(_prob(nc=0, na=0, nv=30, naux=20)) == b.DSRG_ERR_ARG
+    assert call(p, t=np.array([0.1, 0.0, 3.0])) == b.DSRG_ERR_ARG        # t must be > 0
+    assert call(p, w=np.array([1.0, float("inf"), 0.0])) == b.DSRG_ERR_ARG
+    assert call(p, E=0) == b.DSRG_ERR_ARG
+    assert call(p, S=0x20004) == b.DSRG_ERR_ARG                           # misaligned
+    assert call(p, opts=0x100) == b.DSRG_ERR_ARG
+    assert call(p, nb=16) == b.DSRG_ERR_WORKSPACE
+    assert call(p, ws=0x40008) == b.DSRG_ERR_WORKSPACE

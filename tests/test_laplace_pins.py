@@ -106,3 +106,10 @@ def test_h_is_the_ccvv_regulariser_and_the_exact_coulomb_part():
             D = p.eps_c[i] + p.eps_c[j] - p.eps_v[:, None] - p.eps_v[None, :]
             e += 2.0 * float(np.sum(K * K * O.reg_R(D, p.s)))
     assert L.coulomb_exact(p.B_cv, p.eps_c, p.eps_v, p.s) == pytest.approx(e, rel=1e-13)
+
+
+def test_pair_loop_equals_the_four_index_sum():
+    p = _small(seed=12, nc=5, nv=7, naux=10)
+    for s in (0.3, 1.5):
+        assert L.coulomb_exact_pairs(p.B_cv, p.eps_c, p.eps_v, s) == pytest.approx(
+            L.coulomb_exact(p.B_cv, p.eps_c, p.eps_v, s), rel=1e-13)
