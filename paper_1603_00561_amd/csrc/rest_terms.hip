@@ -688,6 +688,29 @@ __global__ void rest_zero_kernel(double *p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
 }
 
+// X[i][j] = X[j][i] for the entries below the strip diagonal blocks (row i in
+// the strip of rows [r0, r1), column j < r0), 32 x 32 tiles through LDS so
+// that reads and writes are both coalesced; grid (column tiles, row tiles)
+// over the whole matrix, tiles with nothing to copy return at once
+__global__ __launch_bounds__(256) void rest_mirror_kernel(double *X, int64_t n, int64_t strip) {
+  __shared__ double tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+  // strips are a multiple of 32 wide, so every row of a tile has the same
+  // strip start
+  const int64_t rstart = (i0 / strip) * strip;
+  if (j0 >= rstart) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t sj = j0 + r, si = i0 + tx;   // source X[sj][si] (upper part)
+    if (sj < n && si < n) tile[r][tx] = X[sj * n + si];
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    if (i < n && j < n && j < rstart) X[i * n + j] = tile[tx][r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launcher
 // ---------------------------------------------------------------------------
@@ -728,14 +751,33 @@ hipError_t launch_rest_terms(const RestPlan &pl, const RestInputs &in, void *ws,
     const double *B;
     int64_t N;
     double *C;
-  } gs[7] = {{in.B_cv, nc * nv, in.B_aa, na2, Pcv},      {in.B_av, na * nv, in.B_aa, na2, Pav},
+  } gs[6] = {{in.B_cv, nc * nv, in.B_aa, na2, Pcv},      {in.B_av, na * nv, in.B_aa, na2, Pav},
              {in.B_ca, nc * na, in.B_aa, na2, Pca},      {in.B_aa, na2, in.B_aa, na2, Paa},
-             {in.B_av, na * nv, in.B_ca, nc * na, Qvc},  {in.B_ca, nc * na, in.B_ca, nc * na, Kcc},
-             {in.B_av, na * nv, in.B_av, na * nv, X}};
+             {in.B_av, na * nv, in.B_ca, nc * na, Qvc},  {in.B_ca, nc * na, in.B_ca, nc * na, Kcc}};
   for (const G &g : gs) {
     if ((e = gemm_f64(true, false, g.M, g.N, naux, 1.0, g.A, g.M, g.B, g.N, 0.0, g.C, g.N, st)) !=
         hipSuccess)
       return e;
+  }
+  // X = (xe|yf) = B_av^T B_av is symmetric: row strips of the upper triangle
+  // (each strip from its diagonal block to the last column), then the rest
+  // mirrored
+  {
+    const int64_t n = na * nv;
+    const int64_t nstrip = std::max<int64_t>(1, std::min<int64_t>(8, n / 768));
+    const int64_t strip = round_up(ceil_div(n, nstrip), 32);
+    for (int64_t r0 = 0; r0 < n; r0 += strip) {
+      const int64_t r1 = std::min(n, r0 + strip);
+      if ((e = gemm_f64(true, false, r1 - r0, n - r0, naux, 1.0, in.B_av + r0, n, in.B_av + r0, n,
+                        0.0, X + r0 * n + r0, n, st)) != hipSuccess)
+        return e;
+    }
+    if (strip < n) {
+      hipLaunchKernelGGL(rest_mirror_kernel,
+                         dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32)), dim3(256), 0,
+                         st, X, n, strip);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   timer_end(st);
   RestInts I{Pcv, Pav, Pca, Paa, Qvc, Kcc};
