@@ -273,7 +273,7 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       int64_t most = 0;
       auto consider = [&](int64_t ncols, int64_t GPc, int64_t nvalid, int64_t K) {
         if (ncols <= 0 || K <= 0) return;
-        int64_t nseg = adj_segments(pl.naux, ncols, K);
+        int64_t nseg = adj_fp64_segments(pl.naux, ncols, GPc, nvalid, K);
         if (split) {
           int64_t segc = 0;
           nseg = i8_segments(pl.naux, ncols, K, segc);

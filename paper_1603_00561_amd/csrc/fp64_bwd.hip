@@ -326,10 +326,15 @@ __global__ __launch_bounds__(256) void ccav_adj_fp64_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint GEMM: C[Q][col(n)] (+)= sum_k A[Q][k] Bm[k][n], with
+// Adjoint GEMM: C[Q][n] (+)= sum_k A[Q][k] Bm[k][n], with
 //   A[Q][k]  = Apan[k / PW][Q][k % PW]   (packed panels, Q rows < naux_p)
-//   Bm[k][n] = TB ? G[n * ldg + k] : G[k * ldg + n]
-//   col(n)   = (n / GP) * nvalid + n % GP for n % GP < nvalid (else skipped)
+//   Bm[k][n] = TB ? G[g(n) * ldg + k] : G[k * ldg + g(n)]
+//   g(n)     = (n / nvalid) * GP + n % nvalid when compact (the valid columns
+//              of every group of GP, side by side), else g(n) = n with the
+//              output column (n / GP) * nvalid + n % GP for n % GP < nvalid
+// The contraction index runs over groups of kgrp of which the first kval are
+// valid (a core orbital's virtual panels): chunks wholly past kval hold only
+// the panels' zero padding and are skipped.
 // 128 x 128 output tile per workgroup of 8 waves (two per SIMD: the FP64
 // matrix cores need a second wave to issue back to back), wave w owning rows
 // 64 (w >> 2) .. +63 and columns 32 (w & 3) .. +31; K chunks of 16 staged
@@ -339,15 +344,35 @@ struct GemmArgs {
   int64_t naux, naux_p;   // rows of C / rows stored per panel
   int64_t K;              // contraction length (multiple of 16)
   int PW;                 // panel width of A (16 or 64)
-  int64_t Ncols;          // columns of Bm (padded index space, even)
+  int64_t Ncols;          // columns of Bm (compact: valid columns only)
   int64_t ldg;
   int64_t GP, nvalid, ldc;
   int accumulate;
+  int compact;
+  int64_t kgrp, kval;     // contraction groups and their valid chunks (multiple of kGK)
   int64_t kseg;      // contraction indices per segment (blockIdx.z), a multiple of kGK
   int64_t zstride;   // doubles between the outputs of two segments
 };
 
 constexpr int kGT = 128, kGK = 16, kGA = kGK + 1, kGThreads = 512;
+
+// A contraction chunk: its first index k and that index's place in its group.
+struct AdjChunk {
+  int64_t k;
+  int64_t in;
+  // the first chunk at or after this one that holds a valid index
+  __device__ __forceinline__ void settle(const GemmArgs &a) {
+    if (in >= a.kval) {
+      k += a.kgrp - in;
+      in = 0;
+    }
+  }
+  __device__ __forceinline__ AdjChunk next(const GemmArgs &a) const {
+    AdjChunk c{k + kGK, in + kGK};
+    c.settle(a);
+    return c;
+  }
+};
 
 template <bool TB>
 __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const double *__restrict__ Apan,
@@ -362,6 +387,8 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
   // this workgroup's segment of the contraction, [kb, ke)
   const int64_t kb = (int64_t)blockIdx.z * a.kseg;
   const int64_t ke = (kb + a.kseg < a.K) ? kb + a.kseg : a.K;
+  // the G column (!TB) or row (TB) each thread loads is the same in every chunk
+  auto gcol = [&](int64_t n) { return a.compact ? (n / a.nvalid) * a.GP + n % a.nvalid : n; };
   C += (int64_t)blockIdx.z * a.zstride;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -376,6 +403,16 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
 
   // a chunk is 128 x 16 of A and 16 x 128 of Bm: 1024 double2 each, two per thread
   d2v ra[2], rb[2];
+  int64_t goff[2];
+  bool gok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = t + h * kGThreads;
+    // !TB: columns n, n + 1 (nvalid even when compact: one group)
+    const int64_t n = TB ? n0 + (idx >> 3) : n0 + 2 * (idx & 63);
+    gok[h] = n < a.Ncols;
+    goff[h] = gcol(n);
+  }
   auto gload = [&](int64_t k0) {
     const int64_t pan = k0 / a.PW, c0 = k0 % a.PW;
     const double *Ab = Apan + pan * a.naux_p * a.PW + c0;
@@ -392,14 +429,12 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
       const int idx = t + h * kGThreads;
       if constexpr (!TB) {
         const int row = idx >> 6, c2 = idx & 63;   // 16 rows x 64 double2
-        const int64_t n = n0 + 2 * c2;
-        rb[h] = (n < a.Ncols) ? *reinterpret_cast<const d2v *>(G + (k0 + row) * a.ldg + n)
-                              : d2v{0.0, 0.0};
+        rb[h] = gok[h] ? *reinterpret_cast<const d2v *>(G + (k0 + row) * a.ldg + goff[h])
+                       : d2v{0.0, 0.0};
       } else {
-        const int nr = idx >> 3, c2 = idx & 7;     // 128 n-rows x 8 double2
-        const int64_t n = n0 + nr;
-        rb[h] = (n < a.Ncols) ? *reinterpret_cast<const d2v *>(G + n * a.ldg + k0 + 2 * c2)
-                              : d2v{0.0, 0.0};
+        const int c2 = idx & 7;                    // 128 n-rows x 8 double2
+        rb[h] = gok[h] ? *reinterpret_cast<const d2v *>(G + goff[h] * a.ldg + k0 + 2 * c2)
+                       : d2v{0.0, 0.0};
       }
     }
   };
@@ -425,12 +460,18 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
     }
   };
 
-  gload(kb);
-  sstore(0);
-  if (kb + kGK < ke) gload(kb + kGK);
+  // chunks c0 (in LDS), c1 (in registers) and c2 (next to load)
+  AdjChunk c0{kb, kb % a.kgrp};
+  c0.settle(a);
+  AdjChunk c1 = c0.next(a), c2 = c1.next(a);
+  if (c0.k < ke) {
+    gload(c0.k);
+    sstore(0);
+    if (c1.k < ke) gload(c1.k);
+  }
   __syncthreads();
   int b = 0;
-  for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
+  for (; c0.k < ke; c0 = c1, c1 = c2, c2 = c2.next(a)) {
     const double *LA = sA[b], *LB = sB[b];
 #pragma unroll
     for (int kk = 0; kk < kGK / 4; ++kk) {
@@ -447,9 +488,9 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[p][q] = mfma64(fa[p], fb[q], acc[p][q]);
     }
-    if (k0 + kGK < ke) {
+    if (c1.k < ke) {
       sstore(b ^ 1);
-      if (k0 + 2 * kGK < ke) gload(k0 + 2 * kGK);
+      if (c2.k < ke) gload(c2.k);
     }
     __syncthreads();
     b ^= 1;
@@ -459,8 +500,8 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
     const int64_t n = n0 + 32 * wc + 16 * q + cl;
     if (n >= a.Ncols) continue;
     const int64_t grp = n / a.GP, cc = n % a.GP;
-    if (cc >= a.nvalid) continue;
-    const int64_t col = grp * a.nvalid + cc;
+    if (!a.compact && cc >= a.nvalid) continue;
+    const int64_t col = a.compact ? n : grp * a.nvalid + cc;
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -514,16 +555,21 @@ static hipError_t gemm(const Plan &pl, void *ws, const double *Apan, int PW, int
   a.naux_p = pl.naux_p;
   a.K = npan * PW;
   a.PW = PW;
-  a.Ncols = Ncols;
+  a.compact = (nvalid % 2 == 0 && Ncols % GP == 0) ? 1 : 0;
+  a.Ncols = adj_fp64_cols(Ncols, GP, nvalid);
   a.ldg = ldg;
   a.GP = GP;
   a.nvalid = nvalid;
   a.ldc = ldc;
   a.accumulate = accumulate ? 1 : 0;
+  // a core orbital's virtual panels (PW 64) hold nv valid columns of ntv 64;
+  // the active panels (PW 16) are one chunk each
+  a.kgrp = (PW == kPanel) ? pl.ntv * kPanel : PW;
+  a.kval = (PW == kPanel) ? round_up(pl.nv, kGK) : PW;
   a.kseg = a.K;
   a.zstride = 0;
   const int64_t ncol = adj_out_cols(Ncols, GP, nvalid);
-  int64_t nseg = adj_segments(pl.naux, Ncols, a.K);
+  int64_t nseg = adj_fp64_segments(pl.naux, Ncols, GP, nvalid, a.K);
   if (nseg > 1) {
     a.kseg = round_up(ceil_div(a.K, nseg), kGK);
     nseg = ceil_div(a.K, a.kseg);
@@ -539,7 +585,7 @@ static hipError_t gemm(const Plan &pl, void *ws, const double *Apan, int PW, int
     a.kseg = a.K;
     nseg = 1;
   }
-  const dim3 grid((unsigned)ceil_div(pl.naux, kGT), (unsigned)ceil_div(Ncols, kGT),
+  const dim3 grid((unsigned)ceil_div(pl.naux, kGT), (unsigned)ceil_div(a.Ncols, kGT),
                   (unsigned)nseg);
   timer_begin(TB ? "gemm_adj_tb_fp64" : "gemm_adj_fp64", st);
   hipLaunchKernelGGL(gemm_adj_fp64_kernel<TB>, grid, dim3(kGThreads), 0, st, Apan, G, a, out);

@@ -35,14 +35,16 @@ inline int8_t *ws_b(void *ws, size_t off) {
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // K segments of an adjoint product with a rows x ncols output (128 x 128
 // tiles; `slots` workgroups run at once: two per CU for the FP64 product),
-// each segment at least 512 long. An output with fewer
-// than 1024 tiles takes enough segments for about 1024 workgroups; a larger
-// one takes the count from 1 to 4 that best fills the last round of
+// each segment at least 512 long and at most nmax of them. An output with
+// fewer than 1024 tiles takes enough segments for about 1024 workgroups; a
+// larger one takes the count from 1 to 4 that best fills the last round of
 // workgroups, ceil(tiles n / slots) / n rounds of the whole contraction, with
 // 1.5 % per extra segment for writing and adding the partial products.
-inline int64_t adj_segments(int64_t rows, int64_t ncols, int64_t K, int64_t slots = 512) {
+inline int64_t adj_segments(int64_t rows, int64_t ncols, int64_t K, int64_t slots = 512,
+                            int64_t nmax = (int64_t)1 << 30) {
   const int64_t tiles = ceil_div(rows, 128) * ceil_div(ncols, 128);
   int64_t kmax = K / 512;
+  if (kmax > nmax) kmax = nmax;
   if (kmax < 1) kmax = 1;
   if (tiles < 1024) {
     int64_t n = ceil_div(1024, tiles > 0 ? tiles : 1);
@@ -65,6 +67,20 @@ inline int64_t adj_segments(int64_t rows, int64_t ncols, int64_t K, int64_t slot
 inline int64_t adj_out_cols(int64_t ncols, int64_t GP, int64_t nvalid) {
   const int64_t rem = ncols % GP;
   return (ncols / GP) * nvalid + (rem < nvalid ? rem : nvalid);
+}
+// columns of the FP64 adjoint products' tile space: with nvalid even, the valid
+// columns of every group of GP side by side, else the padded index space
+inline int64_t adj_fp64_cols(int64_t ncols, int64_t GP, int64_t nvalid) {
+  return (nvalid % 2 == 0 && ncols % GP == 0) ? (ncols / GP) * nvalid : ncols;
+}
+// Segments of an FP64 adjoint product, their partial products bounded by
+// kAdjPartBytes.
+constexpr int64_t kAdjPartBytes = (int64_t)512 << 20;
+inline int64_t adj_fp64_segments(int64_t rows, int64_t ncols, int64_t GP, int64_t nvalid,
+                                 int64_t K) {
+  const int64_t part = 8 * rows * adj_out_cols(ncols, GP, nvalid);
+  const int64_t cap = part > 0 ? kAdjPartBytes / part : 1;
+  return adj_segments(rows, adj_fp64_cols(ncols, GP, nvalid), K, 512, cap < 1 ? 1 : cap);
 }
 // contraction indices per exact int32 segment of the int8 adjoint products
 // (|I_L| <= 4 127^2 kGemmSeg < 2^31)
