@@ -268,29 +268,33 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       // the largest. Shapes (ncols, GP, nvalid, K) as the products take them,
       // for the full-size and the last (smaller) core block.
       const int64_t gp = Wg, n2 = pl.na * Wg, n3 = pl.nc * kActPanel;
+      const int64_t wk = round_up(pl.nv, kQChunk);
       const int64_t n3p = round_up(n3, kQChunk);
       const int64_t blast = pl.nc - (pl.ngb - 1) * pl.gb;
       int64_t most = 0;
-      auto consider = [&](int64_t ncols, int64_t GPc, int64_t nvalid, int64_t K) {
+      // (Kk: the int8 product's contraction length, which runs over wk per
+      // orbital; its output columns are the valid ones side by side)
+      auto consider = [&](int64_t ncols, int64_t GPc, int64_t nvalid, int64_t K, int64_t Kk) {
         if (ncols <= 0 || K <= 0) return;
         int64_t nseg = adj_fp64_segments(pl.naux, ncols, GPc, nvalid, K);
+        const int64_t ncol = adj_out_cols(ncols, GPc, nvalid);
         if (split) {
           int64_t segc = 0;
-          nseg = i8_segments(pl.naux, ncols, K, segc);
+          nseg = i8_segments(pl.naux, ncol, Kk, segc);
         }
-        if (nseg > 1) most = std::max(most, nseg * pl.naux * adj_out_cols(ncols, GPc, nvalid));
+        if (nseg > 1) most = std::max(most, nseg * pl.naux * ncol);
       };
       for (const int64_t bi : {pl.gb, blast})
         for (const int64_t bj : {pl.gb, blast}) {
-          if (term_bits & DSRG_TERM_CCVV) consider(bj * gp, gp, pl.nv, bi * gp);
+          if (term_bits & DSRG_TERM_CCVV) consider(bj * gp, gp, pl.nv, bi * gp, bi * wk);
           if (has_cavv) {
-            consider(bi * gp, gp, pl.nv, n2);
-            consider(n2, gp, pl.nv, bi * gp);
+            consider(bi * gp, gp, pl.nv, n2, pl.na * wk);
+            consider(n2, gp, pl.nv, bi * gp, bi * wk);
           }
         }
       if (has_ccav) {
-        consider(Np, gp, pl.nv, split ? n3p : n3);
-        consider(n3, kActPanel, pl.na, Np);
+        consider(Np, gp, pl.nv, n3, n3p);
+        consider(n3, kActPanel, pl.na, Np, pl.nc * wk);
       }
       if (most > 0) {
         pl.off_gpart = off;
@@ -303,21 +307,25 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
       pl.off_opmax = off;
   if (split && pl.with_grad) {
     // operand slices of the int8 adjoint products (5 bytes per element) and
-    // their row scales; the G operands share one buffer, used in turn
-    const size_t W = (size_t)(pl.ntv * kPanel), Np = (size_t)pl.nc * W,
-                 N2 = (size_t)pl.na * W, N3 = (size_t)(pl.nc * kActPanel);
-    const size_t N3p = (size_t)round_up((int64_t)N3, 32);
+    // their row scales; the G operands share one buffer, used in turn. A
+    // contraction over (orbital, virtual) runs over Wk = nv rounded up to 32
+    // per orbital, and operand rows over (orbital, virtual) hold the nv valid
+    // ones side by side.
+    const size_t Wk = (size_t)round_up(pl.nv, 32), nv = (size_t)pl.nv;
+    const size_t Np = (size_t)pl.nc * Wk, N2 = (size_t)pl.na * Wk,
+                 N3 = (size_t)(pl.nc * pl.na);
+    const size_t N3p = (size_t)round_up(pl.nc * kActPanel, 32);
     const size_t RA = (size_t)round_up(pl.naux, 128);
-    const size_t Nb = (size_t)pl.gb * W;   // rows of one block of core orbitals
+    const size_t gb = (size_t)pl.gb;
     auto r128 = [](size_t n) { return (size_t)round_up((int64_t)n, 128); };
     const bool act = pl.na > 0 && (term_bits & (DSRG_TERM_CAVV | DSRG_TERM_CCAV));
     size_t sb = 0, rbmax = 0;
-    if (term_bits & DSRG_TERM_CCVV) sb = std::max(sb, r128(Nb) * Nb);
+    if (term_bits & DSRG_TERM_CCVV) sb = std::max(sb, r128(gb * nv) * gb * Wk);
     if (pl.na > 0 && (term_bits & DSRG_TERM_CAVV))
-      sb = std::max(sb, std::max(r128(Nb) * N2, r128(N2) * Nb));
+      sb = std::max(sb, std::max(r128(gb * nv) * N2, r128(pl.na * nv) * gb * Wk));
     if (pl.na > 0 && (term_bits & DSRG_TERM_CCAV))
-      sb = std::max(sb, std::max(r128(Np) * N3p, r128(N3) * Np));
-    rbmax = std::max(r128(Np), std::max(r128(N2), r128(N3)));
+      sb = std::max(sb, std::max(r128(pl.nc * nv) * N3p, r128(N3) * Np));
+    rbmax = std::max(r128(pl.nc * nv), std::max(r128(pl.na * nv), r128(N3)));
     pl.off_SA1 = off;
     off = align256(off + 5 * RA * Np);
     pl.off_SA2 = off;

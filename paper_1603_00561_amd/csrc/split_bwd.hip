@@ -659,8 +659,15 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
   // adjoint tiles
   if ((e = launch_adjoint_start_fp64(pl, in, o, ws, st)) != hipSuccess) return e;
   if ((e = launch_slices(pl, in, ws, cavv, st)) != hipSuccess) return e;
-  const int64_t W = pl.ntv * kPanel;             // padded virtual orbitals per orbital
-  const int64_t Np = pl.nc * W, N2 = pl.na * W, N3 = pl.nc * kActPanel;
+  // Memory: G rows and columns over (orbital, virtual) in groups of W = 64 ntv.
+  // Products: a contraction over (orbital, virtual) runs over Wk = nv rounded
+  // up to 32 per orbital (whole chunks, a block of orbitals a contiguous range
+  // of them), and operand rows over (orbital, virtual) hold the nv valid ones
+  // side by side, so the outputs are written densely.
+  const int64_t W = pl.ntv * kPanel;
+  const int64_t nv = pl.nv, Wk = round_up(pl.nv, kQC);
+  const int64_t N2 = pl.na * W, N3 = pl.nc * kActPanel;
+  const int64_t Npk = pl.nc * Wk, N2k = pl.na * Wk;
   const int64_t N3p = round_up(N3, kQC);
   const int64_t RA = round_up(pl.naux, kI8Tile);
   const int64_t big = (int64_t)1 << 40;
@@ -670,23 +677,21 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
   int8_t *SA1 = ws_b(ws, pl.off_SA1), *SA2 = ws_b(ws, pl.off_SA2), *SB = ws_b(ws, pl.off_SB);
   const double *G3 = ws_d(ws, pl.off_g3);
   const int64_t ldcv = pl.nc * pl.nv;
-  const int64_t nqcp = Np / kQC;                 // chunks of A1 (a multiple of 2 per orbital)
+  const int64_t nqcp = Npk / kQC;                // chunks of A1
   auto blk = [&](int64_t I, int64_t &b0, int64_t &nb) {
     b0 = I * pl.gb;
     nb = std::min(pl.gb, pl.nc - b0);
   };
 
-  // A1 = B_cv with rows Q and contraction index (m, e) over the padded range Np;
-  // a block of core orbitals is a contiguous range of its chunks
-  const OpMap Acv = op_map(in.B_cv, big, pl.naux, 0, ldcv, pl.naux, W, pl.nv, pl.nv, 1, Np);
-  if ((e = pack_operand(Acv, RA, Np, sigA1, pmax, SA1, st)) != hipSuccess) return e;
+  // A1 = B_cv with rows Q and contraction index (m, e)
+  const OpMap Acv = op_map(in.B_cv, big, pl.naux, 0, ldcv, pl.naux, Wk, nv, nv, 1, Npk);
+  if ((e = pack_operand(Acv, RA, Npk, sigA1, pmax, SA1, st)) != hipSuccess) return e;
 
   bool written = false;   // dB_cv holds a first product in every block
   if (cavv) {
     // A2 = B_av with contraction index (w, f)
-    const OpMap Aav = op_map(in.B_av, big, pl.naux, 0, pl.na * pl.nv, pl.naux, W, pl.nv, pl.nv,
-                             1, N2);
-    if ((e = pack_operand(Aav, RA, N2, sigA2, pmax, SA2, st)) != hipSuccess) return e;
+    const OpMap Aav = op_map(in.B_av, big, pl.naux, 0, pl.na * nv, pl.naux, Wk, nv, nv, 1, N2k);
+    if ((e = pack_operand(Aav, RA, N2k, sigA2, pmax, SA2, st)) != hipSuccess) return e;
     const double *G2 = ws_d(ws, pl.off_g2);
     for (int64_t I = 0; I < pl.ngb; ++I) {
       int64_t m0, mb;
@@ -694,21 +699,20 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
       // G2 rows of this block and the CAVV eps / s parts from slice-path integrals
       if ((e = launch_cavv_x_split(pl, ws, (int)m0, (int)mb, st)) != hipSuccess) return e;
       if ((e = launch_cavv_adj_epi(pl, in, o, ws, (int)m0, (int)mb, st)) != hipSuccess) return e;
-      const int64_t Nb = mb * W;
       // dB_cv[Q][(m,e)] (+)= sum_(w,f) B_av[Q][(w,f)] G2[(m,e)][(w,f)], m in the block
-      const int64_t RB = round_up(Nb, kI8Tile);
-      const OpMap B2t = op_map(G2, W, pl.nv, W * N2, N2, Nb, W, pl.nv, W, 1, N2);
-      if ((e = pack_operand(B2t, RB, N2, sigB, pmax, SB, st)) != hipSuccess) return e;
-      if ((e = i8_gemm(SA2, sigA2, RA, N2 / kQC, 0, SB, sigB, RB, N2, pl.naux, Nb, W, pl.nv,
-                       o.dB_cv + m0 * pl.nv, ldcv, false, part, pl.gpart_doubles, st)) != hipSuccess)
+      const int64_t RB = round_up(mb * nv, kI8Tile);
+      const OpMap B2t = op_map(G2, nv, nv, W * N2, N2, mb * nv, Wk, nv, W, 1, N2k);
+      if ((e = pack_operand(B2t, RB, N2k, sigB, pmax, SB, st)) != hipSuccess) return e;
+      if ((e = i8_gemm(SA2, sigA2, RA, N2k / kQC, 0, SB, sigB, RB, N2k, pl.naux, mb * nv, nv, nv,
+                       o.dB_cv + m0 * nv, ldcv, false, part, pl.gpart_doubles, st)) != hipSuccess)
         return e;
       // dB_av[Q][(w,f)] (+)= sum_(m,e) B_cv[Q][(m,e)] G2[(m,e)][(w,f)], m in the block
-      const int64_t RB2 = round_up(N2, kI8Tile);
-      const OpMap B2 = op_map(G2, W, pl.nv, W, 1, N2, W, pl.nv, W * N2, N2, Nb);
-      if ((e = pack_operand(B2, RB2, Nb, sigB, pmax, SB, st)) != hipSuccess) return e;
-      if ((e = i8_gemm(SA1, sigA1, RA, nqcp, m0 * W / kQC, SB, sigB, RB2, Nb, pl.naux, N2, W,
-                       pl.nv, o.dB_av, pl.na * pl.nv, I > 0, part, pl.gpart_doubles, st)) !=
-          hipSuccess)
+      const int64_t RB2 = round_up(pl.na * nv, kI8Tile);
+      const OpMap B2 = op_map(G2, nv, nv, W, 1, pl.na * nv, Wk, nv, W * N2, N2, mb * Wk);
+      if ((e = pack_operand(B2, RB2, mb * Wk, sigB, pmax, SB, st)) != hipSuccess) return e;
+      if ((e = i8_gemm(SA1, sigA1, RA, nqcp, m0 * Wk / kQC, SB, sigB, RB2, mb * Wk, pl.naux,
+                       pl.na * nv, nv, nv, o.dB_av, pl.na * nv, I > 0, part, pl.gpart_doubles,
+                       st)) != hipSuccess)
         return e;
     }
     written = true;
@@ -750,24 +754,24 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
                            ws_d(ws, pl.off_slots));
         timer_end(st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const int64_t Ni = ni * W, Nj = nj * W, ld = Nj;
+        const int64_t ld = nj * W;   // row length of the G block
         // dB_cv[Q][(j,b)] (+)= sum_(i,a) B_cv[Q][(i,a)] G[(i,a)][(j,b)]; block J is
         // first written by the pair (0, J)
-        const int64_t RBj = round_up(Nj, kI8Tile);
-        const OpMap Bn = op_map(G, W, pl.nv, W, 1, Nj, W, pl.nv, W * ld, ld, Ni);
-        if ((e = pack_operand(Bn, RBj, Ni, sigB, pmax, SB, st)) != hipSuccess) return e;
-        if ((e = i8_gemm(SA1, sigA1, RA, nqcp, i0 * W / kQC, SB, sigB, RBj, Ni, pl.naux, Nj, W,
-                         pl.nv, o.dB_cv + j0 * pl.nv, ldcv, written || I > 0, part,
+        const int64_t RBj = round_up(nj * nv, kI8Tile);
+        const OpMap Bn = op_map(G, nv, nv, W, 1, nj * nv, Wk, nv, W * ld, ld, ni * Wk);
+        if ((e = pack_operand(Bn, RBj, ni * Wk, sigB, pmax, SB, st)) != hipSuccess) return e;
+        if ((e = i8_gemm(SA1, sigA1, RA, nqcp, i0 * Wk / kQC, SB, sigB, RBj, ni * Wk, pl.naux,
+                         nj * nv, nv, nv, o.dB_cv + j0 * nv, ldcv, written || I > 0, part,
                          pl.gpart_doubles, st)) != hipSuccess)
           return e;
         if (J > I) {
           // dB_cv[Q][(i,a)] += sum_(j,b) B_cv[Q][(j,b)] G[(i,a)][(j,b)]
-          const int64_t RBi = round_up(Ni, kI8Tile);
-          const OpMap Bt = op_map(G, W, pl.nv, W * ld, ld, Ni, W, pl.nv, W, 1, Nj);
-          if ((e = pack_operand(Bt, RBi, Nj, sigB, pmax, SB, st)) != hipSuccess) return e;
-          if ((e = i8_gemm(SA1, sigA1, RA, nqcp, j0 * W / kQC, SB, sigB, RBi, Nj, pl.naux, Ni, W,
-                           pl.nv, o.dB_cv + i0 * pl.nv, ldcv, true, part, pl.gpart_doubles,
-                           st)) != hipSuccess)
+          const int64_t RBi = round_up(ni * nv, kI8Tile);
+          const OpMap Bt = op_map(G, nv, nv, W * ld, ld, ni * nv, Wk, nv, W, 1, nj * Wk);
+          if ((e = pack_operand(Bt, RBi, nj * Wk, sigB, pmax, SB, st)) != hipSuccess) return e;
+          if ((e = i8_gemm(SA1, sigA1, RA, nqcp, j0 * Wk / kQC, SB, sigB, RBi, nj * Wk, pl.naux,
+                           ni * nv, nv, nv, o.dB_cv + i0 * nv, ldcv, true, part,
+                           pl.gpart_doubles, st)) != hipSuccess)
             return e;
         }
       }
@@ -778,19 +782,21 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const OpMap Aca = op_map(in.B_ca, big, pl.naux, 0, pl.nc * pl.na, pl.naux, kActPanel, pl.na,
                              pl.na, 1, N3);
     if ((e = pack_operand(Aca, RA, N3p, sigA2, pmax, SA2, st)) != hipSuccess) return e;
-    const int64_t RB = round_up(Np, kI8Tile);
-    const OpMap B3t = op_map(G3, W, pl.nv, W * N3, N3, Np, kActPanel, pl.na, kActPanel, 1, N3);
+    const int64_t RB = round_up(pl.nc * nv, kI8Tile);
+    const OpMap B3t = op_map(G3, nv, nv, W * N3, N3, pl.nc * nv, kActPanel, pl.na, kActPanel, 1,
+                             N3);
     if ((e = pack_operand(B3t, RB, N3p, sigB, pmax, SB, st)) != hipSuccess) return e;
-    if ((e = i8_gemm(SA2, sigA2, RA, N3p / kQC, 0, SB, sigB, RB, N3p, pl.naux, Np, W, pl.nv,
+    if ((e = i8_gemm(SA2, sigA2, RA, N3p / kQC, 0, SB, sigB, RB, N3p, pl.naux, pl.nc * nv, nv, nv,
                      o.dB_cv, ldcv, written, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
     written = true;
     // dB_ca[Q][(n,u)] = sum_(m,e) B_cv[Q][(m,e)] G3[(m,e)][(n,u)]
-    const int64_t RB3 = round_up(N3, kI8Tile);
-    const OpMap B3 = op_map(G3, kActPanel, pl.na, kActPanel, 1, N3, W, pl.nv, W * N3, N3, Np);
-    if ((e = pack_operand(B3, RB3, Np, sigB, pmax, SB, st)) != hipSuccess) return e;
-    if ((e = i8_gemm(SA1, sigA1, RA, nqcp, 0, SB, sigB, RB3, Np, pl.naux, N3, kActPanel, pl.na,
-                     o.dB_ca, pl.nc * pl.na, false, part, pl.gpart_doubles, st)) != hipSuccess)
+    const int64_t n3v = pl.nc * pl.na;
+    const int64_t RB3 = round_up(n3v, kI8Tile);
+    const OpMap B3 = op_map(G3, pl.na, pl.na, kActPanel, 1, n3v, Wk, nv, W * N3, N3, Npk);
+    if ((e = pack_operand(B3, RB3, Npk, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = i8_gemm(SA1, sigA1, RA, nqcp, 0, SB, sigB, RB3, Npk, pl.naux, n3v, pl.na, pl.na,
+                     o.dB_ca, n3v, false, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
   } else if (o.dB_ca) {
     if ((e = launch_zero_fill(o.dB_ca, pl.naux * pl.nc * pl.na, st)) != hipSuccess) return e;
