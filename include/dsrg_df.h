@@ -89,7 +89,17 @@ enum {
   DSRG_OPT_ATOMIC_REDUCE = 0x100,
   /* Option bit: record a HIP event pair around every kernel the call
    * enqueues, so dsrg_df_kernel_times() can report per-kernel durations. */
-  DSRG_OPT_KERNEL_TIMING = 0x200
+  DSRG_OPT_KERNEL_TIMING = 0x200,
+  /* Option bit (dsrg_df_energy, dsrg_df_energy_noalloc,
+   * dsrg_df_energy_backward): check that the contribution of every CCVV work
+   * item (one tile of virtual pairs (a, b) of one core pair) is <= 0, as
+   * Eq. expensive makes it when every denominator e_i + e_j - e_a - e_b is
+   * negative (R(Delta) <= 0 and (ia|jb)^2 - (ia|jb)(ib|ja) + (ib|ja)^2 >= 0).
+   * A positive or NaN contribution sets bit 0 of the device's sign check
+   * word (dsrg_df_sign_check). The library does not require the orbital
+   * energies to be ordered; this is how a caller can learn that they were
+   * not. The results are the same with and without the bit. */
+  DSRG_OPT_CHECK_SIGNS = 0x400
 };
 
 /* One problem. Orbitals are ordered core | active | virtual; only the three
@@ -422,6 +432,13 @@ dsrg_status dsrg_df_semicanonicalize_workspace_size(const dsrg_semican_problem *
 dsrg_status dsrg_df_semicanonicalize(const dsrg_semican_problem *p, int options, double *U,
                                      double *eps, double *Cs, int *info, void *workspace,
                                      size_t ws_bytes, void *stream);
+
+/* The current device's sign check word (see DSRG_OPT_CHECK_SIGNS): waits for
+ * every stream of the device to finish (hipDeviceSynchronize), stores the word
+ * in *word (host; bit 0: some CCVV work item of a call made with the option
+ * since the last read gave a positive or NaN contribution) and clears it.
+ * DSRG_ERR_ARG if word is NULL, DSRG_ERR_HIP if a HIP call fails. */
+dsrg_status dsrg_df_sign_check(unsigned *word);
 
 /* Text of the last error raised on the calling thread ("" if none). Valid
  * until the next dsrg_df_* call on that thread. */

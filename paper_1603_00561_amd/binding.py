@@ -21,6 +21,7 @@ TERM_BITS = {"ccvv": 1, "cavv": 2, "ccav": 4}
 TERM_ALL = 7
 OPT_ATOMIC_REDUCE = 0x100
 OPT_KERNEL_TIMING = 0x200
+OPT_CHECK_SIGNS = 0x400
 MAX_ACTIVE = 8
 
 EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_noalloc",
@@ -34,7 +35,7 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_noalloc"
             "dsrg_df_rest_workspace_size", "dsrg_df_energy_rest", "dsrg_df_cumulants",
             "dsrg_df_cholesky_workspace_size", "dsrg_df_cholesky",
             "dsrg_df_laplace_fit", "dsrg_df_laplace_workspace_size", "dsrg_df_coulomb_laplace",
-            "dsrg_df_version")
+            "dsrg_df_sign_check", "dsrg_df_version")
 
 
 class DsrgError(RuntimeError):
@@ -110,6 +111,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_energy.restype = i32
     lib.dsrg_df_energy_noalloc.argtypes = [ctypes.POINTER(Problem), i32, i32, vp, vp]
     lib.dsrg_df_energy_noalloc.restype = i32
+    lib.dsrg_df_sign_check.argtypes = [ctypes.POINTER(ctypes.c_uint)]
+    lib.dsrg_df_sign_check.restype = i32
     lib.dsrg_df_energy_backward.argtypes = [ctypes.POINTER(Problem), i32, i32, vp,
                                             vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dsrg_df_energy_backward.restype = i32
@@ -299,12 +302,14 @@ def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.
 
 def energy(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
            terms="all", atomic=False, workspace: Optional[torch.Tensor] = None,
-           timing: bool = False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """E_CCVV, E_CAVV, E_CCAV (device tensor [3], float64) via dsrg_df_energy."""
+           timing: bool = False, out: Optional[torch.Tensor] = None,
+           check_signs: bool = False) -> torch.Tensor:
+    """E_CCVV, E_CAVV, E_CCAV (device tensor [3], float64) via dsrg_df_energy
+    (check_signs: DSRG_OPT_CHECK_SIGNS, read with sign_check())."""
     lib = load_library()
     p, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s)
     dev = B_cv.device
-    mask = _terms_mask(terms, atomic, timing)
+    mask = _terms_mask(terms, atomic, timing) | (OPT_CHECK_SIGNS if check_signs else 0)
     prec = PRECISIONS[precision]
     nbytes = ctypes.c_size_t(0)
     _check(lib.dsrg_df_workspace_size(ctypes.byref(p), prec, mask, 0, ctypes.byref(nbytes)))
@@ -317,18 +322,29 @@ def energy(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
 
 
 def energy_noalloc(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, precision="fp64",
-                   terms="all", atomic=False, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                   terms="all", atomic=False, out: Optional[torch.Tensor] = None,
+                   check_signs: bool = False) -> torch.Tensor:
     """E_CCVV, E_CAVV, E_CCAV via dsrg_df_energy_noalloc (the library's static
     device scratch instead of a workspace; out, when given, is written in place)."""
     lib = load_library()
     p, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s)
     dev = B_cv.device
-    mask = _terms_mask(terms, atomic, False)
+    mask = _terms_mask(terms, atomic, False) | (OPT_CHECK_SIGNS if check_signs else 0)
     E = torch.empty(3, dtype=torch.float64, device=dev) if out is None else out
     _check(lib.dsrg_df_energy_noalloc(ctypes.byref(p), PRECISIONS[precision], mask, E.data_ptr(),
                                       _stream_handle(dev)))
     del keep
     return E
+
+
+def sign_check() -> int:
+    """The current device's sign check word via dsrg_df_sign_check (waits for
+    the device; bit 0: a CCVV work item of a call with check_signs gave a
+    positive or NaN contribution since the last read), then cleared."""
+    lib = load_library()
+    w = ctypes.c_uint(0)
+    _check(lib.dsrg_df_sign_check(ctypes.byref(w)))
+    return int(w.value)
 
 
 def cumulants(rdm1, rdm2, rdm3):
@@ -622,7 +638,7 @@ def coulomb_laplace(B_cv, eps_c, eps_v, t, w, workspace: Optional[torch.Tensor] 
 
 def energy_backward(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, gE, precision="fp64",
                     terms="all", want_energy=True, workspace: Optional[torch.Tensor] = None,
-                    timing: bool = False):
+                    timing: bool = False, check_signs: bool = False):
     """Gradient of sum_t gE[t] E_t via dsrg_df_energy_backward.
 
     Returns a dict with device tensors dB_cv, dB_ca, dB_av, deps_c, deps_a,
@@ -631,7 +647,7 @@ def energy_backward(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s, gE, precis
     p, keep = make_problem_struct(B_cv, B_ca, B_av, eps_c, eps_a, eps_v, gamma1, s)
     dev = B_cv.device
     gE = _as_dev(gE, "gE", (3,), dev)
-    mask = _terms_mask(terms, False, timing)
+    mask = _terms_mask(terms, False, timing) | (OPT_CHECK_SIGNS if check_signs else 0)
     prec = PRECISIONS[precision]
     nbytes = ctypes.c_size_t(0)
     _check(lib.dsrg_df_workspace_size(ctypes.byref(p), prec, mask, 1, ctypes.byref(nbytes)))

@@ -94,7 +94,8 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
     return fail(DSRG_ERR_ARG, "unknown precision %d", precision);
   const int term_bits = terms & DSRG_TERM_ALL;
   if (term_bits == 0) return fail(DSRG_ERR_ARG, "term mask selects no term (0x%x)", terms);
-  if (terms & ~(DSRG_TERM_ALL | DSRG_OPT_ATOMIC_REDUCE | DSRG_OPT_KERNEL_TIMING))
+  if (terms & ~(DSRG_TERM_ALL | DSRG_OPT_ATOMIC_REDUCE | DSRG_OPT_KERNEL_TIMING |
+                DSRG_OPT_CHECK_SIGNS))
     return fail(DSRG_ERR_ARG, "unknown bits in term mask 0x%x", terms);
   const bool need_act = p->na > 0 && (term_bits & (DSRG_TERM_CAVV | DSRG_TERM_CCAV));
   if (need_act && p->na > DSRG_DF_MAX_ACTIVE)
@@ -126,6 +127,23 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   pl.ntv = ceil_div(pl.nv, kPanel);
   pl.ntv_s = (precision == DSRG_SPLIT_OZAKI) ? round_up(pl.ntv, 2) : pl.ntv;
   pl.xld = pl.ntv_s * kPanel;
+  {
+    // every count and byte size formed below is at most one of these
+    // products (panels and slices, the adjoint tiles of all core pairs, the
+    // CAVV integrals, the work lists, the CCAV integrals with up to 1024
+    // auxiliary segments): refuse a problem for which one of them would not
+    // fit in 62 bits, so that the int64 and size_t sums here never overflow
+    const double nc = (double)pl.nc, na = (double)pl.na, W = (double)pl.xld,
+                 q = (double)pl.naux_p;
+    const double big = std::max({8.0 * (nc + na) * W * q, 8.0 * (nc * W) * (nc * W),
+                                 8.0 * nc * na * W * W, (nc * nc) * (W * W),
+                                 8.0 * 1024.0 * (nc * W) * (nc * na + 16.0)});
+    if (!(big < 0x1p62))
+      return fail(DSRG_ERR_UNSUPPORTED,
+                  "problem too large (nc %lld, na %lld, nv %lld, naux %lld): its workspace "
+                  "sizes would not fit in 64 bits",
+                  (long long)pl.nc, (long long)pl.na, (long long)pl.nv, (long long)pl.naux);
+  }
 
   const int64_t npo = tri_off(pl.nc), ntpo = tri_off(pl.ntv);
   // one slot per (core pair, tile pair): 64-wide tiles in FP64, 128-wide on slices
@@ -530,7 +548,26 @@ void timer_end(hipStream_t st) {
 }
 }  // namespace dsrg
 
+// DSRG_OPT_CHECK_SIGNS: the current device's sign check word for the kernels
+static dsrg_status sign_check_setup(int terms, dsrg::Plan &pl) {
+  pl.chk = nullptr;
+  if (!(terms & DSRG_OPT_CHECK_SIGNS)) return DSRG_OK;
+  hipError_t e = dsrg::sign_check_ptr(&pl.chk);
+  if (e != hipSuccess)
+    return fail(DSRG_ERR_HIP, "sign check word lookup failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
 extern "C" {
+
+dsrg_status dsrg_df_sign_check(unsigned *word) {
+  g_err[0] = 0;
+  if (!word) return fail(DSRG_ERR_ARG, "word pointer is NULL");
+  hipError_t e = dsrg::sign_check_read(word);
+  if (e != hipSuccess)
+    return fail(DSRG_ERR_HIP, "sign check word read failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
 
 dsrg_status dsrg_df_workspace_size(const dsrg_df_problem *p, int precision, int terms,
                                    int with_grad, size_t *bytes) {
@@ -552,6 +589,7 @@ dsrg_status dsrg_df_energy(const dsrg_df_problem *p, int precision, int terms, d
   if ((st = check_inputs(p, pl)) != DSRG_OK) return st;
   if (!E_terms || !aligned8(E_terms)) return fail(DSRG_ERR_ARG, "E_terms is NULL or misaligned");
   if ((st = check_workspace(pl, workspace, ws_bytes)) != DSRG_OK) return st;
+  if ((st = sign_check_setup(terms, pl)) != DSRG_OK) return st;
 
   dsrg::Inputs in{p->B_cv, p->B_ca, p->B_av, p->eps_c, p->eps_a, p->eps_v, p->gamma1};
   hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
@@ -578,6 +616,7 @@ dsrg_status dsrg_df_energy_noalloc(const dsrg_df_problem *p, int precision, int 
                 "problem needs %zu bytes of workspace, more than the %zu of the static scratch "
                 "(use dsrg_df_energy with a workspace)",
                 pl.total, dsrg::kNoAllocScratchBytes);
+  if ((st = sign_check_setup(terms, pl)) != DSRG_OK) return st;
   void *ws = nullptr;
   hipError_t e = dsrg::noalloc_scratch(&ws);
   if (e != hipSuccess)
@@ -615,6 +654,7 @@ dsrg_status dsrg_df_energy_backward(const dsrg_df_problem *p, int precision, int
   if (E_terms && !aligned8(E_terms)) return fail(DSRG_ERR_ARG, "E_terms is misaligned");
   if ((st = check_workspace(pl, workspace, ws_bytes)) != DSRG_OK) return st;
 
+  if ((st = sign_check_setup(terms, pl)) != DSRG_OK) return st;
   pl.atomic_reduce = false;   // the adjoint kernels always fill per-workgroup slots
   dsrg::Inputs in{p->B_cv, p->B_ca, p->B_av, p->eps_c, p->eps_a, p->eps_v, p->gamma1};
   dsrg::BwdOut o{dB_cv, pl.na > 0 ? dB_ca : nullptr, pl.na > 0 ? dB_av : nullptr,
@@ -1102,6 +1142,11 @@ dsrg_status make_lt_plan(const dsrg_df_problem *p, int nq, dsrg::LtPlan &pl) {
     return fail(DSRG_ERR_ARG, "sizes must satisfy nc, nv, naux >= 1");
   if (nq < 1 || nq > kLtMaxTerms)
     return fail(DSRG_ERR_ARG, "nq = %d is outside [1, %d]", nq, kLtMaxTerms);
+  // B D_k and Y_k of one term, in bytes, must fit in 62 bits (the sizes below)
+  const double nc = (double)p->nc, nv = (double)p->nv, naux = (double)p->naux;
+  if (!(8.0 * naux * (nc * nv + naux) < 0x1p62))
+    return fail(DSRG_ERR_UNSUPPORTED, "problem too large (nc %lld, nv %lld, naux %lld)",
+                (long long)p->nc, (long long)p->nv, (long long)p->naux);
   pl.nc = p->nc;
   pl.nv = p->nv;
   pl.naux = p->naux;

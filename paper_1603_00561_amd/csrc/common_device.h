@@ -122,6 +122,14 @@ __device__ __forceinline__ double block_sum_n(double v, double *red) {
 
 // Deliver one workgroup's partial energy: its own slot (deterministic
 // reduction) or an FP64 atomic into the term accumulator.
+// Sign check of a CCVV work item's contribution (Eq. expensive): with every
+// denominator Delta = e_i + e_j - e_a - e_b negative, R(Delta) <= 0 and
+// x^2 - x y + y^2 >= 0, so each term and their sum are <= 0 in any rounding.
+// A positive or NaN sum sets bit 0 of *chk (nullptr: not checked).
+__device__ __forceinline__ void check_nonpositive(double t, unsigned *chk) {
+  if (chk && threadIdx.x == 0 && !(t <= 0.0)) atomicOr(chk, 1u);
+}
+
 __device__ __forceinline__ void emit_partial(double t, double *slots, int64_t slot,
                                              double *acc, int atomic_mode) {
   if (threadIdx.x == 0) {

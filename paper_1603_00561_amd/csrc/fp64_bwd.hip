@@ -67,6 +67,7 @@ struct CcvvAdjArgs {
   // entries whose row orbital is in the row block stored)
   int r0, nr, c0, ncb;
   int64_t ld;   // row length of the G block (ncb 64 ntv)
+  unsigned *chk;   // sign check word (nullptr: off)
 };
 
 // pair p of a block pair -> (i, j), i <= j
@@ -212,6 +213,7 @@ __global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
   const double tD = block_sum(d_part, lds);
   __syncthreads();
   const double tS = block_sum(s_part, lds);
+  check_nonpositive(tE, a.chk);
   if (threadIdx.x == 0) {
     slots[a.slot_base + pt.item] = tE;
     atomicAdd(&g.deps_c[c.i], gE0 * tD);
@@ -685,6 +687,7 @@ static hipError_t ccvv_adj_block_fp64(const Plan &pl, const Inputs &in, const Bw
   a.c0 = (int)(J * pl.gb);
   a.ncb = (int)std::min(pl.gb, pl.nc - J * pl.gb);
   a.ld = (int64_t)a.ncb * pl.ntv * kPanel;
+  a.chk = pl.chk;
   const int64_t T = pl.ntv * (pl.ntv + 1) / 2;
   a.slot_base = ccvv_block_slot(pl, I, J, T);
   const int64_t npair = (I == J) ? (int64_t)a.nr * (a.nr + 1) / 2 : (int64_t)a.nr * a.ncb;

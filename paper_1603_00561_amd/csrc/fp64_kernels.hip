@@ -49,6 +49,7 @@ struct CcvvArgs {
   int64_t n0, n1, n2;      // sizes of the first three work classes
   int64_t slot_base;
   int atomic_mode;
+  unsigned *chk;           // sign check word (nullptr: off)
 };
 
 __device__ __forceinline__ double ccvv_weight(int cls) {
@@ -103,6 +104,7 @@ __global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict
     }
   }
   const double t = block_sum(part, lds) * ccvv_weight(c.cls);
+  check_nonpositive(t, a.chk);
   emit_partial(t, slots, a.slot_base + slot, acc, a.atomic_mode);
   }
 }
@@ -561,6 +563,7 @@ hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStr
     a.n2 = pl.nc * ntpo;
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
+    a.chk = pl.chk;
     // persistent: two workgroups per CU (64 KiB of LDS each), items from
     // per-XCD counters
     const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv);

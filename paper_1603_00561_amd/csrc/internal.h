@@ -118,6 +118,7 @@ struct Plan {
   int precision;
   int terms;
   bool atomic_reduce;
+  unsigned *chk = nullptr;   // CCVV sign check word (DSRG_OPT_CHECK_SIGNS), else nullptr
   bool with_grad;
 
   // work counts (workgroups) per term
@@ -225,6 +226,12 @@ hipError_t launch_cumulants(int n, const double *g1, const double *g2, const dou
 constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
 // Device address of the current device's array (looked up once per device).
 hipError_t noalloc_scratch(void **ptr);
+
+// ---- the CCVV sign check word of DSRG_OPT_CHECK_SIGNS (checks.hip) ----
+// Device address of the current device's word (looked up once per device).
+hipError_t sign_check_ptr(unsigned **ptr);
+// Waits for the current device, copies its word to *word and clears it.
+hipError_t sign_check_read(unsigned *word);
 
 // ---- per-kernel timing (api.cpp); no-ops unless the call asked for it ----
 void timer_begin(const char *name, hipStream_t st);

@@ -227,6 +227,7 @@ struct CcvvAdjI8Args {
   // for i in [r0, r0 + nr), columns (j, b) for j in [c0, c0 + ncb); r0 == c0
   // is a diagonal block, else only entries with row orbital i are stored
   int r0, nr, c0, ncb;
+  unsigned *chk;   // sign check word (nullptr: off)
 };
 
 __device__ __forceinline__ void store_transposed128(const double (*T)[kI8Tile + 1], double *dst,
@@ -379,6 +380,7 @@ __global__ __launch_bounds__(512) void ccvv_adj_i8_kernel(
     const double tD = block_sum_n<8>(d_part, red);
     __syncthreads();
     const double tS = block_sum_n<8>(s_part, red);
+    check_nonpositive(tE, a.chk);
     if (threadIdx.x == 0) {
       slots[a.slot_base + slot] = tE;
       atomicAdd(&deps_c[c.i], gE0 * tD);
@@ -743,6 +745,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
         a.nr = (int)ni;
         a.c0 = (int)j0;
         a.ncb = (int)nj;
+        a.chk = pl.chk;
         const int64_t npair = (I == J) ? ni * (ni + 1) / 2 : ni * nj;
         const int64_t items = pairtile_grid(npair, pl.ntv_s / 2);
         const int64_t grid = items < kSlicePersistWG ? items : kSlicePersistWG;

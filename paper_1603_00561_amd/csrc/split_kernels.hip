@@ -120,6 +120,7 @@ struct CcvvI8Args {
   double s;
   int64_t slot_base;
   int atomic_mode;
+  unsigned *chk;   // sign check word (nullptr: off)
 };
 
 __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__ S8,
@@ -203,6 +204,7 @@ __global__ __launch_bounds__(512) void ccvv_i8_kernel(const int8_t *__restrict__
     if (c.cls == 1) __syncthreads();   // T is read before the reduction reuses the LDS
     const double w = (c.cls == 0) ? 4.0 : (c.cls == 3 ? 1.0 : 2.0);
     const double t = block_sum_n<8>(part, reinterpret_cast<double *>(lds)) * w;
+    check_nonpositive(t, a.chk);
     emit_partial(t, slots, a.slot_base + slot, acc, a.atomic_mode);
   }
 }
@@ -482,6 +484,7 @@ hipError_t launch_energy_split(const Plan &pl, const Inputs &in, void *ws, hipSt
     a.s = pl.s;
     a.slot_base = pl.slot_base[0];
     a.atomic_mode = pl.atomic_reduce ? 1 : 0;
+    a.chk = pl.chk;
     const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv_s / 2);
     const int64_t grid = items < kSlicePersistWG ? items : kSlicePersistWG;   // multiples of 8
     double *xs = ws_d(ws, pl.off_xs);

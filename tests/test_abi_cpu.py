@@ -100,6 +100,9 @@ def test_bad_precision_and_terms(lib):
     assert _ws(p, terms=0)[0] == b.DSRG_ERR_ARG
     assert _ws(p, terms=0x1000)[0] == b.DSRG_ERR_ARG
     assert _ws(p, terms=7 | b.OPT_ATOMIC_REDUCE)[0] == 0
+    # the sign check bit is accepted and changes no workspace size
+    assert _ws(p, terms=7 | b.OPT_CHECK_SIGNS) == _ws(p, terms=7)
+    assert lib.dsrg_df_sign_check(None) == b.DSRG_ERR_ARG
     null = ctypes.POINTER(b.Problem)()
     out = ctypes.c_size_t(0)
     assert lib.dsrg_df_workspace_size(null, 0, 7, 0, ctypes.byref(out)) == b.DSRG_ERR_ARG
