@@ -83,7 +83,7 @@ __device__ __forceinline__ void block_pair(const CcvvAdjArgs &a, int64_t p, int 
   }
 }
 
-__global__ __launch_bounds__(256) void ccvv_adj_fp64_kernel(
+__global__ __launch_bounds__(256, 3) void ccvv_adj_fp64_kernel(
     const double *__restrict__ Pcv, const double *__restrict__ eps_c,
     const double *__restrict__ eps_v, CcvvAdjArgs a, GradOut g, double *__restrict__ Gs,
     double *slots) {

@@ -56,7 +56,7 @@ __device__ __forceinline__ double ccvv_weight(int cls) {
   return (cls == 0) ? 4.0 : (cls == 3 ? 1.0 : 2.0);
 }
 
-__global__ __launch_bounds__(256) void ccvv_fp64_kernel(const double *__restrict__ Pcv,
+__global__ __launch_bounds__(256, 3) void ccvv_fp64_kernel(const double *__restrict__ Pcv,
                                                         const double *__restrict__ eps_c,
                                                         const double *__restrict__ eps_v,
                                                         CcvvArgs a, int *ctr, double *slots,
@@ -125,7 +125,7 @@ struct CavvXArgs64 {
   int tri;   // left and right panels are the same orbitals: only the pairs ml <= u
 };
 
-__global__ __launch_bounds__(256) void cavv_fp64_x_kernel(const double *__restrict__ Pcv,
+__global__ __launch_bounds__(256, 3) void cavv_fp64_x_kernel(const double *__restrict__ Pcv,
                                                           const double *__restrict__ Pav,
                                                           CavvXArgs64 a, int *ctr,
                                                           double *__restrict__ Xb) {
@@ -501,7 +501,7 @@ hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, 
   xa.tri = tri ? 1 : 0;
   const int64_t npairs = tri ? (int64_t)nright * (nright + 1) / 2 : (int64_t)mb * nright;
   const int64_t items = pairtile_grid(npairs, ntv);
-  const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
+  const int64_t grid = items < 4 * kPersistCU ? items : 4 * kPersistCU;   // multiples of 8
   hipError_t e = launch_zero(reinterpret_cast<double *>(ctr), 4, st);
   if (e != hipSuccess) return e;
   timer_begin("cavv_fp64_x", st);
@@ -567,7 +567,7 @@ hipError_t launch_energy_fp64(const Plan &pl, const Inputs &in, void *ws, hipStr
     // persistent: two workgroups per CU (64 KiB of LDS each), items from
     // per-XCD counters
     const int64_t items = pairtile_grid(pl.nc * (pl.nc + 1) / 2, pl.ntv);
-    const int64_t grid = items < 2 * kPersistCU ? items : 2 * kPersistCU;   // multiples of 8
+    const int64_t grid = items < 4 * kPersistCU ? items : 4 * kPersistCU;   // multiples of 8
     int *ctr = reinterpret_cast<int *>(ws_d(ws, pl.off_ctr));
     if ((e = launch_zero(ws_d(ws, pl.off_ctr), 4, st)) != hipSuccess) return e;
     timer_begin("ccvv_fp64", st);

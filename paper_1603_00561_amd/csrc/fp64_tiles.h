@@ -335,8 +335,11 @@ __device__ __forceinline__ bool decode_pair_list(int64_t kk, int x, int64_t P, i
   return false;
 }
 
-constexpr int kCcvvKC = 16;
-constexpr int kCcvvLds = 2 * 4 * kCcvvKC * kPanel;   // doubles
+constexpr int kCcvvKC = 8;
+// the double-buffered chunks of four panels, or a 64 x 65 transpose tile
+constexpr int kCcvvLds = (2 * 4 * kCcvvKC * kPanel > kPanel * (kPanel + 1))
+                             ? 2 * 4 * kCcvvKC * kPanel
+                             : kPanel * (kPanel + 1);   // doubles
 
 // Computes ax (and ay for class 0); classes 1-3 derive ay afterwards.
 template <bool NEED_Y>
