@@ -371,7 +371,7 @@ hipError_t launch_active_terms(const ActivePlan &pl, const ActiveInputs &in, voi
                               (int)pl.ncA, st)) != hipSuccess)
     return e;
   // integrals: X[x][u][e][f] = (xe|uf); (xe|mv); (me|xv); (ze|yv); (mv|ny); (mv|wy)
-  if ((e = launch_x_fp64(Pav, Pav, (int)pl.na, (int)pl.ntv, pl.naux_p, 0, (int)pl.na,
+  if ((e = launch_x_fp64(Pav, Pav, (int)pl.na, (int)pl.ntv, (int)pl.nv, pl.naux_p, 0, (int)pl.na,
                          reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)), ws_d(ws, pl.off_x), true,
                          st)) != hipSuccess)
     return e;

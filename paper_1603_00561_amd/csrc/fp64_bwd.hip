@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256, 3) void ccvv_adj_fp64_kernel(
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
   d4 ax[2][2], ay[2][2];
-  ccvv_compute(Pcv, Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
+  ccvv_compute(Pcv, Pcv, a.naux_p, a.ntv, a.nv, c, lds, ax, ay, wr, wc, cl, kl);
   if (threadIdx.x < W) {
     rsum[threadIdx.x] = 0.0;
     csum[threadIdx.x] = 0.0;

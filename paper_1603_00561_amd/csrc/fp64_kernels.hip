@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256, 3) void ccvv_fp64_kernel(const double *__restr
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
   d4 ax[2][2], ay[2][2];
-  ccvv_compute(Pcv, Pcv, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
+  ccvv_compute(Pcv, Pcv, a.naux_p, a.ntv, a.nv, c, lds, ax, ay, wr, wc, cl, kl);
 
   const double eij = eps_c[c.i] + eps_c[c.j];
   double eb[2];
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256, 3) void ccvv_fp64_kernel(const double *__restr
 // tri set (the same panels on both sides), only the pairs m <= u are formed.
 // ---------------------------------------------------------------------------
 struct CavvXArgs64 {
-  int na, ntv;
+  int na, ntv, nv;
   int64_t naux_p;
   int m0, mb;
   int tri;   // left and right panels are the same orbitals: only the pairs ml <= u
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256, 3) void cavv_fp64_x_kernel(const double *__res
   const int wr = wave >> 1, wc = wave & 1;
   const int cl = lane & 15, kl = lane >> 4;
   d4 ax[2][2], ay[2][2];
-  ccvv_compute(Pcv, Pav, a.naux_p, a.ntv, c, lds, ax, ay, wr, wc, cl, kl);
+  ccvv_compute(Pcv, Pav, a.naux_p, a.ntv, a.nv, c, lds, ax, ay, wr, wc, cl, kl);
   const int64_t ld = (int64_t)a.ntv * W;
   double *X = Xb + ((int64_t)ml * a.na + u) * ld * ld;
 #pragma unroll
@@ -488,13 +488,14 @@ static hipError_t launch_ccav_na(const Plan &pl, const Inputs &in, void *ws, hip
     default: return hipErrorInvalidValue;       \
   }
 
-hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv,
+hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv, int nv,
                          int64_t naux_p, int m0, int mb, int *ctr, double *Xb, bool tri,
                          hipStream_t st) {
   if (tri && (m0 != 0 || mb != nright || Pleft != Pright)) return hipErrorInvalidValue;
   CavvXArgs64 xa;
   xa.na = nright;
   xa.ntv = ntv;
+  xa.nv = nv;
   xa.naux_p = naux_p;
   xa.m0 = m0;
   xa.mb = mb;
@@ -513,7 +514,7 @@ hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, 
 
 hipError_t launch_cavv_x_fp64(const Plan &pl, void *ws, int m0, int mb, hipStream_t st) {
   return launch_x_fp64(ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pav), (int)pl.na, (int)pl.ntv,
-                       pl.naux_p, m0, mb, reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)),
+                       (int)pl.nv, pl.naux_p, m0, mb, reinterpret_cast<int *>(ws_d(ws, pl.off_ctr)),
                        ws_d(ws, pl.off_xb), false, st);
 }
 

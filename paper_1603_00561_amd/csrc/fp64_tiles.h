@@ -341,11 +341,15 @@ constexpr int kCcvvLds = (2 * 4 * kCcvvKC * kPanel > kPanel * (kPanel + 1))
                              ? 2 * 4 * kCcvvKC * kPanel
                              : kPanel * (kPanel + 1);   // doubles
 
-// Computes ax (and ay for class 0); classes 1-3 derive ay afterwards.
-template <bool NEED_Y>
+// Computes ax (and ay for class 0); classes 1-3 derive ay afterwards. EDGE:
+// a tile whose rows (ra of 64) or columns (rb of 64) run past nv, the last
+// virtual panel; a wave then multiplies only its 16 x 16 blocks that hold a
+// valid row and column (bit p of pm, bit q of qm; the others stay zero, as
+// the zero padding would have left them).
+template <bool NEED_Y, bool EDGE>
 __device__ __forceinline__ void ccvv_tiles(const double *const *src, int64_t naux_p,
                                            double *lds, d4 (&ax)[2][2], d4 (&ay)[2][2],
-                                           int wr, int wc, int cl, int kl) {
+                                           int wr, int wc, int cl, int kl, int pm, int qm) {
   constexpr int W = kPanel, KC = kCcvvKC;
   constexpr int NP = NEED_Y ? 4 : 2;
   kloop<NP, W, KC>(src, W, naux_p, lds, [&](const double *L) {
@@ -369,6 +373,7 @@ __device__ __forceinline__ void ccvv_tiles(const double *const *src, int64_t nau
       for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
+          if (EDGE && !((pm >> p) & (qm >> q) & 1)) continue;
           ax[p][q] = mfma64(fa[p], fb[q], ax[p][q]);
           if constexpr (NEED_Y) ay[p][q] = mfma64(ga[p], gb[q], ay[p][q]);
         }
@@ -381,7 +386,7 @@ __device__ __forceinline__ void ccvv_tiles(const double *const *src, int64_t nau
 // PL holds the panels of orbital c.i, PR those of orbital c.j (both Pcv for
 // CCVV; Pcv and Pav for the CAVV integrals (me|uf)).
 __device__ __forceinline__ void ccvv_compute(const double *PL, const double *PR, int64_t naux_p,
-                                             int ntv, const CcvvWork &c, double *lds,
+                                             int ntv, int nv, const CcvvWork &c, double *lds,
                                              d4 (&ax)[2][2], d4 (&ay)[2][2], int wr, int wc,
                                              int cl, int kl) {
   constexpr int W = kPanel;
@@ -397,10 +402,21 @@ __device__ __forceinline__ void ccvv_compute(const double *PL, const double *PR,
       ax[p][q] = zero4();
       ay[p][q] = zero4();
     }
-  if (c.cls == 0)
-    ccvv_tiles<true>(src, naux_p, lds, ax, ay, wr, wc, cl, kl);
-  else
-    ccvv_tiles<false>(src, naux_p, lds, ax, ay, wr, wc, cl, kl);
+  // valid rows / columns of the tile, and this wave's 16-blocks that hold any
+  const int ra = nv - W * c.A, rb = nv - W * c.B;
+  if (ra >= W && rb >= W) {
+    if (c.cls == 0)
+      ccvv_tiles<true, false>(src, naux_p, lds, ax, ay, wr, wc, cl, kl, 3, 3);
+    else
+      ccvv_tiles<false, false>(src, naux_p, lds, ax, ay, wr, wc, cl, kl, 3, 3);
+  } else {
+    const int pm = (32 * wr < ra ? 1 : 0) | (32 * wr + 16 < ra ? 2 : 0);
+    const int qm = (32 * wc < rb ? 1 : 0) | (32 * wc + 16 < rb ? 2 : 0);
+    if (c.cls == 0)
+      ccvv_tiles<true, true>(src, naux_p, lds, ax, ay, wr, wc, cl, kl, pm, qm);
+    else
+      ccvv_tiles<false, true>(src, naux_p, lds, ax, ay, wr, wc, cl, kl, pm, qm);
+  }
   if (c.cls == 1) {
     double (*T)[W + 1] = reinterpret_cast<double (*)[W + 1]>(lds);
 #pragma unroll

@@ -248,9 +248,10 @@ hipError_t launch_pack_panels(const double *B, double *P, int64_t nrow, int64_t 
                               int64_t naux, int64_t naux_p, int64_t ntile, int width,
                               hipStream_t st);
 // X[ml][u][e][f] = sum_Q L^Q_{(m0+ml) e} R^Q_{u f} for ml < mb, u < nright, from
-// 64-wide panels (row length ntv 64); ctr: eight work counters, cleared here.
-// tri (L = R, m0 = 0, mb = nright): only the blocks ml <= u are written.
-hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv,
+// 64-wide panels (row length ntv 64, nv valid); ctr: eight work counters,
+// cleared here. tri (L = R, m0 = 0, mb = nright): only the blocks ml <= u are
+// written.
+hipError_t launch_x_fp64(const double *Pleft, const double *Pright, int nright, int ntv, int nv,
                          int64_t naux_p, int m0, int mb, int *ctr, double *Xb, bool tri,
                          hipStream_t st);
 // Column blocks of 16 per workgroup of the J contraction: the largest of 4,
