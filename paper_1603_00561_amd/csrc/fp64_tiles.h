@@ -76,6 +76,7 @@ __device__ __forceinline__ int lcol(int c, int k) {
 template <int NP, int W, int KC, typename F>
 __device__ __forceinline__ void kloop(const double *const *src, int64_t ld, int64_t naux_p,
                                       double *lds, F &&compute) {
+  static_assert(kChunk % KC == 0, "chunks must tile naux_p, a multiple of kChunk");
   constexpr int BUF = NP * KC * W;
   Stage<NP, W, KC> st;
   st.load(src, ld, 0);

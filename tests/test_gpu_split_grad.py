@@ -171,12 +171,13 @@ def test_naux_limit_near_worst_case_level_sums():
 
 
 def test_adjoint_gemm_contraction_segments():
-    """nc = 513 core orbitals with nv = 8: the padded core-virtual index runs to
-    513 * 64 = 32832 > 32768, so the int8 product dE/dB_ca over it is split
-    into exact int32 segments (run side by side, their FP64 results summed in
-    order); the CCVV tiles come in three blocks of 171 core orbitals."""
-    p = make_problem(513, 1, 8, 8, s=0.5, seed=41)
-    assert p.nc * 64 > 32768
+    """nc = 513 core orbitals with nv = 33: the int8 products contract over nv
+    rounded up to 32 per orbital, so the core-virtual index of dE/dB_ca runs
+    to 513 * 64 = 32832 > 32768 and that product is split into exact int32
+    segments (run side by side, their FP64 results summed in order); the CCVV
+    tiles come in three blocks of 171 core orbitals."""
+    p = make_problem(513, 1, 33, 8, s=0.5, seed=41)
+    assert p.nc * (-(-p.nv // 32) * 32) > 32768
     gE = (1.0, 0.75, -0.5)
     g = split_grad(p, gE)
     compare(g, O.gradients(p, gE))
