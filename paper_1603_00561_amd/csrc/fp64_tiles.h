@@ -336,39 +336,108 @@ __device__ __forceinline__ bool decode_pair_list(int64_t kk, int x, int64_t P, i
   return false;
 }
 
+// Workgroup barrier that does not drain the vector-memory counter (a ring of
+// direct global -> LDS copies waits for its copies explicitly); the empty asm
+// keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void ring_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// s_waitcnt with only the vector-memory count (expcnt, lgkmcnt not waited)
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// CCVV / CAVV tile K loop: chunks of kCcvvKC auxiliary indices of up to four
+// 64-column panels are copied global -> LDS directly (global_load_lds, 16
+// bytes per lane: a panel chunk of 8 rows x 512 B is one copy per thread, each
+// wave moving its 1 KB quarter) into a ring of kCcvvRing slots, two chunks
+// ahead of the matrix cores, with one barrier per chunk and no staging
+// registers. LDS rows are stored as in memory (row k of panel p of a slot at
+// (p kCcvvKC + k) 64): a fragment read takes 16 consecutive doubles of a row
+// per 16 lanes.
 constexpr int kCcvvKC = 8;
-// the double-buffered chunks of four panels, or a 64 x 65 transpose tile
-constexpr int kCcvvLds = (2 * 4 * kCcvvKC * kPanel > kPanel * (kPanel + 1))
-                             ? 2 * 4 * kCcvvKC * kPanel
+constexpr int kCcvvRing = 3;
+constexpr int kCcvvStage = 4 * kCcvvKC * kPanel;   // doubles per slot
+// the ring, or a 64 x 65 transpose tile
+constexpr int kCcvvLds = (kCcvvRing * kCcvvStage > kPanel * (kPanel + 1))
+                             ? kCcvvRing * kCcvvStage
                              : kPanel * (kPanel + 1);   // doubles
+static_assert(kChunk % kCcvvKC == 0, "chunks must tile naux_p, a multiple of kChunk");
+
+// One 16-byte global -> LDS copy per lane: lane l of the wave writes LDS
+// bytes lds + 16 l .. +15 (lds wave-uniform). Written out rather than through
+// the builtin, which makes the compiler drain every outstanding copy before
+// any LDS read it cannot prove disjoint, i.e. before each chunk of the ring;
+// the ring's own vector-memory waits and barriers order the copies and the
+// reads. No register receives data (the copy writes LDS only), and the
+// compiler's own vector-memory waits stay conservative: untracked copies can
+// only make them wait longer.
+__device__ __forceinline__ void lds_copy16(const void *g, uint32_t lds) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(g), "s"(lds)
+               : "memory", "m0");
+}
+
+// copies chunk q0 of the NP panels src[] into the ring slot at lds
+template <int NP>
+__device__ __forceinline__ void ccvv_issue(const double *const *src, int64_t q0, double *slot) {
+  static_assert(kCcvvKC * kPanel * 8 == kThreads * 16, "a panel chunk is one copy per thread");
+  const int woff = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * 1024;
+  const uint32_t voff = (threadIdx.x & 63) * 16;
+  const uint32_t base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)slot;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const char *g = reinterpret_cast<const char *>(src[p] + q0 * kPanel) + woff + voff;
+    lds_copy16(g, __builtin_amdgcn_readfirstlane(base + p * kCcvvKC * kPanel * 8 + woff));
+  }
+}
 
 // Computes ax (and ay for class 0); classes 1-3 derive ay afterwards. EDGE:
 // a tile whose rows (ra of 64) or columns (rb of 64) run past nv, the last
 // virtual panel; a wave then multiplies only its 16 x 16 blocks that hold a
 // valid row and column (bit p of pm, bit q of qm; the others stay zero, as
-// the zero padding would have left them).
+// the zero padding would have left them). Ends on a barrier (LDS free).
 template <bool NEED_Y, bool EDGE>
 __device__ __forceinline__ void ccvv_tiles(const double *const *src, int64_t naux_p,
                                            double *lds, d4 (&ax)[2][2], d4 (&ay)[2][2],
                                            int wr, int wc, int cl, int kl, int pm, int qm) {
-  constexpr int W = kPanel, KC = kCcvvKC;
+  constexpr int W = kPanel, KC = kCcvvKC, R = kCcvvRing;
   constexpr int NP = NEED_Y ? 4 : 2;
-  kloop<NP, W, KC>(src, W, naux_p, lds, [&](const double *L) {
+  const int64_t nst = naux_p / KC;
+  for (int s = 0; s < R - 1 && s < nst; ++s) ccvv_issue<NP>(src, (int64_t)s * KC, lds + s * kCcvvStage);
+  int slot = 0;
+  for (int64_t s = 0; s < nst; ++s) {
+    // chunk s has landed (this wave's copies; the barrier: everyone's), and
+    // every wave is done with chunk s - 1, whose slot takes chunk s + R - 1
+    if (s + 1 < nst)
+      wait_vm<(R - 2) * NP>();
+    else
+      wait_vm<0>();
+    ring_barrier();
+    if (s + R - 1 < nst) {
+      const int ns = (slot + R - 1) % R;
+      ccvv_issue<NP>(src, (s + R - 1) * KC, lds + ns * kCcvvStage);
+    }
+    const double *L = lds + slot * kCcvvStage;
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int k = kk * 4 + kl;
       double fa[2], fb[2], ga[2], gb[2];
 #pragma unroll
-      for (int p = 0; p < 2; ++p) fa[p] = L[(0 * KC + k) * W + lcol<W>(32 * wr + 16 * p + cl, k)];
+      for (int p = 0; p < 2; ++p) fa[p] = L[(0 * KC + k) * W + 32 * wr + 16 * p + cl];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) fb[q] = L[(1 * KC + k) * W + lcol<W>(32 * wc + 16 * q + cl, k)];
+      for (int q = 0; q < 2; ++q) fb[q] = L[(1 * KC + k) * W + 32 * wc + 16 * q + cl];
       if constexpr (NEED_Y) {
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
-          ga[p] = L[(2 * KC + k) * W + lcol<W>(32 * wr + 16 * p + cl, k)];
+        for (int p = 0; p < 2; ++p) ga[p] = L[(2 * KC + k) * W + 32 * wr + 16 * p + cl];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-          gb[q] = L[(3 * KC + k) * W + lcol<W>(32 * wc + 16 * q + cl, k)];
+        for (int q = 0; q < 2; ++q) gb[q] = L[(3 * KC + k) * W + 32 * wc + 16 * q + cl];
       }
 #pragma unroll
       for (int p = 0; p < 2; ++p)
@@ -379,7 +448,9 @@ __device__ __forceinline__ void ccvv_tiles(const double *const *src, int64_t nau
           if constexpr (NEED_Y) ay[p][q] = mfma64(ga[p], gb[q], ay[p][q]);
         }
     }
-  });
+    slot = (slot + 1 == R) ? 0 : slot + 1;
+  }
+  __syncthreads();
 }
 
 // Full x, y for one CCVV work item (x^T through LDS for class 1, y = x for
@@ -411,8 +482,9 @@ __device__ __forceinline__ void ccvv_compute(const double *PL, const double *PR,
     else
       ccvv_tiles<false, false>(src, naux_p, lds, ax, ay, wr, wc, cl, kl, 3, 3);
   } else {
-    const int pm = (32 * wr < ra ? 1 : 0) | (32 * wr + 16 < ra ? 2 : 0);
-    const int qm = (32 * wc < rb ? 1 : 0) | (32 * wc + 16 < rb ? 2 : 0);
+    // wave-uniform (wr, wc are): scalar branches around the matrix products
+    const int pm = __builtin_amdgcn_readfirstlane((32 * wr < ra ? 1 : 0) | (32 * wr + 16 < ra ? 2 : 0));
+    const int qm = __builtin_amdgcn_readfirstlane((32 * wc < rb ? 1 : 0) | (32 * wc + 16 < rb ? 2 : 0));
     if (c.cls == 0)
       ccvv_tiles<true, true>(src, naux_p, lds, ax, ay, wr, wc, cl, kl, pm, qm);
     else

@@ -73,28 +73,12 @@ __device__ __forceinline__ void i8_issue_stage(const int8_t *s0, const int8_t *s
         0);
 }
 
-// Workgroup barrier that does not drain the vector-memory counter (the ring
-// waits for its copies explicitly); the empty asm keeps the compiler from
-// moving memory accesses across it.
-__device__ __forceinline__ void ring_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
 // Ties a scalar value (a kernel argument) to this point: its scalar load
 // completes before the K-loop, so no scalar load is in flight there and the
 // loop's LDS waits can count outstanding reads instead of draining them.
 template <class T>
 __device__ __forceinline__ void scalar_here(const T &v) {
   asm volatile("" ::"s"(v));
-}
-
-// s_waitcnt with only the vector-memory count (expcnt, lgkmcnt not waited)
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
 // The K loop of one tile product through the LDS ring: rows from the slice
