@@ -110,6 +110,65 @@ __global__ __launch_bounds__(256) void op_scale_final_kernel(const double *__res
   sig[r] = (mx > 0.0) ? ldexp(1.0, ex) : 1.0;
 }
 
+// Row and column maxima of |G| over an R x C block of an adjoint-tile array,
+// for the operands of the two products that read it (rows of one, columns of
+// the other): row r at base + (r / rblk) ldrb + (r % rblk) ldr, column c at
+// + (c / cblk) ldcb + c % cblk. One 64 x 64 tile per workgroup, one pass over
+// the block; the tile maxima are merged with integer atomic maxima of the
+// values' bit patterns, which order nonnegative doubles as their values
+// (rmax and cmax cleared to zero before; either may be nullptr).
+struct MaxView {
+  const double *base;
+  int64_t R, C;
+  int64_t rblk, ldrb, ldr;
+  int64_t cblk, ldcb;
+};
+
+__global__ __launch_bounds__(256) void op_maxima_kernel(MaxView v, unsigned long long *rmax,
+                                                        unsigned long long *cmax) {
+  __shared__ double cs[4][64];
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t c = c0 + lane;
+  const bool cok = c < v.C;
+  const double *col = v.base + (cok ? (c / v.cblk) * v.ldcb + c % v.cblk : 0);
+  double cm = 0.0;
+  // 64-row tiles blockIdx.y, blockIdx.y + gridDim.y, ...
+  for (int64_t r0 = (int64_t)blockIdx.y * 64; r0 < v.R; r0 += (int64_t)gridDim.y * 64) {
+    for (int i = 0; i < 16; ++i) {
+      const int64_t r = r0 + g * 16 + i;   // the same for the whole wave
+      if (r >= v.R) break;
+      const double x = cok ? fabs(col[(r / v.rblk) * v.ldrb + (r % v.rblk) * v.ldr]) : 0.0;
+      cm = fmax(cm, x);
+      if (rmax) {
+        double m = x;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) atomicMax(rmax + r, (unsigned long long)__double_as_longlong(m));
+      }
+    }
+  }
+  cs[g][lane] = cm;
+  __syncthreads();
+  if (threadIdx.x < 64 && cok && cmax) {
+    const double m = fmax(fmax(cs[0][lane], cs[1][lane]), fmax(cs[2][lane], cs[3][lane]));
+    atomicMax(cmax + c, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// sig[r] = the smallest power of two above the maximum m[r] (bit pattern of a
+// nonnegative double) for r < Rv, 1 for zero maxima and padding rows r < R
+__global__ __launch_bounds__(256) void op_sigma_kernel(const unsigned long long *__restrict__ m,
+                                                       int64_t Rv, int64_t R,
+                                                       double *__restrict__ sig) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= R) return;
+  const double mx = r < Rv ? __longlong_as_double((long long)m[r]) : 0.0;
+  int ex = 0;
+  if (mx > 0.0) (void)frexp(mx, &ex);   // mx < 2^ex
+  sig[r] = (mx > 0.0) ? ldexp(1.0, ex) : 1.0;
+}
+
 // Slices of rows r in the panel layout of the forward path: panel r / 64,
 // chunk qc of 32 contraction indices, slice s, column r % 64 (halves swapped
 // when (r >> 3) & 1). One thread per (row, chunk); consecutive threads take
@@ -599,6 +658,49 @@ static hipError_t pack_operand(const OpMap &m, int64_t R, int64_t K, double *sig
   return hipGetLastError();
 }
 
+// The maxima of an adjoint-tile block for both of its operands (one pass),
+// into rmax [R] and cmax [C] (uint64 bit patterns in the pmax buffer).
+static hipError_t block_maxima(const MaxView &v, double *rmax, double *cmax, hipStream_t st) {
+  timer_begin("op_pack", st);
+  hipError_t e;
+  if (rmax && (e = launch_zero_fill(rmax, v.R, st)) != hipSuccess) return e;
+  if (cmax && (e = launch_zero_fill(cmax, v.C, st)) != hipSuccess) return e;
+  const int64_t ry = std::min<int64_t>(ceil_div(v.R, 64), 32768);
+  hipLaunchKernelGGL(op_maxima_kernel, dim3((unsigned)ceil_div(v.C, 64), (unsigned)ry),
+                     dim3(256), 0, st, v, reinterpret_cast<unsigned long long *>(rmax),
+                     reinterpret_cast<unsigned long long *>(cmax));
+  timer_end(st);
+  return hipGetLastError();
+}
+
+// Slices of an operand with R rows (a multiple of 128, Rv of them valid) and
+// K contraction indices whose row maxima are in m (block_maxima).
+static hipError_t pack_with_maxima(const OpMap &om, int64_t Rv, int64_t R, int64_t K,
+                                   const double *m, double *sig, int8_t *S8, hipStream_t st) {
+  timer_begin("op_pack", st);
+  hipLaunchKernelGGL(op_sigma_kernel, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const unsigned long long *>(m), Rv, R, sig);
+  const int64_t nqc = K / kQC;
+  hipLaunchKernelGGL(op_pack_kernel, dim3((unsigned)ceil_div(R * nqc, 256)), dim3(256), 0, st, om,
+                     R, nqc, sig, S8);
+  timer_end(st);
+  return hipGetLastError();
+}
+
+static MaxView max_view(const double *base, int64_t R, int64_t rblk, int64_t ldrb, int64_t ldr,
+                        int64_t C, int64_t cblk, int64_t ldcb) {
+  MaxView v;
+  v.base = base;
+  v.R = R;
+  v.C = C;
+  v.rblk = rblk;
+  v.ldrb = ldrb;
+  v.ldr = ldr;
+  v.cblk = cblk;
+  v.ldcb = ldcb;
+  return v;
+}
+
 hipError_t launch_adj_sum(const double *P, int nseg, int64_t rows, int64_t ncol, int64_t zstride,
                           double *C, int64_t ldc, bool accumulate, hipStream_t st);
 
@@ -674,6 +776,12 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
   const int64_t RA = round_up(pl.naux, kI8Tile);
   const int64_t big = (int64_t)1 << 40;
   double *pmax = ws_d(ws, pl.off_opmax);
+  // maxima of an adjoint-tile block for its two operands (bit patterns in pmax,
+  // which holds 32 max(RA, rbmax) doubles)
+  const int64_t rbmax = std::max(round_up(pl.nc * pl.nv, kI8Tile),
+                                 std::max(round_up(pl.na * pl.nv, kI8Tile),
+                                          round_up(pl.nc * pl.na, kI8Tile)));
+  double *rmx = pmax, *cmx = pmax + rbmax;
   double *sigA1 = ws_d(ws, pl.off_sigA1), *sigA2 = ws_d(ws, pl.off_sigA2);
   double *sigB = ws_d(ws, pl.off_sigB);
   int8_t *SA1 = ws_b(ws, pl.off_SA1), *SA2 = ws_b(ws, pl.off_SA2), *SB = ws_b(ws, pl.off_SB);
@@ -704,14 +812,18 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
       // dB_cv[Q][(m,e)] (+)= sum_(w,f) B_av[Q][(w,f)] G2[(m,e)][(w,f)], m in the block
       const int64_t RB = round_up(mb * nv, kI8Tile);
       const OpMap B2t = op_map(G2, nv, nv, W * N2, N2, mb * nv, Wk, nv, W, 1, N2k);
-      if ((e = pack_operand(B2t, RB, N2k, sigB, pmax, SB, st)) != hipSuccess) return e;
+      if ((e = block_maxima(max_view(G2, mb * nv, nv, W * N2, N2, pl.na * nv, nv, W), rmx, cmx,
+                            st)) != hipSuccess)
+        return e;
+      if ((e = pack_with_maxima(B2t, mb * nv, RB, N2k, rmx, sigB, SB, st)) != hipSuccess) return e;
       if ((e = i8_gemm(SA2, sigA2, RA, N2k / kQC, 0, SB, sigB, RB, N2k, pl.naux, mb * nv, nv, nv,
                        o.dB_cv + m0 * nv, ldcv, false, part, pl.gpart_doubles, st)) != hipSuccess)
         return e;
       // dB_av[Q][(w,f)] (+)= sum_(m,e) B_cv[Q][(m,e)] G2[(m,e)][(w,f)], m in the block
       const int64_t RB2 = round_up(pl.na * nv, kI8Tile);
       const OpMap B2 = op_map(G2, nv, nv, W, 1, pl.na * nv, Wk, nv, W * N2, N2, mb * Wk);
-      if ((e = pack_operand(B2, RB2, mb * Wk, sigB, pmax, SB, st)) != hipSuccess) return e;
+      if ((e = pack_with_maxima(B2, pl.na * nv, RB2, mb * Wk, cmx, sigB, SB, st)) != hipSuccess)
+        return e;
       if ((e = i8_gemm(SA1, sigA1, RA, nqcp, m0 * Wk / kQC, SB, sigB, RB2, mb * Wk, pl.naux,
                        pl.na * nv, nv, nv, o.dB_av, pl.na * nv, I > 0, part, pl.gpart_doubles,
                        st)) != hipSuccess)
@@ -762,7 +874,12 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
         // first written by the pair (0, J)
         const int64_t RBj = round_up(nj * nv, kI8Tile);
         const OpMap Bn = op_map(G, nv, nv, W, 1, nj * nv, Wk, nv, W * ld, ld, ni * Wk);
-        if ((e = pack_operand(Bn, RBj, ni * Wk, sigB, pmax, SB, st)) != hipSuccess) return e;
+        // Bn reads the block's columns, Bt (off the diagonal) its rows
+        if ((e = block_maxima(max_view(G, ni * nv, nv, W * ld, ld, nj * nv, nv, W),
+                              J > I ? rmx : nullptr, cmx, st)) != hipSuccess)
+          return e;
+        if ((e = pack_with_maxima(Bn, nj * nv, RBj, ni * Wk, cmx, sigB, SB, st)) != hipSuccess)
+          return e;
         if ((e = i8_gemm(SA1, sigA1, RA, nqcp, i0 * Wk / kQC, SB, sigB, RBj, ni * Wk, pl.naux,
                          nj * nv, nv, nv, o.dB_cv + j0 * nv, ldcv, written || I > 0, part,
                          pl.gpart_doubles, st)) != hipSuccess)
@@ -771,7 +888,8 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
           // dB_cv[Q][(i,a)] += sum_(j,b) B_cv[Q][(j,b)] G[(i,a)][(j,b)]
           const int64_t RBi = round_up(ni * nv, kI8Tile);
           const OpMap Bt = op_map(G, nv, nv, W * ld, ld, ni * nv, Wk, nv, W, 1, nj * Wk);
-          if ((e = pack_operand(Bt, RBi, nj * Wk, sigB, pmax, SB, st)) != hipSuccess) return e;
+          if ((e = pack_with_maxima(Bt, ni * nv, RBi, nj * Wk, rmx, sigB, SB, st)) != hipSuccess)
+            return e;
           if ((e = i8_gemm(SA1, sigA1, RA, nqcp, j0 * Wk / kQC, SB, sigB, RBi, nj * Wk, pl.naux,
                            ni * nv, nv, nv, o.dB_cv + i0 * nv, ldcv, true, part,
                            pl.gpart_doubles, st)) != hipSuccess)
@@ -788,7 +906,12 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const int64_t RB = round_up(pl.nc * nv, kI8Tile);
     const OpMap B3t = op_map(G3, nv, nv, W * N3, N3, pl.nc * nv, kActPanel, pl.na, kActPanel, 1,
                              N3);
-    if ((e = pack_operand(B3t, RB, N3p, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = block_maxima(max_view(G3, pl.nc * nv, nv, W * N3, N3, pl.nc * pl.na, pl.na,
+                                   kActPanel),
+                          rmx, cmx, st)) != hipSuccess)
+      return e;
+    if ((e = pack_with_maxima(B3t, pl.nc * nv, RB, N3p, rmx, sigB, SB, st)) != hipSuccess)
+      return e;
     if ((e = i8_gemm(SA2, sigA2, RA, N3p / kQC, 0, SB, sigB, RB, N3p, pl.naux, pl.nc * nv, nv, nv,
                      o.dB_cv, ldcv, written, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
@@ -797,7 +920,7 @@ hipError_t launch_backward_split(const Plan &pl, const Inputs &in, const BwdOut 
     const int64_t n3v = pl.nc * pl.na;
     const int64_t RB3 = round_up(n3v, kI8Tile);
     const OpMap B3 = op_map(G3, pl.na, pl.na, kActPanel, 1, n3v, Wk, nv, W * N3, N3, Npk);
-    if ((e = pack_operand(B3, RB3, Npk, sigB, pmax, SB, st)) != hipSuccess) return e;
+    if ((e = pack_with_maxima(B3, n3v, RB3, Npk, cmx, sigB, SB, st)) != hipSuccess) return e;
     if ((e = i8_gemm(SA1, sigA1, RA, nqcp, 0, SB, sigB, RB3, Npk, pl.naux, n3v, pl.na, pl.na,
                      o.dB_ca, n3v, false, part, pl.gpart_doubles, st)) != hipSuccess)
       return e;
