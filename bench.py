@@ -931,13 +931,17 @@ def bench_semican(args, binding, torch):
 def rest_alg_work(nc, na, nv, naux):
     """Algorithmic flops and HBM bytes of the integral stage of the Table I
     terms: the seven products over the auxiliary index that form (pq|rs)
-    with two or more active indices (the largest, (xe|yf), reads B_av twice
-    and writes na^2 nv^2 values)."""
+    with two or more active indices. The three Gram products (uv|wx),
+    (mu|nv) and (xe|yf) are symmetric, so their unique entries, n (n + 1) / 2
+    of them, count (the largest, (xe|yf), reads B_av twice and writes its
+    na^2 nv^2 values)."""
     na2 = na * na
-    prods = [(nc * nv, na2), (na * nv, na2), (nc * na, na2), (na2, na2), (na * nv, nc * na),
-             (nc * na, nc * na), (na * nv, na * nv)]
-    flops = sum(2.0 * naux * m * n for m, n in prods)
-    nbytes = sum(8.0 * (naux * (m + n) + m * n) for m, n in prods)
+    prods = [(nc * nv, na2), (na * nv, na2), (nc * na, na2), (na * nv, nc * na)]
+    grams = [na2, nc * na, na * nv]
+    flops = (sum(2.0 * naux * m * n for m, n in prods)
+             + sum(2.0 * naux * n * (n + 1) / 2 for n in grams))
+    nbytes = (sum(8.0 * (naux * (m + n) + m * n) for m, n in prods)
+              + sum(8.0 * (2 * naux * n + n * n) for n in grams))
     return flops, nbytes
 
 

@@ -57,6 +57,10 @@ struct GemmGArgs {
   // split K (ktotal > 0): batch z contracts k in [z K, min((z + 1) K, ktotal)),
   // its operands advanced by the batch strides
   int64_t ktotal;
+  // upper-triangle tiles (utiles > 0, square tiles, M = N): the grid runs
+  // over the utiles (utiles + 1) / 2 tiles (r, c), r <= c, of a utiles x
+  // utiles tile grid, row by row
+  int64_t utiles;
 };
 
 template <int TM_, int TN_, int WR_, int WC_, int KC_, int KS_ = 1>
@@ -146,8 +150,21 @@ __global__ __launch_bounds__(G::NT) void gemm_g_kernel(const double *__restrict_
   const int64_t nx = gridDim.x, ny = gridDim.y, per = nx * ny;
   const int64_t id = blockIdx.x + nx * blockIdx.y, xcd = id % 8;
   const int64_t tl = xcd * (per / 8) + std::min<int64_t>(xcd, per % 8) + id / 8;
-  const int64_t m0 = (a.colfast ? tl / ny : tl % nx) * TM;
-  const int64_t n0 = (a.colfast ? tl % ny : tl / nx) * TN;
+  int64_t m0, n0;
+  if (a.utiles > 0) {
+    // row r of the upper triangle starts at tile r T - r (r - 1) / 2
+    const int64_t T = a.utiles;
+    const double b2 = 2.0 * (double)T + 1.0;
+    int64_t r = (int64_t)((b2 - sqrt(b2 * b2 - 8.0 * (double)tl)) * 0.5);
+    auto start = [&](int64_t q) { return q * T - q * (q - 1) / 2; };
+    while (r > 0 && start(r) > tl) --r;
+    while (r + 1 < T && start(r + 1) <= tl) ++r;
+    m0 = r * TM;
+    n0 = (r + tl - start(r)) * TN;
+  } else {
+    m0 = (a.colfast ? tl / ny : tl % nx) * TM;
+    n0 = (a.colfast ? tl % ny : tl / nx) * TN;
+  }
   A += (int64_t)blockIdx.z * a.sa;
   B += (int64_t)blockIdx.z * a.sb;
   C += (int64_t)blockIdx.z * a.sc;
@@ -358,7 +375,7 @@ static hipError_t gemm_g(bool ta, bool tb, int64_t M, int64_t N, int64_t K, doub
                          int64_t batch, bool ktri, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
   GemmGArgs a{M, N, K, lda, ldb, ldc, sa, sb, sc, alpha, beta, ktri ? 1 : 0, 0, 0, 0, M > N ? 1 : 0,
-              0};
+              0, 0};
   auto tiles = [&](int tm, int tn) { return ceil_div(M, tm) * ceil_div(N, tn) * batch; };
   if (M <= GThin::TM && tiles(GThin::TM, GThin::TN) >= 256)
     gemm_g_launch<GThin>(ta, tb, a, batch, A, B, C, st);
@@ -375,6 +392,35 @@ hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double al
                     const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                     double *C, int64_t ldc, hipStream_t st) {
   return gemm_g(ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, false, st);
+}
+
+hipError_t gemm_f64_gram_upper(int64_t n, int64_t K, const double *A, int64_t lda, double *C,
+                               int64_t ldc, int64_t *tile, hipStream_t st) {
+  *tile = 0;
+  if (n <= 0) return hipSuccess;
+  GemmGArgs a{n, n, K, lda, lda, ldc, 0, 0, 0, 1.0, 0.0, 0, 0, 0, 0, 0, 0, 0};
+  auto utiles = [&](int t) { return ceil_div(n, t) * (ceil_div(n, t) + 1) / 2; };
+  // 128 x 128 tiles when they give three or more per CU, else 64 x 64
+  if (utiles(GBig::TM) >= 768) {
+    a.utiles = ceil_div(n, GBig::TM);
+    *tile = GBig::TM;
+    if (pairs_fit(true, false, a, A, A))
+      hipLaunchKernelGGL((gemm_g_kernel<true, false, GBig, false, true>),
+                         dim3((unsigned)utiles(GBig::TM)), dim3(GBig::NT), 0, st, A, A, a, C);
+    else
+      hipLaunchKernelGGL((gemm_g_kernel<true, false, GBig, false, false>),
+                         dim3((unsigned)utiles(GBig::TM)), dim3(GBig::NT), 0, st, A, A, a, C);
+  } else {
+    a.utiles = ceil_div(n, GMid::TM);
+    *tile = GMid::TM;
+    if (pairs_fit(true, false, a, A, A))
+      hipLaunchKernelGGL((gemm_g_kernel<true, false, GMid, false, true>),
+                         dim3((unsigned)utiles(GMid::TM)), dim3(GMid::NT), 0, st, A, A, a, C);
+    else
+      hipLaunchKernelGGL((gemm_g_kernel<true, false, GMid, false, false>),
+                         dim3((unsigned)utiles(GMid::TM)), dim3(GMid::NT), 0, st, A, A, a, C);
+  }
+  return hipGetLastError();
 }
 
 hipError_t gemm_f64_batched(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
@@ -409,7 +455,7 @@ static hipError_t gemm_g_splitk(bool ta, bool tb, int64_t M, int64_t N, int64_t 
   const int64_t kseg = ceil_div(K, nseg);
   nseg = ceil_div(K, kseg);
   GemmGArgs a{M, N, kseg, lda, ldb, N, (ta ? kseg * lda : kseg), (tb ? kseg : kseg * ldb), M * N,
-              1.0, 0.0, 0, 0, 0, 0, M > N ? 1 : 0, K};
+              1.0, 0.0, 0, 0, 0, 0, M > N ? 1 : 0, K, 0};
   auto tiles = [&](int tm, int tn) { return ceil_div(M, tm) * ceil_div(N, tn) * nseg; };
   if (tiles(GBig::TM, GBig::TN) >= 768)
     gemm_g_launch<GBig>(ta, tb, a, nseg, A, B, part, st);
@@ -461,7 +507,7 @@ static hipError_t gemm_g_folded(bool ta, int64_t M, int64_t nin, int64_t K, doub
   const int64_t N = nin * nbatch;
   if (M <= 0 || N <= 0) return hipSuccess;
   if (!folded_fits(M, nin, nbatch)) return hipErrorInvalidValue;
-  GemmGArgs a{M, N, K, lda, ldb, ldc, 0, 0, 0, alpha, 0.0, 0, nin, sb - nin, sc - nin, 0, 0};
+  GemmGArgs a{M, N, K, lda, ldb, ldc, 0, 0, 0, alpha, 0.0, 0, nin, sb - nin, sc - nin, 0, 0, 0};
   if (M <= GThin::TM)
     folded_launch<GThin>(ta, a, A, B, C, st);
   else if (M <= GThin48::TM)

@@ -759,20 +759,13 @@ hipError_t launch_rest_terms(const RestPlan &pl, const RestInputs &in, void *ws,
         hipSuccess)
       return e;
   }
-  // X = (xe|yf) = B_av^T B_av is symmetric: row strips of the upper triangle
-  // (each strip from its diagonal block to the last column), then the rest
-  // mirrored
+  // X = (xe|yf) = B_av^T B_av is symmetric: the tiles of its upper triangle,
+  // then the rest mirrored
   {
     const int64_t n = na * nv;
-    const int64_t nstrip = std::max<int64_t>(1, std::min<int64_t>(8, n / 768));
-    const int64_t strip = round_up(ceil_div(n, nstrip), 32);
-    for (int64_t r0 = 0; r0 < n; r0 += strip) {
-      const int64_t r1 = std::min(n, r0 + strip);
-      if ((e = gemm_f64(true, false, r1 - r0, n - r0, naux, 1.0, in.B_av + r0, n, in.B_av + r0, n,
-                        0.0, X + r0 * n + r0, n, st)) != hipSuccess)
-        return e;
-    }
-    if (strip < n) {
+    int64_t strip = 0;
+    if ((e = gemm_f64_gram_upper(n, naux, in.B_av, n, X, n, &strip, st)) != hipSuccess) return e;
+    if (strip > 0 && strip < n) {
       hipLaunchKernelGGL(rest_mirror_kernel,
                          dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32)), dim3(256), 0,
                          st, X, n, strip);
