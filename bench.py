@@ -1118,7 +1118,8 @@ def bench_laplace(args, binding, torch):
     avg = kernel_table(binding, torch, call, table_steps(args))
     ms_per_step, dom_ms = timed_region(binding, torch, call, args.steps, ["lt_gemm"])
     E = float(res["r"][0].item())
-    flops = 2.0 * p.naux * p.naux * p.nc * p.nv * nq
+    # Y_k is a symmetric Gram matrix: its naux (naux + 1) / 2 unique entries
+    flops = 1.0 * p.naux * (p.naux + 1) * p.nc * p.nv * nq
     gemm_ms = dom_ms * gemm_launches if dom_ms else None
     ach = flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms else None
     # the direct CCVV energy on the same inputs (Coulomb and exchange)

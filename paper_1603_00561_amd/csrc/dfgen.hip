@@ -394,31 +394,41 @@ hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double al
   return gemm_g(ta, tb, M, N, K, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1, false, st);
 }
 
-hipError_t gemm_f64_gram_upper(int64_t n, int64_t K, const double *A, int64_t lda, double *C,
-                               int64_t ldc, int64_t *tile, hipStream_t st) {
+template <class G>
+static void gram_launch(bool trans, const GemmGArgs &a, int64_t batch, const double *A, double *C,
+                        hipStream_t st) {
+  const dim3 grid((unsigned)(a.utiles * (a.utiles + 1) / 2), 1, (unsigned)batch);
+  const bool pr = pairs_fit(trans, !trans, a, A, A);
+  if (trans && pr)
+    hipLaunchKernelGGL((gemm_g_kernel<true, false, G, false, true>), grid, dim3(G::NT), 0, st, A, A,
+                       a, C);
+  else if (trans)
+    hipLaunchKernelGGL((gemm_g_kernel<true, false, G, false, false>), grid, dim3(G::NT), 0, st, A,
+                       A, a, C);
+  else if (pr)
+    hipLaunchKernelGGL((gemm_g_kernel<false, true, G, false, true>), grid, dim3(G::NT), 0, st, A, A,
+                       a, C);
+  else
+    hipLaunchKernelGGL((gemm_g_kernel<false, true, G, false, false>), grid, dim3(G::NT), 0, st, A,
+                       A, a, C);
+}
+
+hipError_t gemm_f64_gram_upper(bool trans, int64_t n, int64_t K, const double *A, int64_t lda,
+                               int64_t sa, double *C, int64_t ldc, int64_t sc, int64_t batch,
+                               int64_t *tile, hipStream_t st) {
   *tile = 0;
-  if (n <= 0) return hipSuccess;
-  GemmGArgs a{n, n, K, lda, lda, ldc, 0, 0, 0, 1.0, 0.0, 0, 0, 0, 0, 0, 0, 0};
-  auto utiles = [&](int t) { return ceil_div(n, t) * (ceil_div(n, t) + 1) / 2; };
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  GemmGArgs a{n, n, K, lda, lda, ldc, sa, sa, sc, 1.0, 0.0, 0, 0, 0, 0, 0, 0, 0};
+  auto utiles = [&](int t) { return ceil_div(n, t) * (ceil_div(n, t) + 1) / 2 * batch; };
   // 128 x 128 tiles when they give three or more per CU, else 64 x 64
   if (utiles(GBig::TM) >= 768) {
     a.utiles = ceil_div(n, GBig::TM);
     *tile = GBig::TM;
-    if (pairs_fit(true, false, a, A, A))
-      hipLaunchKernelGGL((gemm_g_kernel<true, false, GBig, false, true>),
-                         dim3((unsigned)utiles(GBig::TM)), dim3(GBig::NT), 0, st, A, A, a, C);
-    else
-      hipLaunchKernelGGL((gemm_g_kernel<true, false, GBig, false, false>),
-                         dim3((unsigned)utiles(GBig::TM)), dim3(GBig::NT), 0, st, A, A, a, C);
+    gram_launch<GBig>(trans, a, batch, A, C, st);
   } else {
     a.utiles = ceil_div(n, GMid::TM);
     *tile = GMid::TM;
-    if (pairs_fit(true, false, a, A, A))
-      hipLaunchKernelGGL((gemm_g_kernel<true, false, GMid, false, true>),
-                         dim3((unsigned)utiles(GMid::TM)), dim3(GMid::NT), 0, st, A, A, a, C);
-    else
-      hipLaunchKernelGGL((gemm_g_kernel<true, false, GMid, false, false>),
-                         dim3((unsigned)utiles(GMid::TM)), dim3(GMid::NT), 0, st, A, A, a, C);
+    gram_launch<GMid>(trans, a, batch, A, C, st);
   }
   return hipGetLastError();
 }

@@ -311,11 +311,14 @@ hipError_t launch_semican(const SemicanPlan &pl, const double *F, const double *
 hipError_t gemm_f64(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
                     const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                     double *C, int64_t ldc, hipStream_t st);
-// C = A^T A (A: K x n, row-major, leading dimension lda) on the tiles (r, c),
-// r <= c, of the n x n result: the upper triangle in whole tiles, the tiles
-// below it not written; *tile receives the tile size (dfgen.hip)
-hipError_t gemm_f64_gram_upper(int64_t n, int64_t K, const double *A, int64_t lda, double *C,
-                               int64_t ldc, int64_t *tile, hipStream_t st);
+// C_z = A_z^T A_z (trans: A_z K x n) or A_z A_z^T (A_z n x K), row-major with
+// leading dimension lda, for z < batch (A_z = A + z sa, C_z = C + z sc), on
+// the tiles (r, c), r <= c, of the n x n result: the upper triangle in whole
+// tiles, the tiles below it not written; *tile receives the tile size
+// (dfgen.hip)
+hipError_t gemm_f64_gram_upper(bool trans, int64_t n, int64_t K, const double *A, int64_t lda,
+                               int64_t sa, double *C, int64_t ldc, int64_t sc, int64_t batch,
+                               int64_t *tile, hipStream_t st);
 // batch of products C_z = alpha op(A_z) op(B_z) + beta C_z, operands advanced
 // by the strides sa, sb, sc (doubles) per batch index (dfgen.hip)
 hipError_t gemm_f64_batched(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,

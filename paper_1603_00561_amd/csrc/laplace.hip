@@ -9,9 +9,12 @@
 //   E_J ~ -2 sum_k w_k S_k,   S_k = sum_{PQ} (Y_k)_{PQ}^2,
 //   Y_k = (B D_k) B^T over the (i, a) index, D_k = diag(exp(-t_k (e_a - e_i))),
 // a product of 2 naux^2 nc nv flops per term instead of the fifth-order pair
-// sum. Per batch of terms: one scaling kernel writes B D_k, one batched FP64
-// matrix-core product forms the Y_k, one kernel reduces their squares into
-// per-workgroup slots; a last kernel adds the slots of each term in a fixed
+// sum. D_k is positive, so Y_k = C_k C_k^T with C_k = B D_k^{1/2} is a
+// symmetric Gram matrix and only its upper triangle is formed (half the
+// flops). Per batch of terms: one scaling kernel writes C_k, one batched FP64
+// matrix-core product forms the tiles (r, c), r <= c, of the Y_k, one kernel
+// reduces their squares into per-workgroup slots (tiles above the diagonal
+// tiles counted twice); a last kernel adds the slots of each term in a fixed
 // order and combines the terms.
 #include <hip/hip_runtime.h>
 
@@ -148,7 +151,7 @@ struct LtTerms {
   double t[kLtMaxTerms], w[kLtMaxTerms];
 };
 
-// Bs[kk][Q][(i, a)] = B[Q][i][a] exp(-t_{k0 + kk} (e_a - e_i)) for kk < kb
+// Bs[kk][Q][(i, a)] = B[Q][i][a] exp(-t_{k0 + kk} (e_a - e_i) / 2) for kk < kb
 __global__ __launch_bounds__(256) void lt_scale_kernel(const double *__restrict__ B,
                                                        const double *__restrict__ eps_c,
                                                        const double *__restrict__ eps_v,
@@ -160,20 +163,28 @@ __global__ __launch_bounds__(256) void lt_scale_kernel(const double *__restrict_
        e += (int64_t)gridDim.x * 256) {
     const int64_t kk = e / per, r = e % per;
     const int64_t a = r % nv, i = (r / nv) % nc;
-    Bs[e] = B[r] * exp(-T.t[k0 + kk] * (eps_v[a] - eps_c[i]));
+    Bs[e] = B[r] * exp(-0.5 * T.t[k0 + kk] * (eps_v[a] - eps_c[i]));
   }
 }
 
-// slots[(k0 + kk) nwg + blockIdx.x] = sum of squares of this workgroup's
-// elements of Y[kk] (grid nwg x kb, fixed order)
-__global__ __launch_bounds__(256) void lt_sumsq_kernel(const double *__restrict__ Y, int64_t n2,
-                                                       int k0, int64_t nwg,
+// slots[(k0 + kk) nwg + blockIdx.x] = this workgroup's share of ||Y[kk]||_F^2
+// from the upper tiles of the symmetric Y[kk] (tile size tile): rows P =
+// blockIdx.x, + nwg, ..., columns from the start of P's diagonal tile, the
+// diagonal tile once and the tiles right of it twice (grid nwg x kb, fixed
+// order)
+__global__ __launch_bounds__(256) void lt_sumsq_kernel(const double *__restrict__ Y, int64_t n,
+                                                       int64_t tile, int k0, int64_t nwg,
                                                        double *__restrict__ slots) {
   __shared__ double red[4];
-  const double *y = Y + (int64_t)blockIdx.y * n2;
+  const double *y = Y + (int64_t)blockIdx.y * n * n;
   double acc = 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n2; e += nwg * 256)
-    acc = fma(y[e], y[e], acc);
+  for (int64_t P = blockIdx.x; P < n; P += nwg) {
+    const int64_t q0 = (P / tile) * tile, q1 = q0 + tile;
+    for (int64_t Q = q0 + threadIdx.x; Q < n; Q += 256) {
+      const double v = y[P * n + Q];
+      acc = fma(Q < q1 ? v : 2.0 * v, v, acc);
+    }
+  }
   const double t = block_sum(acc, red);
   if (threadIdx.x == 0) slots[(int64_t)(k0 + blockIdx.y) * nwg + blockIdx.x] = t;
 }
@@ -228,13 +239,14 @@ hipError_t launch_coulomb_laplace(const LtPlan &pl, const double *B_cv, const do
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     timer_begin("lt_gemm", st);
-    e = gemm_f64_batched(false, true, pl.naux, pl.naux, ncnv, 1.0, Bs, ncnv, pl.naux * ncnv, B_cv,
-                         ncnv, 0, 0.0, Y, pl.naux, n2, kb, st);
+    int64_t tile = 0;
+    e = gemm_f64_gram_upper(false, pl.naux, ncnv, Bs, ncnv, pl.naux * ncnv, Y, pl.naux, n2, kb,
+                            &tile, st);
     timer_end(st);
     if (e != hipSuccess) return e;
     timer_begin("lt_sumsq", st);
     hipLaunchKernelGGL(lt_sumsq_kernel, dim3((unsigned)pl.nwg, (unsigned)kb), dim3(256), 0, st, Y,
-                       n2, k0, pl.nwg, slots);
+                       pl.naux, tile, k0, pl.nwg, slots);
     timer_end(st);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

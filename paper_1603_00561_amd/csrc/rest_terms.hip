@@ -764,7 +764,9 @@ hipError_t launch_rest_terms(const RestPlan &pl, const RestInputs &in, void *ws,
   {
     const int64_t n = na * nv;
     int64_t strip = 0;
-    if ((e = gemm_f64_gram_upper(n, naux, in.B_av, n, X, n, &strip, st)) != hipSuccess) return e;
+    if ((e = gemm_f64_gram_upper(true, n, naux, in.B_av, n, 0, X, n, 0, 1, &strip, st)) !=
+        hipSuccess)
+      return e;
     if (strip > 0 && strip < n) {
       hipLaunchKernelGGL(rest_mirror_kernel,
                          dim3((unsigned)ceil_div(n, 32), (unsigned)ceil_div(n, 32)), dim3(256), 0,
