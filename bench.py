@@ -427,6 +427,44 @@ def load_traffic(kernel, workload):
     return d.get("bytes_per_launch")
 
 
+# launch shape of the matrix-core rate probe per kind: (workgroups, rounds);
+# about 15-20 ms per launch at the quoted peaks
+PROBE_LAUNCH = {"i8": (2048, 16384), "f64": (2048, 4096)}
+PROBE_PEAK = {"i8": PEAK_TFLOPS["ozaki"], "f64": PEAK_TFLOPS["fp64"]}
+
+
+def mfma_probe_rate(binding, torch, kind):
+    """The matrix-core rate on register operands of full-entropy random bits
+    (dsrg_df_mfma_probe: the operand statistics of the tile kernels without
+    their memory traffic) and the shader clock it ran at. One warm-up launch,
+    then one timed with events on the launch stream. The clock is the median
+    over workgroups of shader cycles per constant-rate tick, times the tick
+    rate (the counter's span over the launch divided by the event-timed
+    length of the launch)."""
+    nwg, iters = PROBE_LAUNCH[kind]
+    dev = torch.device("cuda:0")
+    stamps = torch.zeros(4 * nwg, dtype=torch.int64, device=dev)
+    sink = torch.empty(512 * nwg, dtype=torch.int32 if kind == "i8" else torch.float64,
+                       device=dev)
+    binding.mfma_probe(kind, nwg, iters, stamps, sink)
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    binding.mfma_probe(kind, nwg, iters, stamps, sink)
+    e1.record(st)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    s = stamps.view(nwg, 4).cpu().numpy()
+    cyc, ticks = (s[:, 2] - s[:, 0]).astype(np.float64), (s[:, 3] - s[:, 1]).astype(np.float64)
+    tick_hz = float(s[:, 3].max() - s[:, 1].min()) / (ms * 1e-3)
+    ops = nwg * 8 * iters * 8 * binding.PROBE_OPS[kind]
+    rate = ops / (ms * 1e-3) / 1e12
+    return {"value": rate, "unit": "TOP/s" if kind == "i8" else "TFLOP/s",
+            "clock_GHz": float(np.median(cyc / ticks)) * tick_hz / 1e9,
+            "published_peak": PROBE_PEAK[kind], "frac_of_published": rate / PROBE_PEAK[kind],
+            "launch": f"{nwg} workgroups x 8 waves x {iters} rounds of 8 products, {ms:.2f} ms"}
+
+
 def roofline_kernel(precision, grad):
     """The kernel the roofline is taken on, the names its launches are timed
     under, its unit and the executed operations per algorithmic multiply-add.
@@ -586,6 +624,9 @@ def main():
                          "FP64) with a 16-term exponential sum")
     ap.add_argument("--cd-max-rank", type=int, default=0,
                     help="max_rank of the --cd call (default 6 nao)")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the matrix-core rate probe (dsrg_df_mfma_probe) after the "
+                         "energy / gradient measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB elementwise copy first (known HBM bytes) so "
                          "hardware byte counters can be scaled")
@@ -707,6 +748,22 @@ def main():
                             "peak": PEAK_TFLOPS["ozaki"],
                             "frac": (a3 / PEAK_TFLOPS["ozaki"]) if a3 else None}}
         out["compare"] = cmp_
+    if not args.no_probe:
+        # the sustained matrix-core rates of the run's box, beside the
+        # published peaks the rooflines are priced against
+        probe = {k: mfma_probe_rate(binding, torch, k) for k in ("f64", "i8")}
+        out["mfma_probe"] = probe
+
+        def sustained(roofline, kind):
+            if roofline and roofline.get("achieved"):
+                roofline["probe_rate"] = probe[kind]["value"]
+                roofline["frac_of_probe_rate"] = roofline["achieved"] / probe[kind]["value"]
+        sustained(roof, "f64" if args.precision == "fp64" else "i8")
+        cmp_ = out.get("compare", {})
+        sustained(cmp_.get("roofline"), "i8" if args.precision == "fp64" else "f64")
+        ce = cmp_.get("slice_energy", {}).get("ccvv_i8")
+        if ce and ce.get("executed_TOPs"):
+            ce["frac_of_probe_rate"] = ce["executed_TOPs"] / probe["i8"]["value"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_budget, grad=grad)
     print(json.dumps(out))

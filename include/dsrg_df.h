@@ -477,6 +477,30 @@ dsrg_status dsrg_df_set_gradient_block_bytes(size_t bytes);
 /* The bound in force. */
 size_t dsrg_df_gradient_block_bytes(void);
 
+/* Matrix-core rate probe: a measurement aid for the rooflines of the tile
+ * kernels (its callers are benchmarks), not a step of the method. Enqueues
+ * on `stream` one launch of nwg workgroups of eight waves (two per SIMD);
+ * each wave takes `iters` rounds of eight matrix products on register
+ * operands of full-entropy random bits, each product of a round taking
+ * another A and another B operand (the operand statistics of the tile
+ * kernels, without their memory traffic):
+ *   DSRG_PROBE_I8:  v_mfma_i32_32x32x32_i8, 65536 int8 operations a product;
+ *   DSRG_PROBE_F64: v_mfma_f64_16x16x4f64, 2048 flops a product.
+ * Operations per launch: nwg * 8 * iters * 8 * (65536 or 2048).
+ * stamps: device int64 [4 nwg]; for workgroup g, stamps[4g .. 4g+1] = the
+ *   shader cycle counter and the constant-rate counter before its products
+ *   and stamps[4g+2 .. 4g+3] the same after them, so the clock the products
+ *   ran at is cycles / (ticks / hipDeviceAttributeWallClockRate).
+ * sink: device buffer of nwg * 512 values (uint32 for DSRG_PROBE_I8, double
+ *   for DSRG_PROBE_F64) into which each thread folds its accumulators, so
+ *   that no product can be dropped as dead code.
+ * DSRG_ERR_ARG for an unknown kind, nwg outside [1, 65536], iters outside
+ * [1, 2^24], or a stamps or sink pointer that is NULL or not 8-byte aligned. */
+#define DSRG_PROBE_I8 0
+#define DSRG_PROBE_F64 1
+dsrg_status dsrg_df_mfma_probe(int kind, int64_t nwg, int64_t iters, int64_t *stamps, void *sink,
+                               void *stream);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int dsrg_df_version(void);
 

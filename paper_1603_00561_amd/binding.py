@@ -35,7 +35,7 @@ EXPORTED = ("dsrg_df_workspace_size", "dsrg_df_energy", "dsrg_df_energy_noalloc"
             "dsrg_df_rest_workspace_size", "dsrg_df_energy_rest", "dsrg_df_cumulants",
             "dsrg_df_cholesky_workspace_size", "dsrg_df_cholesky",
             "dsrg_df_laplace_fit", "dsrg_df_laplace_workspace_size", "dsrg_df_coulomb_laplace",
-            "dsrg_df_sign_check", "dsrg_df_version")
+            "dsrg_df_sign_check", "dsrg_df_mfma_probe", "dsrg_df_version")
 
 
 class DsrgError(RuntimeError):
@@ -113,6 +113,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dsrg_df_energy_noalloc.restype = i32
     lib.dsrg_df_sign_check.argtypes = [ctypes.POINTER(ctypes.c_uint)]
     lib.dsrg_df_sign_check.restype = i32
+    lib.dsrg_df_mfma_probe.argtypes = [i32, ctypes.c_int64, ctypes.c_int64, vp, vp, vp]
+    lib.dsrg_df_mfma_probe.restype = i32
     lib.dsrg_df_energy_backward.argtypes = [ctypes.POINTER(Problem), i32, i32, vp,
                                             vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.dsrg_df_energy_backward.restype = i32
@@ -345,6 +347,27 @@ def sign_check() -> int:
     w = ctypes.c_uint(0)
     _check(lib.dsrg_df_sign_check(ctypes.byref(w)))
     return int(w.value)
+
+
+PROBE_KINDS = {"i8": 0, "f64": 1}   # DSRG_PROBE_I8, DSRG_PROBE_F64
+PROBE_OPS = {"i8": 65536, "f64": 2048}   # operations per matrix product
+
+
+def mfma_probe(kind: str, nwg: int, iters: int, stamps: torch.Tensor, sink: torch.Tensor):
+    """Enqueues the matrix-core rate probe (dsrg_df_mfma_probe) on the current
+    stream of stamps' device: nwg workgroups of eight waves, iters rounds of
+    eight products per wave (nwg * 8 * iters * 8 * PROBE_OPS[kind]
+    operations). stamps: int64 [4 nwg] (per workgroup: cycle and constant-rate
+    counters before, then after its products); sink: nwg * 512 int32 (i8) or
+    float64 (f64) values."""
+    lib = load_library()
+    want = torch.int32 if kind == "i8" else torch.float64
+    if stamps.dtype != torch.int64 or stamps.numel() < 4 * nwg or not stamps.is_cuda:
+        raise ValueError("stamps must be a device int64 tensor of 4 nwg entries")
+    if sink.dtype != want or sink.numel() < 512 * nwg or sink.device != stamps.device:
+        raise ValueError("sink must be a device tensor of nwg * 512 entries of the kind's type")
+    _check(lib.dsrg_df_mfma_probe(PROBE_KINDS[kind], nwg, iters, stamps.data_ptr(),
+                                  sink.data_ptr(), _stream_handle(stamps.device)))
 
 
 def cumulants(rdm1, rdm2, rdm3):

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libdsrgdf.so")
 
 SOURCES = ["api.cpp", "fp64_kernels.hip", "fp64_bwd.hip", "split_kernels.hip", "split_bwd.hip",
            "active_terms.hip", "dfgen.hip", "semican.hip", "noalloc.hip",
-           "rest_terms.hip", "cholesky.hip", "laplace.hip", "checks.hip"]
+           "rest_terms.hip", "cholesky.hip", "laplace.hip", "checks.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -569,6 +569,23 @@ dsrg_status dsrg_df_sign_check(unsigned *word) {
   return DSRG_OK;
 }
 
+dsrg_status dsrg_df_mfma_probe(int kind, int64_t nwg, int64_t iters, int64_t *stamps, void *sink,
+                               void *stream) {
+  g_err[0] = 0;
+  if (kind != DSRG_PROBE_I8 && kind != DSRG_PROBE_F64)
+    return fail(DSRG_ERR_ARG, "unknown probe kind %d", kind);
+  if (nwg < 1 || nwg > 65536) return fail(DSRG_ERR_ARG, "nwg = %lld outside [1, 65536]", (long long)nwg);
+  if (iters < 1 || iters > (int64_t(1) << 24))
+    return fail(DSRG_ERR_ARG, "iters = %lld outside [1, 2^24]", (long long)iters);
+  if (!stamps || !sink) return fail(DSRG_ERR_ARG, "stamps or sink is NULL");
+  if ((reinterpret_cast<uintptr_t>(stamps) | reinterpret_cast<uintptr_t>(sink)) & 7)
+    return fail(DSRG_ERR_ARG, "stamps or sink is not 8-byte aligned");
+  hipError_t e = dsrg::launch_mfma_probe(kind, nwg, iters, stamps, sink,
+                                         reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(DSRG_ERR_HIP, "probe launch failed: %s", hipGetErrorString(e));
+  return DSRG_OK;
+}
+
 dsrg_status dsrg_df_workspace_size(const dsrg_df_problem *p, int precision, int terms,
                                    int with_grad, size_t *bytes) {
   g_err[0] = 0;

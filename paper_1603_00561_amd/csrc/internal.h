@@ -232,6 +232,9 @@ hipError_t noalloc_scratch(void **ptr);
 hipError_t sign_check_ptr(unsigned **ptr);
 // Waits for the current device, copies its word to *word and clears it.
 hipError_t sign_check_read(unsigned *word);
+// matrix-core rate probe (probe.hip): kind 0 int8, 1 FP64
+hipError_t launch_mfma_probe(int kind, int64_t nwg, int64_t iters, int64_t *stamps, void *sink,
+                             hipStream_t st);
 
 // ---- per-kernel timing (api.cpp); no-ops unless the call asked for it ----
 void timer_begin(const char *name, hipStream_t st);

@@ -409,3 +409,20 @@ def test_coulomb_laplace_entry_point_validation(lib):
     assert call(p, opts=0x100) == b.DSRG_ERR_ARG
     assert call(p, nb=16) == b.DSRG_ERR_WORKSPACE
     assert call(p, ws=0x40008) == b.DSRG_ERR_WORKSPACE
+
+
+def test_mfma_probe_validation(lib):
+    v = ctypes.c_void_p
+    good = dict(kind=0, nwg=256, iters=16, stamps=0x10000, sink=0x20000)
+
+    def call(**kw):
+        a = dict(good, **kw)
+        return lib.dsrg_df_mfma_probe(a["kind"], a["nwg"], a["iters"],
+                                      v(a["stamps"]) if a["stamps"] else None,
+                                      v(a["sink"]) if a["sink"] else None, None)
+
+    for bad in (dict(kind=2), dict(kind=-1), dict(nwg=0), dict(nwg=65537), dict(iters=0),
+                dict(iters=(1 << 24) + 1), dict(stamps=0), dict(sink=0), dict(stamps=0x10004),
+                dict(sink=0x20004)):
+        assert call(**bad) == b.DSRG_ERR_ARG, bad
+        assert lib.dsrg_df_last_error()
