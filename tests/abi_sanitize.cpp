@@ -213,6 +213,16 @@ void energy_validation() {
   CHECK(dsrg_df_energy_backward(&p, 0, 7, g, g, g, g, g, g, g, g, E, fakews(), gneed - 8,
                                 nullptr) == DSRG_ERR_WORKSPACE);
   CHECK(dsrg_df_sign_check(nullptr) == DSRG_ERR_ARG);
+  int64_t *st = reinterpret_cast<int64_t *>(0x10000);
+  void *sk = reinterpret_cast<void *>(0x20000);
+  CHECK(dsrg_df_mfma_probe(2, 256, 16, st, sk, nullptr) == DSRG_ERR_ARG);
+  CHECK(dsrg_df_mfma_probe(0, 0, 16, st, sk, nullptr) == DSRG_ERR_ARG);
+  CHECK(dsrg_df_mfma_probe(1, 65537, 16, st, sk, nullptr) == DSRG_ERR_ARG);
+  CHECK(dsrg_df_mfma_probe(0, 256, 0, st, sk, nullptr) == DSRG_ERR_ARG);
+  CHECK(dsrg_df_mfma_probe(0, 256, (int64_t(1) << 24) + 1, st, sk, nullptr) == DSRG_ERR_ARG);
+  CHECK(dsrg_df_mfma_probe(1, 256, 16, nullptr, sk, nullptr) == DSRG_ERR_ARG);
+  CHECK(dsrg_df_mfma_probe(1, 256, 16, st + 0, reinterpret_cast<char *>(sk) + 4, nullptr) ==
+        DSRG_ERR_ARG);
 }
 
 void other_entry_points() {
