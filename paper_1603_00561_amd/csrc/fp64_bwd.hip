@@ -749,13 +749,22 @@ hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &
         blk(J, j0, nj);
         if ((e = ccvv_adj_block_fp64(pl, in, o, ws, I, J, st)) != hipSuccess) return e;
         // dB_cv[(j,b)] (+)= sum_(i,a) B_cv[(i,a)] G[(i,a)][(j,b)]; block J is
-        // first written by the pair (0, J)
-        e = gemm<false>(pl, ws, Pcv + i0 * pstride, kPanel, ni * pl.ntv, G, nj * W, nj * W, W,
-                        pl.nv, o.dB_cv + j0 * pl.nv, ldcv, written || I > 0, st);
+        // first written by the pair (0, J). A diagonal block holds both
+        // orientations (the same values), so its product takes the form that
+        // reads G by rows of the output index (128 rows x 16 contraction
+        // values per chunk), as the transposed product does: that form runs
+        // its matrix cores busier (about 0.81 of the cycles against 0.70).
+        const int64_t ldgs = nj * W;
+        e = (I == J) ? gemm<true>(pl, ws, Pcv + i0 * pstride, kPanel, ni * pl.ntv, G, nj * W,
+                                  ldgs, W, pl.nv, o.dB_cv + j0 * pl.nv, ldcv, written || I > 0,
+                                  st)
+                     : gemm<false>(pl, ws, Pcv + i0 * pstride, kPanel, ni * pl.ntv, G, nj * W,
+                                   ldgs, W, pl.nv, o.dB_cv + j0 * pl.nv, ldcv,
+                                   written || I > 0, st);
         if (e != hipSuccess) return e;
         if (J > I) {
           // dB_cv[(i,a)] += sum_(j,b) B_cv[(j,b)] G[(i,a)][(j,b)]
-          e = gemm<true>(pl, ws, Pcv + j0 * pstride, kPanel, nj * pl.ntv, G, ni * W, nj * W, W,
+          e = gemm<true>(pl, ws, Pcv + j0 * pstride, kPanel, nj * pl.ntv, G, ni * W, ldgs, W,
                          pl.nv, o.dB_cv + i0 * pl.nv, ldcv, true, st);
           if (e != hipSuccess) return e;
         }
