@@ -218,6 +218,9 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   if (has_ccav) {
     if (pl.with_grad) {
       off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.naux_p * kActPanel));
+      // the CCAV integrals J[(m,e)][(n,u)] of the adjoint tiles
+      pl.off_j = off;
+      off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.nv) * (size_t)(pl.nc * pl.na));
     } else {
       off = align256(off + sizeof(double) * (size_t)(pl.naux_p * pl.ccav_cols));
       pl.off_j = off;

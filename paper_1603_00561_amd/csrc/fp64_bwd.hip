@@ -223,8 +223,10 @@ __global__ __launch_bounds__(256, 3) void ccvv_adj_fp64_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// CCAV adjoint tiles for (m <= n, 64-row tile T). Per e and active w, with
-// x_u = (me|nu), y_u = (ne|mu), etab = 2I - Gamma:
+// CCAV adjoint tiles for (m <= n, 64-row tile T), from the integrals
+// J[(m,e)][(n,u)] = (me|nu) formed beforehand by one product over the inputs
+// (nc nv rows of nc na). Per e and active w, with x_u = (me|nu),
+// y_u = (ne|mu), etab = 2I - Gamma:
 //   A_w = sum_u etab_uw R1_u (2x_u - y_u),  A'_w = sum_u etab_uw R1_u (2y_u - x_u)
 //   C_w = sum_v etab_wv S_v x_v,            C'_w = sum_v etab_wv S_v y_v
 //   dL/d(me|nw) = gE2 [S_w A_w  + R1_w (2C_w  - C'_w)]  -> G3[(m,e)][(n,w)]
@@ -234,7 +236,6 @@ __global__ __launch_bounds__(256, 3) void ccvv_adj_fp64_kernel(
 // ---------------------------------------------------------------------------
 struct CcavAdjArgs {
   int nc, na, nv, ntv;
-  int64_t naux_p;
   double s;
   int64_t slot_base;
   int64_t N3;   // row length of G3 = nc * 16
@@ -242,19 +243,27 @@ struct CcavAdjArgs {
 
 template <int NA>
 __global__ __launch_bounds__(256) void ccav_adj_fp64_kernel(
-    const double *__restrict__ Pcv, const double *__restrict__ Pca,
-    const double *__restrict__ eps_c, const double *__restrict__ eps_a,
-    const double *__restrict__ eps_v, const double *__restrict__ gamma1, CcavAdjArgs a,
-    GradOut g, double *__restrict__ G3, double *slots) {
+    const double *__restrict__ J, const double *__restrict__ eps_c,
+    const double *__restrict__ eps_a, const double *__restrict__ eps_v,
+    const double *__restrict__ gamma1, CcavAdjArgs a, GradOut g, double *__restrict__ G3,
+    double *slots) {
   constexpr int W = kPanel, WA = kActPanel;
-  __shared__ double lds[kCcavLds];
+  __shared__ double lds[4];
   __shared__ double xs[2][kPanel][kActPanel + 1];
   __shared__ double asum[NA];
   int m, n;
   decode_pair_le(blockIdx.x / a.ntv, a.nc, m, n);
   const int T = (int)(blockIdx.x % a.ntv);
   if (threadIdx.x < NA) asum[threadIdx.x] = 0.0;
-  ccav_compute(Pcv, Pca, a.naux_p, a.ntv, m, n, T, lds, xs);
+  // x_u = (me|nu) into xs[0], y_u = (ne|mu) into xs[1], for the tile's 64 e
+  const int64_t ldj = (int64_t)a.nc * NA;
+  for (int k = threadIdx.x; k < 2 * W * NA; k += 256) {
+    const int which = k / (W * NA), el = (k / NA) % W, u = k % NA;
+    const int e = T * W + el;
+    const int p = which ? n : m, q = which ? m : n;
+    xs[which][el][u] = (e < a.nv) ? J[((int64_t)p * a.nv + e) * ldj + (int64_t)q * NA + u] : 0.0;
+  }
+  __syncthreads();
   const double gE2 = g.gE[2];
   const double wgt = (m == n) ? 0.5 : 1.0;
   double e_part = 0.0, d_part = 0.0, s_part = 0.0;
@@ -610,16 +619,20 @@ static hipError_t launch_adj_act(const Plan &pl, const Inputs &in, const GradOut
     a.na = (int)pl.na;
     a.nv = (int)pl.nv;
     a.ntv = (int)pl.ntv;
-    a.naux_p = pl.naux_p;
     a.s = pl.s;
     a.slot_base = pl.slot_base[2];
     a.N3 = pl.nc * kActPanel;
+    double *J = ws_d(ws, pl.off_j);
     timer_begin("ccav_adj_fp64", st);
-    hipLaunchKernelGGL((ccav_adj_fp64_kernel<NA>), dim3((unsigned)pl.n_ccav), dim3(256), 0, st,
-                       ws_d(ws, pl.off_pcv), ws_d(ws, pl.off_pca), in.eps_c, in.eps_a, in.eps_v,
-                       in.gamma1, a, g, ws_d(ws, pl.off_g3), slots);
+    // J[(m,e)][(n,u)] = sum_Q B^Q_me B^Q_nu: B_cv and B_ca as stored, [Q][(m,e)]
+    // and [Q][(n,u)]
+    hipError_t e = gemm_f64(true, false, pl.nc * pl.nv, pl.nc * pl.na, pl.naux, 1.0, in.B_cv,
+                            pl.nc * pl.nv, in.B_ca, pl.nc * pl.na, 0.0, J, pl.nc * pl.na, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ccav_adj_fp64_kernel<NA>), dim3((unsigned)pl.n_ccav), dim3(256), 0, st, J,
+                       in.eps_c, in.eps_a, in.eps_v, in.gamma1, a, g, ws_d(ws, pl.off_g3), slots);
     timer_end(st);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

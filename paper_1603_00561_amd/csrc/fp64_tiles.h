@@ -609,65 +609,4 @@ __device__ __forceinline__ void cavv_compute(const double *Pcv, const double *Pa
   });
 }
 
-// ---------------------------------------------------------------------------
-// CCAV tiles for one (m <= n, 64-row virtual tile T): x[e][u] = (me|nu),
-// y[e][u] = (ne|mu), na padded to 16 columns; each wave owns 16 rows. The two
-// 64 x 16 tiles are left in LDS as xs[2][64][17] for row-wise epilogues.
-// ---------------------------------------------------------------------------
-constexpr int kCcavKC = 16;
-constexpr int kCcavLdsV = 2 * 2 * kCcavKC * kPanel;       // doubles
-constexpr int kCcavLdsA = 2 * 2 * kCcavKC * kActPanel;    // doubles
-constexpr int kCcavLds = kCcavLdsV + kCcavLdsA;
-
-__device__ __forceinline__ void ccav_compute(const double *Pcv, const double *Pca,
-                                             int64_t naux_p, int ntv, int m, int n, int T,
-                                             double *lds, double (*xs)[kPanel][kActPanel + 1]) {
-  constexpr int W = kPanel, WA = kActPanel, KC = kCcavKC;
-  const int64_t pstride = naux_p * W;
-  const double *srcv[2] = {Pcv + (int64_t)(m * ntv + T) * pstride,
-                           Pcv + (int64_t)(n * ntv + T) * pstride};
-  const double *srca[2] = {Pca + (int64_t)n * naux_p * WA, Pca + (int64_t)m * naux_p * WA};
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int cl = lane & 15, kl = lane >> 4;
-  d4 x = zero4(), y = zero4();
-  double *lv = lds, *la = lds + kCcavLdsV;
-  Stage<2, W, KC> sv;
-  Stage<2, WA, KC> sa;
-  sv.load(srcv, W, 0);
-  sa.load(srca, WA, 0);
-  sv.store(lv);
-  sa.store(la);
-  if (naux_p > KC) {
-    sv.load(srcv, W, KC);
-    sa.load(srca, WA, KC);
-  }
-  __syncthreads();
-  int b = 0;
-  for (int64_t q0 = 0; q0 < naux_p; q0 += KC) {
-    const double *LV = lv + b * (2 * KC * W), *LA = la + b * (2 * KC * WA);
-#pragma unroll
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      const int k = kk * 4 + kl;
-      x = mfma64(LV[(0 * KC + k) * W + lcol<W>(16 * wave + cl, k)], LA[(0 * KC + k) * WA + cl], x);
-      y = mfma64(LV[(1 * KC + k) * W + lcol<W>(16 * wave + cl, k)], LA[(1 * KC + k) * WA + cl], y);
-    }
-    if (q0 + KC < naux_p) {
-      sv.store(lv + (b ^ 1) * (2 * KC * W));
-      sa.store(la + (b ^ 1) * (2 * KC * WA));
-      if (q0 + 2 * KC < naux_p) {
-        sv.load(srcv, W, q0 + 2 * KC);
-        sa.load(srca, WA, q0 + 2 * KC);
-      }
-    }
-    __syncthreads();
-    b ^= 1;
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    xs[0][16 * wave + 4 * r + kl][cl] = x[r];
-    xs[1][16 * wave + 4 * r + kl][cl] = y[r];
-  }
-  __syncthreads();
-}
-
 }  // namespace dsrg
