@@ -205,6 +205,53 @@ __global__ __launch_bounds__(256) void op_pack_kernel(OpMap m, int64_t R, int64_
   }
 }
 
+// The same slices for maps whose contraction index is contiguous in memory
+// (ldk = 1) in blocks of whole chunks (kblk a multiple of 32): one workgroup
+// per (64-row panel, chunk), chunks fastest; thread t takes row t / 4 and the
+// eight contraction indices 8 (t % 4) .. +7, so four threads read a row's 256
+// contiguous bytes (the one-thread-per-row kernel above reads 64 rows per load
+// instruction) and write their eight bytes of each slice in place.
+__global__ __launch_bounds__(256) void op_pack_rows_kernel(OpMap m, int64_t nqc,
+                                                           const double *__restrict__ sig,
+                                                           int8_t *__restrict__ S8) {
+  const int64_t qc = blockIdx.x % nqc, pan = blockIdx.x / nqc;
+  const int c = threadIdx.x >> 2, part = threadIdx.x & 3;
+  const int64_t r = pan * kPanel + c;
+  const double inv = 1.0 / sig[r];   // exact: a power of two
+  const double *row = op_row(m, r);
+  const int64_t k0 = qc * kQC + 8 * part;
+  const int64_t kb = k0 / m.kblk, ke = k0 % m.kblk;
+  uint64_t packed[kSlices] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    double x = 0.0;
+    if (row && ke + j < m.kval && k0 + j < m.klim) x = row[kb * m.ldkb + ke + j];
+    x *= inv * 127.0;
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      const double t = rint(x);
+      packed[s] |= (uint64_t)(uint8_t)(int8_t)(int)t << (8 * j);
+      x = (x - t) * 254.0;
+    }
+  }
+  const int sw = (c >> 3) & 1;
+  int8_t *dst = S8 + (pan * nqc + qc) * (int64_t)kSlicePanelChunk +
+                (((part >> 1) ^ sw) << 4) + ((part & 1) << 3);
+#pragma unroll
+  for (int s = 0; s < kSlices; ++s)
+    *reinterpret_cast<uint64_t *>(dst + (s * kPanel + c) * kQC) = packed[s];
+}
+
+static void launch_op_pack(const OpMap &m, int64_t R, int64_t nqc, const double *sig, int8_t *S8,
+                           hipStream_t st) {
+  if (m.ldk == 1 && m.kblk % kQC == 0 && R % kPanel == 0 && (R / kPanel) * nqc < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(op_pack_rows_kernel, dim3((unsigned)((R / kPanel) * nqc)), dim3(256), 0,
+                       st, m, nqc, sig, S8);
+  else
+    hipLaunchKernelGGL(op_pack_kernel, dim3((unsigned)ceil_div(R * nqc, 256)), dim3(256), 0, st,
+                       m, R, nqc, sig, S8);
+}
+
 // C[Q][n] (=|+=) sum_k A[Q][k] B[n][k] on slices, one 128 x 128 tile per
 // workgroup (A tiles fastest, so the workgroups of one XCD share A panels).
 // Output column n is written at (n / GP) nvalid + n % GP and skipped when
@@ -651,9 +698,7 @@ static hipError_t pack_operand(const OpMap &m, int64_t R, int64_t K, double *sig
                        dim3(256), 0, st, m, R, K, pmax);
   hipLaunchKernelGGL(op_scale_final_kernel, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, st,
                      pmax, R, sig);
-  const int64_t nqc = K / kQC;
-  hipLaunchKernelGGL(op_pack_kernel, dim3((unsigned)ceil_div(R * nqc, 256)), dim3(256), 0, st, m,
-                     R, nqc, sig, S8);
+  launch_op_pack(m, R, K / kQC, sig, S8, st);
   timer_end(st);
   return hipGetLastError();
 }
@@ -680,9 +725,7 @@ static hipError_t pack_with_maxima(const OpMap &om, int64_t Rv, int64_t R, int64
   timer_begin("op_pack", st);
   hipLaunchKernelGGL(op_sigma_kernel, dim3((unsigned)ceil_div(R, 256)), dim3(256), 0, st,
                      reinterpret_cast<const unsigned long long *>(m), Rv, R, sig);
-  const int64_t nqc = K / kQC;
-  hipLaunchKernelGGL(op_pack_kernel, dim3((unsigned)ceil_div(R * nqc, 256)), dim3(256), 0, st, om,
-                     R, nqc, sig, S8);
+  launch_op_pack(om, R, K / kQC, sig, S8, st);
   timer_end(st);
   return hipGetLastError();
 }
