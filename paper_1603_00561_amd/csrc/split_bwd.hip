@@ -530,12 +530,13 @@ __global__ __launch_bounds__(256) void cavv_adj_epi_kernel(
     double *deps_v, double *ds, const double *__restrict__ gE, double *__restrict__ G2,
     double *slots) {
   __shared__ double Xs[NA][2][kAdjT][kAdjT + 1];
-  __shared__ double rs[kAdjT], cs[kAdjT], as_[NA], red[4];
+  __shared__ double csw[4][kAdjT], red[4][NA + 3];
   const int64_t T = (int64_t)a.nt16 * (a.nt16 + 1) / 2;
   const int ml = (int)(blockIdx.x / T);
   int E, F;
   decode_pair_le(blockIdx.x % T, a.nt16, E, F);
   const int el = threadIdx.x >> 4, fl = threadIdx.x & 15;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t ld = a.ld;
   const double *X = Xb + (int64_t)ml * NA * ld * ld;
   const int e0 = E * kAdjT, f0 = F * kAdjT;
@@ -545,11 +546,6 @@ __global__ __launch_bounds__(256) void cavv_adj_epi_kernel(
     Xs[u][0][el][fl] = Xu[(int64_t)(e0 + el) * ld + f0 + fl];
     Xs[u][1][el][fl] = Xu[(int64_t)(f0 + el) * ld + e0 + fl];
   }
-  if (threadIdx.x < kAdjT) {
-    rs[threadIdx.x] = 0.0;
-    cs[threadIdx.x] = 0.0;
-  }
-  if (threadIdx.x < NA) as_[threadIdx.x] = 0.0;
   double Gm[NA][NA], ea[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
@@ -563,8 +559,13 @@ __global__ __launch_bounds__(256) void cavv_adj_epi_kernel(
   const double wgt = (E == F) ? 0.5 : 1.0;
   __syncthreads();
   const int e = e0 + el, f = f0 + fl;
-  double e_part = 0.0, d_part = 0.0, s_part = 0.0;
-  if (e < a.nv && f < a.nv) {
+  const bool ok = e < a.nv && f < a.nv;
+  // per-thread sums: energy, eps (total and per active w) and s parts; the
+  // transposed adjoint values go out through LDS after the loads are done
+  double e_part = 0.0, d_part = 0.0, s_part = 0.0, ddw[NA], gt[NA];
+#pragma unroll
+  for (int w = 0; w < NA; ++w) ddw[w] = gt[w] = 0.0;
+  if (ok) {
     double Xv[NA], Yv[NA], S[NA], R1[NA], dS[NA], dR1[NA], sS[NA], sR1[NA];
     const double base = em - (eps_v[e] + eps_v[f]);
 #pragma unroll
@@ -591,39 +592,76 @@ __global__ __launch_bounds__(256) void cavv_adj_epi_kernel(
     }
     // rows of the batch's core orbitals: (m - m0) W + e
     double *Gn = G2 + ((int64_t)ml * a.W + e) * a.N2 + f;   // + w W
-    double *Gt = G2 + ((int64_t)ml * a.W + f) * a.N2 + e;
 #pragma unroll
     for (int w = 0; w < NA; ++w) {
       const double Wv = 2.0 * Xv[w] - Yv[w], Wp = 2.0 * Yv[w] - Xv[w];
       Gn[(int64_t)w * a.W] = gE1 * (S[w] * Av[w] + R1[w] * (2.0 * Cv[w] - Cp[w]));
-      if (E != F) Gt[(int64_t)w * a.W] = gE1 * (S[w] * Ap[w] + R1[w] * (2.0 * Cp[w] - Cv[w]));
+      gt[w] = gE1 * (S[w] * Ap[w] + R1[w] * (2.0 * Cp[w] - Cv[w]));
       e_part += wgt * S[w] * (Xv[w] * Av[w] + Yv[w] * Ap[w]);
       const double dd = wgt * (Xv[w] * Av[w] * dS[w] + Wv * Cv[w] * dR1[w] +
                                Yv[w] * Ap[w] * dS[w] + Wp * Cp[w] * dR1[w]);
       s_part += wgt * (Xv[w] * Av[w] * sS[w] + Wv * Cv[w] * sR1[w] + Yv[w] * Ap[w] * sS[w] +
                        Wp * Cp[w] * sR1[w]);
       d_part += dd;
-      atomicAdd(&as_[w], dd);
+      ddw[w] = dd;
     }
-    atomicAdd(&rs[el], d_part);
-    atomicAdd(&cs[fl], d_part);
   }
-  __syncthreads();
+  // row sums (over f: the 16 lanes of one e) and column sums (over e: lanes
+  // fl, fl + 16, fl + 32, fl + 48 of each wave, then the four waves), in a
+  // fixed order
+  double rsum = d_part, csum = d_part;
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) rsum += __shfl_xor(rsum, o, 64);
+  csum += __shfl_xor(csum, 16, 64);
+  csum += __shfl_xor(csum, 32, 64);
+  // workgroup sums of the energy, eps and s parts and of each w's eps part
+  double v3[NA + 3];
+  v3[0] = e_part;
+  v3[1] = d_part;
+  v3[2] = s_part;
+#pragma unroll
+  for (int w = 0; w < NA; ++w) v3[3 + w] = ddw[w];
+#pragma unroll
+  for (int k = 0; k < NA + 3; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v3[k] += __shfl_xor(v3[k], o, 64);
+  if (lane < kAdjT) csw[wave][lane] = csum;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NA + 3; ++k) red[wave][k] = v3[k];
+  }
+  if (fl == 0 && e < a.nv) atomicAdd(&deps_v[e], -gE1 * rsum);
+  __syncthreads();   // every thread has read Xs, csw and red are complete
+  if (E != F) {
+#pragma unroll
+    for (int w = 0; w < NA; ++w) Xs[w][0][fl][el] = gt[w];
+  }
   if (threadIdx.x < kAdjT) {
     const int t = threadIdx.x;
-    if (e0 + t < a.nv) atomicAdd(&deps_v[e0 + t], -gE1 * rs[t]);
-    if (f0 + t < a.nv) atomicAdd(&deps_v[f0 + t], -gE1 * cs[t]);
+    const double c = (csw[0][t] + csw[1][t]) + (csw[2][t] + csw[3][t]);
+    if (f0 + t < a.nv) atomicAdd(&deps_v[f0 + t], -gE1 * c);
   }
-  if (threadIdx.x < NA) atomicAdd(&deps_a[threadIdx.x], gE1 * as_[threadIdx.x]);
-  const double tE = block_sum(e_part, red);
-  __syncthreads();
-  const double tD = block_sum(d_part, red);
-  __syncthreads();
-  const double tS = block_sum(s_part, red);
+  if (threadIdx.x < NA) {
+    const int w = threadIdx.x;
+    atomicAdd(&deps_a[w], gE1 * ((red[0][3 + w] + red[1][3 + w]) + (red[2][3 + w] + red[3][3 + w])));
+  }
   if (threadIdx.x == 0) {
+    const double tE = (red[0][0] + red[1][0]) + (red[2][0] + red[3][0]);
+    const double tD = (red[0][1] + red[1][1]) + (red[2][1] + red[3][1]);
+    const double tS = (red[0][2] + red[1][2]) + (red[2][2] + red[3][2]);
     slots[a.slot_base + blockIdx.x] = tE;
     atomicAdd(&deps_c[m], gE1 * tD);
     atomicAdd(ds, gE1 * tS);
+  }
+  if (E != F) {
+    // G2[(m - m0) W + f][w W + e]: rows f, the 16 e of a row from 16 threads
+    __syncthreads();
+    const int r = threadIdx.x >> 4, c = threadIdx.x & 15;
+    if (f0 + r < a.nv && e0 + c < a.nv) {
+      double *Gt = G2 + ((int64_t)ml * a.W + f0 + r) * a.N2 + e0 + c;
+#pragma unroll
+      for (int w = 0; w < NA; ++w) Gt[(int64_t)w * a.W] = Xs[w][0][r][c];
+    }
   }
 }
 
