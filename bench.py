@@ -168,6 +168,29 @@ def timed_region(binding, torch, call, steps, names):
     return (t1 - t0) * 1e3 / steps, (float(np.mean(launches)) if launches else None)
 
 
+def graph_replay_ms(torch, fn, steps):
+    """Wall time per call when one call of fn (which only enqueues work on the
+    current stream) is captured in a HIP graph (torch.cuda.CUDAGraph) and the
+    graph is replayed `steps` times: the same kernels, without the host's
+    per-launch work between them."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
 def table_steps(args):
     return max(1, min(args.steps, 5))
 
@@ -817,6 +840,8 @@ def bench_active(args, p, binding, torch):
         "F_terms": [float(x) for x in Fg],
         "abs_err_vs_oracle": err,
         "roofline": roof,
+        # the same call replayed from a HIP graph (about twenty launches a call)
+        "graph_replay_ms_per_step": graph_replay_ms(torch, lambda: call(False), args.steps),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_active(p, args.cpu_budget)
@@ -974,6 +999,8 @@ def bench_semican(args, binding, torch):
         "kernel_ms": avg,
         "kernel_ms_from": table_note(args),
         "roofline": roof,
+        # the same call replayed from a HIP graph (a few hundred launches a call)
+        "graph_replay_ms_per_step": graph_replay_ms(torch, lambda: call(False), args.steps),
     }
     if not args.no_cpu_baseline:
         cb = cpu_baseline_semican(F.cpu().numpy(), shape, g.nao, eps.cpu().numpy(),

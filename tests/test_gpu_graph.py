@@ -118,3 +118,25 @@ def test_upstream_builds_replay():
     ref = [x.clone() for x in chain(*ins)]
     g, outs = _capture(lambda: chain(*ins))
     _replay_and_check(g, outs, ref, lambda: chain(*oth))
+
+
+def test_active_terms_replay():
+    # F4-F8 (about twenty launches, no host wait inside the call)
+    print("[gpu-graph] energy_active", flush=True)
+    b = _b()
+    p = make_problem(5, 3, 70, 40, seed=31)
+    q = make_problem(5, 3, 70, 40, s=0.3, seed=32)
+    keys = ("B_cv", "B_ca", "B_av", "B_aa", "eps_c", "eps_a", "eps_v", "gamma1")
+    u = [_dev(getattr(p, k)) for k in keys]
+    v = [_dev(getattr(q, k)) for k in keys]
+    ws = torch.empty(b.active_workspace_size(p.nc, p.na, p.nv, p.naux), dtype=torch.uint8,
+                     device="cuda")
+
+    def call(t, s):
+        F = torch.empty(5, dtype=torch.float64, device="cuda")
+        b.energy_active(*t, s, out=F, workspace=ws)
+        return [F]
+
+    ref = [x.clone() for x in call(u, p.s)]
+    g, outs = _capture(lambda: call(u, p.s))
+    _replay_and_check(g, outs, ref, lambda: call(v, q.s))
