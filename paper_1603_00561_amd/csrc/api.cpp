@@ -204,11 +204,12 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
     return fail(DSRG_ERR_UNSUPPORTED, "work list exceeds one launch grid");
 
   size_t off = 0;
-  // FP64 panels: every FP64 kernel; in the slice path only the CCAV GEMM
-  // (the slice-path gradient forms its adjoint tiles with the FP64 kernels)
-  const bool fp64_tiles = !split || pl.with_grad;
+  // FP64 panels: every FP64 kernel; in the slice path only the forward CCAV
+  // product (the gradient's CCAV integrals come from one product over the
+  // inputs, and its other adjoint tiles from the slices)
+  const bool fp64_tiles = !split;
   pl.off_pcv = off;
-  if (fp64_tiles || has_ccav)
+  if (fp64_tiles || (has_ccav && !pl.with_grad))
     off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.ntv * pl.naux_p * kPanel));
   pl.off_pav = off;
   if (!split && has_cavv)
@@ -217,7 +218,8 @@ dsrg_status make_plan(const dsrg_df_problem *p, int precision, int terms, int wi
   pl.off_j = off;
   if (has_ccav) {
     if (pl.with_grad) {
-      off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.naux_p * kActPanel));
+      // B_ca panels of the FP64 adjoint products
+      if (!split) off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.naux_p * kActPanel));
       // the CCAV integrals J[(m,e)][(n,u)] of the adjoint tiles
       pl.off_j = off;
       off = align256(off + sizeof(double) * (size_t)(pl.nc * pl.nv) * (size_t)(pl.nc * pl.na));

@@ -640,9 +640,9 @@ static hipError_t launch_adj_act(const Plan &pl, const Inputs &in, const GradOut
 
 hipError_t launch_zero_fill(double *p, int64_t n, hipStream_t st) { return zero_fill(p, n, st); }
 
-// Gradients of eps and s cleared, the FP64 panels packed, and the CCAV
-// adjoint tiles G3 (whole: nc 64 ntv rows of nc 16) with their energies and
-// eps / s parts.
+// Gradients of eps and s cleared, the FP64 panels packed (FP64 path), and the
+// CCAV adjoint tiles G3 (whole: nc 64 ntv rows of nc 16) with their energies
+// and eps / s parts.
 hipError_t launch_adjoint_start_fp64(const Plan &pl, const Inputs &in, const BwdOut &o, void *ws,
                                      hipStream_t st) {
   hipError_t e;
@@ -651,7 +651,9 @@ hipError_t launch_adjoint_start_fp64(const Plan &pl, const Inputs &in, const Bwd
   if ((e = zero_fill(o.deps_a, pl.na, st)) != hipSuccess) return e;
   if ((e = zero_fill(o.deps_v, pl.nv, st)) != hipSuccess) return e;
   if ((e = zero_fill(o.ds, 1, st)) != hipSuccess) return e;
-  if ((e = launch_pack_fp64(pl, in, ws, st)) != hipSuccess) return e;
+  // the FP64 panels feed the FP64 path's adjoint tiles and products (the
+  // slice path reads its operands from the inputs and its slices)
+  if (pl.precision == 0 && (e = launch_pack_fp64(pl, in, ws, st)) != hipSuccess) return e;
   if ((pl.terms & 4) && pl.na > 0) {
     switch (pl.na) {
       case 1: e = launch_adj_act<1>(pl, in, g, ws, 4, st); break;
