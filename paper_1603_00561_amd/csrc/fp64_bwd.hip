@@ -385,6 +385,15 @@ struct AdjChunk {
   }
 };
 
+// The 16 x 128 chunk of G[k][n] (k-major form) as 1024 double2 pieces: piece
+// idx (thread t + 512 h) holds row adj_row(idx), columns 2 adj_c2(idx) .. +1.
+// A wave's 64 pieces are 64-byte pieces of all 16 rows (four lanes a row),
+// not one row of 1 KB: a wave instruction then spans 16 rows of G, as the
+// n-major form's spans 8 (cfg5 energy + gradient 166.4 -> 161.6 ms; 8 rows of
+// 128 bytes: 164.0 ms).
+__device__ __forceinline__ int adj_row(int idx) { return (idx & 63) >> 2; }
+__device__ __forceinline__ int adj_c2(int idx) { return 4 * (idx >> 6) + (idx & 3); }
+
 template <bool TB>
 __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const double *__restrict__ Apan,
                                                                   const double *__restrict__ G,
@@ -420,7 +429,7 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
   for (int h = 0; h < 2; ++h) {
     const int idx = t + h * kGThreads;
     // !TB: columns n, n + 1 (nvalid even when compact: one group)
-    const int64_t n = TB ? n0 + (idx >> 3) : n0 + 2 * (idx & 63);
+    const int64_t n = TB ? n0 + (idx >> 3) : n0 + 2 * adj_c2(idx);
     gok[h] = n < a.Ncols;
     goff[h] = gcol(n);
   }
@@ -439,7 +448,7 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
     for (int h = 0; h < 2; ++h) {
       const int idx = t + h * kGThreads;
       if constexpr (!TB) {
-        const int row = idx >> 6, c2 = idx & 63;   // 16 rows x 64 double2
+        const int row = adj_row(idx), c2 = adj_c2(idx);   // 16 rows x 64 double2
         rb[h] = gok[h] ? *reinterpret_cast<const d2v *>(G + (k0 + row) * a.ldg + goff[h])
                        : d2v{0.0, 0.0};
       } else {
@@ -461,7 +470,7 @@ __global__ __launch_bounds__(kGThreads, 4) void gemm_adj_fp64_kernel(const doubl
     for (int h = 0; h < 2; ++h) {
       const int idx = t + h * kGThreads;
       if constexpr (!TB) {
-        const int row = idx >> 6, c2 = idx & 63;
+        const int row = adj_row(idx), c2 = adj_c2(idx);
         *reinterpret_cast<d2v *>(&sB[b][row * kGT + ((2 * c2) ^ swz(row))]) = rb[h];
       } else {
         const int nr = idx >> 3, c2 = idx & 7;
@@ -765,10 +774,10 @@ hipError_t launch_backward_fp64(const Plan &pl, const Inputs &in, const BwdOut &
         if ((e = ccvv_adj_block_fp64(pl, in, o, ws, I, J, st)) != hipSuccess) return e;
         // dB_cv[(j,b)] (+)= sum_(i,a) B_cv[(i,a)] G[(i,a)][(j,b)]; block J is
         // first written by the pair (0, J). A diagonal block holds both
-        // orientations (the same values), so its product takes the form that
-        // reads G by rows of the output index (128 rows x 16 contraction
-        // values per chunk), as the transposed product does: that form runs
-        // its matrix cores busier (about 0.81 of the cycles against 0.70).
+        // orientations (the same values), so its product may take either
+        // form; the one that reads G by rows of the output index (128 rows x
+        // 16 contraction values per chunk) is the faster (cfg5 energy +
+        // gradient 161.6 against 162.4 ms).
         const int64_t ldgs = nj * W;
         e = (I == J) ? gemm<true>(pl, ws, Pcv + i0 * pstride, kPanel, ni * pl.ntv, G, nj * W,
                                   ldgs, W, pl.nv, o.dB_cv + j0 * pl.nv, ldcv, written || I > 0,
