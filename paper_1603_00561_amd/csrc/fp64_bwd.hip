@@ -32,11 +32,14 @@ static hipError_t zero_fill(double *p, int64_t n, hipStream_t st) {
 }
 
 // Write a 64 x 64 tile held in LDS (T[r][c], row stride 65) transposed into a
-// row-major global matrix: dst[c * ld + r] = T[r][c], coalesced along r.
+// row-major global matrix: dst[c * ld + r] = T[r][c]; a wave instruction
+// writes 128-byte pieces of four rows c (lane: 16 consecutive r of one of four
+// consecutive c), not one row's 512 bytes.
 __device__ __forceinline__ void store_transposed64(const double (*T)[kPanel + 1], double *dst,
                                                    int64_t ld) {
   for (int k = threadIdx.x; k < kPanel * kPanel; k += kThreads) {
-    const int c = k / kPanel, r = k % kPanel;
+    const int lane = k & 63, wv = k >> 6;
+    const int c = 4 * (wv >> 2) + (lane >> 4), r = 16 * (wv & 3) + (lane & 15);
     dst[(int64_t)c * ld + r] = T[r][c];
   }
 }

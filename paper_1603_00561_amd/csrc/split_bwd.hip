@@ -336,10 +336,14 @@ struct CcvvAdjI8Args {
   unsigned *chk;   // sign check word (nullptr: off)
 };
 
+// dst[c ld + r] = T[r][c] for r < rvalid, c < cvalid; a wave instruction
+// writes 128-byte pieces of four rows c of dst (lane: 16 consecutive r of one
+// of four consecutive c), not one row's 512 bytes
 __device__ __forceinline__ void store_transposed128(const double (*T)[kI8Tile + 1], double *dst,
                                                     int64_t ld, int rvalid, int cvalid) {
   for (int k = threadIdx.x; k < kI8Tile * kI8Tile; k += kI8Threads) {
-    const int c = k / kI8Tile, r = k % kI8Tile;
+    const int lane = k & 63, wv = k >> 6;
+    const int c = 4 * (wv >> 3) + (lane >> 4), r = 16 * (wv & 7) + (lane & 15);
     if (r < rvalid && c < cvalid) dst[(int64_t)c * ld + r] = T[r][c];
   }
 }
